@@ -1,0 +1,199 @@
+/*
+ * spx -- sparse matrix-matrix multiplication, indexing and assignment on one
+ * AMD Instinct MI355X (gfx950).
+ *
+ * The operations follow Buluc & Gilbert, "Parallel Sparse Matrix-Matrix
+ * Multiplication and Indexing: Implementation and Experiments":
+ *   C = A*B over a semiring            Section 3, Algorithm 1 (column-wise SpGEMM)
+ *   B = A(I,J)           (SpRef)       Section 4; computed as R*(A*Q)
+ *   C = A with A(I,J) = B (SpAsgn)     Section 4.1 (A + R B Q, minus the pattern of S A T)
+ *   CSC <-> DCSC                       Section 3.2
+ *
+ * Conventions for every entry point
+ *   - All matrix and index arrays are DEVICE pointers, 0-based.
+ *   - Canonical form: inside each column the row ids in `ir` are strictly
+ *     increasing (no duplicates); in DCSC `jc` is strictly increasing and
+ *     lists nonempty columns only.  Non-canonical input gives undefined
+ *     results unless ctx->validate is set (then SPX_EINVAL).
+ *   - Structural semantics: an output entry exists iff at least one product
+ *     contributes to it; values equal to zero are kept.
+ *   - The caller owns inputs, outputs and plans.  A plan keeps pointers to
+ *     its inputs: they must stay alive and unchanged until the plan's last
+ *     exec call has completed on the stream.
+ *   - All device work is enqueued on ctx->stream.  Plan calls synchronise
+ *     that stream once (to read back output sizes); exec calls do not.
+ *   - Every call returns SPX_OK or an error code; spx_last_error() gives a
+ *     thread-local message.  On error, output buffers are left untouched
+ *     unless the code is SPX_EDEVICE.
+ */
+#ifndef SPX_H
+#define SPX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---------------------------------------------------- */
+enum {
+  SPX_OK = 0,
+  SPX_EINVAL = 1,       /* bad descriptor, dimension mismatch, index out of range */
+  SPX_ENOMEM = 2,       /* the allocation callback (or hipMalloc) failed */
+  SPX_EOVERFLOW = 3,    /* a count does not fit the requested pointer type */
+  SPX_EUNSUPPORTED = 4, /* semiring / value-type combination not provided */
+  SPX_EDEVICE = 5       /* a HIP runtime call failed */
+};
+
+/* ---- descriptors ----------------------------------------------------- */
+enum { SPX_CSC = 0, SPX_DCSC = 1 };                 /* storage format (Section 3.2) */
+enum { SPX_PTR_I32 = 0, SPX_PTR_I64 = 1 };          /* element type of cp */
+enum { SPX_VAL_F32 = 0, SPX_VAL_F64 = 1, SPX_VAL_I64 = 2, SPX_VAL_BOOL = 3 };
+
+/* Semirings (Section 2: matrices over a semiring (S, +, x)).
+ *   PLUS_TIMES  ordinary (+, x); int64 wraps around (two's complement)
+ *   MIN_PLUS    x = +, + = min        (tropical; shortest two-hop paths)
+ *   SELECT2ND   x returns B's value, + keeps the minimum; A may be BOOL
+ *   SELECT1ST   x returns A's value, + keeps the minimum; B may be BOOL
+ *   OR_AND      boolean; pattern only, no values                        */
+enum { SPX_PLUS_TIMES = 0, SPX_MIN_PLUS = 1, SPX_SELECT2ND = 2, SPX_OR_AND = 3, SPX_SELECT1ST = 4 };
+
+/* A sparse matrix in CSC or DCSC.
+ *   m, n   dimensions (each < 2^31)
+ *   nnz    stored entries
+ *   nzc    DCSC: number of nonempty columns = length of jc (ignored for CSC)
+ *   jc     DCSC only: [nzc] ids of the nonempty columns, strictly increasing
+ *   cp     [n+1] (CSC) or [nzc+1] (DCSC) of type ptr_t, cp[0] = 0, cp[last] = nnz
+ *   ir     [nnz] int32 row ids
+ *   num    [nnz] values of type val_t; not read or written for SPX_VAL_BOOL  */
+typedef struct spx_mat {
+  int64_t m, n, nnz, nzc;
+  int32_t fmt, ptr_t, val_t, reserved;
+  int32_t* jc;
+  void* cp;
+  int32_t* ir;
+  void* num;
+} spx_mat;
+
+/* Execution context.
+ *   stream    hipStream_t to enqueue on (NULL: the null stream)
+ *   alloc     device allocator for scratch (and one-shot outputs); NULL: hipMalloc
+ *   free      matching free; called with the pointer alloc returned
+ *   user      passed to alloc / free
+ *   validate  nonzero: check that inputs are canonical before computing   */
+typedef struct spx_ctx {
+  void* stream;
+  void* (*alloc)(size_t bytes, void* user);
+  void (*free)(void* ptr, void* user);
+  void* user;
+  int32_t validate;
+  int32_t reserved;
+} spx_ctx;
+
+/* Tuning knobs of the SpGEMM kernels (NULL = built-in defaults, which
+ * spx_default_tuning() returns).  Columns are binned by their number of
+ * multiplications (an upper bound on their output size):
+ *   tiny_max      columns with <= tiny_max products are formed in one
+ *                 64-lane wave by sorting their products (<= 64)
+ *   medium_max    columns with <= medium_max products use an LDS hash table
+ *   heavy columns are counted with an LDS bitmap over the row space and
+ *   accumulated in row-range parts whose LDS budget is part_lds_bytes
+ *   medium_threads / heavy_threads  workgroup sizes (multiples of 64)    */
+typedef struct spx_tuning {
+  int32_t tiny_max;
+  int32_t medium_max;
+  int32_t part_lds_bytes;
+  int32_t medium_threads;
+  int32_t heavy_threads;
+  int32_t reserved[3];
+} spx_tuning;
+
+/* Statistics of a SpGEMM plan, available once the plan call returned. */
+typedef struct spx_plan_info {
+  int64_t mults;          /* total number of multiplications (sum over columns) */
+  int64_t nnz;            /* nnz(C) */
+  int64_t nzc;            /* nonempty columns of C */
+  int64_t cols_empty, cols_tiny, cols_medium, cols_heavy;
+  int64_t heavy_parts;    /* row-range parts of heavy columns */
+} spx_plan_info;
+
+typedef struct spx_plan spx_plan;
+
+/* ---- SpGEMM: C = A*B over a semiring (Algorithm 1) --------------------
+ * spx_spgemm_plan: validates A (m x k) and B (k x n), runs the symbolic
+ *   phase on the device and returns nnz(C) and the number of nonempty
+ *   columns nzc(C).  Both operands may be CSC or DCSC.  c_fmt selects the
+ *   output format.  Values: PLUS_TIMES and MIN_PLUS need A and B of one
+ *   value type (F32, F64 or I64); SELECT2ND takes B's type, SELECT1ST A's;
+ *   OR_AND produces a pattern (C.val_t = BOOL).
+ * spx_spgemm_exec: fills C.  The caller sets C->m, n, fmt (= c_fmt),
+ *   ptr_t, val_t and provides buffers: cp [n+1] or [nzc+1] of ptr_t,
+ *   jc [nzc] (DCSC), ir [nnz], num [nnz] (unless BOOL).  SPX_EOVERFLOW if
+ *   ptr_t is I32 and nnz >= 2^31.  Several execs of one plan are allowed.
+ * spx_spgemm: one shot; C's buffers come from ctx->alloc (free them with
+ *   ctx->free, or hipFree when ctx->alloc is NULL).                      */
+int spx_spgemm_plan(const spx_ctx* ctx, const spx_mat* A, const spx_mat* B, int32_t semiring, int32_t c_fmt,
+                    const spx_tuning* tuning, spx_plan** plan, int64_t* nnz_c, int64_t* nzc_c);
+int spx_spgemm_exec(spx_plan* plan, spx_mat* C);
+int spx_spgemm(const spx_ctx* ctx, const spx_mat* A, const spx_mat* B, int32_t semiring, int32_t c_fmt,
+               spx_mat* C);
+int spx_plan_get_info(const spx_plan* plan, spx_plan_info* info);
+void spx_plan_destroy(spx_plan* plan);
+void spx_default_tuning(spx_tuning* tuning);
+
+/* ---- SpRef: B = A(I,J) (Section 4) ------------------------------------
+ * B(p,q) = A(I(p), J(q)) for p < lenI, q < lenJ, respecting the order of I
+ * and J; repeated indices replicate rows / columns.  A is CSC or DCSC,
+ * I and J are device int32 arrays (any order, repeats allowed).  The
+ * product R*(A*Q) is formed right to left: A*Q gathers the columns J,
+ * R selects and reorders rows; every output entry receives exactly one
+ * product, so values are copied bit for bit.
+ * spx_spref_plan returns nnz(B); spx_spref_exec fills B (CSC, lenI x lenJ,
+ * caller-allocated: cp [lenJ+1], ir [nnz], num [nnz]).  SPX_EINVAL if an
+ * index is out of range (checked on the device during the plan).       */
+int spx_spref_plan(const spx_ctx* ctx, const spx_mat* A, const int32_t* I, int64_t lenI, const int32_t* J,
+                   int64_t lenJ, spx_plan** plan, int64_t* nnz_b);
+int spx_spref_exec(spx_plan* plan, spx_mat* B);
+
+/* ---- SpAsgn: C = A with the submatrix A(I,J) replaced by B (Section 4.1)
+ * B is lenI x lenJ (CSC or DCSC).  Functional: A is not modified.  C keeps
+ * every A(i,j) with i not in I or j not in J, and takes
+ * C(I(p), J(q)) = B(p,q) for the stored B(p,q); entries of A(I,J) that B
+ * does not store are removed.  A repeated index resolves to its last
+ * occurrence in I (or J), as in sequential assignment.  A and B must have
+ * the same value type.
+ * spx_spasgn_plan returns nnz(C); spx_spasgn_exec fills C (CSC, m x n,
+ * caller-allocated: cp [n+1], ir [nnz], num [nnz]).                      */
+int spx_spasgn_plan(const spx_ctx* ctx, const spx_mat* A, const int32_t* I, int64_t lenI, const int32_t* J,
+                    int64_t lenJ, const spx_mat* B, spx_plan** plan, int64_t* nnz_c);
+int spx_spasgn_exec(spx_plan* plan, spx_mat* C);
+
+/* ---- formats (Section 3.2) ----------------------------------------------
+ * spx_count_nonempty: nzc of a CSC matrix (synchronises the stream).
+ * spx_csc_to_dcsc: writes out->jc [nzc] and out->cp [nzc+1] (ptr_t of
+ *   out) for the CSC matrix A; out->ir / out->num are set to A's arrays
+ *   (DCSC shares them with CSC).  out->nzc must hold spx_count_nonempty's
+ *   result.
+ * spx_dcsc_to_csc: writes out->cp [n+1] for the DCSC matrix A; ir / num
+ *   are shared likewise.                                                 */
+int spx_count_nonempty(const spx_ctx* ctx, const spx_mat* A, int64_t* nzc);
+int spx_csc_to_dcsc(const spx_ctx* ctx, const spx_mat* A, spx_mat* out);
+int spx_dcsc_to_csc(const spx_ctx* ctx, const spx_mat* A, spx_mat* out);
+
+/* Checks that A is canonical (pointers monotone, rows in range and
+ * strictly increasing per column, jc strictly increasing and in range).
+ * *ok = 1 or 0.  Synchronises the stream.                                */
+int spx_check(const spx_ctx* ctx, const spx_mat* A, int32_t* ok);
+
+/* Thread-local message describing the last error of this thread. */
+const char* spx_last_error(void);
+
+/* Library version string. */
+const char* spx_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SPX_H */

@@ -1,0 +1,237 @@
+// Internal helpers shared by the HIP sources of libspx: error handling,
+// scratch allocation, wave-level primitives and semiring arithmetic.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "spx.h"
+
+namespace spx {
+
+constexpr int kWave = 64;
+
+// ---------------------------------------------------------------- errors
+void set_error(const std::string& msg);
+
+struct Status {
+  int code = SPX_OK;
+  bool ok() const { return code == SPX_OK; }
+};
+
+#define SPX_HIP(call)                                                              \
+  do {                                                                             \
+    hipError_t e_ = (call);                                                        \
+    if (e_ != hipSuccess) {                                                        \
+      ::spx::set_error(std::string(#call) + ": " + hipGetErrorString(e_));         \
+      return SPX_EDEVICE;                                                          \
+    }                                                                              \
+  } while (0)
+
+#define SPX_TRY(expr)          \
+  do {                         \
+    int rc_ = (expr);          \
+    if (rc_ != SPX_OK) return rc_; \
+  } while (0)
+
+inline int fail(int code, const std::string& msg) {
+  set_error(msg);
+  return code;
+}
+
+// ---------------------------------------------------------------- scratch
+// Device buffers taken from the context's allocator (or hipMalloc) and
+// released when the owning object is destroyed.
+class Scratch {
+ public:
+  explicit Scratch(const spx_ctx* ctx);
+  ~Scratch();
+  Scratch(const Scratch&) = delete;
+  Scratch& operator=(const Scratch&) = delete;
+  // Returns SPX_OK and sets *out (256-byte aligned), or SPX_ENOMEM.
+  int get(size_t bytes, void** out);
+  template <typename T>
+  int get_n(size_t count, T** out) {
+    void* p = nullptr;
+    int rc = get(count * sizeof(T) + 16, &p);
+    *out = static_cast<T*>(p);
+    return rc;
+  }
+  void release_all();
+  hipStream_t stream() const { return stream_; }
+
+ private:
+  spx_ctx ctx_;
+  hipStream_t stream_;
+  std::vector<void*> bufs_;
+};
+
+inline hipStream_t stream_of(const spx_ctx* ctx) { return ctx ? (hipStream_t)ctx->stream : (hipStream_t)0; }
+
+int device_cu_count();
+
+// Kernel fills (used instead of hipMemsetAsync so that work enqueued by the
+// library can be captured into a HIP graph).
+int fill_i64(int64_t* p, int64_t n, int64_t v, hipStream_t stream);
+int fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t stream);
+
+inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+inline int64_t next_pow2(int64_t x) {
+  int64_t p = 1;
+  while (p < x) p <<= 1;
+  return p;
+}
+inline unsigned grid_for(int64_t items, int per_block, int64_t cap = 1 << 30) {
+  int64_t g = ceil_div(items, per_block);
+  if (g < 1) g = 1;
+  if (g > cap) g = cap;
+  return (unsigned)g;
+}
+
+// Reads element i of a column-pointer array of either index type.
+__device__ __forceinline__ int64_t load_ptr(const void* p, int32_t ptr_t, int64_t i) {
+  return ptr_t == SPX_PTR_I64 ? reinterpret_cast<const int64_t*>(p)[i]
+                              : (int64_t) reinterpret_cast<const int32_t*>(p)[i];
+}
+__device__ __forceinline__ void store_ptr(void* p, int32_t ptr_t, int64_t i, int64_t v) {
+  if (ptr_t == SPX_PTR_I64)
+    reinterpret_cast<int64_t*>(p)[i] = v;
+  else
+    reinterpret_cast<int32_t*>(p)[i] = (int32_t)v;
+}
+
+// ---------------------------------------------------------------- waves
+__device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_max(T v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    T t = __shfl_xor(v, o);
+    v = t > v ? t : v;
+  }
+  return v;
+}
+
+// Inclusive prefix sum over the 64 lanes.
+template <typename T>
+__device__ __forceinline__ T wave_incl_scan(T v) {
+  const int lane = lane_id();
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    T t = __shfl_up(v, o);
+    if (lane >= o) v += t;
+  }
+  return v;
+}
+
+__device__ __forceinline__ uint64_t lanemask_lt() {
+  const int lane = lane_id();
+  return lane == 0 ? 0ull : (~0ull >> (64 - lane));
+}
+
+// Exclusive block-wide prefix sum of one value per thread; `red` is LDS
+// scratch of at least blockDim.x/64 + 1 entries.  Returns the exclusive
+// prefix and writes the block total to *total (all threads).
+template <typename T>
+__device__ __forceinline__ T block_excl_scan(T v, T* red, T* total) {
+  const int lane = lane_id();
+  const int wid = threadIdx.x / kWave;
+  const int nw = blockDim.x / kWave;
+  T incl = wave_incl_scan(v);
+  if (lane == kWave - 1) red[wid] = incl;
+  __syncthreads();
+  if (wid == 0) {
+    T w = lane < nw ? red[lane] : T(0);
+    T wi = wave_incl_scan(w);
+    if (lane < nw) red[lane] = wi - w;
+    if (lane == nw - 1) red[nw] = wi;
+  }
+  __syncthreads();
+  T res = red[wid] + incl - v;
+  *total = red[nw];
+  __syncthreads();
+  return res;
+}
+
+// ---------------------------------------------------------------- semirings
+// mul: product of A(i,k) and B(k,j); add: combine into an accumulator;
+// lds_acc: atomic combine into LDS; ident: value of an untouched slot.
+template <int SR, typename T>
+struct Semiring;
+
+template <typename T>
+struct Semiring<SPX_PLUS_TIMES, T> {
+  static constexpr bool kUsesA = true, kUsesB = true;
+  __device__ static T mul(T a, T b) { return a * b; }
+  __device__ static T add(T acc, T x) { return acc + x; }
+  __device__ static T ident() { return T(0); }
+  __device__ static void lds_acc(T* p, T x) {
+    __hip_atomic_fetch_add(p, x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  }
+};
+template <>
+struct Semiring<SPX_PLUS_TIMES, int64_t> {
+  static constexpr bool kUsesA = true, kUsesB = true;
+  __device__ static int64_t mul(int64_t a, int64_t b) { return (int64_t)((uint64_t)a * (uint64_t)b); }
+  __device__ static int64_t add(int64_t acc, int64_t x) { return (int64_t)((uint64_t)acc + (uint64_t)x); }
+  __device__ static int64_t ident() { return 0; }
+  __device__ static void lds_acc(int64_t* p, int64_t x) {
+    __hip_atomic_fetch_add(reinterpret_cast<unsigned long long*>(p), (unsigned long long)x, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_WORKGROUP);
+  }
+};
+
+template <typename T>
+__device__ __forceinline__ T pos_inf();
+template <>
+__device__ __forceinline__ float pos_inf<float>() { return __builtin_huge_valf(); }
+template <>
+__device__ __forceinline__ double pos_inf<double>() { return __builtin_huge_val(); }
+template <>
+__device__ __forceinline__ int64_t pos_inf<int64_t>() { return INT64_MAX; }
+
+template <typename T>
+struct MinAcc {
+  __device__ static T add(T acc, T x) { return x < acc ? x : acc; }
+  __device__ static T ident() { return pos_inf<T>(); }
+  __device__ static void lds_acc(T* p, T x) {
+    __hip_atomic_fetch_min(p, x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  }
+};
+
+template <typename T>
+struct Semiring<SPX_MIN_PLUS, T> : MinAcc<T> {
+  static constexpr bool kUsesA = true, kUsesB = true;
+  __device__ static T mul(T a, T b) { return a + b; }
+};
+template <>
+struct Semiring<SPX_MIN_PLUS, int64_t> : MinAcc<int64_t> {
+  static constexpr bool kUsesA = true, kUsesB = true;
+  __device__ static int64_t mul(int64_t a, int64_t b) { return (int64_t)((uint64_t)a + (uint64_t)b); }
+};
+template <typename T>
+struct Semiring<SPX_SELECT2ND, T> : MinAcc<T> {
+  static constexpr bool kUsesA = false, kUsesB = true;
+  __device__ static T mul(T, T b) { return b; }
+};
+template <typename T>
+struct Semiring<SPX_SELECT1ST, T> : MinAcc<T> {
+  static constexpr bool kUsesA = true, kUsesB = false;
+  __device__ static T mul(T a, T) { return a; }
+};
+
+// Pattern-only marker type for OR_AND.
+struct NoVal {};
+
+}  // namespace spx

@@ -1,0 +1,83 @@
+// Error reporting, scratch allocation and small fill kernels of libspx.
+#include "common.h"
+
+#include <mutex>
+
+namespace spx {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+Scratch::Scratch(const spx_ctx* ctx) : stream_(stream_of(ctx)) {
+  if (ctx)
+    ctx_ = *ctx;
+  else
+    ctx_ = spx_ctx{};
+}
+
+Scratch::~Scratch() { release_all(); }
+
+int Scratch::get(size_t bytes, void** out) {
+  *out = nullptr;
+  if (bytes == 0) bytes = 16;
+  bytes = (bytes + 255) & ~(size_t)255;
+  void* p = nullptr;
+  if (ctx_.alloc) {
+    p = ctx_.alloc(bytes, ctx_.user);
+    if (!p) return fail(SPX_ENOMEM, "allocation callback failed for " + std::to_string(bytes) + " bytes");
+  } else {
+    if (hipMalloc(&p, bytes) != hipSuccess || !p) {
+      (void)hipGetLastError();
+      return fail(SPX_ENOMEM, "hipMalloc failed for " + std::to_string(bytes) + " bytes");
+    }
+  }
+  bufs_.push_back(p);
+  *out = p;
+  return SPX_OK;
+}
+
+void Scratch::release_all() {
+  for (void* p : bufs_) {
+    if (ctx_.alloc) {
+      if (ctx_.free) ctx_.free(p, ctx_.user);
+    } else {
+      (void)hipFree(p);
+    }
+  }
+  bufs_.clear();
+}
+
+int device_cu_count() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 256;
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) return 256;
+  return cus;
+}
+
+template <typename T>
+__global__ void k_fill(T* p, int64_t n, T v) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+int fill_i64(int64_t* p, int64_t n, int64_t v, hipStream_t stream) {
+  if (n <= 0) return SPX_OK;
+  k_fill<int64_t><<<grid_for(n, 256, 4096), 256, 0, stream>>>(p, n, v);
+  SPX_HIP(hipGetLastError());
+  return SPX_OK;
+}
+
+int fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t stream) {
+  if (n <= 0) return SPX_OK;
+  k_fill<uint32_t><<<grid_for(n, 256, 4096), 256, 0, stream>>>(p, n, v);
+  SPX_HIP(hipGetLastError());
+  return SPX_OK;
+}
+
+}  // namespace spx
+
+extern "C" const char* spx_last_error(void) { return spx::g_last_error.c_str(); }
+
+extern "C" const char* spx_version(void) { return "spx 0.1 (gfx950)"; }

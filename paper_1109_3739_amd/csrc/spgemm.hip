@@ -1,0 +1,1148 @@
+// SpGEMM C = A*B over a semiring on one gfx950 GPU.
+//
+// What is computed is the column-wise product of Section 3 (Algorithm 1):
+// column j of C is the semiring sum, over the nonzeros B(k,j), of
+// A(:,k) "times" B(k,j).  The paper's local kernel (HyperSparseGEMM, an
+// outer product merged through a priority queue, Section 3.1) is prior art
+// for a serial CPU; here every output column is formed independently by a
+// wave or a workgroup, and the only property kept from the paper's kernel
+// is that no pass is proportional to a matrix dimension when the operands
+// are hypersparse (DCSC operands are iterated over their nonempty columns;
+// the column lookup into a DCSC A uses the AUX index of Section 3.2).
+//
+// Two phases.
+//   plan (symbolic): per-entry lookup of A's columns, per-column number of
+//     multiplications, binning of the columns by that count, exact output
+//     counts (a wave-wide sort for tiny columns, an LDS hash for medium ones,
+//     an LDS bitmap over the row space for heavy ones, which also yields
+//     per-row-block counts), int64 scan into column pointers, and a list of
+//     row-range "parts" (each fits one workgroup's LDS) for the numeric phase.
+//   exec (numeric): tiny columns are re-formed by their wave and written;
+//     every part is accumulated in LDS either through a bitmap over its row
+//     range (rank of a row = popcount prefix, which also yields sorted
+//     output) or through a hash table followed by an LDS bitonic sort.
+#include <algorithm>
+#include <cstring>
+#include <memory>
+
+#include "common.h"
+#include "operand.h"
+#include "plan.h"
+#include "scan.h"
+
+namespace spx {
+
+// Semiring for the boolean (pattern only) case; values are never touched.
+template <typename T>
+struct Semiring<SPX_OR_AND, T> {
+  static constexpr bool kUsesA = false, kUsesB = false;
+  __device__ static T mul(T a, T) { return a; }
+  __device__ static T add(T acc, T) { return acc; }
+  __device__ static T ident() { return T(0); }
+  __device__ static void lds_acc(T*, T) {}
+};
+
+// ------------------------------------------------------------------ bins
+// Columns (slots of B) are binned by their number of multiplications mu.
+// The bin id is also the processing order: heavy columns first.
+//   0 .. 40   bitmap-counted columns, id = 40 - floor(log2 mu)
+//   41 .. 48  hash-counted columns, table of 2^(15 - (id - 41)) keys
+//   49        tiny columns (mu <= tiny_max, at most 64): one wave each
+//   50        columns without products
+constexpr int kBinHash0 = 41;
+constexpr int kBinTiny = 49;
+constexpr int kBinEmpty = 50;
+constexpr int kNumBins = 51;
+constexpr int kHashLog2Max = 15;
+constexpr int kHashLog2Min = 8;
+// Columns with more products than this get per-row-block counts so that
+// their numeric work can be split into row-range parts.
+constexpr int kSinglePartMax = 4096;
+constexpr int kBinMultiEnd = kBinHash0 + (kHashLog2Max - 13);  // bins with tables >= 2^14 keys
+constexpr int kBitmapChunkLog2 = 20;                          // rows per bitmap-count chunk
+
+__device__ __forceinline__ int floor_log2_u64(uint64_t x) { return 63 - __clzll(x); }
+__device__ __forceinline__ int ceil_log2_u64(uint64_t x) { return x <= 1 ? 0 : 64 - __clzll(x - 1); }
+
+struct BinCfg {
+  int64_t tiny_max, hash_max;
+};
+
+__device__ __forceinline__ int bin_of(int64_t mu, const BinCfg& c) {
+  if (mu <= 0) return kBinEmpty;
+  if (mu <= c.tiny_max) return kBinTiny;
+  if (mu <= c.hash_max) {
+    int s = ceil_log2_u64((uint64_t)mu) + 1;
+    if (s < kHashLog2Min) s = kHashLog2Min;
+    return kBinHash0 + (kHashLog2Max - s);
+  }
+  int id = 40 - floor_log2_u64((uint64_t)mu);
+  return id < 0 ? 0 : id;
+}
+
+// ------------------------------------------------------------------ kernels: setup
+// For every stored B(k,j): where column k of A starts and how long it is.
+__global__ void k_rowinfo(Operand A, Operand B, const int64_t* aux, int64_t chunk, int64_t* bq_a0, int32_t* bq_alen,
+                          unsigned* err) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < B.nnz; q += stride) {
+    const int32_t k = B.ir[q];
+    int64_t a0 = 0, a1 = 0;
+    if (k < 0 || k >= A.n) {
+      atomicOr(err, 1u);
+    } else {
+      column_range(A, aux, chunk, k, a0, a1);
+    }
+    bq_a0[q] = a0;
+    bq_alen[q] = (int32_t)(a1 - a0);
+  }
+}
+
+// mults[t] = number of multiplications of output column (slot) t; one wave per slot.
+__global__ void k_slot_mults(Operand B, const int32_t* bq_alen, int64_t nslots, int64_t* mults,
+                             unsigned long long* total) {
+  const int lane = lane_id();
+  const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kWave;
+  const int64_t nwaves = (int64_t)gridDim.x * blockDim.x / kWave;
+  int64_t acc = 0;
+  for (int64_t t = wave; t < nslots; t += nwaves) {
+    const int64_t b0 = slot_begin(B, t), b1 = slot_begin(B, t + 1);
+    int64_t s = 0;
+    for (int64_t q = b0 + lane; q < b1; q += kWave) s += bq_alen[q];
+    s = wave_sum(s);
+    if (lane == 0) {
+      mults[t] = s;
+      acc += s;
+    }
+  }
+  if (lane == 0 && acc) atomicAdd(total, (unsigned long long)acc);
+}
+
+// Counting sort of slots into bins: histogram, offsets, fill.
+__global__ void k_bin_count(const int64_t* mults, int64_t nslots, BinCfg cfg, unsigned long long* counts) {
+  __shared__ unsigned hist[kNumBins];
+  for (int i = threadIdx.x; i < kNumBins; i += blockDim.x) hist[i] = 0;
+  __syncthreads();
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < nslots; t += stride)
+    atomicAdd(&hist[bin_of(mults[t], cfg)], 1u);
+  __syncthreads();
+  for (int i = threadIdx.x; i < kNumBins; i += blockDim.x)
+    if (hist[i]) atomicAdd(&counts[i], (unsigned long long)hist[i]);
+}
+
+__global__ void k_bin_offsets(unsigned long long* counts, int64_t* binoff, unsigned long long* fill) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    int64_t run = 0;
+    for (int i = 0; i < kNumBins; ++i) {
+      binoff[i] = run;
+      fill[i] = 0;
+      run += (int64_t)counts[i];
+    }
+    binoff[kNumBins] = run;
+  }
+}
+
+__global__ void k_bin_fill(const int64_t* mults, int64_t nslots, BinCfg cfg, const int64_t* binoff,
+                           unsigned long long* fill, int32_t* list) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < nslots; t += stride) {
+    const int b = bin_of(mults[t], cfg);
+    const int64_t pos = binoff[b] + (int64_t)atomicAdd(&fill[b], 1ull);
+    list[pos] = (int32_t)t;
+  }
+}
+
+// ------------------------------------------------------------------ product iteration
+// Work on one output column is spread over groups of G lanes (G a power of
+// two, at most 64); each group takes one stored B(k,j) at a time and its G
+// lanes stride through A(:,k).  Only rows in [r0, r1) are visited (a part
+// of the row space); the start inside A(:,k) is found by binary search.
+__device__ __forceinline__ int pick_group(int64_t mults, int64_t nq, int blk) {
+  int64_t avg = nq > 0 ? (mults + nq - 1) / nq : 1;
+  int g = 1;
+  while (g < avg && g < kWave && g < blk) g <<= 1;
+  return g;
+}
+
+__device__ __forceinline__ int32_t lower_bound_i32(const int32_t* a, int32_t n, int32_t key) {
+  int32_t lo = 0, hi = n;
+  while (lo < hi) {
+    const int32_t mid = (lo + hi) >> 1;
+    if (a[mid] < key)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+template <class F>
+__device__ __forceinline__ void for_products(const Operand& A, const int64_t* bq_a0, const int32_t* bq_alen, int64_t b0,
+                                             int64_t b1, int G, int32_t r0, int32_t r1, bool full, F&& f) {
+  const int gid = threadIdx.x / G, gl = threadIdx.x & (G - 1), ng = blockDim.x / G;
+  for (int64_t q = b0 + gid; q < b1; q += ng) {
+    const int64_t a0 = bq_a0[q];
+    const int32_t al = bq_alen[q];
+    const int32_t* col = A.ir + a0;
+    int32_t e = 0;
+    if (!full && al > 0 && r0 > 0) e = lower_bound_i32(col, al, r0);
+    for (e += gl; e < al; e += G) {
+      const int32_t r = col[e];
+      if (!full && r >= r1) break;
+      f(q, a0 + e, r);
+    }
+  }
+}
+
+__device__ __forceinline__ uint32_t hash_row(int32_t r, int log2s) {
+  return ((uint32_t)r * 0x9E3779B1u) >> (32 - log2s);
+}
+
+// ------------------------------------------------------------------ count: tiny (one wave)
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Ascending bitonic sort of one 64-bit key per lane across the wave.
+__device__ __forceinline__ uint64_t wave_sort_u64(uint64_t key) {
+  const int lane = lane_id();
+#pragma unroll
+  for (int k = 2; k <= kWave; k <<= 1) {
+#pragma unroll
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      const uint64_t other = __shfl_xor(key, j);
+      const bool up = (lane & k) == 0;
+      const bool lower = (lane & j) == 0;
+      const uint64_t mn = other < key ? other : key;
+      const uint64_t mx = other < key ? key : other;
+      key = (lower == up) ? mn : mx;
+    }
+  }
+  return key;
+}
+
+// Tiny columns (at most 64 products): the wave gathers every product into
+// LDS, sorts the (row, product index) keys across its lanes, and either
+// counts the distinct rows (COUNT) or sums each run of equal rows in product
+// order -- the order of Algorithm 1 -- and writes the column (!COUNT).
+template <int SR, typename T, bool COUNT>
+__global__ void __launch_bounds__(256) k_tiny(Operand A, Operand B, const int64_t* bq_a0, const int32_t* bq_alen,
+                                              const int32_t* list, const int64_t* binoff, int64_t* cnt,
+                                              const int64_t* off, int32_t* cir, T* cnum) {
+  using S = Semiring<SR, T>;
+  constexpr bool kVal = SR != SPX_OR_AND;
+  __shared__ int32_t s_row[4][kWave];
+  __shared__ int32_t s_aux[4][kWave];
+  __shared__ T s_val[4][kWave];
+  const int w = threadIdx.x / kWave, lane = lane_id();
+  const int64_t beg = binoff[kBinTiny], end = binoff[kBinTiny + 1];
+  for (int64_t pos = beg + (int64_t)blockIdx.x * 4 + w; pos < end; pos += (int64_t)gridDim.x * 4) {
+    const int32_t t = list[pos];
+    const int64_t b0 = slot_begin(B, t), b1 = slot_begin(B, t + 1);
+    int total = 0;
+    for (int64_t qc = b0; qc < b1; qc += kWave) {
+      const int64_t q = qc + lane;
+      const int al = q < b1 ? bq_alen[q] : 0;
+      const int incl = wave_incl_scan(al);
+      const int excl = incl - al;
+      const int ctot = __shfl(incl, kWave - 1);
+      if (ctot == 0) continue;
+      s_aux[w][lane] = -1;
+      wave_sync();
+      if (al > 0 && excl < kWave) s_aux[w][excl] = lane;
+      wave_sync();
+      int o = s_aux[w][lane];
+#pragma unroll
+      for (int d = 1; d < kWave; d <<= 1) {
+        const int u = __shfl_up(o, d);
+        if (lane >= d && u > o) o = u;
+      }
+      const int ostart = __shfl(excl, o < 0 ? 0 : o);
+      if (lane < ctot && total + lane < kWave) {
+        const int64_t qq = qc + o;
+        const int64_t e = bq_a0[qq] + (lane - ostart);
+        s_row[w][total + lane] = A.ir[e];
+        if constexpr (kVal) {
+          const T* an = (const T*)A.num;
+          const T* bn = (const T*)B.num;
+          const T a = S::kUsesA ? an[e] : T(0);
+          const T bv = S::kUsesB ? bn[qq] : T(0);
+          s_val[w][total + lane] = S::mul(a, bv);
+        }
+      }
+      total += ctot;
+      wave_sync();
+    }
+    if (total > kWave) total = kWave;  // cannot happen: the bin holds columns with <= 64 products
+    uint64_t key = lane < total ? (((uint64_t)(uint32_t)s_row[w][lane]) << 32) | (uint32_t)lane : ~0ull;
+    key = wave_sort_u64(key);
+    const int32_t row = (int32_t)(key >> 32);
+    const int idx = (int)(key & 0xffffffffu);
+    const int32_t prev = __shfl_up(row, 1);
+    const bool valid = lane < total;
+    const bool head = valid && (lane == 0 || prev != row);
+    const uint64_t hm = __ballot(head);
+    if (COUNT) {
+      if (lane == 0) cnt[t] = __popcll(hm);
+    } else {
+      wave_sync();
+      s_row[w][lane] = row;
+      s_aux[w][lane] = idx;
+      wave_sync();
+      if (head) {
+        const int64_t o = off[t] + __popcll(hm & lanemask_lt());
+        cir[o] = row;
+        if constexpr (kVal) {
+          T acc = s_val[w][idx];
+          for (int l2 = lane + 1; l2 < total && s_row[w][l2] == row; ++l2) acc = S::add(acc, s_val[w][s_aux[w][l2]]);
+          cnum[o] = acc;
+        }
+      }
+    }
+    wave_sync();
+  }
+}
+
+// ------------------------------------------------------------------ count: hash
+// One workgroup per column; key-only open-addressing table of 2^log2s
+// slots (at least twice the number of products).  Columns listed before
+// position `multi_end` also get their distinct rows counted per row block.
+__global__ void k_count_hash(Operand A, Operand B, const int64_t* bq_a0, const int32_t* bq_alen, const int64_t* mults,
+                             const int32_t* list, const int64_t* binoff, int bin, int log2s, int64_t multi_end,
+                             int rbshift, int64_t nblk, uint32_t* blkcnt, int64_t* cnt, unsigned* err) {
+  extern __shared__ __align__(16) unsigned char lds[];
+  uint32_t* keys = (uint32_t*)lds;
+  const uint32_t S = 1u << log2s;
+  uint32_t* lblk = keys + S;  // per-block counters when they fit
+  __shared__ int64_t red[1024 / kWave + 1];
+  const int64_t beg = binoff[bin], end = binoff[bin + 1];
+  for (int64_t pos = beg + blockIdx.x; pos < end; pos += gridDim.x) {
+    const int32_t t = list[pos];
+    const int64_t b0 = slot_begin(B, t), b1 = slot_begin(B, t + 1);
+    const bool want_blk = pos < multi_end;
+    const bool lds_blk = nblk <= 1024;
+    for (uint32_t i = threadIdx.x; i < S; i += blockDim.x) keys[i] = 0xffffffffu;
+    if (want_blk && lds_blk)
+      for (int64_t i = threadIdx.x; i < nblk; i += blockDim.x) lblk[i] = 0;
+    __syncthreads();
+    const int G = pick_group(mults[t], b1 - b0, blockDim.x);
+    int64_t mine = 0;
+    for_products(A, bq_a0, bq_alen, b0, b1, G, 0, 0, true, [&](int64_t, int64_t, int32_t r) {
+      uint32_t h = hash_row(r, log2s);
+      for (uint32_t probe = 0; probe < S; ++probe) {
+        const uint32_t old = atomicCAS(&keys[h], 0xffffffffu, (uint32_t)r);
+        if (old == 0xffffffffu) {
+          ++mine;
+          return;
+        }
+        if (old == (uint32_t)r) return;
+        h = (h + 1) & (S - 1);
+      }
+      atomicOr(err, 2u);
+    });
+    __syncthreads();
+    int64_t total;
+    block_excl_scan(mine, red, &total);
+    if (threadIdx.x == 0) cnt[t] = total;
+    if (want_blk) {
+      uint32_t* dst = blkcnt + (pos - binoff[0]) * nblk;
+      for (uint32_t i = threadIdx.x; i < S; i += blockDim.x) {
+        const uint32_t key = keys[i];
+        if (key != 0xffffffffu) {
+          if (lds_blk)
+            atomicAdd(&lblk[key >> rbshift], 1u);
+          else
+            atomicAdd(&dst[key >> rbshift], 1u);
+        }
+      }
+      if (lds_blk) {
+        __syncthreads();
+        for (int64_t i = threadIdx.x; i < nblk; i += blockDim.x) dst[i] = lblk[i];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------------ count: bitmap
+// One workgroup per heavy column; an LDS bitmap over (a chunk of) the row
+// space marks every row that receives a product.  Popcounts give the exact
+// column count and the per-row-block counts used to cut parts.
+__global__ void k_count_bitmap(Operand A, Operand B, const int64_t* bq_a0, const int32_t* bq_alen,
+                               const int64_t* mults, const int32_t* list, const int64_t* binoff, int64_t m,
+                               int chunk_words, int rbshift, int64_t nblk, uint32_t* blkcnt, int64_t* cnt) {
+  extern __shared__ __align__(16) unsigned char lds[];
+  uint32_t* bm = (uint32_t*)lds;
+  const int blk_per_chunk = (int)(((int64_t)chunk_words * 32 + (1ll << rbshift) - 1) >> rbshift);
+  uint32_t* lblk = bm + chunk_words;
+  __shared__ int64_t red[1024 / kWave + 1];
+  const int64_t beg = binoff[0], end = binoff[kBinHash0];
+  const int64_t chunk_rows = (int64_t)chunk_words * 32;
+  for (int64_t pos = beg + blockIdx.x; pos < end; pos += gridDim.x) {
+    const int32_t t = list[pos];
+    const int64_t b0 = slot_begin(B, t), b1 = slot_begin(B, t + 1);
+    const int G = pick_group(mults[t], b1 - b0, blockDim.x);
+    uint32_t* dst = blkcnt + (pos - beg) * nblk;
+    int64_t total = 0;
+    for (int64_t c0 = 0; c0 < m; c0 += chunk_rows) {
+      const int64_t c1 = c0 + chunk_rows < m ? c0 + chunk_rows : m;
+      const int words = (int)((c1 - c0 + 31) >> 5);
+      for (int i = threadIdx.x; i < words; i += blockDim.x) bm[i] = 0;
+      for (int i = threadIdx.x; i < blk_per_chunk; i += blockDim.x) lblk[i] = 0;
+      __syncthreads();
+      const bool full = (c0 == 0 && c1 == m);
+      for_products(A, bq_a0, bq_alen, b0, b1, G, (int32_t)c0, (int32_t)c1, full, [&](int64_t, int64_t, int32_t r) {
+        const uint32_t d = (uint32_t)(r - (int32_t)c0);
+        if (d < (uint32_t)(c1 - c0)) atomicOr(&bm[d >> 5], 1u << (d & 31));
+      });
+      __syncthreads();
+      int64_t mine = 0;
+      for (int i = threadIdx.x; i < words; i += blockDim.x) {
+        const int pc = __popc(bm[i]);
+        if (pc) {
+          mine += pc;
+          atomicAdd(&lblk[((int64_t)i * 32) >> rbshift], (uint32_t)pc);
+        }
+      }
+      int64_t ctot;
+      block_excl_scan(mine, red, &ctot);
+      total += ctot;
+      const int64_t bfirst = c0 >> rbshift;
+      for (int i = threadIdx.x; i < blk_per_chunk; i += blockDim.x)
+        if (bfirst + i < nblk) dst[bfirst + i] = lblk[i];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) cnt[t] = total;
+  }
+}
+
+// ------------------------------------------------------------------ parts
+struct Part {
+  int64_t off;   // first output position of the part in C
+  int32_t t;     // slot of B / output column
+  int32_t c;     // outputs in the part
+  int32_t r0, r1;  // row range [r0, r1)
+  int32_t mode;  // 0 = bitmap, 1 = hash
+  int32_t pad;
+};
+
+struct PartCfg {
+  int64_t L;       // LDS bytes per part
+  int64_t m;
+  int32_t sz;      // value bytes (0: pattern only)
+  int32_t rbshift;
+  int64_t nblk;
+};
+
+__device__ __forceinline__ int64_t bitmap_bytes(const PartCfg& p, int64_t span, int64_t c) {
+  const int64_t w = (span + 63) >> 6;
+  return w * 8 + ((w * 2 + 7) & ~7ll) + c * (p.sz > 4 ? p.sz : 4) + 64;
+}
+__device__ __forceinline__ bool bitmap_ok(const PartCfg& p, int64_t span, int64_t c) {
+  return c < 65536 && bitmap_bytes(p, span, c) <= p.L;
+}
+__device__ __forceinline__ int64_t hash_bytes(const PartCfg& p, int64_t c) {
+  int64_t p2 = 64;
+  while (p2 < c) p2 <<= 1;
+  const int64_t S = 2 * p2;
+  return S * 4 + ((S * p.sz + 7) & ~7ll) + p2 * 8 + 64;
+}
+__device__ __forceinline__ bool hash_ok(const PartCfg& p, int64_t c) { return hash_bytes(p, c) <= p.L; }
+
+__device__ __forceinline__ int choose_mode(const PartCfg& p, int64_t span, int64_t c) {
+  const bool bok = bitmap_ok(p, span, c), hok = hash_ok(p, c);
+  if (bok && hok) {
+    const int64_t lg = c > 1 ? ceil_log2_u64((uint64_t)c) : 1;
+    const int64_t bitmap_cost = ((span + 63) >> 6) * 3;
+    const int64_t hash_cost = c * lg * (lg + 1) / 2;
+    return bitmap_cost <= hash_cost ? 0 : 1;
+  }
+  return bok ? 0 : 1;
+}
+
+// Walks the row blocks of one multi-part column greedily: a part grows while
+// it still fits the LDS budget in one of the two modes.  With emit == false
+// only counts parts.
+__device__ int64_t cut_parts(const PartCfg& p, const uint32_t* blk, int32_t t, int64_t base_off, bool emit, Part* out,
+                             unsigned* err) {
+  const int64_t RB = 1ll << p.rbshift;
+  int64_t np = 0, run = 0;
+  int64_t b = 0;
+  while (b < p.nblk) {
+    int64_t c = blk[b];
+    int64_t e = b + 1;
+    while (e < p.nblk) {
+      const int64_t c2 = c + blk[e];
+      const int64_t r1 = (e + 1) * RB < p.m ? (e + 1) * RB : p.m;
+      const int64_t span2 = r1 - b * RB;
+      if (bitmap_ok(p, span2, c2) || hash_ok(p, c2)) {
+        c = c2;
+        ++e;
+      } else {
+        break;
+      }
+    }
+    if (c > 0) {
+      const int64_t r0 = b * RB;
+      const int64_t r1 = e * RB < p.m ? e * RB : p.m;
+      if (!bitmap_ok(p, r1 - r0, c) && !hash_ok(p, c)) atomicOr(err, 4u);
+      if (emit) {
+        Part P;
+        P.off = base_off + run;
+        P.t = t;
+        P.c = (int32_t)c;
+        P.r0 = (int32_t)r0;
+        P.r1 = (int32_t)r1;
+        P.mode = choose_mode(p, r1 - r0, c);
+        P.pad = 0;
+        out[np] = P;
+      }
+      ++np;
+      run += c;
+    }
+    b = e;
+  }
+  return np;
+}
+
+// Number of parts of every non-tiny, nonempty column (list positions
+// [0, npos)), or the parts themselves (emit).
+__global__ void k_parts(PartCfg p, const int32_t* list, int64_t npos, int64_t multi_begin, int64_t multi_end,
+                        const int64_t* cnt, const int64_t* off, const uint32_t* blkcnt, int64_t* nparts,
+                        const int64_t* poff, Part* parts, unsigned* err) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const bool emit = parts != nullptr;
+  for (int64_t pos = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; pos < npos; pos += stride) {
+    const int32_t t = list[pos];
+    const int64_t c = cnt[t];
+    int64_t np;
+    if (c == 0) {
+      np = 0;
+    } else if (pos >= multi_begin && pos < multi_end && !(bitmap_ok(p, p.m, c) || hash_ok(p, c))) {
+      np = cut_parts(p, blkcnt + (pos - multi_begin) * p.nblk, t, off[t], emit, emit ? parts + poff[pos] : nullptr,
+                     err);
+    } else {
+      np = 1;
+      if (!emit && !(bitmap_ok(p, p.m, c) || hash_ok(p, c))) atomicOr(err, 4u);
+      if (emit) {
+        Part P;
+        P.off = off[t];
+        P.t = t;
+        P.c = (int32_t)c;
+        P.r0 = 0;
+        P.r1 = (int32_t)p.m;
+        P.mode = choose_mode(p, p.m, c);
+        P.pad = 0;
+        parts[poff[pos]] = P;
+      }
+    }
+    if (!emit) nparts[pos] = np;
+  }
+}
+
+// ------------------------------------------------------------------ numeric: parts
+template <typename T>
+__device__ __forceinline__ void block_bitonic_sort(uint64_t* a, int n2) {
+  for (int k = 2; k <= n2; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int i = threadIdx.x; i < (n2 >> 1); i += blockDim.x) {
+        const int lo = 2 * i - (i & (j - 1));
+        const int hi = lo + j;
+        const bool asc = (lo & k) == 0;
+        const uint64_t x = a[lo], y = a[hi];
+        if ((x > y) == asc) {
+          a[lo] = y;
+          a[hi] = x;
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// One workgroup per part (dynamic work queue).  Bitmap mode: mark rows,
+// popcount prefix gives each row its rank = output position, accumulate
+// values by rank, write rows and values in order.  Hash mode: accumulate
+// into an open-addressing table, then sort (row, slot) keys.
+template <int SR, typename T>
+__global__ void __launch_bounds__(1024) k_numeric_parts(Operand A, Operand B, const int64_t* bq_a0,
+                                                        const int32_t* bq_alen, const int64_t* mults,
+                                                        const int64_t* cnt, const Part* parts, int64_t nparts,
+                                                        unsigned long long* work, int32_t* cir, T* cnum,
+                                                        unsigned* err) {
+  using S = Semiring<SR, T>;
+  constexpr bool kVal = SR != SPX_OR_AND;
+  extern __shared__ __align__(16) unsigned char lds[];
+  __shared__ int64_t s_pi;
+  __shared__ int64_t red[1024 / kWave + 1];
+  __shared__ unsigned s_ctr;
+  const T* an = (const T*)A.num;
+  const T* bn = (const T*)B.num;
+  for (;;) {
+    if (threadIdx.x == 0) s_pi = (int64_t)atomicAdd(work, 1ull);
+    __syncthreads();
+    const int64_t pi = s_pi;
+    __syncthreads();
+    if (pi >= nparts) break;
+    const Part P = parts[pi];
+    const int64_t b0 = slot_begin(B, P.t), b1 = slot_begin(B, P.t + 1);
+    const int64_t span = (int64_t)P.r1 - P.r0;
+    const bool full = (P.r0 == 0 && P.r1 == (int32_t)A.m);
+    // products in this part ~ mults * c / cnt
+    const int64_t ct = cnt[P.t] > 0 ? cnt[P.t] : 1;
+    const int G = pick_group((mults[P.t] * P.c + ct - 1) / ct, b1 - b0, blockDim.x);
+    const int c = P.c;
+    if (P.mode == 0) {
+      const int W = (int)((span + 63) >> 6);
+      uint64_t* bm = (uint64_t*)lds;
+      uint16_t* pre = (uint16_t*)(bm + W);
+      T* vals = (T*)(lds + W * 8 + ((W * 2 + 7) & ~7));
+      for (int i = threadIdx.x; i < W; i += blockDim.x) bm[i] = 0;
+      if constexpr (kVal)
+        for (int i = threadIdx.x; i < c; i += blockDim.x) vals[i] = S::ident();
+      __syncthreads();
+      for_products(A, bq_a0, bq_alen, b0, b1, G, P.r0, P.r1, full, [&](int64_t, int64_t, int32_t r) {
+        const uint32_t d = (uint32_t)(r - P.r0);
+        atomicOr((unsigned long long*)&bm[d >> 6], 1ull << (d & 63));
+      });
+      __syncthreads();
+      // exclusive popcount prefix per word
+      const int per = (W + blockDim.x - 1) / blockDim.x;
+      const int w0 = threadIdx.x * per;
+      const int w1 = w0 + per < W ? w0 + per : W;
+      int64_t s = 0;
+      for (int i = w0; i < w1; ++i) s += __popcll(bm[i]);
+      int64_t tot;
+      int64_t run = block_excl_scan(s, red, &tot);
+      for (int i = w0; i < w1; ++i) {
+        pre[i] = (uint16_t)run;
+        run += __popcll(bm[i]);
+      }
+      if (threadIdx.x == 0 && tot != c) atomicOr(err, 8u);
+      __syncthreads();
+      if constexpr (kVal) {
+        for_products(A, bq_a0, bq_alen, b0, b1, G, P.r0, P.r1, full, [&](int64_t q, int64_t e, int32_t r) {
+          const uint32_t d = (uint32_t)(r - P.r0);
+          const uint64_t word = bm[d >> 6];
+          const int rank = (int)pre[d >> 6] + __popcll(word & ((1ull << (d & 63)) - 1ull));
+          const T a = S::kUsesA ? an[e] : T(0);
+          const T bv = S::kUsesB ? bn[q] : T(0);
+          if (rank < c) S::lds_acc(&vals[rank], S::mul(a, bv));
+        });
+        __syncthreads();
+        for (int i = threadIdx.x; i < c; i += blockDim.x) cnum[P.off + i] = vals[i];
+        __syncthreads();
+      }
+      int32_t* rows = (int32_t*)(lds + W * 8 + ((W * 2 + 7) & ~7));  // reuses the value area
+      for (int i = w0; i < w1; ++i) {
+        uint64_t word = bm[i];
+        int rk = pre[i];
+        while (word) {
+          const int bit = __ffsll((long long)word) - 1;
+          word &= word - 1;
+          if (rk < c) rows[rk] = P.r0 + i * 64 + bit;
+          ++rk;
+        }
+      }
+      __syncthreads();
+      for (int i = threadIdx.x; i < c; i += blockDim.x) cir[P.off + i] = rows[i];
+      __syncthreads();
+    } else {
+      int p2 = 64;
+      while (p2 < c) p2 <<= 1;
+      const uint32_t Sz = 2u * p2;
+      const int log2s = 31 - __clz(Sz);
+      uint32_t* keys = (uint32_t*)lds;
+      T* vals = (T*)(lds + Sz * 4);
+      uint64_t* sortb = (uint64_t*)(lds + Sz * 4 + ((Sz * sizeof(T) * (kVal ? 1 : 0) + 7) & ~7u));
+      for (uint32_t i = threadIdx.x; i < Sz; i += blockDim.x) {
+        keys[i] = 0xffffffffu;
+        if constexpr (kVal) vals[i] = S::ident();
+      }
+      if (threadIdx.x == 0) s_ctr = 0;
+      __syncthreads();
+      for_products(A, bq_a0, bq_alen, b0, b1, G, P.r0, P.r1, full, [&](int64_t q, int64_t e, int32_t r) {
+        uint32_t h = hash_row(r, log2s);
+        for (uint32_t probe = 0; probe < Sz; ++probe) {
+          const uint32_t old = atomicCAS(&keys[h], 0xffffffffu, (uint32_t)r);
+          if (old == 0xffffffffu || old == (uint32_t)r) {
+            if constexpr (kVal) {
+              const T a = S::kUsesA ? an[e] : T(0);
+              const T bv = S::kUsesB ? bn[q] : T(0);
+              S::lds_acc(&vals[h], S::mul(a, bv));
+            }
+            return;
+          }
+          h = (h + 1) & (Sz - 1);
+        }
+        atomicOr(err, 16u);
+      });
+      __syncthreads();
+      for (uint32_t i = threadIdx.x; i < Sz; i += blockDim.x) {
+        const uint32_t key = keys[i];
+        if (key != 0xffffffffu) {
+          const unsigned p = atomicAdd(&s_ctr, 1u);
+          if ((int)p < p2) sortb[p] = ((uint64_t)key << 32) | i;
+        }
+      }
+      __syncthreads();
+      const int found = (int)s_ctr;
+      if (threadIdx.x == 0 && found != c) atomicOr(err, 32u);
+      for (int i = found + threadIdx.x; i < p2; i += blockDim.x) sortb[i] = ~0ull;
+      __syncthreads();
+      block_bitonic_sort<T>(sortb, p2);
+      for (int i = threadIdx.x; i < c; i += blockDim.x) {
+        const uint64_t k = sortb[i];
+        cir[P.off + i] = (int32_t)(k >> 32);
+        if constexpr (kVal) cnum[P.off + i] = vals[k & 0xffffffffu];
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// ------------------------------------------------------------------ output pointers
+__global__ void k_nonzero_flags_count(const int64_t* cnt, int64_t n, unsigned long long* nz) {
+  int64_t s = 0;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += stride) s += cnt[i] > 0;
+  s = wave_sum(s);
+  if (lane_id() == 0 && s) atomicAdd(nz, (unsigned long long)s);
+}
+
+// CSC output: cp[j] = start of column j.  For a DCSC B, column j's start is
+// the offset of the first slot whose column id is >= j.
+__global__ void k_write_csc_cp(Operand B, const int64_t* off, int64_t nslots, int64_t n, void* cp, int32_t ptr_t) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j <= n; j += stride) {
+    int64_t t = j;
+    if (B.fmt == SPX_DCSC) {
+      int64_t lo = 0, hi = nslots;
+      while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if ((int64_t)B.jc[mid] < j)
+          lo = mid + 1;
+        else
+          hi = mid;
+      }
+      t = lo;
+    }
+    store_ptr(cp, ptr_t, j, off[t]);
+  }
+}
+
+// DCSC output: nonempty slot t becomes entry zoff[t] of jc / cp.
+__global__ void k_write_dcsc(Operand B, const int64_t* cnt, const int64_t* off, const int64_t* zoff, int64_t nslots,
+                             int32_t* jc, void* cp, int32_t ptr_t) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < nslots; t += stride) {
+    if (cnt[t] > 0) {
+      const int64_t u = zoff[t];
+      jc[u] = (int32_t)slot_col(B, t);
+      store_ptr(cp, ptr_t, u, off[t]);
+    }
+    if (t == nslots - 1) store_ptr(cp, ptr_t, zoff[nslots], off[nslots]);
+  }
+}
+
+struct NonzeroFlag {
+  const int64_t* cnt;
+  __device__ int64_t operator()(int64_t i) const { return cnt[i] > 0 ? 1 : 0; }
+};
+
+}  // namespace spx
+
+// ==================================================================== host
+using namespace spx;
+
+namespace spx {
+
+struct Summary {
+  unsigned long long mults;
+  unsigned long long nzc;
+  unsigned long long work;
+  unsigned err;
+  unsigned pad;
+};
+
+struct GemmPlan : spx_plan {
+  explicit GemmPlan(const spx_ctx* c) : spx_plan(c, kPlanGemm) {}
+  Operand A{}, B{};
+  int32_t sr = 0, vt = 0, c_fmt = 0;
+  spx_tuning tune{};
+  int64_t nslots = 0, nnz = 0, nzc = 0, mults = 0, nparts = 0;
+  int64_t binoff_h[kNumBins + 1] = {};
+  int64_t* bq_a0 = nullptr;
+  int32_t* bq_alen = nullptr;
+  int64_t* aux = nullptr;
+  int64_t* mults_d = nullptr;
+  int64_t* cnt = nullptr;
+  int64_t* off = nullptr;
+  int64_t* zoff = nullptr;
+  int32_t* list = nullptr;
+  int64_t* binoff = nullptr;
+  Part* parts = nullptr;
+  Summary* sum = nullptr;
+  int64_t L = 0;
+};
+
+int check_mat(const spx_mat* X, const char* name) {
+  if (!X) return fail(SPX_EINVAL, std::string(name) + " is NULL");
+  if (X->m < 0 || X->n < 0 || X->nnz < 0 || X->m >= (1ll << 31) || X->n >= (1ll << 31))
+    return fail(SPX_EINVAL, std::string(name) + ": bad dimensions");
+  if (X->fmt != SPX_CSC && X->fmt != SPX_DCSC) return fail(SPX_EINVAL, std::string(name) + ": bad format");
+  if (X->ptr_t != SPX_PTR_I32 && X->ptr_t != SPX_PTR_I64) return fail(SPX_EINVAL, std::string(name) + ": bad ptr_t");
+  if (X->val_t < SPX_VAL_F32 || X->val_t > SPX_VAL_BOOL) return fail(SPX_EINVAL, std::string(name) + ": bad val_t");
+  if (X->ptr_t == SPX_PTR_I32 && X->nnz >= (1ll << 31)) return fail(SPX_EOVERFLOW, std::string(name) + ": nnz needs I64 pointers");
+  if (X->fmt == SPX_DCSC && (X->nzc < 0 || X->nzc > X->n || (X->nzc > 0 && !X->jc)))
+    return fail(SPX_EINVAL, std::string(name) + ": bad DCSC nzc/jc");
+  if (!X->cp) return fail(SPX_EINVAL, std::string(name) + ": cp is NULL");
+  if (X->nnz > 0 && !X->ir) return fail(SPX_EINVAL, std::string(name) + ": ir is NULL");
+  if (X->nnz > 0 && X->val_t != SPX_VAL_BOOL && !X->num) return fail(SPX_EINVAL, std::string(name) + ": num is NULL");
+  return SPX_OK;
+}
+
+int build_aux(const Operand& X, Scratch& scr, hipStream_t st, int64_t** aux, int64_t* chunk) {
+  *aux = nullptr;
+  *chunk = 1;
+  if (X.fmt != SPX_DCSC) return SPX_OK;
+  *chunk = std::max<int64_t>(1, ceil_div(std::max<int64_t>(X.n, 1), std::max<int64_t>(X.nzc, 1)));
+  const int64_t naux = ceil_div(std::max<int64_t>(X.n, 1), *chunk);
+  SPX_TRY(scr.get_n(naux + 1, aux));
+  k_build_aux<<<grid_for(naux + 1, 256), 256, 0, st>>>(X.jc, X.nzc, *chunk, naux, *aux);
+  SPX_HIP(hipGetLastError());
+  return SPX_OK;
+}
+
+int summary_sync(GemmPlan* P, hipStream_t st, Summary* host) {
+  SPX_HIP(hipMemcpyAsync(host, P->sum, sizeof(Summary), hipMemcpyDeviceToHost, st));
+  SPX_HIP(hipStreamSynchronize(st));
+  return SPX_OK;
+}
+
+}  // namespace spx
+
+extern "C" void spx_default_tuning(spx_tuning* t) {
+  std::memset(t, 0, sizeof(*t));
+  t->tiny_max = 64;
+  t->medium_max = 1 << 14;
+  t->part_lds_bytes = 144 * 1024;
+  t->medium_threads = 256;
+  t->heavy_threads = 1024;
+}
+
+template <int SR, typename T>
+static int launch_numeric(GemmPlan* P, spx_mat* C, hipStream_t st) {
+  int32_t* cir = C->ir;
+  T* cnum = (T*)C->num;
+  unsigned* err = &P->sum->err;
+  const int cus = device_cu_count();
+  if (P->nparts > 0) {
+    unsigned long long* work = &P->sum->work;
+    SPX_TRY(fill_i64((int64_t*)work, 1, 0, st));
+    const int blk = P->tune.heavy_threads;
+    const int per_cu = std::max<int64_t>(1, (160 * 1024) / (P->L + 2048));
+    const unsigned grid = (unsigned)std::min<int64_t>(P->nparts, (int64_t)cus * per_cu);
+    hipLaunchKernelGGL((k_numeric_parts<SR, T>), dim3(grid), dim3(blk), (size_t)P->L, st, P->A, P->B, P->bq_a0,
+                       P->bq_alen, P->mults_d, P->cnt, P->parts, P->nparts, work, cir, cnum, err);
+    SPX_HIP(hipGetLastError());
+  }
+  const int64_t ntiny = P->binoff_h[kBinTiny + 1] - P->binoff_h[kBinTiny];
+  if (ntiny > 0) {
+    hipLaunchKernelGGL((k_tiny<SR, T, false>), dim3(grid_for(ntiny, 4, (int64_t)cus * 16)), dim3(256), 0, st, P->A,
+                       P->B, P->bq_a0, P->bq_alen, P->list, P->binoff, P->cnt, P->off, cir, cnum);
+    SPX_HIP(hipGetLastError());
+  }
+  return SPX_OK;
+}
+
+static int dispatch_numeric(GemmPlan* P, spx_mat* C, hipStream_t st) {
+#define SPX_CASE(SRV, VTV, TY) \
+  if (P->sr == SRV && P->vt == VTV) return launch_numeric<SRV, TY>(P, C, st);
+  SPX_CASE(SPX_PLUS_TIMES, SPX_VAL_F32, float)
+  SPX_CASE(SPX_PLUS_TIMES, SPX_VAL_F64, double)
+  SPX_CASE(SPX_PLUS_TIMES, SPX_VAL_I64, int64_t)
+  SPX_CASE(SPX_MIN_PLUS, SPX_VAL_F32, float)
+  SPX_CASE(SPX_MIN_PLUS, SPX_VAL_F64, double)
+  SPX_CASE(SPX_MIN_PLUS, SPX_VAL_I64, int64_t)
+  SPX_CASE(SPX_SELECT2ND, SPX_VAL_F32, float)
+  SPX_CASE(SPX_SELECT2ND, SPX_VAL_F64, double)
+  SPX_CASE(SPX_SELECT2ND, SPX_VAL_I64, int64_t)
+  SPX_CASE(SPX_SELECT1ST, SPX_VAL_F32, float)
+  SPX_CASE(SPX_SELECT1ST, SPX_VAL_F64, double)
+  SPX_CASE(SPX_SELECT1ST, SPX_VAL_I64, int64_t)
+  if (P->sr == SPX_OR_AND || P->vt == SPX_VAL_BOOL) return launch_numeric<SPX_OR_AND, float>(P, C, st);
+#undef SPX_CASE
+  return fail(SPX_EUNSUPPORTED, "semiring / value type combination not provided");
+}
+
+// Result value type of a product, or -1 when the combination is not provided.
+static int result_type(int32_t sr, const spx_mat* A, const spx_mat* B) {
+  switch (sr) {
+    case SPX_PLUS_TIMES:
+    case SPX_MIN_PLUS:
+      if (A->val_t != B->val_t || A->val_t == SPX_VAL_BOOL) return -1;
+      return A->val_t;
+    case SPX_SELECT2ND: return B->val_t;
+    case SPX_SELECT1ST: return A->val_t;
+    case SPX_OR_AND: return SPX_VAL_BOOL;
+    default: return -1;
+  }
+}
+
+extern "C" int spx_spgemm_plan(const spx_ctx* ctx, const spx_mat* A, const spx_mat* B, int32_t semiring,
+                               int32_t c_fmt, const spx_tuning* tuning, spx_plan** plan, int64_t* nnz_c,
+                               int64_t* nzc_c) {
+  if (!plan) return fail(SPX_EINVAL, "plan is NULL");
+  *plan = nullptr;
+  SPX_TRY(check_mat(A, "A"));
+  SPX_TRY(check_mat(B, "B"));
+  if (A->n != B->m) return fail(SPX_EINVAL, "inner dimensions differ: A is m x k, B must be k x n");
+  if (c_fmt != SPX_CSC && c_fmt != SPX_DCSC) return fail(SPX_EINVAL, "bad output format");
+  const int vt = result_type(semiring, A, B);
+  if (vt < 0) return fail(SPX_EUNSUPPORTED, "semiring / value type combination not provided");
+  spx_tuning tune;
+  spx_default_tuning(&tune);
+  if (tuning) tune = *tuning;
+  if (tune.tiny_max < 0 || tune.tiny_max > 64) return fail(SPX_EINVAL, "tiny_max must be in [0, 64]");
+  if (tune.medium_max < tune.tiny_max || tune.medium_max > (1 << 14))
+    return fail(SPX_EINVAL, "medium_max must be in [tiny_max, 16384]");
+  if (tune.heavy_threads % 64 || tune.heavy_threads < 64 || tune.heavy_threads > 1024 || tune.medium_threads % 64 ||
+      tune.medium_threads < 64 || tune.medium_threads > 1024)
+    return fail(SPX_EINVAL, "thread counts must be multiples of 64 in [64, 1024]");
+
+  auto* P = new GemmPlan(ctx);
+  std::unique_ptr<GemmPlan> guard(P);
+  hipStream_t st = stream_of(ctx);
+  Scratch& scr = P->scratch;
+  P->A = make_operand(A);
+  P->B = make_operand(B);
+  P->sr = semiring;
+  P->vt = vt;
+  P->c_fmt = c_fmt;
+  P->tune = tune;
+  const int sz = value_size(vt);
+  const int64_t m = A->m;
+  P->nslots = nslots_of(P->B);
+  const int64_t nslots = P->nslots;
+  const int cus = device_cu_count();
+
+  // Row blocks: the largest power of two <= 2^14 such that one dense block
+  // fits a part in bitmap mode.
+  int64_t L = tune.part_lds_bytes;
+  if (L > 160 * 1024 - 4096) L = 160 * 1024 - 4096;
+  int rb = 14;
+  while (rb > 6 && ((1ll << rb) * sz + ((1ll << rb) / 64) * 10 + 256) > L) --rb;
+  if (((1ll << rb) * sz + ((1ll << rb) / 64) * 10 + 256) > L) return fail(SPX_EINVAL, "part_lds_bytes too small");
+  P->L = L;
+  const int64_t nblk = std::max<int64_t>(1, ceil_div(m, 1ll << rb));
+
+  SPX_TRY(scr.get_n(1, &P->sum));
+  SPX_TRY(fill_i64((int64_t*)P->sum, sizeof(Summary) / 8, 0, st));
+  SPX_TRY(scr.get_n(std::max<int64_t>(B->nnz, 1), &P->bq_a0));
+  SPX_TRY(scr.get_n(std::max<int64_t>(B->nnz, 1), &P->bq_alen));
+  SPX_TRY(scr.get_n(std::max<int64_t>(nslots, 1), &P->mults_d));
+  SPX_TRY(scr.get_n(std::max<int64_t>(nslots, 1), &P->cnt));
+  SPX_TRY(scr.get_n(nslots + 1, &P->off));
+  SPX_TRY(scr.get_n(nslots + 1, &P->zoff));
+  SPX_TRY(scr.get_n(std::max<int64_t>(nslots, 1), &P->list));
+  SPX_TRY(scr.get_n(kNumBins + 1, &P->binoff));
+  unsigned long long *bincount = nullptr, *binfill = nullptr;
+  SPX_TRY(scr.get_n(kNumBins, &bincount));
+  SPX_TRY(scr.get_n(kNumBins, &binfill));
+  SPX_TRY(fill_i64((int64_t*)bincount, kNumBins, 0, st));
+  SPX_TRY(fill_i64(P->cnt, std::max<int64_t>(nslots, 1), 0, st));
+  unsigned* err = &P->sum->err;
+
+  // AUX index for a DCSC A
+  int64_t chunk = 1;
+  SPX_TRY(build_aux(P->A, scr, st, &P->aux, &chunk));
+  if (B->nnz > 0) {
+    k_rowinfo<<<grid_for(B->nnz, 256, (int64_t)cus * 32), 256, 0, st>>>(P->A, P->B, P->aux, chunk, P->bq_a0,
+                                                                         P->bq_alen, err);
+    SPX_HIP(hipGetLastError());
+  }
+  BinCfg bc{tune.tiny_max, tune.medium_max};
+  if (nslots > 0) {
+    k_slot_mults<<<grid_for(nslots * kWave, 256, (int64_t)cus * 32), 256, 0, st>>>(P->B, P->bq_alen, nslots,
+                                                                                   P->mults_d, &P->sum->mults);
+    SPX_HIP(hipGetLastError());
+    k_bin_count<<<grid_for(nslots, 256, (int64_t)cus * 8), 256, 0, st>>>(P->mults_d, nslots, bc, bincount);
+    SPX_HIP(hipGetLastError());
+  }
+  k_bin_offsets<<<1, 64, 0, st>>>(bincount, P->binoff, binfill);
+  SPX_HIP(hipGetLastError());
+  if (nslots > 0) {
+    k_bin_fill<<<grid_for(nslots, 256, (int64_t)cus * 8), 256, 0, st>>>(P->mults_d, nslots, bc, P->binoff, binfill,
+                                                                        P->list);
+    SPX_HIP(hipGetLastError());
+  }
+  // sync 1: bin sizes and the total number of multiplications
+  Summary hs{};
+  SPX_HIP(hipMemcpyAsync(P->binoff_h, P->binoff, sizeof(P->binoff_h), hipMemcpyDeviceToHost, st));
+  SPX_TRY(summary_sync(P, st, &hs));
+  if (hs.err & 1u) return fail(SPX_EINVAL, "B has a row index outside A's columns");
+  P->mults = (int64_t)hs.mults;
+  const int64_t* bo = P->binoff_h;
+  const int64_t multi_begin = bo[0], multi_end = bo[kBinMultiEnd];
+  const int64_t nmulti = multi_end - multi_begin;
+  uint32_t* blkcnt = nullptr;
+  if (nmulti > 0) {
+    if ((double)nmulti * (double)nblk * 4.0 > 8e9) return fail(SPX_EUNSUPPORTED, "row-block table too large");
+    SPX_TRY(scr.get_n(nmulti * nblk, &blkcnt));
+    SPX_TRY(fill_u32(blkcnt, nmulti * nblk, 0, st));
+  }
+
+  // exact counts
+  const int64_t ntiny = bo[kBinTiny + 1] - bo[kBinTiny];
+  if (ntiny > 0) {
+    k_tiny<SPX_OR_AND, float, true><<<grid_for(ntiny, 4, (int64_t)cus * 16), 256, 0, st>>>(
+        P->A, P->B, P->bq_a0, P->bq_alen, P->list, P->binoff, P->cnt, nullptr, nullptr, nullptr);
+    SPX_HIP(hipGetLastError());
+  }
+  for (int b = kBinHash0; b < kBinTiny; ++b) {
+    const int64_t nb = bo[b + 1] - bo[b];
+    if (nb == 0) continue;
+    const int log2s = kHashLog2Max - (b - kBinHash0);
+    const size_t lds = ((size_t)4 << log2s) + (nblk <= 1024 ? (size_t)nblk * 4 : 0);
+    const int blk = log2s >= 13 ? std::max(tune.medium_threads, 512) : tune.medium_threads;
+    const int per_cu = std::max<int>(1, (int)((160 * 1024) / (lds + 1024)));
+    k_count_hash<<<(unsigned)std::min<int64_t>(nb, (int64_t)cus * per_cu), blk, lds, st>>>(
+        P->A, P->B, P->bq_a0, P->bq_alen, P->mults_d, P->list, P->binoff, b, log2s, multi_end, rb, nblk, blkcnt,
+        P->cnt, err);
+    SPX_HIP(hipGetLastError());
+  }
+  const int64_t nbitmap = bo[kBinHash0] - bo[0];
+  if (nbitmap > 0) {
+    const int64_t mw = ceil_div(std::max<int64_t>(m, 1), 32);
+    const int chunk_words = (int)std::min<int64_t>(mw, 1ll << (kBitmapChunkLog2 - 5));
+    const int blk_per_chunk = (int)ceil_div((int64_t)chunk_words * 32, 1ll << rb);
+    const size_t lds = (size_t)chunk_words * 4 + (size_t)blk_per_chunk * 4 + 16;
+    const int per_cu = std::max<int>(1, (int)((160 * 1024) / (lds + 1024)));
+    k_count_bitmap<<<(unsigned)std::min<int64_t>(nbitmap, (int64_t)cus * per_cu), tune.heavy_threads, lds, st>>>(
+        P->A, P->B, P->bq_a0, P->bq_alen, P->mults_d, P->list, P->binoff, m, chunk_words, rb, nblk, blkcnt, P->cnt);
+    SPX_HIP(hipGetLastError());
+  }
+  // column pointers and nonempty-column offsets
+  SPX_TRY(exclusive_scan(LoadI64{P->cnt}, nslots, P->off, scr, st));
+  SPX_TRY(exclusive_scan(NonzeroFlag{P->cnt}, nslots, P->zoff, scr, st));
+  // parts of the non-tiny columns: list positions [0, bo[kBinTiny])
+  const int64_t npos = bo[kBinTiny];
+  int64_t *np = nullptr, *poff = nullptr;
+  PartCfg pc{L, m, sz, rb, nblk};
+  if (npos > 0) {
+    SPX_TRY(scr.get_n(npos, &np));
+    SPX_TRY(scr.get_n(npos + 1, &poff));
+    k_parts<<<grid_for(npos, 256, (int64_t)cus * 16), 256, 0, st>>>(pc, P->list, npos, multi_begin, multi_end, P->cnt,
+                                                                    P->off, blkcnt, np, nullptr, nullptr, err);
+    SPX_HIP(hipGetLastError());
+    SPX_TRY(exclusive_scan(LoadI64{np}, npos, poff, scr, st));
+  }
+  // sync 2: sizes
+  int64_t tail[3] = {0, 0, 0};
+  SPX_HIP(hipMemcpyAsync(&tail[0], P->off + nslots, 8, hipMemcpyDeviceToHost, st));
+  SPX_HIP(hipMemcpyAsync(&tail[1], P->zoff + nslots, 8, hipMemcpyDeviceToHost, st));
+  if (npos > 0) SPX_HIP(hipMemcpyAsync(&tail[2], poff + npos, 8, hipMemcpyDeviceToHost, st));
+  SPX_TRY(summary_sync(P, st, &hs));
+  if (hs.err & 4u) return fail(SPX_EUNSUPPORTED, "a row block is too dense for the LDS budget");
+  P->nnz = tail[0];
+  P->nzc = tail[1];
+  P->nparts = tail[2];
+  if (P->nparts > 0) {
+    SPX_TRY(scr.get_n(P->nparts, &P->parts));
+    k_parts<<<grid_for(npos, 256, (int64_t)cus * 16), 256, 0, st>>>(pc, P->list, npos, multi_begin, multi_end, P->cnt,
+                                                                    P->off, blkcnt, nullptr, poff, P->parts, err);
+    SPX_HIP(hipGetLastError());
+  }
+  if (nnz_c) *nnz_c = P->nnz;
+  if (nzc_c) *nzc_c = P->nzc;
+  *plan = guard.release();
+  return SPX_OK;
+}
+
+extern "C" int spx_spgemm_exec(spx_plan* plan, spx_mat* C) {
+  if (!plan || plan->kind != kPlanGemm) return fail(SPX_EINVAL, "not a SpGEMM plan");
+  auto* P = static_cast<GemmPlan*>(plan);
+  if (!C) return fail(SPX_EINVAL, "C is NULL");
+  if (C->m != P->A.m || C->n != P->B.n) return fail(SPX_EINVAL, "C has the wrong dimensions");
+  if (C->fmt != P->c_fmt) return fail(SPX_EINVAL, "C's format differs from the planned one");
+  if (C->val_t != P->vt) return fail(SPX_EINVAL, "C's value type differs from the product's");
+  if (C->ptr_t != SPX_PTR_I32 && C->ptr_t != SPX_PTR_I64) return fail(SPX_EINVAL, "bad C ptr_t");
+  if (C->ptr_t == SPX_PTR_I32 && P->nnz >= (1ll << 31)) return fail(SPX_EOVERFLOW, "nnz(C) needs I64 pointers");
+  if (!C->cp || (P->nnz > 0 && !C->ir) || (P->nnz > 0 && P->vt != SPX_VAL_BOOL && !C->num) ||
+      (C->fmt == SPX_DCSC && P->nzc > 0 && !C->jc))
+    return fail(SPX_EINVAL, "C buffers missing");
+  C->nnz = P->nnz;
+  C->nzc = C->fmt == SPX_DCSC ? P->nzc : 0;
+  hipStream_t st = stream_of(&P->ctx);
+  if (P->nnz > 0) SPX_TRY(dispatch_numeric(P, C, st));
+  if (C->fmt == SPX_CSC) {
+    k_write_csc_cp<<<grid_for(C->n + 1, 256, 65536), 256, 0, st>>>(P->B, P->off, P->nslots, C->n, C->cp, C->ptr_t);
+  } else if (P->nslots > 0) {
+    k_write_dcsc<<<grid_for(P->nslots, 256, 65536), 256, 0, st>>>(P->B, P->cnt, P->off, P->zoff, P->nslots, C->jc,
+                                                                   C->cp, C->ptr_t);
+  } else {
+    if (C->ptr_t == SPX_PTR_I64)
+      SPX_TRY(fill_i64((int64_t*)C->cp, 1, 0, st));
+    else
+      SPX_TRY(fill_u32((uint32_t*)C->cp, 1, 0, st));
+  }
+  SPX_HIP(hipGetLastError());
+  return SPX_OK;
+}
+
+extern "C" int spx_plan_get_info(const spx_plan* plan, spx_plan_info* info) {
+  if (!plan || !info) return fail(SPX_EINVAL, "NULL argument");
+  std::memset(info, 0, sizeof(*info));
+  if (plan->kind != kPlanGemm) return SPX_OK;
+  auto* P = static_cast<const GemmPlan*>(plan);
+  const int64_t* bo = P->binoff_h;
+  info->mults = P->mults;
+  info->nnz = P->nnz;
+  info->nzc = P->nzc;
+  info->cols_empty = bo[kBinEmpty + 1] - bo[kBinEmpty];
+  info->cols_tiny = bo[kBinTiny + 1] - bo[kBinTiny];
+  info->cols_medium = bo[kBinTiny] - bo[kBinHash0];
+  info->cols_heavy = bo[kBinHash0] - bo[0];
+  info->heavy_parts = P->nparts;
+  return SPX_OK;
+}
+
+extern "C" void spx_plan_destroy(spx_plan* plan) { delete plan; }
+
+static void* default_alloc(size_t bytes, void*) {
+  void* p = nullptr;
+  if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
+  return p;
+}
+
+extern "C" int spx_spgemm(const spx_ctx* ctx, const spx_mat* A, const spx_mat* B, int32_t semiring, int32_t c_fmt,
+                          spx_mat* C) {
+  if (!C) return fail(SPX_EINVAL, "C is NULL");
+  spx_plan* plan = nullptr;
+  int64_t nnz = 0, nzc = 0;
+  SPX_TRY(spx_spgemm_plan(ctx, A, B, semiring, c_fmt, nullptr, &plan, &nnz, &nzc));
+  std::unique_ptr<spx_plan> guard(plan);
+  auto* P = static_cast<GemmPlan*>(plan);
+  void* (*al)(size_t, void*) = (ctx && ctx->alloc) ? ctx->alloc : default_alloc;
+  void* user = ctx ? ctx->user : nullptr;
+  spx_mat out{};
+  out.m = A->m;
+  out.n = B->n;
+  out.fmt = c_fmt;
+  out.ptr_t = SPX_PTR_I64;
+  out.val_t = P->vt;
+  const int64_t ncp = (c_fmt == SPX_CSC ? B->n : nzc) + 1;
+  out.cp = al((size_t)ncp * 8, user);
+  out.ir = (int32_t*)al((size_t)std::max<int64_t>(nnz, 1) * 4, user);
+  out.num = P->vt == SPX_VAL_BOOL ? nullptr : al((size_t)std::max<int64_t>(nnz, 1) * value_size(P->vt), user);
+  out.jc = c_fmt == SPX_DCSC ? (int32_t*)al((size_t)std::max<int64_t>(nzc, 1) * 4, user) : nullptr;
+  if (!out.cp || !out.ir || (P->vt != SPX_VAL_BOOL && !out.num) || (c_fmt == SPX_DCSC && !out.jc))
+    return fail(SPX_ENOMEM, "allocation of C failed");
+  SPX_TRY(spx_spgemm_exec(plan, &out));
+  *C = out;
+  return SPX_OK;
+}

@@ -1,0 +1,435 @@
+// SpRef B = A(I,J) (Section 4) as the selection-matrix product R*A*Q, with
+// R = sparse(1:len(I), I, 1) and Q = sparse(J, 1:len(J), 1).
+//
+// The product is evaluated right to left, R*(A*Q), and fused:
+//   * A*Q: column q of A*Q is column J(q) of A (Q has one nonzero per column),
+//     so it is a gather of A's columns -- no arithmetic;
+//   * R*(AQ): R has one nonzero per row, so every entry (i, v) of column q
+//     is copied to the rows p with I(p) = i.  The transpose of R in
+//     compressed form (for each row index i the ascending list of p with
+//     I(p) = i) is built once by sorting the pairs (I(p), p).
+// Every output entry receives exactly one product (flops(R*A) = nnz(R*A)),
+// so there is no semiring addition and the values are copied bit for bit.
+// Rows of each output column are put in ascending p order by a wave-wide
+// sort (<= 64 entries), an LDS bitonic sort (<= 4096), or, for longer
+// columns, by scanning p in order and probing A(:,J(q)) by binary search.
+#include <algorithm>
+
+#include "common.h"
+#include "operand.h"
+#include "plan.h"
+#include "scan.h"
+#include "sort.h"
+
+namespace spx {
+
+constexpr int kRefSmall = 64;
+constexpr int kRefMedium = 4096;
+enum { kClsEmpty = 0, kClsSmall = 1, kClsMedium = 2, kClsLarge = 3, kNumCls = 4 };
+
+struct SprefPlan : spx_plan {
+  explicit SprefPlan(const spx_ctx* c) : spx_plan(c, kPlanSpref) {}
+  Operand A{};
+  const int32_t* I = nullptr;
+  const int32_t* J = nullptr;
+  int64_t lenI = 0, lenJ = 0, nnz = 0;
+  int64_t* rptr = nullptr;   // [m+1] start of row index i in rpos
+  int32_t* rpos = nullptr;   // [lenI] positions p grouped by I(p), ascending
+  int64_t* qa0 = nullptr;    // [lenJ] start of A(:,J(q))
+  int32_t* qlen = nullptr;   // [lenJ] its length
+  int64_t* cnt = nullptr;    // [lenJ] nnz(B(:,q))
+  int64_t* off = nullptr;    // [lenJ+1]
+  int32_t* list = nullptr;   // [lenJ] columns grouped by class
+  int64_t* clsoff = nullptr; // [kNumCls+1]
+  int64_t clsoff_h[kNumCls + 1] = {};
+  unsigned* err = nullptr;
+};
+
+__global__ void k_check_index(const int32_t* v, int64_t len, int64_t bound, unsigned* err, unsigned bit) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < len; i += (int64_t)gridDim.x * blockDim.x)
+    if (v[i] < 0 || v[i] >= bound) atomicOr(err, bit);
+}
+
+__global__ void k_row_hist(const int32_t* I, int64_t lenI, int64_t m, unsigned* rcnt) {
+  for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < lenI; p += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t i = I[p];
+    if (i >= 0 && i < m) atomicAdd(&rcnt[i], 1u);
+  }
+}
+
+struct LoadU32 {
+  const unsigned* p;
+  __device__ int64_t operator()(int64_t i) const { return (int64_t)p[i]; }
+};
+
+__global__ void k_pair_keys(const int32_t* I, int64_t lenI, uint64_t* keys) {
+  for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < lenI; p += (int64_t)gridDim.x * blockDim.x)
+    keys[p] = ((uint64_t)(uint32_t)I[p] << 32) | (uint32_t)p;
+}
+
+__global__ void k_low32(const uint64_t* keys, int64_t n, int32_t* out) {
+  for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < n; s += (int64_t)gridDim.x * blockDim.x)
+    out[s] = (int32_t)(keys[s] & 0xffffffffu);
+}
+
+__global__ void k_col_info(Operand A, const int64_t* aux, int64_t chunk, const int32_t* J, int64_t lenJ, int64_t* qa0,
+                           int32_t* qlen) {
+  for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < lenJ; q += (int64_t)gridDim.x * blockDim.x) {
+    int64_t a0 = 0, a1 = 0;
+    const int32_t k = J[q];
+    if (k >= 0 && k < A.n) column_range(A, aux, chunk, k, a0, a1);
+    qa0[q] = a0;
+    qlen[q] = (int32_t)(a1 - a0);
+  }
+}
+
+// nnz(B(:,q)) = sum over the entries (i, v) of A(:,J(q)) of |{p : I(p) = i}|;
+// one wave per column.  Also classifies the column.
+__global__ void k_ref_count(const Operand A, const int64_t* qa0, const int32_t* qlen, const int64_t* rptr, int64_t lenJ,
+                            int64_t* cnt, unsigned long long* clscount) {
+  const int lane = lane_id();
+  const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kWave;
+  const int64_t nw = (int64_t)gridDim.x * blockDim.x / kWave;
+  for (int64_t q = wave; q < lenJ; q += nw) {
+    const int64_t a0 = qa0[q];
+    const int32_t al = qlen[q];
+    int64_t s = 0;
+    for (int32_t e = lane; e < al; e += kWave) {
+      const int32_t i = A.ir[a0 + e];
+      s += rptr[i + 1] - rptr[i];
+    }
+    s = wave_sum(s);
+    if (lane == 0) {
+      cnt[q] = s;
+      const int c = s == 0 ? kClsEmpty : s <= kRefSmall ? kClsSmall : s <= kRefMedium ? kClsMedium : kClsLarge;
+      atomicAdd(&clscount[c], 1ull);
+    }
+  }
+}
+
+__global__ void k_cls_offsets(unsigned long long* clscount, int64_t* clsoff, unsigned long long* fill) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    int64_t run = 0;
+    for (int c = 0; c < kNumCls; ++c) {
+      clsoff[c] = run;
+      fill[c] = 0;
+      run += (int64_t)clscount[c];
+    }
+    clsoff[kNumCls] = run;
+  }
+}
+
+__global__ void k_cls_fill(const int64_t* cnt, int64_t lenJ, const int64_t* clsoff, unsigned long long* fill,
+                           int32_t* list) {
+  for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < lenJ; q += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t s = cnt[q];
+    const int c = s == 0 ? kClsEmpty : s <= kRefSmall ? kClsSmall : s <= kRefMedium ? kClsMedium : kClsLarge;
+    list[clsoff[c] + (int64_t)atomicAdd(&fill[c], 1ull)] = (int32_t)q;
+  }
+}
+
+__device__ __forceinline__ void wsync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ uint64_t wave_sort_keys(uint64_t key) {
+  const int lane = lane_id();
+#pragma unroll
+  for (int k = 2; k <= kWave; k <<= 1) {
+#pragma unroll
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      const uint64_t other = __shfl_xor(key, j);
+      const bool up = (lane & k) == 0;
+      const bool lower = (lane & j) == 0;
+      const uint64_t mn = other < key ? other : key;
+      const uint64_t mx = other < key ? key : other;
+      key = (lower == up) ? mn : mx;
+    }
+  }
+  return key;
+}
+
+// Columns with at most 64 entries: one wave gathers (p, source) pairs into
+// LDS, sorts them by p across its lanes and writes the column.
+__global__ void __launch_bounds__(256) k_ref_small(Operand A, const int64_t* qa0, const int32_t* qlen,
+                                                   const int64_t* rptr, const int32_t* rpos, const int32_t* list,
+                                                   const int64_t* clsoff, const int64_t* off, int vb, int32_t* bir,
+                                                   void* bnum) {
+  __shared__ int32_t s_p[4][kWave];
+  __shared__ int64_t s_e[4][kWave];
+  const int w = threadIdx.x / kWave, lane = lane_id();
+  const int64_t beg = clsoff[kClsSmall], end = clsoff[kClsSmall + 1];
+  for (int64_t pos = beg + (int64_t)blockIdx.x * 4 + w; pos < end; pos += (int64_t)gridDim.x * 4) {
+    const int32_t q = list[pos];
+    const int64_t a0 = qa0[q];
+    const int32_t al = qlen[q];
+    int total = 0;
+    for (int32_t ec = 0; ec < al; ec += kWave) {
+      const int32_t e = ec + lane;
+      int32_t i = 0;
+      int rc = 0;
+      if (e < al) {
+        i = A.ir[a0 + e];
+        rc = (int)(rptr[i + 1] - rptr[i]);
+      }
+      const int incl = wave_incl_scan(rc);
+      const int excl = incl - rc;
+      for (int r = 0; r < rc; ++r) {
+        const int slot = total + excl + r;
+        if (slot < kWave) {
+          s_p[w][slot] = rpos[rptr[i] + r];
+          s_e[w][slot] = a0 + e;
+        }
+      }
+      total += __shfl(incl, kWave - 1);
+    }
+    if (total > kWave) total = kWave;
+    wsync();
+    uint64_t key = lane < total ? ((uint64_t)(uint32_t)s_p[w][lane] << 32) | (uint32_t)lane : ~0ull;
+    key = wave_sort_keys(key);
+    if (lane < total) {
+      const int slot = (int)(key & 0xffffffffu);
+      const int64_t o = off[q] + lane;
+      bir[o] = (int32_t)(key >> 32);
+      copy_value(A.num, s_e[w][slot], bnum, o, vb);
+    }
+    wsync();
+  }
+}
+
+// Columns with at most 4096 entries: one workgroup, LDS bitonic sort.
+__global__ void __launch_bounds__(256) k_ref_medium(Operand A, const int64_t* qa0, const int32_t* qlen,
+                                                    const int64_t* rptr, const int32_t* rpos, const int32_t* list,
+                                                    const int64_t* clsoff, const int64_t* cnt, const int64_t* off,
+                                                    int vb, int32_t* bir, void* bnum) {
+  __shared__ uint64_t s_key[kRefMedium];
+  __shared__ int64_t s_e[kRefMedium];
+  __shared__ int64_t red[256 / kWave + 1];
+  const int64_t beg = clsoff[kClsMedium], end = clsoff[kClsMedium + 1];
+  for (int64_t pos = beg + blockIdx.x; pos < end; pos += gridDim.x) {
+    const int32_t q = list[pos];
+    const int64_t a0 = qa0[q];
+    const int32_t al = qlen[q];
+    const int c = (int)cnt[q];
+    int64_t total = 0;
+    for (int32_t ec = 0; ec < al; ec += blockDim.x) {
+      const int32_t e = ec + threadIdx.x;
+      int32_t i = 0;
+      int64_t rc = 0;
+      if (e < al) {
+        i = A.ir[a0 + e];
+        rc = rptr[i + 1] - rptr[i];
+      }
+      int64_t ctot;
+      const int64_t excl = block_excl_scan(rc, red, &ctot);
+      for (int64_t r = 0; r < rc; ++r) {
+        const int64_t slot = total + excl + r;
+        if (slot < kRefMedium) {
+          s_key[slot] = ((uint64_t)(uint32_t)rpos[rptr[i] + r] << 32) | (uint32_t)slot;
+          s_e[slot] = a0 + e;
+        }
+      }
+      total += ctot;
+    }
+    int p2 = 64;
+    while (p2 < c) p2 <<= 1;
+    for (int s = c + threadIdx.x; s < p2; s += blockDim.x) s_key[s] = ~0ull;
+    __syncthreads();
+    for (int k = 2; k <= p2; k <<= 1) {
+      for (int j = k >> 1; j > 0; j >>= 1) {
+        for (int t = threadIdx.x; t < (p2 >> 1); t += blockDim.x) {
+          const int lo = 2 * t - (t & (j - 1));
+          const int hi = lo + j;
+          const bool asc = (lo & k) == 0;
+          const uint64_t x = s_key[lo], y = s_key[hi];
+          if ((x > y) == asc) {
+            s_key[lo] = y;
+            s_key[hi] = x;
+          }
+        }
+        __syncthreads();
+      }
+    }
+    for (int s = threadIdx.x; s < c; s += blockDim.x) {
+      const uint64_t k = s_key[s];
+      const int64_t o = off[q] + s;
+      bir[o] = (int32_t)(k >> 32);
+      copy_value(A.num, s_e[k & 0xffffffffu], bnum, o, vb);
+    }
+    __syncthreads();
+  }
+}
+
+// Long columns: walk p = 0..lenI-1 in order; B(p,q) exists iff row I(p)
+// is stored in A(:,J(q)) (binary search).  Output is in p order directly.
+__global__ void __launch_bounds__(1024) k_ref_large(Operand A, const int64_t* qa0, const int32_t* qlen,
+                                                    const int32_t* I, int64_t lenI, const int32_t* list,
+                                                    const int64_t* clsoff, const int64_t* off, int vb, int32_t* bir,
+                                                    void* bnum) {
+  __shared__ int64_t red[1024 / kWave + 1];
+  const int64_t beg = clsoff[kClsLarge], end = clsoff[kClsLarge + 1];
+  for (int64_t pos = beg + blockIdx.x; pos < end; pos += gridDim.x) {
+    const int32_t q = list[pos];
+    const int64_t a0 = qa0[q];
+    const int32_t al = qlen[q];
+    const int32_t* col = A.ir + a0;
+    int64_t run = off[q];
+    for (int64_t pc = 0; pc < lenI; pc += blockDim.x) {
+      const int64_t p = pc + threadIdx.x;
+      int64_t found = -1;
+      if (p < lenI) {
+        const int32_t i = I[p];
+        int32_t lo = 0, hi = al;
+        while (lo < hi) {
+          const int32_t mid = (lo + hi) >> 1;
+          if (col[mid] < i)
+            lo = mid + 1;
+          else
+            hi = mid;
+        }
+        if (lo < al && col[lo] == i) found = a0 + lo;
+      }
+      int64_t ctot;
+      const int64_t excl = block_excl_scan((int64_t)(found >= 0), red, &ctot);
+      if (found >= 0) {
+        bir[run + excl] = (int32_t)p;
+        copy_value(A.num, found, bnum, run + excl, vb);
+      }
+      run += ctot;
+    }
+  }
+}
+
+__global__ void k_write_cp(const int64_t* off, int64_t n, void* cp, int32_t ptr_t) {
+  for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j <= n; j += (int64_t)gridDim.x * blockDim.x)
+    store_ptr(cp, ptr_t, j, off[j]);
+}
+
+}  // namespace spx
+
+using namespace spx;
+
+extern "C" int spx_spref_plan(const spx_ctx* ctx, const spx_mat* A, const int32_t* I, int64_t lenI, const int32_t* J,
+                              int64_t lenJ, spx_plan** plan, int64_t* nnz_b) {
+  if (!plan) return fail(SPX_EINVAL, "plan is NULL");
+  *plan = nullptr;
+  SPX_TRY(check_mat(A, "A"));
+  if (lenI < 0 || lenJ < 0 || lenI >= (1ll << 31) || lenJ >= (1ll << 31)) return fail(SPX_EINVAL, "bad index length");
+  if ((lenI > 0 && !I) || (lenJ > 0 && !J)) return fail(SPX_EINVAL, "index vector is NULL");
+  if (A->m > (1ll << 30)) return fail(SPX_EUNSUPPORTED, "SpRef needs m <= 2^30 (dense row map)");
+  auto* P = new SprefPlan(ctx);
+  std::unique_ptr<SprefPlan> guard(P);
+  hipStream_t st = stream_of(ctx);
+  Scratch& scr = P->scratch;
+  P->A = make_operand(A);
+  P->I = I;
+  P->J = J;
+  P->lenI = lenI;
+  P->lenJ = lenJ;
+  const int64_t m = A->m;
+  const int cus = device_cu_count();
+  SPX_TRY(scr.get_n(4, &P->err));
+  SPX_TRY(fill_u32(P->err, 1, 0, st));
+  if (lenI > 0) {
+    k_check_index<<<grid_for(lenI, 256, 4096), 256, 0, st>>>(I, lenI, m, P->err, 1u);
+    SPX_HIP(hipGetLastError());
+  }
+  if (lenJ > 0) {
+    k_check_index<<<grid_for(lenJ, 256, 4096), 256, 0, st>>>(J, lenJ, A->n, P->err, 2u);
+    SPX_HIP(hipGetLastError());
+  }
+  // transpose of R: rows of I grouped by index, positions ascending
+  unsigned* rcnt = nullptr;
+  SPX_TRY(scr.get_n(m + 1, &rcnt));
+  SPX_TRY(fill_u32(rcnt, m + 1, 0, st));
+  SPX_TRY(scr.get_n(m + 1, &P->rptr));
+  SPX_TRY(scr.get_n(std::max<int64_t>(lenI, 1), &P->rpos));
+  if (lenI > 0) {
+    k_row_hist<<<grid_for(lenI, 256, 4096), 256, 0, st>>>(I, lenI, m, rcnt);
+    SPX_HIP(hipGetLastError());
+    uint64_t* keys = nullptr;
+    SPX_TRY(scr.get_n(sort_capacity(lenI), &keys));
+    k_pair_keys<<<grid_for(lenI, 256, 4096), 256, 0, st>>>(I, lenI, keys);
+    SPX_HIP(hipGetLastError());
+    SPX_TRY(sort_u64(keys, lenI, st));
+    k_low32<<<grid_for(lenI, 256, 4096), 256, 0, st>>>(keys, lenI, P->rpos);
+    SPX_HIP(hipGetLastError());
+  }
+  SPX_TRY(exclusive_scan(LoadU32{rcnt}, m, P->rptr, scr, st));
+  // A*Q: the columns J(q) of A
+  int64_t *aux = nullptr, chunk = 1;
+  SPX_TRY(build_aux(P->A, scr, st, &aux, &chunk));
+  SPX_TRY(scr.get_n(std::max<int64_t>(lenJ, 1), &P->qa0));
+  SPX_TRY(scr.get_n(std::max<int64_t>(lenJ, 1), &P->qlen));
+  SPX_TRY(scr.get_n(std::max<int64_t>(lenJ, 1), &P->cnt));
+  SPX_TRY(scr.get_n(lenJ + 1, &P->off));
+  SPX_TRY(scr.get_n(std::max<int64_t>(lenJ, 1), &P->list));
+  SPX_TRY(scr.get_n(kNumCls + 1, &P->clsoff));
+  unsigned long long *clscount = nullptr, *fill = nullptr;
+  SPX_TRY(scr.get_n(kNumCls, &clscount));
+  SPX_TRY(scr.get_n(kNumCls, &fill));
+  SPX_TRY(fill_i64((int64_t*)clscount, kNumCls, 0, st));
+  if (lenJ > 0) {
+    k_col_info<<<grid_for(lenJ, 256, 4096), 256, 0, st>>>(P->A, aux, chunk, J, lenJ, P->qa0, P->qlen);
+    SPX_HIP(hipGetLastError());
+    k_ref_count<<<grid_for(lenJ * kWave, 256, (int64_t)cus * 32), 256, 0, st>>>(P->A, P->qa0, P->qlen, P->rptr, lenJ,
+                                                                                P->cnt, clscount);
+    SPX_HIP(hipGetLastError());
+  }
+  k_cls_offsets<<<1, 64, 0, st>>>(clscount, P->clsoff, fill);
+  SPX_HIP(hipGetLastError());
+  if (lenJ > 0) {
+    k_cls_fill<<<grid_for(lenJ, 256, 4096), 256, 0, st>>>(P->cnt, lenJ, P->clsoff, fill, P->list);
+    SPX_HIP(hipGetLastError());
+  }
+  SPX_TRY(exclusive_scan(LoadI64{P->cnt}, lenJ, P->off, scr, st));
+  unsigned err_h = 0;
+  int64_t nnz = 0;
+  SPX_HIP(hipMemcpyAsync(P->clsoff_h, P->clsoff, sizeof(P->clsoff_h), hipMemcpyDeviceToHost, st));
+  SPX_HIP(hipMemcpyAsync(&nnz, P->off + lenJ, 8, hipMemcpyDeviceToHost, st));
+  SPX_HIP(hipMemcpyAsync(&err_h, P->err, 4, hipMemcpyDeviceToHost, st));
+  SPX_HIP(hipStreamSynchronize(st));
+  if (err_h & 1u) return fail(SPX_EINVAL, "I has an index outside [0, m)");
+  if (err_h & 2u) return fail(SPX_EINVAL, "J has an index outside [0, n)");
+  P->nnz = nnz;
+  if (nnz_b) *nnz_b = nnz;
+  *plan = guard.release();
+  return SPX_OK;
+}
+
+extern "C" int spx_spref_exec(spx_plan* plan, spx_mat* B) {
+  if (!plan || plan->kind != kPlanSpref) return fail(SPX_EINVAL, "not a SpRef plan");
+  auto* P = static_cast<SprefPlan*>(plan);
+  if (!B) return fail(SPX_EINVAL, "B is NULL");
+  if (B->m != P->lenI || B->n != P->lenJ || B->fmt != SPX_CSC) return fail(SPX_EINVAL, "B must be lenI x lenJ CSC");
+  if (B->val_t != P->A.val_t) return fail(SPX_EINVAL, "B's value type must be A's");
+  if (B->ptr_t == SPX_PTR_I32 && P->nnz >= (1ll << 31)) return fail(SPX_EOVERFLOW, "nnz(B) needs I64 pointers");
+  if (!B->cp || (P->nnz > 0 && (!B->ir || (B->val_t != SPX_VAL_BOOL && !B->num))))
+    return fail(SPX_EINVAL, "B buffers missing");
+  B->nnz = P->nnz;
+  B->nzc = 0;
+  hipStream_t st = stream_of(&P->ctx);
+  const int vb = value_size(P->A.val_t);
+  const int cus = device_cu_count();
+  const int64_t* co = P->clsoff_h;
+  if (co[kClsSmall + 1] > co[kClsSmall]) {
+    k_ref_small<<<grid_for(co[kClsSmall + 1] - co[kClsSmall], 4, (int64_t)cus * 16), 256, 0, st>>>(
+        P->A, P->qa0, P->qlen, P->rptr, P->rpos, P->list, P->clsoff, P->off, vb, B->ir, B->num);
+    SPX_HIP(hipGetLastError());
+  }
+  if (co[kClsMedium + 1] > co[kClsMedium]) {
+    k_ref_medium<<<grid_for(co[kClsMedium + 1] - co[kClsMedium], 1, (int64_t)cus * 2), 256, 0, st>>>(
+        P->A, P->qa0, P->qlen, P->rptr, P->rpos, P->list, P->clsoff, P->cnt, P->off, vb, B->ir, B->num);
+    SPX_HIP(hipGetLastError());
+  }
+  if (co[kClsLarge + 1] > co[kClsLarge]) {
+    k_ref_large<<<grid_for(co[kClsLarge + 1] - co[kClsLarge], 1, (int64_t)cus * 2), 1024, 0, st>>>(
+        P->A, P->qa0, P->qlen, P->I, P->lenI, P->list, P->clsoff, P->off, vb, B->ir, B->num);
+    SPX_HIP(hipGetLastError());
+  }
+  k_write_cp<<<grid_for(P->lenJ + 1, 256, 65536), 256, 0, st>>>(P->off, P->lenJ, B->cp, B->ptr_t);
+  SPX_HIP(hipGetLastError());
+  return SPX_OK;
+}

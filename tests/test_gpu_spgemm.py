@@ -1,0 +1,204 @@
+"""GPU parity of SpGEMM against the CPU oracle (element by element)."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from helpers import assert_same_csc
+
+pytestmark = pytest.mark.gpu
+
+
+def gemm(spx, A, B, semiring="plus_times", out_fmt=0, tuning=None, a_dcsc=False, b_dcsc=False, ptr32=False):
+    import torch
+    pd = torch.int32 if ptr32 else torch.int64
+    dA, dB = spx.from_host(A, ptr_dtype=pd), spx.from_host(B, ptr_dtype=pd)
+    if a_dcsc:
+        dA = spx.csc_to_dcsc(dA)
+    if b_dcsc:
+        dB = spx.csc_to_dcsc(dB)
+    plan = spx.GemmPlan(dA, dB, semiring, out_fmt, tuning)
+    C = plan.execute()
+    info = plan.info()
+    plan.close()
+    return C, info
+
+
+def check_against_oracle(spx, A, B, semiring, exact=False, **kw):
+    C, info = gemm(spx, A, B, semiring, **kw)
+    got = C.to_host_csc()
+    ref = oracle.spgemm_csc(A, B, semiring)
+    assert_same_csc(got, ref, exact_values=exact, what=f"{semiring}")
+    mults = int(np.diff(A.cp)[B.ir].sum())
+    assert info["mults"] == mults
+    assert info["nnz"] == ref.cp[-1] <= mults
+    return C, info
+
+
+def test_er_config_plus_times_and_min_plus(spx):
+    A = W.erdos_renyi(4096, 4096, 8, seed=1)
+    C, info = check_against_oracle(spx, A, A, "plus_times")
+    assert info["mults"] == 262144 and info["cols_tiny"] == 4096
+    check_against_oracle(spx, A, A, "min_plus", exact=True)
+
+
+@pytest.mark.parametrize("semiring,values,exact", [
+    ("plus_times", "f64", False), ("plus_times", "f32", False), ("plus_times", "small_int", True),
+    ("min_plus", "f64", True), ("min_plus", "f32", True), ("min_plus", "small_int", True),
+    ("select2nd", "edge_id", True), ("select1st", "edge_id", True), ("or_and", "none", True),
+])
+def test_rmat_semirings(spx, semiring, values, exact):
+    A = W.rmat(13, 8, seed=5, values="f64")
+    rng = np.random.default_rng(7)
+    if values == "f32":
+        A.num = A.num.astype(np.float32)
+    elif values == "small_int":
+        A.num = rng.integers(-3, 4, size=A.nnz).astype(np.int64)
+    elif values == "edge_id":
+        A.num = np.arange(A.nnz, dtype=np.int64)
+    elif values == "none":
+        A.num = None
+    _, info = check_against_oracle(spx, A, A, semiring, exact=exact)
+    assert info["cols_heavy"] > 0 and info["cols_medium"] > 0 and info["cols_tiny"] > 0
+
+
+@pytest.mark.parametrize("tune", [
+    dict(tiny_max=0, medium_max=0),                       # everything through the bitmap count
+    dict(tiny_max=64, medium_max=16384),                  # no bitmap count
+    dict(part_lds_bytes=24 * 1024),                       # many parts, both part modes
+    dict(part_lds_bytes=48 * 1024, heavy_threads=256, medium_threads=64),
+    dict(tiny_max=16, medium_max=256, part_lds_bytes=64 * 1024, heavy_threads=512),
+])
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_forced_paths(spx, tune, dtype):
+    A = W.rmat(14, 8, seed=11, values="f64")
+    A.num = A.num.astype(dtype)
+    t = spx.default_tuning()
+    for k, v in tune.items():
+        setattr(t, k, v)
+    _, info = check_against_oracle(spx, A, A, "plus_times", tuning=t)
+    if "part_lds_bytes" in tune and tune["part_lds_bytes"] <= 24 * 1024:
+        assert info["heavy_parts"] > info["cols_heavy"] + info["cols_medium"]
+
+
+def test_min_plus_forced_paths_exact(spx):
+    A = W.rmat(14, 8, seed=12, values="f64")
+    t = spx.default_tuning()
+    t.part_lds_bytes = 24 * 1024
+    check_against_oracle(spx, A, A, "min_plus", exact=True, tuning=t)
+
+
+def test_rectangular_and_independent(spx):
+    rng = np.random.default_rng(3)
+    A = W.erdos_renyi(3000, 700, 5, seed=4)
+    B = W.rmat(10, 6, seed=8)                       # 1024 x 1024 -> need 700 x n
+    B = W.column_block(B, 0, 700, 0, 1024)
+    check_against_oracle(spx, A, B, "plus_times")
+    check_against_oracle(spx, A, B, "min_plus", exact=True)
+
+
+@pytest.mark.parametrize("out_fmt", [0, 1])
+def test_dcsc_stage_blocks(spx, out_fmt):
+    """One GPU's share of an 8x8 Sparse SUMMA stage: hypersparse blocks in DCSC."""
+    A = W.rmat(15, 8, seed=20)
+    b = A.n // 8
+    blocks = [[W.column_block(A, i * b, (i + 1) * b, k * b, (k + 1) * b) for k in range(8)] for i in range(8)]
+    for k in range(8):
+        X, Y = blocks[0][k], blocks[k][0]
+        assert X.nnz < X.n  # hypersparse
+        C, info = gemm(spx, X, Y, "plus_times", out_fmt=out_fmt, a_dcsc=True, b_dcsc=True)
+        ref = oracle.spgemm_csc(X, Y)
+        got = C.to_host_csc()
+        assert_same_csc(got, ref, what=f"stage block k={k}")
+        if out_fmt == 1:
+            jc, dcp = oracle.csc_to_dcsc(ref.n, ref.cp)
+            cp, ir, num = C.to_host()
+            assert np.array_equal(C.jc.cpu().numpy(), jc) and np.array_equal(cp, dcp)
+
+
+def test_mixed_formats_and_int32_pointers(spx):
+    A = W.rmat(12, 8, seed=30)
+    for a_d, b_d in ((True, False), (False, True)):
+        check_against_oracle(spx, A, A, "plus_times", a_dcsc=a_d, b_dcsc=b_d)
+    check_against_oracle(spx, A, A, "plus_times", ptr32=True)
+
+
+def test_edge_cases(spx):
+    empty = W.from_triples([], [], np.zeros(0), 5, 7)
+    other = W.erdos_renyi(7, 3, 2, seed=1)
+    check_against_oracle(spx, empty, other, "plus_times")
+    one = W.from_triples([0], [0], np.array([2.5]), 1, 1)
+    check_against_oracle(spx, one, one, "plus_times")
+    # B columns that hit only empty columns of A
+    A = W.from_triples([1, 2], [0, 0], np.array([1.0, 2.0]), 3, 3)
+    B = W.from_triples([1, 2, 0], [0, 1, 2], np.array([1.0, 1.0, 3.0]), 3, 3)
+    check_against_oracle(spx, A, B, "plus_times")
+    # zero-column output
+    Z = W.from_triples([], [], np.zeros(0), 4, 0)
+    X = W.erdos_renyi(6, 4, 2, seed=2)
+    C, _ = gemm(spx, X, Z)
+    assert C.nnz == 0 and C.n == 0
+
+
+def test_errors(spx):
+    A = W.erdos_renyi(10, 8, 2, seed=1)
+    dA = spx.from_host(A)
+    with pytest.raises(spx.SpxError) as e:
+        spx.spgemm(dA, dA)  # 10x8 times 10x8
+    assert e.value.code == spx.SPX_EINVAL
+    B = W.erdos_renyi(8, 4, 2, seed=2)
+    dB = spx.from_host(B)
+    dB.num = dB.num.float()
+    with pytest.raises(spx.SpxError) as e:
+        spx.spgemm(dA, dB)  # f64 x f32
+    assert e.value.code == spx.SPX_EUNSUPPORTED
+
+
+@pytest.fixture(scope="module")
+def rmat20():
+    return W.rmat(20, 8, seed=20)
+
+
+def test_rmat20_full_size_sampled(spx, rmat20):
+    """R-MAT scale 20 A*A at full size, default (benchmark) configuration.
+
+    The oracle recomputes sampled columns one by one: the heaviest columns,
+    random nonempty ones and the first/last columns.  Properties that hold at
+    any size are checked over the whole output.
+    """
+    import torch
+    A = rmat20
+    dA = spx.from_host(A)
+    plan = spx.GemmPlan(dA, dA)
+    C = plan.execute()
+    info = plan.info()
+    plan.close()
+    torch.cuda.synchronize()
+    deg = np.diff(A.cp)
+    cs = np.concatenate([[0], np.cumsum(deg[A.ir])])
+    mults_col = cs[A.cp[1:]] - cs[A.cp[:-1]]
+    assert info["mults"] == int(deg[A.ir].sum())
+    cp = C.cp.cpu().numpy()
+    assert cp[0] == 0 and cp[-1] == C.nnz and np.all(np.diff(cp) >= 0)
+    assert np.all(np.diff(cp) <= mults_col)
+    # rows strictly increasing inside every column, all in range
+    ir = C.ir
+    assert int(ir.min()) >= 0 and int(ir.max()) < A.m
+    starts = torch.zeros(C.nnz, dtype=torch.bool, device="cuda")
+    starts[C.cp[:-1][torch.from_numpy(np.diff(cp) > 0).cuda()]] = True
+    bad = (ir[1:] <= ir[:-1]) & ~starts[1:]
+    assert int(bad.sum()) == 0
+    rng = np.random.default_rng(0)
+    heavy = np.argsort(mults_col)[-12:]
+    nonempty = np.nonzero(np.diff(cp) > 0)[0]
+    cols = np.unique(np.concatenate([heavy, rng.choice(nonempty, 300, replace=False), [0, A.n - 1]]))
+    rcp, rir, rnum = oracle.spgemm(A, A, cols=cols)
+    lens = cp[cols + 1] - cp[cols]
+    gcp = np.concatenate([[0], np.cumsum(lens)])
+    idx = np.concatenate([np.arange(cp[j], cp[j + 1]) for j in cols])
+    idx_t = torch.from_numpy(idx).cuda()
+    from types import SimpleNamespace
+    got = SimpleNamespace(cp=gcp, ir=C.ir[idx_t].cpu().numpy(), num=C.num[idx_t].cpu().numpy())
+    assert_same_csc(got, SimpleNamespace(cp=rcp, ir=rir, num=rnum), what="rmat20 sampled columns")
+    del C
+    torch.cuda.empty_cache()
