@@ -1,0 +1,294 @@
+#!/usr/bin/env python3
+"""Benchmark of the SpGEMM hot path on one MI355X.
+
+Workload: C = A*A over (+, x) in FP64 for an R-MAT matrix of scale 20
+(2^20 x 2^20, edge factor 8, quadrant probabilities a=.57 b=c=.19 d=.05,
+duplicates merged, vertices randomly permuted, values uniform [0,1)).
+One step = the whole path for one product: symbolic phase (column lookup,
+multiplication counts, binning, exact column counts, int64 scans, part
+cutting; one host read-back of the output size) and numeric phase (wave /
+LDS accumulation, ordered write-out of IR and NUM, column pointers).  The
+input is resident in HBM before timing starts; the 43 GB output buffer is
+allocated once and rewritten by every step.
+
+Prints one JSON line: GFLOP/s counted as 2 x multiplications per second,
+achieved compulsory GB/s, the roofline of the dominant kernel (HIP events
+on the library's stream over the timed steps), and the CPU oracle timed on
+a bounded sample of the same product.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-extra] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "SpGEMM GFLOP/s (2·mults/s) + GB/s on R-MAT s20 A·A; served p50/p99 vs plain"
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def csc_bytes(nnz, ncols, vbytes=8, ptr_bytes=8):
+    return nnz * (4 + vbytes) + (ncols + 1) * ptr_bytes
+
+
+def kernel_source_digest():
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1109_3739_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hip", ".h")):
+            h.update(open(os.path.join(csrc, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profiles(kernel, launch_bytes_known):
+    """HBM bytes per launch from the committed PMC summary, if it was taken
+    on the current kernel sources; otherwise None."""
+    path = os.path.join(ROOT, "profiles", "traffic_spgemm_rmat20.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        d = json.load(open(path))
+        if d.get("source_digest") != kernel_source_digest():
+            return None
+        k = d["kernels"].get(kernel)
+        return None if k is None else float(k["hbm_bytes_per_launch"])
+    except Exception:
+        return None
+
+
+def time_steps(fn, steps, sync):
+    sync()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    sync()
+    return (time.perf_counter() - t0) / steps
+
+
+def cpu_baseline(A, target_s=15.0):
+    """Oracle on a random sample of output columns of A*A (all host cores)."""
+    import numpy as np
+    import oracle
+    rng = np.random.default_rng(1234)
+    deg = np.diff(A.cp)
+    cs = np.concatenate([[0], np.cumsum(deg[A.ir])])
+    mults_col = cs[A.cp[1:]] - cs[A.cp[:-1]]
+    threads = oracle.max_threads()
+    order = rng.permutation(A.n)
+    # calibrate on 0.2% of the columns, then size the sample for ~target_s
+    n0 = max(64, A.n // 500)
+    t0 = time.perf_counter()
+    oracle.spgemm(A, A, cols=np.sort(order[:n0]), nthreads=threads)
+    t_cal = time.perf_counter() - t0
+    rate = max(int(mults_col[order[:n0]].sum()), 1) / max(t_cal, 1e-3)
+    want = min(rate * target_s, 0.5 * float(mults_col.sum()))  # at most half of the product
+    cum = np.cumsum(mults_col[order])
+    ncols = int(min(A.n, max(n0, np.searchsorted(cum, want) + 1)))
+    cols = np.sort(order[:ncols])
+    mults = int(mults_col[cols].sum())
+    t0 = time.perf_counter()
+    oracle.spgemm(A, A, cols=cols, nthreads=threads)
+    t = time.perf_counter() - t0
+    return {
+        "value": round(2.0 * mults / t / 1e9, 4),
+        "unit": "GFLOP/s",
+        "cores": threads,
+        "kind": "oracle",
+        "sample": f"{ncols} of {A.n} output columns drawn uniformly at random (seed 1234), {mults} mults, "
+                  f"{t:.2f} s; dense-SPA column-wise Gustavson, OpenMP over columns",
+    }
+
+
+def extra_workloads(spx, W, torch):
+    """Latency / bandwidth of the other workloads of the path (context)."""
+    import numpy as np
+    out = {}
+    sync = torch.cuda.synchronize
+
+    # Erdos-Renyi 4096 x 4096, 8 per column: launch-bound latency
+    E = W.erdos_renyi(4096, 4096, 8, seed=1)
+    dE = spx.from_host(E)
+    for sr in ("plus_times", "min_plus"):
+        spx.spgemm(dE, dE, sr)
+        ts = []
+        for _ in range(10):
+            sync()
+            t0 = time.perf_counter()
+            spx.spgemm(dE, dE, sr)
+            sync()
+            ts.append(time.perf_counter() - t0)
+        out[f"er4096_{sr}_ms"] = round(1e3 * statistics.median(ts), 4)
+
+    # one GPU's share of an 8x8 Sparse SUMMA stage: A00 * A00 in DCSC
+    A = W.rmat(20, 8, seed=20)
+    b = A.n // 8
+    blk = W.column_block(A, 0, b, 0, b)
+    dB = spx.csc_to_dcsc(spx.from_host(blk))
+    p = spx.GemmPlan(dB, dB, out_fmt=spx.DCSC)
+    C = p.execute()
+    mults = p.info()["mults"]
+    p.close()
+
+    def stage():
+        q = spx.GemmPlan(dB, dB, out_fmt=spx.DCSC)
+        q.execute(C)
+        q.close()
+
+    for _ in range(3):
+        stage()
+    t = time_steps(stage, 10, sync)
+    out["stage_block_dcsc_ms"] = round(1e3 * t, 4)
+    out["stage_block_gflops"] = round(2 * mults / t / 1e9, 3)
+    out["stage_block_nnz_c"] = int(C.nnz)
+    del C
+
+    # SpRef / SpAsgn on R-MAT scale 22, edge factor 16, int64 edge ids
+    A3 = W.rmat(22, 16, seed=22, values="edge_id")
+    I = W.index_vector(1 << 18, A3.m, seed=221)
+    J = W.index_vector(1 << 18, A3.n, seed=222)
+    Bp = W.erdos_renyi(1 << 18, 1 << 18, 4, seed=223, values="id40")
+    dA3, dI, dJ, dBp = spx.from_host(A3), torch.from_numpy(I).cuda(), torch.from_numpy(J).cuda(), spx.from_host(Bp)
+    R = spx.spref(dA3, dI, dJ)
+    t = time_steps(lambda: spx.spref(dA3, dI, dJ), 5, sync)
+    deg = np.diff(A3.cp)
+    gathered = int(deg[J].sum())
+    ref_bytes = gathered * 12 + R.nnz * 12 + (1 << 18) * 8 * 2 + (1 << 18) * 8
+    out["spref_ms"] = round(1e3 * t, 4)
+    out["spref_gbs"] = round(ref_bytes / t / 1e9, 2)
+    out["spref_nnz"] = int(R.nnz)
+    S = spx.spasgn(dA3, dI, dJ, dBp)
+    t = time_steps(lambda: spx.spasgn(dA3, dI, dJ, dBp), 5, sync)
+    asg_bytes = csc_bytes(A3.nnz, A3.n) + csc_bytes(Bp.nnz, Bp.n) + csc_bytes(S.nnz, A3.n) + (1 << 19) * 4
+    out["spasgn_ms"] = round(1e3 * t, 4)
+    out["spasgn_gbs"] = round(asg_bytes / t / 1e9, 2)
+    out["spasgn_nnz"] = int(S.nnz)
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-extra", action="store_true", help="skip the other workloads")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: this library has no multi-GPU path, run it with --gpus 1",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1109_3739_amd as spx
+    import workloads as W
+
+    spx.load()
+    torch.cuda.set_device(0)
+    sync = torch.cuda.synchronize
+    log("generating R-MAT scale 20")
+    A = W.rmat(20, 8, seed=20)
+    dA = spx.from_host(A)
+    sync()
+
+    # warm-up (also sizes the output once)
+    p = spx.GemmPlan(dA, dA)
+    info = p.info()
+    C = p.execute()
+    p.close()
+    sync()
+    for i in range(args.warmup):
+        p = spx.GemmPlan(dA, dA)
+        p.execute(C)
+        p.close()
+    sync()
+    log(f"warm-up done: mults={info['mults']} nnz(C)={info['nnz']}")
+
+    phase = []
+
+    def step():
+        q = spx.GemmPlan(dA, dA, profile=True)
+        q.execute(C)
+        phase.append(q.times())
+        q.close()
+
+    sync()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    sync()
+    t_step = (time.perf_counter() - t0) / args.steps
+    log(f"timed {args.steps} steps: {1e3 * t_step:.3f} ms/step")
+
+    mults, nnz_c = info["mults"], info["nnz"]
+    comp_bytes = 2 * csc_bytes(A.nnz, A.n) + csc_bytes(nnz_c, A.n)
+    gflops = 2.0 * mults / t_step / 1e9
+    gbs = comp_bytes / t_step / 1e9
+    avg = {k: statistics.mean(ph[k] for ph in phase) for k in phase[0]}
+    # dominant kernel: the launch over the row-range parts of the heavy
+    # columns (it accumulates and writes most of C).  Algorithmic bytes per
+    # launch: A and B read once, its share of C written once.
+    multi_bytes = 2 * csc_bytes(A.nnz, A.n) + info["nnz_multi"] * 12
+    multi_s = avg["numeric_multi_ms"] / 1e3
+    achieved = multi_bytes / multi_s / 1e9
+    roofline = {
+        "bound": "hbm",
+        "kernel": "k_numeric_parts<0,double> (multi-part launch)",
+        "achieved": round(achieved, 2),
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": round(achieved / HBM_PEAK_GBS, 4),
+        "traffic": traffic_from_profiles("k_numeric_parts_multi", multi_bytes),
+        "algorithmic_bytes": int(multi_bytes),
+        "avg_launch_ms": round(avg["numeric_multi_ms"], 4),
+        "parts": int(info["multi_parts"]),
+    }
+    result = {
+        "metric": METRIC,
+        "value": round(gflops, 3),
+        "unit": "GFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * t_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "rmat20_AxA_plus_times_f64", "scale": 20, "edge_factor": 8,
+                   "rmat": [0.57, 0.19, 0.19, 0.05], "seed": 20, "nnz_a": int(A.nnz), "mults": int(mults),
+                   "nnz_c": int(nnz_c), "format": "csc int64 cp / int32 ir / f64"},
+        "gbs": round(gbs, 2),
+        "compulsory_bytes": int(comp_bytes),
+        "phases_ms": {k: round(v, 4) for k, v in avg.items()},
+        "roofline": roofline,
+    }
+    del C
+    torch.cuda.empty_cache()
+    if not args.no_extra:
+        log("other workloads")
+        result["extra"] = extra_workloads(spx, W, torch)
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle, sampled columns)")
+        result["cpu_baseline"] = cpu_baseline(A, args.cpu_seconds)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -81,31 +81,43 @@ typedef struct spx_mat {
  *   alloc     device allocator for scratch (and one-shot outputs); NULL: hipMalloc
  *   free      matching free; called with the pointer alloc returned
  *   user      passed to alloc / free
- *   validate  nonzero: check that inputs are canonical before computing   */
+ *   validate  nonzero: check that inputs are canonical before computing
+ *   profile   nonzero: plans record HIP events around their kernel groups
+ *             (read with spx_plan_get_times)                              */
 typedef struct spx_ctx {
   void* stream;
   void* (*alloc)(size_t bytes, void* user);
   void (*free)(void* ptr, void* user);
   void* user;
   int32_t validate;
-  int32_t reserved;
+  int32_t profile;
 } spx_ctx;
 
 /* Tuning knobs of the SpGEMM kernels (NULL = built-in defaults, which
- * spx_default_tuning() returns).  Columns are binned by their number of
- * multiplications (an upper bound on their output size):
- *   tiny_max      columns with <= tiny_max products are formed in one
- *                 64-lane wave by sorting their products (<= 64)
- *   medium_max    columns with <= medium_max products use an LDS hash table
- *   heavy columns are counted with an LDS bitmap over the row space and
- *   accumulated in row-range parts whose LDS budget is part_lds_bytes
- *   medium_threads / heavy_threads  workgroup sizes (multiples of 64)    */
+ * spx_default_tuning() returns).  Output columns are binned by their
+ * number of multiplications mu (an upper bound on their output size):
+ *   tiny_max         mu <= tiny_max (<= 64): formed by one 64-lane wave that
+ *                    sorts the column's products
+ *   hash_count_max   mu <= hash_count_max (<= 16384): exact count through an
+ *                    LDS hash table; larger columns through an LDS bitmap
+ *   single_part_max  power of two in [64, 4096]: columns with mu at most this
+ *                    are accumulated as one part (LDS hash or bitmap sized
+ *                    for it); larger columns are cut into row-range parts
+ *   part_lds_bytes   LDS budget of one part of a larger column
+ *   *_threads        workgroup sizes (multiples of 64, at most 1024) of the
+ *                    hash count, bitmap count, multi-part and single-part
+ *                    numeric kernels
+ *   bitmap_chunk_log2  rows per work item of the bitmap count (log2)       */
 typedef struct spx_tuning {
   int32_t tiny_max;
-  int32_t medium_max;
+  int32_t hash_count_max;
+  int32_t single_part_max;
   int32_t part_lds_bytes;
-  int32_t medium_threads;
-  int32_t heavy_threads;
+  int32_t count_threads;
+  int32_t bitmap_threads;
+  int32_t part_threads;
+  int32_t single_threads;
+  int32_t bitmap_chunk_log2;
   int32_t reserved[3];
 } spx_tuning;
 
@@ -115,8 +127,22 @@ typedef struct spx_plan_info {
   int64_t nnz;            /* nnz(C) */
   int64_t nzc;            /* nonempty columns of C */
   int64_t cols_empty, cols_tiny, cols_medium, cols_heavy;
-  int64_t heavy_parts;    /* row-range parts of heavy columns */
+  int64_t heavy_parts;    /* row-range parts (every non-tiny nonempty column has >= 1) */
+  int64_t nnz_tiny;       /* entries of C formed by the one-wave path */
+  int64_t nnz_multi;      /* entries of C in parts of columns cut into row ranges */
+  int64_t multi_parts;    /* number of those parts (the first heavy_parts launch) */
 } spx_plan_info;
+
+/* Device time of the kernel groups of the last plan / exec calls of a
+ * SpGEMM plan created with ctx->profile set (milliseconds, HIP events on
+ * the plan's stream; 0 when a group did not run).                       */
+typedef struct spx_times {
+  float symbolic_ms;       /* plan: lookup, counts, binning, exact sizes, scans, parts */
+  float numeric_parts_ms;  /* exec: all parts (LDS bitmap / hash accumulation) */
+  float numeric_multi_ms;  /* exec: the launch over parts of columns cut into row ranges */
+  float numeric_tiny_ms;   /* exec: columns formed by one wave */
+  float pointers_ms;       /* exec: column pointers of C */
+} spx_times;
 
 typedef struct spx_plan spx_plan;
 
@@ -139,6 +165,8 @@ int spx_spgemm_exec(spx_plan* plan, spx_mat* C);
 int spx_spgemm(const spx_ctx* ctx, const spx_mat* A, const spx_mat* B, int32_t semiring, int32_t c_fmt,
                spx_mat* C);
 int spx_plan_get_info(const spx_plan* plan, spx_plan_info* info);
+/* Waits for the recorded events and reports their elapsed times. */
+int spx_plan_get_times(spx_plan* plan, spx_times* times);
 void spx_plan_destroy(spx_plan* plan);
 void spx_default_tuning(spx_tuning* tuning);
 

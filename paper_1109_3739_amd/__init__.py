@@ -30,7 +30,7 @@ SEMIRINGS = {"plus_times": 0, "min_plus": 1, "select2nd": 2, "or_and": 3, "selec
 ERRORS = {1: "EINVAL", 2: "ENOMEM", 3: "EOVERFLOW", 4: "EUNSUPPORTED", 5: "EDEVICE"}
 
 EXPORTS = [
-    "spx_spgemm_plan", "spx_spgemm_exec", "spx_spgemm", "spx_plan_get_info", "spx_plan_destroy",
+    "spx_spgemm_plan", "spx_spgemm_exec", "spx_spgemm", "spx_plan_get_info", "spx_plan_destroy", "spx_plan_get_times",
     "spx_default_tuning", "spx_spref_plan", "spx_spref_exec", "spx_spasgn_plan", "spx_spasgn_exec",
     "spx_count_nonempty", "spx_csc_to_dcsc", "spx_dcsc_to_csc", "spx_check", "spx_last_error", "spx_version",
 ]
@@ -57,20 +57,25 @@ FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
 class spx_ctx(ctypes.Structure):
     _fields_ = [
         ("stream", ctypes.c_void_p), ("alloc", ALLOC_FN), ("free", FREE_FN), ("user", ctypes.c_void_p),
-        ("validate", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("validate", ctypes.c_int32), ("profile", ctypes.c_int32),
     ]
 
 
 class spx_tuning(ctypes.Structure):
-    _fields_ = [
-        ("tiny_max", ctypes.c_int32), ("medium_max", ctypes.c_int32), ("part_lds_bytes", ctypes.c_int32),
-        ("medium_threads", ctypes.c_int32), ("heavy_threads", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3),
-    ]
+    _fields_ = [(k, ctypes.c_int32) for k in (
+        "tiny_max", "hash_count_max", "single_part_max", "part_lds_bytes", "count_threads", "bitmap_threads",
+        "part_threads", "single_threads", "bitmap_chunk_log2", "reserved0", "reserved1", "reserved2")]
 
 
 class spx_plan_info(ctypes.Structure):
     _fields_ = [(k, ctypes.c_int64) for k in
-                ("mults", "nnz", "nzc", "cols_empty", "cols_tiny", "cols_medium", "cols_heavy", "heavy_parts")]
+                ("mults", "nnz", "nzc", "cols_empty", "cols_tiny", "cols_medium", "cols_heavy", "heavy_parts",
+                 "nnz_tiny", "nnz_multi", "multi_parts")]
+
+
+class spx_times(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_float) for k in ("symbolic_ms", "numeric_parts_ms", "numeric_multi_ms", "numeric_tiny_ms",
+                                              "pointers_ms")]
 
 
 _lib = None
@@ -95,6 +100,7 @@ def load():
         "spx_spgemm": ([C, M, M, I32, I32, M], ctypes.c_int),
         "spx_plan_get_info": ([P, ctypes.POINTER(spx_plan_info)], ctypes.c_int),
         "spx_plan_destroy": ([P], None),
+        "spx_plan_get_times": ([P, ctypes.POINTER(spx_times)], ctypes.c_int),
         "spx_default_tuning": ([ctypes.POINTER(spx_tuning)], None),
         "spx_spref_plan": ([C, M, P, I64, P, I64, PP, PI64], ctypes.c_int),
         "spx_spref_exec": ([P, M], ctypes.c_int),
@@ -147,10 +153,10 @@ def _free_cb(ptr, user):
     _t().cuda.caching_allocator_delete(ptr)
 
 
-def make_ctx(stream=None, validate: bool = False) -> spx_ctx:
+def make_ctx(stream=None, validate: bool = False, profile: bool = False) -> spx_ctx:
     torch = _t()
     s = stream if stream is not None else torch.cuda.current_stream()
-    return spx_ctx(ctypes.c_void_p(s.cuda_stream), _alloc_cb, _free_cb, None, int(validate), 0)
+    return spx_ctx(ctypes.c_void_p(s.cuda_stream), _alloc_cb, _free_cb, None, int(validate), int(profile))
 
 
 # ---- matrices ------------------------------------------------------------
@@ -255,10 +261,10 @@ class GemmPlan:
     """Symbolic phase of C = A*B; ``execute()`` runs the numeric phase."""
 
     def __init__(self, A: SpMat, B: SpMat, semiring: str = "plus_times", out_fmt: int = CSC, tuning=None,
-                 stream=None):
+                 stream=None, profile: bool = False, validate: bool = False):
         lib = load()
         self._keep = (A, B)
-        self.ctx = make_ctx(stream)
+        self.ctx = make_ctx(stream, validate=validate, profile=profile)
         self.A, self.B = A.desc(), B.desc()
         self.m, self.n, self.out_fmt = A.m, B.n, out_fmt
         self.handle = ctypes.c_void_p()
@@ -285,6 +291,12 @@ class GemmPlan:
         inf = spx_plan_info()
         _check(load().spx_plan_get_info(self.handle, ctypes.byref(inf)))
         return {k: getattr(inf, k) for k, _ in spx_plan_info._fields_}
+
+    def times(self) -> dict:
+        """Per-phase device milliseconds (plan created with profile=True)."""
+        t = spx_times()
+        _check(load().spx_plan_get_times(self.handle, ctypes.byref(t)))
+        return {k: float(getattr(t, k)) for k, _ in spx_times._fields_}
 
     def alloc_output(self, ptr_dtype=None) -> SpMat:
         torch = _t()

@@ -84,6 +84,22 @@ __device__ __forceinline__ void column_range(const Operand& X, const int64_t* au
   }
 }
 
+// As column_range, also giving the slot of column k (-1 if not stored).
+__device__ __forceinline__ int64_t column_slot(const Operand& X, const int64_t* aux, int64_t chunk, int64_t k) {
+  if (X.fmt == SPX_CSC) return k;
+  const int64_t c = k / chunk;
+  int64_t lo = aux[c], hi = aux[c + 1];
+  const int64_t end = hi;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (X.jc[mid] < k)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  return (lo < end && X.jc[lo] == k) ? lo : -1;
+}
+
 // Builds the AUX index of a DCSC operand into scratch (no-op for CSC).
 int build_aux(const Operand& X, Scratch& scr, hipStream_t st, int64_t** aux, int64_t* chunk);
 

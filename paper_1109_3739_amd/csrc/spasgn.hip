@@ -273,6 +273,13 @@ extern "C" int spx_spasgn_plan(const spx_ctx* ctx, const spx_mat* A, const int32
   if (B->m != lenI || B->n != lenJ) return fail(SPX_EINVAL, "B must be lenI x lenJ");
   if (A->val_t != B->val_t) return fail(SPX_EINVAL, "A and B must have the same value type");
   if ((lenI > 0 && !I) || (lenJ > 0 && !J)) return fail(SPX_EINVAL, "index vector is NULL");
+  if (ctx && ctx->validate) {
+    int32_t ok = 0;
+    SPX_TRY(spx_check(ctx, A, &ok));
+    if (!ok) return fail(SPX_EINVAL, "A is not canonical");
+    SPX_TRY(spx_check(ctx, B, &ok));
+    if (!ok) return fail(SPX_EINVAL, "B is not canonical");
+  }
   auto* P = new SpasgnPlan(ctx);
   std::unique_ptr<SpasgnPlan> guard(P);
   hipStream_t st = stream_of(ctx);

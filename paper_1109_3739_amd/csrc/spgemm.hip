@@ -55,11 +55,8 @@ constexpr int kBinEmpty = 50;
 constexpr int kNumBins = 51;
 constexpr int kHashLog2Max = 15;
 constexpr int kHashLog2Min = 8;
-// Columns with more products than this get per-row-block counts so that
-// their numeric work can be split into row-range parts.
-constexpr int kSinglePartMax = 4096;
-constexpr int kBinMultiEnd = kBinHash0 + (kHashLog2Max - 13);  // bins with tables >= 2^14 keys
 constexpr int kBitmapChunkLog2 = 20;                          // rows per bitmap-count chunk
+constexpr int32_t kSplitMin = 32;  // A columns longer than this get a split-table row
 
 __device__ __forceinline__ int floor_log2_u64(uint64_t x) { return 63 - __clzll(x); }
 __device__ __forceinline__ int ceil_log2_u64(uint64_t x) { return x <= 1 ? 0 : 64 - __clzll(x - 1); }
@@ -81,20 +78,64 @@ __device__ __forceinline__ int bin_of(int64_t mu, const BinCfg& c) {
 }
 
 // ------------------------------------------------------------------ kernels: setup
-// For every stored B(k,j): where column k of A starts and how long it is.
-__global__ void k_rowinfo(Operand A, Operand B, const int64_t* aux, int64_t chunk, int64_t* bq_a0, int32_t* bq_alen,
-                          unsigned* err) {
+// For every stored B(k,j): where column k of A starts, how long it is, and
+// its row of the split table (-1 for short columns).
+__global__ void k_rowinfo(Operand A, Operand B, const int64_t* aux, int64_t chunk, const int64_t* sid_off,
+                          int64_t* bq_a0, int32_t* bq_alen, int32_t* bq_split, unsigned* err) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < B.nnz; q += stride) {
     const int32_t k = B.ir[q];
-    int64_t a0 = 0, a1 = 0;
+    int64_t a0 = 0, a1 = 0, slot = -1;
     if (k < 0 || k >= A.n) {
       atomicOr(err, 1u);
     } else {
-      column_range(A, aux, chunk, k, a0, a1);
+      slot = column_slot(A, aux, chunk, k);
+      if (slot >= 0) {
+        a0 = load_ptr(A.cp, A.ptr_t, slot);
+        a1 = load_ptr(A.cp, A.ptr_t, slot + 1);
+      }
     }
     bq_a0[q] = a0;
     bq_alen[q] = (int32_t)(a1 - a0);
+    bq_split[q] = (sid_off && a1 - a0 > kSplitMin) ? (int32_t)sid_off[slot] : -1;
+  }
+}
+
+// Split table of the long columns of A (see ProdSrc).
+struct LongColumn {
+  Operand A;
+  __device__ int64_t operator()(int64_t k) const { return slot_begin(A, k + 1) - slot_begin(A, k) > kSplitMin; }
+};
+
+__global__ void k_split_rows(Operand A, int64_t nslots, const int64_t* sid_off, int32_t* slot_of_split) {
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < nslots; k += (int64_t)gridDim.x * blockDim.x)
+    if (slot_begin(A, k + 1) - slot_begin(A, k) > kSplitMin) slot_of_split[sid_off[k]] = (int32_t)k;
+}
+
+__global__ void k_split_fill(Operand A, const int64_t* nsplit_d, int64_t cap, const int32_t* slot_of_split,
+                             int32_t* splits, int32_t sstride, int32_t rbshift) {
+  const int64_t nsplit = *nsplit_d < cap ? *nsplit_d : cap;
+  const int64_t total = nsplit * sstride;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t sidx = i / sstride;
+    const int32_t b = (int32_t)(i - sidx * sstride);
+    const int32_t k = slot_of_split[sidx];
+    const int64_t a0 = slot_begin(A, k);
+    const int32_t al = (int32_t)(slot_begin(A, k + 1) - a0);
+    int32_t pos = al;
+    if (b < sstride - 1) {
+      const int64_t key = (int64_t)b << rbshift;
+      int32_t lo = 0, hi = al;
+      while (lo < hi) {
+        const int32_t mid = (lo + hi) >> 1;
+        if ((int64_t)A.ir[a0 + mid] < key)
+          lo = mid + 1;
+        else
+          hi = mid;
+      }
+      pos = lo;
+    }
+    splits[i] = pos;
   }
 }
 
@@ -145,11 +186,20 @@ __global__ void k_bin_offsets(unsigned long long* counts, int64_t* binoff, unsig
 
 __global__ void k_bin_fill(const int64_t* mults, int64_t nslots, BinCfg cfg, const int64_t* binoff,
                            unsigned long long* fill, int32_t* list) {
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < nslots; t += stride) {
-    const int b = bin_of(mults[t], cfg);
-    const int64_t pos = binoff[b] + (int64_t)atomicAdd(&fill[b], 1ull);
-    list[pos] = (int32_t)t;
+  __shared__ unsigned hist[kNumBins];
+  __shared__ int64_t base[kNumBins];
+  for (int64_t t0 = (int64_t)blockIdx.x * blockDim.x; t0 < nslots; t0 += (int64_t)gridDim.x * blockDim.x) {
+    for (int i = threadIdx.x; i < kNumBins; i += blockDim.x) hist[i] = 0;
+    __syncthreads();
+    const int64_t t = t0 + threadIdx.x;
+    const int b = t < nslots ? bin_of(mults[t], cfg) : -1;
+    const unsigned rank = b >= 0 ? atomicAdd(&hist[b], 1u) : 0u;
+    __syncthreads();
+    for (int i = threadIdx.x; i < kNumBins; i += blockDim.x)
+      if (hist[i]) base[i] = binoff[i] + (int64_t)atomicAdd(&fill[i], (unsigned long long)hist[i]);
+    __syncthreads();
+    if (b >= 0) list[base[b] + rank] = (int32_t)t;
+    __syncthreads();
   }
 }
 
@@ -177,21 +227,160 @@ __device__ __forceinline__ int32_t lower_bound_i32(const int32_t* a, int32_t n, 
   return lo;
 }
 
-template <class F>
-__device__ __forceinline__ void for_products(const Operand& A, const int64_t* bq_a0, const int32_t* bq_alen, int64_t b0,
-                                             int64_t b1, int G, int32_t r0, int32_t r1, bool full, F&& f) {
+// Where the products of one output column come from.  For every stored
+// B(k,j) (index q): the start and length of A(:,k), and for long columns of
+// A a row of the split table, whose entry b is the first position in A(:,k)
+// with row >= b * 2^rbshift (b = 0..nblk; the last entry is the length).
+// Parts of the row space start and end on those block boundaries, so a
+// part's range inside a long column costs two loads; short columns are
+// filtered entry by entry.
+struct ProdSrc {
+  const int32_t* air;
+  const int64_t* a0;
+  const int32_t* alen;
+  const int32_t* split;
+  const int32_t* splits;
+  int32_t sstride;
+  int32_t rbshift;
+  int32_t m;
+  int32_t pad;
+};
+
+
+// Calls f(r, a, b) for every product A(r,k)*B(k,j) of the column whose B
+// entries are [b0, b1), restricted to rows [r0, r1) unless `full`.  Each
+// lane issues U independent loads before using them (latency hiding).
+// Lanes diverge: f must not use cross-lane operations.
+template <int U, typename T, bool LOADA, bool LOADB, class F>
+__device__ __forceinline__ void for_products(const ProdSrc& S, const T* an, const T* bn, int64_t b0, int64_t b1,
+                                             int G, int32_t r0, int32_t r1, bool full, F&& f) {
   const int gid = threadIdx.x / G, gl = threadIdx.x & (G - 1), ng = blockDim.x / G;
   for (int64_t q = b0 + gid; q < b1; q += ng) {
-    const int64_t a0 = bq_a0[q];
-    const int32_t al = bq_alen[q];
-    const int32_t* col = A.ir + a0;
-    int32_t e = 0;
-    if (!full && al > 0 && r0 > 0) e = lower_bound_i32(col, al, r0);
-    for (e += gl; e < al; e += G) {
-      const int32_t r = col[e];
-      if (!full && r >= r1) break;
-      f(q, a0 + e, r);
+    const int64_t a0 = S.a0[q];
+    int32_t e0 = 0, e1 = S.alen[q];
+    bool filter = false;
+    if (!full) {
+      const int32_t sid = S.splits ? S.split[q] : -1;
+      if (sid >= 0) {
+        const int32_t* sp = S.splits + (int64_t)sid * S.sstride;
+        e0 = sp[r0 >> S.rbshift];
+        e1 = sp[r1 >= S.m ? S.sstride - 1 : (r1 >> S.rbshift)];
+      } else {
+        filter = true;
+      }
     }
+    T bv = T(0);
+    if constexpr (LOADB) bv = bn[q];
+    const int32_t* col = S.air + a0;
+    for (int32_t e = e0 + gl; e < e1; e += G * U) {
+      int32_t r[U];
+      T a[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int32_t ee = e + u * G;
+        const bool ok = ee < e1;
+        r[u] = ok ? col[ee] : -1;
+        if constexpr (LOADA) a[u] = ok ? an[a0 + ee] : T(0);
+        else a[u] = T(0);
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        if (r[u] < 0) continue;
+        if (filter && (r[u] < r0 || r[u] >= r1)) continue;
+        f(r[u], a[u], bv);
+      }
+    }
+  }
+}
+
+// Block-cooperative iteration over the products of one output column.
+// The column's stored B entries are taken in chunks of kQChunk: all threads
+// first load, in parallel, each entry's range in A (start, length -- from
+// the split table for long columns of A -- and B's value) into an LDS range
+// list with a prefix sum of the lengths; then the products of the chunk are
+// numbered 0..total-1 and every thread takes U of them per round (product
+// p of the round is found by binary search over the prefix), so each round
+// costs one level of global-memory latency for up to blockDim*U products.
+// Must be called by every thread of the workgroup (it contains barriers);
+// chunks hold min(blockDim.x, kQChunk) entries.
+constexpr int kQChunk = 256;
+
+struct RangeLds {
+  int64_t start[kQChunk];
+  int32_t pref[kQChunk + 1];
+  int32_t flt[kQChunk];
+  double bval[kQChunk];  // B's value, stored in the first bytes of each slot
+};
+
+template <int U, typename T, bool LOADA, bool LOADB, class F>
+__device__ __forceinline__ void block_products(const ProdSrc& S, const T* an, const T* bn, int64_t b0, int64_t b1,
+                                               int32_t r0, int32_t r1, bool full, RangeLds& R, int64_t* red, F&& f) {
+  const int qchunk = (int)blockDim.x < kQChunk ? (int)blockDim.x : kQChunk;
+  for (int64_t qc = b0; qc < b1; qc += qchunk) {
+    const int nq = (int)(b1 - qc < qchunk ? b1 - qc : qchunk);
+    int32_t mylen = 0;
+    if ((int)threadIdx.x < nq) {
+      const int i = threadIdx.x;
+      const int64_t q = qc + i;
+      const int64_t a0 = S.a0[q];
+      int32_t e0 = 0, e1 = S.alen[q];
+      int32_t flt = 0;
+      if (!full) {
+        const int32_t sid = S.splits ? S.split[q] : -1;
+        if (sid >= 0) {
+          const int32_t* sp = S.splits + (int64_t)sid * S.sstride;
+          e0 = sp[r0 >> S.rbshift];
+          e1 = sp[r1 >= S.m ? S.sstride - 1 : (r1 >> S.rbshift)];
+        } else {
+          flt = 1;
+        }
+      }
+      R.start[i] = a0 + e0;
+      R.flt[i] = flt;
+      if constexpr (LOADB) reinterpret_cast<T*>(&R.bval[i])[0] = bn[q];
+      mylen = e1 - e0;
+    }
+    int64_t total64;
+    const int64_t ex = block_excl_scan((int64_t)mylen, red, &total64);
+    if ((int)threadIdx.x < nq) R.pref[threadIdx.x] = (int32_t)ex;
+    if (threadIdx.x == 0) R.pref[nq] = (int32_t)total64;
+    __syncthreads();
+    const int32_t total = (int32_t)total64;
+    for (int32_t base = 0; base < total; base += (int32_t)blockDim.x * U) {
+      int32_t r[U];
+      T a[U];
+      int ix[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int32_t p = base + u * (int32_t)blockDim.x + (int32_t)threadIdx.x;
+        r[u] = -1;
+        a[u] = T(0);
+        ix[u] = 0;
+        if (p < total) {
+          int lo = 0, hi = nq;  // last i with pref[i] <= p
+          while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (R.pref[mid] <= p)
+              lo = mid;
+            else
+              hi = mid;
+          }
+          const int64_t e = R.start[lo] + (p - R.pref[lo]);
+          ix[u] = lo;
+          r[u] = S.air[e];
+          if constexpr (LOADA) a[u] = an[e];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        if (r[u] < 0) continue;
+        if (R.flt[ix[u]] && (r[u] < r0 || r[u] >= r1)) continue;
+        T bv = T(0);
+        if constexpr (LOADB) bv = reinterpret_cast<const T*>(&R.bval[ix[u]])[0];
+        f(r[u], a[u], bv);
+      }
+    }
+    __syncthreads();
   }
 }
 
@@ -310,36 +499,37 @@ __global__ void __launch_bounds__(256) k_tiny(Operand A, Operand B, const int64_
 // One workgroup per column; key-only open-addressing table of 2^log2s
 // slots (at least twice the number of products).  Columns listed before
 // position `multi_end` also get their distinct rows counted per row block.
-__global__ void k_count_hash(Operand A, Operand B, const int64_t* bq_a0, const int32_t* bq_alen, const int64_t* mults,
+__global__ void k_count_hash(Operand B, ProdSrc S, const int64_t* mults,
                              const int32_t* list, const int64_t* binoff, int bin, int log2s, int64_t multi_end,
                              int rbshift, int64_t nblk, uint32_t* blkcnt, int64_t* cnt, unsigned* err) {
   extern __shared__ __align__(16) unsigned char lds[];
   uint32_t* keys = (uint32_t*)lds;
-  const uint32_t S = 1u << log2s;
-  uint32_t* lblk = keys + S;  // per-block counters when they fit
+  const uint32_t TS = 1u << log2s;
+  uint32_t* lblk = keys + TS;  // per-block counters when they fit
   __shared__ int64_t red[1024 / kWave + 1];
+  __shared__ RangeLds s_rng;
   const int64_t beg = binoff[bin], end = binoff[bin + 1];
   for (int64_t pos = beg + blockIdx.x; pos < end; pos += gridDim.x) {
     const int32_t t = list[pos];
     const int64_t b0 = slot_begin(B, t), b1 = slot_begin(B, t + 1);
     const bool want_blk = pos < multi_end;
     const bool lds_blk = nblk <= 1024;
-    for (uint32_t i = threadIdx.x; i < S; i += blockDim.x) keys[i] = 0xffffffffu;
+    for (uint32_t i = threadIdx.x; i < TS; i += blockDim.x) keys[i] = 0xffffffffu;
     if (want_blk && lds_blk)
       for (int64_t i = threadIdx.x; i < nblk; i += blockDim.x) lblk[i] = 0;
     __syncthreads();
-    const int G = pick_group(mults[t], b1 - b0, blockDim.x);
     int64_t mine = 0;
-    for_products(A, bq_a0, bq_alen, b0, b1, G, 0, 0, true, [&](int64_t, int64_t, int32_t r) {
+    block_products<8, int, false, false>(S, nullptr, nullptr, b0, b1, 0, 0, true, s_rng, red, [&](int32_t r, int, int) {
+      if (r < 0) return;
       uint32_t h = hash_row(r, log2s);
-      for (uint32_t probe = 0; probe < S; ++probe) {
+      for (uint32_t probe = 0; probe < TS; ++probe) {
         const uint32_t old = atomicCAS(&keys[h], 0xffffffffu, (uint32_t)r);
         if (old == 0xffffffffu) {
           ++mine;
           return;
         }
         if (old == (uint32_t)r) return;
-        h = (h + 1) & (S - 1);
+        h = (h + 1) & (TS - 1);
       }
       atomicOr(err, 2u);
     });
@@ -349,7 +539,7 @@ __global__ void k_count_hash(Operand A, Operand B, const int64_t* bq_a0, const i
     if (threadIdx.x == 0) cnt[t] = total;
     if (want_blk) {
       uint32_t* dst = blkcnt + (pos - binoff[0]) * nblk;
-      for (uint32_t i = threadIdx.x; i < S; i += blockDim.x) {
+      for (uint32_t i = threadIdx.x; i < TS; i += blockDim.x) {
         const uint32_t key = keys[i];
         if (key != 0xffffffffu) {
           if (lds_blk)
@@ -371,51 +561,51 @@ __global__ void k_count_hash(Operand A, Operand B, const int64_t* bq_a0, const i
 // One workgroup per heavy column; an LDS bitmap over (a chunk of) the row
 // space marks every row that receives a product.  Popcounts give the exact
 // column count and the per-row-block counts used to cut parts.
-__global__ void k_count_bitmap(Operand A, Operand B, const int64_t* bq_a0, const int32_t* bq_alen,
-                               const int64_t* mults, const int32_t* list, const int64_t* binoff, int64_t m,
-                               int chunk_words, int rbshift, int64_t nblk, uint32_t* blkcnt, int64_t* cnt) {
+__global__ void k_count_bitmap(Operand B, ProdSrc S, const int64_t* mults, const int32_t* list, const int64_t* binoff,
+                               int64_t m, int chunk_log2, int rbshift, int64_t nblk, uint32_t* blkcnt,
+                               unsigned long long* cnt) {
   extern __shared__ __align__(16) unsigned char lds[];
   uint32_t* bm = (uint32_t*)lds;
-  const int blk_per_chunk = (int)(((int64_t)chunk_words * 32 + (1ll << rbshift) - 1) >> rbshift);
-  uint32_t* lblk = bm + chunk_words;
+  const int64_t chunk_rows = 1ll << chunk_log2;  // a multiple of the row block
+  const int64_t nchunks = (m + chunk_rows - 1) >> chunk_log2;
+  const int blk_per_chunk = (int)(chunk_rows >> rbshift);
+  uint32_t* lblk = bm + (chunk_rows >> 5);
   __shared__ int64_t red[1024 / kWave + 1];
+  __shared__ RangeLds s_rng;
   const int64_t beg = binoff[0], end = binoff[kBinHash0];
-  const int64_t chunk_rows = (int64_t)chunk_words * 32;
-  for (int64_t pos = beg + blockIdx.x; pos < end; pos += gridDim.x) {
+  const int64_t items = (end - beg) * nchunks;
+  for (int64_t item = blockIdx.x; item < items; item += gridDim.x) {
+    const int64_t pos = beg + item / nchunks;
+    const int64_t c0 = (item % nchunks) * chunk_rows;
+    const int64_t c1 = c0 + chunk_rows < m ? c0 + chunk_rows : m;
     const int32_t t = list[pos];
     const int64_t b0 = slot_begin(B, t), b1 = slot_begin(B, t + 1);
-    const int G = pick_group(mults[t], b1 - b0, blockDim.x);
     uint32_t* dst = blkcnt + (pos - beg) * nblk;
-    int64_t total = 0;
-    for (int64_t c0 = 0; c0 < m; c0 += chunk_rows) {
-      const int64_t c1 = c0 + chunk_rows < m ? c0 + chunk_rows : m;
-      const int words = (int)((c1 - c0 + 31) >> 5);
-      for (int i = threadIdx.x; i < words; i += blockDim.x) bm[i] = 0;
-      for (int i = threadIdx.x; i < blk_per_chunk; i += blockDim.x) lblk[i] = 0;
-      __syncthreads();
-      const bool full = (c0 == 0 && c1 == m);
-      for_products(A, bq_a0, bq_alen, b0, b1, G, (int32_t)c0, (int32_t)c1, full, [&](int64_t, int64_t, int32_t r) {
-        const uint32_t d = (uint32_t)(r - (int32_t)c0);
-        if (d < (uint32_t)(c1 - c0)) atomicOr(&bm[d >> 5], 1u << (d & 31));
-      });
-      __syncthreads();
-      int64_t mine = 0;
-      for (int i = threadIdx.x; i < words; i += blockDim.x) {
-        const int pc = __popc(bm[i]);
-        if (pc) {
-          mine += pc;
-          atomicAdd(&lblk[((int64_t)i * 32) >> rbshift], (uint32_t)pc);
-        }
+    const int words = (int)((c1 - c0 + 31) >> 5);
+    for (int i = threadIdx.x; i < words; i += blockDim.x) bm[i] = 0;
+    for (int i = threadIdx.x; i < blk_per_chunk; i += blockDim.x) lblk[i] = 0;
+    __syncthreads();
+    block_products<8, int, false, false>(S, nullptr, nullptr, b0, b1, (int32_t)c0, (int32_t)c1, nchunks == 1, s_rng,
+                                         red, [&](int32_t r, int, int) {
+      const uint32_t d = (uint32_t)(r - (int32_t)c0);
+      if (d < (uint32_t)(c1 - c0)) atomicOr(&bm[d >> 5], 1u << (d & 31));
+    });
+    __syncthreads();
+    int64_t mine = 0;
+    for (int i = threadIdx.x; i < words; i += blockDim.x) {
+      const int pc = __popc(bm[i]);
+      if (pc) {
+        mine += pc;
+        atomicAdd(&lblk[((int64_t)i * 32) >> rbshift], (uint32_t)pc);
       }
-      int64_t ctot;
-      block_excl_scan(mine, red, &ctot);
-      total += ctot;
-      const int64_t bfirst = c0 >> rbshift;
-      for (int i = threadIdx.x; i < blk_per_chunk; i += blockDim.x)
-        if (bfirst + i < nblk) dst[bfirst + i] = lblk[i];
-      __syncthreads();
     }
-    if (threadIdx.x == 0) cnt[t] = total;
+    int64_t ctot;
+    block_excl_scan(mine, red, &ctot);
+    const int64_t bfirst = c0 >> rbshift;
+    for (int i = threadIdx.x; i < blk_per_chunk; i += blockDim.x)
+      if (bfirst + i < nblk) dst[bfirst + i] = lblk[i];
+    if (threadIdx.x == 0 && ctot) atomicAdd(&cnt[t], (unsigned long long)ctot);
+    __syncthreads();
   }
 }
 
@@ -510,7 +700,7 @@ __device__ int64_t cut_parts(const PartCfg& p, const uint32_t* blk, int32_t t, i
 
 // Number of parts of every non-tiny, nonempty column (list positions
 // [0, npos)), or the parts themselves (emit).
-__global__ void k_parts(PartCfg p, const int32_t* list, int64_t npos, int64_t multi_begin, int64_t multi_end,
+__global__ void k_parts(PartCfg p, PartCfg ps, const int32_t* list, int64_t npos, int64_t multi_begin, int64_t multi_end,
                         const int64_t* cnt, const int64_t* off, const uint32_t* blkcnt, int64_t* nparts,
                         const int64_t* poff, Part* parts, unsigned* err) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -526,15 +716,16 @@ __global__ void k_parts(PartCfg p, const int32_t* list, int64_t npos, int64_t mu
                      err);
     } else {
       np = 1;
-      if (!emit && !(bitmap_ok(p, p.m, c) || hash_ok(p, c))) atomicOr(err, 4u);
+      const PartCfg& q = pos < multi_end ? p : ps;
+      if (!emit && !(bitmap_ok(q, q.m, c) || hash_ok(q, c))) atomicOr(err, 4u);
       if (emit) {
         Part P;
         P.off = off[t];
         P.t = t;
         P.c = (int32_t)c;
         P.r0 = 0;
-        P.r1 = (int32_t)p.m;
-        P.mode = choose_mode(p, p.m, c);
+        P.r1 = (int32_t)q.m;
+        P.mode = choose_mode(q, q.m, c);
         P.pad = 0;
         parts[poff[pos]] = P;
       }
@@ -568,17 +759,18 @@ __device__ __forceinline__ void block_bitonic_sort(uint64_t* a, int n2) {
 // values by rank, write rows and values in order.  Hash mode: accumulate
 // into an open-addressing table, then sort (row, slot) keys.
 template <int SR, typename T>
-__global__ void __launch_bounds__(1024) k_numeric_parts(Operand A, Operand B, const int64_t* bq_a0,
-                                                        const int32_t* bq_alen, const int64_t* mults,
+__global__ void __launch_bounds__(1024) k_numeric_parts(Operand A, Operand B, ProdSrc S,
+                                                        const int64_t* mults,
                                                         const int64_t* cnt, const Part* parts, int64_t nparts,
                                                         unsigned long long* work, int32_t* cir, T* cnum,
                                                         unsigned* err) {
-  using S = Semiring<SR, T>;
+  using SR_ = Semiring<SR, T>;
   constexpr bool kVal = SR != SPX_OR_AND;
   extern __shared__ __align__(16) unsigned char lds[];
   __shared__ int64_t s_pi;
   __shared__ int64_t red[1024 / kWave + 1];
   __shared__ unsigned s_ctr;
+  __shared__ RangeLds s_rng;
   const T* an = (const T*)A.num;
   const T* bn = (const T*)B.num;
   for (;;) {
@@ -592,8 +784,6 @@ __global__ void __launch_bounds__(1024) k_numeric_parts(Operand A, Operand B, co
     const int64_t span = (int64_t)P.r1 - P.r0;
     const bool full = (P.r0 == 0 && P.r1 == (int32_t)A.m);
     // products in this part ~ mults * c / cnt
-    const int64_t ct = cnt[P.t] > 0 ? cnt[P.t] : 1;
-    const int G = pick_group((mults[P.t] * P.c + ct - 1) / ct, b1 - b0, blockDim.x);
     const int c = P.c;
     if (P.mode == 0) {
       const int W = (int)((span + 63) >> 6);
@@ -602,9 +792,10 @@ __global__ void __launch_bounds__(1024) k_numeric_parts(Operand A, Operand B, co
       T* vals = (T*)(lds + W * 8 + ((W * 2 + 7) & ~7));
       for (int i = threadIdx.x; i < W; i += blockDim.x) bm[i] = 0;
       if constexpr (kVal)
-        for (int i = threadIdx.x; i < c; i += blockDim.x) vals[i] = S::ident();
+        for (int i = threadIdx.x; i < c; i += blockDim.x) vals[i] = SR_::ident();
       __syncthreads();
-      for_products(A, bq_a0, bq_alen, b0, b1, G, P.r0, P.r1, full, [&](int64_t, int64_t, int32_t r) {
+      block_products<8, int, false, false>(S, nullptr, nullptr, b0, b1, P.r0, P.r1, full, s_rng, red,
+                                           [&](int32_t r, int, int) {
         const uint32_t d = (uint32_t)(r - P.r0);
         atomicOr((unsigned long long*)&bm[d >> 6], 1ull << (d & 63));
       });
@@ -624,13 +815,12 @@ __global__ void __launch_bounds__(1024) k_numeric_parts(Operand A, Operand B, co
       if (threadIdx.x == 0 && tot != c) atomicOr(err, 8u);
       __syncthreads();
       if constexpr (kVal) {
-        for_products(A, bq_a0, bq_alen, b0, b1, G, P.r0, P.r1, full, [&](int64_t q, int64_t e, int32_t r) {
+        block_products<4, T, SR_::kUsesA, SR_::kUsesB>(S, an, bn, b0, b1, P.r0, P.r1, full, s_rng, red,
+                                                       [&](int32_t r, T a, T bv) {
           const uint32_t d = (uint32_t)(r - P.r0);
           const uint64_t word = bm[d >> 6];
           const int rank = (int)pre[d >> 6] + __popcll(word & ((1ull << (d & 63)) - 1ull));
-          const T a = S::kUsesA ? an[e] : T(0);
-          const T bv = S::kUsesB ? bn[q] : T(0);
-          if (rank < c) S::lds_acc(&vals[rank], S::mul(a, bv));
+          if (rank < c) SR_::lds_acc(&vals[rank], SR_::mul(a, bv));
         });
         __syncthreads();
         for (int i = threadIdx.x; i < c; i += blockDim.x) cnum[P.off + i] = vals[i];
@@ -660,20 +850,18 @@ __global__ void __launch_bounds__(1024) k_numeric_parts(Operand A, Operand B, co
       uint64_t* sortb = (uint64_t*)(lds + Sz * 4 + ((Sz * sizeof(T) * (kVal ? 1 : 0) + 7) & ~7u));
       for (uint32_t i = threadIdx.x; i < Sz; i += blockDim.x) {
         keys[i] = 0xffffffffu;
-        if constexpr (kVal) vals[i] = S::ident();
+        if constexpr (kVal) vals[i] = SR_::ident();
       }
       if (threadIdx.x == 0) s_ctr = 0;
       __syncthreads();
-      for_products(A, bq_a0, bq_alen, b0, b1, G, P.r0, P.r1, full, [&](int64_t q, int64_t e, int32_t r) {
+      block_products<4, T, SR_::kUsesA, SR_::kUsesB>(S, an, bn, b0, b1, P.r0, P.r1, full, s_rng, red,
+                                                     [&](int32_t r, T a, T bv) {
+        if (r < 0) return;
         uint32_t h = hash_row(r, log2s);
         for (uint32_t probe = 0; probe < Sz; ++probe) {
           const uint32_t old = atomicCAS(&keys[h], 0xffffffffu, (uint32_t)r);
           if (old == 0xffffffffu || old == (uint32_t)r) {
-            if constexpr (kVal) {
-              const T a = S::kUsesA ? an[e] : T(0);
-              const T bv = S::kUsesB ? bn[q] : T(0);
-              S::lds_acc(&vals[h], S::mul(a, bv));
-            }
+            if constexpr (kVal) SR_::lds_acc(&vals[h], SR_::mul(a, bv));
             return;
           }
           h = (h + 1) & (Sz - 1);
@@ -748,6 +936,25 @@ __global__ void k_write_dcsc(Operand B, const int64_t* cnt, const int64_t* off, 
   }
 }
 
+// Sum of the exact counts of the columns in bin `bin`.
+__global__ void k_bin_sum(const int32_t* list, const int64_t* binoff, int bin, const int64_t* cnt,
+                          unsigned long long* out) {
+  const int64_t beg = binoff[bin], end = binoff[bin + 1];
+  int64_t s = 0;
+  for (int64_t p = beg + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < end; p += (int64_t)gridDim.x * blockDim.x)
+    s += cnt[list[p]];
+  s = wave_sum(s);
+  if (lane_id() == 0 && s) atomicAdd(out, (unsigned long long)s);
+}
+
+__global__ void k_parts_sum(const Part* parts, int64_t n, unsigned long long* out) {
+  int64_t s = 0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    s += parts[i].c;
+  s = wave_sum(s);
+  if (lane_id() == 0 && s) atomicAdd(out, (unsigned long long)s);
+}
+
 struct NonzeroFlag {
   const int64_t* cnt;
   __device__ int64_t operator()(int64_t i) const { return cnt[i] > 0 ? 1 : 0; }
@@ -762,21 +969,43 @@ namespace spx {
 
 struct Summary {
   unsigned long long mults;
-  unsigned long long nzc;
+  unsigned long long nnz_tiny;
+  unsigned long long nnz_multi;
   unsigned long long work;
+  unsigned long long work2;
   unsigned err;
   unsigned pad;
 };
 
+enum { kEvPlan0, kEvPlan1, kEvExec0, kEvMulti, kEvParts, kEvTiny, kEvPtr, kNumEv };
+
 struct GemmPlan : spx_plan {
-  explicit GemmPlan(const spx_ctx* c) : spx_plan(c, kPlanGemm) {}
+  explicit GemmPlan(const spx_ctx* c) : spx_plan(c, kPlanGemm) {
+    if (c && c->profile) {
+      profile = true;
+      for (auto& e : ev) (void)hipEventCreate(&e);
+    }
+  }
+  ~GemmPlan() override {
+    if (profile)
+      for (auto& e : ev) (void)hipEventDestroy(e);
+  }
+  void mark(int i, hipStream_t st) {
+    if (profile) (void)hipEventRecord(ev[i], st);
+  }
+  bool profile = false;
+  bool ran_parts = false, ran_tiny = false;
+  hipEvent_t ev[kNumEv] = {};
   Operand A{}, B{};
   int32_t sr = 0, vt = 0, c_fmt = 0;
   spx_tuning tune{};
-  int64_t nslots = 0, nnz = 0, nzc = 0, mults = 0, nparts = 0;
+  int64_t nslots = 0, nnz = 0, nzc = 0, mults = 0, nparts = 0, psplit = 0, nnz_tiny = 0, nnz_multi = 0;
   int64_t binoff_h[kNumBins + 1] = {};
   int64_t* bq_a0 = nullptr;
   int32_t* bq_alen = nullptr;
+  int32_t* bq_split = nullptr;
+  int32_t* splits = nullptr;
+  ProdSrc src{};
   int64_t* aux = nullptr;
   int64_t* mults_d = nullptr;
   int64_t* cnt = nullptr;
@@ -786,7 +1015,7 @@ struct GemmPlan : spx_plan {
   int64_t* binoff = nullptr;
   Part* parts = nullptr;
   Summary* sum = nullptr;
-  int64_t L = 0;
+  int64_t L = 0, L_single = 0;
 };
 
 int check_mat(const spx_mat* X, const char* name) {
@@ -828,10 +1057,14 @@ int summary_sync(GemmPlan* P, hipStream_t st, Summary* host) {
 extern "C" void spx_default_tuning(spx_tuning* t) {
   std::memset(t, 0, sizeof(*t));
   t->tiny_max = 64;
-  t->medium_max = 1 << 14;
-  t->part_lds_bytes = 144 * 1024;
-  t->medium_threads = 256;
-  t->heavy_threads = 1024;
+  t->hash_count_max = 1 << 14;
+  t->single_part_max = 1024;
+  t->part_lds_bytes = 72 * 1024;
+  t->count_threads = 256;
+  t->bitmap_threads = 1024;
+  t->part_threads = 512;
+  t->single_threads = 256;
+  t->bitmap_chunk_log2 = 20;
 }
 
 template <int SR, typename T>
@@ -840,22 +1073,31 @@ static int launch_numeric(GemmPlan* P, spx_mat* C, hipStream_t st) {
   T* cnum = (T*)C->num;
   unsigned* err = &P->sum->err;
   const int cus = device_cu_count();
-  if (P->nparts > 0) {
-    unsigned long long* work = &P->sum->work;
-    SPX_TRY(fill_i64((int64_t*)work, 1, 0, st));
-    const int blk = P->tune.heavy_threads;
-    const int per_cu = std::max<int64_t>(1, (160 * 1024) / (P->L + 2048));
-    const unsigned grid = (unsigned)std::min<int64_t>(P->nparts, (int64_t)cus * per_cu);
-    hipLaunchKernelGGL((k_numeric_parts<SR, T>), dim3(grid), dim3(blk), (size_t)P->L, st, P->A, P->B, P->bq_a0,
-                       P->bq_alen, P->mults_d, P->cnt, P->parts, P->nparts, work, cir, cnum, err);
+  // parts of multi-part columns [0, psplit), single-part columns [psplit, nparts)
+  const int64_t ranges[2][2] = {{0, P->psplit}, {P->psplit, P->nparts}};
+  for (int r = 0; r < 2; ++r) {
+    const int64_t n0 = ranges[r][0], n1 = ranges[r][1];
+    if (n1 <= n0) continue;
+    unsigned long long* work = r == 0 ? &P->sum->work : &P->sum->work2;
+    SPX_TRY(fill_i64((int64_t*)work, 1, n0, st));
+    const int blk = r == 0 ? P->tune.part_threads : P->tune.single_threads;
+    const int64_t L = r == 0 ? P->L : P->L_single;
+    const int per_cu = (int)std::max<int64_t>(1, std::min<int64_t>((160 * 1024) / (L + 8192), 2048 / blk));
+    const unsigned grid = (unsigned)std::min<int64_t>(n1 - n0, (int64_t)cus * per_cu);
+    hipLaunchKernelGGL((k_numeric_parts<SR, T>), dim3(grid), dim3(blk), (size_t)L, st, P->A, P->B, P->src,
+                       P->mults_d, P->cnt, P->parts, n1, work, cir, cnum, err);
     SPX_HIP(hipGetLastError());
+    if (r == 0) P->mark(kEvMulti, st);
   }
+  if (P->psplit == 0) P->mark(kEvMulti, st);
+  P->mark(kEvParts, st);
   const int64_t ntiny = P->binoff_h[kBinTiny + 1] - P->binoff_h[kBinTiny];
   if (ntiny > 0) {
     hipLaunchKernelGGL((k_tiny<SR, T, false>), dim3(grid_for(ntiny, 4, (int64_t)cus * 16)), dim3(256), 0, st, P->A,
                        P->B, P->bq_a0, P->bq_alen, P->list, P->binoff, P->cnt, P->off, cir, cnum);
     SPX_HIP(hipGetLastError());
   }
+  P->mark(kEvTiny, st);
   return SPX_OK;
 }
 
@@ -908,12 +1150,20 @@ extern "C" int spx_spgemm_plan(const spx_ctx* ctx, const spx_mat* A, const spx_m
   spx_default_tuning(&tune);
   if (tuning) tune = *tuning;
   if (tune.tiny_max < 0 || tune.tiny_max > 64) return fail(SPX_EINVAL, "tiny_max must be in [0, 64]");
-  if (tune.medium_max < tune.tiny_max || tune.medium_max > (1 << 14))
-    return fail(SPX_EINVAL, "medium_max must be in [tiny_max, 16384]");
-  if (tune.heavy_threads % 64 || tune.heavy_threads < 64 || tune.heavy_threads > 1024 || tune.medium_threads % 64 ||
-      tune.medium_threads < 64 || tune.medium_threads > 1024)
-    return fail(SPX_EINVAL, "thread counts must be multiples of 64 in [64, 1024]");
+  if (tune.hash_count_max < tune.tiny_max || tune.hash_count_max > (1 << 14))
+    return fail(SPX_EINVAL, "hash_count_max must be in [tiny_max, 16384]");
+  if (tune.single_part_max < 64 || tune.single_part_max > 4096 || (tune.single_part_max & (tune.single_part_max - 1)))
+    return fail(SPX_EINVAL, "single_part_max must be a power of two in [64, 4096]");
+  for (int th : {tune.count_threads, tune.bitmap_threads, tune.part_threads, tune.single_threads})
+    if (th % 64 || th < 64 || th > 1024) return fail(SPX_EINVAL, "thread counts must be multiples of 64 in [64, 1024]");
 
+  if (ctx && ctx->validate) {
+    int32_t ok = 0;
+    SPX_TRY(spx_check(ctx, A, &ok));
+    if (!ok) return fail(SPX_EINVAL, "A is not canonical");
+    SPX_TRY(spx_check(ctx, B, &ok));
+    if (!ok) return fail(SPX_EINVAL, "B is not canonical");
+  }
   auto* P = new GemmPlan(ctx);
   std::unique_ptr<GemmPlan> guard(P);
   hipStream_t st = stream_of(ctx);
@@ -933,12 +1183,20 @@ extern "C" int spx_spgemm_plan(const spx_ctx* ctx, const spx_mat* A, const spx_m
   // Row blocks: the largest power of two <= 2^14 such that one dense block
   // fits a part in bitmap mode.
   int64_t L = tune.part_lds_bytes;
-  if (L > 160 * 1024 - 4096) L = 160 * 1024 - 4096;
+  if (L > 160 * 1024 - 8192) L = 160 * 1024 - 8192;
   int rb = 14;
   while (rb > 6 && ((1ll << rb) * sz + ((1ll << rb) / 64) * 10 + 256) > L) --rb;
   if (((1ll << rb) * sz + ((1ll << rb) / 64) * 10 + 256) > L) return fail(SPX_EINVAL, "part_lds_bytes too small");
   P->L = L;
+  int sp_log2 = 6;
+  while ((1 << sp_log2) < tune.single_part_max) ++sp_log2;
+  {
+    const int64_t p2 = tune.single_part_max, S2 = 2 * p2;
+    P->L_single = S2 * 4 + ((S2 * sz + 7) & ~7ll) + p2 * 8 + 64;
+    if (P->L_single > 160 * 1024 - 8192) return fail(SPX_EINVAL, "single_part_max too large for LDS");
+  }
   const int64_t nblk = std::max<int64_t>(1, ceil_div(m, 1ll << rb));
+  P->mark(kEvPlan0, st);
 
   SPX_TRY(scr.get_n(1, &P->sum));
   SPX_TRY(fill_i64((int64_t*)P->sum, sizeof(Summary) / 8, 0, st));
@@ -960,12 +1218,31 @@ extern "C" int spx_spgemm_plan(const spx_ctx* ctx, const spx_mat* A, const spx_m
   // AUX index for a DCSC A
   int64_t chunk = 1;
   SPX_TRY(build_aux(P->A, scr, st, &P->aux, &chunk));
-  if (B->nnz > 0) {
-    k_rowinfo<<<grid_for(B->nnz, 256, (int64_t)cus * 32), 256, 0, st>>>(P->A, P->B, P->aux, chunk, P->bq_a0,
-                                                                         P->bq_alen, err);
+  // split table of A's long columns
+  const int64_t nslots_a = nslots_of(P->A);
+  const int64_t split_cap = A->nnz / (kSplitMin + 1) + 1;
+  const int32_t sstride = (int32_t)nblk + 1;
+  int64_t* sid_off = nullptr;
+  if (A->nnz > kSplitMin && nslots_a > 0) {
+    int32_t* slot_of_split = nullptr;
+    SPX_TRY(scr.get_n(nslots_a + 1, &sid_off));
+    SPX_TRY(scr.get_n(split_cap, &slot_of_split));
+    SPX_TRY(scr.get_n(split_cap * sstride, &P->splits));
+    SPX_TRY(exclusive_scan(LongColumn{P->A}, nslots_a, sid_off, scr, st));
+    k_split_rows<<<grid_for(nslots_a, 256, 65536), 256, 0, st>>>(P->A, nslots_a, sid_off, slot_of_split);
+    SPX_HIP(hipGetLastError());
+    k_split_fill<<<grid_for(split_cap * sstride, 256, (int64_t)cus * 64), 256, 0, st>>>(
+        P->A, sid_off + nslots_a, split_cap, slot_of_split, P->splits, sstride, rb);
     SPX_HIP(hipGetLastError());
   }
-  BinCfg bc{tune.tiny_max, tune.medium_max};
+  SPX_TRY(scr.get_n(std::max<int64_t>(B->nnz, 1), &P->bq_split));
+  if (B->nnz > 0) {
+    k_rowinfo<<<grid_for(B->nnz, 256, (int64_t)cus * 32), 256, 0, st>>>(P->A, P->B, P->aux, chunk, sid_off, P->bq_a0,
+                                                                         P->bq_alen, P->bq_split, err);
+    SPX_HIP(hipGetLastError());
+  }
+  P->src = ProdSrc{A->ir, P->bq_a0, P->bq_alen, P->bq_split, P->splits, sstride, rb, (int32_t)m, 0};
+  BinCfg bc{tune.tiny_max, tune.hash_count_max};
   if (nslots > 0) {
     k_slot_mults<<<grid_for(nslots * kWave, 256, (int64_t)cus * 32), 256, 0, st>>>(P->B, P->bq_alen, nslots,
                                                                                    P->mults_d, &P->sum->mults);
@@ -987,7 +1264,8 @@ extern "C" int spx_spgemm_plan(const spx_ctx* ctx, const spx_mat* A, const spx_m
   if (hs.err & 1u) return fail(SPX_EINVAL, "B has a row index outside A's columns");
   P->mults = (int64_t)hs.mults;
   const int64_t* bo = P->binoff_h;
-  const int64_t multi_begin = bo[0], multi_end = bo[kBinMultiEnd];
+  // columns with more than single_part_max products get row-block counts
+  const int64_t multi_begin = bo[0], multi_end = bo[std::min(kBinHash0 + 14 - sp_log2, kBinTiny)];
   const int64_t nmulti = multi_end - multi_begin;
   uint32_t* blkcnt = nullptr;
   if (nmulti > 0) {
@@ -1008,22 +1286,23 @@ extern "C" int spx_spgemm_plan(const spx_ctx* ctx, const spx_mat* A, const spx_m
     if (nb == 0) continue;
     const int log2s = kHashLog2Max - (b - kBinHash0);
     const size_t lds = ((size_t)4 << log2s) + (nblk <= 1024 ? (size_t)nblk * 4 : 0);
-    const int blk = log2s >= 13 ? std::max(tune.medium_threads, 512) : tune.medium_threads;
-    const int per_cu = std::max<int>(1, (int)((160 * 1024) / (lds + 1024)));
+    const int blk = log2s >= 13 ? std::max(tune.count_threads, 512) : tune.count_threads;
+    const int per_cu = std::max<int>(1, (int)((160 * 1024) / (lds + 8192)));
     k_count_hash<<<(unsigned)std::min<int64_t>(nb, (int64_t)cus * per_cu), blk, lds, st>>>(
-        P->A, P->B, P->bq_a0, P->bq_alen, P->mults_d, P->list, P->binoff, b, log2s, multi_end, rb, nblk, blkcnt,
-        P->cnt, err);
+        P->B, P->src, P->mults_d, P->list, P->binoff, b, log2s, multi_end, rb, nblk, blkcnt, P->cnt, err);
     SPX_HIP(hipGetLastError());
   }
   const int64_t nbitmap = bo[kBinHash0] - bo[0];
   if (nbitmap > 0) {
-    const int64_t mw = ceil_div(std::max<int64_t>(m, 1), 32);
-    const int chunk_words = (int)std::min<int64_t>(mw, 1ll << (kBitmapChunkLog2 - 5));
-    const int blk_per_chunk = (int)ceil_div((int64_t)chunk_words * 32, 1ll << rb);
-    const size_t lds = (size_t)chunk_words * 4 + (size_t)blk_per_chunk * 4 + 16;
-    const int per_cu = std::max<int>(1, (int)((160 * 1024) / (lds + 1024)));
-    k_count_bitmap<<<(unsigned)std::min<int64_t>(nbitmap, (int64_t)cus * per_cu), tune.heavy_threads, lds, st>>>(
-        P->A, P->B, P->bq_a0, P->bq_alen, P->mults_d, P->list, P->binoff, m, chunk_words, rb, nblk, blkcnt, P->cnt);
+    // bitmap chunks: a power of two of rows, a multiple of the row block
+    int clog = std::max<int>(rb, std::min<int>(tune.bitmap_chunk_log2, 20));
+    while (clog > rb && (1ll << (clog - 1)) >= m) --clog;
+    const int64_t nchunks = ceil_div(m, 1ll << clog);
+    const size_t lds = ((size_t)1 << clog) / 8 + (((size_t)1 << clog) >> rb) * 4 + 16;
+    const int per_cu = std::max<int>(1, std::min<int>((int)((160 * 1024) / (lds + 8192)), 2048 / tune.bitmap_threads));
+    k_count_bitmap<<<(unsigned)std::min<int64_t>(nbitmap * nchunks, (int64_t)cus * per_cu), tune.bitmap_threads, lds,
+                     st>>>(P->B, P->src, P->mults_d, P->list, P->binoff, m, clog, rb, nblk, blkcnt,
+                           (unsigned long long*)P->cnt);
     SPX_HIP(hipGetLastError());
   }
   // column pointers and nonempty-column offsets
@@ -1033,30 +1312,46 @@ extern "C" int spx_spgemm_plan(const spx_ctx* ctx, const spx_mat* A, const spx_m
   const int64_t npos = bo[kBinTiny];
   int64_t *np = nullptr, *poff = nullptr;
   PartCfg pc{L, m, sz, rb, nblk};
+  PartCfg pcs{P->L_single, m, sz, rb, nblk};
   if (npos > 0) {
     SPX_TRY(scr.get_n(npos, &np));
     SPX_TRY(scr.get_n(npos + 1, &poff));
-    k_parts<<<grid_for(npos, 256, (int64_t)cus * 16), 256, 0, st>>>(pc, P->list, npos, multi_begin, multi_end, P->cnt,
+    k_parts<<<grid_for(npos, 256, (int64_t)cus * 16), 256, 0, st>>>(pc, pcs, P->list, npos, multi_begin, multi_end, P->cnt,
                                                                     P->off, blkcnt, np, nullptr, nullptr, err);
     SPX_HIP(hipGetLastError());
     SPX_TRY(exclusive_scan(LoadI64{np}, npos, poff, scr, st));
   }
+  if (ntiny > 0) {
+    k_bin_sum<<<grid_for(ntiny, 256, 1024), 256, 0, st>>>(P->list, P->binoff, kBinTiny, P->cnt, &P->sum->nnz_tiny);
+    SPX_HIP(hipGetLastError());
+  }
   // sync 2: sizes
-  int64_t tail[3] = {0, 0, 0};
+  int64_t tail[4] = {0, 0, 0, 0};
   SPX_HIP(hipMemcpyAsync(&tail[0], P->off + nslots, 8, hipMemcpyDeviceToHost, st));
   SPX_HIP(hipMemcpyAsync(&tail[1], P->zoff + nslots, 8, hipMemcpyDeviceToHost, st));
-  if (npos > 0) SPX_HIP(hipMemcpyAsync(&tail[2], poff + npos, 8, hipMemcpyDeviceToHost, st));
+  if (npos > 0) {
+    SPX_HIP(hipMemcpyAsync(&tail[2], poff + npos, 8, hipMemcpyDeviceToHost, st));
+    SPX_HIP(hipMemcpyAsync(&tail[3], poff + multi_end, 8, hipMemcpyDeviceToHost, st));
+  }
   SPX_TRY(summary_sync(P, st, &hs));
   if (hs.err & 4u) return fail(SPX_EUNSUPPORTED, "a row block is too dense for the LDS budget");
   P->nnz = tail[0];
   P->nzc = tail[1];
   P->nparts = tail[2];
+  P->psplit = tail[3];
+  P->nnz_tiny = (int64_t)hs.nnz_tiny;
   if (P->nparts > 0) {
     SPX_TRY(scr.get_n(P->nparts, &P->parts));
-    k_parts<<<grid_for(npos, 256, (int64_t)cus * 16), 256, 0, st>>>(pc, P->list, npos, multi_begin, multi_end, P->cnt,
+    k_parts<<<grid_for(npos, 256, (int64_t)cus * 16), 256, 0, st>>>(pc, pcs, P->list, npos, multi_begin, multi_end, P->cnt,
                                                                     P->off, blkcnt, nullptr, poff, P->parts, err);
     SPX_HIP(hipGetLastError());
+    if (P->psplit > 0) {
+      k_parts_sum<<<grid_for(P->psplit, 256, 1024), 256, 0, st>>>(P->parts, P->psplit, &P->sum->nnz_multi);
+      SPX_HIP(hipGetLastError());
+      P->nnz_multi = -1;  // read by spx_plan_get_info
+    }
   }
+  P->mark(kEvPlan1, st);
   if (nnz_c) *nnz_c = P->nnz;
   if (nzc_c) *nzc_c = P->nzc;
   *plan = guard.release();
@@ -1078,7 +1373,14 @@ extern "C" int spx_spgemm_exec(spx_plan* plan, spx_mat* C) {
   C->nnz = P->nnz;
   C->nzc = C->fmt == SPX_DCSC ? P->nzc : 0;
   hipStream_t st = stream_of(&P->ctx);
+  P->mark(kEvExec0, st);
+  P->ran_parts = P->ran_tiny = false;
   if (P->nnz > 0) SPX_TRY(dispatch_numeric(P, C, st));
+  else {
+    P->mark(kEvMulti, st);
+    P->mark(kEvParts, st);
+    P->mark(kEvTiny, st);
+  }
   if (C->fmt == SPX_CSC) {
     k_write_csc_cp<<<grid_for(C->n + 1, 256, 65536), 256, 0, st>>>(P->B, P->off, P->nslots, C->n, C->cp, C->ptr_t);
   } else if (P->nslots > 0) {
@@ -1091,6 +1393,28 @@ extern "C" int spx_spgemm_exec(spx_plan* plan, spx_mat* C) {
       SPX_TRY(fill_u32((uint32_t*)C->cp, 1, 0, st));
   }
   SPX_HIP(hipGetLastError());
+  P->mark(kEvPtr, st);
+  return SPX_OK;
+}
+
+extern "C" int spx_plan_get_times(spx_plan* plan, spx_times* times) {
+  if (!plan || !times) return fail(SPX_EINVAL, "NULL argument");
+  std::memset(times, 0, sizeof(*times));
+  if (plan->kind != kPlanGemm) return fail(SPX_EINVAL, "not a SpGEMM plan");
+  auto* P = static_cast<GemmPlan*>(plan);
+  if (!P->profile) return fail(SPX_EINVAL, "plan was not created with ctx->profile set");
+  SPX_HIP(hipEventSynchronize(P->ev[kEvPlan1]));
+  SPX_HIP(hipEventElapsedTime(&times->symbolic_ms, P->ev[kEvPlan0], P->ev[kEvPlan1]));
+  if (hipEventQuery(P->ev[kEvPtr]) == hipErrorNotReady) SPX_HIP(hipEventSynchronize(P->ev[kEvPtr]));
+  float t = 0;
+  if (hipEventElapsedTime(&t, P->ev[kEvExec0], P->ev[kEvPtr]) != hipSuccess) {
+    (void)hipGetLastError();
+    return SPX_OK;  // exec has not run
+  }
+  SPX_HIP(hipEventElapsedTime(&times->numeric_parts_ms, P->ev[kEvExec0], P->ev[kEvParts]));
+  SPX_HIP(hipEventElapsedTime(&times->numeric_multi_ms, P->ev[kEvExec0], P->ev[kEvMulti]));
+  SPX_HIP(hipEventElapsedTime(&times->numeric_tiny_ms, P->ev[kEvParts], P->ev[kEvTiny]));
+  SPX_HIP(hipEventElapsedTime(&times->pointers_ms, P->ev[kEvTiny], P->ev[kEvPtr]));
   return SPX_OK;
 }
 
@@ -1098,7 +1422,14 @@ extern "C" int spx_plan_get_info(const spx_plan* plan, spx_plan_info* info) {
   if (!plan || !info) return fail(SPX_EINVAL, "NULL argument");
   std::memset(info, 0, sizeof(*info));
   if (plan->kind != kPlanGemm) return SPX_OK;
-  auto* P = static_cast<const GemmPlan*>(plan);
+  auto* P = const_cast<GemmPlan*>(static_cast<const GemmPlan*>(plan));
+  if (P->nnz_multi < 0) {
+    unsigned long long v = 0;
+    hipStream_t st = stream_of(&P->ctx);
+    SPX_HIP(hipMemcpyAsync(&v, &P->sum->nnz_multi, 8, hipMemcpyDeviceToHost, st));
+    SPX_HIP(hipStreamSynchronize(st));
+    P->nnz_multi = (int64_t)v;
+  }
   const int64_t* bo = P->binoff_h;
   info->mults = P->mults;
   info->nnz = P->nnz;
@@ -1108,6 +1439,9 @@ extern "C" int spx_plan_get_info(const spx_plan* plan, spx_plan_info* info) {
   info->cols_medium = bo[kBinTiny] - bo[kBinHash0];
   info->cols_heavy = bo[kBinHash0] - bo[0];
   info->heavy_parts = P->nparts;
+  info->nnz_tiny = P->nnz_tiny;
+  info->nnz_multi = P->nnz_multi;
+  info->multi_parts = P->psplit;
   return SPX_OK;
 }
 

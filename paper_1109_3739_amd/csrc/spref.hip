@@ -319,6 +319,11 @@ extern "C" int spx_spref_plan(const spx_ctx* ctx, const spx_mat* A, const int32_
   if (lenI < 0 || lenJ < 0 || lenI >= (1ll << 31) || lenJ >= (1ll << 31)) return fail(SPX_EINVAL, "bad index length");
   if ((lenI > 0 && !I) || (lenJ > 0 && !J)) return fail(SPX_EINVAL, "index vector is NULL");
   if (A->m > (1ll << 30)) return fail(SPX_EUNSUPPORTED, "SpRef needs m <= 2^30 (dense row map)");
+  if (ctx && ctx->validate) {
+    int32_t ok = 0;
+    SPX_TRY(spx_check(ctx, A, &ok));
+    if (!ok) return fail(SPX_EINVAL, "A is not canonical");
+  }
   auto* P = new SprefPlan(ctx);
   std::unique_ptr<SprefPlan> guard(P);
   hipStream_t st = stream_of(ctx);
