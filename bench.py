@@ -177,6 +177,39 @@ def extra_workloads(spx, W, torch):
     return out
 
 
+def serving(spx, torch, pool_per_scale=3, n_req=400):
+    """Served request stream: plain per-request launches vs continuous
+    batching, at offered loads relative to plain's saturation rate."""
+    from paper_1109_3739_amd import serve
+    pool = serve.make_pool(9 * pool_per_scale, seed=5)
+    store = serve.ResidentStore()
+    scales = {}
+    for key, (s, M) in enumerate(pool):
+        store.add(key, M)
+        scales[key] = s
+    # warm-up of both paths
+    for mode in ("plain", "batched"):
+        serve.Server(store, mode=mode).run(serve.make_requests(store, scales, 40, 1e6, seed=99))
+    sat = serve.Server(store, mode="plain")
+    reqs = sat.run(serve.make_requests(store, scales, n_req, 1e6, seed=7))
+    plain_max = serve.latency_stats(reqs)["throughput_rps"]
+    out = {"pool": f"{len(pool)} matrices, scales 10-18, degree 2-16, half R-MAT / half ER",
+           "plain_saturation_rps": plain_max, "points": []}
+    for frac in (0.5, 0.8, 1.2, 2.0, 4.0):
+        qps = frac * plain_max
+        row = {"qps": round(qps, 1)}
+        for mode in ("plain", "batched"):
+            srv = serve.Server(store, mode=mode)
+            reqs = srv.run(serve.make_requests(store, scales, n_req, qps, seed=int(frac * 100)))
+            st = serve.latency_stats(reqs)
+            st["rounds"] = srv.rounds
+            row[mode] = st
+        out["points"].append(row)
+        log(f"serving qps={qps:.0f}: plain p99 {row['plain'].get('p99_ms')} ms "
+            f"batched p99 {row['batched'].get('p99_ms')} ms")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -284,6 +317,8 @@ def main():
     if not args.no_extra:
         log("other workloads")
         result["extra"] = extra_workloads(spx, W, torch)
+        log("serving")
+        result["serving"] = serving(spx, torch)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle, sampled columns)")
         result["cpu_baseline"] = cpu_baseline(A, args.cpu_seconds)

@@ -170,6 +170,31 @@ int spx_plan_get_times(spx_plan* plan, spx_times* times);
 void spx_plan_destroy(spx_plan* plan);
 void spx_default_tuning(spx_tuning* tuning);
 
+/* ---- Batched SpGEMM: C_i = A_i*B_i for i < count ------------------------
+ * All products of a batch run through one symbolic pass and one persistent
+ * numeric launch: the batch is computed as the single product
+ * [A_1 ... A_n] * blockdiag(B_1, ..., B_n) = [C_1 ... C_n] (Algorithm 1
+ * applied to a block-diagonal right operand), so work items of every
+ * product share the device work lists.
+ * spx_batch_plan: A and B are arrays of `count` CSC descriptors (A_i m_i x k_i,
+ *   B_i k_i x n_i); all A_i (and all B_i) share one value type and the
+ *   semiring rules of spx_spgemm_plan apply.  Copies the operands' patterns
+ *   into the plan, runs the symbolic phase (one synchronisation) and returns
+ *   the total nnz of all C_i and the total length of their column pointers
+ *   (sum of n_i + 1).
+ * spx_batch_exec: refreshes the operand values from A_i.num / B_i.num
+ *   (patterns must be unchanged), runs the numeric phase and fills C[i]:
+ *   C[i].cp points into cp_pool (int64, cp_total entries), C[i].ir / num into
+ *   ir_pool / num_pool (nnz_total entries); the caller owns the pools.
+ * spx_batch_capture / spx_batch_replay: record spx_batch_exec with the given
+ *   pools into a HIP graph once, then launch it on the plan's stream (values
+ *   may change between replays).                                           */
+int spx_batch_plan(const spx_ctx* ctx, int32_t count, const spx_mat* A, const spx_mat* B, int32_t semiring,
+                   const spx_tuning* tuning, spx_plan** plan, int64_t* nnz_total, int64_t* cp_total);
+int spx_batch_exec(spx_plan* plan, int64_t* cp_pool, int32_t* ir_pool, void* num_pool, spx_mat* C);
+int spx_batch_capture(spx_plan* plan, int64_t* cp_pool, int32_t* ir_pool, void* num_pool, spx_mat* C);
+int spx_batch_replay(spx_plan* plan);
+
 /* ---- SpRef: B = A(I,J) (Section 4) ------------------------------------
  * B(p,q) = A(I(p), J(q)) for p < lenI, q < lenJ, respecting the order of I
  * and J; repeated indices replicate rows / columns.  A is CSC or DCSC,

@@ -33,6 +33,7 @@ EXPORTS = [
     "spx_spgemm_plan", "spx_spgemm_exec", "spx_spgemm", "spx_plan_get_info", "spx_plan_destroy", "spx_plan_get_times",
     "spx_default_tuning", "spx_spref_plan", "spx_spref_exec", "spx_spasgn_plan", "spx_spasgn_exec",
     "spx_count_nonempty", "spx_csc_to_dcsc", "spx_dcsc_to_csc", "spx_check", "spx_last_error", "spx_version",
+    "spx_batch_plan", "spx_batch_exec", "spx_batch_capture", "spx_batch_replay",
 ]
 
 
@@ -110,6 +111,10 @@ def load():
         "spx_csc_to_dcsc": ([C, M, M], ctypes.c_int),
         "spx_dcsc_to_csc": ([C, M, M], ctypes.c_int),
         "spx_check": ([C, M, ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
+        "spx_batch_plan": ([C, I32, M, M, I32, ctypes.POINTER(spx_tuning), PP, PI64, PI64], ctypes.c_int),
+        "spx_batch_exec": ([P, P, P, P, M], ctypes.c_int),
+        "spx_batch_capture": ([P, P, P, P, M], ctypes.c_int),
+        "spx_batch_replay": ([P], ctypes.c_int),
         "spx_last_error": ([], ctypes.c_char_p),
         "spx_version": ([], ctypes.c_char_p),
     }
@@ -329,6 +334,90 @@ class GemmPlan:
 def spgemm(A: SpMat, B: SpMat, semiring: str = "plus_times", out_fmt: int = CSC, tuning=None) -> SpMat:
     """C = A*B over ``semiring`` (plan + exec)."""
     p = GemmPlan(A, B, semiring, out_fmt, tuning)
+    try:
+        return p.execute()
+    finally:
+        p.close()
+
+
+# ---- batched SpGEMM ------------------------------------------------------
+class BatchPlan:
+    """C_i = A_i * B_i for all i in one symbolic pass and one persistent
+    numeric launch (see spx_batch_plan).  Outputs are views into pools."""
+
+    def __init__(self, As, Bs, semiring: str = "plus_times", tuning=None, stream=None):
+        lib = load()
+        if len(As) != len(Bs) or not As:
+            raise ValueError("need equally many A_i and B_i")
+        self._keep = (list(As), list(Bs))
+        self.count = len(As)
+        self.ctx = make_ctx(stream)
+        arr = spx_mat * self.count
+        self.A = arr(*[a.desc() for a in As])
+        self.B = arr(*[b.desc() for b in Bs])
+        self.handle = ctypes.c_void_p()
+        nnz, cpt = ctypes.c_int64(), ctypes.c_int64()
+        tp = ctypes.byref(tuning) if tuning is not None else None
+        _check(lib.spx_batch_plan(ctypes.byref(self.ctx), self.count, self.A, self.B, SEMIRINGS[semiring], tp,
+                                  ctypes.byref(self.handle), ctypes.byref(nnz), ctypes.byref(cpt)))
+        self.nnz_total, self.cp_total = nnz.value, cpt.value
+        self.val_t = GemmPlan._result_val(As[0], Bs[0], semiring)
+        self.shapes = [(a.m, b.n) for a, b in zip(As, Bs)]
+        self.pools = None
+        self.C = (spx_mat * self.count)()
+
+    def alloc_pools(self):
+        torch = _t()
+        self.pools = (_empty(self.cp_total, torch.int64), _empty(self.nnz_total, torch.int32),
+                      _val_tensor(self.val_t, self.nnz_total))
+        return self.pools
+
+    def _views(self):
+        cpp, irp, nump = self.pools
+        out = []
+        for i, (m, n) in enumerate(self.shapes):
+            d = self.C[i]
+            c0 = (d.cp - cpp.data_ptr()) // 8
+            e0 = (d.ir - irp.data_ptr()) // 4 if d.nnz else 0
+            out.append(SpMat(m, n, cpp[c0:c0 + n + 1], irp[e0:e0 + d.nnz],
+                             None if nump is None else nump[e0:e0 + d.nnz]))
+        return out
+
+    def _args(self):
+        cpp, irp, nump = self.pools
+        return _ptr(cpp), _ptr(irp), _ptr(nump)
+
+    def execute(self):
+        if self.pools is None:
+            self.alloc_pools()
+        _check(load().spx_batch_exec(self.handle, *self._args(), self.C))
+        return self._views()
+
+    def capture(self):
+        """Record execute() into a HIP graph (on the plan's stream)."""
+        if self.pools is None:
+            self.alloc_pools()
+        _check(load().spx_batch_capture(self.handle, *self._args(), self.C))
+        return self._views()
+
+    def replay(self):
+        _check(load().spx_batch_replay(self.handle))
+
+    def close(self):
+        if self.handle:
+            load().spx_plan_destroy(self.handle)
+            self.handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def batch_spgemm(As, Bs, semiring: str = "plus_times", tuning=None):
+    """[A_i * B_i for i] through one batch plan; returns views into pools."""
+    p = BatchPlan(As, Bs, semiring, tuning)
     try:
         return p.execute()
     finally:

@@ -1,0 +1,322 @@
+// Batched SpGEMM: C_i = A_i * B_i for many products in one pass.
+//
+// The batch is the single product  [A_1 A_2 ... A_n] * blockdiag(B_1, ..., B_n)
+// = [C_1 C_2 ... C_n]: column j of block i of the right operand only has
+// rows inside block i's range, so it only meets the columns of A_i.  The
+// concatenated operands are built once by the plan (patterns) and refreshed
+// by every exec (values); the symbolic phase, the binning and the persistent
+// numeric launches of the ordinary SpGEMM then run over the work items of
+// all products together.  C_i are views into caller-owned pools.
+#include <algorithm>
+#include <cstring>
+#include <vector>
+
+#include "common.h"
+#include "plan.h"
+
+namespace spx {
+
+struct BatchDesc {
+  const void* acp;
+  const int32_t* air;
+  const void* anum;
+  const void* bcp;
+  const int32_t* bir;
+  const void* bnum;
+  int32_t a_ptr_t, b_ptr_t;
+};
+
+struct BatchPlan : spx_plan {
+  explicit BatchPlan(const spx_ctx* c) : spx_plan(c, kPlanBatch) {}
+  ~BatchPlan() override {
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (gemm) spx_plan_destroy(gemm);
+  }
+  int32_t count = 0;
+  int32_t vt_c = 0;
+  int vb_a = 0, vb_b = 0, vb_c = 0;
+  std::vector<int64_t> m_h, n_h, acol_h, anz_h, bcol_h, bnz_h, cnz_h;  // bases, count+1 entries
+  BatchDesc* desc = nullptr;
+  int64_t *acol = nullptr, *anz = nullptr, *bcol = nullptr, *bnz = nullptr;
+  int64_t* acp = nullptr;
+  int32_t* air = nullptr;
+  void* anum = nullptr;
+  int64_t* bcp = nullptr;
+  int32_t* bir = nullptr;
+  void* bnum = nullptr;
+  int64_t* ccp = nullptr;  // column pointers of [C_1 ... C_n]
+  spx_plan* gemm = nullptr;
+  int64_t nnz_total = 0, cp_total = 0, mmax = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+};
+
+__device__ __forceinline__ int find_block(const int64_t* base, int count, int64_t x) {
+  int lo = 0, hi = count;  // last i with base[i] <= x
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (base[mid] <= x)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+// Column pointers of the concatenation: cp[c] = nnz base of block i + its own cp.
+__global__ void k_cat_cp(const BatchDesc* d, int count, const int64_t* colb, const int64_t* nzb, int64_t total,
+                         bool isB, int64_t* out) {
+  for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c <= total; c += (int64_t)gridDim.x * blockDim.x) {
+    if (c == total) {
+      out[c] = nzb[count];
+      continue;
+    }
+    const int i = find_block(colb, count, c);
+    const void* cp = isB ? d[i].bcp : d[i].acp;
+    const int32_t pt = isB ? d[i].b_ptr_t : d[i].a_ptr_t;
+    out[c] = nzb[i] + load_ptr(cp, pt, c - colb[i]);
+  }
+}
+
+// Row indices of the concatenation; B's rows move to block i's column range of A.
+__global__ void k_cat_ir(const BatchDesc* d, int count, const int64_t* nzb, const int64_t* acolb, int64_t total,
+                         bool isB, int32_t* out) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int i = find_block(nzb, count, e);
+    const int64_t k = e - nzb[i];
+    out[e] = isB ? (int32_t)(d[i].bir[k] + acolb[i]) : d[i].air[k];
+  }
+}
+
+__global__ void k_cat_num(const BatchDesc* d, int count, const int64_t* nzb, int64_t total, bool isB, int vb,
+                          void* out) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int i = find_block(nzb, count, e);
+    copy_value(isB ? d[i].bnum : d[i].anum, e - nzb[i], out, e, vb);
+  }
+}
+
+// Per-product column pointers (relative to the product's first entry).
+__global__ void k_batch_cp(const int64_t* ccp, const int64_t* bcol, int count, int64_t total, int64_t* cp_pool) {
+  // entry x of the pool: product i owns [bcol[i] + i, bcol[i+1] + i + 1)
+  for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < total; x += (int64_t)gridDim.x * blockDim.x) {
+    int lo = 0, hi = count;
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (bcol[mid] + mid <= x)
+        lo = mid;
+      else
+        hi = mid;
+    }
+    const int64_t j = x - (bcol[lo] + lo);
+    cp_pool[x] = ccp[bcol[lo] + j] - ccp[bcol[lo]];
+  }
+}
+
+__global__ void k_gather_i64(const int64_t* src, const int64_t* idx, int n, int64_t* out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = src[idx[i]];
+}
+
+static int run_exec(BatchPlan* P, int64_t* cp_pool, int32_t* ir_pool, void* num_pool, hipStream_t st) {
+  const int64_t anz = P->anz_h[P->count], bnz = P->bnz_h[P->count];
+  if (P->vb_a && anz > 0) {
+    k_cat_num<<<grid_for(anz, 256, 65536), 256, 0, st>>>(P->desc, P->count, P->anz, anz, false, P->vb_a, P->anum);
+    SPX_HIP(hipGetLastError());
+  }
+  if (P->vb_b && bnz > 0) {
+    k_cat_num<<<grid_for(bnz, 256, 65536), 256, 0, st>>>(P->desc, P->count, P->bnz, bnz, true, P->vb_b, P->bnum);
+    SPX_HIP(hipGetLastError());
+  }
+  spx_mat C{};
+  C.m = P->mmax;
+  C.n = P->bcol_h[P->count];
+  C.fmt = SPX_CSC;
+  C.ptr_t = SPX_PTR_I64;
+  C.val_t = P->vt_c;
+  C.cp = P->ccp;
+  C.ir = ir_pool;
+  C.num = num_pool;
+  SPX_TRY(spx_spgemm_exec(P->gemm, &C));
+  k_batch_cp<<<grid_for(P->cp_total, 256, 65536), 256, 0, st>>>(P->ccp, P->bcol, P->count, P->cp_total, cp_pool);
+  SPX_HIP(hipGetLastError());
+  return SPX_OK;
+}
+
+static void fill_outputs(BatchPlan* P, int64_t* cp_pool, int32_t* ir_pool, void* num_pool, spx_mat* C) {
+  for (int i = 0; i < P->count; ++i) {
+    spx_mat& c = C[i];
+    std::memset(&c, 0, sizeof(c));
+    c.m = P->m_h[i];
+    c.n = P->n_h[i];
+    c.nnz = P->cnz_h[i + 1] - P->cnz_h[i];
+    c.fmt = SPX_CSC;
+    c.ptr_t = SPX_PTR_I64;
+    c.val_t = P->vt_c;
+    c.cp = cp_pool + P->bcol_h[i] + i;
+    c.ir = ir_pool + P->cnz_h[i];
+    c.num = P->vb_c ? (void*)((char*)num_pool + P->cnz_h[i] * P->vb_c) : nullptr;
+  }
+}
+
+}  // namespace spx
+
+using namespace spx;
+
+extern "C" int spx_batch_plan(const spx_ctx* ctx, int32_t count, const spx_mat* A, const spx_mat* B, int32_t semiring,
+                              const spx_tuning* tuning, spx_plan** plan, int64_t* nnz_total, int64_t* cp_total) {
+  if (!plan) return fail(SPX_EINVAL, "plan is NULL");
+  *plan = nullptr;
+  if (count <= 0 || !A || !B) return fail(SPX_EINVAL, "empty batch");
+  for (int i = 0; i < count; ++i) {
+    SPX_TRY(check_mat(&A[i], "A[i]"));
+    SPX_TRY(check_mat(&B[i], "B[i]"));
+    if (A[i].fmt != SPX_CSC || B[i].fmt != SPX_CSC) return fail(SPX_EUNSUPPORTED, "batched operands must be CSC");
+    if (A[i].n != B[i].m) return fail(SPX_EINVAL, "inner dimensions differ in product " + std::to_string(i));
+    if (A[i].val_t != A[0].val_t || B[i].val_t != B[0].val_t)
+      return fail(SPX_EINVAL, "all A_i (and all B_i) must share one value type");
+  }
+  auto* P = new BatchPlan(ctx);
+  std::unique_ptr<BatchPlan> guard(P);
+  hipStream_t st = stream_of(ctx);
+  Scratch& scr = P->scratch;
+  P->count = count;
+  P->vb_a = value_size(A[0].val_t);
+  P->vb_b = value_size(B[0].val_t);
+  for (auto* v : {&P->m_h, &P->n_h}) v->resize(count);
+  for (auto* v : {&P->acol_h, &P->anz_h, &P->bcol_h, &P->bnz_h, &P->cnz_h}) v->assign(count + 1, 0);
+  std::vector<BatchDesc> hd(count);
+  for (int i = 0; i < count; ++i) {
+    P->m_h[i] = A[i].m;
+    P->n_h[i] = B[i].n;
+    P->mmax = std::max(P->mmax, A[i].m);
+    P->acol_h[i + 1] = P->acol_h[i] + A[i].n;
+    P->anz_h[i + 1] = P->anz_h[i] + A[i].nnz;
+    P->bcol_h[i + 1] = P->bcol_h[i] + B[i].n;
+    P->bnz_h[i + 1] = P->bnz_h[i] + B[i].nnz;
+    hd[i] = BatchDesc{A[i].cp, A[i].ir, A[i].num, B[i].cp, B[i].ir, B[i].num, A[i].ptr_t, B[i].ptr_t};
+  }
+  const int64_t ka = P->acol_h[count], anz = P->anz_h[count], nb = P->bcol_h[count], bnz = P->bnz_h[count];
+  if (ka >= (1ll << 31) || nb >= (1ll << 31)) return fail(SPX_EUNSUPPORTED, "batch too large (2^31 columns)");
+  SPX_TRY(scr.get_n(count, &P->desc));
+  for (auto* pp : {&P->acol, &P->anz, &P->bcol, &P->bnz}) SPX_TRY(scr.get_n(count + 1, pp));
+  SPX_HIP(hipMemcpyAsync(P->desc, hd.data(), sizeof(BatchDesc) * count, hipMemcpyHostToDevice, st));
+  SPX_HIP(hipMemcpyAsync(P->acol, P->acol_h.data(), 8 * (count + 1), hipMemcpyHostToDevice, st));
+  SPX_HIP(hipMemcpyAsync(P->anz, P->anz_h.data(), 8 * (count + 1), hipMemcpyHostToDevice, st));
+  SPX_HIP(hipMemcpyAsync(P->bcol, P->bcol_h.data(), 8 * (count + 1), hipMemcpyHostToDevice, st));
+  SPX_HIP(hipMemcpyAsync(P->bnz, P->bnz_h.data(), 8 * (count + 1), hipMemcpyHostToDevice, st));
+  SPX_TRY(scr.get_n(ka + 1, &P->acp));
+  SPX_TRY(scr.get_n(std::max<int64_t>(anz, 1), &P->air));
+  SPX_TRY(scr.get_n(nb + 1, &P->bcp));
+  SPX_TRY(scr.get_n(std::max<int64_t>(bnz, 1), &P->bir));
+  SPX_TRY(scr.get_n(nb + 1, &P->ccp));
+  if (P->vb_a) SPX_TRY(scr.get(std::max<int64_t>(anz, 1) * P->vb_a, &P->anum));
+  if (P->vb_b) SPX_TRY(scr.get(std::max<int64_t>(bnz, 1) * P->vb_b, &P->bnum));
+  k_cat_cp<<<grid_for(ka + 1, 256, 65536), 256, 0, st>>>(P->desc, count, P->acol, P->anz, ka, false, P->acp);
+  k_cat_cp<<<grid_for(nb + 1, 256, 65536), 256, 0, st>>>(P->desc, count, P->bcol, P->bnz, nb, true, P->bcp);
+  if (anz > 0) k_cat_ir<<<grid_for(anz, 256, 65536), 256, 0, st>>>(P->desc, count, P->anz, P->acol, anz, false, P->air);
+  if (bnz > 0) k_cat_ir<<<grid_for(bnz, 256, 65536), 256, 0, st>>>(P->desc, count, P->bnz, P->acol, bnz, true, P->bir);
+  if (P->vb_a && anz > 0)
+    k_cat_num<<<grid_for(anz, 256, 65536), 256, 0, st>>>(P->desc, count, P->anz, anz, false, P->vb_a, P->anum);
+  if (P->vb_b && bnz > 0)
+    k_cat_num<<<grid_for(bnz, 256, 65536), 256, 0, st>>>(P->desc, count, P->bnz, bnz, true, P->vb_b, P->bnum);
+  SPX_HIP(hipGetLastError());
+  spx_mat Ac{}, Bc{};
+  Ac.m = P->mmax;
+  Ac.n = ka;
+  Ac.nnz = anz;
+  Ac.fmt = SPX_CSC;
+  Ac.ptr_t = SPX_PTR_I64;
+  Ac.val_t = A[0].val_t;
+  Ac.cp = P->acp;
+  Ac.ir = P->air;
+  Ac.num = P->anum;
+  Bc.m = ka;
+  Bc.n = nb;
+  Bc.nnz = bnz;
+  Bc.fmt = SPX_CSC;
+  Bc.ptr_t = SPX_PTR_I64;
+  Bc.val_t = B[0].val_t;
+  Bc.cp = P->bcp;
+  Bc.ir = P->bir;
+  Bc.num = P->bnum;
+  int64_t nnz = 0, nzc = 0;
+  spx_ctx c2 = ctx ? *ctx : spx_ctx{};
+  c2.validate = 0;
+  SPX_TRY(spx_spgemm_plan(&c2, &Ac, &Bc, semiring, SPX_CSC, tuning, &P->gemm, &nnz, &nzc));
+  spx_plan_info info;
+  SPX_TRY(spx_plan_get_info(P->gemm, &info));
+  (void)info;
+  // output nnz base of every product: the offsets of its first column
+  int64_t* cb = nullptr;
+  SPX_TRY(scr.get_n(count + 1, &cb));
+  k_gather_i64<<<grid_for(count + 1, 256), 256, 0, st>>>(gemm_plan_offsets(P->gemm), P->bcol, count + 1, cb);
+  SPX_HIP(hipGetLastError());
+  SPX_HIP(hipMemcpyAsync(P->cnz_h.data(), cb, 8 * (count + 1), hipMemcpyDeviceToHost, st));
+  SPX_HIP(hipStreamSynchronize(st));
+  P->vt_c = semiring == SPX_OR_AND ? SPX_VAL_BOOL
+            : semiring == SPX_SELECT2ND ? B[0].val_t
+            : A[0].val_t;
+  P->vb_c = value_size(P->vt_c);
+  P->nnz_total = nnz;
+  P->cp_total = nb + count;
+  if (nnz_total) *nnz_total = nnz;
+  if (cp_total) *cp_total = P->cp_total;
+  *plan = guard.release();
+  return SPX_OK;
+}
+
+static int batch_args(spx_plan* plan, int64_t* cp_pool, int32_t* ir_pool, void* num_pool, spx_mat* C, BatchPlan** out) {
+  if (!plan || plan->kind != kPlanBatch) return fail(SPX_EINVAL, "not a batch plan");
+  auto* P = static_cast<BatchPlan*>(plan);
+  if (!cp_pool || !C || (P->nnz_total > 0 && (!ir_pool || (P->vb_c && !num_pool))))
+    return fail(SPX_EINVAL, "batch output pools missing");
+  *out = P;
+  return SPX_OK;
+}
+
+extern "C" int spx_batch_exec(spx_plan* plan, int64_t* cp_pool, int32_t* ir_pool, void* num_pool, spx_mat* C) {
+  BatchPlan* P = nullptr;
+  SPX_TRY(batch_args(plan, cp_pool, ir_pool, num_pool, C, &P));
+  SPX_TRY(run_exec(P, cp_pool, ir_pool, num_pool, stream_of(&P->ctx)));
+  fill_outputs(P, cp_pool, ir_pool, num_pool, C);
+  return SPX_OK;
+}
+
+extern "C" int spx_batch_capture(spx_plan* plan, int64_t* cp_pool, int32_t* ir_pool, void* num_pool, spx_mat* C) {
+  BatchPlan* P = nullptr;
+  SPX_TRY(batch_args(plan, cp_pool, ir_pool, num_pool, C, &P));
+  if (P->ctx.profile) return fail(SPX_EINVAL, "capture needs a plan without profiling events");
+  hipStream_t st = stream_of(&P->ctx);
+  if (!st) return fail(SPX_EINVAL, "capture needs a non-null stream");
+  if (P->gexec) {
+    (void)hipGraphExecDestroy(P->gexec);
+    P->gexec = nullptr;
+  }
+  if (P->graph) {
+    (void)hipGraphDestroy(P->graph);
+    P->graph = nullptr;
+  }
+  SPX_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+  const int rc = run_exec(P, cp_pool, ir_pool, num_pool, st);
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(st, &g);
+  if (rc != SPX_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc;
+  }
+  if (e != hipSuccess) return fail(SPX_EDEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+  P->graph = g;
+  SPX_HIP(hipGraphInstantiate(&P->gexec, P->graph, nullptr, nullptr, 0));
+  fill_outputs(P, cp_pool, ir_pool, num_pool, C);
+  return SPX_OK;
+}
+
+extern "C" int spx_batch_replay(spx_plan* plan) {
+  if (!plan || plan->kind != kPlanBatch) return fail(SPX_EINVAL, "not a batch plan");
+  auto* P = static_cast<BatchPlan*>(plan);
+  if (!P->gexec) return fail(SPX_EINVAL, "no captured graph");
+  SPX_HIP(hipGraphLaunch(P->gexec, stream_of(&P->ctx)));
+  return SPX_OK;
+}

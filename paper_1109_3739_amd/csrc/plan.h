@@ -18,7 +18,7 @@ struct spx_plan {
 
 namespace spx {
 
-enum { kPlanGemm = 1, kPlanSpref = 2, kPlanSpasgn = 3 };
+enum { kPlanGemm = 1, kPlanSpref = 2, kPlanSpasgn = 3, kPlanBatch = 4 };
 
 // Validates a descriptor (dimensions, codes, non-NULL buffers).
 int check_mat(const spx_mat* X, const char* name);
@@ -41,4 +41,9 @@ __device__ __forceinline__ void copy_value(const void* from, int64_t src, void* 
     reinterpret_cast<uint32_t*>(to)[dst] = reinterpret_cast<const uint32_t*>(from)[src];
 }
 
+// Device pointer to the output column offsets of a SpGEMM plan (one entry
+// per stored column of B plus the total), valid while the plan lives.
+const int64_t* gemm_plan_offsets(const spx_plan* plan);
+
 }  // namespace spx
+

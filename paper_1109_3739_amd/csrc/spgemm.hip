@@ -1447,6 +1447,11 @@ extern "C" int spx_plan_get_info(const spx_plan* plan, spx_plan_info* info) {
 
 extern "C" void spx_plan_destroy(spx_plan* plan) { delete plan; }
 
+const int64_t* spx::gemm_plan_offsets(const spx_plan* plan) {
+  if (!plan || plan->kind != kPlanGemm) return nullptr;
+  return static_cast<const GemmPlan*>(plan)->off;
+}
+
 static void* default_alloc(size_t bytes, void*) {
   void* p = nullptr;
   if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;

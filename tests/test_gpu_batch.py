@@ -1,0 +1,113 @@
+"""GPU parity of the batched SpGEMM (one plan, one persistent launch for many products)."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from helpers import assert_same_csc
+
+pytestmark = pytest.mark.gpu
+
+
+def host(M):
+    return M.to_host_csc()
+
+
+def test_batch_mixed_products_match_oracle_and_single(spx):
+    rng = np.random.default_rng(0)
+    As, Bs = [], []
+    for i in range(12):
+        kind = i % 3
+        if kind == 0:
+            A = W.erdos_renyi(int(rng.integers(50, 400)), int(rng.integers(50, 400)), 3, seed=i)
+            B = W.erdos_renyi(A.n, int(rng.integers(1, 300)), 2, seed=100 + i)
+        elif kind == 1:
+            A = W.rmat(int(rng.integers(8, 12)), 8, seed=i)
+            B = A
+        else:
+            A = W.rmat(10, 4, seed=i)
+            B = W.column_block(W.rmat(10, 6, seed=200 + i), 0, A.n, 0, 700)
+        As.append(A)
+        Bs.append(B)
+    dA = [spx.from_host(a) for a in As]
+    dB = [spx.from_host(b) for b in Bs]
+    Cs = spx.batch_spgemm(dA, dB)
+    for i, (A, B, C) in enumerate(zip(As, Bs, Cs)):
+        ref = oracle.spgemm_csc(A, B)
+        assert_same_csc(host(C), ref, what=f"product {i}")
+        single = host(spx.spgemm(dA[i], dB[i]))
+        assert np.array_equal(single.cp, host(C).cp) and np.array_equal(single.ir, host(C).ir)
+
+
+@pytest.mark.parametrize("semiring", ["min_plus", "or_and"])
+def test_batch_other_semirings(spx, semiring):
+    As = [W.rmat(9, 8, seed=s) for s in range(5)]
+    if semiring == "or_and":
+        for a in As:
+            a.num = None
+    d = [spx.from_host(a) for a in As]
+    Cs = spx.batch_spgemm(d, d, semiring)
+    for A, C in zip(As, Cs):
+        assert_same_csc(host(C), oracle.spgemm_csc(A, A, semiring), exact_values=True, what=semiring)
+
+
+def galerkin_batch(spx, sizes, dtype):
+    import torch
+    uniq = sorted(set(int(n) for n in sizes))
+    L = {n: spx.from_host(W.laplacian7(n, dtype)) for n in uniq}
+    P = {n: spx.from_host(W.aggregation(n, dtype)) for n in uniq}
+    PT = {n: spx.from_host(W.aggregation(n, dtype, transpose=True)) for n in uniq}
+    As = [L[int(n)] for n in sizes]
+    Ps = [P[int(n)] for n in sizes]
+    PTs = [PT[int(n)] for n in sizes]
+    AP = spx.BatchPlan(As, Ps)
+    APs = AP.execute()
+    G = spx.BatchPlan(PTs, APs)
+    Gs = G.execute()
+    torch.cuda.synchronize()
+    return AP, G, APs, Gs
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_batched_galerkin_closed_form(spx, dtype):
+    sizes = W.galerkin_sizes(24, seed=4, lo=4, hi=24)
+    AP, G, APs, Gs = galerkin_batch(spx, sizes, dtype)
+    for n, C in zip(sizes, Gs):
+        ref = W.laplacian7(int(n) // 2, dtype)
+        got = host(C)
+        assert np.array_equal(got.cp, ref.cp) and np.array_equal(got.ir, ref.ir)
+        assert np.array_equal(got.num, 4 * ref.num)  # small integers: exact in any order
+    AP.close()
+    G.close()
+
+
+def test_batch_graph_replay(spx):
+    """Capture the numeric phase once, replay it with new values, with eager
+    work and synchronisations between replays; check every replay."""
+    import torch
+    sizes = [4, 6, 8, 8, 10]
+    L = [spx.from_host(W.laplacian7(n)) for n in sizes]
+    P = [spx.from_host(W.aggregation(n)) for n in sizes]
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        plan = spx.BatchPlan(L, P, stream=stream)
+        eager = [host(c) for c in plan.execute()]
+        views = plan.capture()
+        for rep, scale in enumerate([1.0, 2.0, 0.5, 3.0]):
+            for a in L:
+                a.num.mul_(scale)  # eager work between replays
+            torch.cuda.synchronize()
+            plan.replay()
+            stream.synchronize()
+            total = np.prod([1.0, 2.0, 0.5, 3.0][:rep + 1])
+            for e, v in zip(eager, views):
+                got = host(v)
+                assert np.array_equal(got.cp, e.cp) and np.array_equal(got.ir, e.ir)
+                assert np.array_equal(got.num, e.num * total), f"replay {rep}"
+        plan.close()
+
+
+def test_batch_errors(spx):
+    A = spx.from_host(W.erdos_renyi(10, 8, 2, seed=1))
+    with pytest.raises(spx.SpxError):
+        spx.batch_spgemm([A], [A])  # 10x8 * 10x8

@@ -1,0 +1,65 @@
+"""Served requests: each result is the same alone and in the mix; admission
+never exceeds the budget; an oversize request is rejected, not stuck."""
+import numpy as np
+import pytest
+
+from helpers import assert_same_csc
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def store_and_pool(spx):
+    from paper_1109_3739_amd import serve
+    pool = serve.make_pool(12, seed=5, scales=range(8, 12), degrees=range(2, 9))
+    store = serve.ResidentStore()
+    scales = {}
+    for key, (s, M) in enumerate(pool):
+        store.add(key, M)
+        scales[key] = s
+    return store, scales
+
+
+def run(spx, store, scales, mode, n=60, qps=1e6, budget=64 << 30, seed=1):
+    from paper_1109_3739_amd import serve
+    reqs = serve.make_requests(store, scales, n, qps, seed=seed)
+    srv = serve.Server(store, mode=mode, budget_bytes=budget)
+    srv.run(reqs, keep_results=True)
+    return reqs, srv
+
+
+def test_results_same_alone_and_in_the_mix(spx, store_and_pool):
+    store, scales = store_and_pool
+    reqs, srv = run(spx, store, scales, "batched")
+    assert srv.rounds < len(reqs)  # requests were really batched
+    for r in reqs:
+        assert r.status == "ok"
+        if r.kind == "spgemm":
+            alone = spx.spgemm(store.f32[r.a], store.f32[r.b])
+        else:
+            alone = spx.spref(store.i64[r.a], r.I, r.J)
+        assert_same_csc(r.result.to_host_csc(), alone.to_host_csc(), exact_values=(r.kind == "spref"),
+                        what=f"request {r.rid} ({r.kind})")
+
+
+def test_plain_mode_matches(spx, store_and_pool):
+    store, scales = store_and_pool
+    a, _ = run(spx, store, scales, "plain", n=20, seed=2)
+    b, _ = run(spx, store, scales, "batched", n=20, seed=2)
+    for x, y in zip(a, b):
+        assert_same_csc(x.result.to_host_csc(), y.result.to_host_csc(), exact_values=(x.kind == "spref"))
+
+
+def test_admission_budget_and_rejection(spx, store_and_pool):
+    from paper_1109_3739_amd import serve
+    store, scales = store_and_pool
+    reqs = serve.make_requests(store, scales, 40, 1e6, seed=3)
+    ests = sorted(serve.estimate_bytes(store, r) for r in reqs)
+    budget = ests[len(ests) // 2]  # the larger half cannot be admitted at all
+    srv = serve.Server(store, mode="batched", budget_bytes=budget)
+    srv.run(reqs)
+    assert srv.max_used <= budget
+    assert all(r.status in ("ok", "rejected") for r in reqs)
+    assert any(r.status == "rejected" for r in reqs) and any(r.status == "ok" for r in reqs)
+    for r in reqs:
+        assert (r.status == "rejected") == (r.est_bytes > budget)
