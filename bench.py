@@ -21,7 +21,6 @@ a bounded sample of the same product.
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import statistics
@@ -43,27 +42,19 @@ def csc_bytes(nnz, ncols, vbytes=8, ptr_bytes=8):
     return nnz * (4 + vbytes) + (ncols + 1) * ptr_bytes
 
 
-def kernel_source_digest():
-    h = hashlib.sha256()
-    csrc = os.path.join(ROOT, "paper_1109_3739_amd", "csrc")
-    for f in sorted(os.listdir(csrc)):
-        if f.endswith((".hip", ".h")):
-            h.update(open(os.path.join(csrc, f), "rb").read())
-    return h.hexdigest()[:16]
-
-
-def traffic_from_profiles(kernel, launch_bytes_known):
+def traffic_from_profiles(kernel):
     """HBM bytes per launch from the committed PMC summary, if it was taken
     on the current kernel sources; otherwise None."""
+    from paper_1109_3739_amd.profiling import source_digest
     path = os.path.join(ROOT, "profiles", "traffic_spgemm_rmat20.json")
     if not os.path.exists(path):
         return None
     try:
         d = json.load(open(path))
-        if d.get("source_digest") != kernel_source_digest():
+        if d.get("source_digest") != source_digest():
             return None
         k = d["kernels"].get(kernel)
-        return None if k is None else float(k["hbm_bytes_per_launch"])
+        return None if k is None else round(float(k["hbm_bytes_per_launch"]))
     except Exception:
         return None
 
@@ -177,6 +168,64 @@ def extra_workloads(spx, W, torch):
     return out
 
 
+def galerkin(spx, W, torch, count=512, seed=4):
+    """Batched Galerkin products P^T (A P) for `count` 7-point Laplacians
+    (n^3 grids, n log-uniform in [16, 96]) with 2x2x2 aggregation: one batch
+    plan per product level (persistent launches over all instances), against
+    2*count separate plan+exec calls on the same GPU.  Parity: every
+    P^T A P must equal 4 x the coarse Laplacian exactly."""
+    import numpy as np
+    from paper_1109_3739_amd import autotune
+    sizes = W.galerkin_sizes(count, seed)
+    out = {"instances": count, "n_range": [int(sizes.min()), int(sizes.max())]}
+    for dt, name in ((np.float64, "f64"), (np.float32, "f32")):
+        uniq = sorted(set(int(n) for n in sizes))
+        L = {n: spx.from_host(W.laplacian7(n, dt)) for n in uniq}
+        P = {n: spx.from_host(W.aggregation(n, dt)) for n in uniq}
+        PT = {n: spx.from_host(W.aggregation(n, dt, transpose=True)) for n in uniq}
+        As = [L[int(n)] for n in sizes]
+        Ps = [P[int(n)] for n in sizes]
+        PTs = [PT[int(n)] for n in sizes]
+        mults = int(sum(L[int(n)].nnz + 4 * int(n) ** 3 for n in sizes))  # A*P: nnz(A); P^T*(AP): nnz(AP)
+        tun, tinfo = autotune.tune_batch(As, Ps)
+
+        def batched():
+            p1 = spx.BatchPlan(As, Ps, tuning=tun)
+            APs = p1.execute()
+            p2 = spx.BatchPlan(PTs, APs, tuning=tun)
+            Gs = p2.execute()
+            p1.close()
+            p2.close()
+            return Gs
+
+        def plain():
+            res = []
+            for a, p_, pt in zip(As, Ps, PTs):
+                ap = spx.spgemm(a, p_)
+                res.append(spx.spgemm(pt, ap))
+            return res
+
+        Gs = batched()
+        torch.cuda.synchronize()
+        ok = True
+        for n, C in zip(sizes[:64], Gs[:64]):
+            ref = W.laplacian7(int(n) // 2, dt)
+            got = C.to_host_csc()
+            ok &= bool(np.array_equal(got.cp, ref.cp) and np.array_equal(got.ir, ref.ir)
+                       and np.array_equal(got.num, 4 * ref.num))
+        del Gs
+        t_b = time_steps(batched, 3, torch.cuda.synchronize)
+        t_p = time_steps(plain, 1, torch.cuda.synchronize)
+        out[name] = {"batched_ms": round(1e3 * t_b, 3), "plain_ms": round(1e3 * t_p, 3),
+                     "speedup": round(t_p / t_b, 2), "mults": mults,
+                     "batched_gflops": round(2 * mults / t_b / 1e9, 2), "closed_form_ok_first64": ok,
+                     "tuning": tinfo["tuning"], "tuning_cached": tinfo["cached"]}
+        log(f"galerkin {name}: batched {1e3 * t_b:.1f} ms, plain {1e3 * t_p:.1f} ms")
+        del L, P, PT, As, Ps, PTs
+        torch.cuda.empty_cache()
+    return out
+
+
 def serving(spx, torch, pool_per_scale=3, n_req=400):
     """Served request stream: plain per-request launches vs continuous
     batching, at offered loads relative to plain's saturation rate."""
@@ -195,9 +244,9 @@ def serving(spx, torch, pool_per_scale=3, n_req=400):
     plain_max = serve.latency_stats(reqs)["throughput_rps"]
     out = {"pool": f"{len(pool)} matrices, scales 10-18, degree 2-16, half R-MAT / half ER",
            "plain_saturation_rps": plain_max, "points": []}
-    for frac in (0.5, 0.8, 1.2, 2.0, 4.0):
+    for frac in (0.5, 0.8, 1.2, 2.0, 3.0, 4.0):
         qps = frac * plain_max
-        row = {"qps": round(qps, 1)}
+        row = {"qps": round(qps, 1), "frac": frac}
         for mode in ("plain", "batched"):
             srv = serve.Server(store, mode=mode)
             reqs = srv.run(serve.make_requests(store, scales, n_req, qps, seed=int(frac * 100)))
@@ -207,6 +256,7 @@ def serving(spx, torch, pool_per_scale=3, n_req=400):
         out["points"].append(row)
         log(f"serving qps={qps:.0f}: plain p99 {row['plain'].get('p99_ms')} ms "
             f"batched p99 {row['batched'].get('p99_ms')} ms")
+    out["equal_p99"] = serve.equal_p99_summary(out["points"])
     return out
 
 
@@ -218,6 +268,8 @@ def main():
     ap.add_argument("--no-extra", action="store_true", help="skip the other workloads")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
+                    help="first run one plain device-to-device copy of BYTES (reference for HBM counters)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -234,6 +286,14 @@ def main():
     spx.load()
     torch.cuda.set_device(0)
     sync = torch.cuda.synchronize
+    if args.calibrate_copy:
+        x = torch.empty(args.calibrate_copy // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+        y = torch.empty_like(x)
+        sync()
+        y.copy_(x)
+        sync()
+        del x, y
+        torch.cuda.empty_cache()
     log("generating R-MAT scale 20")
     A = W.rmat(20, 8, seed=20)
     dA = spx.from_host(A)
@@ -277,6 +337,7 @@ def main():
     # columns (it accumulates and writes most of C).  Algorithmic bytes per
     # launch: A and B read once, its share of C written once.
     multi_bytes = 2 * csc_bytes(A.nnz, A.n) + info["nnz_multi"] * 12
+    info_wg = spx.default_tuning().part_threads
     multi_s = avg["numeric_multi_ms"] / 1e3
     achieved = multi_bytes / multi_s / 1e9
     roofline = {
@@ -286,7 +347,7 @@ def main():
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBS, 4),
-        "traffic": traffic_from_profiles("k_numeric_parts_multi", multi_bytes),
+        "traffic": traffic_from_profiles(f"void spx::k_numeric_parts_wg{info_wg}"),
         "algorithmic_bytes": int(multi_bytes),
         "avg_launch_ms": round(avg["numeric_multi_ms"], 4),
         "parts": int(info["multi_parts"]),
@@ -317,6 +378,8 @@ def main():
     if not args.no_extra:
         log("other workloads")
         result["extra"] = extra_workloads(spx, W, torch)
+        log("batched galerkin")
+        result["galerkin"] = galerkin(spx, W, torch)
         log("serving")
         result["serving"] = serving(spx, torch)
     if not args.no_cpu_baseline:

@@ -107,7 +107,11 @@ typedef struct spx_ctx {
  *   *_threads        workgroup sizes (multiples of 64, at most 1024) of the
  *                    hash count, bitmap count, multi-part and single-part
  *                    numeric kernels
- *   bitmap_chunk_log2  rows per work item of the bitmap count (log2)       */
+ *   bitmap_chunk_log2  rows per work item of the bitmap count (log2); 0: one
+ *                    chunk per row slice
+ *   xcd_slices       the row space is cut into this many slices (parts never
+ *                    straddle one); workgroup w serves slice w mod xcd_slices
+ *                    first, so each XCD's L2 holds one slice of A (1: off)   */
 typedef struct spx_tuning {
   int32_t tiny_max;
   int32_t hash_count_max;
@@ -118,7 +122,8 @@ typedef struct spx_tuning {
   int32_t part_threads;
   int32_t single_threads;
   int32_t bitmap_chunk_log2;
-  int32_t reserved[3];
+  int32_t xcd_slices;
+  int32_t reserved[2];
 } spx_tuning;
 
 /* Statistics of a SpGEMM plan, available once the plan call returned. */

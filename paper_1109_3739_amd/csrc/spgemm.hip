@@ -312,14 +312,16 @@ struct RangeLds {
   double bval[kQChunk];  // B's value, stored in the first bytes of each slot
 };
 
-template <int U, typename T, bool LOADA, bool LOADB, class F>
+// With REUSE the range list left in R by the previous call for the same
+// column and row range is used as is (the column must fit one chunk).
+template <int U, typename T, bool LOADA, bool LOADB, bool REUSE = false, class F>
 __device__ __forceinline__ void block_products(const ProdSrc& S, const T* an, const T* bn, int64_t b0, int64_t b1,
                                                int32_t r0, int32_t r1, bool full, RangeLds& R, int64_t* red, F&& f) {
   const int qchunk = (int)blockDim.x < kQChunk ? (int)blockDim.x : kQChunk;
   for (int64_t qc = b0; qc < b1; qc += qchunk) {
     const int nq = (int)(b1 - qc < qchunk ? b1 - qc : qchunk);
     int32_t mylen = 0;
-    if ((int)threadIdx.x < nq) {
+    if (!REUSE && (int)threadIdx.x < nq) {
       const int i = threadIdx.x;
       const int64_t q = qc + i;
       const int64_t a0 = S.a0[q];
@@ -340,12 +342,14 @@ __device__ __forceinline__ void block_products(const ProdSrc& S, const T* an, co
       if constexpr (LOADB) reinterpret_cast<T*>(&R.bval[i])[0] = bn[q];
       mylen = e1 - e0;
     }
-    int64_t total64;
-    const int64_t ex = block_excl_scan((int64_t)mylen, red, &total64);
-    if ((int)threadIdx.x < nq) R.pref[threadIdx.x] = (int32_t)ex;
-    if (threadIdx.x == 0) R.pref[nq] = (int32_t)total64;
-    __syncthreads();
-    const int32_t total = (int32_t)total64;
+    if (!REUSE) {
+      int64_t total64;
+      const int64_t ex = block_excl_scan((int64_t)mylen, red, &total64);
+      if ((int)threadIdx.x < nq) R.pref[threadIdx.x] = (int32_t)ex;
+      if (threadIdx.x == 0) R.pref[nq] = (int32_t)total64;
+      __syncthreads();
+    }
+    const int32_t total = R.pref[nq];
     for (int32_t base = 0; base < total; base += (int32_t)blockDim.x * U) {
       int32_t r[U];
       T a[U];
@@ -573,10 +577,15 @@ __global__ void k_count_bitmap(Operand B, ProdSrc S, const int64_t* mults, const
   __shared__ int64_t red[1024 / kWave + 1];
   __shared__ RangeLds s_rng;
   const int64_t beg = binoff[0], end = binoff[kBinHash0];
-  const int64_t items = (end - beg) * nchunks;
-  for (int64_t item = blockIdx.x; item < items; item += gridDim.x) {
-    const int64_t pos = beg + item / nchunks;
-    const int64_t c0 = (item % nchunks) * chunk_rows;
+  const int64_t ncols = end - beg;
+  // workgroup w takes chunk w mod nchunks of every (gridDim/nchunks)-th
+  // column (the grid is a multiple of nchunks): workgroups are placed on the
+  // XCDs round robin, so each XCD's L2 serves one slice of A's rows
+  const int64_t wstride = gridDim.x / nchunks;
+  const int64_t chunk = blockIdx.x % nchunks;
+  for (int64_t ci = blockIdx.x / nchunks; ci < ncols; ci += wstride) {
+    const int64_t pos = beg + ci;
+    const int64_t c0 = chunk * chunk_rows;
     const int64_t c1 = c0 + chunk_rows < m ? c0 + chunk_rows : m;
     const int32_t t = list[pos];
     const int64_t b0 = slot_begin(B, t), b1 = slot_begin(B, t + 1);
@@ -616,7 +625,7 @@ struct Part {
   int32_t c;     // outputs in the part
   int32_t r0, r1;  // row range [r0, r1)
   int32_t mode;  // 0 = bitmap, 1 = hash
-  int32_t pad;
+  int32_t slice; // row slice of the part (work queue), nslice = any
 };
 
 struct PartCfg {
@@ -625,6 +634,9 @@ struct PartCfg {
   int32_t sz;      // value bytes (0: pattern only)
   int32_t rbshift;
   int64_t nblk;
+  int64_t slice_blocks;  // row blocks per slice (parts never straddle slices); 0: one slice
+  int32_t nslice;
+  int32_t pad;
 };
 
 __device__ __forceinline__ int64_t bitmap_bytes(const PartCfg& p, int64_t span, int64_t c) {
@@ -665,6 +677,7 @@ __device__ int64_t cut_parts(const PartCfg& p, const uint32_t* blk, int32_t t, i
     int64_t c = blk[b];
     int64_t e = b + 1;
     while (e < p.nblk) {
+      if (p.slice_blocks && e % p.slice_blocks == 0) break;
       const int64_t c2 = c + blk[e];
       const int64_t r1 = (e + 1) * RB < p.m ? (e + 1) * RB : p.m;
       const int64_t span2 = r1 - b * RB;
@@ -687,7 +700,7 @@ __device__ int64_t cut_parts(const PartCfg& p, const uint32_t* blk, int32_t t, i
         P.r0 = (int32_t)r0;
         P.r1 = (int32_t)r1;
         P.mode = choose_mode(p, r1 - r0, c);
-        P.pad = 0;
+        P.slice = p.slice_blocks ? (int32_t)(b / p.slice_blocks) : 0;
         out[np] = P;
       }
       ++np;
@@ -726,7 +739,7 @@ __global__ void k_parts(PartCfg p, PartCfg ps, const int32_t* list, int64_t npos
         P.r0 = 0;
         P.r1 = (int32_t)q.m;
         P.mode = choose_mode(q, q.m, c);
-        P.pad = 0;
+        P.slice = q.nslice;  // full row range: any queue
         parts[poff[pos]] = P;
       }
     }
@@ -761,9 +774,9 @@ __device__ __forceinline__ void block_bitonic_sort(uint64_t* a, int n2) {
 template <int SR, typename T>
 __global__ void __launch_bounds__(1024) k_numeric_parts(Operand A, Operand B, ProdSrc S,
                                                         const int64_t* mults,
-                                                        const int64_t* cnt, const Part* parts, int64_t nparts,
-                                                        unsigned long long* work, int32_t* cir, T* cnum,
-                                                        unsigned* err) {
+                                                        const int64_t* cnt, const Part* parts, const int64_t* qoff,
+                                                        int nq, int nhome, unsigned long long* qctr, int32_t* cir,
+                                                        T* cnum, unsigned* err) {
   using SR_ = Semiring<SR, T>;
   constexpr bool kVal = SR != SPX_OR_AND;
   extern __shared__ __align__(16) unsigned char lds[];
@@ -773,12 +786,30 @@ __global__ void __launch_bounds__(1024) k_numeric_parts(Operand A, Operand B, Pr
   __shared__ RangeLds s_rng;
   const T* an = (const T*)A.num;
   const T* bn = (const T*)B.num;
+  // work queues: queue k holds parts [qoff[k], qoff[k+1]); a workgroup
+  // starts with its home queue (blockIdx.x % nhome: workgroups are placed on
+  // the XCDs round robin, so one queue's rows of A stay in one L2), then
+  // takes the shared queue nq-1, then helps the others.
+  const int home = nhome > 1 ? (int)(blockIdx.x % nhome) : 0;
+  int qi = 0;
   for (;;) {
-    if (threadIdx.x == 0) s_pi = (int64_t)atomicAdd(work, 1ull);
+    if (threadIdx.x == 0) {
+      int64_t got = -1;
+      while (qi < nq) {
+        const int q = qi == 0 ? home : (qi == 1 ? nq - 1 : (home + qi - 1) % (nq - 1));
+        const int64_t idx = (int64_t)atomicAdd(&qctr[q], 1ull);
+        if (qoff[q] + idx < qoff[q + 1]) {
+          got = qoff[q] + idx;
+          break;
+        }
+        ++qi;
+      }
+      s_pi = got;
+    }
     __syncthreads();
     const int64_t pi = s_pi;
     __syncthreads();
-    if (pi >= nparts) break;
+    if (pi < 0) break;
     const Part P = parts[pi];
     const int64_t b0 = slot_begin(B, P.t), b1 = slot_begin(B, P.t + 1);
     const int64_t span = (int64_t)P.r1 - P.r0;
@@ -794,8 +825,8 @@ __global__ void __launch_bounds__(1024) k_numeric_parts(Operand A, Operand B, Pr
       if constexpr (kVal)
         for (int i = threadIdx.x; i < c; i += blockDim.x) vals[i] = SR_::ident();
       __syncthreads();
-      block_products<8, int, false, false>(S, nullptr, nullptr, b0, b1, P.r0, P.r1, full, s_rng, red,
-                                           [&](int32_t r, int, int) {
+      block_products<16, T, false, SR_::kUsesB>(S, an, bn, b0, b1, P.r0, P.r1, full, s_rng, red,
+                                                [&](int32_t r, T, T) {
         const uint32_t d = (uint32_t)(r - P.r0);
         atomicOr((unsigned long long*)&bm[d >> 6], 1ull << (d & 63));
       });
@@ -815,13 +846,16 @@ __global__ void __launch_bounds__(1024) k_numeric_parts(Operand A, Operand B, Pr
       if (threadIdx.x == 0 && tot != c) atomicOr(err, 8u);
       __syncthreads();
       if constexpr (kVal) {
-        block_products<4, T, SR_::kUsesA, SR_::kUsesB>(S, an, bn, b0, b1, P.r0, P.r1, full, s_rng, red,
-                                                       [&](int32_t r, T a, T bv) {
+        auto acc = [&](int32_t r, T a, T bv) {
           const uint32_t d = (uint32_t)(r - P.r0);
           const uint64_t word = bm[d >> 6];
           const int rank = (int)pre[d >> 6] + __popcll(word & ((1ull << (d & 63)) - 1ull));
           if (rank < c) SR_::lds_acc(&vals[rank], SR_::mul(a, bv));
-        });
+        };
+        if (b1 - b0 <= (int64_t)(blockDim.x < kQChunk ? blockDim.x : kQChunk))
+          block_products<8, T, SR_::kUsesA, SR_::kUsesB, true>(S, an, bn, b0, b1, P.r0, P.r1, full, s_rng, red, acc);
+        else
+          block_products<8, T, SR_::kUsesA, SR_::kUsesB>(S, an, bn, b0, b1, P.r0, P.r1, full, s_rng, red, acc);
         __syncthreads();
         for (int i = threadIdx.x; i < c; i += blockDim.x) cnum[P.off + i] = vals[i];
         __syncthreads();
@@ -955,6 +989,55 @@ __global__ void k_parts_sum(const Part* parts, int64_t n, unsigned long long* ou
   if (lane_id() == 0 && s) atomicAdd(out, (unsigned long long)s);
 }
 
+// Counting sort of the multi-part list by row slice (work queue).
+__global__ void k_part_hist(const Part* parts, int64_t n, unsigned long long* hist) {
+  __shared__ unsigned h[66];
+  for (int i = threadIdx.x; i < 66; i += blockDim.x) h[i] = 0;
+  __syncthreads();
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    atomicAdd(&h[parts[i].slice], 1u);
+  __syncthreads();
+  for (int i = threadIdx.x; i < 66; i += blockDim.x)
+    if (h[i]) atomicAdd(&hist[i], (unsigned long long)h[i]);
+}
+
+// Exclusive offsets of nb bins, written to cursor and to qoff (+ qoff[nb]).
+__global__ void k_hist_offsets(unsigned long long* hist, int64_t nb, int64_t base, int64_t* qoff) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    unsigned long long run = 0;
+    for (int64_t b = 0; b < nb; ++b) {
+      const unsigned long long c = hist[b];
+      hist[b] = run;
+      qoff[b] = base + (int64_t)run;
+      run += c;
+    }
+    qoff[nb] = base + (int64_t)run;
+  }
+}
+
+// Per block: rank inside the block by LDS atomics, one global atomic per bin.
+__global__ void k_part_scatter(const Part* in, int64_t n, unsigned long long* cursor, Part* out) {
+  __shared__ unsigned h[66];
+  __shared__ unsigned long long base[66];
+  for (int64_t t0 = (int64_t)blockIdx.x * blockDim.x; t0 < n; t0 += (int64_t)gridDim.x * blockDim.x) {
+    for (int i = threadIdx.x; i < 66; i += blockDim.x) h[i] = 0;
+    __syncthreads();
+    const int64_t i = t0 + threadIdx.x;
+    Part p{};
+    unsigned rk = 0;
+    if (i < n) {
+      p = in[i];
+      rk = atomicAdd(&h[p.slice], 1u);
+    }
+    __syncthreads();
+    for (int b = threadIdx.x; b < 66; b += blockDim.x)
+      if (h[b]) base[b] = atomicAdd(&cursor[b], (unsigned long long)h[b]);
+    __syncthreads();
+    if (i < n) out[base[p.slice] + rk] = p;
+    __syncthreads();
+  }
+}
+
 struct NonzeroFlag {
   const int64_t* cnt;
   __device__ int64_t operator()(int64_t i) const { return cnt[i] > 0 ? 1 : 0; }
@@ -1014,6 +1097,10 @@ struct GemmPlan : spx_plan {
   int32_t* list = nullptr;
   int64_t* binoff = nullptr;
   Part* parts = nullptr;
+  int64_t* qoff_multi = nullptr;
+  int64_t* qoff_single = nullptr;
+  unsigned long long* qctr = nullptr;
+  int32_t nq_multi = 1, nslice = 1, nslice_req = 1;
   Summary* sum = nullptr;
   int64_t L = 0, L_single = 0;
 };
@@ -1064,7 +1151,8 @@ extern "C" void spx_default_tuning(spx_tuning* t) {
   t->bitmap_threads = 1024;
   t->part_threads = 512;
   t->single_threads = 256;
-  t->bitmap_chunk_log2 = 20;
+  t->bitmap_chunk_log2 = 0;
+  t->xcd_slices = 1;
 }
 
 template <int SR, typename T>
@@ -1074,18 +1162,20 @@ static int launch_numeric(GemmPlan* P, spx_mat* C, hipStream_t st) {
   unsigned* err = &P->sum->err;
   const int cus = device_cu_count();
   // parts of multi-part columns [0, psplit), single-part columns [psplit, nparts)
-  const int64_t ranges[2][2] = {{0, P->psplit}, {P->psplit, P->nparts}};
+  if (P->nparts > 0) SPX_TRY(fill_i64((int64_t*)P->qctr, P->nq_multi + 2, 0, st));
   for (int r = 0; r < 2; ++r) {
-    const int64_t n0 = ranges[r][0], n1 = ranges[r][1];
+    const int64_t n0 = r == 0 ? 0 : P->psplit, n1 = r == 0 ? P->psplit : P->nparts;
     if (n1 <= n0) continue;
-    unsigned long long* work = r == 0 ? &P->sum->work : &P->sum->work2;
-    SPX_TRY(fill_i64((int64_t*)work, 1, n0, st));
     const int blk = r == 0 ? P->tune.part_threads : P->tune.single_threads;
     const int64_t L = r == 0 ? P->L : P->L_single;
     const int per_cu = (int)std::max<int64_t>(1, std::min<int64_t>((160 * 1024) / (L + 8192), 2048 / blk));
-    const unsigned grid = (unsigned)std::min<int64_t>(n1 - n0, (int64_t)cus * per_cu);
-    hipLaunchKernelGGL((k_numeric_parts<SR, T>), dim3(grid), dim3(blk), (size_t)L, st, P->A, P->B, P->src,
-                       P->mults_d, P->cnt, P->parts, n1, work, cir, cnum, err);
+    int64_t grid = std::min<int64_t>(n1 - n0, (int64_t)cus * per_cu);
+    if (r == 0 && P->nslice > 1) grid = std::max<int64_t>(P->nslice, grid / P->nslice * P->nslice);
+    const int64_t* qoff = r == 0 ? P->qoff_multi : P->qoff_single;
+    const int nq = r == 0 ? P->nq_multi : 1;
+    unsigned long long* qctr = r == 0 ? P->qctr : P->qctr + P->nq_multi;
+    hipLaunchKernelGGL((k_numeric_parts<SR, T>), dim3((unsigned)grid), dim3(blk), (size_t)L, st, P->A, P->B, P->src,
+                       P->mults_d, P->cnt, P->parts, qoff, nq, r == 0 ? P->nslice : 1, qctr, cir, cnum, err);
     SPX_HIP(hipGetLastError());
     if (r == 0) P->mark(kEvMulti, st);
   }
@@ -1196,6 +1286,7 @@ extern "C" int spx_spgemm_plan(const spx_ctx* ctx, const spx_mat* A, const spx_m
     if (P->L_single > 160 * 1024 - 8192) return fail(SPX_EINVAL, "single_part_max too large for LDS");
   }
   const int64_t nblk = std::max<int64_t>(1, ceil_div(m, 1ll << rb));
+  P->nslice_req = std::max(1, std::min(tune.xcd_slices, 64));
   P->mark(kEvPlan0, st);
 
   SPX_TRY(scr.get_n(1, &P->sum));
@@ -1294,14 +1385,21 @@ extern "C" int spx_spgemm_plan(const spx_ctx* ctx, const spx_mat* A, const spx_m
   }
   const int64_t nbitmap = bo[kBinHash0] - bo[0];
   if (nbitmap > 0) {
-    // bitmap chunks: a power of two of rows, a multiple of the row block
-    int clog = std::max<int>(rb, std::min<int>(tune.bitmap_chunk_log2, 20));
+    // bitmap chunks: a power of two of rows, a multiple of the row block;
+    // 0 = one chunk per row slice
+    int want = tune.bitmap_chunk_log2;
+    if (want <= 0) {
+      want = 0;
+      while ((1ll << want) < ceil_div(m, std::max(1, P->nslice_req))) ++want;
+    }
+    int clog = std::max<int>(rb, std::min<int>(want, 20));
     while (clog > rb && (1ll << (clog - 1)) >= m) --clog;
     const int64_t nchunks = ceil_div(m, 1ll << clog);
     const size_t lds = ((size_t)1 << clog) / 8 + (((size_t)1 << clog) >> rb) * 4 + 16;
     const int per_cu = std::max<int>(1, std::min<int>((int)((160 * 1024) / (lds + 8192)), 2048 / tune.bitmap_threads));
-    k_count_bitmap<<<(unsigned)std::min<int64_t>(nbitmap * nchunks, (int64_t)cus * per_cu), tune.bitmap_threads, lds,
-                     st>>>(P->B, P->src, P->mults_d, P->list, P->binoff, m, clog, rb, nblk, blkcnt,
+    int64_t bgrid = std::min<int64_t>(nbitmap * nchunks, (int64_t)cus * per_cu);
+    bgrid = std::max<int64_t>(nchunks, bgrid / nchunks * nchunks);
+    k_count_bitmap<<<(unsigned)bgrid, tune.bitmap_threads, lds, st>>>(P->B, P->src, P->mults_d, P->list, P->binoff, m, clog, rb, nblk, blkcnt,
                            (unsigned long long*)P->cnt);
     SPX_HIP(hipGetLastError());
   }
@@ -1311,8 +1409,13 @@ extern "C" int spx_spgemm_plan(const spx_ctx* ctx, const spx_mat* A, const spx_m
   // parts of the non-tiny columns: list positions [0, bo[kBinTiny])
   const int64_t npos = bo[kBinTiny];
   int64_t *np = nullptr, *poff = nullptr;
-  PartCfg pc{L, m, sz, rb, nblk};
-  PartCfg pcs{P->L_single, m, sz, rb, nblk};
+  int nslice = std::max(1, std::min(tune.xcd_slices, 64));
+  int64_t slice_blocks = ceil_div(nblk, nslice);
+  nslice = (int)ceil_div(nblk, slice_blocks);
+  if (nslice <= 1) slice_blocks = 0;
+  P->nslice = nslice;
+  PartCfg pc{L, m, sz, rb, nblk, slice_blocks, nslice, 0};
+  PartCfg pcs{P->L_single, m, sz, rb, nblk, 0, nslice, 0};
   if (npos > 0) {
     SPX_TRY(scr.get_n(npos, &np));
     SPX_TRY(scr.get_n(npos + 1, &poff));
@@ -1345,6 +1448,35 @@ extern "C" int spx_spgemm_plan(const spx_ctx* ctx, const spx_mat* A, const spx_m
     k_parts<<<grid_for(npos, 256, (int64_t)cus * 16), 256, 0, st>>>(pc, pcs, P->list, npos, multi_begin, multi_end, P->cnt,
                                                                     P->off, blkcnt, nullptr, poff, P->parts, err);
     SPX_HIP(hipGetLastError());
+    // work queues of the multi-part launch: one per row slice plus a
+    // shared one (parts spanning all rows); the single-part launch has one
+    P->nq_multi = pc.nslice + 1;
+    SPX_TRY(scr.get_n(P->nq_multi + 1, &P->qoff_multi));
+    SPX_TRY(scr.get_n(2, &P->qoff_single));
+    SPX_TRY(scr.get_n(P->nq_multi + 2, &P->qctr));
+    {
+      const int64_t h[2] = {P->psplit, P->nparts};
+      SPX_HIP(hipMemcpyAsync(P->qoff_single, h, sizeof(h), hipMemcpyHostToDevice, st));
+    }
+    if (P->psplit > 0 && pc.nslice <= 1) {
+      // one queue with every multi part, the shared queue empty
+      const int64_t h[3] = {0, P->psplit, P->psplit};
+      SPX_HIP(hipMemcpyAsync(P->qoff_multi, h, sizeof(h), hipMemcpyHostToDevice, st));
+    } else if (P->psplit > 0) {
+      unsigned long long* hist = nullptr;
+      Part* sorted = nullptr;
+      SPX_TRY(scr.get_n(P->nq_multi + 1, &hist));
+      SPX_TRY(scr.get_n(P->nparts, &sorted));
+      SPX_TRY(fill_i64((int64_t*)hist, P->nq_multi + 1, 0, st));
+      k_part_hist<<<grid_for(P->psplit, 256, 4096), 256, 0, st>>>(P->parts, P->psplit, hist);
+      k_hist_offsets<<<1, 64, 0, st>>>(hist, P->nq_multi, 0, P->qoff_multi);
+      k_part_scatter<<<grid_for(P->psplit, 256, 4096), 256, 0, st>>>(P->parts, P->psplit, hist, sorted);
+      SPX_HIP(hipGetLastError());
+      if (P->nparts > P->psplit)
+        SPX_HIP(hipMemcpyAsync(sorted + P->psplit, P->parts + P->psplit, sizeof(Part) * (P->nparts - P->psplit),
+                               hipMemcpyDeviceToDevice, st));
+      P->parts = sorted;
+    }
     if (P->psplit > 0) {
       k_parts_sum<<<grid_for(P->psplit, 256, 1024), 256, 0, st>>>(P->parts, P->psplit, &P->sum->nnz_multi);
       SPX_HIP(hipGetLastError());

@@ -134,7 +134,10 @@ class Server:
         ref = [r for r in reqs if r.kind == "spref"]
         # the batched products go first: their numeric launch is enqueued
         # before the extractions are planned, so the two overlap on the device
-        if gem:
+        if len(gem) == 1:  # a lone product skips the batch set-up
+            with torch.cuda.stream(self.gemm_stream):
+                gem[0].result = spgemm(s.f32[gem[0].a], s.f32[gem[0].b])
+        elif gem:
             with torch.cuda.stream(self.gemm_stream):
                 plan = BatchPlan([s.f32[r.a] for r in gem], [s.f32[r.b] for r in gem], tuning=self.tuning,
                                  stream=self.gemm_stream)
@@ -208,6 +211,28 @@ class Server:
                 if not keep_results:
                     r.result = None
         return requests
+
+
+def equal_p99_summary(points: List[dict]) -> dict:
+    """Throughput of each mode at equal tail latency.  The p99 target is the
+    plain mode's p99 at the lowest offered load above 0.6 x its saturation;
+    for each mode the best throughput among the load points whose p99 stays
+    within the target is reported."""
+    pts = sorted(points, key=lambda p: p["qps"])
+    target = None
+    for p in pts:
+        if p.get("frac", 1.0) >= 0.6:
+            target = p["plain"]["p99_ms"]
+            break
+    if target is None:
+        return {}
+    best = {}
+    for mode in ("plain", "batched"):
+        ok = [p[mode]["throughput_rps"] for p in pts if p[mode].get("p99_ms", 1e30) <= target]
+        best[mode] = max(ok) if ok else None
+    ratio = (best["batched"] / best["plain"]) if best.get("plain") and best.get("batched") else None
+    return {"p99_target_ms": target, "plain_rps": best["plain"], "batched_rps": best["batched"],
+            "batched_over_plain": round(ratio, 3) if ratio else None}
 
 
 def latency_stats(reqs: List[Request], t_first: float = 0.0) -> dict:

@@ -71,6 +71,8 @@ def test_rmat_semirings(spx, semiring, values, exact):
          single_threads=64, bitmap_threads=256),
     dict(single_part_max=4096, single_threads=1024),
     dict(tiny_max=0, hash_count_max=0, bitmap_chunk_log2=10, bitmap_threads=256),  # chunked bitmap count
+    dict(part_lds_bytes=24 * 1024, xcd_slices=1),        # one shared work queue
+    dict(part_lds_bytes=24 * 1024, xcd_slices=3),        # slices not a power of two
 ])
 @pytest.mark.parametrize("dtype", [np.float64, np.float32])
 def test_forced_paths(spx, tune, dtype):

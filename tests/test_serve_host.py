@@ -15,3 +15,14 @@ def test_latency_stats():
     lat = np.array([r.latency for r in reqs if r.status == "ok"])
     assert abs(st["p50_ms"] - 1e3 * np.percentile(lat, 50)) < 1e-6
     assert abs(st["p99_ms"] - 1e3 * np.percentile(lat, 99)) < 1e-6
+
+
+def test_equal_p99_summary():
+    from paper_1109_3739_amd.serve import equal_p99_summary
+    pts = [
+        {"qps": 100, "frac": 0.5, "plain": {"p99_ms": 2.0, "throughput_rps": 100}, "batched": {"p99_ms": 3.0, "throughput_rps": 100}},
+        {"qps": 160, "frac": 0.8, "plain": {"p99_ms": 5.0, "throughput_rps": 160}, "batched": {"p99_ms": 4.0, "throughput_rps": 160}},
+        {"qps": 400, "frac": 2.0, "plain": {"p99_ms": 90.0, "throughput_rps": 200}, "batched": {"p99_ms": 4.5, "throughput_rps": 390}},
+    ]
+    s = equal_p99_summary(pts)
+    assert s["p99_target_ms"] == 5.0 and s["plain_rps"] == 160 and s["batched_rps"] == 390
