@@ -111,7 +111,12 @@ typedef struct spx_ctx {
  *                    chunk per row slice
  *   xcd_slices       the row space is cut into this many slices (parts never
  *                    straddle one); workgroup w serves slice w mod xcd_slices
- *                    first, so each XCD's L2 holds one slice of A (1: off)   */
+ *                    first, so each XCD's L2 holds one slice of A (1: off)
+ *   bitmap_store_mb  HBM (MiB) the plan may hold to keep the row bitmaps of
+ *                    the bitmap-counted columns from the count to the numeric
+ *                    phase, which then reads them instead of gathering those
+ *                    rows again; 0: off.  Above the cap, or if the allocation
+ *                    fails, the numeric phase recomputes them.               */
 typedef struct spx_tuning {
   int32_t tiny_max;
   int32_t hash_count_max;
@@ -123,7 +128,8 @@ typedef struct spx_tuning {
   int32_t single_threads;
   int32_t bitmap_chunk_log2;
   int32_t xcd_slices;
-  int32_t reserved[2];
+  int32_t bitmap_store_mb;
+  int32_t reserved;
 } spx_tuning;
 
 /* Statistics of a SpGEMM plan, available once the plan call returned. */

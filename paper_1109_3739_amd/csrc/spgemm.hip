@@ -567,7 +567,7 @@ __global__ void k_count_hash(Operand B, ProdSrc S, const int64_t* mults,
 // column count and the per-row-block counts used to cut parts.
 __global__ void k_count_bitmap(Operand B, ProdSrc S, const int64_t* mults, const int32_t* list, const int64_t* binoff,
                                int64_t m, int chunk_log2, int rbshift, int64_t nblk, uint32_t* blkcnt,
-                               unsigned long long* cnt) {
+                               unsigned long long* cnt, uint32_t* gbm, int64_t gwords) {
   extern __shared__ __align__(16) unsigned char lds[];
   uint32_t* bm = (uint32_t*)lds;
   const int64_t chunk_rows = 1ll << chunk_log2;  // a multiple of the row block
@@ -614,6 +614,11 @@ __global__ void k_count_bitmap(Operand B, ProdSrc S, const int64_t* mults, const
     for (int i = threadIdx.x; i < blk_per_chunk; i += blockDim.x)
       if (bfirst + i < nblk) dst[bfirst + i] = lblk[i];
     if (threadIdx.x == 0 && ctot) atomicAdd(&cnt[t], (unsigned long long)ctot);
+    if (gbm) {  // keep the column's row set for the numeric phase
+      uint32_t* g = gbm + ci * gwords + (c0 >> 5);
+      const int wr = (words + 1) & ~1;  // whole 64-bit words
+      for (int i = threadIdx.x; i < wr; i += blockDim.x) g[i] = i < words ? bm[i] : 0u;
+    }
     __syncthreads();
   }
 }
@@ -626,6 +631,8 @@ struct Part {
   int32_t r0, r1;  // row range [r0, r1)
   int32_t mode;  // 0 = bitmap, 1 = hash
   int32_t slice; // row slice of the part (work queue), nslice = any
+  int32_t bmi;   // index of the column's stored row bitmap, -1 if none
+  int32_t pad;
 };
 
 struct PartCfg {
@@ -669,7 +676,7 @@ __device__ __forceinline__ int choose_mode(const PartCfg& p, int64_t span, int64
 // it still fits the LDS budget in one of the two modes.  With emit == false
 // only counts parts.
 __device__ int64_t cut_parts(const PartCfg& p, const uint32_t* blk, int32_t t, int64_t base_off, bool emit, Part* out,
-                             unsigned* err) {
+                             int32_t bmi, unsigned* err) {
   const int64_t RB = 1ll << p.rbshift;
   int64_t np = 0, run = 0;
   int64_t b = 0;
@@ -701,6 +708,8 @@ __device__ int64_t cut_parts(const PartCfg& p, const uint32_t* blk, int32_t t, i
         P.r1 = (int32_t)r1;
         P.mode = choose_mode(p, r1 - r0, c);
         P.slice = p.slice_blocks ? (int32_t)(b / p.slice_blocks) : 0;
+        P.bmi = bmi;
+        P.pad = 0;
         out[np] = P;
       }
       ++np;
@@ -714,8 +723,8 @@ __device__ int64_t cut_parts(const PartCfg& p, const uint32_t* blk, int32_t t, i
 // Number of parts of every non-tiny, nonempty column (list positions
 // [0, npos)), or the parts themselves (emit).
 __global__ void k_parts(PartCfg p, PartCfg ps, const int32_t* list, int64_t npos, int64_t multi_begin, int64_t multi_end,
-                        const int64_t* cnt, const int64_t* off, const uint32_t* blkcnt, int64_t* nparts,
-                        const int64_t* poff, Part* parts, unsigned* err) {
+                        int64_t nbm, const int64_t* cnt, const int64_t* off, const uint32_t* blkcnt,
+                        int64_t* nparts, const int64_t* poff, Part* parts, unsigned* err) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   const bool emit = parts != nullptr;
   for (int64_t pos = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; pos < npos; pos += stride) {
@@ -726,7 +735,7 @@ __global__ void k_parts(PartCfg p, PartCfg ps, const int32_t* list, int64_t npos
       np = 0;
     } else if (pos >= multi_begin && pos < multi_end && !(bitmap_ok(p, p.m, c) || hash_ok(p, c))) {
       np = cut_parts(p, blkcnt + (pos - multi_begin) * p.nblk, t, off[t], emit, emit ? parts + poff[pos] : nullptr,
-                     err);
+                     pos - multi_begin < nbm ? (int32_t)(pos - multi_begin) : -1, err);
     } else {
       np = 1;
       const PartCfg& q = pos < multi_end ? p : ps;
@@ -740,6 +749,8 @@ __global__ void k_parts(PartCfg p, PartCfg ps, const int32_t* list, int64_t npos
         P.r1 = (int32_t)q.m;
         P.mode = choose_mode(q, q.m, c);
         P.slice = q.nslice;  // full row range: any queue
+        P.bmi = pos - multi_begin < nbm ? (int32_t)(pos - multi_begin) : -1;
+        P.pad = 0;
         parts[poff[pos]] = P;
       }
     }
@@ -775,7 +786,8 @@ template <int SR, typename T>
 __global__ void __launch_bounds__(1024) k_numeric_parts(Operand A, Operand B, ProdSrc S,
                                                         const int64_t* mults,
                                                         const int64_t* cnt, const Part* parts, const int64_t* qoff,
-                                                        int nq, int nhome, unsigned long long* qctr, int32_t* cir,
+                                                        int nq, int nhome, unsigned long long* qctr,
+                                                        const uint64_t* gbm, int64_t gbm_words, int32_t* cir,
                                                         T* cnum, unsigned* err) {
   using SR_ = Semiring<SR, T>;
   constexpr bool kVal = SR != SPX_OR_AND;
@@ -821,16 +833,25 @@ __global__ void __launch_bounds__(1024) k_numeric_parts(Operand A, Operand B, Pr
       uint64_t* bm = (uint64_t*)lds;
       uint16_t* pre = (uint16_t*)(bm + W);
       T* vals = (T*)(lds + W * 8 + ((W * 2 + 7) & ~7));
-      for (int i = threadIdx.x; i < W; i += blockDim.x) bm[i] = 0;
+      // the row set: the count phase's stored bitmap, else marked here
+      const bool stored = gbm != nullptr && P.bmi >= 0;
+      if (stored) {
+        const uint64_t* g = gbm + (int64_t)P.bmi * gbm_words + (P.r0 >> 6);
+        for (int i = threadIdx.x; i < W; i += blockDim.x) bm[i] = g[i];
+      } else {
+        for (int i = threadIdx.x; i < W; i += blockDim.x) bm[i] = 0;
+      }
       if constexpr (kVal)
         for (int i = threadIdx.x; i < c; i += blockDim.x) vals[i] = SR_::ident();
       __syncthreads();
-      block_products<16, T, false, SR_::kUsesB>(S, an, bn, b0, b1, P.r0, P.r1, full, s_rng, red,
-                                                [&](int32_t r, T, T) {
-        const uint32_t d = (uint32_t)(r - P.r0);
-        atomicOr((unsigned long long*)&bm[d >> 6], 1ull << (d & 63));
-      });
-      __syncthreads();
+      if (!stored) {
+        block_products<16, T, false, SR_::kUsesB>(S, an, bn, b0, b1, P.r0, P.r1, full, s_rng, red,
+                                                  [&](int32_t r, T, T) {
+          const uint32_t d = (uint32_t)(r - P.r0);
+          atomicOr((unsigned long long*)&bm[d >> 6], 1ull << (d & 63));
+        });
+        __syncthreads();
+      }
       // exclusive popcount prefix per word
       const int per = (W + blockDim.x - 1) / blockDim.x;
       const int w0 = threadIdx.x * per;
@@ -852,7 +873,7 @@ __global__ void __launch_bounds__(1024) k_numeric_parts(Operand A, Operand B, Pr
           const int rank = (int)pre[d >> 6] + __popcll(word & ((1ull << (d & 63)) - 1ull));
           if (rank < c) SR_::lds_acc(&vals[rank], SR_::mul(a, bv));
         };
-        if (b1 - b0 <= (int64_t)(blockDim.x < kQChunk ? blockDim.x : kQChunk))
+        if (!stored && b1 - b0 <= (int64_t)(blockDim.x < kQChunk ? blockDim.x : kQChunk))
           block_products<8, T, SR_::kUsesA, SR_::kUsesB, true>(S, an, bn, b0, b1, P.r0, P.r1, full, s_rng, red, acc);
         else
           block_products<8, T, SR_::kUsesA, SR_::kUsesB>(S, an, bn, b0, b1, P.r0, P.r1, full, s_rng, red, acc);
@@ -1103,6 +1124,8 @@ struct GemmPlan : spx_plan {
   int32_t nq_multi = 1, nslice = 1, nslice_req = 1;
   Summary* sum = nullptr;
   int64_t L = 0, L_single = 0;
+  uint64_t* gbm = nullptr;  // stored row bitmaps of the bitmap-counted columns
+  int64_t gbm_words = 0;    // 64-bit words per stored bitmap
 };
 
 int check_mat(const spx_mat* X, const char* name) {
@@ -1153,6 +1176,7 @@ extern "C" void spx_default_tuning(spx_tuning* t) {
   t->single_threads = 256;
   t->bitmap_chunk_log2 = 0;
   t->xcd_slices = 1;
+  t->bitmap_store_mb = 16384;
 }
 
 template <int SR, typename T>
@@ -1175,7 +1199,8 @@ static int launch_numeric(GemmPlan* P, spx_mat* C, hipStream_t st) {
     const int nq = r == 0 ? P->nq_multi : 1;
     unsigned long long* qctr = r == 0 ? P->qctr : P->qctr + P->nq_multi;
     hipLaunchKernelGGL((k_numeric_parts<SR, T>), dim3((unsigned)grid), dim3(blk), (size_t)L, st, P->A, P->B, P->src,
-                       P->mults_d, P->cnt, P->parts, qoff, nq, r == 0 ? P->nslice : 1, qctr, cir, cnum, err);
+                       P->mults_d, P->cnt, P->parts, qoff, nq, r == 0 ? P->nslice : 1, qctr, P->gbm, P->gbm_words,
+                       cir, cnum, err);
     SPX_HIP(hipGetLastError());
     if (r == 0) P->mark(kEvMulti, st);
   }
@@ -1399,8 +1424,17 @@ extern "C" int spx_spgemm_plan(const spx_ctx* ctx, const spx_mat* A, const spx_m
     const int per_cu = std::max<int>(1, std::min<int>((int)((160 * 1024) / (lds + 8192)), 2048 / tune.bitmap_threads));
     int64_t bgrid = std::min<int64_t>(nbitmap * nchunks, (int64_t)cus * per_cu);
     bgrid = std::max<int64_t>(nchunks, bgrid / nchunks * nchunks);
-    k_count_bitmap<<<(unsigned)bgrid, tune.bitmap_threads, lds, st>>>(P->B, P->src, P->mults_d, P->list, P->binoff, m, clog, rb, nblk, blkcnt,
-                           (unsigned long long*)P->cnt);
+    // keep the bitmaps for the numeric phase when they fit the cap
+    const int64_t words = ceil_div(m, 64);
+    if (tune.bitmap_store_mb > 0 && (double)nbitmap * words * 8.0 <= (double)tune.bitmap_store_mb * 1048576.0) {
+      if (scr.get_n(nbitmap * words, &P->gbm) == SPX_OK)
+        P->gbm_words = words;
+      else
+        P->gbm = nullptr;  // not enough memory: recompute instead
+    }
+    k_count_bitmap<<<(unsigned)bgrid, tune.bitmap_threads, lds, st>>>(
+        P->B, P->src, P->mults_d, P->list, P->binoff, m, clog, rb, nblk, blkcnt, (unsigned long long*)P->cnt,
+        (uint32_t*)P->gbm, 2 * P->gbm_words);
     SPX_HIP(hipGetLastError());
   }
   // column pointers and nonempty-column offsets
@@ -1419,7 +1453,8 @@ extern "C" int spx_spgemm_plan(const spx_ctx* ctx, const spx_mat* A, const spx_m
   if (npos > 0) {
     SPX_TRY(scr.get_n(npos, &np));
     SPX_TRY(scr.get_n(npos + 1, &poff));
-    k_parts<<<grid_for(npos, 256, (int64_t)cus * 16), 256, 0, st>>>(pc, pcs, P->list, npos, multi_begin, multi_end, P->cnt,
+    k_parts<<<grid_for(npos, 256, (int64_t)cus * 16), 256, 0, st>>>(pc, pcs, P->list, npos, multi_begin, multi_end,
+                                                                    P->gbm ? nbitmap : 0, P->cnt,
                                                                     P->off, blkcnt, np, nullptr, nullptr, err);
     SPX_HIP(hipGetLastError());
     SPX_TRY(exclusive_scan(LoadI64{np}, npos, poff, scr, st));
@@ -1445,7 +1480,8 @@ extern "C" int spx_spgemm_plan(const spx_ctx* ctx, const spx_mat* A, const spx_m
   P->nnz_tiny = (int64_t)hs.nnz_tiny;
   if (P->nparts > 0) {
     SPX_TRY(scr.get_n(P->nparts, &P->parts));
-    k_parts<<<grid_for(npos, 256, (int64_t)cus * 16), 256, 0, st>>>(pc, pcs, P->list, npos, multi_begin, multi_end, P->cnt,
+    k_parts<<<grid_for(npos, 256, (int64_t)cus * 16), 256, 0, st>>>(pc, pcs, P->list, npos, multi_begin, multi_end,
+                                                                    P->gbm ? nbitmap : 0, P->cnt,
                                                                     P->off, blkcnt, nullptr, poff, P->parts, err);
     SPX_HIP(hipGetLastError());
     // work queues of the multi-part launch: one per row slice plus a

@@ -73,6 +73,9 @@ def test_rmat_semirings(spx, semiring, values, exact):
     dict(tiny_max=0, hash_count_max=0, bitmap_chunk_log2=10, bitmap_threads=256),  # chunked bitmap count
     dict(part_lds_bytes=24 * 1024, xcd_slices=1),        # one shared work queue
     dict(part_lds_bytes=24 * 1024, xcd_slices=3),        # slices not a power of two
+    dict(tiny_max=0, hash_count_max=0, bitmap_store_mb=0),  # numeric phase re-marks the bitmap rows
+    dict(part_lds_bytes=24 * 1024, bitmap_store_mb=0),
+    dict(tiny_max=0, hash_count_max=0, bitmap_store_mb=1),  # over the cap: recomputed
 ])
 @pytest.mark.parametrize("dtype", [np.float64, np.float32])
 def test_forced_paths(spx, tune, dtype):
