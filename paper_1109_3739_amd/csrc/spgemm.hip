@@ -305,16 +305,19 @@ __device__ __forceinline__ void for_products(const ProdSrc& S, const T* an, cons
 // chunks hold min(blockDim.x, kQChunk) entries.
 constexpr int kQChunk = 256;
 
+constexpr int kWinTab = 512;  // windows of 64 products with a table entry
+
 struct RangeLds {
   int64_t start[kQChunk];
   int32_t pref[kQChunk + 1];
   int32_t flt[kQChunk];
   double bval[kQChunk];  // B's value, stored in the first bytes of each slot
+  int16_t wst[kWinTab];  // range holding product 64 k
 };
 
 // With REUSE the range list left in R by the previous call for the same
 // column and row range is used as is (the column must fit one chunk).
-template <int U, typename T, bool LOADA, bool LOADB, bool REUSE = false, class F>
+template <int U, typename T, bool LOADA, bool LOADB, bool REUSE = false, bool WAVE_RUNS = false, class F>
 __device__ __forceinline__ void block_products(const ProdSrc& S, const T* an, const T* bn, int64_t b0, int64_t b1,
                                                int32_t r0, int32_t r1, bool full, RangeLds& R, int64_t* red, F&& f) {
   const int qchunk = (int)blockDim.x < kQChunk ? (int)blockDim.x : kQChunk;
@@ -345,23 +348,69 @@ __device__ __forceinline__ void block_products(const ProdSrc& S, const T* an, co
     if (!REUSE) {
       int64_t total64;
       const int64_t ex = block_excl_scan((int64_t)mylen, red, &total64);
-      if ((int)threadIdx.x < nq) R.pref[threadIdx.x] = (int32_t)ex;
+      if ((int)threadIdx.x < nq) {
+        R.pref[threadIdx.x] = (int32_t)ex;
+        if constexpr (!WAVE_RUNS) {
+          // windows whose first product falls in this range
+          const int64_t k1 = (ex + mylen + kWave - 1) / kWave;
+          for (int64_t k = (ex + kWave - 1) / kWave; k < k1 && k < kWinTab; ++k) R.wst[k] = (int16_t)threadIdx.x;
+        }
+      }
       if (threadIdx.x == 0) R.pref[nq] = (int32_t)total64;
       __syncthreads();
     }
     const int32_t total = R.pref[nq];
+    // Products are numbered in range order and taken in windows of 64 (one
+    // wave, one product per lane).  Each lane finds the range of its product
+    // by a binary search over a short interval of the range list:
+    //  WAVE_RUNS: each wave takes U consecutive windows per round; the range
+    //    of the wave's first product (s0) is found once per round, the lanes
+    //    load the next 64 range starts and a ballot counts those inside the
+    //    round (if all 64 are, the search runs over all ranges after s0);
+    //  otherwise: windows are dealt round robin to the waves and the window
+    //    table (range of each window's first product, written at set-up)
+    //    bounds the search by the ranges of the window's first and next
+    //    window's first product.
+    const int lane = lane_id();
+    const int32_t nwin = (int32_t)blockDim.x / kWave;
+    const int32_t wid = (int32_t)threadIdx.x / kWave;
     for (int32_t base = 0; base < total; base += (int32_t)blockDim.x * U) {
       int32_t r[U];
       T a[U];
       int ix[U];
+      int s0 = 0, s1 = 0;
+      const int32_t pw = base + wid * (U * kWave);
+      if constexpr (WAVE_RUNS) {
+        if (pw < total) {
+          int lo = 0, hi = nq;
+          while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (R.pref[mid] <= pw)
+              lo = mid;
+            else
+              hi = mid;
+          }
+          s0 = __builtin_amdgcn_readfirstlane(lo);
+          const int j = s0 + 1 + lane;
+          const int32_t bj = j <= nq ? R.pref[j] : 0x7fffffff;
+          const uint64_t in_round = __ballot(bj < pw + U * kWave);
+          s1 = in_round == ~0ull ? nq + 1 : s0 + __popcll(in_round) + 1;
+        }
+      }
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        const int32_t p = base + u * (int32_t)blockDim.x + (int32_t)threadIdx.x;
+        const int32_t p0 = WAVE_RUNS ? pw + u * kWave : base + (u * nwin + wid) * kWave;
+        const int32_t p = p0 + lane;
         r[u] = -1;
         a[u] = T(0);
         ix[u] = 0;
         if (p < total) {
-          int lo = 0, hi = nq;  // last i with pref[i] <= p
+          int lo = s0, hi = s1;  // last range with start <= p
+          if constexpr (!WAVE_RUNS) {
+            const int32_t k = p0 / kWave;
+            lo = k < kWinTab ? (int)R.wst[k] : 0;
+            hi = (k + 1 < kWinTab && p0 + kWave < total) ? (int)R.wst[k + 1] + 1 : nq;
+          }
           while (hi - lo > 1) {
             const int mid = (lo + hi) >> 1;
             if (R.pref[mid] <= p)
@@ -523,7 +572,8 @@ __global__ void k_count_hash(Operand B, ProdSrc S, const int64_t* mults,
       for (int64_t i = threadIdx.x; i < nblk; i += blockDim.x) lblk[i] = 0;
     __syncthreads();
     int64_t mine = 0;
-    block_products<8, int, false, false>(S, nullptr, nullptr, b0, b1, 0, 0, true, s_rng, red, [&](int32_t r, int, int) {
+    block_products<8, int, false, false, false, true>(S, nullptr, nullptr, b0, b1, 0, 0, true, s_rng, red,
+                                                      [&](int32_t r, int, int) {
       if (r < 0) return;
       uint32_t h = hash_row(r, log2s);
       for (uint32_t probe = 0; probe < TS; ++probe) {
@@ -594,7 +644,7 @@ __global__ void k_count_bitmap(Operand B, ProdSrc S, const int64_t* mults, const
     for (int i = threadIdx.x; i < words; i += blockDim.x) bm[i] = 0;
     for (int i = threadIdx.x; i < blk_per_chunk; i += blockDim.x) lblk[i] = 0;
     __syncthreads();
-    block_products<8, int, false, false>(S, nullptr, nullptr, b0, b1, (int32_t)c0, (int32_t)c1, nchunks == 1, s_rng,
+    block_products<8, int, false, false, false, true>(S, nullptr, nullptr, b0, b1, (int32_t)c0, (int32_t)c1, nchunks == 1, s_rng,
                                          red, [&](int32_t r, int, int) {
       const uint32_t d = (uint32_t)(r - (int32_t)c0);
       if (d < (uint32_t)(c1 - c0)) atomicOr(&bm[d >> 5], 1u << (d & 31));
@@ -845,7 +895,7 @@ __global__ void __launch_bounds__(1024) k_numeric_parts(Operand A, Operand B, Pr
         for (int i = threadIdx.x; i < c; i += blockDim.x) vals[i] = SR_::ident();
       __syncthreads();
       if (!stored) {
-        block_products<16, T, false, SR_::kUsesB>(S, an, bn, b0, b1, P.r0, P.r1, full, s_rng, red,
+        block_products<8, T, false, SR_::kUsesB>(S, an, bn, b0, b1, P.r0, P.r1, full, s_rng, red,
                                                   [&](int32_t r, T, T) {
           const uint32_t d = (uint32_t)(r - P.r0);
           atomicOr((unsigned long long*)&bm[d >> 6], 1ull << (d & 63));
