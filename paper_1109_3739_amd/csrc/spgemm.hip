@@ -247,80 +247,69 @@ struct ProdSrc {
 };
 
 
-// Calls f(r, a, b) for every product A(r,k)*B(k,j) of the column whose B
-// entries are [b0, b1), restricted to rows [r0, r1) unless `full`.  Each
-// lane issues U independent loads before using them (latency hiding).
-// Lanes diverge: f must not use cross-lane operations.
-template <int U, typename T, bool LOADA, bool LOADB, class F>
-__device__ __forceinline__ void for_products(const ProdSrc& S, const T* an, const T* bn, int64_t b0, int64_t b1,
-                                             int G, int32_t r0, int32_t r1, bool full, F&& f) {
-  const int gid = threadIdx.x / G, gl = threadIdx.x & (G - 1), ng = blockDim.x / G;
-  for (int64_t q = b0 + gid; q < b1; q += ng) {
-    const int64_t a0 = S.a0[q];
-    int32_t e0 = 0, e1 = S.alen[q];
-    bool filter = false;
-    if (!full) {
-      const int32_t sid = S.splits ? S.split[q] : -1;
-      if (sid >= 0) {
-        const int32_t* sp = S.splits + (int64_t)sid * S.sstride;
-        e0 = sp[r0 >> S.rbshift];
-        e1 = sp[r1 >= S.m ? S.sstride - 1 : (r1 >> S.rbshift)];
-      } else {
-        filter = true;
-      }
-    }
-    T bv = T(0);
-    if constexpr (LOADB) bv = bn[q];
-    const int32_t* col = S.air + a0;
-    for (int32_t e = e0 + gl; e < e1; e += G * U) {
-      int32_t r[U];
-      T a[U];
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int32_t ee = e + u * G;
-        const bool ok = ee < e1;
-        r[u] = ok ? col[ee] : -1;
-        if constexpr (LOADA) a[u] = ok ? an[a0 + ee] : T(0);
-        else a[u] = T(0);
-      }
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        if (r[u] < 0) continue;
-        if (filter && (r[u] < r0 || r[u] >= r1)) continue;
-        f(r[u], a[u], bv);
-      }
-    }
-  }
-}
-
 // Block-cooperative iteration over the products of one output column.
 // The column's stored B entries are taken in chunks of kQChunk: all threads
 // first load, in parallel, each entry's range in A (start, length -- from
 // the split table for long columns of A -- and B's value) into an LDS range
 // list with a prefix sum of the lengths; then the products of the chunk are
-// numbered 0..total-1 and every thread takes U of them per round (product
-// p of the round is found by binary search over the prefix), so each round
-// costs one level of global-memory latency for up to blockDim*U products.
+// numbered 0..total-1 and taken in windows of 64 (one per lane of a wave),
+// U windows per wave and round.  A lane finds the range of its product by a
+// binary search over a short stretch of the list (see below), then loads
+// A's row and value.  The work of the U windows is laid out in phases
+// (search bounds, searches, range data, loads, callback) so that the loads
+// of one phase are in flight together: a round costs a few LDS latencies
+// and one global-memory latency for up to blockDim*U products.
+// f receives the U products of a lane at once: rows r[u] (-1: none, e.g.
+// past the end or outside [r0, r1)), A's values a[u] and B's values b[u].
 // Must be called by every thread of the workgroup (it contains barriers);
 // chunks hold min(blockDim.x, kQChunk) entries.
 constexpr int kQChunk = 256;
 
 constexpr int kWinTab = 512;  // windows of 64 products with a table entry
+constexpr int64_t kFilter = 1ll << 62;  // range start flag: filter rows one by one
 
 struct RangeLds {
-  int64_t start[kQChunk];
+  int64_t start[kQChunk];  // position in A (| kFilter for unsplit columns)
   int32_t pref[kQChunk + 1];
-  int32_t flt[kQChunk];
   double bval[kQChunk];  // B's value, stored in the first bytes of each slot
   int16_t wst[kWinTab];  // range holding product 64 k
 };
 
+// Adapts a per-product callback f(r, a, b) to the batch form.
+template <int U, class F>
+struct EachProduct {
+  F f;
+  template <typename T>
+  __device__ __forceinline__ void operator()(const int32_t (&r)[U], const T (&a)[U], const T (&b)[U]) {
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (r[u] >= 0) f(r[u], a[u], b[u]);
+  }
+};
+template <int U, class F>
+__device__ __forceinline__ EachProduct<U, F> each_product(F f) {
+  return EachProduct<U, F>{f};
+}
+
+// Range search of a window:
+//  WAVE_RUNS: each wave takes U consecutive windows per round; the range of
+//    the wave's first product (s0) is found once per round, the lanes load
+//    the next 64 range starts and a ballot counts those inside the round, so
+//    each product searches only among them (if all 64 are inside, among all
+//    ranges after s0);
+//  otherwise: windows are dealt round robin to the waves, and the window
+//    table (range of each window's first product, written at set-up) bounds
+//    the search by the ranges of the window's first product and of the next
+//    window's first product.
 // With REUSE the range list left in R by the previous call for the same
 // column and row range is used as is (the column must fit one chunk).
 template <int U, typename T, bool LOADA, bool LOADB, bool REUSE = false, bool WAVE_RUNS = false, class F>
 __device__ __forceinline__ void block_products(const ProdSrc& S, const T* an, const T* bn, int64_t b0, int64_t b1,
                                                int32_t r0, int32_t r1, bool full, RangeLds& R, int64_t* red, F&& f) {
   const int qchunk = (int)blockDim.x < kQChunk ? (int)blockDim.x : kQChunk;
+  const int lane = lane_id();
+  const int32_t nwin = (int32_t)blockDim.x / kWave;
+  const int32_t wid = __builtin_amdgcn_readfirstlane((int32_t)threadIdx.x / kWave);
   for (int64_t qc = b0; qc < b1; qc += qchunk) {
     const int nq = (int)(b1 - qc < qchunk ? b1 - qc : qchunk);
     int32_t mylen = 0;
@@ -329,7 +318,7 @@ __device__ __forceinline__ void block_products(const ProdSrc& S, const T* an, co
       const int64_t q = qc + i;
       const int64_t a0 = S.a0[q];
       int32_t e0 = 0, e1 = S.alen[q];
-      int32_t flt = 0;
+      int64_t flt = 0;
       if (!full) {
         const int32_t sid = S.splits ? S.split[q] : -1;
         if (sid >= 0) {
@@ -337,11 +326,10 @@ __device__ __forceinline__ void block_products(const ProdSrc& S, const T* an, co
           e0 = sp[r0 >> S.rbshift];
           e1 = sp[r1 >= S.m ? S.sstride - 1 : (r1 >> S.rbshift)];
         } else {
-          flt = 1;
+          flt = kFilter;
         }
       }
-      R.start[i] = a0 + e0;
-      R.flt[i] = flt;
+      R.start[i] = (a0 + e0) | flt;
       if constexpr (LOADB) reinterpret_cast<T*>(&R.bval[i])[0] = bn[q];
       mylen = e1 - e0;
     }
@@ -360,78 +348,101 @@ __device__ __forceinline__ void block_products(const ProdSrc& S, const T* an, co
       __syncthreads();
     }
     const int32_t total = R.pref[nq];
-    // Products are numbered in range order and taken in windows of 64 (one
-    // wave, one product per lane).  Each lane finds the range of its product
-    // by a binary search over a short interval of the range list:
-    //  WAVE_RUNS: each wave takes U consecutive windows per round; the range
-    //    of the wave's first product (s0) is found once per round, the lanes
-    //    load the next 64 range starts and a ballot counts those inside the
-    //    round (if all 64 are, the search runs over all ranges after s0);
-    //  otherwise: windows are dealt round robin to the waves and the window
-    //    table (range of each window's first product, written at set-up)
-    //    bounds the search by the ranges of the window's first and next
-    //    window's first product.
-    const int lane = lane_id();
-    const int32_t nwin = (int32_t)blockDim.x / kWave;
-    const int32_t wid = (int32_t)threadIdx.x / kWave;
     for (int32_t base = 0; base < total; base += (int32_t)blockDim.x * U) {
-      int32_t r[U];
-      T a[U];
-      int ix[U];
-      int s0 = 0, s1 = 0;
       const int32_t pw = base + wid * (U * kWave);
+      // phase 1: search bounds [lo, lo + n) of every window (wave-uniform)
+      int lo[U], n[U];
       if constexpr (WAVE_RUNS) {
+        int s0 = 0, s1 = 1;
         if (pw < total) {
-          int lo = 0, hi = nq;
-          while (hi - lo > 1) {
-            const int mid = (lo + hi) >> 1;
+          int l = 0, h = nq;
+          while (h - l > 1) {
+            const int mid = (l + h) >> 1;
             if (R.pref[mid] <= pw)
-              lo = mid;
+              l = mid;
             else
-              hi = mid;
+              h = mid;
           }
-          s0 = __builtin_amdgcn_readfirstlane(lo);
+          s0 = __builtin_amdgcn_readfirstlane(l);
           const int j = s0 + 1 + lane;
           const int32_t bj = j <= nq ? R.pref[j] : 0x7fffffff;
           const uint64_t in_round = __ballot(bj < pw + U * kWave);
           s1 = in_round == ~0ull ? nq + 1 : s0 + __popcll(in_round) + 1;
         }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          lo[u] = s0;
+          n[u] = s1 - s0;
+        }
+      } else {
+        // all table reads first (one LDS latency), then the bounds
+        int tl[U], th[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int32_t k = base / kWave + u * nwin + wid;
+          const int32_t kc = k < kWinTab - 1 ? k : kWinTab - 2;
+          tl[u] = R.wst[kc];
+          th[u] = R.wst[kc + 1];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int32_t p0 = base + (u * nwin + wid) * kWave;
+          const int32_t k = p0 / kWave;
+          int l = 0, h = 1;
+          if (p0 >= total) {
+          } else if (k + 1 < kWinTab && p0 + kWave < total) {
+            l = tl[u];
+            h = th[u] + 1;
+          } else {
+            l = k < kWinTab ? tl[u] : 0;
+            h = nq;
+          }
+          lo[u] = __builtin_amdgcn_readfirstlane(l);
+          n[u] = __builtin_amdgcn_readfirstlane(h) - lo[u];
+        }
+      }
+      // phase 2: last range with start <= p (uniform trip counts)
+      int32_t p[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int32_t pp = (WAVE_RUNS ? pw + u * kWave : base + (u * nwin + wid) * kWave) + lane;
+        p[u] = pp < total ? pp : total - 1;
+        int pos = lo[u];
+        for (int m = n[u]; m > 1;) {
+          const int half = m >> 1;
+          if (R.pref[pos + half] <= p[u]) pos += half;
+          m -= half;
+        }
+        lo[u] = pos;
+        if (pp >= total) p[u] = -1;
+      }
+      // phase 3: range data; phase 4: A's row and value
+      int64_t e[U];
+      int32_t r[U];
+      T a[U], bv[U];
+      bool fl[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int64_t st = R.start[lo[u]];
+        const int32_t pf = R.pref[lo[u]];
+        fl[u] = (st & kFilter) != 0;
+        e[u] = (st & (kFilter - 1)) + ((p[u] < 0 ? total - 1 : p[u]) - pf);
+        bv[u] = LOADB ? reinterpret_cast<const T*>(&R.bval[lo[u]])[0] : T(0);
       }
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        const int32_t p0 = WAVE_RUNS ? pw + u * kWave : base + (u * nwin + wid) * kWave;
-        const int32_t p = p0 + lane;
         r[u] = -1;
         a[u] = T(0);
-        ix[u] = 0;
-        if (p < total) {
-          int lo = s0, hi = s1;  // last range with start <= p
-          if constexpr (!WAVE_RUNS) {
-            const int32_t k = p0 / kWave;
-            lo = k < kWinTab ? (int)R.wst[k] : 0;
-            hi = (k + 1 < kWinTab && p0 + kWave < total) ? (int)R.wst[k + 1] + 1 : nq;
-          }
-          while (hi - lo > 1) {
-            const int mid = (lo + hi) >> 1;
-            if (R.pref[mid] <= p)
-              lo = mid;
-            else
-              hi = mid;
-          }
-          const int64_t e = R.start[lo] + (p - R.pref[lo]);
-          ix[u] = lo;
-          r[u] = S.air[e];
-          if constexpr (LOADA) a[u] = an[e];
+        // windows wholly past the end load nothing (wave-uniform test)
+        if ((WAVE_RUNS ? pw + u * kWave : base + (u * nwin + wid) * kWave) < total) {
+          r[u] = S.air[e[u]];
+          if constexpr (LOADA) a[u] = an[e[u]];
         }
       }
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        if (r[u] < 0) continue;
-        if (R.flt[ix[u]] && (r[u] < r0 || r[u] >= r1)) continue;
-        T bv = T(0);
-        if constexpr (LOADB) bv = reinterpret_cast<const T*>(&R.bval[ix[u]])[0];
-        f(r[u], a[u], bv);
-      }
+      for (int u = 0; u < U; ++u)
+        if (p[u] < 0 || (fl[u] && (r[u] < r0 || r[u] >= r1))) r[u] = -1;
+      f(r, a, bv);
     }
     __syncthreads();
   }
@@ -573,7 +584,7 @@ __global__ void k_count_hash(Operand B, ProdSrc S, const int64_t* mults,
     __syncthreads();
     int64_t mine = 0;
     block_products<8, int, false, false, false, true>(S, nullptr, nullptr, b0, b1, 0, 0, true, s_rng, red,
-                                                      [&](int32_t r, int, int) {
+                                                      each_product<8>([&](int32_t r, int, int) {
       if (r < 0) return;
       uint32_t h = hash_row(r, log2s);
       for (uint32_t probe = 0; probe < TS; ++probe) {
@@ -586,7 +597,7 @@ __global__ void k_count_hash(Operand B, ProdSrc S, const int64_t* mults,
         h = (h + 1) & (TS - 1);
       }
       atomicOr(err, 2u);
-    });
+    }));
     __syncthreads();
     int64_t total;
     block_excl_scan(mine, red, &total);
@@ -645,10 +656,10 @@ __global__ void k_count_bitmap(Operand B, ProdSrc S, const int64_t* mults, const
     for (int i = threadIdx.x; i < blk_per_chunk; i += blockDim.x) lblk[i] = 0;
     __syncthreads();
     block_products<8, int, false, false, false, true>(S, nullptr, nullptr, b0, b1, (int32_t)c0, (int32_t)c1, nchunks == 1, s_rng,
-                                         red, [&](int32_t r, int, int) {
+                                         red, each_product<8>([&](int32_t r, int, int) {
       const uint32_t d = (uint32_t)(r - (int32_t)c0);
       if (d < (uint32_t)(c1 - c0)) atomicOr(&bm[d >> 5], 1u << (d & 31));
-    });
+    }));
     __syncthreads();
     int64_t mine = 0;
     for (int i = threadIdx.x; i < words; i += blockDim.x) {
@@ -682,7 +693,8 @@ struct Part {
   int32_t mode;  // 0 = bitmap, 1 = hash
   int32_t slice; // row slice of the part (work queue), nslice = any
   int32_t bmi;   // index of the column's stored row bitmap, -1 if none
-  int32_t pad;
+  int32_t nb;    // B entries of the column: [b0, b0 + nb)
+  int64_t b0;
 };
 
 struct PartCfg {
@@ -703,11 +715,14 @@ __device__ __forceinline__ int64_t bitmap_bytes(const PartCfg& p, int64_t span, 
 __device__ __forceinline__ bool bitmap_ok(const PartCfg& p, int64_t span, int64_t c) {
   return c < 65536 && bitmap_bytes(p, span, c) <= p.L;
 }
+// Rows a hash-mode part may span for the two-level rank (longer: sorted).
+constexpr int64_t kRankSpan = 1ll << 20;
+
 __device__ __forceinline__ int64_t hash_bytes(const PartCfg& p, int64_t c) {
   int64_t p2 = 64;
   while (p2 < c) p2 <<= 1;
   const int64_t S = 2 * p2;
-  return S * 4 + ((S * p.sz + 7) & ~7ll) + p2 * 8 + 64;
+  return S * 4 + ((S * p.sz + 7) & ~7ll) + p2 * 10 + (kRankSpan >> 9) + (kRankSpan >> 11) + 64;
 }
 __device__ __forceinline__ bool hash_ok(const PartCfg& p, int64_t c) { return hash_bytes(p, c) <= p.L; }
 
@@ -726,7 +741,7 @@ __device__ __forceinline__ int choose_mode(const PartCfg& p, int64_t span, int64
 // it still fits the LDS budget in one of the two modes.  With emit == false
 // only counts parts.
 __device__ int64_t cut_parts(const PartCfg& p, const uint32_t* blk, int32_t t, int64_t base_off, bool emit, Part* out,
-                             int32_t bmi, unsigned* err) {
+                             int32_t bmi, int64_t b0, int32_t nb, unsigned* err) {
   const int64_t RB = 1ll << p.rbshift;
   int64_t np = 0, run = 0;
   int64_t b = 0;
@@ -759,7 +774,8 @@ __device__ int64_t cut_parts(const PartCfg& p, const uint32_t* blk, int32_t t, i
         P.mode = choose_mode(p, r1 - r0, c);
         P.slice = p.slice_blocks ? (int32_t)(b / p.slice_blocks) : 0;
         P.bmi = bmi;
-        P.pad = 0;
+        P.b0 = b0;
+        P.nb = nb;
         out[np] = P;
       }
       ++np;
@@ -772,7 +788,7 @@ __device__ int64_t cut_parts(const PartCfg& p, const uint32_t* blk, int32_t t, i
 
 // Number of parts of every non-tiny, nonempty column (list positions
 // [0, npos)), or the parts themselves (emit).
-__global__ void k_parts(PartCfg p, PartCfg ps, const int32_t* list, int64_t npos, int64_t multi_begin, int64_t multi_end,
+__global__ void k_parts(Operand B, PartCfg p, PartCfg ps, const int32_t* list, int64_t npos, int64_t multi_begin, int64_t multi_end,
                         int64_t nbm, const int64_t* cnt, const int64_t* off, const uint32_t* blkcnt,
                         int64_t* nparts, const int64_t* poff, Part* parts, unsigned* err) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -784,8 +800,10 @@ __global__ void k_parts(PartCfg p, PartCfg ps, const int32_t* list, int64_t npos
     if (c == 0) {
       np = 0;
     } else if (pos >= multi_begin && pos < multi_end && !(bitmap_ok(p, p.m, c) || hash_ok(p, c))) {
+      const int64_t cb0 = slot_begin(B, t);
       np = cut_parts(p, blkcnt + (pos - multi_begin) * p.nblk, t, off[t], emit, emit ? parts + poff[pos] : nullptr,
-                     pos - multi_begin < nbm ? (int32_t)(pos - multi_begin) : -1, err);
+                     pos - multi_begin < nbm ? (int32_t)(pos - multi_begin) : -1, cb0,
+                     (int32_t)(slot_begin(B, t + 1) - cb0), err);
     } else {
       np = 1;
       const PartCfg& q = pos < multi_end ? p : ps;
@@ -800,7 +818,8 @@ __global__ void k_parts(PartCfg p, PartCfg ps, const int32_t* list, int64_t npos
         P.mode = choose_mode(q, q.m, c);
         P.slice = q.nslice;  // full row range: any queue
         P.bmi = pos - multi_begin < nbm ? (int32_t)(pos - multi_begin) : -1;
-        P.pad = 0;
+        P.b0 = slot_begin(B, t);
+        P.nb = (int32_t)(slot_begin(B, t + 1) - P.b0);
         parts[poff[pos]] = P;
       }
     }
@@ -873,7 +892,7 @@ __global__ void __launch_bounds__(1024) k_numeric_parts(Operand A, Operand B, Pr
     __syncthreads();
     if (pi < 0) break;
     const Part P = parts[pi];
-    const int64_t b0 = slot_begin(B, P.t), b1 = slot_begin(B, P.t + 1);
+    const int64_t b0 = P.b0, b1 = P.b0 + P.nb;
     const int64_t span = (int64_t)P.r1 - P.r0;
     const bool full = (P.r0 == 0 && P.r1 == (int32_t)A.m);
     // products in this part ~ mults * c / cnt
@@ -887,7 +906,19 @@ __global__ void __launch_bounds__(1024) k_numeric_parts(Operand A, Operand B, Pr
       const bool stored = gbm != nullptr && P.bmi >= 0;
       if (stored) {
         const uint64_t* g = gbm + (int64_t)P.bmi * gbm_words + (P.r0 >> 6);
-        for (int i = threadIdx.x; i < W; i += blockDim.x) bm[i] = g[i];
+        for (int i0 = threadIdx.x; i0 < W; i0 += 4 * blockDim.x) {  // 4 loads in flight per thread
+          uint64_t v[4];
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            const int i = i0 + k * (int)blockDim.x;
+            v[k] = i < W ? g[i] : 0ull;
+          }
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            const int i = i0 + k * (int)blockDim.x;
+            if (i < W) bm[i] = v[k];
+          }
+        }
       } else {
         for (int i = threadIdx.x; i < W; i += blockDim.x) bm[i] = 0;
       }
@@ -896,10 +927,10 @@ __global__ void __launch_bounds__(1024) k_numeric_parts(Operand A, Operand B, Pr
       __syncthreads();
       if (!stored) {
         block_products<8, T, false, SR_::kUsesB>(S, an, bn, b0, b1, P.r0, P.r1, full, s_rng, red,
-                                                  [&](int32_t r, T, T) {
+                                                  each_product<8>([&](int32_t r, T, T) {
           const uint32_t d = (uint32_t)(r - P.r0);
           atomicOr((unsigned long long*)&bm[d >> 6], 1ull << (d & 63));
-        });
+        }));
         __syncthreads();
       }
       // exclusive popcount prefix per word
@@ -924,11 +955,23 @@ __global__ void __launch_bounds__(1024) k_numeric_parts(Operand A, Operand B, Pr
       if (threadIdx.x == 0 && tot != c) atomicOr(err, 8u);
       __syncthreads();
       if constexpr (kVal) {
-        auto acc = [&](int32_t r, T a, T bv) {
-          const uint32_t d = (uint32_t)(r - P.r0);
-          const uint64_t word = bm[d >> 6];
-          const int rank = (int)pre[d >> 6] + __popcll(word & ((1ull << (d & 63)) - 1ull));
-          if (rank < c) SR_::lds_acc(&vals[rank], SR_::mul(a, bv));
+        // rank of each product's row: all bitmap words first, then the adds
+        auto acc = [&](const int32_t (&r)[8], const T (&a)[8], const T (&bv)[8]) {
+          uint64_t w[8];
+          int pr[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            const int wi = r[u] >= 0 ? (int)((uint32_t)(r[u] - P.r0) >> 6) : 0;
+            w[u] = bm[wi];
+            pr[u] = pre[wi];
+          }
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            if (r[u] < 0) continue;
+            const uint32_t d = (uint32_t)(r[u] - P.r0);
+            const int rank = pr[u] + __popcll(w[u] & ((1ull << (d & 63)) - 1ull));
+            if (rank < c) SR_::lds_acc(&vals[rank], SR_::mul(a[u], bv[u]));
+          }
         };
         if (!stored && b1 - b0 <= (int64_t)(blockDim.x < kQChunk ? blockDim.x : kQChunk))
           block_products<8, T, SR_::kUsesA, SR_::kUsesB, true>(S, an, bn, b0, b1, P.r0, P.r1, full, s_rng, red, acc);
@@ -945,15 +988,30 @@ __global__ void __launch_bounds__(1024) k_numeric_parts(Operand A, Operand B, Pr
       const int log2s = 31 - __clz(Sz);
       uint32_t* keys = (uint32_t*)lds;
       T* vals = (T*)(lds + Sz * 4);
-      uint64_t* sortb = (uint64_t*)(lds + Sz * 4 + ((Sz * sizeof(T) * (kVal ? 1 : 0) + 7) & ~7u));
+      unsigned char* tail = lds + Sz * 4 + ((Sz * sizeof(T) * (kVal ? 1 : 0) + 7) & ~7u);
+      // row ranks by a two-level bitmap (spans up to kRankSpan rows): level 1
+      // marks the nonempty 64-row groups, level 2 holds one word per nonempty
+      // group; popcount prefixes of both give each row its rank.  Longer spans
+      // sort (row, slot) keys instead.
+      const bool ranked = span <= kRankSpan;
+      const int n1 = (int)((span + 4095) >> 12);
+      uint64_t* l2w = (uint64_t*)tail;
+      uint16_t* l2p = (uint16_t*)(tail + p2 * 8);
+      uint64_t* l1w = (uint64_t*)(tail + p2 * 10);
+      uint16_t* l1p = (uint16_t*)(tail + p2 * 10 + (kRankSpan >> 9));
+      uint64_t* sortb = (uint64_t*)tail;
       for (uint32_t i = threadIdx.x; i < Sz; i += blockDim.x) {
         keys[i] = 0xffffffffu;
         if constexpr (kVal) vals[i] = SR_::ident();
       }
+      if (ranked) {
+        for (int i = threadIdx.x; i < p2; i += blockDim.x) l2w[i] = 0;
+        for (int i = threadIdx.x; i < n1; i += blockDim.x) l1w[i] = 0;
+      }
       if (threadIdx.x == 0) s_ctr = 0;
       __syncthreads();
       block_products<4, T, SR_::kUsesA, SR_::kUsesB>(S, an, bn, b0, b1, P.r0, P.r1, full, s_rng, red,
-                                                     [&](int32_t r, T a, T bv) {
+                                                     each_product<4>([&](int32_t r, T a, T bv) {
         if (r < 0) return;
         uint32_t h = hash_row(r, log2s);
         for (uint32_t probe = 0; probe < Sz; ++probe) {
@@ -965,25 +1023,89 @@ __global__ void __launch_bounds__(1024) k_numeric_parts(Operand A, Operand B, Pr
           h = (h + 1) & (Sz - 1);
         }
         atomicOr(err, 16u);
-      });
+      }));
       __syncthreads();
-      for (uint32_t i = threadIdx.x; i < Sz; i += blockDim.x) {
-        const uint32_t key = keys[i];
-        if (key != 0xffffffffu) {
-          const unsigned p = atomicAdd(&s_ctr, 1u);
-          if ((int)p < p2) sortb[p] = ((uint64_t)key << 32) | i;
+      if (ranked) {
+        // level 1: nonempty groups of 64 rows
+        for (uint32_t i = threadIdx.x; i < Sz; i += blockDim.x) {
+          const uint32_t key = keys[i];
+          if (key != 0xffffffffu) {
+            const uint32_t g = (key - (uint32_t)P.r0) >> 6;
+            atomicOr((unsigned long long*)&l1w[g >> 6], 1ull << (g & 63));
+          }
         }
-      }
-      __syncthreads();
-      const int found = (int)s_ctr;
-      if (threadIdx.x == 0 && found != c) atomicOr(err, 32u);
-      for (int i = found + threadIdx.x; i < p2; i += blockDim.x) sortb[i] = ~0ull;
-      __syncthreads();
-      block_bitonic_sort<T>(sortb, p2);
-      for (int i = threadIdx.x; i < c; i += blockDim.x) {
-        const uint64_t k = sortb[i];
-        cir[P.off + i] = (int32_t)(k >> 32);
-        if constexpr (kVal) cnum[P.off + i] = vals[k & 0xffffffffu];
+        __syncthreads();
+        {
+          const int per = (n1 + (int)blockDim.x - 1) / (int)blockDim.x;
+          const int w0 = threadIdx.x * per, w1 = w0 + per < n1 ? w0 + per : n1;
+          int64_t sum = 0;
+          for (int w = w0; w < w1; ++w) sum += __popcll(l1w[w]);
+          int64_t ng;
+          int64_t run = block_excl_scan(sum, red, &ng);
+          for (int w = w0; w < w1; ++w) {
+            l1p[w] = (uint16_t)run;
+            run += __popcll(l1w[w]);
+          }
+        }
+        __syncthreads();
+        // level 2: the rows of each nonempty group
+        for (uint32_t i = threadIdx.x; i < Sz; i += blockDim.x) {
+          const uint32_t key = keys[i];
+          if (key != 0xffffffffu) {
+            const uint32_t d = key - (uint32_t)P.r0, g = d >> 6;
+            const int gi = l1p[g >> 6] + __popcll(l1w[g >> 6] & ((1ull << (g & 63)) - 1ull));
+            if (gi < p2) atomicOr((unsigned long long*)&l2w[gi], 1ull << (d & 63));
+          }
+        }
+        __syncthreads();
+        int64_t found;
+        {
+          const int per = (p2 + (int)blockDim.x - 1) / (int)blockDim.x;
+          const int w0 = threadIdx.x * per, w1 = w0 + per < p2 ? w0 + per : p2;
+          int64_t sum = 0;
+          for (int w = w0; w < w1; ++w) sum += __popcll(l2w[w]);
+          int64_t run = block_excl_scan(sum, red, &found);
+          for (int w = w0; w < w1; ++w) {
+            l2p[w] = (uint16_t)run;
+            run += __popcll(l2w[w]);
+          }
+        }
+        __syncthreads();
+        if (threadIdx.x == 0 && found != c) atomicOr(err, 32u);
+        // rank = output position
+        for (uint32_t i = threadIdx.x; i < Sz; i += blockDim.x) {
+          const uint32_t key = keys[i];
+          if (key != 0xffffffffu) {
+            const uint32_t d = key - (uint32_t)P.r0, g = d >> 6;
+            const int gi = l1p[g >> 6] + __popcll(l1w[g >> 6] & ((1ull << (g & 63)) - 1ull));
+            if (gi < p2) {
+              const int rank = l2p[gi] + __popcll(l2w[gi] & ((1ull << (d & 63)) - 1ull));
+              if (rank < c) {
+                cir[P.off + rank] = (int32_t)key;
+                if constexpr (kVal) cnum[P.off + rank] = vals[i];
+              }
+            }
+          }
+        }
+      } else {
+        for (uint32_t i = threadIdx.x; i < Sz; i += blockDim.x) {
+          const uint32_t key = keys[i];
+          if (key != 0xffffffffu) {
+            const unsigned p = atomicAdd(&s_ctr, 1u);
+            if ((int)p < p2) sortb[p] = ((uint64_t)key << 32) | i;
+          }
+        }
+        __syncthreads();
+        const int found = (int)s_ctr;
+        if (threadIdx.x == 0 && found != c) atomicOr(err, 32u);
+        for (int i = found + threadIdx.x; i < p2; i += blockDim.x) sortb[i] = ~0ull;
+        __syncthreads();
+        block_bitonic_sort<T>(sortb, p2);
+        for (int i = threadIdx.x; i < c; i += blockDim.x) {
+          const uint64_t k = sortb[i];
+          cir[P.off + i] = (int32_t)(k >> 32);
+          if constexpr (kVal) cnum[P.off + i] = vals[k & 0xffffffffu];
+        }
       }
       __syncthreads();
     }
@@ -1162,8 +1284,8 @@ struct GemmPlan : spx_plan {
   int64_t* binoff = nullptr;
   Part* parts = nullptr;
   int64_t* qoff_multi = nullptr;
-  int64_t* qoff_single = nullptr;
   unsigned long long* qctr = nullptr;
+  int64_t* qoff_single = nullptr;
   int32_t nq_multi = 1, nslice = 1, nslice_req = 1;
   Summary* sum = nullptr;
   int64_t L = 0, L_single = 0;
@@ -1350,7 +1472,7 @@ extern "C" int spx_spgemm_plan(const spx_ctx* ctx, const spx_mat* A, const spx_m
   while ((1 << sp_log2) < tune.single_part_max) ++sp_log2;
   {
     const int64_t p2 = tune.single_part_max, S2 = 2 * p2;
-    P->L_single = S2 * 4 + ((S2 * sz + 7) & ~7ll) + p2 * 8 + 64;
+    P->L_single = S2 * 4 + ((S2 * sz + 7) & ~7ll) + p2 * 10 + (kRankSpan >> 9) + (kRankSpan >> 11) + 64;
     if (P->L_single > 160 * 1024 - 8192) return fail(SPX_EINVAL, "single_part_max too large for LDS");
   }
   const int64_t nblk = std::max<int64_t>(1, ceil_div(m, 1ll << rb));
@@ -1496,7 +1618,7 @@ extern "C" int spx_spgemm_plan(const spx_ctx* ctx, const spx_mat* A, const spx_m
   if (npos > 0) {
     SPX_TRY(scr.get_n(npos, &np));
     SPX_TRY(scr.get_n(npos + 1, &poff));
-    k_parts<<<grid_for(npos, 256, (int64_t)cus * 16), 256, 0, st>>>(pc, pcs, P->list, npos, multi_begin, multi_end,
+    k_parts<<<grid_for(npos, 256, (int64_t)cus * 16), 256, 0, st>>>(P->B, pc, pcs, P->list, npos, multi_begin, multi_end,
                                                                     P->gbm ? nbitmap : 0, P->cnt,
                                                                     P->off, blkcnt, np, nullptr, nullptr, err);
     SPX_HIP(hipGetLastError());
@@ -1523,7 +1645,7 @@ extern "C" int spx_spgemm_plan(const spx_ctx* ctx, const spx_mat* A, const spx_m
   P->nnz_tiny = (int64_t)hs.nnz_tiny;
   if (P->nparts > 0) {
     SPX_TRY(scr.get_n(P->nparts, &P->parts));
-    k_parts<<<grid_for(npos, 256, (int64_t)cus * 16), 256, 0, st>>>(pc, pcs, P->list, npos, multi_begin, multi_end,
+    k_parts<<<grid_for(npos, 256, (int64_t)cus * 16), 256, 0, st>>>(P->B, pc, pcs, P->list, npos, multi_begin, multi_end,
                                                                     P->gbm ? nbitmap : 0, P->cnt,
                                                                     P->off, blkcnt, nullptr, poff, P->parts, err);
     SPX_HIP(hipGetLastError());

@@ -105,6 +105,21 @@ def test_rectangular_and_independent(spx):
     check_against_oracle(spx, A, B, "min_plus", exact=True)
 
 
+def test_tall_hash_parts_sorted_path(spx):
+    # A has more than 2^20 rows, so hash-mode parts spanning all rows take the
+    # sorted path instead of the two-level rank; a shorter A takes the rank
+    A = W.erdos_renyi(3_000_000, 96, 24, seed=21)
+    B = W.erdos_renyi(96, 64, 48, seed=22)
+    for sr, exact in (("plus_times", False), ("min_plus", True)):
+        _, info = check_against_oracle(spx, A, B, sr, exact=exact)
+        assert info["cols_medium"] + info["cols_heavy"] > 0
+    B2 = W.erdos_renyi(96, 64, 40, seed=24)          # single-part columns (960 products)
+    check_against_oracle(spx, A, B2, "plus_times")
+    A2 = W.erdos_renyi(900_000, 96, 24, seed=23)
+    check_against_oracle(spx, A2, B, "plus_times")
+    check_against_oracle(spx, A2, B2, "min_plus", exact=True)
+
+
 @pytest.mark.parametrize("out_fmt", [0, 1])
 def test_dcsc_stage_blocks(spx, out_fmt):
     """One GPU's share of an 8x8 Sparse SUMMA stage: hypersparse blocks in DCSC."""
