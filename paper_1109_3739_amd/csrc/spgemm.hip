@@ -1336,7 +1336,7 @@ extern "C" void spx_default_tuning(spx_tuning* t) {
   t->single_part_max = 1024;
   t->part_lds_bytes = 72 * 1024;
   t->count_threads = 256;
-  t->bitmap_threads = 1024;
+  t->bitmap_threads = 512;
   t->part_threads = 512;
   t->single_threads = 256;
   t->bitmap_chunk_log2 = 0;
@@ -1567,7 +1567,7 @@ extern "C" int spx_spgemm_plan(const spx_ctx* ctx, const spx_mat* A, const spx_m
     if (nb == 0) continue;
     const int log2s = kHashLog2Max - (b - kBinHash0);
     const size_t lds = ((size_t)4 << log2s) + (nblk <= 1024 ? (size_t)nblk * 4 : 0);
-    const int blk = log2s >= 13 ? std::max(tune.count_threads, 512) : tune.count_threads;
+    const int blk = log2s >= 15 ? 1024 : (log2s >= 13 ? std::max(tune.count_threads, 512) : tune.count_threads);
     const int per_cu = std::max<int>(1, (int)((160 * 1024) / (lds + 8192)));
     k_count_hash<<<(unsigned)std::min<int64_t>(nb, (int64_t)cus * per_cu), blk, lds, st>>>(
         P->B, P->src, P->mults_d, P->list, P->binoff, b, log2s, multi_end, rb, nblk, blkcnt, P->cnt, err);
@@ -1578,9 +1578,10 @@ extern "C" int spx_spgemm_plan(const spx_ctx* ctx, const spx_mat* A, const spx_m
     // bitmap chunks: a power of two of rows, a multiple of the row block;
     // 0 = one chunk per row slice
     int want = tune.bitmap_chunk_log2;
-    if (want <= 0) {
+    if (want <= 0) {  // auto: one chunk per row slice, at most 2^19 rows (two workgroups per CU)
       want = 0;
       while ((1ll << want) < ceil_div(m, std::max(1, P->nslice_req))) ++want;
+      want = std::min(want, 19);
     }
     int clog = std::max<int>(rb, std::min<int>(want, 20));
     while (clog > rb && (1ll << (clog - 1)) >= m) --clog;

@@ -107,17 +107,23 @@ def test_rectangular_and_independent(spx):
 
 def test_tall_hash_parts_sorted_path(spx):
     # A has more than 2^20 rows, so hash-mode parts spanning all rows take the
-    # sorted path instead of the two-level rank; a shorter A takes the rank
-    A = W.erdos_renyi(3_000_000, 96, 24, seed=21)
-    B = W.erdos_renyi(96, 64, 48, seed=22)
-    for sr, exact in (("plus_times", False), ("min_plus", True)):
-        _, info = check_against_oracle(spx, A, B, sr, exact=exact)
-        assert info["cols_medium"] + info["cols_heavy"] > 0
-    B2 = W.erdos_renyi(96, 64, 40, seed=24)          # single-part columns (960 products)
-    check_against_oracle(spx, A, B2, "plus_times")
+    # sorted path instead of the two-level rank; a shorter A takes the rank.
+    # (The oracle runs on 2 threads: its dense accumulator has m entries.)
+    def check(A, B, sr, exact):
+        C, info = gemm(spx, A, B, sr)
+        ref = oracle.spgemm_csc(A, B, sr, nthreads=2)
+        assert_same_csc(C.to_host_csc(), ref, exact_values=exact, what=sr)
+        return info
+    A = W.erdos_renyi(1_100_000, 96, 24, seed=21)
+    B = W.erdos_renyi(96, 64, 48, seed=22)            # multi-launch columns (1152 products)
+    B2 = W.erdos_renyi(96, 64, 40, seed=24)           # single-part columns (960 products)
+    info = check(A, B, "plus_times", False)
+    assert info["cols_medium"] == 64
+    check(A, B, "min_plus", True)
+    check(A, B2, "plus_times", False)
     A2 = W.erdos_renyi(900_000, 96, 24, seed=23)
-    check_against_oracle(spx, A2, B, "plus_times")
-    check_against_oracle(spx, A2, B2, "min_plus", exact=True)
+    check(A2, B, "plus_times", False)
+    check(A2, B2, "min_plus", True)
 
 
 @pytest.mark.parametrize("out_fmt", [0, 1])

@@ -100,9 +100,15 @@ def _distinct_rows_per_column(rng, m: int, n: int, d: int) -> np.ndarray:
         raise ValueError("d exceeds the number of rows")
     rows = rng.integers(0, m, size=(n, d), dtype=np.int64)
     rows.sort(axis=1)
+    tries = 0
     while d > 1:
         bad = np.nonzero(np.any(rows[:, 1:] == rows[:, :-1], axis=1))[0]
         if bad.size == 0:
+            break
+        tries += 1
+        if tries > 50:  # dense columns (d close to m): draw those without replacement
+            for j in bad:
+                rows[j] = np.sort(rng.choice(m, size=d, replace=False))
             break
         fresh = rng.integers(0, m, size=(bad.size, d), dtype=np.int64)
         fresh.sort(axis=1)
