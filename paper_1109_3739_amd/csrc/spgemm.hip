@@ -860,8 +860,11 @@ __global__ void __launch_bounds__(1024) k_numeric_parts(Operand A, Operand B, Pr
                                                         T* cnum, unsigned* err) {
   using SR_ = Semiring<SR, T>;
   constexpr bool kVal = SR != SPX_OR_AND;
+  constexpr int kPartBatch = 4;
   extern __shared__ __align__(16) unsigned char lds[];
   __shared__ int64_t s_pi;
+  __shared__ int s_nbat;
+  __shared__ Part s_batch[kPartBatch];
   __shared__ int64_t red[1024 / kWave + 1];
   __shared__ unsigned s_ctr;
   __shared__ RangeLds s_rng;
@@ -872,26 +875,34 @@ __global__ void __launch_bounds__(1024) k_numeric_parts(Operand A, Operand B, Pr
   // the XCDs round robin, so one queue's rows of A stay in one L2), then
   // takes the shared queue nq-1, then helps the others.
   const int home = nhome > 1 ? (int)(blockIdx.x % nhome) : 0;
+  // A ticket is a batch of up to kPartBatch consecutive parts (often of one
+  // column), whose descriptors are loaded together.
   int qi = 0;
   for (;;) {
     if (threadIdx.x == 0) {
       int64_t got = -1;
+      int nbat = 0;
       while (qi < nq) {
         const int q = qi == 0 ? home : (qi == 1 ? nq - 1 : (home + qi - 1) % (nq - 1));
-        const int64_t idx = (int64_t)atomicAdd(&qctr[q], 1ull);
-        if (qoff[q] + idx < qoff[q + 1]) {
-          got = qoff[q] + idx;
+        const int64_t first = qoff[q] + (int64_t)atomicAdd(&qctr[q], (unsigned long long)kPartBatch);
+        if (first < qoff[q + 1]) {
+          got = first;
+          nbat = (int)(qoff[q + 1] - first < kPartBatch ? qoff[q + 1] - first : kPartBatch);
           break;
         }
         ++qi;
       }
       s_pi = got;
+      s_nbat = nbat;
     }
     __syncthreads();
-    const int64_t pi = s_pi;
+    const int64_t pfirst = s_pi;
+    const int nbat = s_nbat;
+    if (pfirst < 0) break;
+    if ((int)threadIdx.x < nbat) s_batch[threadIdx.x] = parts[pfirst + threadIdx.x];
     __syncthreads();
-    if (pi < 0) break;
-    const Part P = parts[pi];
+    for (int bi = 0; bi < nbat; ++bi) {
+    const Part P = s_batch[bi];
     const int64_t b0 = P.b0, b1 = P.b0 + P.nb;
     const int64_t span = (int64_t)P.r1 - P.r0;
     const bool full = (P.r0 == 0 && P.r1 == (int32_t)A.m);
@@ -1108,6 +1119,7 @@ __global__ void __launch_bounds__(1024) k_numeric_parts(Operand A, Operand B, Pr
         }
       }
       __syncthreads();
+    }
     }
   }
 }
