@@ -338,11 +338,9 @@ __device__ __forceinline__ void block_products(const ProdSrc& S, const T* an, co
       const int64_t ex = block_excl_scan((int64_t)mylen, red, &total64);
       if ((int)threadIdx.x < nq) {
         R.pref[threadIdx.x] = (int32_t)ex;
-        if constexpr (!WAVE_RUNS) {
-          // windows whose first product falls in this range
-          const int64_t k1 = (ex + mylen + kWave - 1) / kWave;
-          for (int64_t k = (ex + kWave - 1) / kWave; k < k1 && k < kWinTab; ++k) R.wst[k] = (int16_t)threadIdx.x;
-        }
+        // windows whose first product falls in this range
+        const int64_t k1 = (ex + mylen + kWave - 1) / kWave;
+        for (int64_t k = (ex + kWave - 1) / kWave; k < k1 && k < kWinTab; ++k) R.wst[k] = (int16_t)threadIdx.x;
       }
       if (threadIdx.x == 0) R.pref[nq] = (int32_t)total64;
       __syncthreads();
@@ -355,24 +353,64 @@ __device__ __forceinline__ void block_products(const ProdSrc& S, const T* an, co
       if constexpr (WAVE_RUNS) {
         int s0 = 0, s1 = 1;
         if (pw < total) {
-          int l = 0, h = nq;
-          while (h - l > 1) {
-            const int mid = (l + h) >> 1;
-            if (R.pref[mid] <= pw)
-              l = mid;
-            else
-              h = mid;
+          int l = 0;
+          if (pw / kWave < kWinTab) {
+            l = R.wst[pw / kWave];
+          } else {
+            int h = nq;
+            while (h - l > 1) {
+              const int mid = (l + h) >> 1;
+              if (R.pref[mid] <= pw)
+                l = mid;
+              else
+                h = mid;
+            }
           }
           s0 = __builtin_amdgcn_readfirstlane(l);
           const int j = s0 + 1 + lane;
           const int32_t bj = j <= nq ? R.pref[j] : 0x7fffffff;
           const uint64_t in_round = __ballot(bj < pw + U * kWave);
-          s1 = in_round == ~0ull ? nq + 1 : s0 + __popcll(in_round) + 1;
-        }
+          if (in_round == 0 && pw + U * kWave <= total) {
+            // the whole round lies in range s0: consecutive products, no search
+            const int64_t st = R.start[s0];
+            const int64_t eb = (st & (kFilter - 1)) + (pw - R.pref[s0]) + lane;
+            const bool fl1 = (st & kFilter) != 0;
+            const T b1 = LOADB ? reinterpret_cast<const T*>(&R.bval[s0])[0] : T(0);
+            int32_t r[U];
+            T a[U], bv[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-          lo[u] = s0;
-          n[u] = s1 - s0;
+            for (int u = 0; u < U; ++u) {
+              r[u] = S.air[eb + u * kWave];
+              a[u] = LOADA ? an[eb + u * kWave] : T(0);
+              bv[u] = b1;
+            }
+            if (fl1) {
+#pragma unroll
+              for (int u = 0; u < U; ++u)
+                if (r[u] < r0 || r[u] >= r1) r[u] = -1;
+            }
+            f(r, a, bv);
+            continue;
+          }
+          if (in_round == ~0ull) {
+            s1 = nq + 1;
+          } else {
+            // each window: the ranges starting inside it
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+              const int32_t p0 = pw + u * kWave;
+              lo[u] = s0 + __popcll(__ballot(bj <= p0));
+              n[u] = s0 + __popcll(__ballot(bj < p0 + kWave)) + 1 - lo[u];
+            }
+            s1 = -1;
+          }
+        }
+        if (s1 >= 0) {
+#pragma unroll
+          for (int u = 0; u < U; ++u) {
+            lo[u] = s0;
+            n[u] = s1 - s0;
+          }
         }
       } else {
         // all table reads first (one LDS latency), then the bounds
