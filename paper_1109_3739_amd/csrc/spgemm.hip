@@ -975,7 +975,7 @@ __global__ void __launch_bounds__(1024) k_numeric_parts(Operand A, Operand B, Pr
         for (int i = threadIdx.x; i < c; i += blockDim.x) vals[i] = SR_::ident();
       __syncthreads();
       if (!stored) {
-        block_products<8, T, false, SR_::kUsesB>(S, an, bn, b0, b1, P.r0, P.r1, full, s_rng, red,
+        block_products<8, T, false, SR_::kUsesB, false, true>(S, an, bn, b0, b1, P.r0, P.r1, full, s_rng, red,
                                                   each_product<8>([&](int32_t r, T, T) {
           const uint32_t d = (uint32_t)(r - P.r0);
           atomicOr((unsigned long long*)&bm[d >> 6], 1ull << (d & 63));
@@ -1023,9 +1023,9 @@ __global__ void __launch_bounds__(1024) k_numeric_parts(Operand A, Operand B, Pr
           }
         };
         if (!stored && b1 - b0 <= (int64_t)(blockDim.x < kQChunk ? blockDim.x : kQChunk))
-          block_products<8, T, SR_::kUsesA, SR_::kUsesB, true>(S, an, bn, b0, b1, P.r0, P.r1, full, s_rng, red, acc);
+          block_products<8, T, SR_::kUsesA, SR_::kUsesB, true, true>(S, an, bn, b0, b1, P.r0, P.r1, full, s_rng, red, acc);
         else
-          block_products<8, T, SR_::kUsesA, SR_::kUsesB>(S, an, bn, b0, b1, P.r0, P.r1, full, s_rng, red, acc);
+          block_products<8, T, SR_::kUsesA, SR_::kUsesB, false, true>(S, an, bn, b0, b1, P.r0, P.r1, full, s_rng, red, acc);
         __syncthreads();
         for (int i = threadIdx.x; i < c; i += blockDim.x) cnum[P.off + i] = vals[i];
       }
