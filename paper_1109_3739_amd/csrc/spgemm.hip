@@ -621,8 +621,8 @@ __global__ void k_count_hash(Operand B, ProdSrc S, const int64_t* mults,
       for (int64_t i = threadIdx.x; i < nblk; i += blockDim.x) lblk[i] = 0;
     __syncthreads();
     int64_t mine = 0;
-    block_products<8, int, false, false, false, true>(S, nullptr, nullptr, b0, b1, 0, 0, true, s_rng, red,
-                                                      each_product<8>([&](int32_t r, int, int) {
+    block_products<4, int, false, false, false, true>(S, nullptr, nullptr, b0, b1, 0, 0, true, s_rng, red,
+                                                      each_product<4>([&](int32_t r, int, int) {
       if (r < 0) return;
       uint32_t h = hash_row(r, log2s);
       for (uint32_t probe = 0; probe < TS; ++probe) {
@@ -693,8 +693,8 @@ __global__ void k_count_bitmap(Operand B, ProdSrc S, const int64_t* mults, const
     for (int i = threadIdx.x; i < words; i += blockDim.x) bm[i] = 0;
     for (int i = threadIdx.x; i < blk_per_chunk; i += blockDim.x) lblk[i] = 0;
     __syncthreads();
-    block_products<8, int, false, false, false, true>(S, nullptr, nullptr, b0, b1, (int32_t)c0, (int32_t)c1, nchunks == 1, s_rng,
-                                         red, each_product<8>([&](int32_t r, int, int) {
+    block_products<4, int, false, false, false, true>(S, nullptr, nullptr, b0, b1, (int32_t)c0, (int32_t)c1, nchunks == 1, s_rng,
+                                         red, each_product<4>([&](int32_t r, int, int) {
       const uint32_t d = (uint32_t)(r - (int32_t)c0);
       if (d < (uint32_t)(c1 - c0)) atomicOr(&bm[d >> 5], 1u << (d & 31));
     }));
