@@ -1382,7 +1382,7 @@ int summary_sync(GemmPlan* P, hipStream_t st, Summary* host) {
 extern "C" void spx_default_tuning(spx_tuning* t) {
   std::memset(t, 0, sizeof(*t));
   t->tiny_max = 64;
-  t->hash_count_max = 1 << 14;
+  t->hash_count_max = 1 << 13;
   t->single_part_max = 1024;
   t->part_lds_bytes = 72 * 1024;
   t->count_threads = 256;
@@ -1391,7 +1391,7 @@ extern "C" void spx_default_tuning(spx_tuning* t) {
   t->single_threads = 256;
   t->bitmap_chunk_log2 = 0;
   t->xcd_slices = 1;
-  t->bitmap_store_mb = 16384;
+  t->bitmap_store_mb = 32768;
 }
 
 template <int SR, typename T>
