@@ -990,16 +990,9 @@ __global__ void __launch_bounds__(1024) k_numeric_parts(Operand A, Operand B, Pr
       for (int i = w0; i < w1; ++i) s += __popcll(bm[i]);
       int64_t tot;
       int64_t run = block_excl_scan(s, red, &tot);
-      // rows in rank order, straight from the bitmap
       for (int i = w0; i < w1; ++i) {
         pre[i] = (uint16_t)run;
-        uint64_t word = bm[i];
-        while (word) {
-          const int bit = __ffsll((long long)word) - 1;
-          word &= word - 1;
-          if (run < c) cir[P.off + run] = P.r0 + i * 64 + bit;
-          ++run;
-        }
+        run += __popcll(bm[i]);
       }
       if (threadIdx.x == 0 && tot != c) atomicOr(err, 8u);
       __syncthreads();
@@ -1028,7 +1021,22 @@ __global__ void __launch_bounds__(1024) k_numeric_parts(Operand A, Operand B, Pr
           block_products<8, T, SR_::kUsesA, SR_::kUsesB, false, true>(S, an, bn, b0, b1, P.r0, P.r1, full, s_rng, red, acc);
         __syncthreads();
         for (int i = threadIdx.x; i < c; i += blockDim.x) cnum[P.off + i] = vals[i];
+        __syncthreads();
       }
+      // rows in rank order: staged in the value area, then written coalesced
+      int32_t* rows = (int32_t*)vals;
+      for (int i = w0; i < w1; ++i) {
+        uint64_t word = bm[i];
+        int rk = pre[i];
+        while (word) {
+          const int bit = __ffsll((long long)word) - 1;
+          word &= word - 1;
+          if (rk < c) rows[rk] = P.r0 + i * 64 + bit;
+          ++rk;
+        }
+      }
+      __syncthreads();
+      for (int i = threadIdx.x; i < c; i += blockDim.x) cir[P.off + i] = rows[i];
       __syncthreads();
     } else {
       int p2 = 64;
