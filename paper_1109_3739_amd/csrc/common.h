@@ -164,6 +164,27 @@ __device__ __forceinline__ T block_excl_scan(T v, T* red, T* total) {
   return res;
 }
 
+// The same with one barrier: every wave adds up the totals of the waves
+// before it.  `red` must not be written again before the workgroup's next
+// barrier (callers place one between two scans).
+template <typename T>
+__device__ __forceinline__ T block_excl_scan1(T v, T* red, T* total) {
+  const int lane = lane_id();
+  const int wid = threadIdx.x / kWave;
+  const int nw = blockDim.x / kWave;
+  const T incl = wave_incl_scan(v);
+  if (lane == kWave - 1) red[wid] = incl;
+  __syncthreads();
+  T before = T(0), all = T(0);
+  for (int k = 0; k < nw; ++k) {
+    const T x = red[k];
+    if (k < wid) before += x;
+    all += x;
+  }
+  *total = all;
+  return before + incl - v;
+}
+
 // ---------------------------------------------------------------- semirings
 // mul: product of A(i,k) and B(k,j); add: combine into an accumulator;
 // lds_acc: atomic combine into LDS; ident: value of an untouched slot.

@@ -335,7 +335,7 @@ __device__ __forceinline__ void block_products(const ProdSrc& S, const T* an, co
     }
     if (!REUSE) {
       int64_t total64;
-      const int64_t ex = block_excl_scan((int64_t)mylen, red, &total64);
+      const int64_t ex = block_excl_scan1((int64_t)mylen, red, &total64);
       if ((int)threadIdx.x < nq) {
         R.pref[threadIdx.x] = (int32_t)ex;
         // windows whose first product falls in this range
@@ -638,7 +638,7 @@ __global__ void k_count_hash(Operand B, ProdSrc S, const int64_t* mults,
     }));
     __syncthreads();
     int64_t total;
-    block_excl_scan(mine, red, &total);
+    block_excl_scan1(mine, red, &total);
     if (threadIdx.x == 0) cnt[t] = total;
     if (want_blk) {
       uint32_t* dst = blkcnt + (pos - binoff[0]) * nblk;
@@ -708,7 +708,7 @@ __global__ void k_count_bitmap(Operand B, ProdSrc S, const int64_t* mults, const
       }
     }
     int64_t ctot;
-    block_excl_scan(mine, red, &ctot);
+    block_excl_scan1(mine, red, &ctot);
     const int64_t bfirst = c0 >> rbshift;
     for (int i = threadIdx.x; i < blk_per_chunk; i += blockDim.x)
       if (bfirst + i < nblk) dst[bfirst + i] = lblk[i];
@@ -989,7 +989,7 @@ __global__ void __launch_bounds__(1024) k_numeric_parts(Operand A, Operand B, Pr
       int64_t s = 0;
       for (int i = w0; i < w1; ++i) s += __popcll(bm[i]);
       int64_t tot;
-      int64_t run = block_excl_scan(s, red, &tot);
+      int64_t run = block_excl_scan1(s, red, &tot);
       for (int i = w0; i < w1; ++i) {
         pre[i] = (uint16_t)run;
         run += __popcll(bm[i]);
@@ -1098,7 +1098,7 @@ __global__ void __launch_bounds__(1024) k_numeric_parts(Operand A, Operand B, Pr
           int64_t sum = 0;
           for (int w = w0; w < w1; ++w) sum += __popcll(l1w[w]);
           int64_t ng;
-          int64_t run = block_excl_scan(sum, red, &ng);
+          int64_t run = block_excl_scan1(sum, red, &ng);
           for (int w = w0; w < w1; ++w) {
             l1p[w] = (uint16_t)run;
             run += __popcll(l1w[w]);
@@ -1121,7 +1121,7 @@ __global__ void __launch_bounds__(1024) k_numeric_parts(Operand A, Operand B, Pr
           const int w0 = threadIdx.x * per, w1 = w0 + per < p2 ? w0 + per : p2;
           int64_t sum = 0;
           for (int w = w0; w < w1; ++w) sum += __popcll(l2w[w]);
-          int64_t run = block_excl_scan(sum, red, &found);
+          int64_t run = block_excl_scan1(sum, red, &found);
           for (int w = w0; w < w1; ++w) {
             l2p[w] = (uint16_t)run;
             run += __popcll(l2w[w]);
