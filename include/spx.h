@@ -108,7 +108,7 @@ typedef struct spx_ctx {
  *                    hash count, bitmap count, multi-part and single-part
  *                    numeric kernels
  *   bitmap_chunk_log2  rows per work item of the bitmap count (log2); 0: one
- *                    chunk per row slice, at most 2^19 rows
+ *                    chunk per row slice, at most 2^18 rows
  *   xcd_slices       the row space is cut into this many slices (parts never
  *                    straddle one); workgroup w serves slice w mod xcd_slices
  *                    first, so each XCD's L2 holds one slice of A (1: off)

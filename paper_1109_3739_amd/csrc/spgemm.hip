@@ -1636,10 +1636,10 @@ extern "C" int spx_spgemm_plan(const spx_ctx* ctx, const spx_mat* A, const spx_m
     // bitmap chunks: a power of two of rows, a multiple of the row block;
     // 0 = one chunk per row slice
     int want = tune.bitmap_chunk_log2;
-    if (want <= 0) {  // auto: one chunk per row slice, at most 2^19 rows (two workgroups per CU)
+    if (want <= 0) {  // auto: one chunk per row slice, at most 2^18 rows (four workgroups per CU)
       want = 0;
       while ((1ll << want) < ceil_div(m, std::max(1, P->nslice_req))) ++want;
-      want = std::min(want, 19);
+      want = std::min(want, 18);
     }
     int clog = std::max<int>(rb, std::min<int>(want, 20));
     while (clog > rb && (1ll << (clog - 1)) >= m) --clog;
