@@ -291,16 +291,19 @@ __device__ __forceinline__ EachProduct<U, F> each_product(F f) {
   return EachProduct<U, F>{f};
 }
 
-// Range search of a window:
-//  WAVE_RUNS: each wave takes U consecutive windows per round; the range of
-//    the wave's first product (s0) is found once per round, the lanes load
-//    the next 64 range starts and a ballot counts those inside the round, so
-//    each product searches only among them (if all 64 are inside, among all
-//    ranges after s0);
-//  otherwise: windows are dealt round robin to the waves, and the window
-//    table (range of each window's first product, written at set-up) bounds
-//    the search by the ranges of the window's first product and of the next
-//    window's first product.
+// Range search of a window.  At set-up every range writes its index into
+// the window table for each window (64 products) whose first product it
+// holds (the first kWinTab windows).
+//  WAVE_RUNS: each wave takes U consecutive windows per round.  The range
+//    of the wave's first product (s0) comes from the table (else a binary
+//    search); the lanes load the next 64 range starts, and ballots give each
+//    window the ranges that start inside it, so a window inside one range
+//    needs no search.  A round inside one range skips all of this and loads
+//    consecutive entries.  (If all 64 loaded starts are inside the round,
+//    the search runs over all ranges after s0.)
+//  otherwise: windows are dealt round robin to the waves, and the table
+//    bounds each window's search by the ranges of its first product and of
+//    the next window's first product.
 // With REUSE the range list left in R by the previous call for the same
 // column and row range is used as is (the column must fit one chunk).
 template <int U, typename T, bool LOADA, bool LOADB, bool REUSE = false, bool WAVE_RUNS = false, class F>
