@@ -145,6 +145,21 @@ def extra_workloads(spx, W, torch):
     out["stage_block_nnz_c"] = int(C.nnz)
     del C
 
+    # R-MAT scale 20 times a tall-skinny Erdos-Renyi matrix (n/k = 8192, d2
+    # nonzeros per column): the multi-source BFS frontier expansion
+    dA = spx.from_host(A)
+    tall = {}
+    for d2 in (1, 10, 100, 1000, 10000, 100000):
+        F = W.erdos_renyi(A.n, A.n // 8192, d2, seed=300 + d2)
+        dF = spx.from_host(F)
+        Cf = spx.spgemm(dA, dF)
+        mults = int(np.diff(A.cp)[F.ir].sum())
+        t = time_steps(lambda: spx.spgemm(dA, dF), 5, sync)
+        tall[str(d2)] = {"ms": round(1e3 * t, 4), "gflops": round(2 * mults / t / 1e9, 3), "mults": mults,
+                         "nnz_c": int(Cf.nnz)}
+        del Cf, dF
+    out["tall_skinny_rmat20_x_er"] = tall
+
     # SpRef / SpAsgn on R-MAT scale 22, edge factor 16, int64 edge ids
     A3 = W.rmat(22, 16, seed=22, values="edge_id")
     I = W.index_vector(1 << 18, A3.m, seed=221)

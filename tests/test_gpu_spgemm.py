@@ -105,6 +105,35 @@ def test_rectangular_and_independent(spx):
     check_against_oracle(spx, A, B, "min_plus", exact=True)
 
 
+@pytest.mark.parametrize("tune", [
+    dict(tiny_max=0, hash_count_max=0),                            # every column bitmap-counted and stored
+    dict(tiny_max=0, hash_count_max=0, bitmap_chunk_log2=10),      # chunks end inside the last word
+    dict(tiny_max=0, hash_count_max=0, part_lds_bytes=24 * 1024),  # many parts per stored column
+])
+def test_stored_bitmaps_ragged_rows(spx, tune):
+    # m is not a multiple of 64 (nor of a chunk): the stored bitmaps' last word
+    # is partial; values f64 and an exact semiring
+    A = W.erdos_renyi(50_021, 300, 40, seed=31)
+    B = W.erdos_renyi(300, 200, 120, seed=32)
+    t = spx.default_tuning()
+    for k, v in tune.items():
+        setattr(t, k, v)
+    _, info = check_against_oracle(spx, A, B, "plus_times", tuning=t)
+    assert info["cols_heavy"] == 200
+    check_against_oracle(spx, A, B, "min_plus", exact=True, tuning=t)
+
+
+@pytest.mark.parametrize("d2", [1, 10, 100, 1000, 8000])
+def test_tall_skinny_frontier(spx, d2):
+    # R-MAT times a tall-skinny Erdos-Renyi matrix, n/k = 8192 (multi-source
+    # BFS frontiers of d2 vertices): from a few products per column to
+    # columns that cover most rows
+    A = W.rmat(14, 8, seed=41)
+    F = W.erdos_renyi(A.n, A.n // 8192, d2, seed=42 + d2)
+    check_against_oracle(spx, A, F, "plus_times")
+    check_against_oracle(spx, A, F, "min_plus", exact=True)
+
+
 def test_tall_hash_parts_sorted_path(spx):
     # A has more than 2^20 rows, so hash-mode parts spanning all rows take the
     # sorted path instead of the two-level rank; a shorter A takes the rank.

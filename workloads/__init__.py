@@ -98,6 +98,9 @@ def from_triples(rows, cols, vals, m: int, n: int) -> HostCsc:
 def _distinct_rows_per_column(rng, m: int, n: int, d: int) -> np.ndarray:
     if d > m:
         raise ValueError("d exceeds the number of rows")
+    if d * d > 2 * m:  # a column of d uniform draws would most likely repeat a row
+        return np.stack([np.sort(rng.choice(m, size=d, replace=False)) for _ in range(n)]) if n else \
+            np.zeros((0, d), dtype=np.int64)
     rows = rng.integers(0, m, size=(n, d), dtype=np.int64)
     rows.sort(axis=1)
     tries = 0
