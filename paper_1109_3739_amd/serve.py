@@ -213,11 +213,22 @@ class Server:
         return requests
 
 
+def _best_within(pts: List[dict], target: float) -> dict:
+    best = {}
+    for mode in ("plain", "batched"):
+        ok = [p[mode]["throughput_rps"] for p in pts if p[mode].get("p99_ms", 1e30) <= target]
+        best[mode] = max(ok) if ok else None
+    ratio = (best["batched"] / best["plain"]) if best.get("plain") and best.get("batched") else None
+    return {"p99_target_ms": target, "plain_rps": best["plain"], "batched_rps": best["batched"],
+            "batched_over_plain": round(ratio, 3) if ratio else None}
+
+
 def equal_p99_summary(points: List[dict]) -> dict:
-    """Throughput of each mode at equal tail latency.  The p99 target is the
-    plain mode's p99 at the lowest offered load above 0.6 x its saturation;
-    for each mode the best throughput among the load points whose p99 stays
-    within the target is reported."""
+    """Throughput of each mode at equal tail latency, for two p99 targets:
+    the plain mode's p99 at the lowest offered load above 0.6 x its
+    saturation (moderate load), and its p99 at the load where it reaches
+    its highest throughput (saturation).  For each target and mode, the best
+    throughput among the load points whose p99 stays within the target."""
     pts = sorted(points, key=lambda p: p["qps"])
     target = None
     for p in pts:
@@ -226,13 +237,10 @@ def equal_p99_summary(points: List[dict]) -> dict:
             break
     if target is None:
         return {}
-    best = {}
-    for mode in ("plain", "batched"):
-        ok = [p[mode]["throughput_rps"] for p in pts if p[mode].get("p99_ms", 1e30) <= target]
-        best[mode] = max(ok) if ok else None
-    ratio = (best["batched"] / best["plain"]) if best.get("plain") and best.get("batched") else None
-    return {"p99_target_ms": target, "plain_rps": best["plain"], "batched_rps": best["batched"],
-            "batched_over_plain": round(ratio, 3) if ratio else None}
+    out = _best_within(pts, target)
+    sat = max(pts, key=lambda p: p["plain"].get("throughput_rps") or 0.0)
+    out["saturation"] = _best_within(pts, sat["plain"]["p99_ms"])
+    return out
 
 
 def latency_stats(reqs: List[Request], t_first: float = 0.0) -> dict:

@@ -26,3 +26,7 @@ def test_equal_p99_summary():
     ]
     s = equal_p99_summary(pts)
     assert s["p99_target_ms"] == 5.0 and s["plain_rps"] == 160 and s["batched_rps"] == 390
+    # plain saturates at 200 rps with p99 90 ms; batched serves 390 within it
+    sat = s["saturation"]
+    assert sat["p99_target_ms"] == 90.0 and sat["plain_rps"] == 200 and sat["batched_rps"] == 390
+    assert sat["batched_over_plain"] == 1.95
