@@ -64,37 +64,46 @@ __device__ __forceinline__ int find_block(const int64_t* base, int count, int64_
   return lo;
 }
 
-// Column pointers of the concatenation: cp[c] = nnz base of block i + its own cp.
-__global__ void k_cat_cp(const BatchDesc* d, int count, const int64_t* colb, const int64_t* nzb, int64_t total,
-                         bool isB, int64_t* out) {
-  for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c <= total; c += (int64_t)gridDim.x * blockDim.x) {
-    if (c == total) {
-      out[c] = nzb[count];
-      continue;
+// Concatenation of one array of every product.  Product i is handled by the
+// workgroups with blockIdx.y == i (mod gridDim.y), which stride over its
+// elements, so no element searches for its product.
+//   kCatAIr / kCatBIr: row indices (B's rows move to block i's column range
+//   of A); kCatANum / kCatBNum: values; kCatACp / kCatBCp: column pointers,
+//   cp[c] = nnz base of block i + its own cp (the final entry is written
+//   separately).
+enum CatKind { kCatAIr, kCatBIr, kCatANum, kCatBNum, kCatACp, kCatBCp };
+
+__global__ void k_cat(const BatchDesc* d, int count, const int64_t* nzb, const int64_t* colb, const int64_t* acolb,
+                      int kind, int vb, void* out) {
+  for (int i = blockIdx.y; i < count; i += gridDim.y) {
+    const bool cp = kind == kCatACp || kind == kCatBCp;
+    const int64_t base = cp ? colb[i] : nzb[i];
+    const int64_t len = (cp ? colb[i + 1] : nzb[i + 1]) - base;
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < len; k += (int64_t)gridDim.x * blockDim.x) {
+      switch (kind) {
+        case kCatAIr: static_cast<int32_t*>(out)[base + k] = d[i].air[k]; break;
+        case kCatBIr: static_cast<int32_t*>(out)[base + k] = (int32_t)(d[i].bir[k] + acolb[i]); break;
+        case kCatANum: copy_value(d[i].anum, k, out, base + k, vb); break;
+        case kCatBNum: copy_value(d[i].bnum, k, out, base + k, vb); break;
+        case kCatACp: static_cast<int64_t*>(out)[base + k] = nzb[i] + load_ptr(d[i].acp, d[i].a_ptr_t, k); break;
+        default: static_cast<int64_t*>(out)[base + k] = nzb[i] + load_ptr(d[i].bcp, d[i].b_ptr_t, k); break;
+      }
     }
-    const int i = find_block(colb, count, c);
-    const void* cp = isB ? d[i].bcp : d[i].acp;
-    const int32_t pt = isB ? d[i].b_ptr_t : d[i].a_ptr_t;
-    out[c] = nzb[i] + load_ptr(cp, pt, c - colb[i]);
   }
 }
 
-// Row indices of the concatenation; B's rows move to block i's column range of A.
-__global__ void k_cat_ir(const BatchDesc* d, int count, const int64_t* nzb, const int64_t* acolb, int64_t total,
-                         bool isB, int32_t* out) {
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
-    const int i = find_block(nzb, count, e);
-    const int64_t k = e - nzb[i];
-    out[e] = isB ? (int32_t)(d[i].bir[k] + acolb[i]) : d[i].air[k];
-  }
+// Largest per-product length of a prefix array (count + 1 entries).
+static int64_t max_len(const std::vector<int64_t>& pre) {
+  int64_t m = 0;
+  for (size_t i = 1; i < pre.size(); ++i) m = std::max(m, pre[i] - pre[i - 1]);
+  return m;
 }
 
-__global__ void k_cat_num(const BatchDesc* d, int count, const int64_t* nzb, int64_t total, bool isB, int vb,
-                          void* out) {
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
-    const int i = find_block(nzb, count, e);
-    copy_value(isB ? d[i].bnum : d[i].anum, e - nzb[i], out, e, vb);
-  }
+static void launch_cat(BatchPlan* P, int kind, const int64_t* nzb, const int64_t* colb, int vb, void* out,
+                       int64_t max_len, hipStream_t st) {
+  const unsigned gy = (unsigned)std::min<int64_t>(P->count, 65535);
+  const unsigned gx = (unsigned)std::max<int64_t>(1, std::min<int64_t>(ceil_div(max_len, 256 * 4), 64));
+  k_cat<<<dim3(gx, gy), 256, 0, st>>>(P->desc, P->count, nzb, colb, P->acol, kind, vb, out);
 }
 
 // Per-product column pointers (relative to the product's first entry).
@@ -122,11 +131,11 @@ __global__ void k_gather_i64(const int64_t* src, const int64_t* idx, int n, int6
 static int run_exec(BatchPlan* P, int64_t* cp_pool, int32_t* ir_pool, void* num_pool, hipStream_t st) {
   const int64_t anz = P->anz_h[P->count], bnz = P->bnz_h[P->count];
   if (P->vb_a && anz > 0) {
-    k_cat_num<<<grid_for(anz, 256, 65536), 256, 0, st>>>(P->desc, P->count, P->anz, anz, false, P->vb_a, P->anum);
+    launch_cat(P, kCatANum, P->anz, P->acol, P->vb_a, P->anum, max_len(P->anz_h), st);
     SPX_HIP(hipGetLastError());
   }
   if (P->vb_b && bnz > 0) {
-    k_cat_num<<<grid_for(bnz, 256, 65536), 256, 0, st>>>(P->desc, P->count, P->bnz, bnz, true, P->vb_b, P->bnum);
+    launch_cat(P, kCatBNum, P->bnz, P->bcol, P->vb_b, P->bnum, max_len(P->bnz_h), st);
     SPX_HIP(hipGetLastError());
   }
   spx_mat C{};
@@ -213,14 +222,13 @@ extern "C" int spx_batch_plan(const spx_ctx* ctx, int32_t count, const spx_mat* 
   SPX_TRY(scr.get_n(nb + 1, &P->ccp));
   if (P->vb_a) SPX_TRY(scr.get(std::max<int64_t>(anz, 1) * P->vb_a, &P->anum));
   if (P->vb_b) SPX_TRY(scr.get(std::max<int64_t>(bnz, 1) * P->vb_b, &P->bnum));
-  k_cat_cp<<<grid_for(ka + 1, 256, 65536), 256, 0, st>>>(P->desc, count, P->acol, P->anz, ka, false, P->acp);
-  k_cat_cp<<<grid_for(nb + 1, 256, 65536), 256, 0, st>>>(P->desc, count, P->bcol, P->bnz, nb, true, P->bcp);
-  if (anz > 0) k_cat_ir<<<grid_for(anz, 256, 65536), 256, 0, st>>>(P->desc, count, P->anz, P->acol, anz, false, P->air);
-  if (bnz > 0) k_cat_ir<<<grid_for(bnz, 256, 65536), 256, 0, st>>>(P->desc, count, P->bnz, P->acol, bnz, true, P->bir);
-  if (P->vb_a && anz > 0)
-    k_cat_num<<<grid_for(anz, 256, 65536), 256, 0, st>>>(P->desc, count, P->anz, anz, false, P->vb_a, P->anum);
-  if (P->vb_b && bnz > 0)
-    k_cat_num<<<grid_for(bnz, 256, 65536), 256, 0, st>>>(P->desc, count, P->bnz, bnz, true, P->vb_b, P->bnum);
+  // patterns of the concatenated operands (values are copied by every exec)
+  launch_cat(P, kCatACp, P->anz, P->acol, 0, P->acp, max_len(P->acol_h), st);
+  launch_cat(P, kCatBCp, P->bnz, P->bcol, 0, P->bcp, max_len(P->bcol_h), st);
+  SPX_TRY(fill_i64(P->acp + ka, 1, anz, st));
+  SPX_TRY(fill_i64(P->bcp + nb, 1, bnz, st));
+  if (anz > 0) launch_cat(P, kCatAIr, P->anz, P->acol, 0, P->air, max_len(P->anz_h), st);
+  if (bnz > 0) launch_cat(P, kCatBIr, P->bnz, P->bcol, 0, P->bir, max_len(P->bnz_h), st);
   SPX_HIP(hipGetLastError());
   spx_mat Ac{}, Bc{};
   Ac.m = P->mmax;
