@@ -518,6 +518,24 @@ __device__ __forceinline__ uint64_t wave_sort_u64(uint64_t key) {
   return key;
 }
 
+// The same for 32-bit keys (one lane exchange per step instead of two).
+__device__ __forceinline__ uint32_t wave_sort_u32(uint32_t key) {
+  const int lane = lane_id();
+#pragma unroll
+  for (int k = 2; k <= kWave; k <<= 1) {
+#pragma unroll
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      const uint32_t other = __shfl_xor(key, j);
+      const bool up = (lane & k) == 0;
+      const bool lower = (lane & j) == 0;
+      const uint32_t mn = other < key ? other : key;
+      const uint32_t mx = other < key ? key : other;
+      key = (lower == up) ? mn : mx;
+    }
+  }
+  return key;
+}
+
 // Tiny columns (at most 64 products): the wave gathers every product into
 // LDS, sorts the (row, product index) keys across its lanes, and either
 // counts the distinct rows (COUNT) or sums each run of equal rows in product
@@ -571,10 +589,22 @@ __global__ void __launch_bounds__(256) k_tiny(Operand A, Operand B, const int64_
       wave_sync();
     }
     if (total > kWave) total = kWave;  // cannot happen: the bin holds columns with <= 64 products
-    uint64_t key = lane < total ? (((uint64_t)(uint32_t)s_row[w][lane]) << 32) | (uint32_t)lane : ~0ull;
-    key = wave_sort_u64(key);
-    const int32_t row = (int32_t)(key >> 32);
-    const int idx = (int)(key & 0xffffffffu);
+    // sort (row, product index): 32-bit keys when the rows leave 6 bits for
+    // the index (the count needs the rows only)
+    int32_t row;
+    int idx;
+    if (COUNT || A.m <= (1ll << 25)) {
+      const uint32_t k32 = lane < total ? (COUNT ? (uint32_t)s_row[w][lane] : ((uint32_t)s_row[w][lane] << 6) | lane)
+                                        : 0xffffffffu;
+      const uint32_t key = wave_sort_u32(k32);
+      row = COUNT ? (int32_t)key : (int32_t)(key >> 6);
+      idx = COUNT ? 0 : (int)(key & 63u);
+    } else {
+      uint64_t key = lane < total ? (((uint64_t)(uint32_t)s_row[w][lane]) << 32) | (uint32_t)lane : ~0ull;
+      key = wave_sort_u64(key);
+      row = (int32_t)(key >> 32);
+      idx = (int)(key & 0xffffffffu);
+    }
     const int32_t prev = __shfl_up(row, 1);
     const bool valid = lane < total;
     const bool head = valid && (lane == 0 || prev != row);

@@ -134,6 +134,18 @@ def test_tall_skinny_frontier(spx, d2):
     check_against_oracle(spx, A, F, "min_plus", exact=True)
 
 
+def test_tiny_columns_wide_row_ids(spx):
+    # tiny columns whose row ids need more than 25 bits: the wave sort takes
+    # 64-bit (row, index) keys instead of 32-bit ones
+    A = W.erdos_renyi(40_000_000, 64, 4, seed=51)
+    B = W.erdos_renyi(64, 100, 8, seed=52)
+    for sr, exact in (("plus_times", False), ("min_plus", True)):
+        C, info = gemm(spx, A, B, sr)
+        assert info["cols_tiny"] == 100
+        ref = oracle.spgemm_csc(A, B, sr, nthreads=1)
+        assert_same_csc(C.to_host_csc(), ref, exact_values=exact, what=sr)
+
+
 def test_tall_hash_parts_sorted_path(spx):
     # A has more than 2^20 rows, so hash-mode parts spanning all rows take the
     # sorted path instead of the two-level rank; a shorter A takes the rank.
