@@ -2,12 +2,16 @@
 //
 // The batch is the single product  [A_1 A_2 ... A_n] * blockdiag(B_1, ..., B_n)
 // = [C_1 C_2 ... C_n]: column j of block i of the right operand only has
-// rows inside block i's range, so it only meets the columns of A_i.  The
+// rows inside block i's range, so it only meets the columns of A_i.  Left
+// operands passed more than once (the same arrays) enter the concatenation
+// once, and every B_i that uses them points at that block.  The
 // concatenated operands are built once by the plan (patterns) and refreshed
 // by every exec (values); the symbolic phase, the binning and the persistent
 // numeric launches of the ordinary SpGEMM then run over the work items of
 // all products together.  C_i are views into caller-owned pools.
 #include <algorithm>
+#include <map>
+#include <tuple>
 #include <cstring>
 #include <vector>
 
@@ -34,11 +38,13 @@ struct BatchPlan : spx_plan {
     if (gemm) spx_plan_destroy(gemm);
   }
   int32_t count = 0;
+  int32_t count_a = 0;  // distinct left operands
   int32_t vt_c = 0;
   int vb_a = 0, vb_b = 0, vb_c = 0;
   std::vector<int64_t> m_h, n_h, acol_h, anz_h, bcol_h, bnz_h, cnz_h;  // bases, count+1 entries
   BatchDesc* desc = nullptr;
   int64_t *acol = nullptr, *anz = nullptr, *bcol = nullptr, *bnz = nullptr;
+  int64_t* acolp = nullptr;  // per product: first column of its left operand's block
   int64_t* acp = nullptr;
   int32_t* air = nullptr;
   void* anum = nullptr;
@@ -101,9 +107,10 @@ static int64_t max_len(const std::vector<int64_t>& pre) {
 
 static void launch_cat(BatchPlan* P, int kind, const int64_t* nzb, const int64_t* colb, int vb, void* out,
                        int64_t max_len, hipStream_t st) {
-  const unsigned gy = (unsigned)std::min<int64_t>(P->count, 65535);
+  const int n = (kind == kCatAIr || kind == kCatANum || kind == kCatACp) ? P->count_a : P->count;
+  const unsigned gy = (unsigned)std::min<int64_t>(n, 65535);
   const unsigned gx = (unsigned)std::max<int64_t>(1, std::min<int64_t>(ceil_div(max_len, 256 * 4), 64));
-  k_cat<<<dim3(gx, gy), 256, 0, st>>>(P->desc, P->count, nzb, colb, P->acol, kind, vb, out);
+  k_cat<<<dim3(gx, gy), 256, 0, st>>>(P->desc, n, nzb, colb, P->acolp, kind, vb, out);
 }
 
 // Per-product column pointers (relative to the product's first entry).
@@ -129,7 +136,7 @@ __global__ void k_gather_i64(const int64_t* src, const int64_t* idx, int n, int6
 }
 
 static int run_exec(BatchPlan* P, int64_t* cp_pool, int32_t* ir_pool, void* num_pool, hipStream_t st) {
-  const int64_t anz = P->anz_h[P->count], bnz = P->bnz_h[P->count];
+  const int64_t anz = P->anz_h[P->count_a], bnz = P->bnz_h[P->count];
   if (P->vb_a && anz > 0) {
     launch_cat(P, kCatANum, P->anz, P->acol, P->vb_a, P->anum, max_len(P->anz_h), st);
     SPX_HIP(hipGetLastError());
@@ -194,25 +201,54 @@ extern "C" int spx_batch_plan(const spx_ctx* ctx, int32_t count, const spx_mat* 
   P->vb_a = value_size(A[0].val_t);
   P->vb_b = value_size(B[0].val_t);
   for (auto* v : {&P->m_h, &P->n_h}) v->resize(count);
-  for (auto* v : {&P->acol_h, &P->anz_h, &P->bcol_h, &P->bnz_h, &P->cnz_h}) v->assign(count + 1, 0);
+  for (auto* v : {&P->bcol_h, &P->bnz_h, &P->cnz_h}) v->assign(count + 1, 0);
+  // distinct left operands (entry u of the descriptors holds the u-th one;
+  // the B fields of entry i hold product i)
   std::vector<BatchDesc> hd(count);
+  std::vector<int64_t> acolp_h(count);
+  std::map<std::tuple<const void*, const void*, const void*, int64_t, int64_t, int64_t, int32_t>, int> seen;
+  P->acol_h.assign(1, 0);
+  P->anz_h.assign(1, 0);
   for (int i = 0; i < count; ++i) {
     P->m_h[i] = A[i].m;
     P->n_h[i] = B[i].n;
     P->mmax = std::max(P->mmax, A[i].m);
-    P->acol_h[i + 1] = P->acol_h[i] + A[i].n;
-    P->anz_h[i + 1] = P->anz_h[i] + A[i].nnz;
+    const auto key = std::make_tuple((const void*)A[i].cp, (const void*)A[i].ir, (const void*)A[i].num, A[i].m,
+                                     A[i].n, A[i].nnz, A[i].ptr_t);
+    auto it = seen.find(key);
+    int u;
+    if (it == seen.end()) {
+      u = (int)seen.size();
+      seen.emplace(key, u);
+      hd[u].acp = A[i].cp;
+      hd[u].air = A[i].ir;
+      hd[u].anum = A[i].num;
+      hd[u].a_ptr_t = A[i].ptr_t;
+      P->acol_h.push_back(P->acol_h.back() + A[i].n);
+      P->anz_h.push_back(P->anz_h.back() + A[i].nnz);
+    } else {
+      u = it->second;
+    }
+    acolp_h[i] = P->acol_h[u];
     P->bcol_h[i + 1] = P->bcol_h[i] + B[i].n;
     P->bnz_h[i + 1] = P->bnz_h[i] + B[i].nnz;
-    hd[i] = BatchDesc{A[i].cp, A[i].ir, A[i].num, B[i].cp, B[i].ir, B[i].num, A[i].ptr_t, B[i].ptr_t};
+    hd[i].bcp = B[i].cp;
+    hd[i].bir = B[i].ir;
+    hd[i].bnum = B[i].num;
+    hd[i].b_ptr_t = B[i].ptr_t;
   }
-  const int64_t ka = P->acol_h[count], anz = P->anz_h[count], nb = P->bcol_h[count], bnz = P->bnz_h[count];
+  P->count_a = (int32_t)seen.size();
+  const int na = P->count_a;
+  const int64_t ka = P->acol_h[na], anz = P->anz_h[na], nb = P->bcol_h[count], bnz = P->bnz_h[count];
   if (ka >= (1ll << 31) || nb >= (1ll << 31)) return fail(SPX_EUNSUPPORTED, "batch too large (2^31 columns)");
   SPX_TRY(scr.get_n(count, &P->desc));
-  for (auto* pp : {&P->acol, &P->anz, &P->bcol, &P->bnz}) SPX_TRY(scr.get_n(count + 1, pp));
+  for (auto* pp : {&P->acol, &P->anz}) SPX_TRY(scr.get_n(na + 1, pp));
+  for (auto* pp : {&P->bcol, &P->bnz}) SPX_TRY(scr.get_n(count + 1, pp));
+  SPX_TRY(scr.get_n(count, &P->acolp));
   SPX_HIP(hipMemcpyAsync(P->desc, hd.data(), sizeof(BatchDesc) * count, hipMemcpyHostToDevice, st));
-  SPX_HIP(hipMemcpyAsync(P->acol, P->acol_h.data(), 8 * (count + 1), hipMemcpyHostToDevice, st));
-  SPX_HIP(hipMemcpyAsync(P->anz, P->anz_h.data(), 8 * (count + 1), hipMemcpyHostToDevice, st));
+  SPX_HIP(hipMemcpyAsync(P->acol, P->acol_h.data(), 8 * (na + 1), hipMemcpyHostToDevice, st));
+  SPX_HIP(hipMemcpyAsync(P->anz, P->anz_h.data(), 8 * (na + 1), hipMemcpyHostToDevice, st));
+  SPX_HIP(hipMemcpyAsync(P->acolp, acolp_h.data(), 8 * count, hipMemcpyHostToDevice, st));
   SPX_HIP(hipMemcpyAsync(P->bcol, P->bcol_h.data(), 8 * (count + 1), hipMemcpyHostToDevice, st));
   SPX_HIP(hipMemcpyAsync(P->bnz, P->bnz_h.data(), 8 * (count + 1), hipMemcpyHostToDevice, st));
   SPX_TRY(scr.get_n(ka + 1, &P->acp));

@@ -536,97 +536,151 @@ __device__ __forceinline__ uint32_t wave_sort_u32(uint32_t key) {
   return key;
 }
 
-// Tiny columns (at most 64 products): the wave gathers every product into
-// LDS, sorts the (row, product index) keys across its lanes, and either
-// counts the distinct rows (COUNT) or sums each run of equal rows in product
-// order -- the order of Algorithm 1 -- and writes the column (!COUNT).
-template <int SR, typename T, bool COUNT>
-__global__ void __launch_bounds__(256) k_tiny(Operand A, Operand B, const int64_t* bq_a0, const int32_t* bq_alen,
-                                              const int32_t* list, const int64_t* binoff, int64_t* cnt,
-                                              const int64_t* off, int32_t* cir, T* cnum) {
+// Group-wide helpers over G lanes: the whole wave (G = 64) or one of its
+// aligned halves (G = 32); shuffles stay inside the group.
+template <int G>
+__device__ __forceinline__ int group_incl_scan(int v, int gl) {
+#pragma unroll
+  for (int d = 1; d < G; d <<= 1) {
+    const int t = __shfl_up(v, d, G);
+    if (gl >= d) v += t;
+  }
+  return v;
+}
+
+template <int G, typename K>
+__device__ __forceinline__ K group_sort(K key, int gl) {  // ascending bitonic sort, one key per lane
+#pragma unroll
+  for (int k = 2; k <= G; k <<= 1) {
+#pragma unroll
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      const K other = __shfl_xor(key, j, G);
+      const bool up = (gl & k) == 0;
+      const bool lower = (gl & j) == 0;
+      const K mn = other < key ? other : key;
+      const K mx = other < key ? key : other;
+      key = (lower == up) ? mn : mx;
+    }
+  }
+  return key;
+}
+
+// One tiny column (at most G products) in a group of G lanes: the group
+// gathers every product into LDS, sorts the (row, product index) keys, and
+// either counts the distinct rows (COUNT) or sums each run of equal rows in
+// product order -- the order of Algorithm 1 -- and writes the column.
+template <int G, int SR, typename T, bool COUNT>
+__device__ __forceinline__ void tiny_column(const Operand& A, const Operand& B, const int64_t* bq_a0,
+                                            const int32_t* bq_alen, int32_t t, int64_t* cnt, const int64_t* off,
+                                            int32_t* cir, T* cnum, int32_t* s_row, int32_t* s_aux, T* s_val) {
   using S = Semiring<SR, T>;
   constexpr bool kVal = SR != SPX_OR_AND;
+  const int lane = lane_id();
+  const int gl = lane & (G - 1);
+  const int gb = lane & ~(G - 1);
+  s_row += gb;
+  s_aux += gb;
+  s_val += gb;
+  const int64_t b0 = slot_begin(B, t), b1 = slot_begin(B, t + 1);
+  int total = 0;
+  for (int64_t qc = b0; qc < b1; qc += G) {
+    const int64_t q = qc + gl;
+    const int al = q < b1 ? bq_alen[q] : 0;
+    const int incl = group_incl_scan<G>(al, gl);
+    const int excl = incl - al;
+    const int ctot = __shfl(incl, G - 1, G);
+    if (ctot == 0) continue;
+    s_aux[gl] = -1;
+    wave_sync();
+    if (al > 0 && excl < G) s_aux[excl] = gl;
+    wave_sync();
+    int o = s_aux[gl];
+#pragma unroll
+    for (int d = 1; d < G; d <<= 1) {
+      const int u = __shfl_up(o, d, G);
+      if (gl >= d && u > o) o = u;
+    }
+    const int ostart = __shfl(excl, o < 0 ? 0 : o, G);
+    if (gl < ctot && total + gl < G) {
+      const int64_t qq = qc + o;
+      const int64_t e = bq_a0[qq] + (gl - ostart);
+      s_row[total + gl] = A.ir[e];
+      if constexpr (kVal) {
+        const T* an = (const T*)A.num;
+        const T* bn = (const T*)B.num;
+        const T a = S::kUsesA ? an[e] : T(0);
+        const T bv = S::kUsesB ? bn[qq] : T(0);
+        s_val[total + gl] = S::mul(a, bv);
+      }
+    }
+    total += ctot;
+    wave_sync();
+  }
+  if (total > G) total = G;  // cannot happen: the caller checked the column's products
+  // sort (row, product index): 32-bit keys when the rows leave 6 bits for
+  // the index (the count needs the rows only)
+  int32_t row;
+  int idx;
+  if (COUNT || A.m <= (1ll << 25)) {
+    const uint32_t k32 = gl < total ? (COUNT ? (uint32_t)s_row[gl] : ((uint32_t)s_row[gl] << 6) | gl) : 0xffffffffu;
+    const uint32_t key = group_sort<G, uint32_t>(k32, gl);
+    row = COUNT ? (int32_t)key : (int32_t)(key >> 6);
+    idx = COUNT ? 0 : (int)(key & 63u);
+  } else {
+    const uint64_t k64 = gl < total ? (((uint64_t)(uint32_t)s_row[gl]) << 32) | (uint32_t)gl : ~0ull;
+    const uint64_t key = group_sort<G, uint64_t>(k64, gl);
+    row = (int32_t)(key >> 32);
+    idx = (int)(key & 0xffffffffu);
+  }
+  const int32_t prev = __shfl_up(row, 1, G);
+  const bool valid = gl < total;
+  const bool head = valid && (gl == 0 || prev != row);
+  const uint64_t gmask = G == 64 ? ~0ull : (0xffffffffull << gb);
+  const uint64_t hm = __ballot(head) & gmask;
+  if (COUNT) {
+    if (gl == 0) cnt[t] = __popcll(hm);
+  } else {
+    wave_sync();
+    s_row[gl] = row;
+    s_aux[gl] = idx;
+    wave_sync();
+    if (head) {
+      const int64_t o = off[t] + __popcll(hm & lanemask_lt());
+      cir[o] = row;
+      if constexpr (kVal) {
+        T acc = s_val[idx];
+        for (int l2 = gl + 1; l2 < total && s_row[l2] == row; ++l2) acc = S::add(acc, s_val[s_aux[l2]]);
+        cnum[o] = acc;
+      }
+    }
+  }
+  wave_sync();
+}
+
+// Tiny columns (at most 64 products), one wave per pair of consecutive
+// columns of the bin: two columns of at most 32 products each share the
+// wave (one per half), otherwise they are done one after the other.
+template <int SR, typename T, bool COUNT>
+__global__ void __launch_bounds__(256) k_tiny(Operand A, Operand B, const int64_t* bq_a0, const int32_t* bq_alen,
+                                              const int64_t* mults, const int32_t* list, const int64_t* binoff,
+                                              int64_t* cnt, const int64_t* off, int32_t* cir, T* cnum) {
   __shared__ int32_t s_row[4][kWave];
   __shared__ int32_t s_aux[4][kWave];
   __shared__ T s_val[4][kWave];
   const int w = threadIdx.x / kWave, lane = lane_id();
   const int64_t beg = binoff[kBinTiny], end = binoff[kBinTiny + 1];
-  for (int64_t pos = beg + (int64_t)blockIdx.x * 4 + w; pos < end; pos += (int64_t)gridDim.x * 4) {
-    const int32_t t = list[pos];
-    const int64_t b0 = slot_begin(B, t), b1 = slot_begin(B, t + 1);
-    int total = 0;
-    for (int64_t qc = b0; qc < b1; qc += kWave) {
-      const int64_t q = qc + lane;
-      const int al = q < b1 ? bq_alen[q] : 0;
-      const int incl = wave_incl_scan(al);
-      const int excl = incl - al;
-      const int ctot = __shfl(incl, kWave - 1);
-      if (ctot == 0) continue;
-      s_aux[w][lane] = -1;
-      wave_sync();
-      if (al > 0 && excl < kWave) s_aux[w][excl] = lane;
-      wave_sync();
-      int o = s_aux[w][lane];
-#pragma unroll
-      for (int d = 1; d < kWave; d <<= 1) {
-        const int u = __shfl_up(o, d);
-        if (lane >= d && u > o) o = u;
-      }
-      const int ostart = __shfl(excl, o < 0 ? 0 : o);
-      if (lane < ctot && total + lane < kWave) {
-        const int64_t qq = qc + o;
-        const int64_t e = bq_a0[qq] + (lane - ostart);
-        s_row[w][total + lane] = A.ir[e];
-        if constexpr (kVal) {
-          const T* an = (const T*)A.num;
-          const T* bn = (const T*)B.num;
-          const T a = S::kUsesA ? an[e] : T(0);
-          const T bv = S::kUsesB ? bn[qq] : T(0);
-          s_val[w][total + lane] = S::mul(a, bv);
-        }
-      }
-      total += ctot;
-      wave_sync();
-    }
-    if (total > kWave) total = kWave;  // cannot happen: the bin holds columns with <= 64 products
-    // sort (row, product index): 32-bit keys when the rows leave 6 bits for
-    // the index (the count needs the rows only)
-    int32_t row;
-    int idx;
-    if (COUNT || A.m <= (1ll << 25)) {
-      const uint32_t k32 = lane < total ? (COUNT ? (uint32_t)s_row[w][lane] : ((uint32_t)s_row[w][lane] << 6) | lane)
-                                        : 0xffffffffu;
-      const uint32_t key = wave_sort_u32(k32);
-      row = COUNT ? (int32_t)key : (int32_t)(key >> 6);
-      idx = COUNT ? 0 : (int)(key & 63u);
+  for (int64_t pos = beg + ((int64_t)blockIdx.x * 4 + w) * 2; pos < end; pos += (int64_t)gridDim.x * 8) {
+    const int32_t t0 = list[pos];
+    const bool has1 = pos + 1 < end;
+    const int32_t t1 = has1 ? list[pos + 1] : 0;
+    if (has1 && mults[t0] <= 32 && mults[t1] <= 32) {
+      tiny_column<32, SR, T, COUNT>(A, B, bq_a0, bq_alen, lane < 32 ? t0 : t1, cnt, off, cir, cnum, s_row[w], s_aux[w],
+                                    s_val[w]);
     } else {
-      uint64_t key = lane < total ? (((uint64_t)(uint32_t)s_row[w][lane]) << 32) | (uint32_t)lane : ~0ull;
-      key = wave_sort_u64(key);
-      row = (int32_t)(key >> 32);
-      idx = (int)(key & 0xffffffffu);
+      tiny_column<64, SR, T, COUNT>(A, B, bq_a0, bq_alen, t0, cnt, off, cir, cnum, s_row[w], s_aux[w], s_val[w]);
+      if (has1)
+        tiny_column<64, SR, T, COUNT>(A, B, bq_a0, bq_alen, t1, cnt, off, cir, cnum, s_row[w], s_aux[w], s_val[w]);
     }
-    const int32_t prev = __shfl_up(row, 1);
-    const bool valid = lane < total;
-    const bool head = valid && (lane == 0 || prev != row);
-    const uint64_t hm = __ballot(head);
-    if (COUNT) {
-      if (lane == 0) cnt[t] = __popcll(hm);
-    } else {
-      wave_sync();
-      s_row[w][lane] = row;
-      s_aux[w][lane] = idx;
-      wave_sync();
-      if (head) {
-        const int64_t o = off[t] + __popcll(hm & lanemask_lt());
-        cir[o] = row;
-        if constexpr (kVal) {
-          T acc = s_val[w][idx];
-          for (int l2 = lane + 1; l2 < total && s_row[w][l2] == row; ++l2) acc = S::add(acc, s_val[w][s_aux[w][l2]]);
-          cnum[o] = acc;
-        }
-      }
-    }
-    wave_sync();
   }
 }
 
@@ -1464,8 +1518,8 @@ static int launch_numeric(GemmPlan* P, spx_mat* C, hipStream_t st) {
   P->mark(kEvParts, st);
   const int64_t ntiny = P->binoff_h[kBinTiny + 1] - P->binoff_h[kBinTiny];
   if (ntiny > 0) {
-    hipLaunchKernelGGL((k_tiny<SR, T, false>), dim3(grid_for(ntiny, 4, (int64_t)cus * 16)), dim3(256), 0, st, P->A,
-                       P->B, P->bq_a0, P->bq_alen, P->list, P->binoff, P->cnt, P->off, cir, cnum);
+    hipLaunchKernelGGL((k_tiny<SR, T, false>), dim3(grid_for(ntiny, 8, (int64_t)cus * 16)), dim3(256), 0, st, P->A,
+                       P->B, P->bq_a0, P->bq_alen, P->mults_d, P->list, P->binoff, P->cnt, P->off, cir, cnum);
     SPX_HIP(hipGetLastError());
   }
   P->mark(kEvTiny, st);
@@ -1649,8 +1703,8 @@ extern "C" int spx_spgemm_plan(const spx_ctx* ctx, const spx_mat* A, const spx_m
   // exact counts
   const int64_t ntiny = bo[kBinTiny + 1] - bo[kBinTiny];
   if (ntiny > 0) {
-    k_tiny<SPX_OR_AND, float, true><<<grid_for(ntiny, 4, (int64_t)cus * 16), 256, 0, st>>>(
-        P->A, P->B, P->bq_a0, P->bq_alen, P->list, P->binoff, P->cnt, nullptr, nullptr, nullptr);
+    k_tiny<SPX_OR_AND, float, true><<<grid_for(ntiny, 8, (int64_t)cus * 16), 256, 0, st>>>(
+        P->A, P->B, P->bq_a0, P->bq_alen, P->mults_d, P->list, P->binoff, P->cnt, nullptr, nullptr, nullptr);
     SPX_HIP(hipGetLastError());
   }
   for (int b = kBinHash0; b < kBinTiny; ++b) {

@@ -39,6 +39,23 @@ def test_batch_mixed_products_match_oracle_and_single(spx):
         assert np.array_equal(single.cp, host(C).cp) and np.array_equal(single.ir, host(C).ir)
 
 
+def test_batch_repeated_left_operands(spx):
+    # the same left operand (same device arrays) in several products enters
+    # the concatenation once; every product still gets its own result
+    A1 = W.rmat(10, 8, seed=61)
+    A2 = W.erdos_renyi(1024, 1024, 5, seed=62)
+    dA1, dA2 = spx.from_host(A1), spx.from_host(A2)
+    Bs = [W.erdos_renyi(1024, int(n), d, seed=70 + k) for k, (n, d) in enumerate([(300, 3), (50, 9), (700, 1),
+                                                                                     (1, 4), (256, 6), (900, 2)])]
+    order = [dA1, dA2, dA1, dA1, dA2, dA1]
+    hostA = [A1, A2, A1, A1, A2, A1]
+    dB = [spx.from_host(b) for b in Bs]
+    for sr, exact in (("plus_times", False), ("min_plus", True)):
+        Cs = spx.batch_spgemm(order, dB, sr)
+        for i, (A, B, C) in enumerate(zip(hostA, Bs, Cs)):
+            assert_same_csc(host(C), oracle.spgemm_csc(A, B, sr), exact_values=exact, what=f"{sr} product {i}")
+
+
 @pytest.mark.parametrize("semiring", ["min_plus", "or_and"])
 def test_batch_other_semirings(spx, semiring):
     As = [W.rmat(9, 8, seed=s) for s in range(5)]
