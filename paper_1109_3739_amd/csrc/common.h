@@ -64,9 +64,14 @@ class Scratch {
   hipStream_t stream() const { return stream_; }
 
  private:
+  static constexpr size_t kArenaSmall = 256 << 10;  // requests up to this size share blocks
+  static constexpr size_t kArenaBlock = 2 << 20;
+  int raw_alloc(size_t bytes, void** out);
   spx_ctx ctx_;
   hipStream_t stream_;
   std::vector<void*> bufs_;
+  char* arena_ = nullptr;
+  size_t arena_used_ = 0, arena_size_ = 0;
 };
 
 inline hipStream_t stream_of(const spx_ctx* ctx) { return ctx ? (hipStream_t)ctx->stream : (hipStream_t)0; }

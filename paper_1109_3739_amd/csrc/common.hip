@@ -18,10 +18,7 @@ Scratch::Scratch(const spx_ctx* ctx) : stream_(stream_of(ctx)) {
 
 Scratch::~Scratch() { release_all(); }
 
-int Scratch::get(size_t bytes, void** out) {
-  *out = nullptr;
-  if (bytes == 0) bytes = 16;
-  bytes = (bytes + 255) & ~(size_t)255;
+int Scratch::raw_alloc(size_t bytes, void** out) {
   void* p = nullptr;
   if (ctx_.alloc) {
     p = ctx_.alloc(bytes, ctx_.user);
@@ -37,6 +34,25 @@ int Scratch::get(size_t bytes, void** out) {
   return SPX_OK;
 }
 
+int Scratch::get(size_t bytes, void** out) {
+  *out = nullptr;
+  if (bytes == 0) bytes = 16;
+  bytes = (bytes + 255) & ~(size_t)255;
+  if (bytes > kArenaSmall) return raw_alloc(bytes, out);
+  // small buffers are cut from shared blocks (one allocation call per block)
+  if (arena_used_ + bytes > arena_size_) {
+    void* blk = nullptr;
+    const int rc = raw_alloc(kArenaBlock, &blk);
+    if (rc != SPX_OK) return rc;
+    arena_ = static_cast<char*>(blk);
+    arena_used_ = 0;
+    arena_size_ = kArenaBlock;
+  }
+  *out = arena_ + arena_used_;
+  arena_used_ += bytes;
+  return SPX_OK;
+}
+
 void Scratch::release_all() {
   for (void* p : bufs_) {
     if (ctx_.alloc) {
@@ -46,6 +62,8 @@ void Scratch::release_all() {
     }
   }
   bufs_.clear();
+  arena_ = nullptr;
+  arena_used_ = arena_size_ = 0;
 }
 
 int device_cu_count() {
