@@ -19,6 +19,13 @@
 //     with the subtraction replaced by an elementwise mask that drops the
 //     pattern of A(I,J)); repeated indices resolved so that the last
 //     occurrence wins, evaluated by direct loops.
+//   * Extend-add A(I,J) = A(I,J) + B: SpAsgn without the S A T term
+//     (Section 4.1), i.e. C = A + R B Q.  R and Q are the selection
+//     matrices of SpAsgn, so a repeated index makes several B entries land
+//     on one position, where the semiring sum combines them.  Evaluated by
+//     direct loops: each output value starts from A's value (if stored) and
+//     adds the landing B values in B's storage order (column q ascending,
+//     then row p ascending).
 //   * CSC -> DCSC compression (Section 3.2): keep only the nonempty columns,
 //     with JC listing their ids.
 //
@@ -139,6 +146,51 @@ int spgemm_typed(int sr, int64_t m, const int64_t* acp, const int32_t* air, cons
     case SELECT2ND: spgemm_run<T, Select2nd<T>>(m, acp, air, a, bcp, bir, b, ncols, cols, counts, offs, cir, c, nthreads); return 0;
     case SELECT1ST: spgemm_run<T, Select1st<T>>(m, acp, air, a, bcp, bir, b, ncols, cols, counts, offs, cir, c, nthreads); return 0;
     default: return -1;
+  }
+}
+
+// ---- Extend-add by direct loops ---------------------------------------------
+// One column j of C = A + R B Q: the stored A(:,j) entries, then every stored
+// B(p,q) with J(q) = j in B's storage order, are listed with their target row;
+// a stable sort by row keeps that order among entries of one row, and each
+// run of one row is folded left to right with the semiring sum `Add`.
+template <typename T, typename Add>
+void extend_add_typed(int64_t m, int64_t n, const int64_t* acp, const int32_t* air, const T* anum,
+                      const int32_t* I, const std::vector<std::vector<int64_t>>& qs_of, const int64_t* bcp,
+                      const int32_t* bir, const T* bnum, int64_t* counts, const int64_t* offs, int32_t* cir,
+                      T* cnum, int nthreads) {
+  (void)m;
+#pragma omp parallel num_threads(nthreads)
+  {
+    std::vector<std::pair<int32_t, int64_t>> col;  // (row, source): >= 0 A position, < 0 B position -(e+1)
+#pragma omp for schedule(dynamic, 256)
+    for (int64_t j = 0; j < n; ++j) {
+      col.clear();
+      for (int64_t e = acp[j]; e < acp[j + 1]; ++e) col.emplace_back(air[e], e);
+      for (int64_t q : qs_of[j])
+        for (int64_t e = bcp[q]; e < bcp[q + 1]; ++e) col.emplace_back(I[bir[e]], -(e + 1));
+      std::stable_sort(col.begin(), col.end(),
+                       [](const std::pair<int32_t, int64_t>& x, const std::pair<int32_t, int64_t>& y) {
+                         return x.first < y.first;
+                       });
+      int64_t out = 0;
+      for (size_t t = 0; t < col.size();) {
+        size_t u = t + 1;
+        while (u < col.size() && col[u].first == col[t].first) ++u;
+        if (cir) {
+          cir[offs[j] + out] = col[t].first;
+          if (cnum) {
+            auto value = [&](int64_t s) { return s >= 0 ? anum[s] : bnum[-s - 1]; };
+            T acc = value(col[t].second);
+            for (size_t k = t + 1; k < u; ++k) acc = Add::add(acc, value(col[k].second));
+            cnum[offs[j] + out] = acc;
+          }
+        }
+        ++out;
+        t = u;
+      }
+      if (counts) counts[j] = out;
+    }
   }
 }
 
@@ -270,6 +322,60 @@ int oracle_spasgn(int64_t m, int64_t n, const int64_t* acp, const int32_t* air, 
     }
   }
   return 0;
+}
+
+// ---- Extend-add C = A + R B Q (Section 4.1, SpAsgn without S A T) ----------
+// Semiring `sr` chooses the sum: + for PLUS_TIMES, min for MIN_PLUS,
+// SELECT2ND and SELECT1ST; OR_AND or vt = BOOL give the pattern only.
+// counts[j] = nnz(C(:,j)); the fill pass (offs, cir, cnum non-NULL) writes
+// rows ascending.  Returns -1 for an index out of range.
+int oracle_extend_add(int sr, int vt, int64_t m, int64_t n, const int64_t* acp, const int32_t* air,
+                      const void* anum, int64_t lenI, const int32_t* I, int64_t lenJ, const int32_t* J,
+                      const int64_t* bcp, const int32_t* bir, const void* bnum, int64_t* counts,
+                      const int64_t* offs, int32_t* cir, void* cnum, int nthreads) {
+  for (int64_t p = 0; p < lenI; ++p)
+    if (I[p] < 0 || I[p] >= m) return -1;
+  std::vector<std::vector<int64_t>> qs_of((size_t)n);
+  for (int64_t q = 0; q < lenJ; ++q) {
+    if (J[q] < 0 || J[q] >= n) return -1;
+    qs_of[J[q]].push_back(q);
+  }
+  if (nthreads < 1) nthreads = 1;
+  if (sr == OR_AND || vt == BOOL) {
+    extend_add_typed<double, PlusTimes<double>>(m, n, acp, air, nullptr, I, qs_of, bcp, bir, nullptr, counts,
+                                                offs, cir, nullptr, nthreads);
+    return 0;
+  }
+  const bool plus = sr == PLUS_TIMES;
+  switch (vt) {
+    case F32:
+      if (plus)
+        extend_add_typed<float, PlusTimes<float>>(m, n, acp, air, (const float*)anum, I, qs_of, bcp, bir,
+                                                  (const float*)bnum, counts, offs, cir, (float*)cnum, nthreads);
+      else
+        extend_add_typed<float, MinPlus<float>>(m, n, acp, air, (const float*)anum, I, qs_of, bcp, bir,
+                                                (const float*)bnum, counts, offs, cir, (float*)cnum, nthreads);
+      return 0;
+    case F64:
+      if (plus)
+        extend_add_typed<double, PlusTimes<double>>(m, n, acp, air, (const double*)anum, I, qs_of, bcp, bir,
+                                                    (const double*)bnum, counts, offs, cir, (double*)cnum, nthreads);
+      else
+        extend_add_typed<double, MinPlus<double>>(m, n, acp, air, (const double*)anum, I, qs_of, bcp, bir,
+                                                  (const double*)bnum, counts, offs, cir, (double*)cnum, nthreads);
+      return 0;
+    case I64:
+      if (plus)
+        extend_add_typed<int64_t, PlusTimes<int64_t>>(m, n, acp, air, (const int64_t*)anum, I, qs_of, bcp, bir,
+                                                      (const int64_t*)bnum, counts, offs, cir, (int64_t*)cnum,
+                                                      nthreads);
+      else
+        extend_add_typed<int64_t, MinPlus<int64_t>>(m, n, acp, air, (const int64_t*)anum, I, qs_of, bcp, bir,
+                                                    (const int64_t*)bnum, counts, offs, cir, (int64_t*)cnum,
+                                                    nthreads);
+      return 0;
+    default: return -2;
+  }
 }
 
 // ---- CSC -> DCSC (Section 3.2) -----------------------------------------------

@@ -316,6 +316,120 @@ def test_spasgn_roundtrips():
     assert np.array_equal(E.ir, A.ir) and np.array_equal(E.num, A.num)
 
 
+# ---------------------------------------------------------------- extend-add
+def selection_matrices(I, J, m, n):
+    """Dense R (m x len(I)) and Q (len(J) x n) with R[I(p), p] = Q[q, J(q)] = 1."""
+    R = np.zeros((m, I.size))
+    R[I, np.arange(I.size)] = 1
+    Q = np.zeros((J.size, n))
+    Q[np.arange(J.size), J] = 1
+    return R, Q
+
+
+@pytest.mark.parametrize("dtype", [np.int64, np.float64])
+def test_extend_add_vs_dense_selection_product(dtype):
+    # C = A + R B Q with repeated indices: the dense product sums every B
+    # value that lands on one position.  Positive integer values keep every
+    # stored entry nonzero, so the dense pattern is the structural one.
+    rng = np.random.default_rng(41)
+    for trial in range(10):
+        m, n = int(rng.integers(1, 25)), int(rng.integers(1, 25))
+        A = rand_csc(rng, m, n, 0.3, dtype, lo=1, hi=9)
+        if dtype == np.int64:
+            A.num = np.abs(A.num) + 1
+        I = rng.integers(0, m, size=int(rng.integers(0, 15))).astype(np.int32)
+        J = rng.integers(0, n, size=int(rng.integers(0, 15))).astype(np.int32)
+        B = rand_csc(rng, I.size, J.size, 0.5, dtype, lo=1, hi=9)
+        if dtype == np.int64:
+            B.num = np.abs(B.num) + 1
+        else:
+            A.num, B.num = np.floor(A.num), np.floor(B.num)
+        C = oracle.extend_add(A, I, J, B)
+        DA, PA = as_dense(A)
+        DB, PB = as_dense(B)
+        R, Q = selection_matrices(I, J, m, n)
+        want = DA + R @ DB.astype(np.float64) @ Q
+        want_pat = PA | ((R @ PB.astype(np.float64) @ Q) > 0)
+        DC, PC = as_dense(C)
+        assert np.array_equal(PC, want_pat)
+        assert np.array_equal(DC.astype(np.float64), want)
+        for j in range(C.n):
+            assert np.all(np.diff(C.ir[C.cp[j]:C.cp[j + 1]]) > 0)
+
+
+def test_extend_add_min_plus_is_scatter_min():
+    rng = np.random.default_rng(43)
+    for trial in range(8):
+        m, n = int(rng.integers(1, 20)), int(rng.integers(1, 20))
+        A = rand_csc(rng, m, n, 0.3, np.float64, lo=-5, hi=5)
+        I = rng.integers(0, m, size=int(rng.integers(1, 12))).astype(np.int32)
+        J = rng.integers(0, n, size=int(rng.integers(1, 12))).astype(np.int32)
+        B = rand_csc(rng, I.size, J.size, 0.5, np.float64, lo=-5, hi=5)
+        C = oracle.extend_add(A, I, J, B, semiring="min_plus")
+        want, pat = as_dense(A, fill=np.inf)
+        for q in range(B.n):
+            for e in range(B.cp[q], B.cp[q + 1]):
+                i, j = I[B.ir[e]], J[q]
+                np.minimum.at(want, (i, j), B.num[e])
+                pat[i, j] = True
+        got, gpat = as_dense(C, fill=np.inf)
+        assert np.array_equal(gpat, pat) and np.array_equal(got, want)
+
+
+def test_extend_add_identity_indices_is_sparse_sum():
+    import scipy.sparse as sp
+    rng = np.random.default_rng(45)
+    A = rand_csc(rng, 40, 30, 0.2)
+    B = rand_csc(rng, 40, 30, 0.2)
+    C = oracle.extend_add(A, np.arange(40, dtype=np.int32), np.arange(30, dtype=np.int32), B)
+    SA = sp.csc_matrix((A.num, A.ir, A.cp), shape=(40, 30))
+    SB = sp.csc_matrix((B.num, B.ir, B.cp), shape=(40, 30))
+    S = (SA + SB).tocsc()
+    S.sort_indices()
+    assert np.array_equal(C.cp, S.indptr) and np.array_equal(C.ir, S.indices)
+    assert np.allclose(C.num, S.data, rtol=0, atol=1e-15)
+    P = oracle.extend_add(A, np.arange(40, dtype=np.int32), np.arange(30, dtype=np.int32), B, semiring="or_and")
+    assert P.num is None and np.array_equal(P.ir, C.ir)
+
+
+def test_extend_add_on_empty_block_equals_spasgn():
+    # Where A(I,J) stores nothing and I, J have no repeats, there is nothing
+    # to add to: extend-add and SpAsgn give the same matrix.
+    rng = np.random.default_rng(47)
+    A = W.rmat(9, 8, seed=5, values="edge_id")
+    I = rng.choice(A.m, 60, replace=False).astype(np.int32)
+    J = rng.choice(A.n, 50, replace=False).astype(np.int32)
+    keep = np.ones(A.ir.size, dtype=bool)
+    inI = np.zeros(A.m, dtype=bool)
+    inI[I] = True
+    inJ = np.zeros(A.n, dtype=bool)
+    inJ[J] = True
+    cols = np.repeat(np.arange(A.n), np.diff(A.cp))
+    keep &= ~(inI[A.ir] & inJ[cols])
+    A0 = W.from_triples(A.ir[keep], cols[keep], A.num[keep], A.m, A.n)
+    B = W.erdos_renyi(60, 50, 5, seed=6, values="id40")
+    E = oracle.extend_add(A0, I, J, B)
+    S = oracle.spasgn(A0, I, J, B)
+    assert np.array_equal(E.cp, S.cp) and np.array_equal(E.ir, S.ir) and np.array_equal(E.num, S.num)
+
+
+def test_extend_add_sums_in_storage_order():
+    # One position receives A's value and two B values (I repeats row 0).
+    # In float32, (1 + 2^24) rounds back to 2^24, so A-first, then B in
+    # storage order gives 0; any other order gives 1.
+    A = W.from_triples([0], [0], np.array([1.0], np.float32), 1, 1)
+    B = W.from_triples([0, 1], [0, 0], np.array([2.0 ** 24, -2.0 ** 24], np.float32), 2, 1)
+    C = oracle.extend_add(A, np.array([0, 0], np.int32), np.array([0], np.int32), B)
+    assert C.ir.tolist() == [0] and C.num.tolist() == [0.0]
+
+
+def test_extend_add_rejects_bad_index():
+    A = W.erdos_renyi(5, 5, 2, seed=1)
+    B = W.erdos_renyi(1, 1, 1, seed=2)
+    with pytest.raises(ValueError):
+        oracle.extend_add(A, np.array([5], np.int32), np.array([0], np.int32), B)
+
+
 # ---------------------------------------------------------------- generators
 def test_generators_shapes():
     v = W.index_vector(1 << 12, 1 << 16, seed=1)
