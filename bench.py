@@ -180,6 +180,13 @@ def extra_workloads(spx, W, torch):
     out["spasgn_ms"] = round(1e3 * t, 4)
     out["spasgn_gbs"] = round(asg_bytes / t / 1e9, 2)
     out["spasgn_nnz"] = int(S.nnz)
+    del S
+    E = spx.extend_add(dA3, dI, dJ, dBp)
+    t = time_steps(lambda: spx.extend_add(dA3, dI, dJ, dBp), 5, sync)
+    ea_bytes = csc_bytes(A3.nnz, A3.n) + csc_bytes(Bp.nnz, Bp.n) + csc_bytes(E.nnz, A3.n) + (1 << 19) * 4
+    out["extend_add_ms"] = round(1e3 * t, 4)
+    out["extend_add_gbs"] = round(ea_bytes / t / 1e9, 2)
+    out["extend_add_nnz"] = int(E.nnz)
     return out
 
 

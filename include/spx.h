@@ -7,6 +7,7 @@
  *   C = A*B over a semiring            Section 3, Algorithm 1 (column-wise SpGEMM)
  *   B = A(I,J)           (SpRef)       Section 4; computed as R*(A*Q)
  *   C = A with A(I,J) = B (SpAsgn)     Section 4.1 (A + R B Q, minus the pattern of S A T)
+ *   A(I,J) = A(I,J) + B  (extend-add)  Section 4.1 (A + R B Q)
  *   CSC <-> DCSC                       Section 3.2
  *
  * Conventions for every entry point
@@ -232,6 +233,28 @@ int spx_spref_exec(spx_plan* plan, spx_mat* B);
 int spx_spasgn_plan(const spx_ctx* ctx, const spx_mat* A, const int32_t* I, int64_t lenI, const int32_t* J,
                     int64_t lenJ, const spx_mat* B, spx_plan** plan, int64_t* nnz_c);
 int spx_spasgn_exec(spx_plan* plan, spx_mat* C);
+
+/* ---- Extend-add: A(I,J) = A(I,J) + B (Section 4.1) ----------------------
+ * SpAsgn without the S*A*T term: C = A + R*B*Q, with R and Q SpAsgn's
+ * selection matrices (R(I(p), p) = 1, Q(q, J(q)) = 1).  Functional: A is
+ * not modified.  C keeps every stored A entry and every position
+ * (I(p), J(q)) of a stored B(p,q); where several of these meet (A stores
+ * the position, or I or J repeats an index) their values are combined with
+ * the semiring's sum: + for PLUS_TIMES, min for MIN_PLUS, SELECT2ND and
+ * SELECT1ST.  The sum starts from A's value (if stored) and adds the B
+ * values in B's storage order (column q ascending, then row p ascending),
+ * so results do not depend on scheduling.  OR_AND takes pattern-only (BOOL)
+ * operands; BOOL operands give the pattern union under any semiring.
+ * A and B are CSC with the same value type; B is lenI x lenJ with
+ * nnz(B) < 2^32; I and J are device int32 arrays (any order, repeats
+ * allowed).  At most 4096 B entries may land in one column of C
+ * (SPX_EUNSUPPORTED otherwise).
+ * spx_extend_add_plan returns nnz(C) (SPX_EINVAL for an index out of range);
+ * spx_extend_add_exec fills C (CSC, m x n, value type of A, caller-allocated:
+ * cp [n+1], ir [nnz], num [nnz]).                                         */
+int spx_extend_add_plan(const spx_ctx* ctx, const spx_mat* A, const int32_t* I, int64_t lenI, const int32_t* J,
+                        int64_t lenJ, const spx_mat* B, int32_t semiring, spx_plan** plan, int64_t* nnz_c);
+int spx_extend_add_exec(spx_plan* plan, spx_mat* C);
 
 /* ---- formats (Section 3.2) ----------------------------------------------
  * spx_count_nonempty: nzc of a CSC matrix (synchronises the stream).

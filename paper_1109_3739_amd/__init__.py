@@ -32,6 +32,7 @@ ERRORS = {1: "EINVAL", 2: "ENOMEM", 3: "EOVERFLOW", 4: "EUNSUPPORTED", 5: "EDEVI
 EXPORTS = [
     "spx_spgemm_plan", "spx_spgemm_exec", "spx_spgemm", "spx_plan_get_info", "spx_plan_destroy", "spx_plan_get_times",
     "spx_default_tuning", "spx_spref_plan", "spx_spref_exec", "spx_spasgn_plan", "spx_spasgn_exec",
+    "spx_extend_add_plan", "spx_extend_add_exec",
     "spx_count_nonempty", "spx_csc_to_dcsc", "spx_dcsc_to_csc", "spx_check", "spx_last_error", "spx_version",
     "spx_batch_plan", "spx_batch_exec", "spx_batch_capture", "spx_batch_replay",
 ]
@@ -107,6 +108,8 @@ def load():
         "spx_spref_exec": ([P, M], ctypes.c_int),
         "spx_spasgn_plan": ([C, M, P, I64, P, I64, M, PP, PI64], ctypes.c_int),
         "spx_spasgn_exec": ([P, M], ctypes.c_int),
+        "spx_extend_add_plan": ([C, M, P, I64, P, I64, M, ctypes.c_int32, PP, PI64], ctypes.c_int),
+        "spx_extend_add_exec": ([P, M], ctypes.c_int),
         "spx_count_nonempty": ([C, M, PI64], ctypes.c_int),
         "spx_csc_to_dcsc": ([C, M, M], ctypes.c_int),
         "spx_dcsc_to_csc": ([C, M, M], ctypes.c_int),
@@ -469,6 +472,27 @@ def spasgn(A: SpMat, I, J, B: SpMat) -> SpMat:
                   _val_tensor(A.val_t, nnz.value))
         d = C.desc()
         _check(lib.spx_spasgn_exec(h, ctypes.byref(d)))
+    finally:
+        lib.spx_plan_destroy(h)
+    return C
+
+
+def extend_add(A: SpMat, I, J, B: SpMat, semiring: str = "plus_times") -> SpMat:
+    """C = A + R*B*Q (A(I, J) = A(I, J) + B); repeated indices accumulate."""
+    lib = load()
+    torch = _t()
+    I, J = _idx(I), _idx(J)
+    ctx = make_ctx()
+    a, b = A.desc(), B.desc()
+    h = ctypes.c_void_p()
+    nnz = ctypes.c_int64()
+    _check(lib.spx_extend_add_plan(ctypes.byref(ctx), ctypes.byref(a), _ptr(I), I.numel(), _ptr(J), J.numel(),
+                                   ctypes.byref(b), SEMIRINGS[semiring], ctypes.byref(h), ctypes.byref(nnz)))
+    try:
+        C = SpMat(A.m, A.n, _empty(A.n + 1, torch.int64), _empty(nnz.value, torch.int32),
+                  _val_tensor(A.val_t, nnz.value))
+        d = C.desc()
+        _check(lib.spx_extend_add_exec(h, ctypes.byref(d)))
     finally:
         lib.spx_plan_destroy(h)
     return C

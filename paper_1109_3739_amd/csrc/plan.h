@@ -18,7 +18,7 @@ struct spx_plan {
 
 namespace spx {
 
-enum { kPlanGemm = 1, kPlanSpref = 2, kPlanSpasgn = 3, kPlanBatch = 4 };
+enum { kPlanGemm = 1, kPlanSpref = 2, kPlanSpasgn = 3, kPlanBatch = 4, kPlanExtAdd = 5 };
 
 // Validates a descriptor (dimensions, codes, non-NULL buffers).
 int check_mat(const spx_mat* X, const char* name);

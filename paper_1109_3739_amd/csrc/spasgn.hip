@@ -12,6 +12,13 @@
 // Repeated indices: the last occurrence in I (and J) wins, as sequential
 // assignment would leave it (the selection matrices are built from last
 // occurrences, and S, T are 0/1 patterns).
+//
+// Extend-add C = A + R B Q (Section 4.1: SpAsgn without the S A T term) is
+// computed with the same column split.  Without the mask nothing of A is
+// dropped; a repeated index lands several B entries on one position, where
+// the semiring sum combines them.  Each modified column sorts its landing
+// entries by (row, position in B), so a row's values are added to A's value
+// in B's storage order.
 #include <algorithm>
 
 #include "common.h"
@@ -258,6 +265,226 @@ __global__ void k_asgn_write_cp(const int64_t* off, int64_t n, void* cp, int32_t
     store_ptr(cp, ptr_t, j, off[j]);
 }
 
+// ------------------------------------------------------------ extend-add
+struct ExtAddPlan : spx_plan {
+  explicit ExtAddPlan(const spx_ctx* c) : spx_plan(c, kPlanExtAdd) {}
+  Operand A{}, B{};
+  const int32_t* I = nullptr;
+  int64_t lenI = 0, lenJ = 0, nnz = 0, nmod = 0;
+  int32_t sr = 0;
+  int32_t* lastJ = nullptr;  // [n] >= 0 for the columns that receive B entries
+  int32_t* qcnt = nullptr;   // [n] number of q with J(q) = j
+  int64_t* qoff = nullptr;   // [n+1]
+  int32_t* qlist = nullptr;  // [lenJ] the q of each column, grouped by column
+  int64_t* cnt = nullptr;    // [n]
+  int64_t* off = nullptr;    // [n+1] = C.cp
+  int32_t* mod = nullptr;    // [n] modified columns
+  unsigned* err = nullptr;
+  unsigned long long* nmod_d = nullptr;
+};
+
+__global__ void k_check_range(const int32_t* v, int64_t len, int64_t bound, unsigned* err, unsigned bit) {
+  for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < len; p += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t x = v[p];
+    if (x < 0 || x >= bound) atomicOr(err, bit);
+  }
+}
+
+__global__ void k_count_q(const int32_t* J, int64_t lenJ, int64_t n, int32_t* qcnt) {
+  for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < lenJ; q += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t j = J[q];
+    if (j >= 0 && j < n) atomicAdd(&qcnt[j], 1);
+  }
+}
+
+// Groups the q by column (any order inside a group: the sort keys of the
+// column kernel fix the order of the landing entries).  Leaves qcnt at zero.
+__global__ void k_scatter_q(const int32_t* J, int64_t lenJ, const int64_t* qoff, int32_t* qcnt, int32_t* qlist) {
+  for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < lenJ; q += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t j = J[q];
+    qlist[qoff[j] + atomicSub(&qcnt[j], 1) - 1] = (int32_t)q;
+  }
+}
+
+struct LoadI32 {
+  const int32_t* p;
+  __device__ int64_t operator()(int64_t i) const { return p[i]; }
+};
+
+// Ascending bitonic sort of s[0, n) in LDS (n <= kAsgnMaxInsert), padded with ~0.
+__device__ __forceinline__ void lds_sort_keys(uint64_t* s, int n) {
+  int p2 = 1;
+  while (p2 < n) p2 <<= 1;
+  for (int t = n + threadIdx.x; t < p2; t += blockDim.x) s[t] = ~0ull;
+  __syncthreads();
+  for (int k = 2; k <= p2; k <<= 1) {
+    for (int jj = k >> 1; jj > 0; jj >>= 1) {
+      for (int t = threadIdx.x; t < (p2 >> 1); t += blockDim.x) {
+        const int lo = 2 * t - (t & (jj - 1));
+        const int hi = lo + jj;
+        const bool asc = (lo & k) == 0;
+        const uint64_t x = s[lo], y = s[hi];
+        if ((x > y) == asc) {
+          s[lo] = y;
+          s[hi] = x;
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// Number of rows < row in the sorted column col[0, len).
+__device__ __forceinline__ int64_t rows_below(const int32_t* col, int64_t len, int32_t row) {
+  int64_t lo = 0, hi = len;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (col[mid] < row)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+// One workgroup per modified column j (grid-stride over the list):
+//   1. the landing entries of every B(:,q) with J(q) = j go into LDS as keys
+//      (I(p) << 32 | e), e the entry's position in B, and are sorted;
+//   2. the distinct rows are listed (first key of each) and looked up in A(:,j);
+//   3. count pass: nnz(C(:,j)) = nnz(A(:,j)) + distinct rows not in A(:,j);
+//      fill pass: A's entries move down by the new rows below them and add
+//      the values landing on their row; each new row takes the sum of its
+//      landing values.  Sums run in key order (B's storage order).
+template <bool kFill, bool kVals, typename T, class Acc>
+__global__ void __launch_bounds__(256) k_ea_column(Operand A, Operand B, const int32_t* I, const int32_t* mod,
+                                                   int64_t nmod, const int64_t* qoff, const int32_t* qlist,
+                                                   int64_t* cnt, const int64_t* off, unsigned* err, int32_t* cir,
+                                                   T* cnum) {
+  __shared__ uint64_t s_key[kAsgnMaxInsert];
+  __shared__ int32_t s_head[kAsgnMaxInsert + 1];  // sorted position of each distinct row's first key
+  __shared__ int32_t s_nin[kAsgnMaxInsert + 1];   // distinct rows before k that A(:,j) lacks
+  __shared__ int64_t red[256 / kWave + 1];
+  const T* anum = static_cast<const T*>(A.num);
+  const T* bnum = static_cast<const T*>(B.num);
+  for (int64_t u = blockIdx.x; u < nmod; u += gridDim.x) {
+    const int32_t j = mod[u];
+    const int64_t a0 = slot_begin(A, j), a1 = slot_begin(A, j + 1);
+    const int32_t* acol = A.ir + a0;
+    const int64_t alen = a1 - a0;
+    int64_t nins = 0;
+    for (int64_t t = qoff[j]; t < qoff[j + 1]; ++t) {
+      const int32_t q = qlist[t];
+      const int64_t b0 = slot_begin(B, q), b1 = slot_begin(B, q + 1);
+      for (int64_t e = b0 + threadIdx.x; e < b1; e += blockDim.x) {
+        const int64_t slot = nins + (e - b0);
+        if (slot < kAsgnMaxInsert) s_key[slot] = ((uint64_t)(uint32_t)I[B.ir[e]] << 32) | (uint32_t)e;
+      }
+      nins += b1 - b0;
+    }
+    if (nins > kAsgnMaxInsert) {  // uniform across the workgroup
+      if (!kFill && threadIdx.x == 0) atomicOr(err, 4u);
+      __syncthreads();
+      continue;
+    }
+    lds_sort_keys(s_key, (int)nins);
+    // distinct rows
+    int nu = 0;
+    for (int tc = 0; tc < nins; tc += blockDim.x) {
+      const int t = tc + threadIdx.x;
+      int64_t head = 0;
+      if (t < nins) head = t == 0 || (s_key[t] >> 32) != (s_key[t - 1] >> 32);
+      int64_t tot;
+      const int64_t ex = block_excl_scan(head, red, &tot);
+      if (head) s_head[nu + ex] = t;
+      nu += (int)tot;
+    }
+    if (threadIdx.x == 0) s_head[nu] = (int)nins;
+    __syncthreads();
+    // which distinct rows A(:,j) lacks
+    int64_t nnew = 0;
+    for (int kc = 0; kc < nu; kc += blockDim.x) {
+      const int k = kc + threadIdx.x;
+      int64_t fresh = 0;
+      if (k < nu) {
+        const int32_t row = (int32_t)(s_key[s_head[k]] >> 32);
+        const int64_t at = rows_below(acol, alen, row);
+        fresh = !(at < alen && acol[at] == row);
+      }
+      int64_t tot;
+      const int64_t ex = block_excl_scan(fresh, red, &tot);
+      if (k < nu) s_nin[k] = (int)(nnew + ex);
+      nnew += tot;
+    }
+    if (threadIdx.x == 0) s_nin[nu] = (int)nnew;
+    __syncthreads();
+    if (!kFill) {
+      if (threadIdx.x == 0) cnt[j] = alen + nnew;
+      continue;
+    }
+    const int64_t cbase = off[j];
+    // A's entries
+    for (int64_t t = threadIdx.x; t < alen; t += blockDim.x) {
+      const int32_t row = acol[t];
+      int lo = 0, hi = nu;  // distinct landing rows < row
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if ((int32_t)(s_key[s_head[mid]] >> 32) < row)
+          lo = mid + 1;
+        else
+          hi = mid;
+      }
+      const int64_t o = cbase + t + s_nin[lo];
+      cir[o] = row;
+      if (kVals) {
+        T acc = anum[a0 + t];
+        if (lo < nu && (int32_t)(s_key[s_head[lo]] >> 32) == row)
+          for (int h = s_head[lo]; h < s_head[lo + 1]; ++h) acc = Acc::add(acc, bnum[(uint32_t)s_key[h]]);
+        cnum[o] = acc;
+      }
+    }
+    // new rows
+    for (int k = threadIdx.x; k < nu; k += blockDim.x) {
+      if (s_nin[k + 1] == s_nin[k]) continue;  // A(:,j) stores this row
+      const int32_t row = (int32_t)(s_key[s_head[k]] >> 32);
+      const int64_t o = cbase + s_nin[k] + rows_below(acol, alen, row);
+      cir[o] = row;
+      if (kVals) {
+        T acc = bnum[(uint32_t)s_key[s_head[k]]];
+        for (int h = s_head[k] + 1; h < s_head[k + 1]; ++h) acc = Acc::add(acc, bnum[(uint32_t)s_key[h]]);
+        cnum[o] = acc;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+template <bool kFill, bool kVals, typename T, class Acc>
+int launch_ea(const ExtAddPlan* P, int32_t* cir, void* cnum, hipStream_t st) {
+  const int cus = device_cu_count();
+  k_ea_column<kFill, kVals, T, Acc><<<(unsigned)std::min<int64_t>(P->nmod, (int64_t)cus * 4), 256, 0, st>>>(
+      P->A, P->B, P->I, P->mod, P->nmod, P->qoff, P->qlist, P->cnt, P->off, P->err, cir, static_cast<T*>(cnum));
+  SPX_HIP(hipGetLastError());
+  return SPX_OK;
+}
+
+template <bool kFill>
+int dispatch_ea(const ExtAddPlan* P, int32_t* cir, void* cnum, hipStream_t st) {
+  const int32_t vt = P->A.val_t;
+  if (vt == SPX_VAL_BOOL || P->sr == SPX_OR_AND) return launch_ea<kFill, false, float, MinAcc<float>>(P, cir, nullptr, st);
+  const bool plus = P->sr == SPX_PLUS_TIMES;
+  switch (vt) {
+    case SPX_VAL_F32:
+      return plus ? launch_ea<kFill, true, float, Semiring<SPX_PLUS_TIMES, float>>(P, cir, cnum, st)
+                  : launch_ea<kFill, true, float, MinAcc<float>>(P, cir, cnum, st);
+    case SPX_VAL_F64:
+      return plus ? launch_ea<kFill, true, double, Semiring<SPX_PLUS_TIMES, double>>(P, cir, cnum, st)
+                  : launch_ea<kFill, true, double, MinAcc<double>>(P, cir, cnum, st);
+    default:
+      return plus ? launch_ea<kFill, true, int64_t, Semiring<SPX_PLUS_TIMES, int64_t>>(P, cir, cnum, st)
+                  : launch_ea<kFill, true, int64_t, MinAcc<int64_t>>(P, cir, cnum, st);
+  }
+}
+
 }  // namespace spx
 
 using namespace spx;
@@ -371,6 +598,119 @@ extern "C" int spx_spasgn_exec(spx_plan* plan, spx_mat* C) {
         P->A, P->B, P->I, P->lastI, P->lastJ, P->mod, P->nmod, P->off, P->doff, P->drows, vb, C->ir, C->num);
     SPX_HIP(hipGetLastError());
   }
+  k_asgn_write_cp<<<grid_for(P->A.n + 1, 256, 65536), 256, 0, st>>>(P->off, P->A.n, C->cp, C->ptr_t);
+  SPX_HIP(hipGetLastError());
+  return SPX_OK;
+}
+
+extern "C" int spx_extend_add_plan(const spx_ctx* ctx, const spx_mat* A, const int32_t* I, int64_t lenI,
+                                   const int32_t* J, int64_t lenJ, const spx_mat* B, int32_t semiring,
+                                   spx_plan** plan, int64_t* nnz_c) {
+  if (!plan) return fail(SPX_EINVAL, "plan is NULL");
+  *plan = nullptr;
+  SPX_TRY(check_mat(A, "A"));
+  SPX_TRY(check_mat(B, "B"));
+  if (A->fmt != SPX_CSC || B->fmt != SPX_CSC) return fail(SPX_EUNSUPPORTED, "extend-add takes CSC operands");
+  if (lenI < 0 || lenJ < 0 || lenI >= (1ll << 31) || lenJ >= (1ll << 31)) return fail(SPX_EINVAL, "bad index length");
+  if (B->m != lenI || B->n != lenJ) return fail(SPX_EINVAL, "B must be lenI x lenJ");
+  if (A->val_t != B->val_t) return fail(SPX_EINVAL, "A and B must have the same value type");
+  if (semiring < SPX_PLUS_TIMES || semiring > SPX_SELECT1ST) return fail(SPX_EINVAL, "unknown semiring");
+  if (semiring == SPX_OR_AND && A->val_t != SPX_VAL_BOOL)
+    return fail(SPX_EUNSUPPORTED, "OR_AND extend-add takes pattern-only (BOOL) operands");
+  if (B->nnz >= (1ll << 32)) return fail(SPX_EUNSUPPORTED, "nnz(B) must be below 2^32");
+  if ((lenI > 0 && !I) || (lenJ > 0 && !J)) return fail(SPX_EINVAL, "index vector is NULL");
+  if (ctx && ctx->validate) {
+    int32_t ok = 0;
+    SPX_TRY(spx_check(ctx, A, &ok));
+    if (!ok) return fail(SPX_EINVAL, "A is not canonical");
+    SPX_TRY(spx_check(ctx, B, &ok));
+    if (!ok) return fail(SPX_EINVAL, "B is not canonical");
+  }
+  auto* P = new ExtAddPlan(ctx);
+  std::unique_ptr<ExtAddPlan> guard(P);
+  hipStream_t st = stream_of(ctx);
+  Scratch& scr = P->scratch;
+  P->A = make_operand(A);
+  P->B = make_operand(B);
+  P->I = I;
+  P->lenI = lenI;
+  P->lenJ = lenJ;
+  P->sr = semiring;
+  const int64_t m = A->m, n = A->n;
+  SPX_TRY(scr.get_n(4, &P->err));
+  SPX_TRY(fill_u32(P->err, 1, 0, st));
+  SPX_TRY(scr.get_n(1, &P->nmod_d));
+  SPX_TRY(fill_i64((int64_t*)P->nmod_d, 1, 0, st));
+  SPX_TRY(scr.get_n(std::max<int64_t>(n, 1), &P->lastJ));
+  SPX_TRY(scr.get_n(std::max<int64_t>(n, 1), &P->qcnt));
+  SPX_TRY(fill_u32((uint32_t*)P->lastJ, n, 0xffffffffu, st));
+  SPX_TRY(fill_u32((uint32_t*)P->qcnt, n, 0u, st));
+  if (lenI > 0) {
+    k_check_range<<<grid_for(lenI, 256, 4096), 256, 0, st>>>(I, lenI, m, P->err, 1u);
+    SPX_HIP(hipGetLastError());
+  }
+  if (lenJ > 0) {
+    k_last_occ<<<grid_for(lenJ, 256, 4096), 256, 0, st>>>(J, lenJ, n, P->lastJ, P->err, 2u);
+    SPX_HIP(hipGetLastError());
+    k_count_q<<<grid_for(lenJ, 256, 4096), 256, 0, st>>>(J, lenJ, n, P->qcnt);
+    SPX_HIP(hipGetLastError());
+  }
+  SPX_TRY(scr.get_n(std::max<int64_t>(n, 1), &P->cnt));
+  SPX_TRY(scr.get_n(n + 1, &P->off));
+  SPX_TRY(scr.get_n(std::max<int64_t>(n, 1), &P->mod));
+  if (n > 0) {
+    k_asgn_cols<<<grid_for(n, 256, 65536), 256, 0, st>>>(P->A, P->lastJ, P->cnt, P->mod, P->nmod_d);
+    SPX_HIP(hipGetLastError());
+  }
+  unsigned long long nmod_h = 0;
+  unsigned err_h = 0;
+  SPX_HIP(hipMemcpyAsync(&nmod_h, P->nmod_d, 8, hipMemcpyDeviceToHost, st));
+  SPX_HIP(hipMemcpyAsync(&err_h, P->err, 4, hipMemcpyDeviceToHost, st));
+  SPX_HIP(hipStreamSynchronize(st));
+  if (err_h & 1u) return fail(SPX_EINVAL, "I has an index outside [0, m)");
+  if (err_h & 2u) return fail(SPX_EINVAL, "J has an index outside [0, n)");
+  P->nmod = (int64_t)nmod_h;
+  SPX_TRY(scr.get_n(n + 1, &P->qoff));
+  SPX_TRY(scr.get_n(std::max<int64_t>(lenJ, 1), &P->qlist));
+  SPX_TRY(exclusive_scan(LoadI32{P->qcnt}, n, P->qoff, scr, st));
+  if (lenJ > 0) {
+    k_scatter_q<<<grid_for(lenJ, 256, 4096), 256, 0, st>>>(J, lenJ, P->qoff, P->qcnt, P->qlist);
+    SPX_HIP(hipGetLastError());
+  }
+  if (P->nmod > 0) SPX_TRY(dispatch_ea<false>(P, nullptr, nullptr, st));
+  SPX_TRY(exclusive_scan(LoadI64{P->cnt}, n, P->off, scr, st));
+  int64_t total = 0;
+  SPX_HIP(hipMemcpyAsync(&total, P->off + n, 8, hipMemcpyDeviceToHost, st));
+  SPX_HIP(hipMemcpyAsync(&err_h, P->err, 4, hipMemcpyDeviceToHost, st));
+  SPX_HIP(hipStreamSynchronize(st));
+  if (err_h & 4u) return fail(SPX_EUNSUPPORTED, "a column of C receives more than 4096 entries of B");
+  P->nnz = total;
+  if (nnz_c) *nnz_c = P->nnz;
+  *plan = guard.release();
+  return SPX_OK;
+}
+
+extern "C" int spx_extend_add_exec(spx_plan* plan, spx_mat* C) {
+  if (!plan || plan->kind != kPlanExtAdd) return fail(SPX_EINVAL, "not an extend-add plan");
+  auto* P = static_cast<ExtAddPlan*>(plan);
+  if (!C) return fail(SPX_EINVAL, "C is NULL");
+  if (C->m != P->A.m || C->n != P->A.n || C->fmt != SPX_CSC) return fail(SPX_EINVAL, "C must be m x n CSC");
+  if (C->val_t != P->A.val_t) return fail(SPX_EINVAL, "C's value type must be A's");
+  if (C->ptr_t == SPX_PTR_I32 && P->nnz >= (1ll << 31)) return fail(SPX_EOVERFLOW, "nnz(C) needs I64 pointers");
+  if (!C->cp || (P->nnz > 0 && (!C->ir || (C->val_t != SPX_VAL_BOOL && !C->num))))
+    return fail(SPX_EINVAL, "C buffers missing");
+  C->nnz = P->nnz;
+  C->nzc = 0;
+  hipStream_t st = stream_of(&P->ctx);
+  const int vb = value_size(P->A.val_t);
+  const int cus = device_cu_count();
+  if (P->A.nnz > 0) {
+    const int64_t tiles = ceil_div(P->A.nnz, kCopyTile);
+    k_asgn_copy<<<(unsigned)std::min<int64_t>(tiles, (int64_t)cus * 8), 256, 0, st>>>(P->A, P->lastJ, P->off, vb,
+                                                                                       C->ir, C->num);
+    SPX_HIP(hipGetLastError());
+  }
+  if (P->nmod > 0) SPX_TRY(dispatch_ea<true>(P, C->ir, C->num, st));
   k_asgn_write_cp<<<grid_for(P->A.n + 1, 256, 65536), 256, 0, st>>>(P->off, P->A.n, C->cp, C->ptr_t);
   SPX_HIP(hipGetLastError());
   return SPX_OK;

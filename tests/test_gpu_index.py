@@ -141,3 +141,93 @@ def test_config3_spref_full(spx, config3):
 def test_config3_spasgn_full(spx, config3):
     A, I, J, Bp = config3
     spasgn_check(spx, A, I, J, Bp)
+
+
+# ---------------------------------------------------------------- extend-add
+def with_values(M, kind, rng):
+    """Copy of M with fresh values of ``kind`` (f32, f64, i64 or none)."""
+    from types import SimpleNamespace
+    nnz = M.ir.size
+    num = {"f32": lambda: rng.random(nnz).astype(np.float32),
+           "f64": lambda: rng.random(nnz),
+           "i64": lambda: rng.integers(-2**40, 2**40, size=nnz),
+           "none": lambda: None}[kind]()
+    return SimpleNamespace(m=M.m, n=M.n, cp=M.cp, ir=M.ir, num=num)
+
+
+def extend_add_check(spx, A, I, J, B, semiring="plus_times"):
+    C = spx.extend_add(spx.from_host(A), I, J, spx.from_host(B), semiring=semiring).to_host_csc()
+    ref = oracle.extend_add(A, I, J, B, semiring=semiring)
+    # both sides add in B's storage order, so even float sums are bit-exact
+    assert_same_csc(C, ref, exact_values=True, what=f"extend_add {semiring}")
+    return C
+
+
+@pytest.mark.parametrize("kind,semiring", [("f64", "plus_times"), ("f32", "plus_times"), ("i64", "plus_times"),
+                                           ("f64", "min_plus"), ("f32", "select2nd"), ("i64", "min_plus"),
+                                           ("none", "or_and"), ("none", "plus_times")])
+def test_extend_add_small_with_repeats(spx, kind, semiring):
+    rng = np.random.default_rng(61)
+    for trial in range(4):
+        A = with_values(W.rmat(10, 8, seed=40 + trial), kind, rng)
+        lI, lJ = int(rng.integers(1, 400)), int(rng.integers(1, 400))
+        I = rng.integers(0, A.m, size=lI).astype(np.int32)
+        J = rng.integers(0, A.n, size=lJ).astype(np.int32)
+        B = with_values(W.erdos_renyi(lI, lJ, min(5, lI), seed=50 + trial), kind, rng)
+        extend_add_check(spx, A, I, J, B, semiring)
+
+
+def test_extend_add_identity_is_sparse_sum_and_edges(spx):
+    rng = np.random.default_rng(63)
+    A = with_values(W.rmat(11, 8, seed=7), "f64", rng)
+    B = with_values(W.rmat(11, 8, seed=8), "f64", rng)
+    idx = np.arange(A.m, dtype=np.int32)
+    extend_add_check(spx, A, idx, idx, B)
+    # no indices, empty B, empty A
+    E = W.from_triples([], [], np.empty(0), 0, 0)
+    C = extend_add_check(spx, A, np.empty(0, np.int32), np.empty(0, np.int32), E)
+    assert np.array_equal(C.ir, A.ir)
+    J = rng.integers(0, A.n, size=50).astype(np.int32)
+    extend_add_check(spx, A, np.empty(0, np.int32), J, W.from_triples([], [], np.empty(0), 0, 50))
+    Z = W.from_triples([], [], np.empty(0), A.m, A.n)
+    I = rng.integers(0, A.m, size=300).astype(np.int32)
+    extend_add_check(spx, Z, I, J, with_values(W.erdos_renyi(300, 50, 7, seed=9), "f64", rng))
+
+
+def test_extend_add_crowded_column(spx):
+    # One column of C receives 4096 B entries (the LDS limit) from 8 repeated
+    # column indices with many repeated rows: a 4096-key sort, 16 scan chunks
+    # and long sums; a 4097th entry is refused.
+    rng = np.random.default_rng(65)
+    A = with_values(W.erdos_renyi(5000, 3, 900, seed=11), "f64", rng)
+    I = rng.integers(0, 5000, size=1024).astype(np.int32)
+    J = np.array([1] * 8 + [0, 2], dtype=np.int32)
+    rows = np.concatenate([np.arange(512)] * 8 + [np.arange(10), np.arange(20)])
+    cols = np.concatenate([np.full(512, q) for q in range(8)] + [np.full(10, 8), np.full(20, 9)])
+    B = W.from_triples(rows, cols, rng.random(rows.size), 1024, 10)
+    C = extend_add_check(spx, A, I, J, B)
+    assert np.diff(C.cp)[1] > 900
+    rows2 = np.concatenate([rows, [600]])
+    cols2 = np.concatenate([cols, [0]])
+    B2 = W.from_triples(rows2, cols2, rng.random(rows2.size), 1024, 10)
+    with pytest.raises(spx.SpxError) as e:
+        spx.extend_add(spx.from_host(A), I, J, spx.from_host(B2))
+    assert e.value.code == spx.SPX_EUNSUPPORTED
+
+
+def test_extend_add_errors(spx):
+    A = W.erdos_renyi(10, 10, 2, seed=1)
+    B = W.erdos_renyi(1, 1, 1, seed=2)
+    for I, J in (([10], [0]), ([0], [-1])):
+        with pytest.raises(spx.SpxError) as e:
+            spx.extend_add(spx.from_host(A), np.array(I, np.int32), np.array(J, np.int32), spx.from_host(B))
+        assert e.value.code == spx.SPX_EINVAL
+    with pytest.raises(spx.SpxError) as e:
+        spx.extend_add(spx.from_host(A), np.array([0], np.int32), np.array([0], np.int32), spx.from_host(B),
+                       semiring="or_and")
+    assert e.value.code == spx.SPX_EUNSUPPORTED
+
+
+def test_config3_extend_add_full(spx, config3):
+    A, I, J, Bp = config3
+    extend_add_check(spx, A, I, J, Bp)
