@@ -225,6 +225,24 @@ def extend_add(A, I, J, B, semiring: str = "plus_times", nthreads: int = 0):
     return SimpleNamespace(m=A.m, n=A.n, cp=cp, ir=ir, num=num)
 
 
+def summa_stages(As, Bs, semiring: str = "plus_times", nthreads: int = 0):
+    """One processor's block of Sparse SUMMA (Algorithm 2): C = C + A_k*B_k
+    for the stages k in order.  Each stage is a local product (Algorithm 1,
+    ``spgemm``); the running sum adds it entry by entry with the semiring's
+    sum (``extend_add`` with identity indices)."""
+    if len(As) != len(Bs) or not As:
+        raise ValueError("need equally many A_k and B_k")
+    C = None
+    for A, B in zip(As, Bs):
+        P = spgemm_csc(A, B, semiring, nthreads=nthreads)
+        if C is None:
+            C = P
+            continue
+        C = extend_add(C, np.arange(C.m, dtype=np.int32), np.arange(C.n, dtype=np.int32), P,
+                       semiring="or_and" if P.num is None else semiring, nthreads=nthreads)
+    return C
+
+
 def csc_to_dcsc(n: int, cp):
     """(jc int32[nzc], dcp int64[nzc+1]) of a CSC column-pointer array."""
     lib = _load()

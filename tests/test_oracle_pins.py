@@ -430,6 +430,69 @@ def test_extend_add_rejects_bad_index():
         oracle.extend_add(A, np.array([5], np.int32), np.array([0], np.int32), B)
 
 
+# ---------------------------------------------------------------- SUMMA stages
+def inner_split(A, B, cuts):
+    """Stage blocks A(:, K_k), B(K_k, :) of the inner index ranges between cuts."""
+    As, Bs = [], []
+    for k0, k1 in zip(cuts[:-1], cuts[1:]):
+        As.append(W.column_block(A, 0, A.m, k0, k1))
+        Bt = W.column_block(B, k0, k1, 0, B.n)
+        Bs.append(Bt)
+    return As, Bs
+
+
+@pytest.mark.parametrize("semiring", ["plus_times", "min_plus", "or_and"])
+def test_summa_stages_of_an_inner_split_equal_the_product(semiring):
+    # sum_k A(:,K_k) B(K_k,:) = A B for any partition of the inner index set
+    rng = np.random.default_rng(51)
+    for trial in range(6):
+        m, k, n = (int(x) for x in rng.integers(1, 40, size=3))
+        A = rand_csc(rng, m, k, 0.25, np.int64)
+        B = rand_csc(rng, k, n, 0.25, np.int64)
+        cuts = np.unique(np.concatenate([[0, k], rng.integers(0, k + 1, size=int(rng.integers(0, 6)))]))
+        As, Bs = inner_split(A, B, list(cuts))
+        got = oracle.summa_stages(As, Bs, semiring)
+        want = oracle.spgemm_csc(A, B, semiring)
+        assert np.array_equal(got.cp, want.cp) and np.array_equal(got.ir, want.ir)
+        if want.num is not None:
+            assert np.array_equal(got.num, want.num)
+
+
+def test_summa_stages_vs_dense():
+    rng = np.random.default_rng(53)
+    for trial in range(6):
+        K = int(rng.integers(1, 5))
+        m, n = int(rng.integers(1, 20)), int(rng.integers(1, 20))
+        bs = [int(x) for x in rng.integers(0, 12, size=K)]
+        As = [rand_csc(rng, m, b, 0.3, np.int64) for b in bs]
+        Bs = [rand_csc(rng, b, n, 0.3, np.int64) for b in bs]
+        C = oracle.summa_stages(As, Bs)
+        want = np.zeros((m, n), dtype=np.int64)
+        pat = np.zeros((m, n), dtype=bool)
+        for X, Y in zip(As, Bs):
+            DX, PX = as_dense(X)
+            DY, PY = as_dense(Y)
+            want += DX.astype(np.int64) @ DY.astype(np.int64)
+            pat |= (PX.astype(np.int64) @ PY.astype(np.int64)) > 0
+        DC, PC = as_dense(C)
+        assert np.array_equal(PC, pat)
+        assert np.array_equal(DC.astype(np.int64)[pat], want[pat])
+
+
+def test_summa_stages_min_plus_vs_dense():
+    rng = np.random.default_rng(55)
+    As = [rand_csc(rng, 9, b, 0.4, np.float64, lo=0, hi=4) for b in (3, 5, 2)]
+    Bs = [rand_csc(rng, b, 7, 0.4, np.float64, lo=0, hi=4) for b in (3, 5, 2)]
+    C = oracle.summa_stages(As, Bs, "min_plus")
+    want = np.full((9, 7), np.inf)
+    for X, Y in zip(As, Bs):
+        DX, _ = as_dense(X, fill=np.inf)
+        DY, _ = as_dense(Y, fill=np.inf)
+        want = np.minimum(want, np.min(DX[:, :, None] + DY[None, :, :], axis=1))
+    got, pat = as_dense(C, fill=np.inf)
+    assert np.array_equal(pat, np.isfinite(want)) and np.array_equal(got, want)
+
+
 # ---------------------------------------------------------------- generators
 def test_generators_shapes():
     v = W.index_vector(1 << 12, 1 << 16, seed=1)
