@@ -145,6 +145,36 @@ def extra_workloads(spx, W, torch):
     out["stage_block_nnz_c"] = int(C.nnz)
     del C
 
+    # all 8 stages of that processor: C_00 = sum_k A_0k * A_k0 as one stage-sum
+    # plan, against the 8 stage products formed separately (partials not merged)
+    As = [spx.csc_to_dcsc(spx.from_host(W.column_block(A, 0, b, k * b, (k + 1) * b))) for k in range(8)]
+    Bs = [spx.csc_to_dcsc(spx.from_host(W.column_block(A, k * b, (k + 1) * b, 0, b))) for k in range(8)]
+    sp = spx.StageSumPlan(As, Bs, out_fmt=spx.DCSC)
+    S = sp.execute()
+    smults = sp.info()["mults"]
+    sp.close()
+
+    def stage_sum():
+        q = spx.StageSumPlan(As, Bs, out_fmt=spx.DCSC)
+        q.execute(S)
+        q.close()
+
+    def stages_apart():
+        for X, Y in zip(As, Bs):
+            q = spx.GemmPlan(X, Y, out_fmt=spx.DCSC)
+            q.execute()
+            q.close()
+
+    for _ in range(2):
+        stage_sum()
+        stages_apart()
+    t = time_steps(stage_sum, 10, sync)
+    t_apart = time_steps(stages_apart, 5, sync)
+    out["summa_8x8_c00"] = {"stages": 8, "ms": round(1e3 * t, 4), "gflops": round(2 * smults / t / 1e9, 3),
+                            "mults": smults, "nnz_c": int(S.nnz),
+                            "stage_products_apart_ms": round(1e3 * t_apart, 4)}
+    del S, As, Bs
+
     # R-MAT scale 20 times a tall-skinny Erdos-Renyi matrix (n/k = 8192, d2
     # nonzeros per column): the multi-source BFS frontier expansion
     dA = spx.from_host(A)

@@ -8,6 +8,7 @@
  *   B = A(I,J)           (SpRef)       Section 4; computed as R*(A*Q)
  *   C = A with A(I,J) = B (SpAsgn)     Section 4.1 (A + R B Q, minus the pattern of S A T)
  *   A(I,J) = A(I,J) + B  (extend-add)  Section 4.1 (A + R B Q)
+ *   C = sum_k A_k*B_k    (stage sum)   Section 3.3, Algorithm 2 (one processor's SUMMA stages)
  *   CSC <-> DCSC                       Section 3.2
  *
  * Conventions for every entry point
@@ -181,6 +182,27 @@ int spx_plan_get_info(const spx_plan* plan, spx_plan_info* info);
 int spx_plan_get_times(spx_plan* plan, spx_times* times);
 void spx_plan_destroy(spx_plan* plan);
 void spx_default_tuning(spx_tuning* tuning);
+
+/* ---- Sparse SUMMA stage accumulation: C = sum_k A_k*B_k (Algorithm 2) ---
+ * One processor's output block of Sparse SUMMA (Section 3.3): over the
+ * stages k < count it accumulates C = C + A_k*B_k with the semiring's sum.
+ * With every stage block resident, the stages are computed as the single
+ * product [A_1 ... A_K] * [B_1; ...; B_K]: each output column accumulates
+ * the products of all stages at once, and no partial C is written.
+ * spx_spgemm_sum_plan: A and B are arrays of `count` >= 1 descriptors,
+ *   A_k m x b_k and B_k b_k x n (CSC or DCSC, sum of b_k below 2^31); all
+ *   A_k (and all B_k) share one value type; the semiring rules of
+ *   spx_spgemm_plan apply.  Copies the blocks' patterns into the plan
+ *   (about 12 bytes per stored entry plus 8 per column of the stacked
+ *   right operand), runs the symbolic phase and returns nnz(C) and nzc(C).
+ * spx_spgemm_sum_exec: refreshes the values from A_k.num / B_k.num
+ *   (patterns must be unchanged) and fills C as spx_spgemm_exec does.
+ * spx_plan_get_info / spx_plan_get_times report the inner product.
+ * An output entry exists iff some stage contributes a product to it; the
+ * order of the floating-point sums is unspecified, as in spx_spgemm.     */
+int spx_spgemm_sum_plan(const spx_ctx* ctx, int32_t count, const spx_mat* A, const spx_mat* B, int32_t semiring,
+                        int32_t c_fmt, const spx_tuning* tuning, spx_plan** plan, int64_t* nnz_c, int64_t* nzc_c);
+int spx_spgemm_sum_exec(spx_plan* plan, spx_mat* C);
 
 /* ---- Batched SpGEMM: C_i = A_i*B_i for i < count ------------------------
  * All products of a batch run through one symbolic pass and one persistent

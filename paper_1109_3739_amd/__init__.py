@@ -32,7 +32,7 @@ ERRORS = {1: "EINVAL", 2: "ENOMEM", 3: "EOVERFLOW", 4: "EUNSUPPORTED", 5: "EDEVI
 EXPORTS = [
     "spx_spgemm_plan", "spx_spgemm_exec", "spx_spgemm", "spx_plan_get_info", "spx_plan_destroy", "spx_plan_get_times",
     "spx_default_tuning", "spx_spref_plan", "spx_spref_exec", "spx_spasgn_plan", "spx_spasgn_exec",
-    "spx_extend_add_plan", "spx_extend_add_exec",
+    "spx_extend_add_plan", "spx_extend_add_exec", "spx_spgemm_sum_plan", "spx_spgemm_sum_exec",
     "spx_count_nonempty", "spx_csc_to_dcsc", "spx_dcsc_to_csc", "spx_check", "spx_last_error", "spx_version",
     "spx_batch_plan", "spx_batch_exec", "spx_batch_capture", "spx_batch_replay",
 ]
@@ -110,6 +110,8 @@ def load():
         "spx_spasgn_exec": ([P, M], ctypes.c_int),
         "spx_extend_add_plan": ([C, M, P, I64, P, I64, M, ctypes.c_int32, PP, PI64], ctypes.c_int),
         "spx_extend_add_exec": ([P, M], ctypes.c_int),
+        "spx_spgemm_sum_plan": ([C, I32, M, M, I32, I32, ctypes.POINTER(spx_tuning), PP, PI64, PI64], ctypes.c_int),
+        "spx_spgemm_sum_exec": ([P, M], ctypes.c_int),
         "spx_count_nonempty": ([C, M, PI64], ctypes.c_int),
         "spx_csc_to_dcsc": ([C, M, M], ctypes.c_int),
         "spx_dcsc_to_csc": ([C, M, M], ctypes.c_int),
@@ -344,6 +346,49 @@ def spgemm(A: SpMat, B: SpMat, semiring: str = "plus_times", out_fmt: int = CSC,
 
 
 # ---- batched SpGEMM ------------------------------------------------------
+class StageSumPlan(GemmPlan):
+    """C = sum_k A_k * B_k: one processor's Sparse SUMMA stages computed as one
+    product over the concatenated inner dimension (see spx_spgemm_sum_plan)."""
+
+    def __init__(self, As, Bs, semiring: str = "plus_times", out_fmt: int = CSC, tuning=None, stream=None,
+                 profile: bool = False, validate: bool = False):
+        lib = load()
+        if len(As) != len(Bs) or not As:
+            raise ValueError("need equally many A_k and B_k")
+        self._keep = (list(As), list(Bs))
+        self.count = len(As)
+        self.ctx = make_ctx(stream, validate=validate, profile=profile)
+        arr = spx_mat * self.count
+        self.A = arr(*[a.desc() for a in As])
+        self.B = arr(*[b.desc() for b in Bs])
+        self.m, self.n, self.out_fmt = As[0].m, Bs[0].n, out_fmt
+        self.handle = ctypes.c_void_p()
+        nnz, nzc = ctypes.c_int64(), ctypes.c_int64()
+        tp = ctypes.byref(tuning) if tuning is not None else None
+        _check(lib.spx_spgemm_sum_plan(ctypes.byref(self.ctx), self.count, self.A, self.B, SEMIRINGS[semiring],
+                                       out_fmt, tp, ctypes.byref(self.handle), ctypes.byref(nnz),
+                                       ctypes.byref(nzc)))
+        self.nnz, self.nzc = nnz.value, nzc.value
+        self.semiring = semiring
+        self.val_t = self._result_val(As[0], Bs[0], semiring)
+
+    def execute(self, C: Optional[SpMat] = None) -> SpMat:
+        if C is None:
+            C = self.alloc_output()
+        d = C.desc()
+        _check(load().spx_spgemm_sum_exec(self.handle, ctypes.byref(d)))
+        return C
+
+
+def spgemm_sum(As, Bs, semiring: str = "plus_times", out_fmt: int = CSC, tuning=None) -> SpMat:
+    """C = sum_k A_k * B_k over ``semiring`` (plan + exec)."""
+    p = StageSumPlan(As, Bs, semiring, out_fmt, tuning)
+    try:
+        return p.execute()
+    finally:
+        p.close()
+
+
 class BatchPlan:
     """C_i = A_i * B_i for all i in one symbolic pass and one persistent
     numeric launch (see spx_batch_plan).  Outputs are views into pools."""

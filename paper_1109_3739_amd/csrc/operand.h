@@ -34,7 +34,7 @@ inline Operand make_operand(const spx_mat* X) {
 
 // Stored columns ("slots"): all n columns of a CSC matrix, the nzc nonempty
 // ones of a DCSC matrix.
-inline int64_t nslots_of(const Operand& X) { return X.fmt == SPX_DCSC ? X.nzc : X.n; }
+__host__ __device__ inline int64_t nslots_of(const Operand& X) { return X.fmt == SPX_DCSC ? X.nzc : X.n; }
 
 __device__ __forceinline__ int64_t slot_begin(const Operand& X, int64_t t) { return load_ptr(X.cp, X.ptr_t, t); }
 __device__ __forceinline__ int64_t slot_col(const Operand& X, int64_t t) {

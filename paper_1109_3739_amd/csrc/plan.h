@@ -18,7 +18,7 @@ struct spx_plan {
 
 namespace spx {
 
-enum { kPlanGemm = 1, kPlanSpref = 2, kPlanSpasgn = 3, kPlanBatch = 4, kPlanExtAdd = 5 };
+enum { kPlanGemm = 1, kPlanSpref = 2, kPlanSpasgn = 3, kPlanBatch = 4, kPlanExtAdd = 5, kPlanSum = 6 };
 
 // Validates a descriptor (dimensions, codes, non-NULL buffers).
 int check_mat(const spx_mat* X, const char* name);
@@ -44,6 +44,9 @@ __device__ __forceinline__ void copy_value(const void* from, int64_t src, void* 
 // Device pointer to the output column offsets of a SpGEMM plan (one entry
 // per stored column of B plus the total), valid while the plan lives.
 const int64_t* gemm_plan_offsets(const spx_plan* plan);
+
+// The SpGEMM plan inside a stage-sum plan (plan->kind == kPlanSum).
+const spx_plan* sum_plan_inner(const spx_plan* plan);
 
 }  // namespace spx
 
