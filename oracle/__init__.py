@@ -243,6 +243,23 @@ def summa_stages(As, Bs, semiring: str = "plus_times", nthreads: int = 0):
     return C
 
 
+def contract(A, row_agg=None, m_coarse: int = 0, col_agg=None, n_coarse: int = 0, semiring: str = "plus_times",
+             nthreads: int = 0):
+    """C = S_r A S_c^T with S_r(row_agg[u], u) = 1 and S_c(col_agg[v], v) = 1
+    (None: identity).  These S are the selection matrices R and Q^T of
+    extend-add with I = row_agg, J = col_agg, so C = 0 + R A Q: every stored
+    A(u,v) is added at (row_agg[u], col_agg[v]) with the semiring's sum."""
+    I = np.arange(A.m, dtype=np.int32) if row_agg is None else np.asarray(row_agg, dtype=np.int32)
+    J = np.arange(A.n, dtype=np.int32) if col_agg is None else np.asarray(col_agg, dtype=np.int32)
+    mc = A.m if row_agg is None else int(m_coarse)
+    nc = A.n if col_agg is None else int(n_coarse)
+    pattern = semiring == "or_and" or A.num is None
+    empty = SimpleNamespace(m=mc, n=nc, cp=np.zeros(nc + 1, dtype=np.int64), ir=np.zeros(0, dtype=np.int32),
+                            num=None if pattern else np.zeros(0, dtype=A.num.dtype))
+    src = SimpleNamespace(m=A.m, n=A.n, cp=A.cp, ir=A.ir, num=None if pattern else A.num)
+    return extend_add(empty, I, J, src, semiring="or_and" if pattern else semiring, nthreads=nthreads)
+
+
 def csc_to_dcsc(n: int, cp):
     """(jc int32[nzc], dcp int64[nzc+1]) of a CSC column-pointer array."""
     lib = _load()

@@ -493,6 +493,59 @@ def test_summa_stages_min_plus_vs_dense():
     assert np.array_equal(pat, np.isfinite(want)) and np.array_equal(got, want)
 
 
+# ---------------------------------------------------------------- contraction
+def aggregation_matrix(agg, nc, n):
+    """CSC of S (nc x n) with S(agg[v], v) = 1."""
+    return W.from_triples(np.asarray(agg, np.int64), np.arange(n, dtype=np.int64), np.ones(n, np.int64), nc, n)
+
+
+def transpose_csc(M):
+    rows = np.repeat(np.arange(M.n, dtype=np.int64), np.diff(M.cp))
+    return W.from_triples(rows, M.ir.astype(np.int64), M.num, M.n, M.m)
+
+
+@pytest.mark.parametrize("semiring", ["plus_times", "min_plus", "or_and"])
+def test_contract_equals_both_parenthesizations(semiring):
+    # S A S^T = (S A) S^T = S (A S^T), each product by the oracle's Algorithm 1
+    rng = np.random.default_rng(57)
+    for trial in range(6):
+        n = int(rng.integers(1, 60))
+        A = rand_csc(rng, n, n, 0.15, np.int64)
+        order = int(rng.integers(1, 9))
+        agg = np.arange(n) // order if trial % 2 == 0 else rng.integers(0, max(1, n // 3), size=n)
+        nc = int(agg.max()) + 1 if n else 0
+        S = aggregation_matrix(agg, nc, n)
+        if semiring == "min_plus":
+            S.num = np.zeros_like(S.num)  # the min-plus one
+        St = transpose_csc(S)
+        left = oracle.spgemm_csc(oracle.spgemm_csc(S, A, semiring), St, semiring)
+        right = oracle.spgemm_csc(S, oracle.spgemm_csc(A, St, semiring), semiring)
+        C = oracle.contract(A, agg, nc, agg, nc, semiring)
+        for other in (left, right):
+            assert np.array_equal(C.cp, other.cp) and np.array_equal(C.ir, other.ir)
+            if other.num is not None:
+                assert np.array_equal(C.num, other.num)
+
+
+def test_contract_vs_dense_and_one_sided():
+    rng = np.random.default_rng(59)
+    A = rand_csc(rng, 30, 24, 0.2, np.int64)
+    ra = np.sort(rng.integers(0, 7, size=30))
+    ca = rng.integers(0, 5, size=24)
+    Sr = np.zeros((7, 30), np.int64)
+    Sr[ra, np.arange(30)] = 1
+    Sc = np.zeros((5, 24), np.int64)
+    Sc[ca, np.arange(24)] = 1
+    DA, PA = as_dense(A)
+    DA = DA.astype(np.int64)
+    for row, col, want, pat in ((ra, ca, Sr @ DA @ Sc.T, Sr @ PA @ Sc.T > 0),
+                                (ra, None, Sr @ DA, Sr @ PA > 0),
+                                (None, ca, DA @ Sc.T, PA @ Sc.T > 0)):
+        C = oracle.contract(A, row, 7, col, 5)
+        DC, PC = as_dense(C)
+        assert np.array_equal(PC, pat) and np.array_equal(DC.astype(np.int64)[pat], want[pat])
+
+
 # ---------------------------------------------------------------- generators
 def test_generators_shapes():
     v = W.index_vector(1 << 12, 1 << 16, seed=1)
