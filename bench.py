@@ -217,6 +217,46 @@ def extra_workloads(spx, W, torch):
     out["extend_add_ms"] = round(1e3 * t, 4)
     out["extend_add_gbs"] = round(ea_bytes / t / 1e9, 2)
     out["extend_add_nnz"] = int(E.nnz)
+    del E, R
+
+    # restriction S A S^T of orders 2, 4, 8 on R-MAT scale 23: one fused pass
+    # over A, against both parenthesizations with S, S^T and the intermediate
+    # product materialized
+    A23 = W.rmat(23, 8, seed=23)
+    dA23 = spx.from_host(A23)
+    n23 = A23.n
+    res = {}
+    for order in (2, 4, 8):
+        agg = spx.restriction_map(n23, order)
+        nc = n23 // order
+        ones = torch.ones(n23, dtype=torch.float64, device="cuda")
+        dS = spx.SpMat(nc, n23, torch.arange(n23 + 1, dtype=torch.int64, device="cuda"), agg, ones)
+        dSt = spx.SpMat(n23, nc, torch.arange(0, n23 + 1, order, dtype=torch.int64, device="cuda"),
+                        torch.arange(n23, dtype=torch.int32, device="cuda"), ones)
+        p = spx.ContractPlan(dA23, agg, nc, agg, nc)
+        Cr = p.execute()
+        p.close()
+
+        def fused():
+            q = spx.ContractPlan(dA23, agg, nc, agg, nc)
+            q.execute(Cr)
+            q.close()
+
+        def left():
+            spx.spgemm(spx.spgemm(dS, dA23), dSt)
+
+        def right():
+            spx.spgemm(dS, spx.spgemm(dA23, dSt))
+
+        for f in (fused, left, right):
+            f()
+        t = time_steps(fused, 5, sync)
+        byts = csc_bytes(A23.nnz, n23) + csc_bytes(Cr.nnz, nc)
+        res[str(order)] = {"ms": round(1e3 * t, 4), "gbs": round(byts / t / 1e9, 2), "nnz_c": int(Cr.nnz),
+                           "two_products_left_ms": round(1e3 * time_steps(left, 3, sync), 4),
+                           "two_products_right_ms": round(1e3 * time_steps(right, 3, sync), 4)}
+        del Cr, dS, dSt
+    out["restriction_rmat23"] = {"nnz_a": int(A23.nnz), "orders": res}
     return out
 
 

@@ -9,6 +9,7 @@
  *   C = A with A(I,J) = B (SpAsgn)     Section 4.1 (A + R B Q, minus the pattern of S A T)
  *   A(I,J) = A(I,J) + B  (extend-add)  Section 4.1 (A + R B Q)
  *   C = sum_k A_k*B_k    (stage sum)   Section 3.3, Algorithm 2 (one processor's SUMMA stages)
+ *   C = S_r*A*S_c^T      (contraction) Section 5.3.2 restriction, as one SpGEMM pass
  *   CSC <-> DCSC                       Section 3.2
  *
  * Conventions for every entry point
@@ -203,6 +204,29 @@ void spx_default_tuning(spx_tuning* tuning);
 int spx_spgemm_sum_plan(const spx_ctx* ctx, int32_t count, const spx_mat* A, const spx_mat* B, int32_t semiring,
                         int32_t c_fmt, const spx_tuning* tuning, spx_plan** plan, int64_t* nnz_c, int64_t* nzc_c);
 int spx_spgemm_sum_exec(spx_plan* plan, spx_mat* C);
+
+/* ---- Graph contraction / restriction: C = S_r*A*S_c^T (Section 5.3.2) ---
+ * S_r (m_coarse x m) has the single unit entry S_r(row_agg[u], u) in every
+ * column u, and S_c (n_coarse x n) likewise with col_agg; a NULL map makes
+ * that side the identity (its coarse dimension is then ignored).  So
+ * C(I,J) is the semiring sum of the stored A(u,v) with row_agg[u] = I and
+ * col_agg[v] = J (restriction of order r: agg[v] = v / r; graph
+ * contraction: S*A*S^T with one map for both sides).  The triple product
+ * is one SpGEMM pass over A and forms neither S_r*A nor A*S_c^T (Section 6
+ * asks for such a primitive).
+ * row_agg must be non-decreasing (SPX_EUNSUPPORTED otherwise); col_agg may
+ * be in any order.  Map values must lie in [0, coarse dimension)
+ * (SPX_EINVAL).  Semirings: PLUS_TIMES (sums, S entries 1) and MIN_PLUS
+ * (minima, S entries 0) on A's value type; SELECT1ST (minimum of A's
+ * values) and OR_AND (pattern) with any A.  The plan keeps A's pointers and
+ * values (patterns must stay unchanged; values may change between execs)
+ * plus 4 bytes per entry of A for the mapped row ids.
+ * spx_contract_exec fills C (m_coarse x n_coarse) as spx_spgemm_exec does;
+ * spx_plan_get_info / spx_plan_get_times report the inner product.       */
+int spx_contract_plan(const spx_ctx* ctx, const spx_mat* A, const int32_t* row_agg, int64_t m_coarse,
+                      const int32_t* col_agg, int64_t n_coarse, int32_t semiring, int32_t c_fmt,
+                      const spx_tuning* tuning, spx_plan** plan, int64_t* nnz_c, int64_t* nzc_c);
+int spx_contract_exec(spx_plan* plan, spx_mat* C);
 
 /* ---- Batched SpGEMM: C_i = A_i*B_i for i < count ------------------------
  * All products of a batch run through one symbolic pass and one persistent

@@ -33,6 +33,7 @@ EXPORTS = [
     "spx_spgemm_plan", "spx_spgemm_exec", "spx_spgemm", "spx_plan_get_info", "spx_plan_destroy", "spx_plan_get_times",
     "spx_default_tuning", "spx_spref_plan", "spx_spref_exec", "spx_spasgn_plan", "spx_spasgn_exec",
     "spx_extend_add_plan", "spx_extend_add_exec", "spx_spgemm_sum_plan", "spx_spgemm_sum_exec",
+    "spx_contract_plan", "spx_contract_exec",
     "spx_count_nonempty", "spx_csc_to_dcsc", "spx_dcsc_to_csc", "spx_check", "spx_last_error", "spx_version",
     "spx_batch_plan", "spx_batch_exec", "spx_batch_capture", "spx_batch_replay",
 ]
@@ -112,6 +113,9 @@ def load():
         "spx_extend_add_exec": ([P, M], ctypes.c_int),
         "spx_spgemm_sum_plan": ([C, I32, M, M, I32, I32, ctypes.POINTER(spx_tuning), PP, PI64, PI64], ctypes.c_int),
         "spx_spgemm_sum_exec": ([P, M], ctypes.c_int),
+        "spx_contract_plan": ([C, M, P, I64, P, I64, I32, I32, ctypes.POINTER(spx_tuning), PP, PI64, PI64],
+                              ctypes.c_int),
+        "spx_contract_exec": ([P, M], ctypes.c_int),
         "spx_count_nonempty": ([C, M, PI64], ctypes.c_int),
         "spx_csc_to_dcsc": ([C, M, M], ctypes.c_int),
         "spx_dcsc_to_csc": ([C, M, M], ctypes.c_int),
@@ -378,6 +382,65 @@ class StageSumPlan(GemmPlan):
         d = C.desc()
         _check(load().spx_spgemm_sum_exec(self.handle, ctypes.byref(d)))
         return C
+
+
+class ContractPlan(GemmPlan):
+    """C = S_r * A * S_c^T for unit aggregation operators S_r(row_agg[u], u),
+    S_c(col_agg[v], v) (see spx_contract_plan); None: identity on that side."""
+
+    def __init__(self, A: SpMat, row_agg=None, m_coarse: int = 0, col_agg=None, n_coarse: int = 0,
+                 semiring: str = "plus_times", out_fmt: int = CSC, tuning=None, stream=None, profile: bool = False):
+        lib = load()
+        ra = None if row_agg is None else _idx(row_agg)
+        ca = None if col_agg is None else _idx(col_agg)
+        self._keep = (A, ra, ca)
+        self.ctx = make_ctx(stream, profile=profile)
+        self.A = A.desc()
+        self.m = A.m if ra is None else int(m_coarse)
+        self.n = A.n if ca is None else int(n_coarse)
+        self.out_fmt = out_fmt
+        self.handle = ctypes.c_void_p()
+        nnz, nzc = ctypes.c_int64(), ctypes.c_int64()
+        tp = ctypes.byref(tuning) if tuning is not None else None
+        _check(lib.spx_contract_plan(ctypes.byref(self.ctx), ctypes.byref(self.A), _ptr(ra), self.m, _ptr(ca),
+                                     self.n, SEMIRINGS[semiring], out_fmt, tp, ctypes.byref(self.handle),
+                                     ctypes.byref(nnz), ctypes.byref(nzc)))
+        self.nnz, self.nzc = nnz.value, nzc.value
+        self.semiring = semiring
+        self.val_t = VAL_BOOL if semiring == "or_and" else A.val_t
+
+    def execute(self, C: Optional[SpMat] = None) -> SpMat:
+        if C is None:
+            C = self.alloc_output()
+        d = C.desc()
+        _check(load().spx_contract_exec(self.handle, ctypes.byref(d)))
+        return C
+
+
+def contract(A: SpMat, row_agg=None, m_coarse: int = 0, col_agg=None, n_coarse: int = 0,
+             semiring: str = "plus_times", out_fmt: int = CSC) -> SpMat:
+    """C = S_r * A * S_c^T with S(agg[v], v) = 1 on each side given (plan + exec)."""
+    p = ContractPlan(A, row_agg, m_coarse, col_agg, n_coarse, semiring, out_fmt)
+    try:
+        return p.execute()
+    finally:
+        p.close()
+
+
+def restriction_map(n: int, order: int, device="cuda"):
+    """agg[v] = v // order: the restriction operator of the given order
+    (S is ceil(n / order) x n with one unit entry per column)."""
+    torch = _t()
+    return torch.div(torch.arange(n, dtype=torch.int32, device=device), order, rounding_mode="floor")
+
+
+def restrict(A: SpMat, order: int, semiring: str = "plus_times", out_fmt: int = CSC) -> SpMat:
+    """S * A * S^T for the restriction operator of ``order`` (A square)."""
+    if A.m != A.n:
+        raise ValueError("restriction on both sides needs a square matrix")
+    agg = restriction_map(A.n, order)
+    nc = -(-A.n // order)
+    return contract(A, agg, nc, agg, nc, semiring, out_fmt)
 
 
 def spgemm_sum(As, Bs, semiring: str = "plus_times", out_fmt: int = CSC, tuning=None) -> SpMat:

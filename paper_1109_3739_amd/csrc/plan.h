@@ -18,7 +18,7 @@ struct spx_plan {
 
 namespace spx {
 
-enum { kPlanGemm = 1, kPlanSpref = 2, kPlanSpasgn = 3, kPlanBatch = 4, kPlanExtAdd = 5, kPlanSum = 6 };
+enum { kPlanGemm = 1, kPlanSpref = 2, kPlanSpasgn = 3, kPlanBatch = 4, kPlanExtAdd = 5, kPlanSum = 6, kPlanContract = 7 };
 
 // Validates a descriptor (dimensions, codes, non-NULL buffers).
 int check_mat(const spx_mat* X, const char* name);
@@ -47,6 +47,9 @@ const int64_t* gemm_plan_offsets(const spx_plan* plan);
 
 // The SpGEMM plan inside a stage-sum plan (plan->kind == kPlanSum).
 const spx_plan* sum_plan_inner(const spx_plan* plan);
+
+// The SpGEMM plan inside a contraction plan (plan->kind == kPlanContract).
+const spx_plan* contract_plan_inner(const spx_plan* plan);
 
 }  // namespace spx
 

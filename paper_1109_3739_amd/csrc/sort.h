@@ -11,7 +11,7 @@ constexpr int kSortTile = 4096;
 constexpr int kSortThreads = 512;
 
 // All stages k <= kSortTile of the network, per tile.
-__global__ void __launch_bounds__(kSortThreads) k_bitonic_tile_full(uint64_t* keys) {
+static __global__ void __launch_bounds__(kSortThreads) k_bitonic_tile_full(uint64_t* keys) {
   __shared__ uint64_t s[kSortTile];
   const int64_t base = (int64_t)blockIdx.x * kSortTile;
   for (int i = threadIdx.x; i < kSortTile; i += kSortThreads) s[i] = keys[base + i];
@@ -35,7 +35,7 @@ __global__ void __launch_bounds__(kSortThreads) k_bitonic_tile_full(uint64_t* ke
 }
 
 // One stage (k, j) with j >= kSortTile, over global memory.
-__global__ void k_bitonic_global(uint64_t* keys, int64_t n, int64_t k, int64_t j) {
+static __global__ void k_bitonic_global(uint64_t* keys, int64_t n, int64_t k, int64_t j) {
   const int64_t half = n >> 1;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < half; i += (int64_t)gridDim.x * blockDim.x) {
     const int64_t lo = 2 * i - (i & (j - 1));
@@ -50,7 +50,7 @@ __global__ void k_bitonic_global(uint64_t* keys, int64_t n, int64_t k, int64_t j
 }
 
 // Remaining stages j < kSortTile of merge step k > kSortTile, per tile.
-__global__ void __launch_bounds__(kSortThreads) k_bitonic_tile_merge(uint64_t* keys, int64_t k) {
+static __global__ void __launch_bounds__(kSortThreads) k_bitonic_tile_merge(uint64_t* keys, int64_t k) {
   __shared__ uint64_t s[kSortTile];
   const int64_t base = (int64_t)blockIdx.x * kSortTile;
   for (int i = threadIdx.x; i < kSortTile; i += kSortThreads) s[i] = keys[base + i];
@@ -71,7 +71,7 @@ __global__ void __launch_bounds__(kSortThreads) k_bitonic_tile_merge(uint64_t* k
   for (int i = threadIdx.x; i < kSortTile; i += kSortThreads) keys[base + i] = s[i];
 }
 
-__global__ void k_pad_u64(uint64_t* keys, int64_t from, int64_t to) {
+static __global__ void k_pad_u64(uint64_t* keys, int64_t from, int64_t to) {
   for (int64_t i = from + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < to; i += (int64_t)gridDim.x * blockDim.x)
     keys[i] = ~0ull;
 }

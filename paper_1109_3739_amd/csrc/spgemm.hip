@@ -1880,6 +1880,7 @@ extern "C" int spx_plan_get_times(spx_plan* plan, spx_times* times) {
   if (!plan || !times) return fail(SPX_EINVAL, "NULL argument");
   std::memset(times, 0, sizeof(*times));
   if (plan->kind == kPlanSum) plan = const_cast<spx_plan*>(sum_plan_inner(plan));
+  if (plan->kind == kPlanContract) plan = const_cast<spx_plan*>(contract_plan_inner(plan));
   if (plan->kind != kPlanGemm) return fail(SPX_EINVAL, "not a SpGEMM plan");
   auto* P = static_cast<GemmPlan*>(plan);
   if (!P->profile) return fail(SPX_EINVAL, "plan was not created with ctx->profile set");
@@ -1902,6 +1903,7 @@ extern "C" int spx_plan_get_info(const spx_plan* plan, spx_plan_info* info) {
   if (!plan || !info) return fail(SPX_EINVAL, "NULL argument");
   std::memset(info, 0, sizeof(*info));
   if (plan->kind == kPlanSum) plan = sum_plan_inner(plan);
+  if (plan->kind == kPlanContract) plan = contract_plan_inner(plan);
   if (plan->kind != kPlanGemm) return SPX_OK;
   auto* P = const_cast<GemmPlan*>(static_cast<const GemmPlan*>(plan));
   if (P->nnz_multi < 0) {

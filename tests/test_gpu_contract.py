@@ -1,0 +1,88 @@
+"""GPU parity of graph contraction / restriction C = S_r A S_c^T (one SpGEMM
+pass over A with mapped row ids) against the oracle."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from helpers import assert_same_csc
+
+pytestmark = pytest.mark.gpu
+
+
+def contract_check(spx, A, row_agg, mc, col_agg, nc, semiring="plus_times", exact=False, a_dcsc=False,
+                   out_fmt=0):
+    import torch
+    dA = spx.from_host(A)
+    if a_dcsc:
+        dA = spx.csc_to_dcsc(dA)
+    ra = None if row_agg is None else torch.from_numpy(np.asarray(row_agg, np.int32)).cuda()
+    ca = None if col_agg is None else torch.from_numpy(np.asarray(col_agg, np.int32)).cuda()
+    plan = spx.ContractPlan(dA, ra, mc, ca, nc, semiring, out_fmt)
+    C = plan.execute()
+    info = plan.info()
+    plan.close()
+    ref = oracle.contract(A, row_agg, mc, col_agg, nc, semiring)
+    assert_same_csc(C.to_host_csc(), ref, exact_values=exact, what=f"contract {semiring}")
+    assert info["mults"] == A.ir.size and info["nnz"] == ref.cp[-1]
+    return C
+
+
+@pytest.mark.parametrize("order", [1, 2, 3, 4, 8])
+def test_restriction_orders(spx, order):
+    A = W.rmat(13, 8, seed=80 + order)
+    agg = np.arange(A.n) // order
+    nc = -(-A.n // order)
+    contract_check(spx, A, agg, nc, agg, nc, "plus_times", out_fmt=order % 2)
+    Ai = W.rmat(12, 8, seed=90 + order, values="edge_id")
+    agg = np.arange(Ai.n) // order
+    nc = -(-Ai.n // order)
+    contract_check(spx, Ai, agg, nc, agg, nc, "plus_times", exact=True, a_dcsc=True)
+    contract_check(spx, Ai, agg, nc, agg, nc, "min_plus", exact=True)
+    contract_check(spx, Ai, agg, nc, agg, nc, "select1st", exact=True)
+    contract_check(spx, Ai, agg, nc, agg, nc, "or_and", exact=True)
+
+
+def test_one_sided_and_unsorted_column_maps(spx):
+    rng = np.random.default_rng(83)
+    A = W.rmat(12, 8, seed=84, values="edge_id")
+    ra = np.sort(rng.integers(0, 700, size=A.m))
+    ca = rng.integers(0, 500, size=A.n)
+    contract_check(spx, A, ra, 700, None, 0, exact=True)   # S A
+    contract_check(spx, A, None, 0, ca, 500, exact=True)   # A S^T, vertices in any order
+    contract_check(spx, A, ra, 700, ca, 500, exact=True)
+    contract_check(spx, A, None, 0, None, 0, exact=True)   # identity on both sides
+    Af = W.rmat(12, 8, seed=85, values="f32")
+    contract_check(spx, Af, ra, 700, ca, 500)
+
+
+def test_contraction_matches_two_explicit_products(spx):
+    # S (A S^T) with materialized S and intermediate, on the GPU's own SpGEMM
+    A = W.rmat(14, 8, seed=86, values="edge_id")
+    agg = np.arange(A.n) // 4
+    nc = A.n // 4
+    S = W.from_triples(agg, np.arange(A.n), np.ones(A.n, np.int64), nc, A.n)
+    St = W.from_triples(np.arange(A.n), agg, np.ones(A.n, np.int64), A.n, nc)
+    dS, dSt, dA = spx.from_host(S), spx.from_host(St), spx.from_host(A)
+    two = spx.spgemm(dS, spx.spgemm(dA, dSt)).to_host_csc()
+    C = contract_check(spx, A, agg, nc, agg, nc, exact=True)
+    assert_same_csc(C.to_host_csc(), two, exact_values=True, what="fused vs two products")
+
+
+def test_restriction_order8_rmat18(spx):
+    A = W.rmat(18, 8, seed=87)
+    agg = np.arange(A.n) // 8
+    contract_check(spx, A, agg, A.n // 8, agg, A.n // 8)
+
+
+def test_contraction_errors(spx):
+    import torch
+    A = spx.from_host(W.erdos_renyi(20, 20, 3, seed=1))
+    down = torch.from_numpy(np.arange(20, dtype=np.int32)[::-1].copy()).cuda()
+    with pytest.raises(spx.SpxError) as e:
+        spx.contract(A, down, 20, None, 0)
+    assert e.value.code == spx.SPX_EUNSUPPORTED
+    big = torch.full((20,), 7, dtype=torch.int32, device="cuda")
+    with pytest.raises(spx.SpxError) as e:
+        spx.contract(A, None, 0, big, 5)
+    assert e.value.code == spx.SPX_EINVAL
