@@ -145,6 +145,19 @@ __device__ __forceinline__ uint64_t lanemask_lt() {
   return lane == 0 ? 0ull : (~0ull >> (64 - lane));
 }
 
+// Claims one slot of a global counter for every lane with `pred` set, with a
+// single atomic per wave (lanes not taking part must still be active or have
+// left the loop together).  Returns the lane's slot (undefined without pred).
+__device__ __forceinline__ unsigned long long wave_claim(unsigned long long* ctr, bool pred) {
+  const uint64_t mask = __ballot(pred);
+  if (mask == 0) return 0;
+  const int leader = __ffsll((unsigned long long)mask) - 1;
+  unsigned long long base = 0;
+  if (lane_id() == leader) base = atomicAdd(ctr, (unsigned long long)__popcll(mask));
+  base = __shfl(base, leader);
+  return base + (unsigned long long)__popcll(mask & lanemask_lt());
+}
+
 // Exclusive block-wide prefix sum of one value per thread; `red` is LDS
 // scratch of at least blockDim.x/64 + 1 entries.  Returns the exclusive
 // prefix and writes the block total to *total (all threads).

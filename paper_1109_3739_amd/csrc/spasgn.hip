@@ -29,6 +29,9 @@
 namespace spx {
 
 constexpr int kAsgnMaxInsert = 4096;  // inserted rows per column handled in LDS
+// Columns with at most this many inserted (landing) entries take one wave and
+// a small LDS area; the others go to a list served by 256-thread workgroups.
+constexpr int kAsgnSmall = 64;
 constexpr int64_t kCopyTile = 4096;   // A entries per copy workgroup
 
 struct SpasgnPlan : spx_plan {
@@ -45,6 +48,9 @@ struct SpasgnPlan : spx_plan {
   int64_t* dcnt = nullptr;   // [nmod] dropped entries per modified column
   int64_t* doff = nullptr;   // [nmod+1]
   int32_t* drows = nullptr;  // [ndrop] rows of the dropped entries
+  int32_t* big = nullptr;    // modified columns (indices into mod) above kAsgnSmall inserts
+  unsigned long long* nbig_d = nullptr;
+  int64_t nbig = 0;
   unsigned* err = nullptr;
   unsigned long long* nmod_d = nullptr;
 };
@@ -62,19 +68,18 @@ __global__ void k_last_occ(const int32_t* v, int64_t len, int64_t bound, int32_t
 // Unmodified columns keep their length; modified ones are listed.
 __global__ void k_asgn_cols(Operand A, const int32_t* lastJ, int64_t* cnt, int32_t* mod, unsigned long long* nmod) {
   for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < A.n; j += (int64_t)gridDim.x * blockDim.x) {
-    if (lastJ[j] < 0) {
-      cnt[j] = slot_begin(A, j + 1) - slot_begin(A, j);
-    } else {
-      cnt[j] = 0;
-      mod[atomicAdd(nmod, 1ull)] = (int32_t)j;
-    }
+    const bool modified = lastJ[j] >= 0;
+    cnt[j] = modified ? 0 : slot_begin(A, j + 1) - slot_begin(A, j);
+    const unsigned long long slot = wave_claim(nmod, modified);
+    if (modified) mod[slot] = (int32_t)j;
   }
 }
 
 // Per modified column: kept A entries, dropped ones, inserted B entries.
 __global__ void __launch_bounds__(256) k_asgn_mod_count(Operand A, Operand B, const int32_t* I, const int32_t* lastI,
                                                         const int32_t* lastJ, const int32_t* mod, int64_t nmod,
-                                                        int64_t* cnt, int64_t* dcnt, unsigned* err) {
+                                                        int64_t* cnt, int64_t* dcnt, int32_t* big,
+                                                        unsigned long long* nbig, unsigned* err) {
   __shared__ int64_t red[256 / kWave + 1];
   for (int64_t u = blockIdx.x; u < nmod; u += gridDim.x) {
     const int32_t j = mod[u];
@@ -93,7 +98,10 @@ __global__ void __launch_bounds__(256) k_asgn_mod_count(Operand A, Operand B, co
     if (threadIdx.x == 0) {
       cnt[j] = tk + ti;
       dcnt[u] = (a1 - a0) - tk;
-      if (ti > kAsgnMaxInsert) atomicOr(err, 4u);
+      if (ti > kAsgnMaxInsert)
+        atomicOr(err, 4u);
+      else if (ti > kAsgnSmall)
+        big[atomicAdd(nbig, 1ull)] = (int32_t)u;
     }
   }
 }
@@ -143,15 +151,20 @@ __global__ void __launch_bounds__(256) k_asgn_copy(Operand A, const int32_t* las
 }
 
 // Modified columns: merge the kept A entries (rows not in I, ascending) with
-// the inserted rows I(p) (sorted here), by merge-path positions.
+// the inserted rows I(p) (sorted here), by merge-path positions.  CAP is the
+// LDS capacity for inserted rows: the one-wave variant (CAP = kAsgnSmall)
+// runs over all modified columns and skips larger ones, which the 256-thread
+// variant takes from `list`.
+template <int CAP>
 __global__ void __launch_bounds__(256) k_asgn_mod_fill(Operand A, Operand B, const int32_t* I, const int32_t* lastI,
-                                                       const int32_t* lastJ, const int32_t* mod, int64_t nmod,
-                                                       const int64_t* off, const int64_t* doff, int32_t* drows,
-                                                       int vb, int32_t* cir, void* cnum) {
-  __shared__ uint64_t s_key[kAsgnMaxInsert];
-  __shared__ int64_t s_src[kAsgnMaxInsert];
+                                                       const int32_t* lastJ, const int32_t* mod, const int32_t* list,
+                                                       int64_t nlist, const int64_t* off, const int64_t* doff,
+                                                       int32_t* drows, int vb, int32_t* cir, void* cnum) {
+  __shared__ uint64_t s_key[CAP];
+  __shared__ int64_t s_src[CAP];
   __shared__ int64_t red[256 / kWave + 1];
-  for (int64_t u = blockIdx.x; u < nmod; u += gridDim.x) {
+  for (int64_t w = blockIdx.x; w < nlist; w += gridDim.x) {
+    const int64_t u = list ? list[w] : w;
     const int32_t j = mod[u];
     const int64_t a0 = slot_begin(A, j), a1 = slot_begin(A, j + 1);
     const int32_t q = lastJ[j];
@@ -170,13 +183,16 @@ __global__ void __launch_bounds__(256) k_asgn_mod_fill(Operand A, Operand B, con
       }
       int64_t tot;
       const int64_t ex = block_excl_scan(take, red, &tot);
-      if (take && nins + ex < kAsgnMaxInsert) {
+      if (take && nins + ex < CAP) {
         s_key[nins + ex] = ((uint64_t)(uint32_t)row << 32) | (uint32_t)(nins + ex);
         s_src[nins + ex] = e;
       }
       nins += tot;
     }
-    if (nins > kAsgnMaxInsert) nins = kAsgnMaxInsert;
+    if (nins > CAP) {  // uniform: a column of the other variant
+      __syncthreads();
+      continue;
+    }
     int p2 = 1;
     while (p2 < nins) p2 <<= 1;
     for (int s = (int)nins + threadIdx.x; s < p2; s += blockDim.x) s_key[s] = ~0ull;
@@ -279,6 +295,9 @@ struct ExtAddPlan : spx_plan {
   int64_t* cnt = nullptr;    // [n]
   int64_t* off = nullptr;    // [n+1] = C.cp
   int32_t* mod = nullptr;    // [n] modified columns
+  int32_t* big = nullptr;    // modified columns (indices into mod) above kAsgnSmall landing entries
+  unsigned long long* nbig_d = nullptr;
+  int64_t nbig = 0;
   unsigned* err = nullptr;
   unsigned long long* nmod_d = nullptr;
 };
@@ -355,18 +374,25 @@ __device__ __forceinline__ int64_t rows_below(const int32_t* col, int64_t len, i
 //      fill pass: A's entries move down by the new rows below them and add
 //      the values landing on their row; each new row takes the sum of its
 //      landing values.  Sums run in key order (B's storage order).
-template <bool kFill, bool kVals, typename T, class Acc>
+// CAP bounds the landing entries held in LDS.  The one-wave variant
+// (CAP = kAsgnSmall, `list` NULL) runs over every modified column; in the
+// count pass it hands larger columns to the `big` list, which the 256-thread
+// variant (CAP = kAsgnMaxInsert) then serves (its length read from *nlist_d).
+template <bool kFill, bool kVals, int CAP, typename T, class Acc>
 __global__ void __launch_bounds__(256) k_ea_column(Operand A, Operand B, const int32_t* I, const int32_t* mod,
-                                                   int64_t nmod, const int64_t* qoff, const int32_t* qlist,
-                                                   int64_t* cnt, const int64_t* off, unsigned* err, int32_t* cir,
-                                                   T* cnum) {
-  __shared__ uint64_t s_key[kAsgnMaxInsert];
-  __shared__ int32_t s_head[kAsgnMaxInsert + 1];  // sorted position of each distinct row's first key
-  __shared__ int32_t s_nin[kAsgnMaxInsert + 1];   // distinct rows before k that A(:,j) lacks
+                                                   const int32_t* list, const unsigned long long* nlist_d,
+                                                   int64_t nlist_h, const int64_t* qoff, const int32_t* qlist,
+                                                   int64_t* cnt, const int64_t* off, int32_t* big,
+                                                   unsigned long long* nbig, unsigned* err, int32_t* cir, T* cnum) {
+  __shared__ uint64_t s_key[CAP];
+  __shared__ int32_t s_head[CAP + 1];  // sorted position of each distinct row's first key
+  __shared__ int32_t s_nin[CAP + 1];   // distinct rows before k that A(:,j) lacks
   __shared__ int64_t red[256 / kWave + 1];
   const T* anum = static_cast<const T*>(A.num);
   const T* bnum = static_cast<const T*>(B.num);
-  for (int64_t u = blockIdx.x; u < nmod; u += gridDim.x) {
+  const int64_t nl = nlist_d ? (int64_t)*nlist_d : nlist_h;
+  for (int64_t w = blockIdx.x; w < nl; w += gridDim.x) {
+    const int64_t u = list ? list[w] : w;
     const int32_t j = mod[u];
     const int64_t a0 = slot_begin(A, j), a1 = slot_begin(A, j + 1);
     const int32_t* acol = A.ir + a0;
@@ -377,12 +403,17 @@ __global__ void __launch_bounds__(256) k_ea_column(Operand A, Operand B, const i
       const int64_t b0 = slot_begin(B, q), b1 = slot_begin(B, q + 1);
       for (int64_t e = b0 + threadIdx.x; e < b1; e += blockDim.x) {
         const int64_t slot = nins + (e - b0);
-        if (slot < kAsgnMaxInsert) s_key[slot] = ((uint64_t)(uint32_t)I[B.ir[e]] << 32) | (uint32_t)e;
+        if (slot < CAP) s_key[slot] = ((uint64_t)(uint32_t)I[B.ir[e]] << 32) | (uint32_t)e;
       }
       nins += b1 - b0;
     }
-    if (nins > kAsgnMaxInsert) {  // uniform across the workgroup
-      if (!kFill && threadIdx.x == 0) atomicOr(err, 4u);
+    if (nins > CAP) {  // uniform across the workgroup
+      if (!kFill && threadIdx.x == 0) {
+        if (CAP < kAsgnMaxInsert)
+          big[atomicAdd(nbig, 1ull)] = (int32_t)u;
+        else
+          atomicOr(err, 4u);
+      }
       __syncthreads();
       continue;
     }
@@ -458,12 +489,25 @@ __global__ void __launch_bounds__(256) k_ea_column(Operand A, Operand B, const i
   }
 }
 
+// One-wave variant over all modified columns, then the 256-thread variant
+// over the big list (its length is on the device in the count pass; the fill
+// pass knows it from the plan).
 template <bool kFill, bool kVals, typename T, class Acc>
 int launch_ea(const ExtAddPlan* P, int32_t* cir, void* cnum, hipStream_t st) {
   const int cus = device_cu_count();
-  k_ea_column<kFill, kVals, T, Acc><<<(unsigned)std::min<int64_t>(P->nmod, (int64_t)cus * 4), 256, 0, st>>>(
-      P->A, P->B, P->I, P->mod, P->nmod, P->qoff, P->qlist, P->cnt, P->off, P->err, cir, static_cast<T*>(cnum));
+  T* out = static_cast<T*>(cnum);
+  k_ea_column<kFill, kVals, kAsgnSmall, T, Acc><<<(unsigned)std::min<int64_t>(P->nmod, (int64_t)cus * 32), 64, 0,
+                                                  st>>>(P->A, P->B, P->I, P->mod, nullptr, nullptr, P->nmod, P->qoff,
+                                                        P->qlist, P->cnt, P->off, P->big, P->nbig_d, P->err, cir,
+                                                        out);
   SPX_HIP(hipGetLastError());
+  if (!kFill || P->nbig > 0) {
+    const int64_t grid = kFill ? std::min<int64_t>(P->nbig, (int64_t)cus * 4) : (int64_t)cus * 4;
+    k_ea_column<kFill, kVals, kAsgnMaxInsert, T, Acc><<<(unsigned)grid, 256, 0, st>>>(
+        P->A, P->B, P->I, P->mod, P->big, kFill ? nullptr : P->nbig_d, P->nbig, P->qoff, P->qlist, P->cnt, P->off,
+        P->big, P->nbig_d, P->err, cir, out);
+    SPX_HIP(hipGetLastError());
+  }
   return SPX_OK;
 }
 
@@ -552,21 +596,26 @@ extern "C" int spx_spasgn_plan(const spx_ctx* ctx, const spx_mat* A, const int32
   P->nmod = (int64_t)nmod_h;
   SPX_TRY(scr.get_n(std::max<int64_t>(P->nmod, 1), &P->dcnt));
   SPX_TRY(scr.get_n(P->nmod + 1, &P->doff));
+  SPX_TRY(scr.get_n(std::max<int64_t>(P->nmod, 1), &P->big));
+  SPX_TRY(scr.get_n(1, &P->nbig_d));
+  SPX_TRY(fill_i64((int64_t*)P->nbig_d, 1, 0, st));
   if (P->nmod > 0) {
-    k_asgn_mod_count<<<(unsigned)std::min<int64_t>(P->nmod, (int64_t)cus * 8), 256, 0, st>>>(
-        P->A, P->B, I, P->lastI, P->lastJ, P->mod, P->nmod, P->cnt, P->dcnt, P->err);
+    k_asgn_mod_count<<<(unsigned)std::min<int64_t>(P->nmod, (int64_t)cus * 32), 64, 0, st>>>(
+        P->A, P->B, I, P->lastI, P->lastJ, P->mod, P->nmod, P->cnt, P->dcnt, P->big, P->nbig_d, P->err);
     SPX_HIP(hipGetLastError());
   }
   SPX_TRY(exclusive_scan(LoadI64{P->cnt}, n, P->off, scr, st));
   SPX_TRY(exclusive_scan(LoadI64{P->dcnt}, P->nmod, P->doff, scr, st));
-  int64_t tail[2] = {0, 0};
+  int64_t tail[3] = {0, 0, 0};
   SPX_HIP(hipMemcpyAsync(&tail[0], P->off + n, 8, hipMemcpyDeviceToHost, st));
   SPX_HIP(hipMemcpyAsync(&tail[1], P->doff + P->nmod, 8, hipMemcpyDeviceToHost, st));
+  SPX_HIP(hipMemcpyAsync(&tail[2], P->nbig_d, 8, hipMemcpyDeviceToHost, st));
   SPX_HIP(hipMemcpyAsync(&err_h, P->err, 4, hipMemcpyDeviceToHost, st));
   SPX_HIP(hipStreamSynchronize(st));
   if (err_h & 4u) return fail(SPX_EUNSUPPORTED, "a column of B inserts more than 4096 rows");
   P->nnz = tail[0];
   P->ndrop = tail[1];
+  P->nbig = tail[2];
   SPX_TRY(scr.get_n(std::max<int64_t>(P->ndrop, 1), &P->drows));
   if (nnz_c) *nnz_c = P->nnz;
   *plan = guard.release();
@@ -594,8 +643,15 @@ extern "C" int spx_spasgn_exec(spx_plan* plan, spx_mat* C) {
     SPX_HIP(hipGetLastError());
   }
   if (P->nmod > 0) {
-    k_asgn_mod_fill<<<(unsigned)std::min<int64_t>(P->nmod, (int64_t)cus * 2), 256, 0, st>>>(
-        P->A, P->B, P->I, P->lastI, P->lastJ, P->mod, P->nmod, P->off, P->doff, P->drows, vb, C->ir, C->num);
+    k_asgn_mod_fill<kAsgnSmall><<<(unsigned)std::min<int64_t>(P->nmod, (int64_t)cus * 32), 64, 0, st>>>(
+        P->A, P->B, P->I, P->lastI, P->lastJ, P->mod, nullptr, P->nmod, P->off, P->doff, P->drows, vb, C->ir,
+        C->num);
+    SPX_HIP(hipGetLastError());
+  }
+  if (P->nbig > 0) {
+    k_asgn_mod_fill<kAsgnMaxInsert><<<(unsigned)std::min<int64_t>(P->nbig, (int64_t)cus * 2), 256, 0, st>>>(
+        P->A, P->B, P->I, P->lastI, P->lastJ, P->mod, P->big, P->nbig, P->off, P->doff, P->drows, vb, C->ir,
+        C->num);
     SPX_HIP(hipGetLastError());
   }
   k_asgn_write_cp<<<grid_for(P->A.n + 1, 256, 65536), 256, 0, st>>>(P->off, P->A.n, C->cp, C->ptr_t);
@@ -677,10 +733,14 @@ extern "C" int spx_extend_add_plan(const spx_ctx* ctx, const spx_mat* A, const i
     k_scatter_q<<<grid_for(lenJ, 256, 4096), 256, 0, st>>>(J, lenJ, P->qoff, P->qcnt, P->qlist);
     SPX_HIP(hipGetLastError());
   }
+  SPX_TRY(scr.get_n(std::max<int64_t>(P->nmod, 1), &P->big));
+  SPX_TRY(scr.get_n(1, &P->nbig_d));
+  SPX_TRY(fill_i64((int64_t*)P->nbig_d, 1, 0, st));
   if (P->nmod > 0) SPX_TRY(dispatch_ea<false>(P, nullptr, nullptr, st));
   SPX_TRY(exclusive_scan(LoadI64{P->cnt}, n, P->off, scr, st));
   int64_t total = 0;
   SPX_HIP(hipMemcpyAsync(&total, P->off + n, 8, hipMemcpyDeviceToHost, st));
+  SPX_HIP(hipMemcpyAsync(&P->nbig, P->nbig_d, 8, hipMemcpyDeviceToHost, st));
   SPX_HIP(hipMemcpyAsync(&err_h, P->err, 4, hipMemcpyDeviceToHost, st));
   SPX_HIP(hipStreamSynchronize(st));
   if (err_h & 4u) return fail(SPX_EUNSUPPORTED, "a column of C receives more than 4096 entries of B");

@@ -90,6 +90,7 @@ __global__ void k_ref_count(const Operand A, const int64_t* qa0, const int32_t* 
   const int lane = lane_id();
   const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kWave;
   const int64_t nw = (int64_t)gridDim.x * blockDim.x / kWave;
+  unsigned long long n0 = 0, n1 = 0, n2 = 0, n3 = 0;  // class counts of this wave's columns
   for (int64_t q = wave; q < lenJ; q += nw) {
     const int64_t a0 = qa0[q];
     const int32_t al = qlen[q];
@@ -99,11 +100,18 @@ __global__ void k_ref_count(const Operand A, const int64_t* qa0, const int32_t* 
       s += rptr[i + 1] - rptr[i];
     }
     s = wave_sum(s);
-    if (lane == 0) {
-      cnt[q] = s;
-      const int c = s == 0 ? kClsEmpty : s <= kRefSmall ? kClsSmall : s <= kRefMedium ? kClsMedium : kClsLarge;
-      atomicAdd(&clscount[c], 1ull);
-    }
+    const int c = s == 0 ? kClsEmpty : s <= kRefSmall ? kClsSmall : s <= kRefMedium ? kClsMedium : kClsLarge;
+    n0 += c == kClsEmpty;
+    n1 += c == kClsSmall;
+    n2 += c == kClsMedium;
+    n3 += c == kClsLarge;
+    if (lane == 0) cnt[q] = s;
+  }
+  if (lane == 0) {
+    if (n0) atomicAdd(&clscount[kClsEmpty], n0);
+    if (n1) atomicAdd(&clscount[kClsSmall], n1);
+    if (n2) atomicAdd(&clscount[kClsMedium], n2);
+    if (n3) atomicAdd(&clscount[kClsLarge], n3);
   }
 }
 
@@ -124,7 +132,10 @@ __global__ void k_cls_fill(const int64_t* cnt, int64_t lenJ, const int64_t* clso
   for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < lenJ; q += (int64_t)gridDim.x * blockDim.x) {
     const int64_t s = cnt[q];
     const int c = s == 0 ? kClsEmpty : s <= kRefSmall ? kClsSmall : s <= kRefMedium ? kClsMedium : kClsLarge;
-    list[clsoff[c] + (int64_t)atomicAdd(&fill[c], 1ull)] = (int32_t)q;
+    for (int k = 0; k < kNumCls; ++k) {  // one atomic per wave and class
+      const unsigned long long slot = wave_claim(&fill[k], c == k);
+      if (c == k) list[clsoff[k] + (int64_t)slot] = (int32_t)q;
+    }
   }
 }
 

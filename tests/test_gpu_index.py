@@ -90,6 +90,27 @@ def test_spasgn_small_with_repeats(spx):
         spasgn_check(spx, A, I, J, B)
 
 
+def test_spasgn_insert_sizes_around_the_wave_limit(spx):
+    # inserted rows per column of 1, 64, 65, 100 and 3000 exercise both the
+    # one-wave and the workgroup variants of the modified-column kernels
+    rng = np.random.default_rng(19)
+    A = W.rmat(12, 8, seed=18, values="edge_id")
+    I = rng.choice(A.m, 3500, replace=False).astype(np.int32)
+    J = rng.choice(A.n, 6, replace=False).astype(np.int32)
+    sizes = [1, 64, 65, 100, 3000, 0]
+    rows = np.concatenate([np.sort(rng.choice(3500, k, replace=False)) for k in sizes])
+    cols = np.repeat(np.arange(6), sizes)
+    B = W.from_triples(rows, cols, (1 << 40) + np.arange(rows.size, dtype=np.int64), 3500, 6)
+    spasgn_check(spx, A, I, J, B)
+    extend_add_check(spx, A, I, J, B)
+    Jr = np.concatenate([J, J[:3]]).astype(np.int32)  # repeated columns: landing entries add up
+    extra = np.sort(rng.choice(3500, 70, replace=False))  # column 7 lands on J[1] too
+    Br = W.from_triples(np.concatenate([rows, extra]), np.concatenate([cols, np.full(70, 7)]),
+                        np.arange(rows.size + 70, dtype=np.int64), 3500, 9)
+    spasgn_check(spx, A, I, Jr, Br)
+    extend_add_check(spx, A, I, Jr, Br)
+
+
 def test_spasgn_roundtrip(spx):
     A = W.rmat(12, 8, seed=31, values="edge_id")
     I = W.index_vector(500, A.m, seed=1, repeat_frac=0.0)
