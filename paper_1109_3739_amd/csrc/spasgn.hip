@@ -51,6 +51,7 @@ struct SpasgnPlan : spx_plan {
   int32_t* big = nullptr;    // modified columns (indices into mod) above kAsgnSmall inserts
   unsigned long long* nbig_d = nullptr;
   int64_t nbig = 0;
+  int64_t* tstart = nullptr;  // first column of every copy tile of A
   unsigned* err = nullptr;
   unsigned long long* nmod_d = nullptr;
 };
@@ -65,14 +66,38 @@ __global__ void k_last_occ(const int32_t* v, int64_t len, int64_t bound, int32_t
   }
 }
 
-// Unmodified columns keep their length; modified ones are listed.
-__global__ void k_asgn_cols(Operand A, const int32_t* lastJ, int64_t* cnt, int32_t* mod, unsigned long long* nmod) {
-  for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < A.n; j += (int64_t)gridDim.x * blockDim.x) {
-    const bool modified = lastJ[j] >= 0;
-    cnt[j] = modified ? 0 : slot_begin(A, j + 1) - slot_begin(A, j);
-    const unsigned long long slot = wave_claim(nmod, modified);
-    if (modified) mod[slot] = (int32_t)j;
-  }
+// Unmodified columns keep their length (modified ones are counted later).
+__global__ void k_asgn_cols(Operand A, const int32_t* lastJ, int64_t* cnt) {
+  for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < A.n; j += (int64_t)gridDim.x * blockDim.x)
+    cnt[j] = lastJ[j] >= 0 ? 0 : slot_begin(A, j + 1) - slot_begin(A, j);
+}
+
+// 1 for a column that receives B's entries.
+struct LoadModified {
+  const int32_t* lastJ;
+  __device__ int64_t operator()(int64_t j) const { return lastJ[j] >= 0; }
+};
+
+// The modified columns in ascending order, at their scan positions.
+__global__ void k_list_modified(const int32_t* lastJ, int64_t n, const int64_t* pos, int32_t* mod) {
+  for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x)
+    if (lastJ[j] >= 0) mod[pos[j]] = (int32_t)j;
+}
+
+// Lists the modified columns and leaves their number in *nmod.
+int list_modified(const Operand& A, const int32_t* lastJ, int64_t* cnt, int32_t* mod, unsigned long long* nmod,
+                  Scratch& scr, hipStream_t st) {
+  const int64_t n = A.n;
+  if (n == 0) return fill_i64(reinterpret_cast<int64_t*>(nmod), 1, 0, st);
+  k_asgn_cols<<<grid_for(n, 256, 65536), 256, 0, st>>>(A, lastJ, cnt);
+  SPX_HIP(hipGetLastError());
+  int64_t* pos = nullptr;
+  SPX_TRY(scr.get_n(n + 1, &pos));
+  SPX_TRY(exclusive_scan(LoadModified{lastJ}, n, pos, scr, st));
+  k_list_modified<<<grid_for(n, 256, 65536), 256, 0, st>>>(lastJ, n, pos, mod);
+  SPX_HIP(hipGetLastError());
+  SPX_HIP(hipMemcpyAsync(nmod, pos + n, 8, hipMemcpyDeviceToDevice, st));
+  return SPX_OK;
 }
 
 // Per modified column: kept A entries, dropped ones, inserted B entries.
@@ -107,44 +132,75 @@ __global__ void __launch_bounds__(256) k_asgn_mod_count(Operand A, Operand B, co
 }
 
 // Copies the unmodified columns: each workgroup takes a tile of A's
-// entries, finds their columns by binary search over A's pointers and
-// writes them at C's offsets.
-__global__ void __launch_bounds__(256) k_asgn_copy(Operand A, const int32_t* lastJ, const int64_t* off, int vb,
-                                                   int32_t* cir, void* cnum) {
-  __shared__ int64_t s_range[2];
+// entries, whose first column the plan has found (k_tile_starts).  One pass
+// over the tile's columns then writes,
+// in LDS, each column's output shift off[c] - cp[c] (a sentinel for the
+// modified columns) and the column of every entry of the tile, so the
+// entries are copied with no further pointer loads.  Tiles spanning more
+// than kCopyMapCols columns (long runs of empty columns) search each
+// entry's column instead.
+constexpr int kCopyMapCols = 2048;
+constexpr int64_t kCopySkip = INT64_MIN;
+
+// tstart[t] = the column holding entry t * kCopyTile (t < number of tiles);
+// tstart[nt] = n - 1.  One pass over the column pointers.
+__global__ void k_tile_starts(Operand A, int64_t nt, int64_t* tstart) {
+  for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < A.n; c += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t s0 = slot_begin(A, c), s1 = slot_begin(A, c + 1);
+    for (int64_t t = (s0 + kCopyTile - 1) / kCopyTile; t * kCopyTile < s1; ++t) tstart[t] = c;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) tstart[nt] = A.n - 1;
+}
+
+int tile_starts(const Operand& A, Scratch& scr, hipStream_t st, int64_t** tstart) {
+  const int64_t nt = ceil_div(A.nnz, kCopyTile);
+  SPX_TRY(scr.get_n(nt + 1, tstart));
+  if (A.n > 0) {
+    k_tile_starts<<<grid_for(A.n, 256, 65536), 256, 0, st>>>(A, nt, *tstart);
+    SPX_HIP(hipGetLastError());
+  }
+  return SPX_OK;
+}
+
+__global__ void __launch_bounds__(256) k_asgn_copy(Operand A, const int64_t* tstart, const int32_t* lastJ,
+                                                   const int64_t* off, int vb, int32_t* cir, void* cnum) {
+  __shared__ int64_t s_shift[kCopyMapCols];
+  __shared__ int16_t s_col[kCopyTile];
   const int64_t nt = (A.nnz + kCopyTile - 1) / kCopyTile;
   for (int64_t tile = blockIdx.x; tile < nt; tile += gridDim.x) {
     const int64_t e0 = tile * kCopyTile;
     const int64_t e1 = e0 + kCopyTile < A.nnz ? e0 + kCopyTile : A.nnz;
-    if (threadIdx.x < 2) {
-      // column of entry e0 (resp. e1-1): last j with cp[j] <= e
-      const int64_t e = threadIdx.x == 0 ? e0 : e1 - 1;
-      int64_t lo = 0, hi = A.n;  // find first j with cp[j+1] > e
-      while (lo < hi) {
-        const int64_t mid = (lo + hi) >> 1;
-        if (slot_begin(A, mid + 1) <= e)
-          lo = mid + 1;
-        else
-          hi = mid;
+    // the tile's columns lie in [j0, j1] (j1: the next tile's first column)
+    const int64_t j0 = tstart[tile], j1 = tstart[tile + 1];
+    const bool mapped = j1 - j0 < kCopyMapCols;
+    if (mapped) {
+      for (int64_t c = j0 + threadIdx.x; c <= j1; c += blockDim.x) {
+        const int64_t s0 = slot_begin(A, c), s1 = slot_begin(A, c + 1);
+        s_shift[c - j0] = lastJ[c] >= 0 ? kCopySkip : off[c] - s0;
+        for (int64_t e = s0 > e0 ? s0 : e0; e < s1 && e < e1; ++e) s_col[e - e0] = (int16_t)(c - j0);
       }
-      s_range[threadIdx.x] = lo;
-    }
-    __syncthreads();
-    const int64_t j0 = s_range[0], j1 = s_range[1];
-    for (int64_t e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
-      int64_t lo = j0, hi = j1;
-      while (lo < hi) {
-        const int64_t mid = (lo + hi) >> 1;
-        if (slot_begin(A, mid + 1) <= e)
-          lo = mid + 1;
-        else
-          hi = mid;
+      __syncthreads();
+      for (int64_t e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
+        const int64_t sh = s_shift[s_col[e - e0]];
+        if (sh == kCopySkip) continue;
+        cir[e + sh] = A.ir[e];
+        copy_value(A.num, e, cnum, e + sh, vb);
       }
-      const int64_t j = lo;
-      if (lastJ[j] >= 0) continue;
-      const int64_t o = off[j] + (e - slot_begin(A, j));
-      cir[o] = A.ir[e];
-      copy_value(A.num, e, cnum, o, vb);
+    } else {
+      for (int64_t e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
+        int64_t lo = j0, hi = j1;
+        while (lo < hi) {
+          const int64_t mid = (lo + hi) >> 1;
+          if (slot_begin(A, mid + 1) <= e)
+            lo = mid + 1;
+          else
+            hi = mid;
+        }
+        if (lastJ[lo] >= 0) continue;
+        const int64_t o = off[lo] + (e - slot_begin(A, lo));
+        cir[o] = A.ir[e];
+        copy_value(A.num, e, cnum, o, vb);
+      }
     }
     __syncthreads();
   }
@@ -298,6 +354,7 @@ struct ExtAddPlan : spx_plan {
   int32_t* big = nullptr;    // modified columns (indices into mod) above kAsgnSmall landing entries
   unsigned long long* nbig_d = nullptr;
   int64_t nbig = 0;
+  int64_t* tstart = nullptr;  // first column of every copy tile of A
   unsigned* err = nullptr;
   unsigned long long* nmod_d = nullptr;
 };
@@ -582,10 +639,8 @@ extern "C" int spx_spasgn_plan(const spx_ctx* ctx, const spx_mat* A, const int32
   SPX_TRY(scr.get_n(std::max<int64_t>(n, 1), &P->cnt));
   SPX_TRY(scr.get_n(n + 1, &P->off));
   SPX_TRY(scr.get_n(std::max<int64_t>(n, 1), &P->mod));
-  if (n > 0) {
-    k_asgn_cols<<<grid_for(n, 256, 65536), 256, 0, st>>>(P->A, P->lastJ, P->cnt, P->mod, P->nmod_d);
-    SPX_HIP(hipGetLastError());
-  }
+  SPX_TRY(list_modified(P->A, P->lastJ, P->cnt, P->mod, P->nmod_d, scr, st));
+  SPX_TRY(tile_starts(P->A, scr, st, &P->tstart));
   unsigned long long nmod_h = 0;
   unsigned err_h = 0;
   SPX_HIP(hipMemcpyAsync(&nmod_h, P->nmod_d, 8, hipMemcpyDeviceToHost, st));
@@ -638,8 +693,8 @@ extern "C" int spx_spasgn_exec(spx_plan* plan, spx_mat* C) {
   const int cus = device_cu_count();
   if (P->A.nnz > 0) {
     const int64_t tiles = ceil_div(P->A.nnz, kCopyTile);
-    k_asgn_copy<<<(unsigned)std::min<int64_t>(tiles, (int64_t)cus * 8), 256, 0, st>>>(P->A, P->lastJ, P->off, vb,
-                                                                                       C->ir, C->num);
+    k_asgn_copy<<<(unsigned)std::min<int64_t>(tiles, (int64_t)cus * 8), 256, 0, st>>>(P->A, P->tstart, P->lastJ,
+                                                                                       P->off, vb, C->ir, C->num);
     SPX_HIP(hipGetLastError());
   }
   if (P->nmod > 0) {
@@ -714,10 +769,8 @@ extern "C" int spx_extend_add_plan(const spx_ctx* ctx, const spx_mat* A, const i
   SPX_TRY(scr.get_n(std::max<int64_t>(n, 1), &P->cnt));
   SPX_TRY(scr.get_n(n + 1, &P->off));
   SPX_TRY(scr.get_n(std::max<int64_t>(n, 1), &P->mod));
-  if (n > 0) {
-    k_asgn_cols<<<grid_for(n, 256, 65536), 256, 0, st>>>(P->A, P->lastJ, P->cnt, P->mod, P->nmod_d);
-    SPX_HIP(hipGetLastError());
-  }
+  SPX_TRY(list_modified(P->A, P->lastJ, P->cnt, P->mod, P->nmod_d, scr, st));
+  SPX_TRY(tile_starts(P->A, scr, st, &P->tstart));
   unsigned long long nmod_h = 0;
   unsigned err_h = 0;
   SPX_HIP(hipMemcpyAsync(&nmod_h, P->nmod_d, 8, hipMemcpyDeviceToHost, st));
@@ -766,8 +819,8 @@ extern "C" int spx_extend_add_exec(spx_plan* plan, spx_mat* C) {
   const int cus = device_cu_count();
   if (P->A.nnz > 0) {
     const int64_t tiles = ceil_div(P->A.nnz, kCopyTile);
-    k_asgn_copy<<<(unsigned)std::min<int64_t>(tiles, (int64_t)cus * 8), 256, 0, st>>>(P->A, P->lastJ, P->off, vb,
-                                                                                       C->ir, C->num);
+    k_asgn_copy<<<(unsigned)std::min<int64_t>(tiles, (int64_t)cus * 8), 256, 0, st>>>(P->A, P->tstart, P->lastJ,
+                                                                                       P->off, vb, C->ir, C->num);
     SPX_HIP(hipGetLastError());
   }
   if (P->nmod > 0) SPX_TRY(dispatch_ea<true>(P, C->ir, C->num, st));

@@ -107,12 +107,17 @@ __global__ void k_ref_count(const Operand A, const int64_t* qa0, const int32_t* 
     n3 += c == kClsLarge;
     if (lane == 0) cnt[q] = s;
   }
+  __shared__ unsigned long long s_cls[kNumCls];  // the workgroup's class counts
+  if (threadIdx.x < kNumCls) s_cls[threadIdx.x] = 0;
+  __syncthreads();
   if (lane == 0) {
-    if (n0) atomicAdd(&clscount[kClsEmpty], n0);
-    if (n1) atomicAdd(&clscount[kClsSmall], n1);
-    if (n2) atomicAdd(&clscount[kClsMedium], n2);
-    if (n3) atomicAdd(&clscount[kClsLarge], n3);
+    if (n0) atomicAdd(&s_cls[kClsEmpty], n0);
+    if (n1) atomicAdd(&s_cls[kClsSmall], n1);
+    if (n2) atomicAdd(&s_cls[kClsMedium], n2);
+    if (n3) atomicAdd(&s_cls[kClsLarge], n3);
   }
+  __syncthreads();
+  if (threadIdx.x < kNumCls && s_cls[threadIdx.x]) atomicAdd(&clscount[threadIdx.x], s_cls[threadIdx.x]);
 }
 
 __global__ void k_cls_offsets(unsigned long long* clscount, int64_t* clsoff, unsigned long long* fill) {
@@ -390,7 +395,7 @@ extern "C" int spx_spref_plan(const spx_ctx* ctx, const spx_mat* A, const int32_
   if (lenJ > 0) {
     k_col_info<<<grid_for(lenJ, 256, 4096), 256, 0, st>>>(P->A, aux, chunk, J, lenJ, P->qa0, P->qlen);
     SPX_HIP(hipGetLastError());
-    k_ref_count<<<grid_for(lenJ * kWave, 256, (int64_t)cus * 32), 256, 0, st>>>(P->A, P->qa0, P->qlen, P->rptr, lenJ,
+    k_ref_count<<<grid_for(lenJ * kWave, 256, (int64_t)cus * 8), 256, 0, st>>>(P->A, P->qa0, P->qlen, P->rptr, lenJ,
                                                                                 P->cnt, clscount);
     SPX_HIP(hipGetLastError());
   }
