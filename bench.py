@@ -17,6 +17,11 @@ on the library's stream over the timed steps), and the CPU oracle timed on
 a bounded sample of the same product.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-extra] [--no-cpu-baseline]
+    python bench.py --extra-only {latency,stages,tall,index,restriction}
+
+The other workloads (printed under "extra") give context: launch-bound
+latency, the Sparse SUMMA stage block and stage sum, the tall-skinny
+product, SpRef / SpAsgn / extend-add, and the restriction S A S^T.
 """
 from __future__ import annotations
 
@@ -102,161 +107,172 @@ def cpu_baseline(A, target_s=15.0):
     }
 
 
-def extra_workloads(spx, W, torch):
-    """Latency / bandwidth of the other workloads of the path (context)."""
+def extra_workloads(spx, W, torch, only=None):
+    """Latency / bandwidth of the other workloads of the path (context).
+    ``only``: run one group (latency, stages, tall, index, restriction)."""
     import numpy as np
     out = {}
     sync = torch.cuda.synchronize
 
-    # Erdos-Renyi 4096 x 4096, 8 per column: launch-bound latency
-    E = W.erdos_renyi(4096, 4096, 8, seed=1)
-    dE = spx.from_host(E)
-    for sr in ("plus_times", "min_plus"):
-        spx.spgemm(dE, dE, sr)
-        ts = []
-        for _ in range(10):
-            sync()
-            t0 = time.perf_counter()
+    def want(name):
+        return only is None or only == name
+
+    if want("stages") or want("tall"):
+        A = W.rmat(20, 8, seed=20)
+
+    if want("latency"):
+        # Erdos-Renyi 4096 x 4096, 8 per column: launch-bound latency
+        E = W.erdos_renyi(4096, 4096, 8, seed=1)
+        dE = spx.from_host(E)
+        for sr in ("plus_times", "min_plus"):
             spx.spgemm(dE, dE, sr)
-            sync()
-            ts.append(time.perf_counter() - t0)
-        out[f"er4096_{sr}_ms"] = round(1e3 * statistics.median(ts), 4)
+            ts = []
+            for _ in range(10):
+                sync()
+                t0 = time.perf_counter()
+                spx.spgemm(dE, dE, sr)
+                sync()
+                ts.append(time.perf_counter() - t0)
+            out[f"er4096_{sr}_ms"] = round(1e3 * statistics.median(ts), 4)
 
-    # one GPU's share of an 8x8 Sparse SUMMA stage: A00 * A00 in DCSC
-    A = W.rmat(20, 8, seed=20)
-    b = A.n // 8
-    blk = W.column_block(A, 0, b, 0, b)
-    dB = spx.csc_to_dcsc(spx.from_host(blk))
-    p = spx.GemmPlan(dB, dB, out_fmt=spx.DCSC)
-    C = p.execute()
-    mults = p.info()["mults"]
-    p.close()
-
-    def stage():
-        q = spx.GemmPlan(dB, dB, out_fmt=spx.DCSC)
-        q.execute(C)
-        q.close()
-
-    for _ in range(3):
-        stage()
-    t = time_steps(stage, 10, sync)
-    out["stage_block_dcsc_ms"] = round(1e3 * t, 4)
-    out["stage_block_gflops"] = round(2 * mults / t / 1e9, 3)
-    out["stage_block_nnz_c"] = int(C.nnz)
-    del C
-
-    # all 8 stages of that processor: C_00 = sum_k A_0k * A_k0 as one stage-sum
-    # plan, against the 8 stage products formed separately (partials not merged)
-    As = [spx.csc_to_dcsc(spx.from_host(W.column_block(A, 0, b, k * b, (k + 1) * b))) for k in range(8)]
-    Bs = [spx.csc_to_dcsc(spx.from_host(W.column_block(A, k * b, (k + 1) * b, 0, b))) for k in range(8)]
-    sp = spx.StageSumPlan(As, Bs, out_fmt=spx.DCSC)
-    S = sp.execute()
-    smults = sp.info()["mults"]
-    sp.close()
-
-    def stage_sum():
-        q = spx.StageSumPlan(As, Bs, out_fmt=spx.DCSC)
-        q.execute(S)
-        q.close()
-
-    def stages_apart():
-        for X, Y in zip(As, Bs):
-            q = spx.GemmPlan(X, Y, out_fmt=spx.DCSC)
-            q.execute()
-            q.close()
-
-    for _ in range(2):
-        stage_sum()
-        stages_apart()
-    t = time_steps(stage_sum, 10, sync)
-    t_apart = time_steps(stages_apart, 5, sync)
-    out["summa_8x8_c00"] = {"stages": 8, "ms": round(1e3 * t, 4), "gflops": round(2 * smults / t / 1e9, 3),
-                            "mults": smults, "nnz_c": int(S.nnz),
-                            "stage_products_apart_ms": round(1e3 * t_apart, 4)}
-    del S, As, Bs
-
-    # R-MAT scale 20 times a tall-skinny Erdos-Renyi matrix (n/k = 8192, d2
-    # nonzeros per column): the multi-source BFS frontier expansion
-    dA = spx.from_host(A)
-    tall = {}
-    for d2 in (1, 10, 100, 1000, 10000, 100000):
-        F = W.erdos_renyi(A.n, A.n // 8192, d2, seed=300 + d2)
-        dF = spx.from_host(F)
-        Cf = spx.spgemm(dA, dF)
-        mults = int(np.diff(A.cp)[F.ir].sum())
-        t = time_steps(lambda: spx.spgemm(dA, dF), 5, sync)
-        tall[str(d2)] = {"ms": round(1e3 * t, 4), "gflops": round(2 * mults / t / 1e9, 3), "mults": mults,
-                         "nnz_c": int(Cf.nnz)}
-        del Cf, dF
-    out["tall_skinny_rmat20_x_er"] = tall
-
-    # SpRef / SpAsgn on R-MAT scale 22, edge factor 16, int64 edge ids
-    A3 = W.rmat(22, 16, seed=22, values="edge_id")
-    I = W.index_vector(1 << 18, A3.m, seed=221)
-    J = W.index_vector(1 << 18, A3.n, seed=222)
-    Bp = W.erdos_renyi(1 << 18, 1 << 18, 4, seed=223, values="id40")
-    dA3, dI, dJ, dBp = spx.from_host(A3), torch.from_numpy(I).cuda(), torch.from_numpy(J).cuda(), spx.from_host(Bp)
-    R = spx.spref(dA3, dI, dJ)
-    t = time_steps(lambda: spx.spref(dA3, dI, dJ), 5, sync)
-    deg = np.diff(A3.cp)
-    gathered = int(deg[J].sum())
-    ref_bytes = gathered * 12 + R.nnz * 12 + (1 << 18) * 8 * 2 + (1 << 18) * 8
-    out["spref_ms"] = round(1e3 * t, 4)
-    out["spref_gbs"] = round(ref_bytes / t / 1e9, 2)
-    out["spref_nnz"] = int(R.nnz)
-    S = spx.spasgn(dA3, dI, dJ, dBp)
-    t = time_steps(lambda: spx.spasgn(dA3, dI, dJ, dBp), 5, sync)
-    asg_bytes = csc_bytes(A3.nnz, A3.n) + csc_bytes(Bp.nnz, Bp.n) + csc_bytes(S.nnz, A3.n) + (1 << 19) * 4
-    out["spasgn_ms"] = round(1e3 * t, 4)
-    out["spasgn_gbs"] = round(asg_bytes / t / 1e9, 2)
-    out["spasgn_nnz"] = int(S.nnz)
-    del S
-    E = spx.extend_add(dA3, dI, dJ, dBp)
-    t = time_steps(lambda: spx.extend_add(dA3, dI, dJ, dBp), 5, sync)
-    ea_bytes = csc_bytes(A3.nnz, A3.n) + csc_bytes(Bp.nnz, Bp.n) + csc_bytes(E.nnz, A3.n) + (1 << 19) * 4
-    out["extend_add_ms"] = round(1e3 * t, 4)
-    out["extend_add_gbs"] = round(ea_bytes / t / 1e9, 2)
-    out["extend_add_nnz"] = int(E.nnz)
-    del E, R
-
-    # restriction S A S^T of orders 2, 4, 8 on R-MAT scale 23: one fused pass
-    # over A, against both parenthesizations with S, S^T and the intermediate
-    # product materialized
-    A23 = W.rmat(23, 8, seed=23)
-    dA23 = spx.from_host(A23)
-    n23 = A23.n
-    res = {}
-    for order in (2, 4, 8):
-        agg = spx.restriction_map(n23, order)
-        nc = n23 // order
-        ones = torch.ones(n23, dtype=torch.float64, device="cuda")
-        dS = spx.SpMat(nc, n23, torch.arange(n23 + 1, dtype=torch.int64, device="cuda"), agg, ones)
-        dSt = spx.SpMat(n23, nc, torch.arange(0, n23 + 1, order, dtype=torch.int64, device="cuda"),
-                        torch.arange(n23, dtype=torch.int32, device="cuda"), ones)
-        p = spx.ContractPlan(dA23, agg, nc, agg, nc)
-        Cr = p.execute()
+    if want("stages"):
+        # one GPU's share of an 8x8 Sparse SUMMA stage: A00 * A00 in DCSC
+        b = A.n // 8
+        blk = W.column_block(A, 0, b, 0, b)
+        dB = spx.csc_to_dcsc(spx.from_host(blk))
+        p = spx.GemmPlan(dB, dB, out_fmt=spx.DCSC)
+        C = p.execute()
+        mults = p.info()["mults"]
         p.close()
 
-        def fused():
-            q = spx.ContractPlan(dA23, agg, nc, agg, nc)
-            q.execute(Cr)
+        def stage():
+            q = spx.GemmPlan(dB, dB, out_fmt=spx.DCSC)
+            q.execute(C)
             q.close()
 
-        def left():
-            spx.spgemm(spx.spgemm(dS, dA23), dSt)
+        for _ in range(3):
+            stage()
+        t = time_steps(stage, 10, sync)
+        out["stage_block_dcsc_ms"] = round(1e3 * t, 4)
+        out["stage_block_gflops"] = round(2 * mults / t / 1e9, 3)
+        out["stage_block_nnz_c"] = int(C.nnz)
+        del C
 
-        def right():
-            spx.spgemm(dS, spx.spgemm(dA23, dSt))
+        # all 8 stages of that processor: C_00 = sum_k A_0k * A_k0 as one stage-sum
+        # plan, against the 8 stage products formed separately (partials not merged)
+        As = [spx.csc_to_dcsc(spx.from_host(W.column_block(A, 0, b, k * b, (k + 1) * b))) for k in range(8)]
+        Bs = [spx.csc_to_dcsc(spx.from_host(W.column_block(A, k * b, (k + 1) * b, 0, b))) for k in range(8)]
+        sp = spx.StageSumPlan(As, Bs, out_fmt=spx.DCSC)
+        S = sp.execute()
+        smults = sp.info()["mults"]
+        sp.close()
 
-        for f in (fused, left, right):
-            f()
-        t = time_steps(fused, 5, sync)
-        byts = csc_bytes(A23.nnz, n23) + csc_bytes(Cr.nnz, nc)
-        res[str(order)] = {"ms": round(1e3 * t, 4), "gbs": round(byts / t / 1e9, 2), "nnz_c": int(Cr.nnz),
-                           "two_products_left_ms": round(1e3 * time_steps(left, 3, sync), 4),
-                           "two_products_right_ms": round(1e3 * time_steps(right, 3, sync), 4)}
-        del Cr, dS, dSt
-    out["restriction_rmat23"] = {"nnz_a": int(A23.nnz), "orders": res}
+        def stage_sum():
+            q = spx.StageSumPlan(As, Bs, out_fmt=spx.DCSC)
+            q.execute(S)
+            q.close()
+
+        def stages_apart():
+            for X, Y in zip(As, Bs):
+                q = spx.GemmPlan(X, Y, out_fmt=spx.DCSC)
+                q.execute()
+                q.close()
+
+        for _ in range(2):
+            stage_sum()
+            stages_apart()
+        t = time_steps(stage_sum, 10, sync)
+        t_apart = time_steps(stages_apart, 5, sync)
+        out["summa_8x8_c00"] = {"stages": 8, "ms": round(1e3 * t, 4), "gflops": round(2 * smults / t / 1e9, 3),
+                                "mults": smults, "nnz_c": int(S.nnz),
+                                "stage_products_apart_ms": round(1e3 * t_apart, 4)}
+        del S, As, Bs
+
+    if want("tall"):
+        # R-MAT scale 20 times a tall-skinny Erdos-Renyi matrix (n/k = 8192, d2
+        # nonzeros per column): the multi-source BFS frontier expansion
+        dA = spx.from_host(A)
+        tall = {}
+        for d2 in (1, 10, 100, 1000, 10000, 100000):
+            F = W.erdos_renyi(A.n, A.n // 8192, d2, seed=300 + d2)
+            dF = spx.from_host(F)
+            Cf = spx.spgemm(dA, dF)
+            mults = int(np.diff(A.cp)[F.ir].sum())
+            t = time_steps(lambda: spx.spgemm(dA, dF), 5, sync)
+            tall[str(d2)] = {"ms": round(1e3 * t, 4), "gflops": round(2 * mults / t / 1e9, 3), "mults": mults,
+                             "nnz_c": int(Cf.nnz)}
+            del Cf, dF
+        out["tall_skinny_rmat20_x_er"] = tall
+
+    if want("index"):
+        # SpRef / SpAsgn on R-MAT scale 22, edge factor 16, int64 edge ids
+        A3 = W.rmat(22, 16, seed=22, values="edge_id")
+        I = W.index_vector(1 << 18, A3.m, seed=221)
+        J = W.index_vector(1 << 18, A3.n, seed=222)
+        Bp = W.erdos_renyi(1 << 18, 1 << 18, 4, seed=223, values="id40")
+        dA3, dI, dJ, dBp = spx.from_host(A3), torch.from_numpy(I).cuda(), torch.from_numpy(J).cuda(), spx.from_host(Bp)
+        R = spx.spref(dA3, dI, dJ)
+        t = time_steps(lambda: spx.spref(dA3, dI, dJ), 5, sync)
+        deg = np.diff(A3.cp)
+        gathered = int(deg[J].sum())
+        ref_bytes = gathered * 12 + R.nnz * 12 + (1 << 18) * 8 * 2 + (1 << 18) * 8
+        out["spref_ms"] = round(1e3 * t, 4)
+        out["spref_gbs"] = round(ref_bytes / t / 1e9, 2)
+        out["spref_nnz"] = int(R.nnz)
+        S = spx.spasgn(dA3, dI, dJ, dBp)
+        t = time_steps(lambda: spx.spasgn(dA3, dI, dJ, dBp), 5, sync)
+        asg_bytes = csc_bytes(A3.nnz, A3.n) + csc_bytes(Bp.nnz, Bp.n) + csc_bytes(S.nnz, A3.n) + (1 << 19) * 4
+        out["spasgn_ms"] = round(1e3 * t, 4)
+        out["spasgn_gbs"] = round(asg_bytes / t / 1e9, 2)
+        out["spasgn_nnz"] = int(S.nnz)
+        del S
+        E = spx.extend_add(dA3, dI, dJ, dBp)
+        t = time_steps(lambda: spx.extend_add(dA3, dI, dJ, dBp), 5, sync)
+        ea_bytes = csc_bytes(A3.nnz, A3.n) + csc_bytes(Bp.nnz, Bp.n) + csc_bytes(E.nnz, A3.n) + (1 << 19) * 4
+        out["extend_add_ms"] = round(1e3 * t, 4)
+        out["extend_add_gbs"] = round(ea_bytes / t / 1e9, 2)
+        out["extend_add_nnz"] = int(E.nnz)
+        del E, R
+
+    if want("restriction"):
+        # restriction S A S^T of orders 2, 4, 8 on R-MAT scale 23: one fused pass
+        # over A, against both parenthesizations with S, S^T and the intermediate
+        # product materialized
+        A23 = W.rmat(23, 8, seed=23)
+        dA23 = spx.from_host(A23)
+        n23 = A23.n
+        res = {}
+        for order in (2, 4, 8):
+            agg = spx.restriction_map(n23, order)
+            nc = n23 // order
+            ones = torch.ones(n23, dtype=torch.float64, device="cuda")
+            dS = spx.SpMat(nc, n23, torch.arange(n23 + 1, dtype=torch.int64, device="cuda"), agg, ones)
+            dSt = spx.SpMat(n23, nc, torch.arange(0, n23 + 1, order, dtype=torch.int64, device="cuda"),
+                            torch.arange(n23, dtype=torch.int32, device="cuda"), ones)
+            p = spx.ContractPlan(dA23, agg, nc, agg, nc)
+            Cr = p.execute()
+            p.close()
+
+            def fused():
+                q = spx.ContractPlan(dA23, agg, nc, agg, nc)
+                q.execute(Cr)
+                q.close()
+
+            def left():
+                spx.spgemm(spx.spgemm(dS, dA23), dSt)
+
+            def right():
+                spx.spgemm(dS, spx.spgemm(dA23, dSt))
+
+            for f in (fused, left, right):
+                f()
+            t = time_steps(fused, 5, sync)
+            byts = csc_bytes(A23.nnz, n23) + csc_bytes(Cr.nnz, nc)
+            res[str(order)] = {"ms": round(1e3 * t, 4), "gbs": round(byts / t / 1e9, 2), "nnz_c": int(Cr.nnz),
+                               "two_products_left_ms": round(1e3 * time_steps(left, 3, sync), 4),
+                               "two_products_right_ms": round(1e3 * time_steps(right, 3, sync), 4)}
+            del Cr, dS, dSt
+        out["restriction_rmat23"] = {"nnz_a": int(A23.nnz), "orders": res}
     return out
 
 
@@ -358,6 +374,8 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-extra", action="store_true", help="skip the other workloads")
+    ap.add_argument("--extra-only", choices=["latency", "stages", "tall", "index", "restriction"],
+                    help="run only this group of the other workloads and print its figures")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
@@ -386,6 +404,9 @@ def main():
         sync()
         del x, y
         torch.cuda.empty_cache()
+    if args.extra_only:
+        print(json.dumps({"extra": extra_workloads(spx, W, torch, only=args.extra_only)}), flush=True)
+        return
     log("generating R-MAT scale 20")
     A = W.rmat(20, 8, seed=20)
     dA = spx.from_host(A)

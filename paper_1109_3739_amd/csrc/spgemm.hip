@@ -112,30 +112,29 @@ __global__ void k_split_rows(Operand A, int64_t nslots, const int64_t* sid_off, 
     if (slot_begin(A, k + 1) - slot_begin(A, k) > kSplitMin) slot_of_split[sid_off[k]] = (int32_t)k;
 }
 
+// Row of the split table of one long column: entry b (< sstride - 1) is the
+// first position whose row lies in row block b or later, the last entry the
+// column length.  One wave per column walks its rows once: the entry at
+// position e fills the blocks after its predecessor's block up to its own.
 __global__ void k_split_fill(Operand A, const int64_t* nsplit_d, int64_t cap, const int32_t* slot_of_split,
                              int32_t* splits, int32_t sstride, int32_t rbshift) {
   const int64_t nsplit = *nsplit_d < cap ? *nsplit_d : cap;
-  const int64_t total = nsplit * sstride;
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t sidx = i / sstride;
-    const int32_t b = (int32_t)(i - sidx * sstride);
+  const int lane = lane_id();
+  const int64_t w0 = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kWave;
+  const int64_t nw = (int64_t)gridDim.x * blockDim.x / kWave;
+  for (int64_t sidx = w0; sidx < nsplit; sidx += nw) {
     const int32_t k = slot_of_split[sidx];
     const int64_t a0 = slot_begin(A, k);
     const int32_t al = (int32_t)(slot_begin(A, k + 1) - a0);
-    int32_t pos = al;
-    if (b < sstride - 1) {
-      const int64_t key = (int64_t)b << rbshift;
-      int32_t lo = 0, hi = al;
-      while (lo < hi) {
-        const int32_t mid = (lo + hi) >> 1;
-        if ((int64_t)A.ir[a0 + mid] < key)
-          lo = mid + 1;
-        else
-          hi = mid;
-      }
-      pos = lo;
+    const int32_t* col = A.ir + a0;
+    int32_t* out = splits + sidx * sstride;
+    for (int32_t e = lane; e < al; e += kWave) {
+      const int32_t cur = col[e] >> rbshift;
+      const int32_t prev = e == 0 ? -1 : (col[e - 1] >> rbshift);
+      for (int32_t b = prev + 1; b <= cur; ++b) out[b] = e;
     }
-    splits[i] = pos;
+    const int32_t last = al > 0 ? (col[al - 1] >> rbshift) : -1;
+    for (int32_t b = last + 1 + lane; b < sstride; b += kWave) out[b] = al;
   }
 }
 
@@ -156,7 +155,12 @@ __global__ void k_slot_mults(Operand B, const int32_t* bq_alen, int64_t nslots, 
       acc += s;
     }
   }
-  if (lane == 0 && acc) atomicAdd(total, (unsigned long long)acc);
+  __shared__ unsigned long long s_acc;  // one atomic per workgroup on the shared total
+  if (threadIdx.x == 0) s_acc = 0;
+  __syncthreads();
+  if (lane == 0 && acc) atomicAdd(&s_acc, (unsigned long long)acc);
+  __syncthreads();
+  if (threadIdx.x == 0 && s_acc) atomicAdd(total, s_acc);
 }
 
 // Counting sort of slots into bins: histogram, offsets, fill.
@@ -1657,7 +1661,7 @@ extern "C" int spx_spgemm_plan(const spx_ctx* ctx, const spx_mat* A, const spx_m
     SPX_TRY(exclusive_scan(LongColumn{P->A}, nslots_a, sid_off, scr, st));
     k_split_rows<<<grid_for(nslots_a, 256, 65536), 256, 0, st>>>(P->A, nslots_a, sid_off, slot_of_split);
     SPX_HIP(hipGetLastError());
-    k_split_fill<<<grid_for(split_cap * sstride, 256, (int64_t)cus * 64), 256, 0, st>>>(
+    k_split_fill<<<grid_for(split_cap * kWave, 256, (int64_t)cus * 32), 256, 0, st>>>(
         P->A, sid_off + nslots_a, split_cap, slot_of_split, P->splits, sstride, rb);
     SPX_HIP(hipGetLastError());
   }
@@ -1670,7 +1674,7 @@ extern "C" int spx_spgemm_plan(const spx_ctx* ctx, const spx_mat* A, const spx_m
   P->src = ProdSrc{A->ir, P->bq_a0, P->bq_alen, P->bq_split, P->splits, sstride, rb, (int32_t)m, 0};
   BinCfg bc{tune.tiny_max, tune.hash_count_max};
   if (nslots > 0) {
-    k_slot_mults<<<grid_for(nslots * kWave, 256, (int64_t)cus * 32), 256, 0, st>>>(P->B, P->bq_alen, nslots,
+    k_slot_mults<<<grid_for(nslots * kWave, 256, (int64_t)cus * 16), 256, 0, st>>>(P->B, P->bq_alen, nslots,
                                                                                    P->mults_d, &P->sum->mults);
     SPX_HIP(hipGetLastError());
     k_bin_count<<<grid_for(nslots, 256, (int64_t)cus * 8), 256, 0, st>>>(P->mults_d, nslots, bc, bincount);
