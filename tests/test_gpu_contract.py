@@ -86,3 +86,18 @@ def test_contraction_errors(spx):
     with pytest.raises(spx.SpxError) as e:
         spx.contract(A, None, 0, big, 5)
     assert e.value.code == spx.SPX_EINVAL
+
+
+def test_contraction_int32_pointers_and_empty(spx):
+    import torch
+    A = W.rmat(11, 8, seed=88, values="edge_id")
+    agg = np.arange(A.n) // 4
+    dA = spx.from_host(A, ptr_dtype=torch.int32)
+    ga = torch.from_numpy(agg.astype(np.int32)).cuda()
+    C = spx.contract(dA, ga, A.n // 4, ga, A.n // 4).to_host_csc()
+    ref = oracle.contract(A, agg, A.n // 4, agg, A.n // 4)
+    assert_same_csc(C, ref, exact_values=True, what="int32 pointers")
+    E = W.from_triples([], [], np.empty(0, np.int64), 64, 64)
+    e = np.arange(64) // 8
+    contract_check(spx, E, e, 8, e, 8, exact=True)
+    contract_check(spx, E, None, 0, None, 0, exact=True)

@@ -95,3 +95,19 @@ def test_stage_sum_errors(spx):
     assert e.value.code == spx.SPX_EINVAL
     with pytest.raises(ValueError):
         spx.spgemm_sum([], [])
+
+
+def test_stage_sum_int32_pointers_and_empty_stages(spx):
+    import torch
+    A = W.rmat(12, 8, seed=74, values="edge_id")
+    b = A.n // 4
+    As = [W.column_block(A, 0, A.m, k * b, (k + 1) * b) for k in range(4)]
+    Bs = [W.column_block(A, k * b, (k + 1) * b, 0, A.n) for k in range(4)]
+    dAs = [spx.from_host(X, ptr_dtype=torch.int32) for X in As]
+    dBs = [spx.from_host(X, ptr_dtype=torch.int32) for X in Bs]
+    C = spx.spgemm_sum(dAs, dBs).to_host_csc()
+    assert_same_csc(C, oracle.summa_stages(As, Bs), exact_values=True, what="int32 pointers")
+    Z = [W.from_triples([], [], np.empty(0, np.int64), 50, 30), W.from_triples([], [], np.empty(0, np.int64), 50, 0)]
+    Y = [W.from_triples([], [], np.empty(0, np.int64), 30, 20), W.from_triples([], [], np.empty(0, np.int64), 0, 20)]
+    C = stage_sum_check(spx, Z, Y, "plus_times", exact=True)
+    assert C.nnz == 0
