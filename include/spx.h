@@ -119,7 +119,13 @@ typedef struct spx_ctx {
  *                    the bitmap-counted columns from the count to the numeric
  *                    phase, which then reads them instead of gathering those
  *                    rows again; 0: off.  Above the cap, or if the allocation
- *                    fails, the numeric phase recomputes them.               */
+ *                    fails, the numeric phase recomputes them.
+ *   range_chunk      B entries per range set-up round of the multi-part
+ *                    launch: 256, 512, or 0 = chosen per product (512 when the
+ *                    cut columns would make more than one set-up per two
+ *                    multiplications, as with a tall-skinny B); 512 costs
+ *                    5 KiB of the part budget and is skipped if a dense row
+ *                    block would then no longer fit.                       */
 typedef struct spx_tuning {
   int32_t tiny_max;
   int32_t hash_count_max;
@@ -132,7 +138,7 @@ typedef struct spx_tuning {
   int32_t bitmap_chunk_log2;
   int32_t xcd_slices;
   int32_t bitmap_store_mb;
-  int32_t reserved;
+  int32_t range_chunk;
 } spx_tuning;
 
 /* Statistics of a SpGEMM plan, available once the plan call returned. */

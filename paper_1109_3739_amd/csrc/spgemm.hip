@@ -266,18 +266,24 @@ struct ProdSrc {
 // f receives the U products of a lane at once: rows r[u] (-1: none, e.g.
 // past the end or outside [r0, r1)), A's values a[u] and B's values b[u].
 // Must be called by every thread of the workgroup (it contains barriers);
-// chunks hold min(blockDim.x, kQChunk) entries.
+// chunks hold min(blockDim.x, QC) entries, QC the capacity of the range list
+// (kQChunk, or kQChunkWide for columns with very many B entries per product).
 constexpr int kQChunk = 256;
+constexpr int kQChunkWide = 512;
 
 constexpr int kWinTab = 512;  // windows of 64 products with a table entry
 constexpr int64_t kFilter = 1ll << 62;  // range start flag: filter rows one by one
 
-struct RangeLds {
-  int64_t start[kQChunk];  // position in A (| kFilter for unsplit columns)
-  int32_t pref[kQChunk + 1];
-  double bval[kQChunk];  // B's value, stored in the first bytes of each slot
+template <int QC>
+struct RangeLdsT {
+  int64_t start[QC];  // position in A (| kFilter for unsplit columns)
+  int32_t pref[QC + 1];
+  double bval[QC];  // B's value, stored in the first bytes of each slot
   int16_t wst[kWinTab];  // range holding product 64 k
 };
+using RangeLds = RangeLdsT<kQChunk>;
+// LDS that the wide range list takes beyond the ordinary one.
+constexpr int64_t kWideExtraLds = sizeof(RangeLdsT<kQChunkWide>) - sizeof(RangeLdsT<kQChunk>);
 
 // Adapts a per-product callback f(r, a, b) to the batch form.
 template <int U, class F>
@@ -310,10 +316,11 @@ __device__ __forceinline__ EachProduct<U, F> each_product(F f) {
 //    the next window's first product.
 // With REUSE the range list left in R by the previous call for the same
 // column and row range is used as is (the column must fit one chunk).
-template <int U, typename T, bool LOADA, bool LOADB, bool REUSE = false, bool WAVE_RUNS = false, class F>
+template <int U, typename T, bool LOADA, bool LOADB, bool REUSE = false, bool WAVE_RUNS = false, int QC, class F>
 __device__ __forceinline__ void block_products(const ProdSrc& S, const T* an, const T* bn, int64_t b0, int64_t b1,
-                                               int32_t r0, int32_t r1, bool full, RangeLds& R, int64_t* red, F&& f) {
-  const int qchunk = (int)blockDim.x < kQChunk ? (int)blockDim.x : kQChunk;
+                                               int32_t r0, int32_t r1, bool full, RangeLdsT<QC>& R, int64_t* red,
+                                               F&& f) {
+  const int qchunk = (int)blockDim.x < QC ? (int)blockDim.x : QC;
   const int lane = lane_id();
   const int32_t nwin = (int32_t)blockDim.x / kWave;
   const int32_t wid = __builtin_amdgcn_readfirstlane((int32_t)threadIdx.x / kWave);
@@ -917,11 +924,16 @@ __device__ int64_t cut_parts(const PartCfg& p, const uint32_t* blk, int32_t t, i
 
 // Number of parts of every non-tiny, nonempty column (list positions
 // [0, npos)), or the parts themselves (emit).
+// In the counting pass, setup_acc (if given) receives the sums over the cut
+// columns of (B entries x parts) and of their multiplications, which tell
+// how many range set-ups the multi-part launch makes per product.
 __global__ void k_parts(Operand B, PartCfg p, PartCfg ps, const int32_t* list, int64_t npos, int64_t multi_begin, int64_t multi_end,
                         int64_t nbm, const int64_t* cnt, const int64_t* off, const uint32_t* blkcnt,
-                        int64_t* nparts, const int64_t* poff, Part* parts, unsigned* err) {
+                        int64_t* nparts, const int64_t* poff, Part* parts, const int64_t* mults,
+                        unsigned long long* setup_acc, unsigned* err) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   const bool emit = parts != nullptr;
+  unsigned long long my_setup = 0, my_mults = 0;
   for (int64_t pos = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; pos < npos; pos += stride) {
     const int32_t t = list[pos];
     const int64_t c = cnt[t];
@@ -933,6 +945,10 @@ __global__ void k_parts(Operand B, PartCfg p, PartCfg ps, const int32_t* list, i
       np = cut_parts(p, blkcnt + (pos - multi_begin) * p.nblk, t, off[t], emit, emit ? parts + poff[pos] : nullptr,
                      pos - multi_begin < nbm ? (int32_t)(pos - multi_begin) : -1, cb0,
                      (int32_t)(slot_begin(B, t + 1) - cb0), err);
+      if (setup_acc && np > 1) {
+        my_setup += (unsigned long long)(slot_begin(B, t + 1) - cb0) * (unsigned long long)np;
+        my_mults += (unsigned long long)mults[t];
+      }
     } else {
       np = 1;
       const PartCfg& q = pos < multi_end ? p : ps;
@@ -953,6 +969,15 @@ __global__ void k_parts(Operand B, PartCfg p, PartCfg ps, const int32_t* list, i
       }
     }
     if (!emit) nparts[pos] = np;
+  }
+  if (setup_acc) {  // one pair of atomics per workgroup
+    __shared__ unsigned long long s_acc[2];
+    if (threadIdx.x < 2) s_acc[threadIdx.x] = 0;
+    __syncthreads();
+    if (my_setup) atomicAdd(&s_acc[0], my_setup);
+    if (my_mults) atomicAdd(&s_acc[1], my_mults);
+    __syncthreads();
+    if (threadIdx.x < 2 && s_acc[threadIdx.x]) atomicAdd(&setup_acc[threadIdx.x], s_acc[threadIdx.x]);
   }
 }
 
@@ -980,7 +1005,7 @@ __device__ __forceinline__ void block_bitonic_sort(uint64_t* a, int n2) {
 // popcount prefix gives each row its rank = output position, accumulate
 // values by rank, write rows and values in order.  Hash mode: accumulate
 // into an open-addressing table, then sort (row, slot) keys.
-template <int SR, typename T>
+template <int SR, typename T, int QC>
 __global__ void __launch_bounds__(1024) k_numeric_parts(Operand A, Operand B, ProdSrc S,
                                                         const int64_t* mults,
                                                         const int64_t* cnt, const Part* parts, const int64_t* qoff,
@@ -996,7 +1021,7 @@ __global__ void __launch_bounds__(1024) k_numeric_parts(Operand A, Operand B, Pr
   __shared__ Part s_batch[kPartBatch];
   __shared__ int64_t red[1024 / kWave + 1];
   __shared__ unsigned s_ctr;
-  __shared__ RangeLds s_rng;
+  __shared__ RangeLdsT<QC> s_rng;
   const T* an = (const T*)A.num;
   const T* bn = (const T*)B.num;
   // work queues: queue k holds parts [qoff[k], qoff[k+1]); a workgroup
@@ -1106,7 +1131,7 @@ __global__ void __launch_bounds__(1024) k_numeric_parts(Operand A, Operand B, Pr
             if (rank < c) SR_::lds_acc(&vals[rank], SR_::mul(a[u], bv[u]));
           }
         };
-        if (!stored && b1 - b0 <= (int64_t)(blockDim.x < kQChunk ? blockDim.x : kQChunk))
+        if (!stored && b1 - b0 <= (int64_t)(blockDim.x < QC ? blockDim.x : QC))
           block_products<8, T, SR_::kUsesA, SR_::kUsesB, true, true>(S, an, bn, b0, b1, P.r0, P.r1, full, s_rng, red, acc);
         else
           block_products<8, T, SR_::kUsesA, SR_::kUsesB, false, true>(S, an, bn, b0, b1, P.r0, P.r1, full, s_rng, red, acc);
@@ -1389,8 +1414,8 @@ struct Summary {
   unsigned long long mults;
   unsigned long long nnz_tiny;
   unsigned long long nnz_multi;
-  unsigned long long work;
-  unsigned long long work2;
+  unsigned long long setup;      // sum over cut columns of (B entries x parts)
+  unsigned long long cut_mults;  // multiplications of the cut columns
   unsigned err;
   unsigned pad;
 };
@@ -1438,6 +1463,7 @@ struct GemmPlan : spx_plan {
   int32_t nq_multi = 1, nslice = 1, nslice_req = 1;
   Summary* sum = nullptr;
   int64_t L = 0, L_single = 0;
+  bool wide = false;  // the multi-part launch uses the wide range list
   uint64_t* gbm = nullptr;  // stored row bitmaps of the bitmap-counted columns
   int64_t gbm_words = 0;    // 64-bit words per stored bitmap
 };
@@ -1512,9 +1538,14 @@ static int launch_numeric(GemmPlan* P, spx_mat* C, hipStream_t st) {
     const int64_t* qoff = r == 0 ? P->qoff_multi : P->qoff_single;
     const int nq = r == 0 ? P->nq_multi : 1;
     unsigned long long* qctr = r == 0 ? P->qctr : P->qctr + P->nq_multi;
-    hipLaunchKernelGGL((k_numeric_parts<SR, T>), dim3((unsigned)grid), dim3(blk), (size_t)L, st, P->A, P->B, P->src,
-                       P->mults_d, P->cnt, P->parts, qoff, nq, r == 0 ? P->nslice : 1, qctr, P->gbm, P->gbm_words,
-                       cir, cnum, err);
+    if (r == 0 && P->wide)
+      hipLaunchKernelGGL((k_numeric_parts<SR, T, kQChunkWide>), dim3((unsigned)grid), dim3(blk), (size_t)L, st, P->A,
+                         P->B, P->src, P->mults_d, P->cnt, P->parts, qoff, nq, P->nslice, qctr, P->gbm,
+                         P->gbm_words, cir, cnum, err);
+    else
+      hipLaunchKernelGGL((k_numeric_parts<SR, T, kQChunk>), dim3((unsigned)grid), dim3(blk), (size_t)L, st, P->A,
+                         P->B, P->src, P->mults_d, P->cnt, P->parts, qoff, nq, r == 0 ? P->nslice : 1, qctr, P->gbm,
+                         P->gbm_words, cir, cnum, err);
     SPX_HIP(hipGetLastError());
     if (r == 0) P->mark(kEvMulti, st);
   }
@@ -1583,6 +1614,8 @@ extern "C" int spx_spgemm_plan(const spx_ctx* ctx, const spx_mat* A, const spx_m
     return fail(SPX_EINVAL, "hash_count_max must be in [tiny_max, 16384]");
   if (tune.single_part_max < 64 || tune.single_part_max > 4096 || (tune.single_part_max & (tune.single_part_max - 1)))
     return fail(SPX_EINVAL, "single_part_max must be a power of two in [64, 4096]");
+  if (tune.range_chunk != 0 && tune.range_chunk != kQChunk && tune.range_chunk != kQChunkWide)
+    return fail(SPX_EINVAL, "range_chunk must be 0, 256 or 512");
   for (int th : {tune.count_threads, tune.bitmap_threads, tune.part_threads, tune.single_threads})
     if (th % 64 || th < 64 || th > 1024) return fail(SPX_EINVAL, "thread counts must be multiples of 64 in [64, 1024]");
 
@@ -1770,7 +1803,8 @@ extern "C" int spx_spgemm_plan(const spx_ctx* ctx, const spx_mat* A, const spx_m
     SPX_TRY(scr.get_n(npos + 1, &poff));
     k_parts<<<grid_for(npos, 256, (int64_t)cus * 16), 256, 0, st>>>(P->B, pc, pcs, P->list, npos, multi_begin, multi_end,
                                                                     P->gbm ? nbitmap : 0, P->cnt,
-                                                                    P->off, blkcnt, np, nullptr, nullptr, err);
+                                                                    P->off, blkcnt, np, nullptr, nullptr, P->mults_d,
+                                                                    &P->sum->setup, err);
     SPX_HIP(hipGetLastError());
     SPX_TRY(exclusive_scan(LoadI64{np}, npos, poff, scr, st));
   }
@@ -1788,6 +1822,30 @@ extern "C" int spx_spgemm_plan(const spx_ctx* ctx, const spx_mat* A, const spx_m
   }
   SPX_TRY(summary_sync(P, st, &hs));
   if (hs.err & 4u) return fail(SPX_EUNSUPPORTED, "a row block is too dense for the LDS budget");
+  // Columns with many B entries per product (a tall-skinny right operand):
+  // every part walks all of its column's B entries, so range set-ups
+  // outnumber products.  Then the multi-part launch takes twice as many B
+  // entries per set-up round, and its parts are re-cut for the LDS that the
+  // larger range list leaves, if a dense row block still fits.
+  const bool want_wide = tune.range_chunk == kQChunkWide ||
+                         (tune.range_chunk == 0 && hs.cut_mults > 0 && 2 * hs.setup > hs.cut_mults);
+  if (npos > 0 && want_wide) {
+    const int64_t Lw = L - kWideExtraLds;
+    if (((1ll << rb) * sz + ((1ll << rb) / 64) * 10 + 256) <= Lw) {
+      P->wide = true;
+      P->L = Lw;
+      pc.L = Lw;
+      k_parts<<<grid_for(npos, 256, (int64_t)cus * 16), 256, 0, st>>>(
+          P->B, pc, pcs, P->list, npos, multi_begin, multi_end, P->gbm ? nbitmap : 0, P->cnt, P->off, blkcnt, np,
+          nullptr, nullptr, P->mults_d, nullptr, err);
+      SPX_HIP(hipGetLastError());
+      SPX_TRY(exclusive_scan(LoadI64{np}, npos, poff, scr, st));
+      SPX_HIP(hipMemcpyAsync(&tail[2], poff + npos, 8, hipMemcpyDeviceToHost, st));
+      SPX_HIP(hipMemcpyAsync(&tail[3], poff + multi_end, 8, hipMemcpyDeviceToHost, st));
+      SPX_TRY(summary_sync(P, st, &hs));
+      if (hs.err & 4u) return fail(SPX_EUNSUPPORTED, "a row block is too dense for the LDS budget");
+    }
+  }
   P->nnz = tail[0];
   P->nzc = tail[1];
   P->nparts = tail[2];
@@ -1797,7 +1855,8 @@ extern "C" int spx_spgemm_plan(const spx_ctx* ctx, const spx_mat* A, const spx_m
     SPX_TRY(scr.get_n(P->nparts, &P->parts));
     k_parts<<<grid_for(npos, 256, (int64_t)cus * 16), 256, 0, st>>>(P->B, pc, pcs, P->list, npos, multi_begin, multi_end,
                                                                     P->gbm ? nbitmap : 0, P->cnt,
-                                                                    P->off, blkcnt, nullptr, poff, P->parts, err);
+                                                                    P->off, blkcnt, nullptr, poff, P->parts,
+                                                                    P->mults_d, nullptr, err);
     SPX_HIP(hipGetLastError());
     // work queues of the multi-part launch: one per row slice plus a
     // shared one (parts spanning all rows); the single-part launch has one

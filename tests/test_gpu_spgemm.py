@@ -76,6 +76,9 @@ def test_rmat_semirings(spx, semiring, values, exact):
     dict(tiny_max=0, hash_count_max=0, bitmap_store_mb=0),  # numeric phase re-marks the bitmap rows
     dict(part_lds_bytes=24 * 1024, bitmap_store_mb=0),
     dict(tiny_max=0, hash_count_max=0, bitmap_store_mb=1),  # over the cap: recomputed
+    dict(range_chunk=512),                                 # wide range list in the multi-part launch
+    dict(range_chunk=512, part_lds_bytes=24 * 1024),
+    dict(range_chunk=256, part_lds_bytes=24 * 1024),
 ])
 @pytest.mark.parametrize("dtype", [np.float64, np.float32])
 def test_forced_paths(spx, tune, dtype):
@@ -132,6 +135,24 @@ def test_tall_skinny_frontier(spx, d2):
     F = W.erdos_renyi(A.n, A.n // 8192, d2, seed=42 + d2)
     check_against_oracle(spx, A, F, "plus_times")
     check_against_oracle(spx, A, F, "min_plus", exact=True)
+
+
+def test_tall_skinny_many_parts(spx):
+    # 16 columns of 20000 B entries over 2^17 rows: about ten parts per
+    # column and few products per B entry, so the plan picks the wide range
+    # list by itself; the forced settings give the same result
+    A = W.rmat(17, 8, seed=43)
+    F = W.erdos_renyi(A.n, 16, 20000, seed=44)
+    check_against_oracle(spx, A, F, "plus_times")
+    check_against_oracle(spx, A, F, "min_plus", exact=True)
+    for rc in (256, 512):
+        t = spx.default_tuning()
+        t.range_chunk = rc
+        check_against_oracle(spx, A, F, "plus_times", tuning=t)
+    t = spx.default_tuning()
+    t.range_chunk = 300
+    with pytest.raises(spx.SpxError):
+        gemm(spx, A, F, "plus_times", tuning=t)
 
 
 def test_tiny_columns_wide_row_ids(spx):
