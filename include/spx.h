@@ -125,7 +125,13 @@ typedef struct spx_ctx {
  *                    cut columns would make more than one set-up per two
  *                    multiplications, as with a tall-skinny B); 512 costs
  *                    5 KiB of the part budget and is skipped if a dense row
- *                    block would then no longer fit.                       */
+ *                    block would then no longer fit.
+ *   bucket_parts     1: every part of a cut column visits only the B entries
+ *                    whose A column has rows in the part's range (lists built
+ *                    by the plan, one entry per B entry and part reached);
+ *                    -1: parts walk all of their column's B entries; 0: lists
+ *                    when range set-ups would outnumber multiplications 3 to
+ *                    2 (a very tall-skinny B).                               */
 typedef struct spx_tuning {
   int32_t tiny_max;
   int32_t hash_count_max;
@@ -139,6 +145,8 @@ typedef struct spx_tuning {
   int32_t xcd_slices;
   int32_t bitmap_store_mb;
   int32_t range_chunk;
+  int32_t bucket_parts;
+  int32_t reserved;
 } spx_tuning;
 
 /* Statistics of a SpGEMM plan, available once the plan call returned. */

@@ -263,6 +263,8 @@ struct ProdSrc {
 // (search bounds, searches, range data, loads, callback) so that the loads
 // of one phase are in flight together: a round costs a few LDS latencies
 // and one global-memory latency for up to blockDim*U products.
+// qidx (if given) lists the B entries to visit: qidx[b0, b1) instead of
+// b0 .. b1-1.
 // f receives the U products of a lane at once: rows r[u] (-1: none, e.g.
 // past the end or outside [r0, r1)), A's values a[u] and B's values b[u].
 // Must be called by every thread of the workgroup (it contains barriers);
@@ -319,7 +321,7 @@ __device__ __forceinline__ EachProduct<U, F> each_product(F f) {
 template <int U, typename T, bool LOADA, bool LOADB, bool REUSE = false, bool WAVE_RUNS = false, int QC, class F>
 __device__ __forceinline__ void block_products(const ProdSrc& S, const T* an, const T* bn, int64_t b0, int64_t b1,
                                                int32_t r0, int32_t r1, bool full, RangeLdsT<QC>& R, int64_t* red,
-                                               F&& f) {
+                                               const int32_t* qidx, F&& f) {
   const int qchunk = (int)blockDim.x < QC ? (int)blockDim.x : QC;
   const int lane = lane_id();
   const int32_t nwin = (int32_t)blockDim.x / kWave;
@@ -329,7 +331,7 @@ __device__ __forceinline__ void block_products(const ProdSrc& S, const T* an, co
     int32_t mylen = 0;
     if (!REUSE && (int)threadIdx.x < nq) {
       const int i = threadIdx.x;
-      const int64_t q = qc + i;
+      const int64_t q = qidx ? (int64_t)qidx[qc + i] : qc + i;
       const int64_t a0 = S.a0[q];
       int32_t e0 = 0, e1 = S.alen[q];
       int64_t flt = 0;
@@ -719,7 +721,7 @@ __global__ void k_count_hash(Operand B, ProdSrc S, const int64_t* mults,
       for (int64_t i = threadIdx.x; i < nblk; i += blockDim.x) lblk[i] = 0;
     __syncthreads();
     int64_t mine = 0;
-    block_products<4, int, false, false, false, true>(S, nullptr, nullptr, b0, b1, 0, 0, true, s_rng, red,
+    block_products<4, int, false, false, false, true>(S, nullptr, nullptr, b0, b1, 0, 0, true, s_rng, red, nullptr,
                                                       each_product<4>([&](int32_t r, int, int) {
       if (r < 0) return;
       uint32_t h = hash_row(r, log2s);
@@ -792,7 +794,7 @@ __global__ void k_count_bitmap(Operand B, ProdSrc S, const int64_t* mults, const
     for (int i = threadIdx.x; i < blk_per_chunk; i += blockDim.x) lblk[i] = 0;
     __syncthreads();
     block_products<4, int, false, false, false, true>(S, nullptr, nullptr, b0, b1, (int32_t)c0, (int32_t)c1, nchunks == 1, s_rng,
-                                         red, each_product<4>([&](int32_t r, int, int) {
+                                         red, nullptr, each_product<4>([&](int32_t r, int, int) {
       const uint32_t d = (uint32_t)(r - (int32_t)c0);
       if (d < (uint32_t)(c1 - c0)) atomicOr(&bm[d >> 5], 1u << (d & 31));
     }));
@@ -826,10 +828,10 @@ struct Part {
   int32_t t;     // slot of B / output column
   int32_t c;     // outputs in the part
   int32_t r0, r1;  // row range [r0, r1)
-  int32_t mode;  // 0 = bitmap, 1 = hash
+  int32_t mode;  // bit 0: 0 = bitmap, 1 = hash; bit 1: [b0, b0 + nb) indexes the bucket list
   int32_t slice; // row slice of the part (work queue), nslice = any
   int32_t bmi;   // index of the column's stored row bitmap, -1 if none
-  int32_t nb;    // B entries of the column: [b0, b0 + nb)
+  int32_t nb;    // B entries of the column: [b0, b0 + nb) (or the part's bucket)
   int64_t b0;
 };
 
@@ -981,6 +983,143 @@ __global__ void k_parts(Operand B, PartCfg p, PartCfg ps, const int32_t* list, i
   }
 }
 
+// ------------------------------------------------------------------ buckets
+// With a tall-skinny B, every part of a cut column walks all of the column's
+// B entries although the few rows of each A(:,k) reach few parts.  Bucket
+// mode lists, per part, only the B entries whose A column has rows in the
+// part's row range: about one list entry per multiplication instead of one
+// range set-up per B entry and part.
+//   k_bucket_map:   per cut column, the part of every row block (-1: none);
+//   k_bucket<FILL>: per B entry of a cut column, each part it reaches gets a
+//                   count (FILL false) or the entry's index (FILL true);
+//   k_bucket_parts: points every part of a cut column at its bucket.
+// Cut columns are the list positions [multi_begin, multi_end) with more
+// than one part.
+__global__ void k_bucket_map(PartCfg p, const int64_t* np, const int64_t* poff, int64_t multi_begin,
+                             int64_t multi_end, const Part* parts, int32_t* map) {
+  for (int64_t pos = multi_begin + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; pos < multi_end;
+       pos += (int64_t)gridDim.x * blockDim.x) {
+    int32_t* mp = map + (pos - multi_begin) * p.nblk;
+    for (int64_t b = 0; b < p.nblk; ++b) mp[b] = -1;
+    if (np[pos] <= 1) continue;
+    for (int64_t i = poff[pos]; i < poff[pos + 1]; ++i) {
+      const int64_t bl0 = parts[i].r0 >> p.rbshift;
+      const int64_t bl1 = ((int64_t)parts[i].r1 + (1ll << p.rbshift) - 1) >> p.rbshift;
+      for (int64_t b = bl0; b < bl1 && b < p.nblk; ++b) mp[b] = (int32_t)(i - poff[pos]);
+    }
+  }
+}
+
+// One workgroup takes a strided share of one cut column's B entries and
+// counts, per part, in LDS: the counting pass then adds its counts to bcnt,
+// the filling pass reserves a range of each part's bucket (one atomic per
+// part and workgroup) and walks its B entries again to fill the ranges.
+// Columns with more than kBucketLds parts use global atomics per entry.
+constexpr int kBucketLds = 4096;
+
+template <bool FILL>
+__global__ void __launch_bounds__(256) k_bucket(Operand B, ProdSrc S, PartCfg p, const int32_t* list,
+                                                const int64_t* np, const int64_t* poff, int64_t multi_begin,
+                                                int64_t multi_end, const Part* parts, const int32_t* map,
+                                                unsigned* bcnt, const int64_t* boff, unsigned* bfill,
+                                                int32_t* qlist, int64_t qcap, unsigned* err) {
+  __shared__ unsigned s_cnt[kBucketLds];
+  __shared__ int64_t s_base[FILL ? kBucketLds : 1];
+  for (int64_t pos = multi_begin + blockIdx.y; pos < multi_end; pos += gridDim.y) {
+    const int64_t npp = np[pos];
+    if (npp <= 1) continue;
+    const int32_t t = list[pos];
+    const int64_t cb0 = slot_begin(B, t), cb1 = slot_begin(B, t + 1);
+    const int64_t pbeg = poff[pos];
+    const int32_t* mp = map + (pos - multi_begin) * p.nblk;
+    const bool local = npp <= kBucketLds;
+    // calls f(j) for every part j of the column that B entry q reaches
+    auto reach = [&](int64_t q, auto&& f) {
+      const int64_t a0 = S.a0[q];
+      const int32_t alen = S.alen[q];
+      const int32_t sid = S.splits ? S.split[q] : -1;
+      if (sid >= 0 && alen > 2 * npp) {  // long A column: probe each part through the split table
+        const int32_t* sp = S.splits + (int64_t)sid * S.sstride;
+        for (int64_t j = 0; j < npp; ++j) {
+          const Part& pj = parts[pbeg + j];
+          const int32_t e0 = sp[pj.r0 >> S.rbshift];
+          const int32_t e1 = sp[pj.r1 >= S.m ? S.sstride - 1 : (pj.r1 >> S.rbshift)];
+          if (e1 > e0) f(j);
+        }
+      } else {  // short A column: walk its rows (sorted, so its parts come in order)
+        int32_t last = -1;
+        for (int32_t e = 0; e < alen; ++e) {
+          const int32_t j = mp[S.air[a0 + e] >> S.rbshift];
+          if (j >= 0 && j != last) {
+            f(j);
+            last = j;
+          }
+        }
+      }
+    };
+    const int64_t q0 = cb0 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t qs = (int64_t)gridDim.x * blockDim.x;
+    if (!local) {  // uniform for the workgroup
+      for (int64_t q = q0; q < cb1; q += qs)
+        reach(q, [&](int64_t j) {
+          if (FILL) {
+            const int64_t at = boff[pbeg + j] + atomicAdd(&bfill[pbeg + j], 1u);
+            if (at < qcap)
+              qlist[at] = (int32_t)q;
+            else
+              atomicOr(err, 32u);
+          } else {
+            atomicAdd(&bcnt[pbeg + j], 1u);
+          }
+        });
+      continue;
+    }
+    for (int64_t j = threadIdx.x; j < npp; j += blockDim.x) s_cnt[j] = 0;
+    __syncthreads();
+    for (int64_t q = q0; q < cb1; q += qs) reach(q, [&](int64_t j) { atomicAdd(&s_cnt[j], 1u); });
+    __syncthreads();
+    for (int64_t j = threadIdx.x; j < npp; j += blockDim.x) {
+      const unsigned c = s_cnt[j];
+      if (!FILL) {
+        if (c) atomicAdd(&bcnt[pbeg + j], c);
+      } else {
+        s_base[j] = c ? boff[pbeg + j] + atomicAdd(&bfill[pbeg + j], c) : 0;
+        s_cnt[j] = 0;
+      }
+    }
+    __syncthreads();
+    if (FILL) {
+      for (int64_t q = q0; q < cb1; q += qs)
+        reach(q, [&](int64_t j) {
+          const int64_t at = s_base[j] + atomicAdd(&s_cnt[j], 1u);
+          if (at < qcap)
+            qlist[at] = (int32_t)q;
+          else
+            atomicOr(err, 32u);
+        });
+      __syncthreads();
+    }
+  }
+}
+
+__global__ void k_bucket_parts(const int64_t* np, const int64_t* poff, int64_t multi_begin, int64_t multi_end,
+                               const unsigned* bcnt, const int64_t* boff, Part* parts) {
+  for (int64_t pos = multi_begin + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; pos < multi_end;
+       pos += (int64_t)gridDim.x * blockDim.x) {
+    if (np[pos] <= 1) continue;
+    for (int64_t i = poff[pos]; i < poff[pos + 1]; ++i) {
+      parts[i].b0 = boff[i];
+      parts[i].nb = (int32_t)bcnt[i];
+      parts[i].mode |= 2;
+    }
+  }
+}
+
+struct LoadBucket {
+  const unsigned* p;
+  __device__ int64_t operator()(int64_t i) const { return (int64_t)p[i]; }
+};
+
 // ------------------------------------------------------------------ numeric: parts
 template <typename T>
 __device__ __forceinline__ void block_bitonic_sort(uint64_t* a, int n2) {
@@ -1010,8 +1149,8 @@ __global__ void __launch_bounds__(1024) k_numeric_parts(Operand A, Operand B, Pr
                                                         const int64_t* mults,
                                                         const int64_t* cnt, const Part* parts, const int64_t* qoff,
                                                         int nq, int nhome, unsigned long long* qctr,
-                                                        const uint64_t* gbm, int64_t gbm_words, int32_t* cir,
-                                                        T* cnum, unsigned* err) {
+                                                        const uint64_t* gbm, int64_t gbm_words,
+                                                        const int32_t* qlist, int32_t* cir, T* cnum, unsigned* err) {
   using SR_ = Semiring<SR, T>;
   constexpr bool kVal = SR != SPX_OR_AND;
   constexpr int kPartBatch = 4;
@@ -1058,11 +1197,12 @@ __global__ void __launch_bounds__(1024) k_numeric_parts(Operand A, Operand B, Pr
     for (int bi = 0; bi < nbat; ++bi) {
     const Part P = s_batch[bi];
     const int64_t b0 = P.b0, b1 = P.b0 + P.nb;
+    const int32_t* qx = (P.mode & 2) ? qlist : nullptr;  // a bucketed part visits only its bucket
     const int64_t span = (int64_t)P.r1 - P.r0;
     const bool full = (P.r0 == 0 && P.r1 == (int32_t)A.m);
     // products in this part ~ mults * c / cnt
     const int c = P.c;
-    if (P.mode == 0) {
+    if ((P.mode & 1) == 0) {
       const int W = (int)((span + 63) >> 6);
       uint64_t* bm = (uint64_t*)lds;
       uint16_t* pre = (uint16_t*)(bm + W);
@@ -1091,7 +1231,7 @@ __global__ void __launch_bounds__(1024) k_numeric_parts(Operand A, Operand B, Pr
         for (int i = threadIdx.x; i < c; i += blockDim.x) vals[i] = SR_::ident();
       __syncthreads();
       if (!stored) {
-        block_products<8, T, false, SR_::kUsesB, false, true>(S, an, bn, b0, b1, P.r0, P.r1, full, s_rng, red,
+        block_products<8, T, false, SR_::kUsesB, false, true>(S, an, bn, b0, b1, P.r0, P.r1, full, s_rng, red, qx,
                                                   each_product<8>([&](int32_t r, T, T) {
           const uint32_t d = (uint32_t)(r - P.r0);
           atomicOr((unsigned long long*)&bm[d >> 6], 1ull << (d & 63));
@@ -1132,9 +1272,9 @@ __global__ void __launch_bounds__(1024) k_numeric_parts(Operand A, Operand B, Pr
           }
         };
         if (!stored && b1 - b0 <= (int64_t)(blockDim.x < QC ? blockDim.x : QC))
-          block_products<8, T, SR_::kUsesA, SR_::kUsesB, true, true>(S, an, bn, b0, b1, P.r0, P.r1, full, s_rng, red, acc);
+          block_products<8, T, SR_::kUsesA, SR_::kUsesB, true, true>(S, an, bn, b0, b1, P.r0, P.r1, full, s_rng, red, qx, acc);
         else
-          block_products<8, T, SR_::kUsesA, SR_::kUsesB, false, true>(S, an, bn, b0, b1, P.r0, P.r1, full, s_rng, red, acc);
+          block_products<8, T, SR_::kUsesA, SR_::kUsesB, false, true>(S, an, bn, b0, b1, P.r0, P.r1, full, s_rng, red, qx, acc);
         __syncthreads();
         for (int i = threadIdx.x; i < c; i += blockDim.x) cnum[P.off + i] = vals[i];
         __syncthreads();
@@ -1183,7 +1323,7 @@ __global__ void __launch_bounds__(1024) k_numeric_parts(Operand A, Operand B, Pr
       }
       if (threadIdx.x == 0) s_ctr = 0;
       __syncthreads();
-      block_products<4, T, SR_::kUsesA, SR_::kUsesB>(S, an, bn, b0, b1, P.r0, P.r1, full, s_rng, red,
+      block_products<4, T, SR_::kUsesA, SR_::kUsesB>(S, an, bn, b0, b1, P.r0, P.r1, full, s_rng, red, qx,
                                                      each_product<4>([&](int32_t r, T a, T bv) {
         if (r < 0) return;
         uint32_t h = hash_row(r, log2s);
@@ -1464,6 +1604,7 @@ struct GemmPlan : spx_plan {
   Summary* sum = nullptr;
   int64_t L = 0, L_single = 0;
   bool wide = false;  // the multi-part launch uses the wide range list
+  int32_t* qlist = nullptr;  // B entries of the parts of bucketed columns, grouped by part
   uint64_t* gbm = nullptr;  // stored row bitmaps of the bitmap-counted columns
   int64_t gbm_words = 0;    // 64-bit words per stored bitmap
 };
@@ -1541,11 +1682,11 @@ static int launch_numeric(GemmPlan* P, spx_mat* C, hipStream_t st) {
     if (r == 0 && P->wide)
       hipLaunchKernelGGL((k_numeric_parts<SR, T, kQChunkWide>), dim3((unsigned)grid), dim3(blk), (size_t)L, st, P->A,
                          P->B, P->src, P->mults_d, P->cnt, P->parts, qoff, nq, P->nslice, qctr, P->gbm,
-                         P->gbm_words, cir, cnum, err);
+                         P->gbm_words, P->qlist, cir, cnum, err);
     else
       hipLaunchKernelGGL((k_numeric_parts<SR, T, kQChunk>), dim3((unsigned)grid), dim3(blk), (size_t)L, st, P->A,
                          P->B, P->src, P->mults_d, P->cnt, P->parts, qoff, nq, r == 0 ? P->nslice : 1, qctr, P->gbm,
-                         P->gbm_words, cir, cnum, err);
+                         P->gbm_words, P->qlist, cir, cnum, err);
     SPX_HIP(hipGetLastError());
     if (r == 0) P->mark(kEvMulti, st);
   }
@@ -1835,9 +1976,10 @@ extern "C" int spx_spgemm_plan(const spx_ctx* ctx, const spx_mat* A, const spx_m
       P->wide = true;
       P->L = Lw;
       pc.L = Lw;
+      SPX_TRY(fill_i64(reinterpret_cast<int64_t*>(&P->sum->setup), 2, 0, st));  // the cut columns may change
       k_parts<<<grid_for(npos, 256, (int64_t)cus * 16), 256, 0, st>>>(
           P->B, pc, pcs, P->list, npos, multi_begin, multi_end, P->gbm ? nbitmap : 0, P->cnt, P->off, blkcnt, np,
-          nullptr, nullptr, P->mults_d, nullptr, err);
+          nullptr, nullptr, P->mults_d, &P->sum->setup, err);
       SPX_HIP(hipGetLastError());
       SPX_TRY(exclusive_scan(LoadI64{np}, npos, poff, scr, st));
       SPX_HIP(hipMemcpyAsync(&tail[2], poff + npos, 8, hipMemcpyDeviceToHost, st));
@@ -1858,6 +2000,39 @@ extern "C" int spx_spgemm_plan(const spx_ctx* ctx, const spx_mat* A, const spx_m
                                                                     P->off, blkcnt, nullptr, poff, P->parts,
                                                                     P->mults_d, nullptr, err);
     SPX_HIP(hipGetLastError());
+    // bucket mode: range set-ups would outnumber multiplications 3 to 2
+    // (building the lists costs about three walks over the cut columns' rows;
+    // measured on R-MAT times tall-skinny B, the lists pay off above ~1.3)
+    const int64_t nmulti = multi_end - multi_begin;
+    const bool bucket_auto = tune.bucket_parts == 0 && hs.cut_mults > 0 && 2 * hs.setup > 3 * hs.cut_mults;
+    if (P->psplit > 0 && (bucket_auto || tune.bucket_parts > 0) && nblk <= 4096 && nmulti * nblk <= (1ll << 27) &&
+        B->nnz < (1ll << 31) && hs.cut_mults > 0) {
+      int32_t* map = nullptr;
+      unsigned *bcnt = nullptr, *bfill = nullptr;
+      int64_t* boff = nullptr;
+      SPX_TRY(scr.get_n(nmulti * nblk, &map));
+      SPX_TRY(scr.get_n(P->psplit, &bcnt));
+      SPX_TRY(scr.get_n(P->psplit, &bfill));
+      SPX_TRY(scr.get_n(P->psplit + 1, &boff));
+      SPX_TRY(scr.get_n((int64_t)hs.cut_mults, &P->qlist));  // a B entry reaches at most alen parts
+      SPX_TRY(fill_u32(bcnt, P->psplit, 0, st));
+      SPX_TRY(fill_u32(bfill, P->psplit, 0, st));
+      k_bucket_map<<<grid_for(nmulti, 256, 4096), 256, 0, st>>>(pc, np, poff, multi_begin, multi_end, P->parts, map);
+      SPX_HIP(hipGetLastError());
+      const dim3 bgrid(64, (unsigned)std::min<int64_t>(nmulti, 4096));
+      k_bucket<false><<<bgrid, 256, 0, st>>>(P->B, P->src, pc, P->list, np, poff, multi_begin, multi_end, P->parts,
+                                              map, bcnt, nullptr, nullptr, nullptr, 0, err);
+      SPX_HIP(hipGetLastError());
+      SPX_TRY(exclusive_scan(LoadBucket{bcnt}, P->psplit, boff, scr, st));
+      k_bucket<true><<<bgrid, 256, 0, st>>>(P->B, P->src, pc, P->list, np, poff, multi_begin, multi_end, P->parts,
+                                             map, nullptr, boff, bfill, P->qlist, (int64_t)hs.cut_mults, err);
+      SPX_HIP(hipGetLastError());
+      k_bucket_parts<<<grid_for(nmulti, 256, 4096), 256, 0, st>>>(np, poff, multi_begin, multi_end, bcnt, boff,
+                                                                  P->parts);
+      SPX_HIP(hipGetLastError());
+      SPX_TRY(summary_sync(P, st, &hs));
+      if (hs.err & 32u) return fail(SPX_EDEVICE, "bucket lists exceeded their bound");
+    }
     // work queues of the multi-part launch: one per row slice plus a
     // shared one (parts spanning all rows); the single-part launch has one
     P->nq_multi = pc.nslice + 1;

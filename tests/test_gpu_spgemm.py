@@ -79,6 +79,9 @@ def test_rmat_semirings(spx, semiring, values, exact):
     dict(range_chunk=512),                                 # wide range list in the multi-part launch
     dict(range_chunk=512, part_lds_bytes=24 * 1024),
     dict(range_chunk=256, part_lds_bytes=24 * 1024),
+    dict(bucket_parts=1),                                  # parts visit only their bucket of B entries
+    dict(bucket_parts=1, part_lds_bytes=24 * 1024, range_chunk=512),
+    dict(bucket_parts=1, part_lds_bytes=24 * 1024, xcd_slices=3),
 ])
 @pytest.mark.parametrize("dtype", [np.float64, np.float32])
 def test_forced_paths(spx, tune, dtype):
@@ -140,14 +143,15 @@ def test_tall_skinny_frontier(spx, d2):
 def test_tall_skinny_many_parts(spx):
     # 16 columns of 20000 B entries over 2^17 rows: about ten parts per
     # column and few products per B entry, so the plan picks the wide range
-    # list by itself; the forced settings give the same result
+    # list by itself; forced settings (wide list, per-part buckets) agree
     A = W.rmat(17, 8, seed=43)
     F = W.erdos_renyi(A.n, 16, 20000, seed=44)
     check_against_oracle(spx, A, F, "plus_times")
     check_against_oracle(spx, A, F, "min_plus", exact=True)
-    for rc in (256, 512):
+    for rc, bp in ((256, -1), (512, -1), (256, 1), (512, 1)):
         t = spx.default_tuning()
         t.range_chunk = rc
+        t.bucket_parts = bp
         check_against_oracle(spx, A, F, "plus_times", tuning=t)
     t = spx.default_tuning()
     t.range_chunk = 300
