@@ -266,6 +266,13 @@ int spx_batch_plan(const spx_ctx* ctx, int32_t count, const spx_mat* A, const sp
 int spx_batch_exec(spx_plan* plan, int64_t* cp_pool, int32_t* ir_pool, void* num_pool, spx_mat* C);
 int spx_batch_capture(spx_plan* plan, int64_t* cp_pool, int32_t* ir_pool, void* num_pool, spx_mat* C);
 int spx_batch_replay(spx_plan* plan);
+/* spx_batch_spgemm: one shot (plan, pools, exec, plan destroyed).  The three
+ * pools come from ctx->alloc (hipMalloc without one) and begin at C[0].cp,
+ * C[0].ir and C[0].num (NULL for a pattern result); the caller frees those
+ * three pointers with ctx->free (hipFree).  tuning may be NULL.  Returns
+ * once the work is enqueued on ctx->stream.                               */
+int spx_batch_spgemm(const spx_ctx* ctx, int32_t count, const spx_mat* A, const spx_mat* B, int32_t semiring,
+                     const spx_tuning* tuning, spx_mat* C);
 
 /* ---- SpRef: B = A(I,J) (Section 4) ------------------------------------
  * B(p,q) = A(I(p), J(q)) for p < lenI, q < lenJ, respecting the order of I
@@ -280,6 +287,11 @@ int spx_batch_replay(spx_plan* plan);
 int spx_spref_plan(const spx_ctx* ctx, const spx_mat* A, const int32_t* I, int64_t lenI, const int32_t* J,
                    int64_t lenJ, spx_plan** plan, int64_t* nnz_b);
 int spx_spref_exec(spx_plan* plan, spx_mat* B);
+/* One shot: B's buffers (CSC, int64 cp, A's value type) come from
+ * ctx->alloc (hipMalloc without one); free B->cp, B->ir, B->num with
+ * ctx->free (hipFree).  Nothing stays allocated on error.                 */
+int spx_spref(const spx_ctx* ctx, const spx_mat* A, const int32_t* I, int64_t lenI, const int32_t* J, int64_t lenJ,
+              spx_mat* B);
 
 /* ---- SpAsgn: C = A with the submatrix A(I,J) replaced by B (Section 4.1)
  * B is lenI x lenJ (CSC or DCSC).  Functional: A is not modified.  C keeps
@@ -293,6 +305,9 @@ int spx_spref_exec(spx_plan* plan, spx_mat* B);
 int spx_spasgn_plan(const spx_ctx* ctx, const spx_mat* A, const int32_t* I, int64_t lenI, const int32_t* J,
                     int64_t lenJ, const spx_mat* B, spx_plan** plan, int64_t* nnz_c);
 int spx_spasgn_exec(spx_plan* plan, spx_mat* C);
+/* One shot, with C's buffers from ctx->alloc as for spx_spref.             */
+int spx_spasgn(const spx_ctx* ctx, const spx_mat* A, const int32_t* I, int64_t lenI, const int32_t* J, int64_t lenJ,
+               const spx_mat* B, spx_mat* C);
 
 /* ---- Extend-add: A(I,J) = A(I,J) + B (Section 4.1) ----------------------
  * SpAsgn without the S*A*T term: C = A + R*B*Q, with R and Q SpAsgn's
@@ -315,6 +330,9 @@ int spx_spasgn_exec(spx_plan* plan, spx_mat* C);
 int spx_extend_add_plan(const spx_ctx* ctx, const spx_mat* A, const int32_t* I, int64_t lenI, const int32_t* J,
                         int64_t lenJ, const spx_mat* B, int32_t semiring, spx_plan** plan, int64_t* nnz_c);
 int spx_extend_add_exec(spx_plan* plan, spx_mat* C);
+/* One shot, with C's buffers from ctx->alloc as for spx_spref.             */
+int spx_extend_add(const spx_ctx* ctx, const spx_mat* A, const int32_t* I, int64_t lenI, const int32_t* J,
+                   int64_t lenJ, const spx_mat* B, int32_t semiring, spx_mat* C);
 
 /* ---- formats (Section 3.2) ----------------------------------------------
  * spx_count_nonempty: nzc of a CSC matrix (synchronises the stream).

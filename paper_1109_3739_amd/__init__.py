@@ -33,7 +33,7 @@ EXPORTS = [
     "spx_spgemm_plan", "spx_spgemm_exec", "spx_spgemm", "spx_plan_get_info", "spx_plan_destroy", "spx_plan_get_times",
     "spx_default_tuning", "spx_spref_plan", "spx_spref_exec", "spx_spasgn_plan", "spx_spasgn_exec",
     "spx_extend_add_plan", "spx_extend_add_exec", "spx_spgemm_sum_plan", "spx_spgemm_sum_exec",
-    "spx_contract_plan", "spx_contract_exec",
+    "spx_contract_plan", "spx_contract_exec", "spx_spref", "spx_spasgn", "spx_extend_add", "spx_batch_spgemm",
     "spx_count_nonempty", "spx_csc_to_dcsc", "spx_dcsc_to_csc", "spx_check", "spx_last_error", "spx_version",
     "spx_batch_plan", "spx_batch_exec", "spx_batch_capture", "spx_batch_replay",
 ]
@@ -116,6 +116,10 @@ def load():
         "spx_contract_plan": ([C, M, P, I64, P, I64, I32, I32, ctypes.POINTER(spx_tuning), PP, PI64, PI64],
                               ctypes.c_int),
         "spx_contract_exec": ([P, M], ctypes.c_int),
+        "spx_spref": ([C, M, P, I64, P, I64, M], ctypes.c_int),
+        "spx_spasgn": ([C, M, P, I64, P, I64, M, M], ctypes.c_int),
+        "spx_extend_add": ([C, M, P, I64, P, I64, M, I32, M], ctypes.c_int),
+        "spx_batch_spgemm": ([C, I32, M, M, I32, ctypes.POINTER(spx_tuning), M], ctypes.c_int),
         "spx_count_nonempty": ([C, M, PI64], ctypes.c_int),
         "spx_csc_to_dcsc": ([C, M, M], ctypes.c_int),
         "spx_dcsc_to_csc": ([C, M, M], ctypes.c_int),

@@ -364,3 +364,21 @@ extern "C" int spx_batch_replay(spx_plan* plan) {
   SPX_HIP(hipGraphLaunch(P->gexec, stream_of(&P->ctx)));
   return SPX_OK;
 }
+
+extern "C" int spx_batch_spgemm(const spx_ctx* ctx, int32_t count, const spx_mat* A, const spx_mat* B,
+                                int32_t semiring, const spx_tuning* tuning, spx_mat* C) {
+  if (!C) return fail(SPX_EINVAL, "C is NULL");
+  spx_plan* plan = nullptr;
+  int64_t nnz_total = 0, cp_total = 0;
+  SPX_TRY(spx_batch_plan(ctx, count, A, B, semiring, tuning, &plan, &nnz_total, &cp_total));
+  std::unique_ptr<spx_plan> guard(plan);
+  auto* P = static_cast<BatchPlan*>(plan);
+  OutAlloc oa(ctx);
+  void *cp = nullptr, *ir = nullptr, *num = nullptr;
+  SPX_TRY(oa.get((size_t)cp_total * 8, &cp));
+  SPX_TRY(oa.get((size_t)std::max<int64_t>(nnz_total, 1) * 4, &ir));
+  if (P->vb_c) SPX_TRY(oa.get((size_t)std::max<int64_t>(nnz_total, 1) * P->vb_c, &num));
+  SPX_TRY(spx_batch_exec(plan, static_cast<int64_t*>(cp), static_cast<int32_t*>(ir), num, C));
+  oa.keep();
+  return SPX_OK;
+}

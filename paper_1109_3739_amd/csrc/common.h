@@ -45,6 +45,21 @@ inline int fail(int code, const std::string& msg) {
 // ---------------------------------------------------------------- scratch
 // Device buffers taken from the context's allocator (or hipMalloc) and
 // released when the owning object is destroyed.
+// Output buffers of the one-shot entry points: from ctx->alloc (hipMalloc
+// without one).  Unless keep() is called, the destructor releases them, so an
+// entry point that fails half way leaves nothing behind.
+class OutAlloc {
+ public:
+  explicit OutAlloc(const spx_ctx* ctx) : ctx_(ctx) {}
+  ~OutAlloc();
+  int get(size_t bytes, void** out);
+  void keep() { got_.clear(); }
+
+ private:
+  const spx_ctx* ctx_;
+  std::vector<void*> got_;
+};
+
 class Scratch {
  public:
   explicit Scratch(const spx_ctx* ctx);

@@ -66,6 +66,32 @@ void Scratch::release_all() {
   arena_used_ = arena_size_ = 0;
 }
 
+OutAlloc::~OutAlloc() {
+  for (void* p : got_) {
+    if (ctx_ && ctx_->alloc) {
+      if (ctx_->free) ctx_->free(p, ctx_->user);
+    } else {
+      (void)hipFree(p);
+    }
+  }
+}
+
+int OutAlloc::get(size_t bytes, void** out) {
+  *out = nullptr;
+  if (bytes == 0) bytes = 16;
+  void* p = nullptr;
+  if (ctx_ && ctx_->alloc) {
+    p = ctx_->alloc(bytes, ctx_->user);
+  } else if (hipMalloc(&p, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    p = nullptr;
+  }
+  if (!p) return fail(SPX_ENOMEM, "allocation of an output buffer failed (" + std::to_string(bytes) + " bytes)");
+  got_.push_back(p);
+  *out = p;
+  return SPX_OK;
+}
+
 int device_cu_count() {
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 256;

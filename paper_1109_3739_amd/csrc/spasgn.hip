@@ -828,3 +828,42 @@ extern "C" int spx_extend_add_exec(spx_plan* plan, spx_mat* C) {
   SPX_HIP(hipGetLastError());
   return SPX_OK;
 }
+
+// One-shot forms: plan, output buffers from ctx->alloc, exec, plan destroyed.
+static int one_shot_csc(const spx_ctx* ctx, spx_plan* plan, int64_t nnz, const spx_mat* A,
+                        int (*exec)(spx_plan*, spx_mat*), spx_mat* C) {
+  std::unique_ptr<spx_plan> guard(plan);
+  OutAlloc oa(ctx);
+  spx_mat out{};
+  out.m = A->m;
+  out.n = A->n;
+  out.fmt = SPX_CSC;
+  out.ptr_t = SPX_PTR_I64;
+  out.val_t = A->val_t;
+  const int vb = value_size(A->val_t);
+  SPX_TRY(oa.get((size_t)(A->n + 1) * 8, &out.cp));
+  SPX_TRY(oa.get((size_t)std::max<int64_t>(nnz, 1) * 4, reinterpret_cast<void**>(&out.ir)));
+  if (vb) SPX_TRY(oa.get((size_t)std::max<int64_t>(nnz, 1) * vb, &out.num));
+  SPX_TRY(exec(plan, &out));
+  oa.keep();
+  *C = out;
+  return SPX_OK;
+}
+
+extern "C" int spx_spasgn(const spx_ctx* ctx, const spx_mat* A, const int32_t* I, int64_t lenI, const int32_t* J,
+                          int64_t lenJ, const spx_mat* B, spx_mat* C) {
+  if (!C) return fail(SPX_EINVAL, "C is NULL");
+  spx_plan* plan = nullptr;
+  int64_t nnz = 0;
+  SPX_TRY(spx_spasgn_plan(ctx, A, I, lenI, J, lenJ, B, &plan, &nnz));
+  return one_shot_csc(ctx, plan, nnz, A, spx_spasgn_exec, C);
+}
+
+extern "C" int spx_extend_add(const spx_ctx* ctx, const spx_mat* A, const int32_t* I, int64_t lenI, const int32_t* J,
+                              int64_t lenJ, const spx_mat* B, int32_t semiring, spx_mat* C) {
+  if (!C) return fail(SPX_EINVAL, "C is NULL");
+  spx_plan* plan = nullptr;
+  int64_t nnz = 0;
+  SPX_TRY(spx_extend_add_plan(ctx, A, I, lenI, J, lenJ, B, semiring, &plan, &nnz));
+  return one_shot_csc(ctx, plan, nnz, A, spx_extend_add_exec, C);
+}

@@ -2173,12 +2173,6 @@ const int64_t* spx::gemm_plan_offsets(const spx_plan* plan) {
   return static_cast<const GemmPlan*>(plan)->off;
 }
 
-static void* default_alloc(size_t bytes, void*) {
-  void* p = nullptr;
-  if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
-  return p;
-}
-
 extern "C" int spx_spgemm(const spx_ctx* ctx, const spx_mat* A, const spx_mat* B, int32_t semiring, int32_t c_fmt,
                           spx_mat* C) {
   if (!C) return fail(SPX_EINVAL, "C is NULL");
@@ -2187,8 +2181,7 @@ extern "C" int spx_spgemm(const spx_ctx* ctx, const spx_mat* A, const spx_mat* B
   SPX_TRY(spx_spgemm_plan(ctx, A, B, semiring, c_fmt, nullptr, &plan, &nnz, &nzc));
   std::unique_ptr<spx_plan> guard(plan);
   auto* P = static_cast<GemmPlan*>(plan);
-  void* (*al)(size_t, void*) = (ctx && ctx->alloc) ? ctx->alloc : default_alloc;
-  void* user = ctx ? ctx->user : nullptr;
+  OutAlloc oa(ctx);
   spx_mat out{};
   out.m = A->m;
   out.n = B->n;
@@ -2196,13 +2189,12 @@ extern "C" int spx_spgemm(const spx_ctx* ctx, const spx_mat* A, const spx_mat* B
   out.ptr_t = SPX_PTR_I64;
   out.val_t = P->vt;
   const int64_t ncp = (c_fmt == SPX_CSC ? B->n : nzc) + 1;
-  out.cp = al((size_t)ncp * 8, user);
-  out.ir = (int32_t*)al((size_t)std::max<int64_t>(nnz, 1) * 4, user);
-  out.num = P->vt == SPX_VAL_BOOL ? nullptr : al((size_t)std::max<int64_t>(nnz, 1) * value_size(P->vt), user);
-  out.jc = c_fmt == SPX_DCSC ? (int32_t*)al((size_t)std::max<int64_t>(nzc, 1) * 4, user) : nullptr;
-  if (!out.cp || !out.ir || (P->vt != SPX_VAL_BOOL && !out.num) || (c_fmt == SPX_DCSC && !out.jc))
-    return fail(SPX_ENOMEM, "allocation of C failed");
+  SPX_TRY(oa.get((size_t)ncp * 8, &out.cp));
+  SPX_TRY(oa.get((size_t)std::max<int64_t>(nnz, 1) * 4, reinterpret_cast<void**>(&out.ir)));
+  if (P->vt != SPX_VAL_BOOL) SPX_TRY(oa.get((size_t)std::max<int64_t>(nnz, 1) * value_size(P->vt), &out.num));
+  if (c_fmt == SPX_DCSC) SPX_TRY(oa.get((size_t)std::max<int64_t>(nzc, 1) * 4, reinterpret_cast<void**>(&out.jc)));
   SPX_TRY(spx_spgemm_exec(plan, &out));
+  oa.keep();
   *C = out;
   return SPX_OK;
 }

@@ -454,3 +454,27 @@ extern "C" int spx_spref_exec(spx_plan* plan, spx_mat* B) {
   SPX_HIP(hipGetLastError());
   return SPX_OK;
 }
+
+extern "C" int spx_spref(const spx_ctx* ctx, const spx_mat* A, const int32_t* I, int64_t lenI, const int32_t* J,
+                         int64_t lenJ, spx_mat* B) {
+  if (!B) return fail(SPX_EINVAL, "B is NULL");
+  spx_plan* plan = nullptr;
+  int64_t nnz = 0;
+  SPX_TRY(spx_spref_plan(ctx, A, I, lenI, J, lenJ, &plan, &nnz));
+  std::unique_ptr<spx_plan> guard(plan);
+  OutAlloc oa(ctx);
+  spx_mat out{};
+  out.m = lenI;
+  out.n = lenJ;
+  out.fmt = SPX_CSC;
+  out.ptr_t = SPX_PTR_I64;
+  out.val_t = A->val_t;
+  const int vb = value_size(A->val_t);
+  SPX_TRY(oa.get((size_t)(lenJ + 1) * 8, &out.cp));
+  SPX_TRY(oa.get((size_t)std::max<int64_t>(nnz, 1) * 4, reinterpret_cast<void**>(&out.ir)));
+  if (vb) SPX_TRY(oa.get((size_t)std::max<int64_t>(nnz, 1) * vb, &out.num));
+  SPX_TRY(spx_spref_exec(plan, &out));
+  oa.keep();
+  *B = out;
+  return SPX_OK;
+}
