@@ -138,14 +138,56 @@ __global__ void k_split_fill(Operand A, const int64_t* nsplit_d, int64_t cap, co
   }
 }
 
-// mults[t] = number of multiplications of output column (slot) t; one wave per slot.
+// mults[t] = number of multiplications of output column (slot) t.  Groups
+// of 8 lanes take one slot each (most columns hold a few B entries); slots
+// with more than kLongSlot entries are listed for whole waves instead
+// (k_slot_mults_long), so a long column holds up no group.  The total goes
+// to *total with one atomic per workgroup.
+constexpr int64_t kLongSlot = 512;
+
+__device__ __forceinline__ void add_total(int64_t acc, bool mine, unsigned long long* total) {
+  __shared__ unsigned long long s_acc;
+  if (threadIdx.x == 0) s_acc = 0;
+  __syncthreads();
+  if (mine && acc) atomicAdd(&s_acc, (unsigned long long)acc);
+  __syncthreads();
+  if (threadIdx.x == 0 && s_acc) atomicAdd(total, s_acc);
+}
+
 __global__ void k_slot_mults(Operand B, const int32_t* bq_alen, int64_t nslots, int64_t* mults,
-                             unsigned long long* total) {
+                             unsigned long long* total, int32_t* longs, unsigned long long* nlong) {
+  constexpr int G = 8;
+  const int gl = lane_id() & (G - 1);
+  const int64_t grp = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / G;
+  const int64_t ngrp = (int64_t)gridDim.x * blockDim.x / G;
+  int64_t acc = 0;
+  for (int64_t t = grp; t < nslots; t += ngrp) {
+    const int64_t b0 = slot_begin(B, t), b1 = slot_begin(B, t + 1);
+    if (b1 - b0 > kLongSlot) {
+      if (gl == 0) longs[atomicAdd(nlong, 1ull)] = (int32_t)t;
+      continue;
+    }
+    int64_t s = 0;
+    for (int64_t q = b0 + gl; q < b1; q += G) s += bq_alen[q];
+#pragma unroll
+    for (int d = 1; d < G; d <<= 1) s += __shfl_xor(s, d, G);
+    if (gl == 0) {
+      mults[t] = s;
+      acc += s;
+    }
+  }
+  add_total(acc, gl == 0, total);
+}
+
+__global__ void k_slot_mults_long(Operand B, const int32_t* bq_alen, const int32_t* longs,
+                                  const unsigned long long* nlong, int64_t* mults, unsigned long long* total) {
   const int lane = lane_id();
+  const int64_t n = (int64_t)*nlong;
   const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kWave;
   const int64_t nwaves = (int64_t)gridDim.x * blockDim.x / kWave;
   int64_t acc = 0;
-  for (int64_t t = wave; t < nslots; t += nwaves) {
+  for (int64_t i = wave; i < n; i += nwaves) {
+    const int32_t t = longs[i];
     const int64_t b0 = slot_begin(B, t), b1 = slot_begin(B, t + 1);
     int64_t s = 0;
     for (int64_t q = b0 + lane; q < b1; q += kWave) s += bq_alen[q];
@@ -155,12 +197,7 @@ __global__ void k_slot_mults(Operand B, const int32_t* bq_alen, int64_t nslots, 
       acc += s;
     }
   }
-  __shared__ unsigned long long s_acc;  // one atomic per workgroup on the shared total
-  if (threadIdx.x == 0) s_acc = 0;
-  __syncthreads();
-  if (lane == 0 && acc) atomicAdd(&s_acc, (unsigned long long)acc);
-  __syncthreads();
-  if (threadIdx.x == 0 && s_acc) atomicAdd(total, s_acc);
+  add_total(acc, lane == 0, total);
 }
 
 // Counting sort of slots into bins: histogram, offsets, fill.
@@ -188,21 +225,32 @@ __global__ void k_bin_offsets(unsigned long long* counts, int64_t* binoff, unsig
   }
 }
 
+// Each thread ranks kFillPer slots per round in LDS, so a workgroup reserves
+// its ranges of the bins once per blockDim * kFillPer slots.
+constexpr int kFillPer = 8;
 __global__ void k_bin_fill(const int64_t* mults, int64_t nslots, BinCfg cfg, const int64_t* binoff,
                            unsigned long long* fill, int32_t* list) {
   __shared__ unsigned hist[kNumBins];
   __shared__ int64_t base[kNumBins];
-  for (int64_t t0 = (int64_t)blockIdx.x * blockDim.x; t0 < nslots; t0 += (int64_t)gridDim.x * blockDim.x) {
+  const int64_t span = (int64_t)blockDim.x * kFillPer;
+  for (int64_t t0 = (int64_t)blockIdx.x * span; t0 < nslots; t0 += (int64_t)gridDim.x * span) {
     for (int i = threadIdx.x; i < kNumBins; i += blockDim.x) hist[i] = 0;
     __syncthreads();
-    const int64_t t = t0 + threadIdx.x;
-    const int b = t < nslots ? bin_of(mults[t], cfg) : -1;
-    const unsigned rank = b >= 0 ? atomicAdd(&hist[b], 1u) : 0u;
+    int b[kFillPer];
+    unsigned rank[kFillPer];
+#pragma unroll
+    for (int k = 0; k < kFillPer; ++k) {
+      const int64_t t = t0 + (int64_t)k * blockDim.x + threadIdx.x;
+      b[k] = t < nslots ? bin_of(mults[t], cfg) : -1;
+      rank[k] = b[k] >= 0 ? atomicAdd(&hist[b[k]], 1u) : 0u;
+    }
     __syncthreads();
     for (int i = threadIdx.x; i < kNumBins; i += blockDim.x)
       if (hist[i]) base[i] = binoff[i] + (int64_t)atomicAdd(&fill[i], (unsigned long long)hist[i]);
     __syncthreads();
-    if (b >= 0) list[base[b] + rank] = (int32_t)t;
+#pragma unroll
+    for (int k = 0; k < kFillPer; ++k)
+      if (b[k] >= 0) list[base[b[k]] + rank[k]] = (int32_t)(t0 + (int64_t)k * blockDim.x + threadIdx.x);
     __syncthreads();
   }
 }
@@ -1848,8 +1896,15 @@ extern "C" int spx_spgemm_plan(const spx_ctx* ctx, const spx_mat* A, const spx_m
   P->src = ProdSrc{A->ir, P->bq_a0, P->bq_alen, P->bq_split, P->splits, sstride, rb, (int32_t)m, 0};
   BinCfg bc{tune.tiny_max, tune.hash_count_max};
   if (nslots > 0) {
-    k_slot_mults<<<grid_for(nslots * kWave, 256, (int64_t)cus * 16), 256, 0, st>>>(P->B, P->bq_alen, nslots,
-                                                                                   P->mults_d, &P->sum->mults);
+    int32_t* longs = nullptr;
+    unsigned long long* nlong = nullptr;
+    SPX_TRY(scr.get_n(std::max<int64_t>(nslots, 1), &longs));
+    SPX_TRY(scr.get_n(1, &nlong));
+    SPX_TRY(fill_i64(reinterpret_cast<int64_t*>(nlong), 1, 0, st));
+    k_slot_mults<<<grid_for(nslots * 8, 256, (int64_t)cus * 16), 256, 0, st>>>(P->B, P->bq_alen, nslots, P->mults_d,
+                                                                              &P->sum->mults, longs, nlong);
+    SPX_HIP(hipGetLastError());
+    k_slot_mults_long<<<(unsigned)cus * 4, 256, 0, st>>>(P->B, P->bq_alen, longs, nlong, P->mults_d, &P->sum->mults);
     SPX_HIP(hipGetLastError());
     k_bin_count<<<grid_for(nslots, 256, (int64_t)cus * 8), 256, 0, st>>>(P->mults_d, nslots, bc, bincount);
     SPX_HIP(hipGetLastError());
@@ -1857,7 +1912,8 @@ extern "C" int spx_spgemm_plan(const spx_ctx* ctx, const spx_mat* A, const spx_m
   k_bin_offsets<<<1, 64, 0, st>>>(bincount, P->binoff, binfill);
   SPX_HIP(hipGetLastError());
   if (nslots > 0) {
-    k_bin_fill<<<grid_for(nslots, 256, (int64_t)cus * 8), 256, 0, st>>>(P->mults_d, nslots, bc, P->binoff, binfill,
+    k_bin_fill<<<grid_for(ceil_div(nslots, kFillPer), 256, (int64_t)cus * 8), 256, 0, st>>>(P->mults_d, nslots, bc,
+                                                                                           P->binoff, binfill,
                                                                         P->list);
     SPX_HIP(hipGetLastError());
   }
