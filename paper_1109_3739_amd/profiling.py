@@ -3,13 +3,15 @@
     python -m paper_1109_3739_amd.profiling stats  <results.db> [regex]
     python -m paper_1109_3739_amd.profiling traffic <fetch_counter_collection.csv> <write_counter_collection.csv>
         <kernel_regex> <copy_regex> <copy_bytes> <out.json>
+    python -m paper_1109_3739_amd.profiling counters <kernel_regex> <counter_collection.csv> [...]
 
 `stats` prints per-kernel dispatch counts and durations (grouped by kernel
 name and workgroup size).  `traffic` turns FETCH_SIZE / WRITE_SIZE (KiB per
 dispatch) of the kernels matching kernel_regex into HBM bytes per launch,
 each scaled by the ratio of the known size of a plain copy to what the same
 counter reports for that copy (copy_regex), and records the digest of the
-kernel sources the counters were taken on.
+kernel sources the counters were taken on.  `counters` prints the average
+per dispatch of every counter in the CSVs for the matching kernels.
 """
 from __future__ import annotations
 
@@ -66,6 +68,23 @@ def pmc_per_dispatch(csv_path: str, counter: str):
     return out
 
 
+def counters(kernel_regex: str, csv_paths) -> None:
+    """Average per dispatch of every counter in the given rocprofv3 counter
+    CSVs, per kernel and workgroup size, for kernels matching the regex."""
+    pat = re.compile(kernel_regex)
+    table = collections.defaultdict(dict)
+    for path in csv_paths:
+        names = sorted({r["Counter_Name"] for r in csv.DictReader(open(path))})
+        for name in names:
+            for (k, wg), vs in pmc_per_dispatch(path, name).items():
+                if pat.search(k):
+                    table[(re.sub(r"[(<].*", "", k), wg)][name] = (sum(vs) / len(vs), len(vs))
+    for (k, wg), row in sorted(table.items()):
+        print(f"{k} (workgroup {wg})")
+        for name, (avg, n) in sorted(row.items()):
+            print(f"  {name:36s} {avg:20.1f}   ({n} dispatches)")
+
+
 def traffic(fetch_csv, write_csv, kernel_regex, copy_regex, copy_bytes, out_json):
     kpat, cpat = re.compile(kernel_regex), re.compile(copy_regex)
     res = {"source_digest": source_digest(), "copy_bytes": int(copy_bytes), "kernels": {}}
@@ -98,6 +117,8 @@ def traffic(fetch_csv, write_csv, kernel_regex, copy_regex, copy_bytes, out_json
 if __name__ == "__main__":
     if len(sys.argv) >= 3 and sys.argv[1] == "stats":
         print_stats(sys.argv[2], sys.argv[3] if len(sys.argv) > 3 else ".*")
+    elif len(sys.argv) >= 4 and sys.argv[1] == "counters":
+        counters(sys.argv[2], sys.argv[3:])
     elif len(sys.argv) == 8 and sys.argv[1] == "traffic":
         traffic(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5], int(sys.argv[6]), sys.argv[7])
     else:
