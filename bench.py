@@ -17,7 +17,7 @@ on the library's stream over the timed steps), and the CPU oracle timed on
 a bounded sample of the same product.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-extra] [--no-cpu-baseline]
-    python bench.py --extra-only {latency,stages,tall,index,restriction}
+    python bench.py --extra-only {latency,stages,tall,index,restriction,galerkin}
 
 The other workloads (printed under "extra") give context: launch-bound
 latency, the Sparse SUMMA stage block and stage sum, the tall-skinny
@@ -324,11 +324,58 @@ def galerkin(spx, W, torch, count=512, seed=4):
         del Gs
         t_b = time_steps(batched, 3, torch.cuda.synchronize)
         t_p = time_steps(plain, 1, torch.cuda.synchronize)
+
+        # fused P^T A P: with the aggregation S = P^T, P^T A P = S A S^T, one
+        # contraction of the block-diagonal matrix of all instances with the
+        # concatenated aggregation maps (A P is never formed)
+        n64 = sizes.astype(np.int64)
+        fo = np.concatenate([[0], np.cumsum(n64 ** 3)])
+        co = np.concatenate([[0], np.cumsum((n64 // 2) ** 3)])
+        zo = np.concatenate([[0], np.cumsum([L[int(n)].nnz for n in sizes])])
+        dev = torch.device("cuda")
+        bd_cp = torch.cat([L[int(n)].cp[:-1] + int(zo[i]) for i, n in enumerate(sizes)]
+                          + [torch.tensor([int(zo[-1])], dtype=torch.int64, device=dev)])
+        bd_ir = torch.cat([L[int(n)].ir + int(fo[i]) for i, n in enumerate(sizes)])
+        bd_num = torch.cat([L[int(n)].num for n in sizes])
+        Abd = spx.SpMat(int(fo[-1]), int(fo[-1]), bd_cp, bd_ir, bd_num)
+
+        def agg_of(n):
+            v = torch.arange(n ** 3, dtype=torch.int64, device=dev)
+            h = n // 2
+            return ((v % n) // 2 + h * (((v // n) % n) // 2) + h * h * (v // (n * n) // 2)).to(torch.int32)
+
+        agg = torch.cat([agg_of(int(n)) + int(co[i]) for i, n in enumerate(sizes)])
+        nct = int(co[-1])
+
+        def fused():
+            q = spx.ContractPlan(Abd, agg, nct, agg, nct)
+            G = q.execute()
+            q.close()
+            return G
+
+        G = fused()
+        torch.cuda.synchronize()
+        cp_h, ir_h, num_h = G.cp.cpu().numpy(), G.ir.cpu().numpy(), G.num.cpu().numpy()
+        ok_f = True
+        for i, n in enumerate(sizes[:64]):
+            ref = W.laplacian7(int(n) // 2, dt)
+            c0, c1 = int(co[i]), int(co[i + 1])
+            sub_cp = cp_h[c0:c1 + 1] - cp_h[c0]
+            sl = slice(int(cp_h[c0]), int(cp_h[c1]))
+            ok_f &= bool(np.array_equal(sub_cp, ref.cp) and np.array_equal(ir_h[sl] - c0, ref.ir)
+                         and np.array_equal(num_h[sl], 4 * ref.num))
+        del G
+        t_f = time_steps(fused, 3, torch.cuda.synchronize)
+        fmults = int(zo[-1])
+        del Abd, bd_cp, bd_ir, bd_num, agg
         out[name] = {"batched_ms": round(1e3 * t_b, 3), "plain_ms": round(1e3 * t_p, 3),
                      "speedup": round(t_p / t_b, 2), "mults": mults,
                      "batched_gflops": round(2 * mults / t_b / 1e9, 2), "closed_form_ok_first64": ok,
+                     "fused_contraction_ms": round(1e3 * t_f, 3), "fused_mults": fmults,
+                     "fused_closed_form_ok_first64": ok_f,
                      "tuning": tinfo["tuning"], "tuning_cached": tinfo["cached"]}
-        log(f"galerkin {name}: batched {1e3 * t_b:.1f} ms, plain {1e3 * t_p:.1f} ms")
+        log(f"galerkin {name}: batched {1e3 * t_b:.1f} ms, fused contraction {1e3 * t_f:.1f} ms, "
+            f"plain {1e3 * t_p:.1f} ms")
         del L, P, PT, As, Ps, PTs
         torch.cuda.empty_cache()
     return out
@@ -374,7 +421,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-extra", action="store_true", help="skip the other workloads")
-    ap.add_argument("--extra-only", choices=["latency", "stages", "tall", "index", "restriction"],
+    ap.add_argument("--extra-only", choices=["latency", "stages", "tall", "index", "restriction", "galerkin"],
                     help="run only this group of the other workloads and print its figures")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -404,6 +451,9 @@ def main():
         sync()
         del x, y
         torch.cuda.empty_cache()
+    if args.extra_only == "galerkin":
+        print(json.dumps({"galerkin": galerkin(spx, W, torch)}), flush=True)
+        return
     if args.extra_only:
         print(json.dumps({"extra": extra_workloads(spx, W, torch, only=args.extra_only)}), flush=True)
         return

@@ -228,9 +228,11 @@ int spx_spgemm_sum_exec(spx_plan* plan, spx_mat* C);
  * contraction: S*A*S^T with one map for both sides).  The triple product
  * is one SpGEMM pass over A and forms neither S_r*A nor A*S_c^T (Section 6
  * asks for such a primitive).
- * row_agg must be non-decreasing (SPX_EUNSUPPORTED otherwise); col_agg may
- * be in any order.  Map values must lie in [0, coarse dimension)
- * (SPX_EINVAL).  Semirings: PLUS_TIMES (sums, S entries 1) and MIN_PLUS
+ * Maps may be in any order; values must lie in [0, coarse dimension)
+ * (SPX_EINVAL).  A non-decreasing row_agg keeps A's entry order; any other
+ * row_agg makes the plan sort every column of A by mapped row (columns of
+ * at most 4096 entries, SPX_EUNSUPPORTED otherwise; 12 more bytes per entry
+ * of A) and every exec gather A's values in that order.  Semirings: PLUS_TIMES (sums, S entries 1) and MIN_PLUS
  * (minima, S entries 0) on A's value type; SELECT1ST (minimum of A's
  * values) and OR_AND (pattern) with any A.  The plan keeps A's pointers and
  * values (patterns must stay unchanged; values may change between execs)

@@ -7,12 +7,14 @@
 // exactly one product, to C(row_agg(u), col_agg(v)):
 //     C = S_r * A * S_c^T = A_r * S_c^T,
 // where A_r is A with its row ids replaced by row_agg (same columns, same
-// values).  A non-decreasing row_agg keeps A_r's columns sorted (with
-// repeated row ids), which is all the SpGEMM kernels need: they only take
-// lower bounds over a column's rows, and their accumulators merge repeated
-// rows as they merge rows reached from several columns.  So the triple
-// product is one symbolic and one numeric pass over A; neither S_r * A nor
-// A * S_c^T is formed, and both parenthesizations give this same pass.
+// values).  The SpGEMM kernels need each column's rows non-decreasing (they
+// only take lower bounds over a column's rows, and their accumulators merge
+// repeated rows as they merge rows reached from several columns).  A
+// non-decreasing row_agg keeps A's order; any other map has the plan sort
+// each column of A_r by mapped row and keep the permutation, through which
+// every exec gathers A's values.  So the triple product is one symbolic and
+// one numeric pass over A; neither S_r * A nor A * S_c^T is formed, and both
+// parenthesizations give this same pass.
 // S_c^T (n x n') lists in column J the vertices v with col_agg(v) = J in
 // ascending order, with value one of the semiring (1 for PLUS_TIMES, 0 for
 // MIN_PLUS, pattern for SELECT1ST and OR_AND).
@@ -32,20 +34,30 @@ struct ContractPlan : spx_plan {
   ~ContractPlan() override {
     if (gemm) spx_plan_destroy(gemm);
   }
-  int32_t* air = nullptr;  // A's row ids through row_agg
+  int32_t* air = nullptr;  // A's row ids through row_agg (sorted within each column)
+  int64_t* aperm = nullptr;  // unsorted row_agg: source entry of each entry of A_r
+  void* anum = nullptr;      // and A's values in that order (refreshed by exec)
+  const void* src_num = nullptr;
+  int64_t nnz = 0;
+  int vb = 0;
   int64_t* scp = nullptr;  // S_c^T: [n'+1] pointers, [n] rows, [n] values
   int32_t* sir = nullptr;
   void* snum = nullptr;
   spx_plan* gemm = nullptr;
 };
 
-// err bit 1: an aggregate id out of range; bit 2: row_agg decreases somewhere.
+// err bit 1: an aggregate id out of range; bit 2 (row map) or 4 (column
+// map): the map decreases somewhere.  Flags are gathered per thread and
+// combined per wave, so an unsorted map costs one atomic per wave.
 __global__ void k_check_agg(const int32_t* agg, int64_t n, int64_t bound, unsigned* err, unsigned need_sorted) {
+  unsigned flags = 0;
   for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
     const int32_t a = agg[v];
-    if (a < 0 || a >= bound) atomicOr(err, 1u);
-    if (v + 1 < n && agg[v + 1] < a) atomicOr(err, need_sorted ? 2u : 4u);
+    if (a < 0 || a >= bound) flags |= 1u;
+    if (v + 1 < n && agg[v + 1] < a) flags |= need_sorted ? 2u : 4u;
   }
+  const uint64_t m1 = __ballot((flags & 1u) != 0), m2 = __ballot((flags & 6u) != 0);
+  if (lane_id() == 0 && (m1 | m2)) atomicOr(err, (m1 ? 1u : 0u) | (m2 ? (need_sorted ? 2u : 4u) : 0u));
 }
 
 __global__ void k_map_rows(const int32_t* ir, int64_t nnz, const int32_t* agg, int32_t* out) {
@@ -64,6 +76,15 @@ __global__ void k_iota(int32_t* out, int64_t n) {
     out[v] = (int32_t)v;
 }
 
+// Vertices into their aggregate's column of S_c^T (any order inside a column;
+// the column sort puts them in ascending order).
+__global__ void k_scatter_agg(const int32_t* agg, int64_t n, const int64_t* scp, unsigned* cur, int32_t* sir) {
+  for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t a = agg[v];
+    sir[scp[a] + atomicAdd(&cur[a], 1u)] = (int32_t)v;
+  }
+}
+
 __global__ void k_agg_keys(const int32_t* agg, int64_t n, uint64_t* keys) {
   for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
     keys[v] = ((uint64_t)(uint32_t)agg[v] << 32) | (uint32_t)v;
@@ -72,6 +93,108 @@ __global__ void k_agg_keys(const int32_t* agg, int64_t n, uint64_t* keys) {
 __global__ void k_key_low(const uint64_t* keys, int64_t n, int32_t* out) {
   for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
     out[v] = (int32_t)(uint32_t)keys[v];
+}
+
+// Sorting the columns of A_r by mapped row (unsorted row_agg), or the columns
+// of S_c^T by row (row_agg NULL; in place, no permutation).  Groups of
+// G lanes sort one stored column of at most G entries each ((row, position)
+// keys in registers): G = 16 takes every column and lists the longer ones,
+// G = 64 takes that list and lists the columns above 64 entries for
+// k_sort_cols_block.
+constexpr int kColSortMax = 4096;  // longest column the plan sorts (LDS bitonic)
+
+template <int G>
+__global__ void k_sort_cols_group(Operand A, const int32_t* row_agg, const int32_t* list_in,
+                                  const unsigned long long* nlist_in, int32_t* ir_r, int64_t* perm, int32_t* list_out,
+                                  unsigned long long* nlist_out) {
+  const int gl = lane_id() & (G - 1);
+  const int64_t n = list_in ? (int64_t)*nlist_in : nslots_of(A);
+  const int64_t g0 = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / G;
+  const int64_t ng = (int64_t)gridDim.x * blockDim.x / G;
+  for (int64_t i = g0; i < n; i += ng) {
+    const int64_t t = list_in ? list_in[i] : i;
+    const int64_t a0 = slot_begin(A, t), a1 = slot_begin(A, t + 1);
+    const int64_t len = a1 - a0;
+    if (len > G) {
+      if (gl == 0) list_out[atomicAdd(nlist_out, 1ull)] = (int32_t)t;
+      continue;
+    }
+    uint64_t key = ~0ull;
+    if (gl < len) {
+      const int32_t r = A.ir[a0 + gl];
+      key = ((uint64_t)(uint32_t)(row_agg ? row_agg[r] : r) << 32) | (uint32_t)gl;
+    }
+#pragma unroll
+    for (int k = 2; k <= G; k <<= 1) {
+#pragma unroll
+      for (int j = k >> 1; j > 0; j >>= 1) {
+        const uint64_t other = __shfl_xor(key, j, G);
+        const bool up = (gl & k) == 0, lower = (gl & j) == 0;
+        const uint64_t mn = other < key ? other : key, mx = other < key ? key : other;
+        key = (lower == up) ? mn : mx;
+      }
+    }
+    if (gl < len) {
+      ir_r[a0 + gl] = (int32_t)(key >> 32);
+      if (perm) perm[a0 + gl] = a0 + (int64_t)(uint32_t)key;
+    }
+  }
+}
+
+__global__ void __launch_bounds__(256) k_sort_cols_block(Operand A, const int32_t* row_agg, const int32_t* longs,
+                                                         const unsigned long long* nlong, int32_t* ir_r, int64_t* perm,
+                                                         unsigned* err) {
+  __shared__ uint64_t s[kColSortMax];
+  const int64_t nl = (int64_t)*nlong;
+  for (int64_t i = blockIdx.x; i < nl; i += gridDim.x) {
+    const int32_t t = longs[i];
+    const int64_t a0 = slot_begin(A, t), a1 = slot_begin(A, t + 1);
+    const int len = (int)(a1 - a0);
+    if (a1 - a0 > kColSortMax) {  // uniform
+      if (threadIdx.x == 0) atomicOr(err, 8u);
+      continue;
+    }
+    int p2 = 1;
+    while (p2 < len) p2 <<= 1;
+    for (int j = threadIdx.x; j < p2; j += blockDim.x) {
+      uint64_t key = ~0ull;
+      if (j < len) {
+        const int32_t r = A.ir[a0 + j];
+        key = ((uint64_t)(uint32_t)(row_agg ? row_agg[r] : r) << 32) | (uint32_t)j;
+      }
+      s[j] = key;
+    }
+    __syncthreads();
+    for (int k = 2; k <= p2; k <<= 1) {
+      for (int jj = k >> 1; jj > 0; jj >>= 1) {
+        for (int x = threadIdx.x; x < (p2 >> 1); x += blockDim.x) {
+          const int lo = 2 * x - (x & (jj - 1));
+          const int hi = lo + jj;
+          const bool asc = (lo & k) == 0;
+          const uint64_t a = s[lo], b = s[hi];
+          if ((a > b) == asc) {
+            s[lo] = b;
+            s[hi] = a;
+          }
+        }
+        __syncthreads();
+      }
+    }
+    for (int j = threadIdx.x; j < len; j += blockDim.x) {
+      ir_r[a0 + j] = (int32_t)(s[j] >> 32);
+      if (perm) perm[a0 + j] = a0 + (int64_t)(uint32_t)s[j];
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void k_gather_values(const int64_t* perm, int64_t n, const void* src, int vb, void* dst) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+    if (vb == 8)
+      static_cast<uint64_t*>(dst)[e] = static_cast<const uint64_t*>(src)[perm[e]];
+    else
+      static_cast<uint32_t*>(dst)[e] = static_cast<const uint32_t*>(src)[perm[e]];
+  }
 }
 
 template <typename T>
@@ -129,16 +252,49 @@ extern "C" int spx_contract_plan(const spx_ctx* ctx, const spx_mat* A, const int
   SPX_HIP(hipMemcpyAsync(&cerr_h, cerr, 4, hipMemcpyDeviceToHost, st));
   SPX_HIP(hipStreamSynchronize(st));
   if ((err_h | cerr_h) & 1u) return fail(SPX_EINVAL, "an aggregate id is out of range");
-  if (err_h & 2u) return fail(SPX_EUNSUPPORTED, "row_agg must be non-decreasing");
+  const bool row_sorted = !(err_h & 2u);
   const bool col_sorted = !(cerr_h & 4u);
 
   // left operand: A with mapped rows (A's pointers and values)
   spx_mat Ar = *A;
   if (row_agg) {
     SPX_TRY(scr.get_n(std::max<int64_t>(A->nnz, 1), &P->air));
-    if (A->nnz > 0) {
-      k_map_rows<<<grid_for(A->nnz, 256, 65536), 256, 0, st>>>(A->ir, A->nnz, row_agg, P->air);
+    if (row_sorted) {
+      if (A->nnz > 0) {
+        k_map_rows<<<grid_for(A->nnz, 256, 65536), 256, 0, st>>>(A->ir, A->nnz, row_agg, P->air);
+        SPX_HIP(hipGetLastError());
+      }
+    } else if (A->nnz > 0) {
+      // sort every column by mapped row; values follow through the permutation
+      const Operand Ao = make_operand(A);
+      const int64_t ns = nslots_of(Ao);
+      int32_t *mids = nullptr, *longs = nullptr;
+      unsigned long long* nl = nullptr;  // [0] columns above 16 entries, [1] above 64
+      SPX_TRY(scr.get_n(std::max<int64_t>(A->nnz, 1), &P->aperm));
+      SPX_TRY(scr.get_n(std::max<int64_t>(ns, 1), &mids));
+      SPX_TRY(scr.get_n(std::max<int64_t>(ns, 1), &longs));
+      SPX_TRY(scr.get_n(2, &nl));
+      SPX_TRY(fill_i64(reinterpret_cast<int64_t*>(nl), 2, 0, st));
+      k_sort_cols_group<16><<<grid_for(ns * 16, 256, 65536), 256, 0, st>>>(Ao, row_agg, nullptr, nullptr, P->air,
+                                                                            P->aperm, mids, nl);
       SPX_HIP(hipGetLastError());
+      k_sort_cols_group<kWave><<<(unsigned)device_cu_count() * 16, 256, 0, st>>>(Ao, row_agg, mids, nl, P->air,
+                                                                                 P->aperm, longs, nl + 1);
+      SPX_HIP(hipGetLastError());
+      unsigned long long* nlong = nl + 1;
+      k_sort_cols_block<<<(unsigned)device_cu_count() * 4, 256, 0, st>>>(Ao, row_agg, longs, nlong, P->air, P->aperm,
+                                                                        err);
+      SPX_HIP(hipGetLastError());
+      SPX_HIP(hipMemcpyAsync(&err_h, err, 4, hipMemcpyDeviceToHost, st));
+      SPX_HIP(hipStreamSynchronize(st));
+      if (err_h & 8u) return fail(SPX_EUNSUPPORTED, "with an unsorted row_agg, columns of A may hold at most 4096 entries");
+      P->vb = value_size(A->val_t);
+      P->nnz = A->nnz;
+      P->src_num = A->num;
+      if (P->vb) {
+        SPX_TRY(scr.get(A->nnz * P->vb, &P->anum));
+        Ar.num = P->anum;
+      }
     }
     Ar.ir = P->air;
     Ar.m = m_coarse;
@@ -162,13 +318,48 @@ extern "C" int spx_contract_plan(const spx_ctx* ctx, const spx_mat* A, const int
       k_iota<<<grid_for(n, 256, 65536), 256, 0, st>>>(P->sir, n);
       SPX_HIP(hipGetLastError());
     } else if (n > 0) {
-      uint64_t* keys = nullptr;
-      SPX_TRY(scr.get_n(sort_capacity(n), &keys));
-      k_agg_keys<<<grid_for(n, 256, 65536), 256, 0, st>>>(col_agg, n, keys);
+      // counting scatter into the aggregates' columns, then each column sorted
+      unsigned* cur = nullptr;
+      int32_t *mids = nullptr, *longs = nullptr;
+      unsigned long long* nl = nullptr;
+      SPX_TRY(scr.get_n(std::max<int64_t>(n_coarse, 1), &cur));
+      SPX_TRY(scr.get_n(std::max<int64_t>(n_coarse, 1), &mids));
+      SPX_TRY(scr.get_n(std::max<int64_t>(n_coarse, 1), &longs));
+      SPX_TRY(scr.get_n(2, &nl));
+      SPX_TRY(fill_u32(cur, n_coarse, 0, st));
+      SPX_TRY(fill_i64(reinterpret_cast<int64_t*>(nl), 2, 0, st));
+      SPX_TRY(fill_u32(err, 1, 0, st));
+      k_scatter_agg<<<grid_for(n, 256, 65536), 256, 0, st>>>(col_agg, n, P->scp, cur, P->sir);
       SPX_HIP(hipGetLastError());
-      SPX_TRY(sort_u64(keys, n, st));
-      k_key_low<<<grid_for(n, 256, 65536), 256, 0, st>>>(keys, n, P->sir);
+      Operand So{};
+      So.m = n;
+      So.n = n_coarse;
+      So.nnz = n;
+      So.fmt = SPX_CSC;
+      So.ptr_t = SPX_PTR_I64;
+      So.val_t = SPX_VAL_BOOL;
+      So.cp = P->scp;
+      So.ir = P->sir;
+      k_sort_cols_group<16><<<grid_for(n_coarse * 16, 256, 65536), 256, 0, st>>>(So, nullptr, nullptr, nullptr, P->sir,
+                                                                                  nullptr, mids, nl);
       SPX_HIP(hipGetLastError());
+      k_sort_cols_group<kWave><<<(unsigned)device_cu_count() * 16, 256, 0, st>>>(So, nullptr, mids, nl, P->sir,
+                                                                                 nullptr, longs, nl + 1);
+      SPX_HIP(hipGetLastError());
+      k_sort_cols_block<<<(unsigned)device_cu_count() * 4, 256, 0, st>>>(So, nullptr, longs, nl + 1, P->sir, nullptr,
+                                                                        err);
+      SPX_HIP(hipGetLastError());
+      SPX_HIP(hipMemcpyAsync(&err_h, err, 4, hipMemcpyDeviceToHost, st));
+      SPX_HIP(hipStreamSynchronize(st));
+      if (err_h & 8u) {  // an aggregate above 4096 vertices: one global sort of (aggregate, vertex) keys
+        uint64_t* keys = nullptr;
+        SPX_TRY(scr.get_n(sort_capacity(n), &keys));
+        k_agg_keys<<<grid_for(n, 256, 65536), 256, 0, st>>>(col_agg, n, keys);
+        SPX_HIP(hipGetLastError());
+        SPX_TRY(sort_u64(keys, n, st));
+        k_key_low<<<grid_for(n, 256, 65536), 256, 0, st>>>(keys, n, P->sir);
+        SPX_HIP(hipGetLastError());
+      }
     }
   } else {  // S_c = I: scp[j] = j, sir[v] = v
     int64_t* ones = nullptr;
@@ -211,7 +402,13 @@ extern "C" int spx_contract_plan(const spx_ctx* ctx, const spx_mat* A, const int
 
 extern "C" int spx_contract_exec(spx_plan* plan, spx_mat* C) {
   if (!plan || plan->kind != kPlanContract) return fail(SPX_EINVAL, "not a contraction plan");
-  return spx_spgemm_exec(static_cast<ContractPlan*>(plan)->gemm, C);
+  auto* P = static_cast<ContractPlan*>(plan);
+  if (P->aperm && P->vb && P->nnz > 0) {  // A's current values in the sorted order
+    k_gather_values<<<grid_for(P->nnz, 256, 65536), 256, 0, stream_of(&P->ctx)>>>(P->aperm, P->nnz, P->src_num,
+                                                                                   P->vb, P->anum);
+    SPX_HIP(hipGetLastError());
+  }
+  return spx_spgemm_exec(P->gemm, C);
 }
 
 namespace spx {

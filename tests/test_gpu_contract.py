@@ -75,12 +75,32 @@ def test_restriction_order8_rmat18(spx):
     contract_check(spx, A, agg, A.n // 8, agg, A.n // 8)
 
 
+def test_unsorted_row_maps(spx):
+    # any row aggregation: the plan sorts A's columns by mapped row (one wave
+    # per column up to 64 entries, a workgroup up to 4096) and exec gathers
+    # A's values through the permutation
+    rng = np.random.default_rng(89)
+    A = W.rmat(12, 8, seed=90, values="edge_id")
+    agg = rng.integers(0, 600, size=A.n)
+    contract_check(spx, A, agg, 600, agg, 600, exact=True)            # graph contraction, random aggregates
+    contract_check(spx, A, agg, 600, None, 0, exact=True, a_dcsc=True)
+    contract_check(spx, A, np.arange(A.m)[::-1], A.m, None, 0, exact=True)  # a reversal
+    Af = W.rmat(12, 8, seed=91, values="f64")
+    contract_check(spx, Af, agg, 600, agg, 600, "min_plus", exact=True)
+    contract_check(spx, Af, agg, 600, agg, 600, out_fmt=1)
+    # columns of 100 to 3000 entries take the workgroup sort
+    D = W.erdos_renyi(5000, 40, 3000, seed=92, values="edge_id")
+    ragg = rng.integers(0, 70, size=D.m)
+    contract_check(spx, D, ragg, 70, np.arange(40) // 4, 10, exact=True)
+
+
 def test_contraction_errors(spx):
     import torch
     A = spx.from_host(W.erdos_renyi(20, 20, 3, seed=1))
-    down = torch.from_numpy(np.arange(20, dtype=np.int32)[::-1].copy()).cuda()
+    L = spx.from_host(W.erdos_renyi(6000, 3, 5000, seed=2))  # a column above 4096 entries
+    down = torch.from_numpy(np.arange(6000, dtype=np.int32)[::-1].copy()).cuda()
     with pytest.raises(spx.SpxError) as e:
-        spx.contract(A, down, 20, None, 0)
+        spx.contract(L, down, 6000, None, 0)
     assert e.value.code == spx.SPX_EUNSUPPORTED
     big = torch.full((20,), 7, dtype=torch.int32, device="cuda")
     with pytest.raises(spx.SpxError) as e:
