@@ -98,47 +98,88 @@ __global__ void k_key_low(const uint64_t* keys, int64_t n, int32_t* out) {
 // Sorting the columns of A_r by mapped row (unsorted row_agg), or the columns
 // of S_c^T by row (row_agg NULL; in place, no permutation).  Groups of
 // G lanes sort one stored column of at most G entries each ((row, position)
-// keys in registers): G = 16 takes every column and lists the longer ones,
+// keys in registers): G = 8 takes every column and lists the longer ones,
 // G = 64 takes that list and lists the columns above 64 entries for
-// k_sort_cols_block.
+// k_sort_cols_block.  A sort is a chain of lane exchanges, so short groups
+// and 32-bit keys (K = uint32_t: the row above log2(G) position bits, when
+// the rows fit) keep the chain short.  Each group loads U columns before it
+// sorts any of them, so the loads of U columns overlap.
 constexpr int kColSortMax = 4096;  // longest column the plan sorts (LDS bitonic)
 
-template <int G>
+template <int G, int U, typename K>
 __global__ void k_sort_cols_group(Operand A, const int32_t* row_agg, const int32_t* list_in,
                                   const unsigned long long* nlist_in, int32_t* ir_r, int64_t* perm, int32_t* list_out,
                                   unsigned long long* nlist_out) {
+  constexpr int kPosBits = G == 8 ? 3 : (G == 16 ? 4 : (G == 32 ? 5 : 6));
+  constexpr int kShift = sizeof(K) == 4 ? kPosBits : 32;
   const int gl = lane_id() & (G - 1);
   const int64_t n = list_in ? (int64_t)*nlist_in : nslots_of(A);
   const int64_t g0 = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / G;
   const int64_t ng = (int64_t)gridDim.x * blockDim.x / G;
-  for (int64_t i = g0; i < n; i += ng) {
-    const int64_t t = list_in ? list_in[i] : i;
-    const int64_t a0 = slot_begin(A, t), a1 = slot_begin(A, t + 1);
-    const int64_t len = a1 - a0;
-    if (len > G) {
-      if (gl == 0) list_out[atomicAdd(nlist_out, 1ull)] = (int32_t)t;
-      continue;
-    }
-    uint64_t key = ~0ull;
-    if (gl < len) {
-      const int32_t r = A.ir[a0 + gl];
-      key = ((uint64_t)(uint32_t)(row_agg ? row_agg[r] : r) << 32) | (uint32_t)gl;
+  for (int64_t i = g0; i < n; i += U * ng) {
+    int64_t t[U], a0[U], len[U];
+    int32_t key_row[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t idx = i + u * ng;
+      t[u] = idx < n ? (list_in ? (int64_t)list_in[idx] : idx) : -1;
     }
 #pragma unroll
-    for (int k = 2; k <= G; k <<= 1) {
+    for (int u = 0; u < U; ++u) {
+      a0[u] = t[u] >= 0 ? slot_begin(A, t[u]) : 0;
+      len[u] = t[u] >= 0 ? slot_begin(A, t[u] + 1) - a0[u] : 0;
+    }
 #pragma unroll
-      for (int j = k >> 1; j > 0; j >>= 1) {
-        const uint64_t other = __shfl_xor(key, j, G);
-        const bool up = (gl & k) == 0, lower = (gl & j) == 0;
-        const uint64_t mn = other < key ? other : key, mx = other < key ? key : other;
-        key = (lower == up) ? mn : mx;
+    for (int u = 0; u < U; ++u) key_row[u] = gl < len[u] && len[u] <= G ? A.ir[a0[u] + gl] : 0;
+    if (row_agg) {
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (gl < len[u] && len[u] <= G) key_row[u] = row_agg[key_row[u]];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (t[u] < 0) continue;  // uniform in the group
+      if (len[u] > G) {
+        if (gl == 0) list_out[atomicAdd(nlist_out, 1ull)] = (int32_t)t[u];
+        continue;
+      }
+      K key = gl < len[u] ? (K)(((K)(uint32_t)key_row[u] << kShift) | (K)gl) : ~(K)0;
+#pragma unroll
+      for (int k = 2; k <= G; k <<= 1) {
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1) {
+          const K other = __shfl_xor(key, j, G);
+          const bool up = (gl & k) == 0, lower = (gl & j) == 0;
+          const K mn = other < key ? other : key, mx = other < key ? key : other;
+          key = (lower == up) ? mn : mx;
+        }
+      }
+      if (gl < len[u]) {
+        ir_r[a0[u] + gl] = (int32_t)(key >> kShift);
+        if (perm) perm[a0[u] + gl] = a0[u] + (int64_t)(key & (((K)1 << kShift) - 1));
       }
     }
-    if (gl < len) {
-      ir_r[a0 + gl] = (int32_t)(key >> 32);
-      if (perm) perm[a0 + gl] = a0 + (int64_t)(uint32_t)key;
-    }
   }
+}
+
+// Launches the group tiers over every column of A; columns longer than 64
+// entries are listed in `longs` (count in nl[1]).  nl[0..1] must be zero.
+// `max_row` bounds the sort keys' rows (exclusive).
+static int sort_cols_groups(const Operand& A, const int32_t* row_agg, int64_t ns, int64_t max_row, int32_t* ir_r,
+                            int64_t* perm, int32_t* mids, int32_t* longs, unsigned long long* nl, hipStream_t st) {
+  const unsigned g8 = grid_for(ns * 8 / 2, 256, 65536);
+  if (max_row <= (1ll << 29))
+    k_sort_cols_group<8, 2, uint32_t><<<g8, 256, 0, st>>>(A, row_agg, nullptr, nullptr, ir_r, perm, mids, nl);
+  else
+    k_sort_cols_group<8, 2, uint64_t><<<g8, 256, 0, st>>>(A, row_agg, nullptr, nullptr, ir_r, perm, mids, nl);
+  SPX_HIP(hipGetLastError());
+  const unsigned g64 = (unsigned)device_cu_count() * 16;
+  if (max_row <= (1ll << 26))
+    k_sort_cols_group<kWave, 1, uint32_t><<<g64, 256, 0, st>>>(A, row_agg, mids, nl, ir_r, perm, longs, nl + 1);
+  else
+    k_sort_cols_group<kWave, 1, uint64_t><<<g64, 256, 0, st>>>(A, row_agg, mids, nl, ir_r, perm, longs, nl + 1);
+  SPX_HIP(hipGetLastError());
+  return SPX_OK;
 }
 
 __global__ void __launch_bounds__(256) k_sort_cols_block(Operand A, const int32_t* row_agg, const int32_t* longs,
@@ -269,18 +310,13 @@ extern "C" int spx_contract_plan(const spx_ctx* ctx, const spx_mat* A, const int
       const Operand Ao = make_operand(A);
       const int64_t ns = nslots_of(Ao);
       int32_t *mids = nullptr, *longs = nullptr;
-      unsigned long long* nl = nullptr;  // [0] columns above 16 entries, [1] above 64
+      unsigned long long* nl = nullptr;  // [0] columns above 8 entries, [1] above 64
       SPX_TRY(scr.get_n(std::max<int64_t>(A->nnz, 1), &P->aperm));
       SPX_TRY(scr.get_n(std::max<int64_t>(ns, 1), &mids));
       SPX_TRY(scr.get_n(std::max<int64_t>(ns, 1), &longs));
       SPX_TRY(scr.get_n(2, &nl));
       SPX_TRY(fill_i64(reinterpret_cast<int64_t*>(nl), 2, 0, st));
-      k_sort_cols_group<16><<<grid_for(ns * 16, 256, 65536), 256, 0, st>>>(Ao, row_agg, nullptr, nullptr, P->air,
-                                                                            P->aperm, mids, nl);
-      SPX_HIP(hipGetLastError());
-      k_sort_cols_group<kWave><<<(unsigned)device_cu_count() * 16, 256, 0, st>>>(Ao, row_agg, mids, nl, P->air,
-                                                                                 P->aperm, longs, nl + 1);
-      SPX_HIP(hipGetLastError());
+      SPX_TRY(sort_cols_groups(Ao, row_agg, ns, m_coarse, P->air, P->aperm, mids, longs, nl, st));
       unsigned long long* nlong = nl + 1;
       k_sort_cols_block<<<(unsigned)device_cu_count() * 4, 256, 0, st>>>(Ao, row_agg, longs, nlong, P->air, P->aperm,
                                                                         err);
@@ -340,12 +376,7 @@ extern "C" int spx_contract_plan(const spx_ctx* ctx, const spx_mat* A, const int
       So.val_t = SPX_VAL_BOOL;
       So.cp = P->scp;
       So.ir = P->sir;
-      k_sort_cols_group<16><<<grid_for(n_coarse * 16, 256, 65536), 256, 0, st>>>(So, nullptr, nullptr, nullptr, P->sir,
-                                                                                  nullptr, mids, nl);
-      SPX_HIP(hipGetLastError());
-      k_sort_cols_group<kWave><<<(unsigned)device_cu_count() * 16, 256, 0, st>>>(So, nullptr, mids, nl, P->sir,
-                                                                                 nullptr, longs, nl + 1);
-      SPX_HIP(hipGetLastError());
+      SPX_TRY(sort_cols_groups(So, nullptr, n_coarse, n, P->sir, nullptr, mids, longs, nl, st));
       k_sort_cols_block<<<(unsigned)device_cu_count() * 4, 256, 0, st>>>(So, nullptr, longs, nl + 1, P->sir, nullptr,
                                                                         err);
       SPX_HIP(hipGetLastError());

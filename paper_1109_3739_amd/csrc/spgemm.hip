@@ -643,10 +643,21 @@ __device__ __forceinline__ void tiny_column(const Operand& A, const Operand& B, 
   s_aux += gb;
   s_val += gb;
   const int64_t b0 = slot_begin(B, t), b1 = slot_begin(B, t + 1);
+  // the output offset is loaded with the column's pointers, so its latency
+  // overlaps theirs instead of adding a level at the end
+  const int64_t obase = COUNT ? 0 : off[t];
+  const T* an = (const T*)A.num;
+  const T* bn = (const T*)B.num;
   int total = 0;
   for (int64_t qc = b0; qc < b1; qc += G) {
     const int64_t q = qc + gl;
-    const int al = q < b1 ? bq_alen[q] : 0;
+    const bool inq = q < b1;
+    // each lane loads its own B entry's A range (and value) next to its
+    // length; the lanes that take the products get them by shuffles
+    const int al = inq ? bq_alen[q] : 0;
+    const int64_t qa0 = inq ? bq_a0[q] : 0;
+    T qb = T(0);
+    if constexpr (kVal && S::kUsesB) qb = inq ? bn[q] : T(0);
     const int incl = group_incl_scan<G>(al, gl);
     const int excl = incl - al;
     const int ctot = __shfl(incl, G - 1, G);
@@ -661,16 +672,16 @@ __device__ __forceinline__ void tiny_column(const Operand& A, const Operand& B, 
       const int u = __shfl_up(o, d, G);
       if (gl >= d && u > o) o = u;
     }
-    const int ostart = __shfl(excl, o < 0 ? 0 : o, G);
+    const int src = o < 0 ? 0 : o;
+    const int ostart = __shfl(excl, src, G);
+    const int64_t ea0 = __shfl(qa0, src, G);
+    T bv = T(0);
+    if constexpr (kVal && S::kUsesB) bv = __shfl(qb, src, G);
     if (gl < ctot && total + gl < G) {
-      const int64_t qq = qc + o;
-      const int64_t e = bq_a0[qq] + (gl - ostart);
+      const int64_t e = ea0 + (gl - ostart);
       s_row[total + gl] = A.ir[e];
       if constexpr (kVal) {
-        const T* an = (const T*)A.num;
-        const T* bn = (const T*)B.num;
         const T a = S::kUsesA ? an[e] : T(0);
-        const T bv = S::kUsesB ? bn[qq] : T(0);
         s_val[total + gl] = S::mul(a, bv);
       }
     }
@@ -701,18 +712,25 @@ __device__ __forceinline__ void tiny_column(const Operand& A, const Operand& B, 
   if (COUNT) {
     if (gl == 0) cnt[t] = __popcll(hm);
   } else {
-    wave_sync();
-    s_row[gl] = row;
-    s_aux[gl] = idx;
-    wave_sync();
-    if (head) {
-      const int64_t o = off[t] + __popcll(hm & lanemask_lt());
-      cir[o] = row;
-      if constexpr (kVal) {
-        T acc = s_val[idx];
-        for (int l2 = gl + 1; l2 < total && s_row[l2] == row; ++l2) acc = S::add(acc, s_val[s_aux[l2]]);
-        cnum[o] = acc;
+    // every lane holds its sorted product's value; a head lane folds its run
+    // left to right (product order) from the values of the lanes after it
+    const uint64_t hg = hm >> gb;  // the group's heads, bit gl for lane gl
+    const uint64_t later = gl + 1 < 64 ? hg >> (gl + 1) : 0ull;
+    const int run = !head ? 0 : (later ? __ffsll((long long)later) : total - gl);
+    T acc = T(0);
+    if constexpr (kVal) {
+      const T v = valid ? s_val[idx] : T(0);
+      acc = v;
+      const int maxrun = wave_max(run);
+      for (int d = 1; d < maxrun; ++d) {
+        const T x = __shfl_down(v, (unsigned)d, G);
+        if (d < run) acc = S::add(acc, x);
       }
+    }
+    if (head) {
+      const int64_t o = obase + __popcll(hm & lanemask_lt());
+      cir[o] = row;
+      if constexpr (kVal) cnum[o] = acc;
     }
   }
   wave_sync();
@@ -730,11 +748,21 @@ __global__ void __launch_bounds__(256) k_tiny(Operand A, Operand B, const int64_
   __shared__ T s_val[4][kWave];
   const int w = threadIdx.x / kWave, lane = lane_id();
   const int64_t beg = binoff[kBinTiny], end = binoff[kBinTiny + 1];
-  for (int64_t pos = beg + ((int64_t)blockIdx.x * 4 + w) * 2; pos < end; pos += (int64_t)gridDim.x * 8) {
-    const int32_t t0 = list[pos];
+  const int64_t stride = (int64_t)gridDim.x * 8;
+  int64_t pos = beg + ((int64_t)blockIdx.x * 4 + w) * 2;
+  // the column ids of the wave's next pair are loaded one pair ahead
+  int32_t t0 = 0, t1 = 0;
+  if (pos < end) {
+    t0 = list[pos];
+    t1 = pos + 1 < end ? list[pos + 1] : 0;
+  }
+  for (; pos < end; pos += stride) {
     const bool has1 = pos + 1 < end;
-    const int32_t t1 = has1 ? list[pos + 1] : 0;
-    if (has1 && mults[t0] <= 32 && mults[t1] <= 32) {
+    const int64_t m0 = mults[t0], m1 = has1 ? mults[t1] : 0;
+    const int64_t np = pos + stride;
+    const int32_t n0 = np < end ? list[np] : 0;
+    const int32_t n1 = np + 1 < end ? list[np + 1] : 0;
+    if (has1 && m0 <= 32 && m1 <= 32) {
       tiny_column<32, SR, T, COUNT>(A, B, bq_a0, bq_alen, lane < 32 ? t0 : t1, cnt, off, cir, cnum, s_row[w], s_aux[w],
                                     s_val[w]);
     } else {
@@ -742,6 +770,8 @@ __global__ void __launch_bounds__(256) k_tiny(Operand A, Operand B, const int64_
       if (has1)
         tiny_column<64, SR, T, COUNT>(A, B, bq_a0, bq_alen, t1, cnt, off, cir, cnum, s_row[w], s_aux[w], s_val[w]);
     }
+    t0 = n0;
+    t1 = n1;
   }
 }
 

@@ -121,3 +121,15 @@ def test_contraction_int32_pointers_and_empty(spx):
     e = np.arange(64) // 8
     contract_check(spx, E, e, 8, e, 8, exact=True)
     contract_check(spx, E, None, 0, None, 0, exact=True)
+
+
+def test_unsorted_row_map_wide_ids(spx):
+    # mapped rows above 2^26 leave too few bits for a 32-bit (row, position)
+    # key in the 64-lane sort, which then takes 64-bit keys
+    rng = np.random.default_rng(95)
+    m = (1 << 26) + 4096
+    A = W.erdos_renyi(m, 64, 40, seed=94, values="edge_id")
+    agg = rng.integers(0, m, size=m, dtype=np.int64).astype(np.int32)
+    agg[A.ir[:5]] = m - 1  # the largest id, and repeated rows
+    contract_check(spx, A, agg, m, None, 0, exact=True)
+    contract_check(spx, A, agg, m, np.arange(64) // 2, 32, exact=True)
