@@ -42,6 +42,19 @@ def test_er_config_plus_times_and_min_plus(spx):
     check_against_oracle(spx, A, A, "min_plus", exact=True)
 
 
+@pytest.mark.parametrize("d", [4, 8])
+@pytest.mark.parametrize("values", ["f64", "f32"])
+def test_tiny_columns_add_in_product_order(spx, d, values):
+    # columns of at most 64 products (d^2 here) take the one-wave path, which
+    # adds each row's products in Algorithm 1's order (B's entries in storage
+    # order, then A's rows): the floating-point sums equal the oracle's bitwise.
+    # d = 4 pairs two columns per wave, d = 8 gives each column a whole wave.
+    A = W.erdos_renyi(4096, 4096, d, seed=30 + d, values=values)
+    B = W.erdos_renyi(4096, 4096, d, seed=40 + d, values=values)
+    C, info = check_against_oracle(spx, A, B, "plus_times", exact=True)
+    assert info["cols_tiny"] == 4096
+
+
 @pytest.mark.parametrize("semiring,values,exact", [
     ("plus_times", "f64", False), ("plus_times", "f32", False), ("plus_times", "small_int", True),
     ("min_plus", "f64", True), ("min_plus", "f32", True), ("min_plus", "small_int", True),
