@@ -155,6 +155,38 @@ __device__ __forceinline__ T wave_incl_scan(T v) {
   return v;
 }
 
+// Value held by lane (lane ^ j), j a power of two below 64, without the LDS
+// permute path: j = 1, 2 are quad permutes (DPP); j = 4 a half-row mirror
+// (lane -> lane ^ 7) followed by a quad reversal (^ 3); j = 8 a rotation of
+// each 16-lane row by 8; j = 16 and 32 the gfx950 lane swaps, which return
+// every row pair (half pair) as [even, even] and [odd, odd], so a lane takes
+// the copy of the other row.  The source lane must be active; j must be a
+// constant after unrolling (the switch folds away).
+__device__ __forceinline__ uint32_t xor_lane_u32(uint32_t v, int j) {
+  switch (j) {
+    case 1: return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, false);
+    case 2: return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xF, 0xF, false);
+    case 4: {
+      const int m = __builtin_amdgcn_update_dpp(0, (int)v, 0x141, 0xF, 0xF, false);
+      return (uint32_t)__builtin_amdgcn_update_dpp(0, m, 0x1B, 0xF, 0xF, false);
+    }
+    case 8: return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x128, 0xF, 0xF, false);
+    case 16: {
+      const auto s = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+      return (__lane_id() & 16) ? s[0] : s[1];
+    }
+    default: {
+      const auto s = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+      return (__lane_id() & 32) ? s[0] : s[1];
+    }
+  }
+}
+__device__ __forceinline__ uint64_t xor_lane(uint64_t v, int j) {
+  const uint32_t lo = xor_lane_u32((uint32_t)v, j), hi = xor_lane_u32((uint32_t)(v >> 32), j);
+  return ((uint64_t)hi << 32) | lo;
+}
+__device__ __forceinline__ uint32_t xor_lane(uint32_t v, int j) { return xor_lane_u32(v, j); }
+
 __device__ __forceinline__ uint64_t lanemask_lt() {
   const int lane = lane_id();
   return lane == 0 ? 0ull : (~0ull >> (64 - lane));

@@ -148,7 +148,7 @@ __global__ void k_sort_cols_group(Operand A, const int32_t* row_agg, const int32
       for (int k = 2; k <= G; k <<= 1) {
 #pragma unroll
         for (int j = k >> 1; j > 0; j >>= 1) {
-          const K other = __shfl_xor(key, j, G);
+          const K other = xor_lane(key, j);
           const bool up = (gl & k) == 0, lower = (gl & j) == 0;
           const K mn = other < key ? other : key, mx = other < key ? key : other;
           key = (lower == up) ? mn : mx;

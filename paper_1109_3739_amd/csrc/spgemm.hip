@@ -561,42 +561,6 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Ascending bitonic sort of one 64-bit key per lane across the wave.
-__device__ __forceinline__ uint64_t wave_sort_u64(uint64_t key) {
-  const int lane = lane_id();
-#pragma unroll
-  for (int k = 2; k <= kWave; k <<= 1) {
-#pragma unroll
-    for (int j = k >> 1; j > 0; j >>= 1) {
-      const uint64_t other = __shfl_xor(key, j);
-      const bool up = (lane & k) == 0;
-      const bool lower = (lane & j) == 0;
-      const uint64_t mn = other < key ? other : key;
-      const uint64_t mx = other < key ? key : other;
-      key = (lower == up) ? mn : mx;
-    }
-  }
-  return key;
-}
-
-// The same for 32-bit keys (one lane exchange per step instead of two).
-__device__ __forceinline__ uint32_t wave_sort_u32(uint32_t key) {
-  const int lane = lane_id();
-#pragma unroll
-  for (int k = 2; k <= kWave; k <<= 1) {
-#pragma unroll
-    for (int j = k >> 1; j > 0; j >>= 1) {
-      const uint32_t other = __shfl_xor(key, j);
-      const bool up = (lane & k) == 0;
-      const bool lower = (lane & j) == 0;
-      const uint32_t mn = other < key ? other : key;
-      const uint32_t mx = other < key ? key : other;
-      key = (lower == up) ? mn : mx;
-    }
-  }
-  return key;
-}
-
 // Group-wide helpers over G lanes: the whole wave (G = 64) or one of its
 // aligned halves (G = 32); shuffles stay inside the group.
 template <int G>
@@ -615,7 +579,7 @@ __device__ __forceinline__ K group_sort(K key, int gl) {  // ascending bitonic s
   for (int k = 2; k <= G; k <<= 1) {
 #pragma unroll
     for (int j = k >> 1; j > 0; j >>= 1) {
-      const K other = __shfl_xor(key, j, G);
+      const K other = xor_lane(key, j);
       const bool up = (gl & k) == 0;
       const bool lower = (gl & j) == 0;
       const K mn = other < key ? other : key;

@@ -156,7 +156,7 @@ __device__ __forceinline__ uint64_t wave_sort_keys(uint64_t key) {
   for (int k = 2; k <= kWave; k <<= 1) {
 #pragma unroll
     for (int j = k >> 1; j > 0; j >>= 1) {
-      const uint64_t other = __shfl_xor(key, j);
+      const uint64_t other = xor_lane(key, j);
       const bool up = (lane & k) == 0;
       const bool lower = (lane & j) == 0;
       const uint64_t mn = other < key ? other : key;
