@@ -562,15 +562,40 @@ __device__ __forceinline__ void wave_sync() {
 }
 
 // Group-wide helpers over G lanes: the whole wave (G = 64) or one of its
-// aligned halves (G = 32); shuffles stay inside the group.
-template <int G>
-__device__ __forceinline__ int group_incl_scan(int v, int gl) {
-#pragma unroll
-  for (int d = 1; d < G; d <<= 1) {
-    const int t = __shfl_up(v, d, G);
-    if (gl >= d) v += t;
-  }
+// aligned halves (G = 32); exchanges stay inside the group.
+// Inclusive scan with op by DPP: shifts by 1, 2, 4, 8 inside each 16-lane
+// row, then the last lane of row 0 (2) is added into row 1 (3), and for
+// G = 64 lane 31 into rows 2 and 3.  Lanes without a source receive ident.
+template <int G, class Op>
+__device__ __forceinline__ int group_scan(int v, int ident, Op op) {
+  static_assert(G == 32 || G == 64, "groups of 32 or 64 lanes");
+  v = op(v, __builtin_amdgcn_update_dpp(ident, v, 0x111, 0xF, 0xF, false));  // row_shr:1
+  v = op(v, __builtin_amdgcn_update_dpp(ident, v, 0x112, 0xF, 0xF, false));  // row_shr:2
+  v = op(v, __builtin_amdgcn_update_dpp(ident, v, 0x114, 0xF, 0xF, false));  // row_shr:4
+  v = op(v, __builtin_amdgcn_update_dpp(ident, v, 0x118, 0xF, 0xF, false));  // row_shr:8
+  v = op(v, __builtin_amdgcn_update_dpp(ident, v, 0x142, 0xA, 0xF, false));  // row_bcast:15
+  if constexpr (G == 64) v = op(v, __builtin_amdgcn_update_dpp(ident, v, 0x143, 0xC, 0xF, false));  // row_bcast:31
   return v;
+}
+
+// Value of the next lane (lane + 1; 0 in lane 63) by a DPP wave shift.
+template <typename T>
+__device__ __forceinline__ T lane_next(T v) {
+  if constexpr (sizeof(T) == 4) {
+    const int u = __builtin_bit_cast(int, v);
+    return __builtin_bit_cast(T, __builtin_amdgcn_update_dpp(0, u, 0x130, 0xF, 0xF, false));  // wave_shl:1
+  } else {
+    static_assert(sizeof(T) == 8, "32- or 64-bit values");
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, 0x130, 0xF, 0xF, false);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), 0x130, 0xF, 0xF, false);
+    return __builtin_bit_cast(T, ((uint64_t)hi << 32) | lo);
+  }
+}
+
+template <int G>
+__device__ __forceinline__ int group_incl_scan(int v, int) {
+  return group_scan<G>(v, 0, [](int x, int y) { return x + y; });
 }
 
 template <int G, typename K>
@@ -630,12 +655,7 @@ __device__ __forceinline__ void tiny_column(const Operand& A, const Operand& B, 
     wave_sync();
     if (al > 0 && excl < G) s_aux[excl] = gl;
     wave_sync();
-    int o = s_aux[gl];
-#pragma unroll
-    for (int d = 1; d < G; d <<= 1) {
-      const int u = __shfl_up(o, d, G);
-      if (gl >= d && u > o) o = u;
-    }
+    const int o = group_scan<G>(s_aux[gl], -1, [](int x, int y) { return x > y ? x : y; });
     const int src = o < 0 ? 0 : o;
     const int ostart = __shfl(excl, src, G);
     const int64_t ea0 = __shfl(qa0, src, G);
@@ -685,9 +705,16 @@ __device__ __forceinline__ void tiny_column(const Operand& A, const Operand& B, 
     if constexpr (kVal) {
       const T v = valid ? s_val[idx] : T(0);
       acc = v;
-      const int maxrun = wave_max(run);
+      int mr = run;  // longest run of the wave
+#pragma unroll
+      for (int j = 32; j > 0; j >>= 1) {
+        const int t = (int)xor_lane_u32((uint32_t)mr, j);
+        mr = t > mr ? t : mr;
+      }
+      const int maxrun = __builtin_amdgcn_readfirstlane(mr);
+      T x = v;  // after d steps: the value of lane gl + d (inside the group while d < run)
       for (int d = 1; d < maxrun; ++d) {
-        const T x = __shfl_down(v, (unsigned)d, G);
+        x = lane_next(x);
         if (d < run) acc = S::add(acc, x);
       }
     }
