@@ -649,7 +649,10 @@ __device__ __forceinline__ void tiny_column(const Operand& A, const Operand& B, 
     if constexpr (kVal && S::kUsesB) qb = inq ? bn[q] : T(0);
     const int incl = group_incl_scan<G>(al, gl);
     const int excl = incl - al;
-    const int ctot = __shfl(incl, G - 1, G);
+    // the group's total: its last lane, read as a scalar (lanes of an idle
+    // half may hold stale values, which only that half would read)
+    const int ctot = G == 64 ? __builtin_amdgcn_readlane(incl, 63)
+                             : (lane < 32 ? __builtin_amdgcn_readlane(incl, 31) : __builtin_amdgcn_readlane(incl, 63));
     if (ctot == 0) continue;
     s_aux[gl] = -1;
     wave_sync();
@@ -688,7 +691,8 @@ __device__ __forceinline__ void tiny_column(const Operand& A, const Operand& B, 
     row = (int32_t)(key >> 32);
     idx = (int)(key & 0xffffffffu);
   }
-  const int32_t prev = __shfl_up(row, 1, G);
+  // the previous lane's row (DPP wave shift; lane 0 of a group never uses it)
+  const int32_t prev = __builtin_amdgcn_update_dpp(0, row, 0x138, 0xF, 0xF, false);  // wave_shr:1
   const bool valid = gl < total;
   const bool head = valid && (gl == 0 || prev != row);
   const uint64_t gmask = G == 64 ? ~0ull : (0xffffffffull << gb);
