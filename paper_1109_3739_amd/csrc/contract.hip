@@ -65,9 +65,37 @@ __global__ void k_map_rows(const int32_t* ir, int64_t nnz, const int32_t* agg, i
     out[e] = agg[ir[e]];
 }
 
+// Runs of equal aggregate ids in a wave (consecutive vertices often share
+// an aggregate): a lane heads a run when its id differs from the lane
+// before it, and the head's atomic counts (or claims slots for) the whole
+// run.  The valid lanes of a wave (v < n) are a prefix of it.
+struct AggRun {
+  int32_t a;      // this lane's aggregate, -1 past the end
+  bool head;
+  int len;        // run length (heads)
+  int head_lane;  // the head of this lane's run (valid lanes)
+};
+__device__ __forceinline__ AggRun agg_run(const int32_t* agg, int64_t v, int64_t n) {
+  const int lane = lane_id();
+  AggRun R;
+  R.a = v < n ? agg[v] : -1;
+  const int32_t prev = __shfl_up(R.a, 1);
+  R.head = R.a >= 0 && (lane == 0 || prev != R.a);
+  const uint64_t hm = __ballot(R.head);
+  const int nvalid = __popcll(__ballot(R.a >= 0));
+  const uint64_t later = lane < 63 ? hm >> (lane + 1) : 0ull;
+  R.len = later ? __ffsll((long long)later) : nvalid - lane;
+  const uint64_t upto = hm & (lane == 63 ? ~0ull : ((2ull << lane) - 1ull));
+  R.head_lane = upto ? 63 - __clzll((long long)upto) : 0;
+  return R;
+}
+
 __global__ void k_count_agg(const int32_t* agg, int64_t n, int64_t* cnt) {
-  for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
-    atomicAdd(reinterpret_cast<unsigned long long*>(&cnt[agg[v]]), 1ull);
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t w = blockIdx.x * (int64_t)blockDim.x + threadIdx.x - lane_id(); w < n; w += stride) {
+    const AggRun R = agg_run(agg, w + lane_id(), n);
+    if (R.head) atomicAdd(reinterpret_cast<unsigned long long*>(&cnt[R.a]), (unsigned long long)R.len);
+  }
 }
 
 // Rows of S_c^T when col_agg is non-decreasing: vertex v sits at position v.
@@ -79,9 +107,14 @@ __global__ void k_iota(int32_t* out, int64_t n) {
 // Vertices into their aggregate's column of S_c^T (any order inside a column;
 // the column sort puts them in ascending order).
 __global__ void k_scatter_agg(const int32_t* agg, int64_t n, const int64_t* scp, unsigned* cur, int32_t* sir) {
-  for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
-    const int32_t a = agg[v];
-    sir[scp[a] + atomicAdd(&cur[a], 1u)] = (int32_t)v;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t w = blockIdx.x * (int64_t)blockDim.x + threadIdx.x - lane_id(); w < n; w += stride) {
+    const int64_t v = w + lane_id();
+    const AggRun R = agg_run(agg, v, n);
+    unsigned base = 0;
+    if (R.head) base = atomicAdd(&cur[R.a], (unsigned)R.len);
+    base = __shfl(base, R.head_lane);
+    if (R.a >= 0) sir[scp[R.a] + base + (unsigned)(lane_id() - R.head_lane)] = (int32_t)v;
   }
 }
 
