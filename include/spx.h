@@ -230,9 +230,10 @@ int spx_spgemm_sum_exec(spx_plan* plan, spx_mat* C);
  * asks for such a primitive).
  * Maps may be in any order; values must lie in [0, coarse dimension)
  * (SPX_EINVAL).  A non-decreasing row_agg keeps A's entry order; any other
- * row_agg makes the plan sort every column of A by mapped row (columns of
- * at most 4096 entries, SPX_EUNSUPPORTED otherwise; 12 more bytes per entry
- * of A) and every exec gather A's values in that order.  Semirings: PLUS_TIMES (sums, S entries 1) and MIN_PLUS
+ * row_agg makes the plan sort every column of A by mapped row (in
+ * registers or LDS up to 4096 entries, longer columns by one global sort
+ * each; 12 more bytes per entry of A) and every exec gather A's values in
+ * that order.  Semirings: PLUS_TIMES (sums, S entries 1) and MIN_PLUS
  * (minima, S entries 0) on A's value type; SELECT1ST (minimum of A's
  * values) and OR_AND (pattern) with any A.  The plan keeps A's pointers and
  * values (patterns must stay unchanged; values may change between execs)

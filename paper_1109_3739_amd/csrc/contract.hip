@@ -215,9 +215,11 @@ static int sort_cols_groups(const Operand& A, const int32_t* row_agg, int64_t ns
   return SPX_OK;
 }
 
+// Columns above kColSortMax entries are listed in `huge` (count *nhuge) for
+// one global sort each, or, without a list, flagged in err (bit 8).
 __global__ void __launch_bounds__(256) k_sort_cols_block(Operand A, const int32_t* row_agg, const int32_t* longs,
                                                          const unsigned long long* nlong, int32_t* ir_r, int64_t* perm,
-                                                         unsigned* err) {
+                                                         unsigned* err, int32_t* huge, unsigned long long* nhuge) {
   __shared__ uint64_t s[kColSortMax];
   const int64_t nl = (int64_t)*nlong;
   for (int64_t i = blockIdx.x; i < nl; i += gridDim.x) {
@@ -225,7 +227,12 @@ __global__ void __launch_bounds__(256) k_sort_cols_block(Operand A, const int32_
     const int64_t a0 = slot_begin(A, t), a1 = slot_begin(A, t + 1);
     const int len = (int)(a1 - a0);
     if (a1 - a0 > kColSortMax) {  // uniform
-      if (threadIdx.x == 0) atomicOr(err, 8u);
+      if (threadIdx.x == 0) {
+        if (huge)
+          huge[atomicAdd(nhuge, 1ull)] = t;
+        else
+          atomicOr(err, 8u);
+      }
       continue;
     }
     int p2 = 1;
@@ -259,6 +266,28 @@ __global__ void __launch_bounds__(256) k_sort_cols_block(Operand A, const int32_
       if (perm) perm[a0 + j] = a0 + (int64_t)(uint32_t)s[j];
     }
     __syncthreads();
+  }
+}
+
+// First position and length of each listed column.
+__global__ void k_col_extents(Operand A, const int32_t* cols, int64_t n, int64_t* ext) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t a0 = slot_begin(A, cols[i]);
+    ext[2 * i] = a0;
+    ext[2 * i + 1] = slot_begin(A, cols[i] + 1) - a0;
+  }
+}
+
+// (mapped row, position) keys of one column, and their sorted order written
+// back as the column's rows and value permutation.
+__global__ void k_col_keys(const int32_t* ir, int64_t a0, int64_t len, const int32_t* row_agg, uint64_t* keys) {
+  for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < len; j += (int64_t)gridDim.x * blockDim.x)
+    keys[j] = ((uint64_t)(uint32_t)row_agg[ir[a0 + j]] << 32) | (uint32_t)j;
+}
+__global__ void k_col_unkey(const uint64_t* keys, int64_t a0, int64_t len, int32_t* ir_r, int64_t* perm) {
+  for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < len; j += (int64_t)gridDim.x * blockDim.x) {
+    ir_r[a0 + j] = (int32_t)(keys[j] >> 32);
+    perm[a0 + j] = a0 + (int64_t)(uint32_t)keys[j];
   }
 }
 
@@ -343,20 +372,43 @@ extern "C" int spx_contract_plan(const spx_ctx* ctx, const spx_mat* A, const int
       const Operand Ao = make_operand(A);
       const int64_t ns = nslots_of(Ao);
       int32_t *mids = nullptr, *longs = nullptr;
-      unsigned long long* nl = nullptr;  // [0] columns above 8 entries, [1] above 64
+      unsigned long long* nl = nullptr;  // [0] columns above 8 entries, [1] above 64, [2] above 4096
       SPX_TRY(scr.get_n(std::max<int64_t>(A->nnz, 1), &P->aperm));
       SPX_TRY(scr.get_n(std::max<int64_t>(ns, 1), &mids));
       SPX_TRY(scr.get_n(std::max<int64_t>(ns, 1), &longs));
-      SPX_TRY(scr.get_n(2, &nl));
-      SPX_TRY(fill_i64(reinterpret_cast<int64_t*>(nl), 2, 0, st));
+      SPX_TRY(scr.get_n(3, &nl));
+      SPX_TRY(fill_i64(reinterpret_cast<int64_t*>(nl), 3, 0, st));
       SPX_TRY(sort_cols_groups(Ao, row_agg, ns, m_coarse, P->air, P->aperm, mids, longs, nl, st));
-      unsigned long long* nlong = nl + 1;
-      k_sort_cols_block<<<(unsigned)device_cu_count() * 4, 256, 0, st>>>(Ao, row_agg, longs, nlong, P->air, P->aperm,
-                                                                        err);
+      // columns above the LDS sort: listed in mids (free again once the
+      // 64-lane tier has run), then one global sort each
+      int32_t* huge = mids;
+      k_sort_cols_block<<<(unsigned)device_cu_count() * 4, 256, 0, st>>>(Ao, row_agg, longs, nl + 1, P->air, P->aperm,
+                                                                        err, huge, nl + 2);
       SPX_HIP(hipGetLastError());
-      SPX_HIP(hipMemcpyAsync(&err_h, err, 4, hipMemcpyDeviceToHost, st));
+      unsigned long long nhuge = 0;
+      SPX_HIP(hipMemcpyAsync(&nhuge, nl + 2, 8, hipMemcpyDeviceToHost, st));
       SPX_HIP(hipStreamSynchronize(st));
-      if (err_h & 8u) return fail(SPX_EUNSUPPORTED, "with an unsorted row_agg, columns of A may hold at most 4096 entries");
+      if (nhuge > 0) {
+        int64_t* ext = nullptr;
+        SPX_TRY(scr.get_n(2 * (int64_t)nhuge, &ext));
+        k_col_extents<<<grid_for((int64_t)nhuge, 256, 1024), 256, 0, st>>>(Ao, huge, (int64_t)nhuge, ext);
+        SPX_HIP(hipGetLastError());
+        std::vector<int64_t> ext_h(2 * nhuge);
+        SPX_HIP(hipMemcpyAsync(ext_h.data(), ext, ext_h.size() * 8, hipMemcpyDeviceToHost, st));
+        SPX_HIP(hipStreamSynchronize(st));
+        int64_t maxlen = 0;
+        for (size_t i = 0; i < nhuge; ++i) maxlen = std::max(maxlen, ext_h[2 * i + 1]);
+        uint64_t* keys = nullptr;
+        SPX_TRY(scr.get_n(sort_capacity(maxlen), &keys));
+        for (size_t i = 0; i < nhuge; ++i) {
+          const int64_t a0 = ext_h[2 * i], len = ext_h[2 * i + 1];
+          k_col_keys<<<grid_for(len, 256, 4096), 256, 0, st>>>(A->ir, a0, len, row_agg, keys);
+          SPX_HIP(hipGetLastError());
+          SPX_TRY(sort_u64(keys, len, st));
+          k_col_unkey<<<grid_for(len, 256, 4096), 256, 0, st>>>(keys, a0, len, P->air, P->aperm);
+          SPX_HIP(hipGetLastError());
+        }
+      }
       P->vb = value_size(A->val_t);
       P->nnz = A->nnz;
       P->src_num = A->num;
@@ -411,7 +463,7 @@ extern "C" int spx_contract_plan(const spx_ctx* ctx, const spx_mat* A, const int
       So.ir = P->sir;
       SPX_TRY(sort_cols_groups(So, nullptr, n_coarse, n, P->sir, nullptr, mids, longs, nl, st));
       k_sort_cols_block<<<(unsigned)device_cu_count() * 4, 256, 0, st>>>(So, nullptr, longs, nl + 1, P->sir, nullptr,
-                                                                        err);
+                                                                        err, nullptr, nullptr);
       SPX_HIP(hipGetLastError());
       SPX_HIP(hipMemcpyAsync(&err_h, err, 4, hipMemcpyDeviceToHost, st));
       SPX_HIP(hipStreamSynchronize(st));

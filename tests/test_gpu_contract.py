@@ -94,14 +94,24 @@ def test_unsorted_row_maps(spx):
     contract_check(spx, D, ragg, 70, np.arange(40) // 4, 10, exact=True)
 
 
+def test_unsorted_row_map_hub_columns(spx):
+    # columns above 4096 entries (hubs) take one global sort each under an
+    # unsorted row map; the others the group and workgroup sorts
+    rng = np.random.default_rng(96)
+    L = W.erdos_renyi(9000, 5, 6000, seed=2, values="edge_id")
+    contract_check(spx, L, np.arange(9000)[::-1], 9000, None, 0, exact=True)  # a reversal
+    agg = rng.integers(0, 300, size=9000)
+    contract_check(spx, L, agg, 300, np.array([0, 1, 0, 2, 1]), 3, exact=True)
+    H = W.rmat(16, 16, seed=97, values="f64")  # an R-MAT hub beside short columns
+    assert np.diff(H.cp).max() > 4096
+    hagg = rng.integers(0, 2000, size=H.m)
+    contract_check(spx, H, hagg, 2000, hagg, 2000, "min_plus", exact=True)
+    contract_check(spx, H, hagg, 2000, None, 0, a_dcsc=True)
+
+
 def test_contraction_errors(spx):
     import torch
     A = spx.from_host(W.erdos_renyi(20, 20, 3, seed=1))
-    L = spx.from_host(W.erdos_renyi(6000, 3, 5000, seed=2))  # a column above 4096 entries
-    down = torch.from_numpy(np.arange(6000, dtype=np.int32)[::-1].copy()).cuda()
-    with pytest.raises(spx.SpxError) as e:
-        spx.contract(L, down, 6000, None, 0)
-    assert e.value.code == spx.SPX_EUNSUPPORTED
     big = torch.full((20,), 7, dtype=torch.int32, device="cuda")
     with pytest.raises(spx.SpxError) as e:
         spx.contract(A, None, 0, big, 5)
