@@ -143,15 +143,33 @@ __device__ __forceinline__ T wave_max(T v) {
   return v;
 }
 
-// Inclusive prefix sum over the 64 lanes.
+// Value moved by the DPP control CTRL with rows outside ROW_MASK (and lanes
+// without a source) reading 0.  32- or 64-bit integers.
+template <int CTRL, int ROW_MASK, typename T>
+__device__ __forceinline__ T dpp_move(T v) {
+  if constexpr (sizeof(T) == 4) {
+    return (T)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROW_MASK, 0xF, false);
+  } else {
+    static_assert(sizeof(T) == 8, "32- or 64-bit integers");
+    const uint64_t u = (uint64_t)v;
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, CTRL, ROW_MASK, 0xF, false);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), CTRL, ROW_MASK, 0xF, false);
+    return (T)(((uint64_t)hi << 32) | lo);
+  }
+}
+
+// Inclusive prefix sum over the 64 lanes (all active): shifts by 1, 2, 4, 8
+// inside each 16-lane row, then the last lane of rows 0 and 2 is added into
+// rows 1 and 3, and lane 31 into rows 2 and 3.
 template <typename T>
 __device__ __forceinline__ T wave_incl_scan(T v) {
-  const int lane = lane_id();
-#pragma unroll
-  for (int o = 1; o < kWave; o <<= 1) {
-    T t = __shfl_up(v, o);
-    if (lane >= o) v += t;
-  }
+  static_assert(__is_integral(T), "integer scans");
+  v += dpp_move<0x111, 0xF>(v);  // row_shr:1
+  v += dpp_move<0x112, 0xF>(v);  // row_shr:2
+  v += dpp_move<0x114, 0xF>(v);  // row_shr:4
+  v += dpp_move<0x118, 0xF>(v);  // row_shr:8
+  v += dpp_move<0x142, 0xA>(v);  // row_bcast:15
+  v += dpp_move<0x143, 0xC>(v);  // row_bcast:31
   return v;
 }
 
