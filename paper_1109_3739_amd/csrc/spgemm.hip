@@ -873,11 +873,24 @@ __global__ void k_count_bitmap(Operand B, ProdSrc S, const int64_t* mults, const
     }));
     __syncthreads();
     int64_t mine = 0;
-    for (int i = threadIdx.x; i < words; i += blockDim.x) {
-      const int pc = __popc(bm[i]);
-      if (pc) {
+    if (rbshift >= 11) {
+      // a wave's 64 words (2048 rows, 64-aligned) lie in one row block:
+      // one LDS add per wave instead of one per nonzero word at one address
+      const int lane = lane_id();
+      for (int w = (int)threadIdx.x - lane; w < words; w += blockDim.x) {
+        const int i = w + lane;
+        const int pc = i < words ? __popc(bm[i]) : 0;
         mine += pc;
-        atomicAdd(&lblk[((int64_t)i * 32) >> rbshift], (uint32_t)pc);
+        const int s = __builtin_amdgcn_readlane(wave_incl_scan(pc), 63);
+        if (lane == 0 && s) atomicAdd(&lblk[((int64_t)w * 32) >> rbshift], (uint32_t)s);
+      }
+    } else {
+      for (int i = threadIdx.x; i < words; i += blockDim.x) {
+        const int pc = __popc(bm[i]);
+        if (pc) {
+          mine += pc;
+          atomicAdd(&lblk[((int64_t)i * 32) >> rbshift], (uint32_t)pc);
+        }
       }
     }
     int64_t ctot;
