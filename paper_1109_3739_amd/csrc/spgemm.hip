@@ -839,7 +839,7 @@ __global__ void k_count_hash(Operand B, ProdSrc S, const int64_t* mults,
 // column count and the per-row-block counts used to cut parts.
 __global__ void k_count_bitmap(Operand B, ProdSrc S, const int64_t* mults, const int32_t* list, const int64_t* binoff,
                                int64_t m, int chunk_log2, int rbshift, int64_t nblk, uint32_t* blkcnt,
-                               unsigned long long* cnt, uint32_t* gbm, int64_t gwords) {
+                               unsigned long long* cnt, uint32_t* gbm, int64_t gwords, unsigned long long* qctr) {
   extern __shared__ __align__(16) unsigned char lds[];
   uint32_t* bm = (uint32_t*)lds;
   const int64_t chunk_rows = 1ll << chunk_log2;  // a multiple of the row block
@@ -850,12 +850,18 @@ __global__ void k_count_bitmap(Operand B, ProdSrc S, const int64_t* mults, const
   __shared__ RangeLds s_rng;
   const int64_t beg = binoff[0], end = binoff[kBinHash0];
   const int64_t ncols = end - beg;
-  // workgroup w takes chunk w mod nchunks of every (gridDim/nchunks)-th
-  // column (the grid is a multiple of nchunks): workgroups are placed on the
-  // XCDs round robin, so each XCD's L2 serves one slice of A's rows
-  const int64_t wstride = gridDim.x / nchunks;
+  // workgroup w works on row chunk w mod nchunks (the grid is a multiple of
+  // nchunks): workgroups are placed on the XCDs round robin, so each XCD's L2
+  // serves one slice of A's rows.  The chunk's columns are handed out one at
+  // a time by its counter qctr[chunk] (zero at launch), in list order, which
+  // puts the heaviest columns first.
   const int64_t chunk = blockIdx.x % nchunks;
-  for (int64_t ci = blockIdx.x / nchunks; ci < ncols; ci += wstride) {
+  __shared__ int64_t s_ci;
+  for (;;) {
+    if (threadIdx.x == 0) s_ci = (int64_t)atomicAdd(&qctr[chunk], 1ull);
+    __syncthreads();
+    const int64_t ci = s_ci;
+    if (ci >= ncols) break;
     const int64_t pos = beg + ci;
     const int64_t c0 = chunk * chunk_rows;
     const int64_t c1 = c0 + chunk_rows < m ? c0 + chunk_rows : m;
@@ -2007,6 +2013,9 @@ extern "C" int spx_spgemm_plan(const spx_ctx* ctx, const spx_mat* A, const spx_m
     const int per_cu = std::max<int>(1, std::min<int>((int)((160 * 1024) / (lds + 8192)), 2048 / tune.bitmap_threads));
     int64_t bgrid = std::min<int64_t>(nbitmap * nchunks, (int64_t)cus * per_cu);
     bgrid = std::max<int64_t>(nchunks, bgrid / nchunks * nchunks);
+    unsigned long long* bqctr = nullptr;  // per-chunk column counters
+    SPX_TRY(scr.get_n(nchunks, &bqctr));
+    SPX_TRY(fill_i64((int64_t*)bqctr, nchunks, 0, st));
     // keep the bitmaps for the numeric phase when they fit the cap
     const int64_t words = ceil_div(m, 64);
     if (tune.bitmap_store_mb > 0 && (double)nbitmap * words * 8.0 <= (double)tune.bitmap_store_mb * 1048576.0) {
@@ -2017,7 +2026,7 @@ extern "C" int spx_spgemm_plan(const spx_ctx* ctx, const spx_mat* A, const spx_m
     }
     k_count_bitmap<<<(unsigned)bgrid, tune.bitmap_threads, lds, st>>>(
         P->B, P->src, P->mults_d, P->list, P->binoff, m, clog, rb, nblk, blkcnt, (unsigned long long*)P->cnt,
-        (uint32_t*)P->gbm, 2 * P->gbm_words);
+        (uint32_t*)P->gbm, 2 * P->gbm_words, bqctr);
     SPX_HIP(hipGetLastError());
   }
   // column pointers and nonempty-column offsets
