@@ -79,6 +79,7 @@ def test_rmat_semirings(spx, semiring, values, exact):
     dict(tiny_max=0, hash_count_max=0),                   # everything through the bitmap count
     dict(tiny_max=64, hash_count_max=16384),              # no bitmap count
     dict(part_lds_bytes=24 * 1024),                       # many parts, both part modes
+    dict(part_lds_bytes=12 * 1024),                       # row blocks of 1024 (f64) / 2048 (f32) rows
     dict(part_lds_bytes=48 * 1024, part_threads=256, count_threads=64, single_part_max=256),
     dict(tiny_max=16, hash_count_max=256, part_lds_bytes=64 * 1024, part_threads=512, single_part_max=64,
          single_threads=64, bitmap_threads=256),
@@ -128,6 +129,7 @@ def test_rectangular_and_independent(spx):
     dict(tiny_max=0, hash_count_max=0),                            # every column bitmap-counted and stored
     dict(tiny_max=0, hash_count_max=0, bitmap_chunk_log2=10),      # chunks end inside the last word
     dict(tiny_max=0, hash_count_max=0, part_lds_bytes=24 * 1024),  # many parts per stored column
+    dict(tiny_max=0, hash_count_max=0, part_lds_bytes=12 * 1024),  # row blocks shorter than a wave's words
 ])
 def test_stored_bitmaps_ragged_rows(spx, tune):
     # m is not a multiple of 64 (nor of a chunk): the stored bitmaps' last word
