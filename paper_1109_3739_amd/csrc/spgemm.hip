@@ -869,7 +869,11 @@ __global__ void k_count_bitmap(Operand B, ProdSrc S, const int64_t* mults, const
     const int64_t b0 = slot_begin(B, t), b1 = slot_begin(B, t + 1);
     uint32_t* dst = blkcnt + (pos - beg) * nblk;
     const int words = (int)((c1 - c0 + 31) >> 5);
-    for (int i = threadIdx.x; i < words; i += blockDim.x) bm[i] = 0;
+    {  // 16-byte LDS stores (the LDS base is 16-byte aligned), then the ragged end
+      const int w4 = words >> 2;
+      for (int i = threadIdx.x; i < w4; i += blockDim.x) reinterpret_cast<uint4*>(bm)[i] = make_uint4(0u, 0u, 0u, 0u);
+      for (int i = (w4 << 2) + (int)threadIdx.x; i < words; i += blockDim.x) bm[i] = 0;
+    }
     for (int i = threadIdx.x; i < blk_per_chunk; i += blockDim.x) lblk[i] = 0;
     __syncthreads();
     block_products<4, int, false, false, false, true>(S, nullptr, nullptr, b0, b1, (int32_t)c0, (int32_t)c1, nchunks == 1, s_rng,
@@ -906,9 +910,14 @@ __global__ void k_count_bitmap(Operand B, ProdSrc S, const int64_t* mults, const
       if (bfirst + i < nblk) dst[bfirst + i] = lblk[i];
     if (threadIdx.x == 0 && ctot) atomicAdd(&cnt[t], (unsigned long long)ctot);
     if (gbm) {  // keep the column's row set for the numeric phase
-      uint32_t* g = gbm + ci * gwords + (c0 >> 5);
-      const int wr = (words + 1) & ~1;  // whole 64-bit words
-      for (int i = threadIdx.x; i < wr; i += blockDim.x) g[i] = i < words ? bm[i] : 0u;
+      // whole 64-bit words (gwords is even and c0 a multiple of 64 rows, so g
+      // is 8-byte aligned); a ragged chunk's last word is padded with zeros
+      uint2* g = reinterpret_cast<uint2*>(gbm + ci * gwords + (c0 >> 5));
+      const int w2 = (words + 1) >> 1;
+      for (int i = threadIdx.x; i < w2; i += blockDim.x) {
+        const int k = 2 * i;
+        g[i] = make_uint2(bm[k], k + 1 < words ? bm[k + 1] : 0u);
+      }
     }
     __syncthreads();
   }
