@@ -295,8 +295,18 @@ struct ProdSrc {
   int32_t sstride;
   int32_t rbshift;
   int32_t m;
-  int32_t pad;
+  int32_t off32;  // 1: positions in A fit 29 bits, loads take 32-bit byte offsets
 };
+
+// A's row and value at position o through a 32-bit byte offset from the base
+// (valid when o < 2^29, so o * 8 does not wrap).
+__device__ __forceinline__ int32_t load_row32(const int32_t* air, uint32_t o) {
+  return *reinterpret_cast<const int32_t*>(reinterpret_cast<const char*>(air) + (o << 2));
+}
+template <typename T>
+__device__ __forceinline__ T load_val32(const T* an, uint32_t o) {
+  return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(an) + o * (uint32_t)sizeof(T));
+}
 
 
 // Block-cooperative iteration over the products of one output column.
@@ -366,7 +376,11 @@ __device__ __forceinline__ EachProduct<U, F> each_product(F f) {
 //    the next window's first product.
 // With REUSE the range list left in R by the previous call for the same
 // column and row range is used as is (the column must fit one chunk).
-template <int U, typename T, bool LOADA, bool LOADB, bool REUSE = false, bool WAVE_RUNS = false, int QC, class F>
+// Row-only passes (LOADA false) load through 32-bit byte offsets when
+// S.off32 is set; value passes do so only with VAL32 (a separate kernel
+// instantiation, so that the 64-bit path's registers are not held too).
+template <int U, typename T, bool LOADA, bool LOADB, bool REUSE = false, bool WAVE_RUNS = false, bool VAL32 = false,
+          int QC, class F>
 __device__ __forceinline__ void block_products(const ProdSrc& S, const T* an, const T* bn, int64_t b0, int64_t b1,
                                                int32_t r0, int32_t r1, bool full, RangeLdsT<QC>& R, int64_t* red,
                                                const int32_t* qidx, F&& f) {
@@ -442,11 +456,21 @@ __device__ __forceinline__ void block_products(const ProdSrc& S, const T* an, co
             const T b1 = LOADB ? reinterpret_cast<const T*>(&R.bval[s0])[0] : T(0);
             int32_t r[U];
             T a[U], bv[U];
+            if (VAL32 || (!LOADA && S.off32)) {  // VAL32: the caller's A fits 29-bit positions
+              const uint32_t eb32 = (uint32_t)eb;
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-              r[u] = S.air[eb + u * kWave];
-              a[u] = LOADA ? an[eb + u * kWave] : T(0);
-              bv[u] = b1;
+              for (int u = 0; u < U; ++u) {
+                r[u] = load_row32(S.air, eb32 + (uint32_t)(u * kWave));
+                a[u] = LOADA ? load_val32(an, eb32 + (uint32_t)(u * kWave)) : T(0);
+                bv[u] = b1;
+              }
+            } else {
+#pragma unroll
+              for (int u = 0; u < U; ++u) {
+                r[u] = S.air[eb + u * kWave];
+                a[u] = LOADA ? an[eb + u * kWave] : T(0);
+                bv[u] = b1;
+              }
             }
             if (fl1) {
 #pragma unroll
@@ -519,26 +543,41 @@ __device__ __forceinline__ void block_products(const ProdSrc& S, const T* an, co
         if (pp >= total) p[u] = -1;
       }
       // phase 3: range data; phase 4: A's row and value
-      int64_t e[U];
+      int64_t st[U];
+      int32_t d[U];
       int32_t r[U];
       T a[U], bv[U];
       bool fl[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        const int64_t st = R.start[lo[u]];
+        st[u] = R.start[lo[u]];
         const int32_t pf = R.pref[lo[u]];
-        fl[u] = (st & kFilter) != 0;
-        e[u] = (st & (kFilter - 1)) + ((p[u] < 0 ? total - 1 : p[u]) - pf);
+        fl[u] = (st[u] & kFilter) != 0;
+        d[u] = (p[u] < 0 ? total - 1 : p[u]) - pf;
         bv[u] = LOADB ? reinterpret_cast<const T*>(&R.bval[lo[u]])[0] : T(0);
       }
+      if (VAL32 || (!LOADA && S.off32)) {
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        r[u] = -1;
-        a[u] = T(0);
-        // windows wholly past the end load nothing (wave-uniform test)
-        if ((WAVE_RUNS ? pw + u * kWave : base + (u * nwin + wid) * kWave) < total) {
-          r[u] = S.air[e[u]];
-          if constexpr (LOADA) a[u] = an[e[u]];
+        for (int u = 0; u < U; ++u) {
+          r[u] = -1;
+          a[u] = T(0);
+          // windows wholly past the end load nothing (wave-uniform test)
+          if ((WAVE_RUNS ? pw + u * kWave : base + (u * nwin + wid) * kWave) < total) {
+            const uint32_t o = (uint32_t)st[u] + (uint32_t)d[u];  // the flag is above bit 31
+            r[u] = load_row32(S.air, o);
+            if constexpr (LOADA) a[u] = load_val32(an, o);
+          }
+        }
+      } else {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          r[u] = -1;
+          a[u] = T(0);
+          if ((WAVE_RUNS ? pw + u * kWave : base + (u * nwin + wid) * kWave) < total) {
+            const int64_t e = (st[u] & (kFilter - 1)) + d[u];
+            r[u] = S.air[e];
+            if constexpr (LOADA) a[u] = an[e];
+          }
         }
       }
 #pragma unroll
@@ -1245,7 +1284,7 @@ __device__ __forceinline__ void block_bitonic_sort(uint64_t* a, int n2) {
 // popcount prefix gives each row its rank = output position, accumulate
 // values by rank, write rows and values in order.  Hash mode: accumulate
 // into an open-addressing table, then sort (row, slot) keys.
-template <int SR, typename T, int QC>
+template <int SR, typename T, int QC, bool OFF32>
 __global__ void __launch_bounds__(1024) k_numeric_parts(Operand A, Operand B, ProdSrc S,
                                                         const int64_t* mults,
                                                         const int64_t* cnt, const Part* parts, const int64_t* qoff,
@@ -1332,7 +1371,7 @@ __global__ void __launch_bounds__(1024) k_numeric_parts(Operand A, Operand B, Pr
         for (int i = threadIdx.x; i < c; i += blockDim.x) vals[i] = SR_::ident();
       __syncthreads();
       if (!stored) {
-        block_products<8, T, false, SR_::kUsesB, false, true>(S, an, bn, b0, b1, P.r0, P.r1, full, s_rng, red, qx,
+        block_products<8, T, false, SR_::kUsesB, false, true, OFF32>(S, an, bn, b0, b1, P.r0, P.r1, full, s_rng, red, qx,
                                                   each_product<8>([&](int32_t r, T, T) {
           const uint32_t d = (uint32_t)(r - P.r0);
           atomicOr((unsigned long long*)&bm[d >> 6], 1ull << (d & 63));
@@ -1373,9 +1412,9 @@ __global__ void __launch_bounds__(1024) k_numeric_parts(Operand A, Operand B, Pr
           }
         };
         if (!stored && b1 - b0 <= (int64_t)(blockDim.x < QC ? blockDim.x : QC))
-          block_products<8, T, SR_::kUsesA, SR_::kUsesB, true, true>(S, an, bn, b0, b1, P.r0, P.r1, full, s_rng, red, qx, acc);
+          block_products<8, T, SR_::kUsesA, SR_::kUsesB, true, true, OFF32>(S, an, bn, b0, b1, P.r0, P.r1, full, s_rng, red, qx, acc);
         else
-          block_products<8, T, SR_::kUsesA, SR_::kUsesB, false, true>(S, an, bn, b0, b1, P.r0, P.r1, full, s_rng, red, qx, acc);
+          block_products<8, T, SR_::kUsesA, SR_::kUsesB, false, true, OFF32>(S, an, bn, b0, b1, P.r0, P.r1, full, s_rng, red, qx, acc);
         __syncthreads();
         for (int i = threadIdx.x; i < c; i += blockDim.x) cnum[P.off + i] = vals[i];
         __syncthreads();
@@ -1424,7 +1463,7 @@ __global__ void __launch_bounds__(1024) k_numeric_parts(Operand A, Operand B, Pr
       }
       if (threadIdx.x == 0) s_ctr = 0;
       __syncthreads();
-      block_products<4, T, SR_::kUsesA, SR_::kUsesB>(S, an, bn, b0, b1, P.r0, P.r1, full, s_rng, red, qx,
+      block_products<4, T, SR_::kUsesA, SR_::kUsesB, false, false, OFF32>(S, an, bn, b0, b1, P.r0, P.r1, full, s_rng, red, qx,
                                                      each_product<4>([&](int32_t r, T a, T bv) {
         if (r < 0) return;
         uint32_t h = hash_row(r, log2s);
@@ -1781,11 +1820,15 @@ static int launch_numeric(GemmPlan* P, spx_mat* C, hipStream_t st) {
     const int nq = r == 0 ? P->nq_multi : 1;
     unsigned long long* qctr = r == 0 ? P->qctr : P->qctr + P->nq_multi;
     if (r == 0 && P->wide)
-      hipLaunchKernelGGL((k_numeric_parts<SR, T, kQChunkWide>), dim3((unsigned)grid), dim3(blk), (size_t)L, st, P->A,
-                         P->B, P->src, P->mults_d, P->cnt, P->parts, qoff, nq, P->nslice, qctr, P->gbm,
+      hipLaunchKernelGGL((k_numeric_parts<SR, T, kQChunkWide, false>), dim3((unsigned)grid), dim3(blk), (size_t)L, st,
+                         P->A, P->B, P->src, P->mults_d, P->cnt, P->parts, qoff, nq, P->nslice, qctr, P->gbm,
+                         P->gbm_words, P->qlist, cir, cnum, err);
+    else if (P->src.off32)  // A's positions fit 29 bits: gathers through 32-bit offsets
+      hipLaunchKernelGGL((k_numeric_parts<SR, T, kQChunk, true>), dim3((unsigned)grid), dim3(blk), (size_t)L, st, P->A,
+                         P->B, P->src, P->mults_d, P->cnt, P->parts, qoff, nq, r == 0 ? P->nslice : 1, qctr, P->gbm,
                          P->gbm_words, P->qlist, cir, cnum, err);
     else
-      hipLaunchKernelGGL((k_numeric_parts<SR, T, kQChunk>), dim3((unsigned)grid), dim3(blk), (size_t)L, st, P->A,
+      hipLaunchKernelGGL((k_numeric_parts<SR, T, kQChunk, false>), dim3((unsigned)grid), dim3(blk), (size_t)L, st, P->A,
                          P->B, P->src, P->mults_d, P->cnt, P->parts, qoff, nq, r == 0 ? P->nslice : 1, qctr, P->gbm,
                          P->gbm_words, P->qlist, cir, cnum, err);
     SPX_HIP(hipGetLastError());
@@ -1946,7 +1989,8 @@ extern "C" int spx_spgemm_plan(const spx_ctx* ctx, const spx_mat* A, const spx_m
                                                                          P->bq_alen, P->bq_split, err);
     SPX_HIP(hipGetLastError());
   }
-  P->src = ProdSrc{A->ir, P->bq_a0, P->bq_alen, P->bq_split, P->splits, sstride, rb, (int32_t)m, 0};
+  P->src = ProdSrc{A->ir, P->bq_a0, P->bq_alen, P->bq_split, P->splits, sstride, rb, (int32_t)m,
+                   A->nnz < (1ll << 29) ? 1 : 0};
   BinCfg bc{tune.tiny_max, tune.hash_count_max};
   if (nslots > 0) {
     int32_t* longs = nullptr;
