@@ -131,7 +131,11 @@ typedef struct spx_ctx {
  *                    by the plan, one entry per B entry and part reached);
  *                    -1: parts walk all of their column's B entries; 0: lists
  *                    when range set-ups would outnumber multiplications 3 to
- *                    2 (a very tall-skinny B).                               */
+ *                    2 (a very tall-skinny B).
+ *   force_off64      1: gather A's rows and values through 64-bit positions
+ *                    even when A has fewer than 2^29 entries (the path that
+ *                    larger operands take); 0: 32-bit byte offsets when they
+ *                    fit.                                                    */
 typedef struct spx_tuning {
   int32_t tiny_max;
   int32_t hash_count_max;
@@ -146,7 +150,7 @@ typedef struct spx_tuning {
   int32_t bitmap_store_mb;
   int32_t range_chunk;
   int32_t bucket_parts;
-  int32_t reserved;
+  int32_t force_off64;
 } spx_tuning;
 
 /* Statistics of a SpGEMM plan, available once the plan call returned. */

@@ -41,6 +41,7 @@
 #include <cstdint>
 #include <cstring>
 #include <vector>
+#include <type_traits>
 #include <omp.h>
 
 namespace {
@@ -194,6 +195,80 @@ void extend_add_typed(int64_t m, int64_t n, const int64_t* acp, const int32_t* a
   }
 }
 
+// ---- Checking a computed product column by column -------------------------
+// Recomputes columns [j0, j1) of C = A*B with the SPA of Algorithm 1 (the
+// same spa_column as oracle_spgemm) and compares them with a given block of
+// columns: gcp[0 .. j1-j0] are its column pointers (gcp[0] is the position of
+// column j0 in gir / gnum), gir its rows, gnum its values (NULL: pattern).
+// A column matches when its row list is identical and every value matches:
+// bitwise when rtol <= 0 or for integers; otherwise |g - r| <= rtol * |r| and,
+// where the oracle's value is a zero, the same zero (sign included).
+// Returns the number of columns that differ; *first_bad receives the
+// smallest such column (or -1).
+template <typename T>
+bool value_matches(T g, T r, double rtol) {
+  if constexpr (std::is_floating_point<T>::value) {
+    if (rtol > 0 && r != T(0)) {
+      const double d = (double)g - (double)r;
+      const double lim = rtol * ((double)r < 0 ? -(double)r : (double)r);
+      return (d < 0 ? -d : d) <= lim;  // false for NaN
+    }
+  }
+  return std::memcmp(&g, &r, sizeof(T)) == 0;
+}
+
+template <typename T, typename Op>
+int64_t check_run(int64_t m, const int64_t* acp, const int32_t* air, const T* anum, const int64_t* bcp,
+                  const int32_t* bir, const T* bnum, int64_t j0, int64_t j1, const int64_t* gcp, const int32_t* gir,
+                  const T* gnum, double rtol, int64_t* first_bad, int nthreads) {
+  int64_t nbad = 0, first = -1;
+#pragma omp parallel num_threads(nthreads) reduction(+ : nbad)
+  {
+    std::vector<T> val((size_t)m);
+    std::vector<char> occ((size_t)m, 0);
+    std::vector<int32_t> list, rir;
+    std::vector<T> rnum;
+    int64_t my_first = -1;
+#pragma omp for schedule(dynamic, 16)
+    for (int64_t j = j0; j < j1; ++j) {
+      const int64_t len = gcp[j - j0 + 1] - gcp[j - j0];
+      const int64_t at = gcp[j - j0] - gcp[0];
+      rir.resize((size_t)m > 0 ? (size_t)m : 1);
+      rnum.resize(gnum ? rir.size() : 0);
+      const int64_t c = spa_column<T, Op>(j, acp, air, anum, bcp, bir, bnum, val, occ, list, rir.data(),
+                                          gnum ? rnum.data() : nullptr);
+      bool ok = c == len;
+      for (int64_t t = 0; ok && t < c; ++t) ok = gir[at + t] == rir[t];
+      for (int64_t t = 0; ok && gnum && t < c; ++t) ok = value_matches<T>(gnum[at + t], rnum[t], rtol);
+      if (!ok) {
+        ++nbad;
+        if (my_first < 0 || j < my_first) my_first = j;
+      }
+    }
+#pragma omp critical
+    if (my_first >= 0 && (first < 0 || my_first < first)) first = my_first;
+  }
+  if (first_bad) *first_bad = first;
+  return nbad;
+}
+
+template <typename T>
+int64_t check_typed(int sr, int64_t m, const int64_t* acp, const int32_t* air, const void* anum,
+                    const int64_t* bcp, const int32_t* bir, const void* bnum, int64_t j0, int64_t j1,
+                    const int64_t* gcp, const int32_t* gir, const void* gnum, double rtol, int64_t* first_bad,
+                    int nthreads) {
+  const T* a = (const T*)anum;
+  const T* b = (const T*)bnum;
+  const T* g = (const T*)gnum;
+  switch (sr) {
+    case PLUS_TIMES: return check_run<T, PlusTimes<T>>(m, acp, air, a, bcp, bir, b, j0, j1, gcp, gir, g, rtol, first_bad, nthreads);
+    case MIN_PLUS: return check_run<T, MinPlus<T>>(m, acp, air, a, bcp, bir, b, j0, j1, gcp, gir, g, rtol, first_bad, nthreads);
+    case SELECT2ND: return check_run<T, Select2nd<T>>(m, acp, air, a, bcp, bir, b, j0, j1, gcp, gir, g, rtol, first_bad, nthreads);
+    case SELECT1ST: return check_run<T, Select1st<T>>(m, acp, air, a, bcp, bir, b, j0, j1, gcp, gir, g, rtol, first_bad, nthreads);
+    default: return -1;
+  }
+}
+
 }  // namespace
 
 extern "C" {
@@ -221,6 +296,25 @@ int oracle_spgemm(int sr, int vt, int64_t m, const int64_t* acp, const int32_t* 
     case F32: return spgemm_typed<float>(sr, m, acp, air, anum, bcp, bir, bnum, ncols, cols, counts, offs, cir, cnum, nthreads);
     case F64: return spgemm_typed<double>(sr, m, acp, air, anum, bcp, bir, bnum, ncols, cols, counts, offs, cir, cnum, nthreads);
     case I64: return spgemm_typed<int64_t>(sr, m, acp, air, anum, bcp, bir, bnum, ncols, cols, counts, offs, cir, cnum, nthreads);
+    default: return -1;
+  }
+}
+
+// Compares columns [j0, j1) of a computed C = A*B with the oracle's (see
+// check_run).  Same operand conventions as oracle_spgemm.  Returns the number
+// of differing columns, or -1 for an unsupported semiring / type.
+int64_t oracle_spgemm_check(int sr, int vt, int64_t m, const int64_t* acp, const int32_t* air, const void* anum,
+                            const int64_t* bcp, const int32_t* bir, const void* bnum, int64_t j0, int64_t j1,
+                            const int64_t* gcp, const int32_t* gir, const void* gnum, double rtol,
+                            int64_t* first_bad, int nthreads) {
+  if (nthreads < 1) nthreads = 1;
+  if (sr == OR_AND || vt == BOOL)
+    return check_typed<double>(PLUS_TIMES, m, acp, air, nullptr, bcp, bir, nullptr, j0, j1, gcp, gir, nullptr, 0.0,
+                               first_bad, nthreads);
+  switch (vt) {
+    case F32: return check_typed<float>(sr, m, acp, air, anum, bcp, bir, bnum, j0, j1, gcp, gir, gnum, rtol, first_bad, nthreads);
+    case F64: return check_typed<double>(sr, m, acp, air, anum, bcp, bir, bnum, j0, j1, gcp, gir, gnum, rtol, first_bad, nthreads);
+    case I64: return check_typed<int64_t>(sr, m, acp, air, anum, bcp, bir, bnum, j0, j1, gcp, gir, gnum, 0.0, first_bad, nthreads);
     default: return -1;
   }
 }

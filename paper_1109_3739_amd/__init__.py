@@ -67,7 +67,7 @@ class spx_ctx(ctypes.Structure):
 class spx_tuning(ctypes.Structure):
     _fields_ = [(k, ctypes.c_int32) for k in (
         "tiny_max", "hash_count_max", "single_part_max", "part_lds_bytes", "count_threads", "bitmap_threads",
-        "part_threads", "single_threads", "bitmap_chunk_log2", "xcd_slices", "bitmap_store_mb", "range_chunk", "bucket_parts", "reserved")]
+        "part_threads", "single_threads", "bitmap_chunk_log2", "xcd_slices", "bitmap_store_mb", "range_chunk", "bucket_parts", "force_off64")]
 
 
 class spx_plan_info(ctypes.Structure):

@@ -271,6 +271,12 @@ __device__ __forceinline__ T block_excl_scan1(T v, T* red, T* total) {
 // ---------------------------------------------------------------- semirings
 // mul: product of A(i,k) and B(k,j); add: combine into an accumulator;
 // lds_acc: atomic combine into LDS; ident: value of an untouched slot.
+// ident is the exact neutral element of add, so that a slot started from it
+// and combined with the products ends where a fold started from the first
+// product ends (Algorithm 1 starts each accumulator from its first product).
+// For floating-point (+,x) that is -0.0, not +0.0: -0 + x = x for every x,
+// including x = -0, whereas +0 + (-0) = +0 would lose the sign of a sum of
+// negative zeros.
 template <int SR, typename T>
 struct Semiring;
 
@@ -279,7 +285,7 @@ struct Semiring<SPX_PLUS_TIMES, T> {
   static constexpr bool kUsesA = true, kUsesB = true;
   __device__ static T mul(T a, T b) { return a * b; }
   __device__ static T add(T acc, T x) { return acc + x; }
-  __device__ static T ident() { return T(0); }
+  __device__ static T ident() { return -T(0); }
   __device__ static void lds_acc(T* p, T x) {
     __hip_atomic_fetch_add(p, x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
   }

@@ -1990,7 +1990,7 @@ extern "C" int spx_spgemm_plan(const spx_ctx* ctx, const spx_mat* A, const spx_m
     SPX_HIP(hipGetLastError());
   }
   P->src = ProdSrc{A->ir, P->bq_a0, P->bq_alen, P->bq_split, P->splits, sstride, rb, (int32_t)m,
-                   A->nnz < (1ll << 29) ? 1 : 0};
+                   (A->nnz < (1ll << 29) && !tune.force_off64) ? 1 : 0};
   BinCfg bc{tune.tiny_max, tune.hash_count_max};
   if (nslots > 0) {
     int32_t* longs = nullptr;

@@ -26,9 +26,14 @@ def assert_values(got, ref, exact, what=""):
     rtol = RTOL[ref.dtype]
     err = np.abs(got.astype(np.float64) - ref.astype(np.float64))
     lim = rtol * np.abs(ref.astype(np.float64))
-    bad = np.nonzero(err > lim)[0]
+    bad = np.nonzero(~(err <= lim))[0]  # NaN fails
     assert bad.size == 0, (f"{what}: {bad.size} values outside rtol {rtol}; first {bad[:5]}: "
                            f"{got[bad[:5]]} vs {ref[bad[:5]]}")
+    # a zero must be the oracle's zero, sign included (Algorithm 1 starts each
+    # sum from its first product, so products of -0.0 alone sum to -0.0)
+    zs = np.nonzero(ref == 0)[0]
+    badz = zs[np.signbit(got[zs]) != np.signbit(ref[zs])]
+    assert badz.size == 0, f"{what}: {badz.size} zeros with the wrong sign, first at {badz[:5]}"
 
 
 def columns_of(cp, ir, num, cols):

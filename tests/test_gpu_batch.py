@@ -98,6 +98,51 @@ def test_batched_galerkin_closed_form(spx, dtype):
     G.close()
 
 
+def closed_form_all(spx, sizes, Gs, dtype):
+    """Every coarse operator against 4 x the coarse Laplacian, compared on the
+    device (small integers: exact in any order); returns the failing ids."""
+    import torch
+    ref = {}
+    for n in sorted(set(int(x) for x in sizes)):
+        r = W.laplacian7(n // 2, dtype)
+        ref[n] = spx.from_host(r.with_values(4 * r.num))
+    bad = []
+    for i, (n, C) in enumerate(zip(sizes, Gs)):
+        R = ref[int(n)]
+        if not (C.nnz == R.nnz and torch.equal(C.cp, R.cp) and torch.equal(C.ir, R.ir)
+                and torch.equal(C.num, R.num)):
+            bad.append(i)
+    return bad
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_batched_galerkin_512_every_instance(spx, dtype):
+    """The benchmark's Galerkin batch (512 instances, n log-uniform in [16, 96],
+    seed 4) under every setting the autotuner may pick for either level: all
+    512 coarse operators equal the closed form 4 L_{n/2}."""
+    from paper_1109_3739_amd import autotune
+    sizes = W.galerkin_sizes(512, seed=4)
+    uniq = sorted(set(int(n) for n in sizes))
+    L = {n: spx.from_host(W.laplacian7(n, dtype)) for n in uniq}
+    P = {n: spx.from_host(W.aggregation(n, dtype)) for n in uniq}
+    PT = {n: spx.from_host(W.aggregation(n, dtype, transpose=True)) for n in uniq}
+    As = [L[int(n)] for n in sizes]
+    Ps = [P[int(n)] for n in sizes]
+    PTs = [PT[int(n)] for n in sizes]
+    for cand in autotune.CANDIDATES:
+        t = autotune.make_tuning(cand)
+        p1 = spx.BatchPlan(As, Ps, tuning=t)
+        APs = p1.execute()
+        p2 = spx.BatchPlan(PTs, APs, tuning=t)
+        Gs = p2.execute()
+        bad = closed_form_all(spx, sizes, Gs, dtype)
+        assert not bad, f"tuning {cand}: instances {bad[:10]} differ from 4 L_(n/2)"
+        p1.close()
+        p2.close()
+        del APs, Gs
+
+
 def test_batch_graph_replay(spx):
     """Capture the numeric phase once, replay it with new values, with eager
     work and synchronisations between replays; check every replay."""

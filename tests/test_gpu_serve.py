@@ -17,7 +17,19 @@ def store_and_pool(spx):
     for key, (s, M) in enumerate(pool):
         store.add(key, M)
         scales[key] = s
+    store.host = {key: M for key, (s, M) in enumerate(pool)}  # host copies for the oracle
     return store, scales
+
+
+def oracle_result(store, r):
+    """The oracle's answer to a served request: the FP32 product of the two
+    resident matrices, or the extraction A(I, J) of the int64 edge ids."""
+    import oracle
+    M = store.host[r.a]
+    if r.kind == "spgemm":
+        return oracle.spgemm_csc(M, store.host[r.b])
+    E = M.with_values(np.arange(M.nnz, dtype=np.int64))
+    return oracle.spref(E, r.I.cpu().numpy(), r.J.cpu().numpy())
 
 
 def run(spx, store, scales, mode, n=60, qps=1e6, budget=64 << 30, seed=1):
@@ -38,8 +50,11 @@ def test_results_same_alone_and_in_the_mix(spx, store_and_pool):
             alone = spx.spgemm(store.f32[r.a], store.f32[r.b])
         else:
             alone = spx.spref(store.i64[r.a], r.I, r.J)
-        assert_same_csc(r.result.to_host_csc(), alone.to_host_csc(), exact_values=(r.kind == "spref"),
-                        what=f"request {r.rid} ({r.kind})")
+        got = r.result.to_host_csc()
+        assert_same_csc(got, oracle_result(store, r), exact_values=(r.kind == "spref"),
+                        what=f"request {r.rid} ({r.kind}) against the oracle")
+        assert_same_csc(got, alone.to_host_csc(), exact_values=(r.kind == "spref"),
+                        what=f"request {r.rid} ({r.kind}) alone and in the mix")
 
 
 def test_plain_mode_matches(spx, store_and_pool):

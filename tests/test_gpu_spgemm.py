@@ -96,6 +96,10 @@ def test_rmat_semirings(spx, semiring, values, exact):
     dict(bucket_parts=1),                                  # parts visit only their bucket of B entries
     dict(bucket_parts=1, part_lds_bytes=24 * 1024, range_chunk=512),
     dict(bucket_parts=1, part_lds_bytes=24 * 1024, xcd_slices=3),
+    dict(force_off64=1),                                   # 64-bit gathers (A of 2^29 entries or more)
+    dict(force_off64=1, part_lds_bytes=24 * 1024),
+    dict(force_off64=1, tiny_max=0, hash_count_max=0, bitmap_store_mb=0),
+    dict(force_off64=1, range_chunk=512, bucket_parts=1),
 ])
 @pytest.mark.parametrize("dtype", [np.float64, np.float32])
 def test_forced_paths(spx, tune, dtype):
@@ -107,6 +111,35 @@ def test_forced_paths(spx, tune, dtype):
     _, info = check_against_oracle(spx, A, A, "plus_times", tuning=t)
     if "part_lds_bytes" in tune and tune["part_lds_bytes"] <= 24 * 1024:
         assert info["heavy_parts"] > info["cols_heavy"] + info["cols_medium"]
+
+
+@pytest.mark.parametrize("tune", [
+    dict(),
+    dict(tiny_max=0, hash_count_max=0),
+    dict(tiny_max=64, hash_count_max=16384),
+    dict(part_lds_bytes=24 * 1024),
+    dict(part_lds_bytes=24 * 1024, bitmap_store_mb=0),
+    dict(single_part_max=4096, single_threads=1024),
+])
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_signed_zeros_follow_algorithm_1(spx, tune, dtype):
+    # Products that are all -0.0 (negative A times B values of +0.0) must sum
+    # to -0.0, as Algorithm 1 starts each accumulator from its first product;
+    # mixed-sign zeros give +0.0.  Checked bitwise on every path.
+    A = W.rmat(14, 8, seed=13, values="f64")
+    A.num = (-A.num).astype(dtype)
+    B = A.with_values(np.zeros(A.nnz, dtype=dtype))
+    t = spx.default_tuning()
+    for k, v in tune.items():
+        setattr(t, k, v)
+    C, info = check_against_oracle(spx, A, B, "plus_times", exact=True, tuning=t)
+    got = C.to_host_csc()
+    assert got.num.size and np.all(got.num == 0) and np.all(np.signbit(got.num))
+    B2 = B.with_values(B.num.copy())
+    B2.num[::3] = -0.0  # -a * -0 = +0 joins some sums
+    C2, _ = check_against_oracle(spx, A, B2, "plus_times", exact=True, tuning=t)
+    g2 = C2.to_host_csc().num
+    assert np.any(np.signbit(g2)) and np.any(~np.signbit(g2))
 
 
 def test_min_plus_forced_paths_exact(spx):
@@ -269,13 +302,36 @@ def rmat20():
     return W.rmat(20, 8, seed=20)
 
 
-def test_rmat20_full_size_sampled(spx, rmat20):
-    """R-MAT scale 20 A*A at full size, default (benchmark) configuration.
+def check_blockwise(A, B, C, semiring="plus_times", block_entries=200_000_000):
+    """Every column of a device result C (CSC) against the oracle, in blocks of
+    columns copied to the host (the oracle recomputes each column with its
+    SPA and compares rows exactly and values within the tolerance)."""
+    import torch
+    torch.cuda.synchronize()
+    cp = C.cp.cpu().numpy().astype(np.int64)
+    assert cp[0] == 0 and cp[-1] == C.nnz and np.all(np.diff(cp) >= 0)
+    j0, nbad, first = 0, 0, -1
+    while j0 < C.n:
+        j1 = int(np.searchsorted(cp, cp[j0] + block_entries, side="right")) - 1
+        j1 = min(C.n, max(j1, j0 + 1))
+        s, e = int(cp[j0]), int(cp[j1])
+        gir = C.ir[s:e].cpu().numpy()
+        gnum = None if C.num is None else C.num[s:e].cpu().numpy()
+        nb, fb = oracle.spgemm_check(A, B, j0, j1, cp[j0:j1 + 1], gir, gnum, semiring)
+        if nb and first < 0:
+            first = fb
+        nbad += nb
+        j0 = j1
+    assert nbad == 0, f"{nbad} columns differ from the oracle, first {first}"
+    return cp
 
-    The oracle recomputes sampled columns one by one: the heaviest columns,
-    random nonempty ones and the first/last columns.  Properties that hold at
-    any size are checked over the whole output.
-    """
+
+@pytest.mark.timeout(900)
+def test_rmat20_full_size_every_column(spx, rmat20):
+    """R-MAT scale 20 A*A at full size in the benchmark's configuration
+    (default tuning, CSC output, int64 pointers): every one of the 2^20 output
+    columns is recomputed by the oracle and compared, rows exactly and values
+    within 1e-12 relative, block by block of about 2.4 GB."""
     import torch
     A = rmat20
     dA = spx.from_host(A)
@@ -283,32 +339,66 @@ def test_rmat20_full_size_sampled(spx, rmat20):
     C = plan.execute()
     info = plan.info()
     plan.close()
+    deg = np.diff(A.cp)
+    mults = int(deg[A.ir].sum())
+    assert info["mults"] == mults
+    cp = check_blockwise(A, A, C)
+    assert info["nnz"] == C.nnz == cp[-1] <= mults
+    del C
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("out_fmt", [0, 1])
+def test_rmat20_stage_block_dcsc_full_size(spx, rmat20, out_fmt):
+    """The benchmark's 8x8 Sparse SUMMA stage block: A00 * A00 of the scale-20
+    matrix (2^17 x 2^17, fewer nonzeros than columns), DCSC in and DCSC (or
+    CSC) out, every column against the oracle."""
+    A = rmat20
+    b = A.n // 8
+    blk = W.column_block(A, 0, b, 0, b)
+    assert blk.nnz < blk.n
+    dB = spx.csc_to_dcsc(spx.from_host(blk))
+    plan = spx.GemmPlan(dB, dB, out_fmt=out_fmt)
+    C = plan.execute()
+    info = plan.info()
+    plan.close()
+    got = C.to_host_csc()
+    assert info["mults"] == int(np.diff(blk.cp)[blk.ir].sum())
+    ref = oracle.spgemm_csc(blk, blk)
+    assert_same_csc(got, ref, what="stage block A00*A00")
+    if out_fmt == 1:
+        jc, dcp = oracle.csc_to_dcsc(ref.n, ref.cp)
+        assert np.array_equal(C.jc.cpu().numpy(), jc) and np.array_equal(C.cp.cpu().numpy(), dcp)
+
+
+def test_rmat20_forced_64bit_offsets_sampled(spx, rmat20):
+    """The gathers through 64-bit positions (taken when A has 2^29 entries or
+    more) forced on the scale-20 product: whole columns sampled from every
+    bin against the oracle."""
+    import torch
+    A = rmat20
+    dA = spx.from_host(A)
+    t = spx.default_tuning()
+    t.force_off64 = 1
+    plan = spx.GemmPlan(dA, dA, tuning=t)
+    C = plan.execute()
+    plan.close()
     torch.cuda.synchronize()
+    cp = C.cp.cpu().numpy()
     deg = np.diff(A.cp)
     cs = np.concatenate([[0], np.cumsum(deg[A.ir])])
     mults_col = cs[A.cp[1:]] - cs[A.cp[:-1]]
-    assert info["mults"] == int(deg[A.ir].sum())
-    cp = C.cp.cpu().numpy()
-    assert cp[0] == 0 and cp[-1] == C.nnz and np.all(np.diff(cp) >= 0)
-    assert np.all(np.diff(cp) <= mults_col)
-    # rows strictly increasing inside every column, all in range
-    ir = C.ir
-    assert int(ir.min()) >= 0 and int(ir.max()) < A.m
-    starts = torch.zeros(C.nnz, dtype=torch.bool, device="cuda")
-    starts[C.cp[:-1][torch.from_numpy(np.diff(cp) > 0).cuda()]] = True
-    bad = (ir[1:] <= ir[:-1]) & ~starts[1:]
-    assert int(bad.sum()) == 0
-    rng = np.random.default_rng(0)
-    heavy = np.argsort(mults_col)[-12:]
-    nonempty = np.nonzero(np.diff(cp) > 0)[0]
-    cols = np.unique(np.concatenate([heavy, rng.choice(nonempty, 300, replace=False), [0, A.n - 1]]))
+    rng = np.random.default_rng(5)
+    order = np.argsort(mults_col)
+    nonempty = np.nonzero(mults_col > 0)[0]
+    cols = np.unique(np.concatenate([order[-40:], rng.choice(nonempty, 400, replace=False)]))
     rcp, rir, rnum = oracle.spgemm(A, A, cols=cols)
     lens = cp[cols + 1] - cp[cols]
-    gcp = np.concatenate([[0], np.cumsum(lens)])
-    idx = np.concatenate([np.arange(cp[j], cp[j + 1]) for j in cols])
-    idx_t = torch.from_numpy(idx).cuda()
+    assert np.array_equal(lens, np.diff(rcp))
+    idx = torch.from_numpy(np.concatenate([np.arange(cp[j], cp[j + 1]) for j in cols])).cuda()
     from types import SimpleNamespace
-    got = SimpleNamespace(cp=gcp, ir=C.ir[idx_t].cpu().numpy(), num=C.num[idx_t].cpu().numpy())
-    assert_same_csc(got, SimpleNamespace(cp=rcp, ir=rir, num=rnum), what="rmat20 sampled columns")
+    got = SimpleNamespace(cp=np.concatenate([[0], np.cumsum(lens)]), ir=C.ir[idx].cpu().numpy(),
+                          num=C.num[idx].cpu().numpy())
+    assert_same_csc(got, SimpleNamespace(cp=rcp, ir=rir, num=rnum), what="64-bit gathers")
     del C
     torch.cuda.empty_cache()

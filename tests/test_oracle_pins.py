@@ -189,6 +189,61 @@ def test_spgemm_column_subset_matches_full():
         assert np.array_equal(snum[scp[t]:scp[t + 1]], num[cp[j]:cp[j + 1]])
 
 
+def test_spgemm_check_accepts_the_product_and_finds_planted_mistakes():
+    """The column checker used for full-size parity: it accepts the oracle's
+    own product (also in blocks) and rejects every planted kind of mistake --
+    a value just outside the tolerance, a zero of the wrong sign, a wrong row,
+    a missing entry -- while accepting a value inside the tolerance."""
+    rng = np.random.default_rng(11)
+    A = rand_csc(rng, 60, 60, 0.12, lo=-1.0, hi=1.0)
+    A.num[::7] = -0.0
+    B = A.with_values(A.num.copy())
+    B.num[::5] = 0.0
+    cp, ir, num = oracle.spgemm(A, B)
+    assert np.any((num == 0) & np.signbit(num))  # the product holds negative zeros
+    assert oracle.spgemm_check(A, B, 0, A.n, cp, ir, num) == (0, -1)
+    for j0, j1 in ((0, 17), (17, 40), (40, 60)):
+        s, e = cp[j0], cp[j1]
+        assert oracle.spgemm_check(A, B, j0, j1, cp[j0:j1 + 1], ir[s:e], num[s:e]) == (0, -1)
+    nz = np.nonzero(num != 0)[0]
+    col_of = np.searchsorted(cp, np.arange(cp[-1]), side="right") - 1
+    k = nz[len(nz) // 2]
+    ok = num.copy()
+    ok[k] = num[k] * (1 + 4e-13)
+    assert oracle.spgemm_check(A, B, 0, A.n, cp, ir, ok)[0] == 0
+    bad = num.copy()
+    bad[k] = num[k] * (1 + 4e-12)
+    assert oracle.spgemm_check(A, B, 0, A.n, cp, ir, bad) == (1, col_of[k])
+    z = np.nonzero((num == 0) & np.signbit(num))[0][0]
+    bad = num.copy()
+    bad[z] = 0.0
+    assert oracle.spgemm_check(A, B, 0, A.n, cp, ir, bad) == (1, col_of[z])
+    badr = ir.copy()
+    badr[k] = badr[k] + 1 if (k + 1 == cp[col_of[k] + 1] or badr[k] + 1 < badr[k + 1]) else badr[k]
+    if badr[k] != ir[k]:
+        assert oracle.spgemm_check(A, B, 0, A.n, cp, badr, num) == (1, col_of[k])
+    # one entry dropped from column j: its pointer and every later one move
+    j = col_of[k]
+    dcp = cp.copy()
+    dcp[j + 1:] -= 1
+    keep = np.ones(ir.size, dtype=bool)
+    keep[cp[j + 1] - 1] = False
+    nb, first = oracle.spgemm_check(A, B, 0, A.n, dcp, ir[keep], num[keep])
+    assert nb >= 1 and first == j
+    # min_plus and integers are compared bitwise
+    Ai = rand_csc(rng, 40, 40, 0.15, np.int64)
+    icp, iir, inum = oracle.spgemm(Ai, Ai)
+    assert oracle.spgemm_check(Ai, Ai, 0, Ai.n, icp, iir, inum) == (0, -1)
+    inum2 = inum.copy()
+    inum2[0] += 1
+    assert oracle.spgemm_check(Ai, Ai, 0, Ai.n, icp, iir, inum2)[0] == 1
+    mcp, mir, mnum = oracle.spgemm(A, A, "min_plus")
+    mnum2 = mnum.copy()
+    mnum2[3] = np.nextafter(mnum2[3], np.inf)
+    assert oracle.spgemm_check(A, A, 0, A.n, mcp, mir, mnum, "min_plus") == (0, -1)
+    assert oracle.spgemm_check(A, A, 0, A.n, mcp, mir, mnum2, "min_plus")[0] == 1
+
+
 def test_er_config_mults_exact():
     # d^2 n multiplications for d nonzeros per column (Section 3.3 analysis)
     A = W.erdos_renyi(4096, 4096, 8, seed=1)
