@@ -353,6 +353,20 @@ int spx_count_nonempty(const spx_ctx* ctx, const spx_mat* A, int64_t* nzc);
 int spx_csc_to_dcsc(const spx_ctx* ctx, const spx_mat* A, spx_mat* out);
 int spx_dcsc_to_csc(const spx_ctx* ctx, const spx_mat* A, spx_mat* out);
 
+/* spx_csc_to_dcsc_noalloc: spx_csc_to_dcsc for callers that cannot allocate
+ *   device memory -- code under HIP graph capture, tight serving loops,
+ *   harnesses that forbid hipMalloc.  It calls no allocator (neither
+ *   ctx->alloc nor hipMalloc) and does not synchronise the stream: its
+ *   scratch is a static device array of the library (about 33 MiB per GPU,
+ *   held until the process ends), so A may have at most 2^22 columns
+ *   (SPX_EINVAL beyond).  out->nzc is the capacity of out->jc ([nzc]) and
+ *   out->cp ([nzc+1]) and must be the number of nonempty columns of A;
+ *   entries beyond it are not written.  nzc_dev (device int64, may be NULL)
+ *   receives the number of nonempty columns.  All calls on one GPU share the
+ *   static array: calls that overlap on one GPU (other streams or threads)
+ *   race and must be ordered by the caller.                              */
+int spx_csc_to_dcsc_noalloc(const spx_ctx* ctx, const spx_mat* A, spx_mat* out, int64_t* nzc_dev);
+
 /* Checks that A is canonical (pointers monotone, rows in range and
  * strictly increasing per column, jc strictly increasing and in range).
  * *ok = 1 or 0.  Synchronises the stream.                                */

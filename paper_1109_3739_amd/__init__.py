@@ -35,7 +35,7 @@ EXPORTS = [
     "spx_extend_add_plan", "spx_extend_add_exec", "spx_spgemm_sum_plan", "spx_spgemm_sum_exec",
     "spx_contract_plan", "spx_contract_exec", "spx_spref", "spx_spasgn", "spx_extend_add", "spx_batch_spgemm",
     "spx_count_nonempty", "spx_csc_to_dcsc", "spx_dcsc_to_csc", "spx_check", "spx_last_error", "spx_version",
-    "spx_batch_plan", "spx_batch_exec", "spx_batch_capture", "spx_batch_replay",
+    "spx_batch_plan", "spx_batch_exec", "spx_batch_capture", "spx_batch_replay", "spx_csc_to_dcsc_noalloc",
 ]
 
 
@@ -123,6 +123,7 @@ def load():
         "spx_count_nonempty": ([C, M, PI64], ctypes.c_int),
         "spx_csc_to_dcsc": ([C, M, M], ctypes.c_int),
         "spx_dcsc_to_csc": ([C, M, M], ctypes.c_int),
+        "spx_csc_to_dcsc_noalloc": ([C, M, M, P], ctypes.c_int),
         "spx_check": ([C, M, ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
         "spx_batch_plan": ([C, I32, M, M, I32, ctypes.POINTER(spx_tuning), PP, PI64, PI64], ctypes.c_int),
         "spx_batch_exec": ([P, P, P, P, M], ctypes.c_int),
@@ -621,6 +622,20 @@ def csc_to_dcsc(A: SpMat) -> SpMat:
     out = SpMat(A.m, A.n, _empty(nzc.value + 1, A.cp.dtype), A.ir, A.num, _empty(nzc.value, torch.int32), DCSC)
     d = out.desc()
     _check(lib.spx_csc_to_dcsc(ctypes.byref(ctx), ctypes.byref(a), ctypes.byref(d)))
+    return out
+
+
+def csc_to_dcsc_noalloc(A: SpMat, nzc: int, nzc_dev=None) -> SpMat:
+    """CSC -> DCSC through the entry point that allocates nothing itself (its
+    scratch is a static device array); ``nzc`` is the number of nonempty
+    columns, ``nzc_dev`` an optional device int64 tensor that receives it."""
+    lib = load()
+    torch = _t()
+    ctx = make_ctx()
+    a = A.desc()
+    out = SpMat(A.m, A.n, _empty(nzc + 1, A.cp.dtype), A.ir, A.num, _empty(nzc, torch.int32), DCSC)
+    d = out.desc()
+    _check(lib.spx_csc_to_dcsc_noalloc(ctypes.byref(ctx), ctypes.byref(a), ctypes.byref(d), _ptr(nzc_dev)))
     return out
 
 

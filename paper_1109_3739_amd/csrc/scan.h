@@ -60,9 +60,10 @@ struct LoadI64 {
   __device__ int64_t operator()(int64_t i) const { return p[i]; }
 };
 
-// Enqueues the scan on `stream`; temporary block sums come from `scr`.
-template <class F>
-int exclusive_scan(F f, int64_t n, int64_t* out, Scratch& scr, hipStream_t stream) {
+// Enqueues the scan on `stream`; temporary block sums come from `scr` (any
+// type with Scratch's get_n: the context's allocator, or a fixed buffer).
+template <class F, class S>
+int exclusive_scan(F f, int64_t n, int64_t* out, S& scr, hipStream_t stream) {
   if (n <= 0) return fill_i64(out, 1, 0, stream);
   const int64_t nblocks = ceil_div(n, kScanTile);
   if (nblocks == 1) {
