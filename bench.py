@@ -17,7 +17,7 @@ on the library's stream over the timed steps), and the CPU oracle timed on
 a bounded sample of the same product.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-extra] [--no-cpu-baseline]
-    python bench.py --extra-only {latency,stages,tall,index,restriction,galerkin}
+    python bench.py --extra-only {latency,stages,tall,index,restriction,galerkin,serving}
 
 The other workloads (printed under "extra") give context: launch-bound
 latency, the Sparse SUMMA stage block and stage sum, the tall-skinny
@@ -387,32 +387,39 @@ def galerkin(spx, W, torch, count=512, seed=4):
     return out
 
 
-def serving(spx, torch, pool_per_scale=3, n_req=400):
+def serving(spx, torch, pool_size=256, n_req=5000, discard=500,
+            fracs=(0.5, 0.6, 0.7, 0.8, 0.9, 1.0, 1.1, 1.2, 1.3, 1.4, 1.5, 2.0, 3.0)):
     """Served request stream: plain per-request launches vs continuous
-    batching, at offered loads relative to plain's saturation rate."""
+    batching, at offered loads relative to plain's saturation rate.  A pool
+    of `pool_size` resident matrices (scales 10-18, about 28 per scale);
+    each load point runs `n_req` Poisson arrivals and leaves the first
+    `discard` out of the statistics."""
     from paper_1109_3739_amd import serve
-    pool = serve.make_pool(9 * pool_per_scale, seed=5)
+    pool = serve.make_pool(pool_size, seed=5)
     store = serve.ResidentStore()
     scales = {}
     for key, (s, M) in enumerate(pool):
         store.add(key, M)
         scales[key] = s
+    del pool
     # warm-up of both paths
     for mode in ("plain", "batched"):
-        serve.Server(store, mode=mode).run(serve.make_requests(store, scales, 40, 1e6, seed=99))
+        serve.Server(store, mode=mode).run(serve.make_requests(store, scales, 200, 1e6, seed=99))
     sat = serve.Server(store, mode="plain")
     reqs = sat.run(serve.make_requests(store, scales, n_req, 1e6, seed=7))
-    plain_max = serve.latency_stats(reqs)["throughput_rps"]
-    out = {"pool": f"{len(pool)} matrices, scales 10-18, degree 2-16, half R-MAT / half ER",
+    plain_max = serve.latency_stats(reqs, skip=discard)["throughput_rps"]
+    out = {"pool": f"{pool_size} matrices, scales 10-18, degree 2-16, half R-MAT / half ER",
+           "requests_per_point": n_req, "discarded_per_point": discard, "lanes": 3,
            "plain_saturation_rps": plain_max, "points": []}
-    for frac in (0.5, 0.8, 1.2, 2.0, 3.0, 4.0):
+    for frac in fracs:
         qps = frac * plain_max
         row = {"qps": round(qps, 1), "frac": frac}
         for mode in ("plain", "batched"):
             srv = serve.Server(store, mode=mode)
             reqs = srv.run(serve.make_requests(store, scales, n_req, qps, seed=int(frac * 100)))
-            st = serve.latency_stats(reqs)
-            st["rounds"] = srv.rounds
+            st = serve.latency_stats(reqs, skip=discard)
+            st["batches"] = srv.rounds
+            st["max_busy_lanes"] = srv.max_busy_lanes
             row[mode] = st
         out["points"].append(row)
         log(f"serving qps={qps:.0f}: plain p99 {row['plain'].get('p99_ms')} ms "
@@ -427,7 +434,8 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-extra", action="store_true", help="skip the other workloads")
-    ap.add_argument("--extra-only", choices=["latency", "stages", "tall", "index", "restriction", "galerkin"],
+    ap.add_argument("--extra-only", choices=["latency", "stages", "tall", "index", "restriction", "galerkin",
+                                             "serving"],
                     help="run only this group of the other workloads and print its figures")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -459,6 +467,9 @@ def main():
         torch.cuda.empty_cache()
     if args.extra_only == "galerkin":
         print(json.dumps({"galerkin": galerkin(spx, W, torch)}), flush=True)
+        return
+    if args.extra_only == "serving":
+        print(json.dumps({"serving": serving(spx, torch)}), flush=True)
         return
     if args.extra_only:
         print(json.dumps({"extra": extra_workloads(spx, W, torch, only=args.extra_only)}), flush=True)
