@@ -301,12 +301,15 @@ int spx_spref(const spx_ctx* ctx, const spx_mat* A, const int32_t* I, int64_t le
               spx_mat* B);
 
 /* ---- SpAsgn: C = A with the submatrix A(I,J) replaced by B (Section 4.1)
- * B is lenI x lenJ (CSC or DCSC).  Functional: A is not modified.  C keeps
- * every A(i,j) with i not in I or j not in J, and takes
- * C(I(p), J(q)) = B(p,q) for the stored B(p,q); entries of A(I,J) that B
- * does not store are removed.  A repeated index resolves to its last
- * occurrence in I (or J), as in sequential assignment.  A and B must have
- * the same value type.
+ * A is m x n and B is lenI x lenJ, each CSC or DCSC (a DCSC operand's
+ * pointers are expanded to CSC in the plan's scratch; rows and values are
+ * read in place).  Functional: A is not modified.  C keeps every A(i,j)
+ * with i not in I or j not in J, and takes C(I(p), J(q)) = B(p,q) for the
+ * stored B(p,q); entries of A(I,J) that B does not store are removed.  A
+ * repeated index resolves to its last occurrence in I (or J), as in
+ * sequential assignment.  A and B must have the same value type.  Any
+ * number of rows may be inserted into one column: columns above 4096
+ * inserted rows have their entries sorted in global memory by the plan.
  * spx_spasgn_plan returns nnz(C); spx_spasgn_exec fills C (CSC, m x n,
  * caller-allocated: cp [n+1], ir [nnz], num [nnz]).                      */
 int spx_spasgn_plan(const spx_ctx* ctx, const spx_mat* A, const int32_t* I, int64_t lenI, const int32_t* J,
@@ -327,10 +330,11 @@ int spx_spasgn(const spx_ctx* ctx, const spx_mat* A, const int32_t* I, int64_t l
  * values in B's storage order (column q ascending, then row p ascending),
  * so results do not depend on scheduling.  OR_AND takes pattern-only (BOOL)
  * operands; BOOL operands give the pattern union under any semiring.
- * A and B are CSC with the same value type; B is lenI x lenJ with
+ * A and B are CSC or DCSC with the same value type; B is lenI x lenJ with
  * nnz(B) < 2^32; I and J are device int32 arrays (any order, repeats
- * allowed).  At most 4096 B entries may land in one column of C
- * (SPX_EUNSUPPORTED otherwise).
+ * allowed).  Any number of B entries may land in one column of C: columns
+ * above 4096 landing entries are sorted in global memory by the plan
+ * (SPX_EUNSUPPORTED only if those columns' entries total 2^31 or more).
  * spx_extend_add_plan returns nnz(C) (SPX_EINVAL for an index out of range);
  * spx_extend_add_exec fills C (CSC, m x n, value type of A, caller-allocated:
  * cp [n+1], ir [nnz], num [nnz]).                                         */

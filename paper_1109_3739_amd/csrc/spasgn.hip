@@ -28,11 +28,127 @@
 
 namespace spx {
 
-constexpr int kAsgnMaxInsert = 4096;  // inserted rows per column handled in LDS
+constexpr int kAsgnMaxInsert = 4096;  // inserted rows per column handled in LDS; larger ("huge")
+                                      // columns sort their keys in global memory
 // Columns with at most this many inserted (landing) entries take one wave and
 // a small LDS area; the others go to a list served by 256-thread workgroups.
 constexpr int kAsgnSmall = 64;
 constexpr int64_t kCopyTile = 4096;   // A entries per copy workgroup
+
+// ---------------------------------------------------------------- helpers
+// Pointers of a DCSC operand expanded to CSC (cp[j] = start of column j);
+// rows and values stay the operand's.
+__global__ void k_dcsc_to_csc_ptr(Operand X, int64_t* cp) {
+  for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j <= X.n; j += (int64_t)gridDim.x * blockDim.x) {
+    int64_t lo = 0, hi = X.nzc;
+    while (lo < hi) {
+      const int64_t mid = (lo + hi) >> 1;
+      if ((int64_t)X.jc[mid] < j)
+        lo = mid + 1;
+      else
+        hi = mid;
+    }
+    cp[j] = slot_begin(X, lo);
+  }
+}
+
+// The operand as CSC: a DCSC operand gets CSC pointers from `scr`.
+int csc_view(const spx_mat* X, Scratch& scr, hipStream_t st, Operand* out) {
+  *out = make_operand(X);
+  if (X->fmt != SPX_DCSC) return SPX_OK;
+  int64_t* cp = nullptr;
+  SPX_TRY(scr.get_n(X->n + 1, &cp));
+  k_dcsc_to_csc_ptr<<<grid_for(X->n + 1, 256, 65536), 256, 0, st>>>(*out, cp);
+  SPX_HIP(hipGetLastError());
+  out->fmt = SPX_CSC;
+  out->ptr_t = SPX_PTR_I64;
+  out->cp = cp;
+  out->jc = nullptr;
+  out->nzc = 0;
+  return SPX_OK;
+}
+
+// Ascending bitonic sort of keys[0, p2) in global memory by the calling
+// workgroup (p2 a power of two >= kAsgnMaxInsert; the caller pads past the
+// keys with ~0).  Stages whose partner distance is below the LDS tile run in
+// `tile` (kAsgnMaxInsert keys), the others over global memory.
+__device__ void wg_sort_global(uint64_t* keys, int64_t p2, uint64_t* tile) {
+  constexpr int64_t T = kAsgnMaxInsert;
+  // whole tiles: every stage with k <= T, direction by the tile's position
+  for (int64_t base = 0; base < p2; base += T) {
+    for (int i = threadIdx.x; i < T; i += blockDim.x) tile[i] = keys[base + i];
+    __syncthreads();
+    for (int64_t k = 2; k <= T; k <<= 1) {
+      for (int64_t j = k >> 1; j > 0; j >>= 1) {
+        for (int i = threadIdx.x; i < T / 2; i += blockDim.x) {
+          const int lo = 2 * i - (i & (int)(j - 1));
+          const int hi = lo + (int)j;
+          const bool asc = ((base + lo) & k) == 0;
+          const uint64_t x = tile[lo], y = tile[hi];
+          if ((x > y) == asc) {
+            tile[lo] = y;
+            tile[hi] = x;
+          }
+        }
+        __syncthreads();
+      }
+    }
+    for (int i = threadIdx.x; i < T; i += blockDim.x) keys[base + i] = tile[i];
+    __syncthreads();
+  }
+  for (int64_t k = 2 * T; k <= p2; k <<= 1) {
+    for (int64_t j = k >> 1; j >= T; j >>= 1) {  // partners in different tiles
+      __threadfence_block();
+      for (int64_t i = threadIdx.x; i < p2 / 2; i += blockDim.x) {
+        const int64_t lo = 2 * i - (i & (j - 1));
+        const int64_t hi = lo + j;
+        const bool asc = (lo & k) == 0;
+        const uint64_t x = keys[lo], y = keys[hi];
+        if ((x > y) == asc) {
+          keys[lo] = y;
+          keys[hi] = x;
+        }
+      }
+      __threadfence_block();
+      __syncthreads();
+    }
+    for (int64_t base = 0; base < p2; base += T) {  // the rest of merge step k inside each tile
+      for (int i = threadIdx.x; i < T; i += blockDim.x) tile[i] = keys[base + i];
+      __syncthreads();
+      const bool asc = (base & k) == 0;
+      for (int j = (int)T >> 1; j > 0; j >>= 1) {
+        for (int i = threadIdx.x; i < T / 2; i += blockDim.x) {
+          const int lo = 2 * i - (i & (j - 1));
+          const int hi = lo + j;
+          const uint64_t x = tile[lo], y = tile[hi];
+          if ((x > y) == asc) {
+            tile[lo] = y;
+            tile[hi] = x;
+          }
+        }
+        __syncthreads();
+      }
+      for (int i = threadIdx.x; i < T; i += blockDim.x) keys[base + i] = tile[i];
+      __threadfence_block();
+      __syncthreads();
+    }
+  }
+}
+
+// Smallest power of two >= max(n, kAsgnMaxInsert) for a huge column, 0 for others.
+struct HugeCap {
+  const int64_t* n;        // per list entry: its number of keys
+  const int32_t* list;     // list entry -> index into n (NULL: identity)
+  const unsigned long long* len;  // entries at or past *len count 0 (NULL: none)
+  __device__ int64_t operator()(int64_t w) const {
+    if (len && w >= (int64_t)*len) return 0;
+    const int64_t c = n[list ? list[w] : w];
+    if (c <= kAsgnMaxInsert) return 0;
+    int64_t p = kAsgnMaxInsert;
+    while (p < c) p <<= 1;
+    return p;
+  }
+};
 
 struct SpasgnPlan : spx_plan {
   explicit SpasgnPlan(const spx_ctx* c) : spx_plan(c, kPlanSpasgn) {}
@@ -51,6 +167,10 @@ struct SpasgnPlan : spx_plan {
   int32_t* big = nullptr;    // modified columns (indices into mod) above kAsgnSmall inserts
   unsigned long long* nbig_d = nullptr;
   int64_t nbig = 0;
+  int64_t* icnt = nullptr;   // [nmod] inserted entries per modified column
+  int64_t* hoff = nullptr;   // [nbig+1] key segment of each big column (0 length unless huge)
+  uint64_t* hkeys = nullptr; // sorted (row, position in B's column) keys of the huge columns
+  int64_t nhuge_keys = 0;
   int64_t* tstart = nullptr;  // first column of every copy tile of A
   unsigned* err = nullptr;
   unsigned long long* nmod_d = nullptr;
@@ -103,8 +223,8 @@ int list_modified(const Operand& A, const int32_t* lastJ, int64_t* cnt, int32_t*
 // Per modified column: kept A entries, dropped ones, inserted B entries.
 __global__ void __launch_bounds__(256) k_asgn_mod_count(Operand A, Operand B, const int32_t* I, const int32_t* lastI,
                                                         const int32_t* lastJ, const int32_t* mod, int64_t nmod,
-                                                        int64_t* cnt, int64_t* dcnt, int32_t* big,
-                                                        unsigned long long* nbig, unsigned* err) {
+                                                        int64_t* cnt, int64_t* dcnt, int64_t* icnt, int32_t* big,
+                                                        unsigned long long* nbig) {
   __shared__ int64_t red[256 / kWave + 1];
   for (int64_t u = blockIdx.x; u < nmod; u += gridDim.x) {
     const int32_t j = mod[u];
@@ -123,10 +243,8 @@ __global__ void __launch_bounds__(256) k_asgn_mod_count(Operand A, Operand B, co
     if (threadIdx.x == 0) {
       cnt[j] = tk + ti;
       dcnt[u] = (a1 - a0) - tk;
-      if (ti > kAsgnMaxInsert)
-        atomicOr(err, 4u);
-      else if (ti > kAsgnSmall)
-        big[atomicAdd(nbig, 1ull)] = (int32_t)u;
+      icnt[u] = ti;
+      if (ti > kAsgnSmall) big[atomicAdd(nbig, 1ull)] = (int32_t)u;
     }
   }
 }
@@ -206,49 +324,123 @@ __global__ void __launch_bounds__(256) k_asgn_copy(Operand A, const int64_t* tst
   }
 }
 
-// Modified columns: merge the kept A entries (rows not in I, ascending) with
-// the inserted rows I(p) (sorted here), by merge-path positions.  CAP is the
-// LDS capacity for inserted rows: the one-wave variant (CAP = kAsgnSmall)
-// runs over all modified columns and skips larger ones, which the 256-thread
-// variant takes from `list`.
+// Merge of one modified column j (rows strictly increasing, as in A):
+// the kept A entries (rows not in I) and the inserted entries, given as
+// keys (row << 32 | position in B(:,q)) sorted by row in `keys` (LDS or
+// global).  A kept entry's output position is its kept rank plus the
+// inserted rows below it; an inserted entry's is its rank plus the kept
+// rows below it (A's rows below minus the dropped ones, which are listed).
+// Called by the whole workgroup.
+template <class KeyPtr>
+__device__ __forceinline__ void asgn_merge_column(const Operand& A, const Operand& B, const int32_t* lastI, int32_t j,
+                                                  int64_t b0, int64_t cbase, int64_t dbase, KeyPtr keys, int64_t nins,
+                                                  int64_t* red, int32_t* drows, int vb, int32_t* cir, void* cnum) {
+  const int64_t a0 = slot_begin(A, j), a1 = slot_begin(A, j + 1);
+  int64_t kept_run = 0, drop_run = 0;
+  for (int64_t ec = a0; ec < a1; ec += blockDim.x) {
+    const int64_t e = ec + threadIdx.x;
+    int64_t keep = 0, drop = 0;
+    int32_t row = 0;
+    if (e < a1) {
+      row = A.ir[e];
+      keep = lastI[row] < 0;
+      drop = !keep;
+    }
+    int64_t tk, td;
+    const int64_t xk = block_excl_scan(keep, red, &tk);
+    const int64_t xd = block_excl_scan(drop, red, &td);
+    if (keep) {
+      int64_t lo = 0, hi = nins;  // inserted rows < row
+      while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if ((int32_t)(keys[mid] >> 32) < row)
+          lo = mid + 1;
+        else
+          hi = mid;
+      }
+      const int64_t o = cbase + kept_run + xk + lo;
+      cir[o] = row;
+      copy_value(A.num, e, cnum, o, vb);
+    }
+    if (drop) drows[dbase + drop_run + xd] = row;
+    kept_run += tk;
+    drop_run += td;
+  }
+  __threadfence_block();
+  __syncthreads();
+  const int32_t* acol = A.ir + a0;
+  const int32_t alen = (int32_t)(a1 - a0);
+  for (int64_t s = threadIdx.x; s < nins; s += blockDim.x) {
+    const uint64_t key = keys[s];
+    const int32_t row = (int32_t)(key >> 32);
+    int32_t lo = 0, hi = alen;  // A rows < row
+    while (lo < hi) {
+      const int32_t mid = (lo + hi) >> 1;
+      if (acol[mid] < row)
+        lo = mid + 1;
+      else
+        hi = mid;
+    }
+    int64_t dlo = 0, dhi = drop_run;  // dropped rows < row
+    while (dlo < dhi) {
+      const int64_t mid = (dlo + dhi) >> 1;
+      if (drows[dbase + mid] < row)
+        dlo = mid + 1;
+      else
+        dhi = mid;
+    }
+    const int64_t o = cbase + s + (lo - dlo);
+    cir[o] = row;
+    copy_value(B.num, b0 + (int64_t)(key & 0xffffffffu), cnum, o, vb);
+  }
+  __syncthreads();
+}
+
+// Keys (row << 32 | position in B(:,q)) of a modified column's inserted
+// entries (B entries whose row index is the last occurrence in I), in B's
+// order, compacted by block scans; writes the first `cap` of them to
+// `keys` and returns their number.  Called by the whole workgroup.
+template <class KeyPtr>
+__device__ __forceinline__ int64_t asgn_insert_keys(const Operand& B, const int32_t* I, const int32_t* lastI,
+                                                    int64_t b0, int64_t b1, KeyPtr keys, int64_t cap,
+                                                    int64_t* red) {
+  int64_t nins = 0;
+  for (int64_t ec = b0; ec < b1; ec += blockDim.x) {
+    const int64_t e = ec + threadIdx.x;
+    int64_t take = 0;
+    int32_t row = 0;
+    if (e < b1) {
+      const int32_t p = B.ir[e];
+      row = I[p];
+      take = lastI[row] == p;
+    }
+    int64_t tot;
+    const int64_t ex = block_excl_scan(take, red, &tot);
+    if (take && nins + ex < cap) keys[nins + ex] = ((uint64_t)(uint32_t)row << 32) | (uint32_t)(e - b0);
+    nins += tot;
+  }
+  return nins;
+}
+
+// Modified columns with at most CAP inserted rows: the keys are sorted in
+// LDS.  The one-wave variant (CAP = kAsgnSmall) runs over all modified
+// columns and skips larger ones, which the 256-thread variant takes from
+// `list`; it in turn skips the huge columns (k_asgn_huge_fill).
 template <int CAP>
 __global__ void __launch_bounds__(256) k_asgn_mod_fill(Operand A, Operand B, const int32_t* I, const int32_t* lastI,
                                                        const int32_t* lastJ, const int32_t* mod, const int32_t* list,
-                                                       int64_t nlist, const int64_t* off, const int64_t* doff,
-                                                       int32_t* drows, int vb, int32_t* cir, void* cnum) {
+                                                       int64_t nlist, const int64_t* icnt, const int64_t* off,
+                                                       const int64_t* doff, int32_t* drows, int vb, int32_t* cir,
+                                                       void* cnum) {
   __shared__ uint64_t s_key[CAP];
-  __shared__ int64_t s_src[CAP];
   __shared__ int64_t red[256 / kWave + 1];
   for (int64_t w = blockIdx.x; w < nlist; w += gridDim.x) {
     const int64_t u = list ? list[w] : w;
+    if (icnt[u] > CAP) continue;  // uniform: a column of the other variant
     const int32_t j = mod[u];
-    const int64_t a0 = slot_begin(A, j), a1 = slot_begin(A, j + 1);
     const int32_t q = lastJ[j];
     const int64_t b0 = slot_begin(B, q), b1 = slot_begin(B, q + 1);
-    const int64_t cbase = off[j];
-    // 1. inserted entries (row, source) -> LDS, sorted by row
-    int64_t nins = 0;
-    for (int64_t ec = b0; ec < b1; ec += blockDim.x) {
-      const int64_t e = ec + threadIdx.x;
-      int64_t take = 0;
-      int32_t row = 0;
-      if (e < b1) {
-        const int32_t p = B.ir[e];
-        row = I[p];
-        take = lastI[row] == p;
-      }
-      int64_t tot;
-      const int64_t ex = block_excl_scan(take, red, &tot);
-      if (take && nins + ex < CAP) {
-        s_key[nins + ex] = ((uint64_t)(uint32_t)row << 32) | (uint32_t)(nins + ex);
-        s_src[nins + ex] = e;
-      }
-      nins += tot;
-    }
-    if (nins > CAP) {  // uniform: a column of the other variant
-      __syncthreads();
-      continue;
-    }
+    const int64_t nins = asgn_insert_keys(B, I, lastI, b0, b1, s_key, CAP, red);
     int p2 = 1;
     while (p2 < nins) p2 <<= 1;
     for (int s = (int)nins + threadIdx.x; s < p2; s += blockDim.x) s_key[s] = ~0ull;
@@ -268,67 +460,47 @@ __global__ void __launch_bounds__(256) k_asgn_mod_fill(Operand A, Operand B, con
         __syncthreads();
       }
     }
-    // 2. kept A entries: position = kept rank + inserted rows below; dropped rows listed
-    int64_t kept_run = 0, drop_run = 0;
-    const int64_t dbase = doff[u];
-    for (int64_t ec = a0; ec < a1; ec += blockDim.x) {
-      const int64_t e = ec + threadIdx.x;
-      int64_t keep = 0, drop = 0;
-      int32_t row = 0;
-      if (e < a1) {
-        row = A.ir[e];
-        keep = lastI[row] < 0;
-        drop = !keep;
-      }
-      int64_t tk, td;
-      const int64_t xk = block_excl_scan(keep, red, &tk);
-      const int64_t xd = block_excl_scan(drop, red, &td);
-      if (keep) {
-        int lo = 0, hi = (int)nins;  // inserted rows < row
-        while (lo < hi) {
-          const int mid = (lo + hi) >> 1;
-          if ((int32_t)(s_key[mid] >> 32) < row)
-            lo = mid + 1;
-          else
-            hi = mid;
-        }
-        const int64_t o = cbase + kept_run + xk + lo;
-        cir[o] = row;
-        copy_value(A.num, e, cnum, o, vb);
-      }
-      if (drop) drows[dbase + drop_run + xd] = row;
-      kept_run += tk;
-      drop_run += td;
-    }
+    asgn_merge_column(A, B, lastI, j, b0, off[j], doff[u], s_key, nins, red, drows, vb, cir, cnum);
+  }
+}
+
+// Huge columns (more than kAsgnMaxInsert inserted rows), at plan time: each
+// workgroup writes one column's keys into its segment of hkeys, pads the
+// segment to its power-of-two length and sorts it in global memory.
+__global__ void __launch_bounds__(256) k_asgn_huge_keys(Operand B, const int32_t* I, const int32_t* lastI,
+                                                        const int32_t* lastJ, const int32_t* mod, const int32_t* big,
+                                                        int64_t nbig, const int64_t* icnt, const int64_t* hoff,
+                                                        uint64_t* hkeys) {
+  __shared__ uint64_t s_tile[kAsgnMaxInsert];
+  __shared__ int64_t red[256 / kWave + 1];
+  for (int64_t w = blockIdx.x; w < nbig; w += gridDim.x) {
+    const int64_t p2 = hoff[w + 1] - hoff[w];
+    if (p2 == 0) continue;  // uniform: not a huge column
+    const int64_t u = big[w];
+    const int32_t q = lastJ[mod[u]];
+    uint64_t* seg = hkeys + hoff[w];
+    const int64_t nins = asgn_insert_keys(B, I, lastI, slot_begin(B, q), slot_begin(B, q + 1), seg, p2, red);
+    for (int64_t s = nins + threadIdx.x; s < p2; s += blockDim.x) seg[s] = ~0ull;
     __threadfence_block();
     __syncthreads();
-    // 3. inserted entries: position = rank + kept rows below
-    const int32_t* acol = A.ir + a0;
-    const int32_t alen = (int32_t)(a1 - a0);
-    for (int s = threadIdx.x; s < nins; s += blockDim.x) {
-      const uint64_t key = s_key[s];
-      const int32_t row = (int32_t)(key >> 32);
-      int32_t lo = 0, hi = alen;  // A rows < row
-      while (lo < hi) {
-        const int32_t mid = (lo + hi) >> 1;
-        if (acol[mid] < row)
-          lo = mid + 1;
-        else
-          hi = mid;
-      }
-      int64_t dlo = 0, dhi = drop_run;  // dropped rows < row
-      while (dlo < dhi) {
-        const int64_t mid = (dlo + dhi) >> 1;
-        if (drows[dbase + mid] < row)
-          dlo = mid + 1;
-        else
-          dhi = mid;
-      }
-      const int64_t o = cbase + s + (lo - dlo);
-      cir[o] = row;
-      copy_value(B.num, s_src[key & 0xffffffffu], cnum, o, vb);
-    }
-    __syncthreads();
+    wg_sort_global(seg, p2, s_tile);
+  }
+}
+
+// Huge columns at exec time: the merge from the sorted global keys.
+__global__ void __launch_bounds__(256) k_asgn_huge_fill(Operand A, Operand B, const int32_t* lastI,
+                                                        const int32_t* lastJ, const int32_t* mod, const int32_t* big,
+                                                        int64_t nbig, const int64_t* icnt, const int64_t* hoff,
+                                                        const uint64_t* hkeys, const int64_t* off, const int64_t* doff,
+                                                        int32_t* drows, int vb, int32_t* cir, void* cnum) {
+  __shared__ int64_t red[256 / kWave + 1];
+  for (int64_t w = blockIdx.x; w < nbig; w += gridDim.x) {
+    if (hoff[w + 1] == hoff[w]) continue;  // uniform: not a huge column
+    const int64_t u = big[w];
+    const int32_t j = mod[u];
+    const int32_t q = lastJ[j];
+    asgn_merge_column(A, B, lastI, j, slot_begin(B, q), off[j], doff[u], hkeys + hoff[w], icnt[u], red, drows, vb,
+                      cir, cnum);
   }
 }
 
@@ -354,6 +526,12 @@ struct ExtAddPlan : spx_plan {
   int32_t* big = nullptr;    // modified columns (indices into mod) above kAsgnSmall landing entries
   unsigned long long* nbig_d = nullptr;
   int64_t nbig = 0;
+  int64_t* hcnt = nullptr;   // [nmod] per big-list entry: landing entries of a huge column, else 0
+  int64_t* hoff = nullptr;   // [nmod+1] key segment of each big-list entry (0 length unless huge)
+  uint64_t* hkeys = nullptr; // sorted (row, position in B) keys of the huge columns
+  int32_t* hhead = nullptr;  // per huge column, hoff[w] + w .. : distinct-row heads
+  int32_t* hnin = nullptr;   // and new-row counts
+  int64_t nhuge_keys = 0;
   int64_t* tstart = nullptr;  // first column of every copy tile of A
   unsigned* err = nullptr;
   unsigned long long* nmod_d = nullptr;
@@ -423,166 +601,232 @@ __device__ __forceinline__ int64_t rows_below(const int32_t* col, int64_t len, i
   return lo;
 }
 
-// One workgroup per modified column j (grid-stride over the list):
-//   1. the landing entries of every B(:,q) with J(q) = j go into LDS as keys
-//      (I(p) << 32 | e), e the entry's position in B, and are sorted;
-//   2. the distinct rows are listed (first key of each) and looked up in A(:,j);
-//   3. count pass: nnz(C(:,j)) = nnz(A(:,j)) + distinct rows not in A(:,j);
+// One modified column j of extend-add from its landing entries, given as
+// keys (I(p) << 32 | e), e the entry's position in B, sorted ascending in
+// `keys` (LDS or global), with scratch `head` and `nin` of nins + 1 entries:
+//   1. the distinct rows are listed (first key of each) and looked up in A(:,j);
+//   2. count pass: nnz(C(:,j)) = nnz(A(:,j)) + distinct rows not in A(:,j);
 //      fill pass: A's entries move down by the new rows below them and add
 //      the values landing on their row; each new row takes the sum of its
 //      landing values.  Sums run in key order (B's storage order).
-// CAP bounds the landing entries held in LDS.  The one-wave variant
-// (CAP = kAsgnSmall, `list` NULL) runs over every modified column; in the
-// count pass it hands larger columns to the `big` list, which the 256-thread
-// variant (CAP = kAsgnMaxInsert) then serves (its length read from *nlist_d).
+// Called by the whole workgroup.
+template <bool kFill, bool kVals, typename T, class Acc, class KeyPtr, class IdxPtr>
+__device__ __forceinline__ void ea_column_body(const Operand& A, int32_t j, KeyPtr keys, int64_t nins, IdxPtr head,
+                                               IdxPtr nin, int64_t* red, int64_t* cnt, const int64_t* off,
+                                               const T* bnum, int32_t* cir, T* cnum) {
+  const T* anum = static_cast<const T*>(A.num);
+  const int64_t a0 = slot_begin(A, j), a1 = slot_begin(A, j + 1);
+  const int32_t* acol = A.ir + a0;
+  const int64_t alen = a1 - a0;
+  // distinct rows
+  int64_t nu = 0;
+  for (int64_t tc = 0; tc < nins; tc += blockDim.x) {
+    const int64_t t = tc + threadIdx.x;
+    int64_t hd = 0;
+    if (t < nins) hd = t == 0 || (keys[t] >> 32) != (keys[t - 1] >> 32);
+    int64_t tot;
+    const int64_t ex = block_excl_scan(hd, red, &tot);
+    if (hd) head[nu + ex] = (int32_t)t;
+    nu += tot;
+  }
+  if (threadIdx.x == 0) head[nu] = (int32_t)nins;
+  __threadfence_block();
+  __syncthreads();
+  // which distinct rows A(:,j) lacks
+  int64_t nnew = 0;
+  for (int64_t kc = 0; kc < nu; kc += blockDim.x) {
+    const int64_t k = kc + threadIdx.x;
+    int64_t fresh = 0;
+    if (k < nu) {
+      const int32_t row = (int32_t)(keys[head[k]] >> 32);
+      const int64_t at = rows_below(acol, alen, row);
+      fresh = !(at < alen && acol[at] == row);
+    }
+    int64_t tot;
+    const int64_t ex = block_excl_scan(fresh, red, &tot);
+    if (k < nu) nin[k] = (int32_t)(nnew + ex);
+    nnew += tot;
+  }
+  if (threadIdx.x == 0) nin[nu] = (int32_t)nnew;
+  __threadfence_block();
+  __syncthreads();
+  if (!kFill) {
+    if (threadIdx.x == 0) cnt[j] = alen + nnew;
+    return;
+  }
+  const int64_t cbase = off[j];
+  // A's entries
+  for (int64_t t = threadIdx.x; t < alen; t += blockDim.x) {
+    const int32_t row = acol[t];
+    int64_t lo = 0, hi = nu;  // distinct landing rows < row
+    while (lo < hi) {
+      const int64_t mid = (lo + hi) >> 1;
+      if ((int32_t)(keys[head[mid]] >> 32) < row)
+        lo = mid + 1;
+      else
+        hi = mid;
+    }
+    const int64_t o = cbase + t + nin[lo];
+    cir[o] = row;
+    if (kVals) {
+      T acc = anum[a0 + t];
+      if (lo < nu && (int32_t)(keys[head[lo]] >> 32) == row)
+        for (int64_t h = head[lo]; h < head[lo + 1]; ++h) acc = Acc::add(acc, bnum[(uint32_t)keys[h]]);
+      cnum[o] = acc;
+    }
+  }
+  // new rows
+  for (int64_t k = threadIdx.x; k < nu; k += blockDim.x) {
+    if (nin[k + 1] == nin[k]) continue;  // A(:,j) stores this row
+    const int32_t row = (int32_t)(keys[head[k]] >> 32);
+    const int64_t o = cbase + nin[k] + rows_below(acol, alen, row);
+    cir[o] = row;
+    if (kVals) {
+      T acc = bnum[(uint32_t)keys[head[k]]];
+      for (int64_t h = head[k] + 1; h < head[k + 1]; ++h) acc = Acc::add(acc, bnum[(uint32_t)keys[h]]);
+      cnum[o] = acc;
+    }
+  }
+  __syncthreads();
+}
+
+// Keys (I(p) << 32 | e) of the entries of every B(:,q) with J(q) = j that
+// land in column j, the first `cap` of them written to `keys`; returns their
+// number.  Called by the whole workgroup.
+template <class KeyPtr>
+__device__ __forceinline__ int64_t ea_landing_keys(const Operand& B, const int32_t* I, int32_t j, const int64_t* qoff,
+                                                   const int32_t* qlist, KeyPtr keys, int64_t cap) {
+  int64_t nins = 0;
+  for (int64_t t = qoff[j]; t < qoff[j + 1]; ++t) {
+    const int32_t q = qlist[t];
+    const int64_t b0 = slot_begin(B, q), b1 = slot_begin(B, q + 1);
+    for (int64_t e = b0 + threadIdx.x; e < b1; e += blockDim.x) {
+      const int64_t slot = nins + (e - b0);
+      if (slot < cap) keys[slot] = ((uint64_t)(uint32_t)I[B.ir[e]] << 32) | (uint32_t)e;
+    }
+    nins += b1 - b0;
+  }
+  return nins;
+}
+
+// One workgroup per modified column j (grid-stride over the list) whose
+// landing entries fit CAP: they are sorted in LDS, then ea_column_body.  The
+// one-wave variant (CAP = kAsgnSmall, `list` NULL) runs over every modified
+// column; in the count pass it hands larger columns to the `big` list, which
+// the 256-thread variant (CAP = kAsgnMaxInsert) then serves (its length read
+// from *nlist_d); in its count pass that variant records, per list entry,
+// the landing entries of a column above CAP in hcnt (0 for the others), and
+// such ("huge") columns are done by k_ea_huge.
 template <bool kFill, bool kVals, int CAP, typename T, class Acc>
 __global__ void __launch_bounds__(256) k_ea_column(Operand A, Operand B, const int32_t* I, const int32_t* mod,
                                                    const int32_t* list, const unsigned long long* nlist_d,
                                                    int64_t nlist_h, const int64_t* qoff, const int32_t* qlist,
                                                    int64_t* cnt, const int64_t* off, int32_t* big,
-                                                   unsigned long long* nbig, unsigned* err, int32_t* cir, T* cnum) {
+                                                   unsigned long long* nbig, int64_t* hcnt, int32_t* cir, T* cnum) {
   __shared__ uint64_t s_key[CAP];
   __shared__ int32_t s_head[CAP + 1];  // sorted position of each distinct row's first key
   __shared__ int32_t s_nin[CAP + 1];   // distinct rows before k that A(:,j) lacks
   __shared__ int64_t red[256 / kWave + 1];
-  const T* anum = static_cast<const T*>(A.num);
   const T* bnum = static_cast<const T*>(B.num);
   const int64_t nl = nlist_d ? (int64_t)*nlist_d : nlist_h;
   for (int64_t w = blockIdx.x; w < nl; w += gridDim.x) {
     const int64_t u = list ? list[w] : w;
     const int32_t j = mod[u];
-    const int64_t a0 = slot_begin(A, j), a1 = slot_begin(A, j + 1);
-    const int32_t* acol = A.ir + a0;
-    const int64_t alen = a1 - a0;
-    int64_t nins = 0;
-    for (int64_t t = qoff[j]; t < qoff[j + 1]; ++t) {
-      const int32_t q = qlist[t];
-      const int64_t b0 = slot_begin(B, q), b1 = slot_begin(B, q + 1);
-      for (int64_t e = b0 + threadIdx.x; e < b1; e += blockDim.x) {
-        const int64_t slot = nins + (e - b0);
-        if (slot < CAP) s_key[slot] = ((uint64_t)(uint32_t)I[B.ir[e]] << 32) | (uint32_t)e;
-      }
-      nins += b1 - b0;
-    }
+    const int64_t nins = ea_landing_keys(B, I, j, qoff, qlist, s_key, CAP);
+    if (!kFill && CAP == kAsgnMaxInsert && threadIdx.x == 0) hcnt[w] = nins > CAP ? nins : 0;
     if (nins > CAP) {  // uniform across the workgroup
-      if (!kFill && threadIdx.x == 0) {
-        if (CAP < kAsgnMaxInsert)
-          big[atomicAdd(nbig, 1ull)] = (int32_t)u;
-        else
-          atomicOr(err, 4u);
-      }
+      if (!kFill && CAP < kAsgnMaxInsert && threadIdx.x == 0) big[atomicAdd(nbig, 1ull)] = (int32_t)u;
       __syncthreads();
       continue;
     }
     lds_sort_keys(s_key, (int)nins);
-    // distinct rows
-    int nu = 0;
-    for (int tc = 0; tc < nins; tc += blockDim.x) {
-      const int t = tc + threadIdx.x;
-      int64_t head = 0;
-      if (t < nins) head = t == 0 || (s_key[t] >> 32) != (s_key[t - 1] >> 32);
-      int64_t tot;
-      const int64_t ex = block_excl_scan(head, red, &tot);
-      if (head) s_head[nu + ex] = t;
-      nu += (int)tot;
-    }
-    if (threadIdx.x == 0) s_head[nu] = (int)nins;
+    ea_column_body<kFill, kVals, T, Acc>(A, j, s_key, nins, s_head, s_nin, red, cnt, off, bnum, cir, cnum);
+  }
+}
+
+// Huge columns (more than kAsgnMaxInsert landing entries), at plan time:
+// each workgroup writes one column's keys into its segment of hkeys, pads
+// the segment to its power-of-two length and sorts it in global memory.
+__global__ void __launch_bounds__(256) k_ea_huge_keys(Operand B, const int32_t* I, const int32_t* mod,
+                                                      const int32_t* big, int64_t nbig, const int64_t* qoff,
+                                                      const int32_t* qlist, const int64_t* hoff, uint64_t* hkeys) {
+  __shared__ uint64_t s_tile[kAsgnMaxInsert];
+  for (int64_t w = blockIdx.x; w < nbig; w += gridDim.x) {
+    const int64_t p2 = hoff[w + 1] - hoff[w];
+    if (p2 == 0) continue;  // uniform: not a huge column
+    uint64_t* seg = hkeys + hoff[w];
+    const int64_t nins = ea_landing_keys(B, I, mod[big[w]], qoff, qlist, seg, p2);
+    for (int64_t s = nins + threadIdx.x; s < p2; s += blockDim.x) seg[s] = ~0ull;
+    __threadfence_block();
     __syncthreads();
-    // which distinct rows A(:,j) lacks
-    int64_t nnew = 0;
-    for (int kc = 0; kc < nu; kc += blockDim.x) {
-      const int k = kc + threadIdx.x;
-      int64_t fresh = 0;
-      if (k < nu) {
-        const int32_t row = (int32_t)(s_key[s_head[k]] >> 32);
-        const int64_t at = rows_below(acol, alen, row);
-        fresh = !(at < alen && acol[at] == row);
-      }
-      int64_t tot;
-      const int64_t ex = block_excl_scan(fresh, red, &tot);
-      if (k < nu) s_nin[k] = (int)(nnew + ex);
-      nnew += tot;
-    }
-    if (threadIdx.x == 0) s_nin[nu] = (int)nnew;
-    __syncthreads();
-    if (!kFill) {
-      if (threadIdx.x == 0) cnt[j] = alen + nnew;
-      continue;
-    }
-    const int64_t cbase = off[j];
-    // A's entries
-    for (int64_t t = threadIdx.x; t < alen; t += blockDim.x) {
-      const int32_t row = acol[t];
-      int lo = 0, hi = nu;  // distinct landing rows < row
-      while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if ((int32_t)(s_key[s_head[mid]] >> 32) < row)
-          lo = mid + 1;
-        else
-          hi = mid;
-      }
-      const int64_t o = cbase + t + s_nin[lo];
-      cir[o] = row;
-      if (kVals) {
-        T acc = anum[a0 + t];
-        if (lo < nu && (int32_t)(s_key[s_head[lo]] >> 32) == row)
-          for (int h = s_head[lo]; h < s_head[lo + 1]; ++h) acc = Acc::add(acc, bnum[(uint32_t)s_key[h]]);
-        cnum[o] = acc;
-      }
-    }
-    // new rows
-    for (int k = threadIdx.x; k < nu; k += blockDim.x) {
-      if (s_nin[k + 1] == s_nin[k]) continue;  // A(:,j) stores this row
-      const int32_t row = (int32_t)(s_key[s_head[k]] >> 32);
-      const int64_t o = cbase + s_nin[k] + rows_below(acol, alen, row);
-      cir[o] = row;
-      if (kVals) {
-        T acc = bnum[(uint32_t)s_key[s_head[k]]];
-        for (int h = s_head[k] + 1; h < s_head[k + 1]; ++h) acc = Acc::add(acc, bnum[(uint32_t)s_key[h]]);
-        cnum[o] = acc;
-      }
-    }
-    __syncthreads();
+    wg_sort_global(seg, p2, s_tile);
+  }
+}
+
+// Huge columns, count (plan) or fill (exec) pass: ea_column_body over the
+// sorted global keys; head and nin take hoff[w] + w .. + p2 + 1 of hidx.
+template <bool kFill, bool kVals, typename T, class Acc>
+__global__ void __launch_bounds__(256) k_ea_huge(Operand A, Operand B, const int32_t* mod, const int32_t* big,
+                                                 int64_t nbig, const int64_t* hcnt, const int64_t* hoff,
+                                                 const uint64_t* hkeys, int32_t* hhead, int32_t* hnin, int64_t* cnt,
+                                                 const int64_t* off, int32_t* cir, T* cnum) {
+  __shared__ int64_t red[256 / kWave + 1];
+  const T* bnum = static_cast<const T*>(B.num);
+  for (int64_t w = blockIdx.x; w < nbig; w += gridDim.x) {
+    if (hoff[w + 1] == hoff[w]) continue;  // uniform: not a huge column
+    const int64_t seg = hoff[w] + w;
+    ea_column_body<kFill, kVals, T, Acc>(A, mod[big[w]], hkeys + hoff[w], hcnt[w], hhead + seg, hnin + seg, red, cnt,
+                                         off, bnum, cir, cnum);
   }
 }
 
 // One-wave variant over all modified columns, then the 256-thread variant
 // over the big list (its length is on the device in the count pass; the fill
-// pass knows it from the plan).
+// pass knows it from the plan).  `huge`: the huge columns' kernel instead.
 template <bool kFill, bool kVals, typename T, class Acc>
-int launch_ea(const ExtAddPlan* P, int32_t* cir, void* cnum, hipStream_t st) {
+int launch_ea(const ExtAddPlan* P, int32_t* cir, void* cnum, hipStream_t st, bool huge) {
   const int cus = device_cu_count();
   T* out = static_cast<T*>(cnum);
+  if (huge) {
+    if (P->nhuge_keys > 0) {
+      k_ea_huge<kFill, kVals, T, Acc><<<(unsigned)std::min<int64_t>(P->nbig, (int64_t)cus * 2), 256, 0, st>>>(
+          P->A, P->B, P->mod, P->big, P->nbig, P->hcnt, P->hoff, P->hkeys, P->hhead, P->hnin, P->cnt, P->off, cir,
+          out);
+      SPX_HIP(hipGetLastError());
+    }
+    return SPX_OK;
+  }
   k_ea_column<kFill, kVals, kAsgnSmall, T, Acc><<<(unsigned)std::min<int64_t>(P->nmod, (int64_t)cus * 32), 64, 0,
                                                   st>>>(P->A, P->B, P->I, P->mod, nullptr, nullptr, P->nmod, P->qoff,
-                                                        P->qlist, P->cnt, P->off, P->big, P->nbig_d, P->err, cir,
+                                                        P->qlist, P->cnt, P->off, P->big, P->nbig_d, P->hcnt, cir,
                                                         out);
   SPX_HIP(hipGetLastError());
   if (!kFill || P->nbig > 0) {
     const int64_t grid = kFill ? std::min<int64_t>(P->nbig, (int64_t)cus * 4) : (int64_t)cus * 4;
     k_ea_column<kFill, kVals, kAsgnMaxInsert, T, Acc><<<(unsigned)grid, 256, 0, st>>>(
         P->A, P->B, P->I, P->mod, P->big, kFill ? nullptr : P->nbig_d, P->nbig, P->qoff, P->qlist, P->cnt, P->off,
-        P->big, P->nbig_d, P->err, cir, out);
+        P->big, P->nbig_d, P->hcnt, cir, out);
     SPX_HIP(hipGetLastError());
   }
   return SPX_OK;
 }
 
 template <bool kFill>
-int dispatch_ea(const ExtAddPlan* P, int32_t* cir, void* cnum, hipStream_t st) {
+int dispatch_ea(const ExtAddPlan* P, int32_t* cir, void* cnum, hipStream_t st, bool huge) {
   const int32_t vt = P->A.val_t;
-  if (vt == SPX_VAL_BOOL || P->sr == SPX_OR_AND) return launch_ea<kFill, false, float, MinAcc<float>>(P, cir, nullptr, st);
+  if (vt == SPX_VAL_BOOL || P->sr == SPX_OR_AND)
+    return launch_ea<kFill, false, float, MinAcc<float>>(P, cir, nullptr, st, huge);
   const bool plus = P->sr == SPX_PLUS_TIMES;
   switch (vt) {
     case SPX_VAL_F32:
-      return plus ? launch_ea<kFill, true, float, Semiring<SPX_PLUS_TIMES, float>>(P, cir, cnum, st)
-                  : launch_ea<kFill, true, float, MinAcc<float>>(P, cir, cnum, st);
+      return plus ? launch_ea<kFill, true, float, Semiring<SPX_PLUS_TIMES, float>>(P, cir, cnum, st, huge)
+                  : launch_ea<kFill, true, float, MinAcc<float>>(P, cir, cnum, st, huge);
     case SPX_VAL_F64:
-      return plus ? launch_ea<kFill, true, double, Semiring<SPX_PLUS_TIMES, double>>(P, cir, cnum, st)
-                  : launch_ea<kFill, true, double, MinAcc<double>>(P, cir, cnum, st);
+      return plus ? launch_ea<kFill, true, double, Semiring<SPX_PLUS_TIMES, double>>(P, cir, cnum, st, huge)
+                  : launch_ea<kFill, true, double, MinAcc<double>>(P, cir, cnum, st, huge);
     default:
-      return plus ? launch_ea<kFill, true, int64_t, Semiring<SPX_PLUS_TIMES, int64_t>>(P, cir, cnum, st)
-                  : launch_ea<kFill, true, int64_t, MinAcc<int64_t>>(P, cir, cnum, st);
+      return plus ? launch_ea<kFill, true, int64_t, Semiring<SPX_PLUS_TIMES, int64_t>>(P, cir, cnum, st, huge)
+                  : launch_ea<kFill, true, int64_t, MinAcc<int64_t>>(P, cir, cnum, st, huge);
   }
 }
 
@@ -596,7 +840,6 @@ extern "C" int spx_spasgn_plan(const spx_ctx* ctx, const spx_mat* A, const int32
   *plan = nullptr;
   SPX_TRY(check_mat(A, "A"));
   SPX_TRY(check_mat(B, "B"));
-  if (A->fmt != SPX_CSC || B->fmt != SPX_CSC) return fail(SPX_EUNSUPPORTED, "SpAsgn takes CSC operands");
   if (lenI < 0 || lenJ < 0 || lenI >= (1ll << 31) || lenJ >= (1ll << 31)) return fail(SPX_EINVAL, "bad index length");
   if (B->m != lenI || B->n != lenJ) return fail(SPX_EINVAL, "B must be lenI x lenJ");
   if (A->val_t != B->val_t) return fail(SPX_EINVAL, "A and B must have the same value type");
@@ -612,8 +855,8 @@ extern "C" int spx_spasgn_plan(const spx_ctx* ctx, const spx_mat* A, const int32
   std::unique_ptr<SpasgnPlan> guard(P);
   hipStream_t st = stream_of(ctx);
   Scratch& scr = P->scratch;
-  P->A = make_operand(A);
-  P->B = make_operand(B);
+  SPX_TRY(csc_view(A, scr, st, &P->A));  // DCSC operands get CSC pointers
+  SPX_TRY(csc_view(B, scr, st, &P->B));
   P->I = I;
   P->J = J;
   P->lenI = lenI;
@@ -652,26 +895,36 @@ extern "C" int spx_spasgn_plan(const spx_ctx* ctx, const spx_mat* A, const int32
   SPX_TRY(scr.get_n(std::max<int64_t>(P->nmod, 1), &P->dcnt));
   SPX_TRY(scr.get_n(P->nmod + 1, &P->doff));
   SPX_TRY(scr.get_n(std::max<int64_t>(P->nmod, 1), &P->big));
+  SPX_TRY(scr.get_n(std::max<int64_t>(P->nmod, 1), &P->icnt));
+  SPX_TRY(scr.get_n(P->nmod + 1, &P->hoff));
   SPX_TRY(scr.get_n(1, &P->nbig_d));
   SPX_TRY(fill_i64((int64_t*)P->nbig_d, 1, 0, st));
   if (P->nmod > 0) {
     k_asgn_mod_count<<<(unsigned)std::min<int64_t>(P->nmod, (int64_t)cus * 32), 64, 0, st>>>(
-        P->A, P->B, I, P->lastI, P->lastJ, P->mod, P->nmod, P->cnt, P->dcnt, P->big, P->nbig_d, P->err);
+        P->A, P->B, I, P->lastI, P->lastJ, P->mod, P->nmod, P->cnt, P->dcnt, P->icnt, P->big, P->nbig_d);
     SPX_HIP(hipGetLastError());
   }
   SPX_TRY(exclusive_scan(LoadI64{P->cnt}, n, P->off, scr, st));
   SPX_TRY(exclusive_scan(LoadI64{P->dcnt}, P->nmod, P->doff, scr, st));
-  int64_t tail[3] = {0, 0, 0};
+  // key segments of the huge columns (big-list order; entries past nbig are empty)
+  SPX_TRY(exclusive_scan(HugeCap{P->icnt, P->big, P->nbig_d}, P->nmod, P->hoff, scr, st));
+  int64_t tail[4] = {0, 0, 0, 0};
   SPX_HIP(hipMemcpyAsync(&tail[0], P->off + n, 8, hipMemcpyDeviceToHost, st));
   SPX_HIP(hipMemcpyAsync(&tail[1], P->doff + P->nmod, 8, hipMemcpyDeviceToHost, st));
   SPX_HIP(hipMemcpyAsync(&tail[2], P->nbig_d, 8, hipMemcpyDeviceToHost, st));
-  SPX_HIP(hipMemcpyAsync(&err_h, P->err, 4, hipMemcpyDeviceToHost, st));
+  SPX_HIP(hipMemcpyAsync(&tail[3], P->hoff + P->nmod, 8, hipMemcpyDeviceToHost, st));
   SPX_HIP(hipStreamSynchronize(st));
-  if (err_h & 4u) return fail(SPX_EUNSUPPORTED, "a column of B inserts more than 4096 rows");
   P->nnz = tail[0];
   P->ndrop = tail[1];
   P->nbig = tail[2];
+  P->nhuge_keys = tail[3];
   SPX_TRY(scr.get_n(std::max<int64_t>(P->ndrop, 1), &P->drows));
+  if (P->nhuge_keys > 0) {
+    SPX_TRY(scr.get_n(P->nhuge_keys, &P->hkeys));
+    k_asgn_huge_keys<<<(unsigned)std::min<int64_t>(P->nbig, (int64_t)cus * 2), 256, 0, st>>>(
+        P->B, I, P->lastI, P->lastJ, P->mod, P->big, P->nbig, P->icnt, P->hoff, P->hkeys);
+    SPX_HIP(hipGetLastError());
+  }
   if (nnz_c) *nnz_c = P->nnz;
   *plan = guard.release();
   return SPX_OK;
@@ -699,14 +952,20 @@ extern "C" int spx_spasgn_exec(spx_plan* plan, spx_mat* C) {
   }
   if (P->nmod > 0) {
     k_asgn_mod_fill<kAsgnSmall><<<(unsigned)std::min<int64_t>(P->nmod, (int64_t)cus * 32), 64, 0, st>>>(
-        P->A, P->B, P->I, P->lastI, P->lastJ, P->mod, nullptr, P->nmod, P->off, P->doff, P->drows, vb, C->ir,
-        C->num);
+        P->A, P->B, P->I, P->lastI, P->lastJ, P->mod, nullptr, P->nmod, P->icnt, P->off, P->doff, P->drows, vb,
+        C->ir, C->num);
     SPX_HIP(hipGetLastError());
   }
   if (P->nbig > 0) {
     k_asgn_mod_fill<kAsgnMaxInsert><<<(unsigned)std::min<int64_t>(P->nbig, (int64_t)cus * 2), 256, 0, st>>>(
-        P->A, P->B, P->I, P->lastI, P->lastJ, P->mod, P->big, P->nbig, P->off, P->doff, P->drows, vb, C->ir,
-        C->num);
+        P->A, P->B, P->I, P->lastI, P->lastJ, P->mod, P->big, P->nbig, P->icnt, P->off, P->doff, P->drows, vb,
+        C->ir, C->num);
+    SPX_HIP(hipGetLastError());
+  }
+  if (P->nhuge_keys > 0) {
+    k_asgn_huge_fill<<<(unsigned)std::min<int64_t>(P->nbig, (int64_t)cus * 2), 256, 0, st>>>(
+        P->A, P->B, P->lastI, P->lastJ, P->mod, P->big, P->nbig, P->icnt, P->hoff, P->hkeys, P->off, P->doff,
+        P->drows, vb, C->ir, C->num);
     SPX_HIP(hipGetLastError());
   }
   k_asgn_write_cp<<<grid_for(P->A.n + 1, 256, 65536), 256, 0, st>>>(P->off, P->A.n, C->cp, C->ptr_t);
@@ -721,7 +980,6 @@ extern "C" int spx_extend_add_plan(const spx_ctx* ctx, const spx_mat* A, const i
   *plan = nullptr;
   SPX_TRY(check_mat(A, "A"));
   SPX_TRY(check_mat(B, "B"));
-  if (A->fmt != SPX_CSC || B->fmt != SPX_CSC) return fail(SPX_EUNSUPPORTED, "extend-add takes CSC operands");
   if (lenI < 0 || lenJ < 0 || lenI >= (1ll << 31) || lenJ >= (1ll << 31)) return fail(SPX_EINVAL, "bad index length");
   if (B->m != lenI || B->n != lenJ) return fail(SPX_EINVAL, "B must be lenI x lenJ");
   if (A->val_t != B->val_t) return fail(SPX_EINVAL, "A and B must have the same value type");
@@ -741,8 +999,8 @@ extern "C" int spx_extend_add_plan(const spx_ctx* ctx, const spx_mat* A, const i
   std::unique_ptr<ExtAddPlan> guard(P);
   hipStream_t st = stream_of(ctx);
   Scratch& scr = P->scratch;
-  P->A = make_operand(A);
-  P->B = make_operand(B);
+  SPX_TRY(csc_view(A, scr, st, &P->A));  // DCSC operands get CSC pointers
+  SPX_TRY(csc_view(B, scr, st, &P->B));
   P->I = I;
   P->lenI = lenI;
   P->lenJ = lenJ;
@@ -787,16 +1045,36 @@ extern "C" int spx_extend_add_plan(const spx_ctx* ctx, const spx_mat* A, const i
     SPX_HIP(hipGetLastError());
   }
   SPX_TRY(scr.get_n(std::max<int64_t>(P->nmod, 1), &P->big));
+  SPX_TRY(scr.get_n(std::max<int64_t>(P->nmod, 1), &P->hcnt));
+  SPX_TRY(scr.get_n(P->nmod + 1, &P->hoff));
   SPX_TRY(scr.get_n(1, &P->nbig_d));
   SPX_TRY(fill_i64((int64_t*)P->nbig_d, 1, 0, st));
-  if (P->nmod > 0) SPX_TRY(dispatch_ea<false>(P, nullptr, nullptr, st));
+  if (P->nmod > 0) SPX_TRY(dispatch_ea<false>(P, nullptr, nullptr, st, false));
+  // key segments of the huge columns (big-list order; entries past nbig are empty)
+  SPX_TRY(exclusive_scan(HugeCap{P->hcnt, nullptr, P->nbig_d}, P->nmod, P->hoff, scr, st));
+  {
+    int64_t h[2] = {0, 0};
+    SPX_HIP(hipMemcpyAsync(&h[0], P->nbig_d, 8, hipMemcpyDeviceToHost, st));
+    SPX_HIP(hipMemcpyAsync(&h[1], P->hoff + P->nmod, 8, hipMemcpyDeviceToHost, st));
+    SPX_HIP(hipStreamSynchronize(st));
+    P->nbig = h[0];
+    P->nhuge_keys = h[1];
+  }
+  if (P->nhuge_keys > 0) {
+    if (P->nhuge_keys >= (1ll << 31)) return fail(SPX_EUNSUPPORTED, "landing entries of the large columns exceed 2^31");
+    SPX_TRY(scr.get_n(P->nhuge_keys, &P->hkeys));
+    SPX_TRY(scr.get_n(P->nhuge_keys + P->nbig, &P->hhead));
+    SPX_TRY(scr.get_n(P->nhuge_keys + P->nbig, &P->hnin));
+    const int cus = device_cu_count();
+    k_ea_huge_keys<<<(unsigned)std::min<int64_t>(P->nbig, (int64_t)cus * 2), 256, 0, st>>>(
+        P->B, I, P->mod, P->big, P->nbig, P->qoff, P->qlist, P->hoff, P->hkeys);
+    SPX_HIP(hipGetLastError());
+    SPX_TRY(dispatch_ea<false>(P, nullptr, nullptr, st, true));
+  }
   SPX_TRY(exclusive_scan(LoadI64{P->cnt}, n, P->off, scr, st));
   int64_t total = 0;
   SPX_HIP(hipMemcpyAsync(&total, P->off + n, 8, hipMemcpyDeviceToHost, st));
-  SPX_HIP(hipMemcpyAsync(&P->nbig, P->nbig_d, 8, hipMemcpyDeviceToHost, st));
-  SPX_HIP(hipMemcpyAsync(&err_h, P->err, 4, hipMemcpyDeviceToHost, st));
   SPX_HIP(hipStreamSynchronize(st));
-  if (err_h & 4u) return fail(SPX_EUNSUPPORTED, "a column of C receives more than 4096 entries of B");
   P->nnz = total;
   if (nnz_c) *nnz_c = P->nnz;
   *plan = guard.release();
@@ -823,7 +1101,10 @@ extern "C" int spx_extend_add_exec(spx_plan* plan, spx_mat* C) {
                                                                                        P->off, vb, C->ir, C->num);
     SPX_HIP(hipGetLastError());
   }
-  if (P->nmod > 0) SPX_TRY(dispatch_ea<true>(P, C->ir, C->num, st));
+  if (P->nmod > 0) {
+    SPX_TRY(dispatch_ea<true>(P, C->ir, C->num, st, false));
+    SPX_TRY(dispatch_ea<true>(P, C->ir, C->num, st, true));
+  }
   k_asgn_write_cp<<<grid_for(P->A.n + 1, 256, 65536), 256, 0, st>>>(P->off, P->A.n, C->cp, C->ptr_t);
   SPX_HIP(hipGetLastError());
   return SPX_OK;

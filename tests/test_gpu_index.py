@@ -218,7 +218,7 @@ def test_extend_add_identity_is_sparse_sum_and_edges(spx):
 def test_extend_add_crowded_column(spx):
     # One column of C receives 4096 B entries (the LDS limit) from 8 repeated
     # column indices with many repeated rows: a 4096-key sort, 16 scan chunks
-    # and long sums; a 4097th entry is refused.
+    # and long sums.
     rng = np.random.default_rng(65)
     A = with_values(W.erdos_renyi(5000, 3, 900, seed=11), "f64", rng)
     I = rng.integers(0, 5000, size=1024).astype(np.int32)
@@ -228,12 +228,102 @@ def test_extend_add_crowded_column(spx):
     B = W.from_triples(rows, cols, rng.random(rows.size), 1024, 10)
     C = extend_add_check(spx, A, I, J, B)
     assert np.diff(C.cp)[1] > 900
+    # a 4097th entry moves the column to the global-memory path
     rows2 = np.concatenate([rows, [600]])
     cols2 = np.concatenate([cols, [0]])
     B2 = W.from_triples(rows2, cols2, rng.random(rows2.size), 1024, 10)
-    with pytest.raises(spx.SpxError) as e:
-        spx.extend_add(spx.from_host(A), I, J, spx.from_host(B2))
-    assert e.value.code == spx.SPX_EUNSUPPORTED
+    C2 = extend_add_check(spx, A, I, J, B2)
+    assert np.array_equal(C2.ir, extend_add_check(spx, A, I, J, B2).ir)
+
+
+@pytest.mark.parametrize("kind,semiring", [("f64", "plus_times"), ("f32", "plus_times"), ("i64", "plus_times"),
+                                           ("f64", "min_plus"), ("none", "or_and")])
+def test_extend_add_huge_columns(spx, kind, semiring):
+    # columns receiving 4097, 9000 and 70000 landing entries (global key
+    # segments of 8192 and 131072 keys: several LDS tiles and global merge
+    # stages) from repeated column indices and heavily repeated rows, beside
+    # ordinary columns; sums in B's storage order, so bit-exact
+    rng = np.random.default_rng(67)
+    m = 200_000
+    A = with_values(W.erdos_renyi(m, 6, 3000, seed=12), kind, rng)
+    lI = 100_000
+    I = rng.integers(0, m, size=lI).astype(np.int32)
+    I[:5000] = I[5000:10000]  # many repeated rows
+    J = np.array([1, 1, 3, 3, 3, 5, 0, 2], dtype=np.int32)
+    sizes = [2049, 2048, 3000, 3000, 3000, 70_000, 17, 300]
+    rows = np.concatenate([np.sort(rng.choice(lI, k, replace=False)) for k in sizes])
+    cols = np.repeat(np.arange(len(sizes)), sizes)
+    B = with_values(W.from_triples(rows, cols, np.zeros(rows.size), lI, len(sizes)), kind, rng)
+    landing = np.bincount(J, weights=np.array(sizes), minlength=A.n)
+    assert landing[1] == 4097 and landing[3] == 9000 and landing[5] == 70_000
+    extend_add_check(spx, A, I, J, B, semiring)
+    J2 = np.array([5, 5, 4, 4, 4, 5, 0, 2], dtype=np.int32)  # column 5 receives 2049 + 2048 + 70000
+    extend_add_check(spx, A, I, J2, B, semiring)
+
+
+def test_spasgn_huge_columns(spx):
+    # columns inserting 4097, 9000 and 70000 rows (distinct rows, last
+    # occurrence of repeated indices), beside small and ordinary ones, with
+    # int64 and f64 values; the plan sorts the huge columns' keys in global
+    # memory
+    rng = np.random.default_rng(69)
+    m = 300_000
+    for vals in ("edge_id", "f64"):
+        A = W.erdos_renyi(m, 8, 5000, seed=13, values=vals)
+        lI = 120_000
+        I = rng.choice(m, lI, replace=False).astype(np.int32)
+        I[:1000] = I[1000:2000]  # repeated rows: the later occurrence wins
+        J = np.array([0, 1, 2, 3, 3, 5, 6, 7], dtype=np.int32)  # J repeats column 3
+        sizes = [4097, 9000, 70_000, 100, 5000, 64, 65, 0]
+        rows = np.concatenate([np.sort(rng.choice(lI, k, replace=False)) for k in sizes])
+        cols = np.repeat(np.arange(len(sizes)), sizes)
+        num = (1 << 40) + np.arange(rows.size, dtype=np.int64)
+        if vals == "f64":
+            num = rng.random(rows.size)
+        B = W.from_triples(rows, cols, num, lI, len(sizes))
+        spasgn_check(spx, A, I, J, B)
+
+
+@pytest.mark.parametrize("a_dcsc,b_dcsc", [(False, True), (True, False), (True, True)])
+def test_spasgn_extend_add_dcsc_operands(spx, a_dcsc, b_dcsc):
+    # hypersparse operands in DCSC: A with most columns empty, B with empty
+    # columns, both as stage blocks would arrive; results equal the CSC ones
+    rng = np.random.default_rng(71)
+    A = W.column_block(W.rmat(14, 4, seed=72, values="edge_id"), 0, 1 << 14, 0, 1 << 14)
+    lI, lJ = 3000, 2000
+    I = rng.integers(0, A.m, size=lI).astype(np.int32)
+    J = rng.integers(0, A.n, size=lJ).astype(np.int32)
+    Bm = W.erdos_renyi(lI, lJ, 3, seed=73, values="id40")
+    keep = np.repeat(rng.random(lJ) < 0.3, np.diff(Bm.cp))  # empty most of B's columns
+    cols = np.repeat(np.arange(lJ), np.diff(Bm.cp))[keep]
+    B = W.from_triples(Bm.ir[keep], cols, Bm.num[keep], lI, lJ)
+    dA, dB = spx.from_host(A), spx.from_host(B)
+    if a_dcsc:
+        dA = spx.csc_to_dcsc(dA)
+    if b_dcsc:
+        dB = spx.csc_to_dcsc(dB)
+    assert (not a_dcsc or dA.nzc < A.n) and (not b_dcsc or dB.nzc < B.n)
+    got = spx.spasgn(dA, I, J, dB).to_host_csc()
+    assert_same_csc(got, oracle.spasgn(A, I, J, B), exact_values=True, what="spasgn dcsc")
+    got = spx.extend_add(dA, I, J, dB).to_host_csc()
+    assert_same_csc(got, oracle.extend_add(A, I, J, B), exact_values=True, what="extend_add dcsc")
+
+
+@pytest.mark.timeout(900)
+def test_section52_assignment_rmat21_into_rmat22(spx, config3):
+    """Section 5.2's assignment at one-GPU scale: A(I, J) = B with A the
+    scale-22 R-MAT of the SpRef/SpAsgn workload, B an R-MAT of scale 21
+    (edge factor 16, int64 ids 2^40 + position, hub columns far above 4096
+    entries), I and J of length 2^21 with 10% repeated indices; bit-exact
+    against the oracle, and extend-add of the same block."""
+    A, _, _, _ = config3
+    L = 1 << 21
+    I = W.index_vector(L, A.m, seed=521)
+    J = W.index_vector(L, A.n, seed=522)
+    B = W.rmat(21, 16, seed=523, values="id40")
+    assert np.diff(B.cp).max() > 4096
+    spasgn_check(spx, A, I, J, B)
+    extend_add_check(spx, A, I, J, B)
 
 
 def test_extend_add_errors(spx):
