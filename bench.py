@@ -73,37 +73,71 @@ def time_steps(fn, steps, sync):
     return (time.perf_counter() - t0) / steps
 
 
-def cpu_baseline(A, target_s=15.0):
-    """Oracle on a random sample of output columns of A*A (all host cores)."""
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(A, target_s=4.0, reps=3):
+    """The oracle (dense-SPA column-wise Gustavson, OpenMP over columns) on
+    random samples of the output columns of A*A, at all host threads and at
+    one thread: each sample sized for about `target_s` seconds, timed `reps`
+    times, median reported.  A sample, not the whole product (which takes
+    minutes on one thread); the rate is GFLOP/s = 2 x mults / s of the
+    sampled columns."""
     import numpy as np
     import oracle
     rng = np.random.default_rng(1234)
     deg = np.diff(A.cp)
     cs = np.concatenate([[0], np.cumsum(deg[A.ir])])
     mults_col = cs[A.cp[1:]] - cs[A.cp[:-1]]
-    threads = oracle.max_threads()
     order = rng.permutation(A.n)
-    # calibrate on 0.2% of the columns, then size the sample for ~target_s
-    n0 = max(64, A.n // 500)
-    t0 = time.perf_counter()
-    oracle.spgemm(A, A, cols=np.sort(order[:n0]), nthreads=threads)
-    t_cal = time.perf_counter() - t0
-    rate = max(int(mults_col[order[:n0]].sum()), 1) / max(t_cal, 1e-3)
-    want = min(rate * target_s, 0.5 * float(mults_col.sum()))  # at most half of the product
     cum = np.cumsum(mults_col[order])
-    ncols = int(min(A.n, max(n0, np.searchsorted(cum, want) + 1)))
-    cols = np.sort(order[:ncols])
-    mults = int(mults_col[cols].sum())
-    t0 = time.perf_counter()
-    oracle.spgemm(A, A, cols=cols, nthreads=threads)
-    t = time.perf_counter() - t0
+    total = float(mults_col.sum())
+
+    def leg(threads):
+        # calibrate on a small sample, then size the sample for ~target_s
+        n0 = max(64, A.n // (500 if threads > 1 else 8000))
+        t0 = time.perf_counter()
+        oracle.spgemm(A, A, cols=np.sort(order[:n0]), nthreads=threads)
+        rate = max(int(cum[n0 - 1]), 1) / max(time.perf_counter() - t0, 1e-3)
+        want = min(rate * target_s, 0.5 * total)
+        ncols = int(min(A.n, max(n0, np.searchsorted(cum, want) + 1)))
+        cols = np.sort(order[:ncols])
+        mults = int(mults_col[cols].sum())
+        ts = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            oracle.spgemm(A, A, cols=cols, nthreads=threads)
+            ts.append(time.perf_counter() - t0)
+        t = statistics.median(ts)
+        return {"gflops": round(2.0 * mults / t / 1e9, 4), "seconds_median": round(t, 3),
+                "seconds_all": [round(x, 3) for x in ts], "columns": ncols, "mults": mults,
+                "whole_product_s_estimate": round(t * total / mults, 1)}
+
+    threads = oracle.max_threads()
+    multi = leg(threads)
+    single = leg(1)
     return {
-        "value": round(2.0 * mults / t / 1e9, 4),
+        "value": multi["gflops"],
         "unit": "GFLOP/s",
         "cores": threads,
         "kind": "oracle",
-        "sample": f"{ncols} of {A.n} output columns drawn uniformly at random (seed 1234), {mults} mults, "
-                  f"{t:.2f} s; dense-SPA column-wise Gustavson, OpenMP over columns",
+        "cpu_model": cpu_model(),
+        "host_logical_cpus": os.cpu_count(),
+        "sample": f"a sample, not the whole product: {multi['columns']} of {A.n} output columns drawn uniformly "
+                  f"at random (seed 1234), {multi['mults']} mults, median of {reps} runs "
+                  f"({multi['seconds_median']} s) at {threads} threads; dense-SPA column-wise Gustavson, "
+                  f"OpenMP over columns",
+        "all_threads": multi,
+        "single_thread": {**single, "cores": 1,
+                          "sample": f"{single['columns']} of {A.n} columns (the first of the same random order), "
+                                    f"median of {reps} runs at 1 thread"},
     }
 
 
@@ -438,7 +472,7 @@ def main():
                                              "serving"],
                     help="run only this group of the other workloads and print its figures")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-seconds", type=float, default=4.0, help="seconds per timed run of each CPU leg")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="first run one plain device-to-device copy of BYTES (reference for HBM counters)")
     args = ap.parse_args()
@@ -563,7 +597,7 @@ def main():
         log("serving")
         result["serving"] = serving(spx, torch)
     if not args.no_cpu_baseline:
-        log("cpu baseline (oracle, sampled columns)")
+        log("cpu baseline (oracle, sampled columns, all threads and one thread)")
         result["cpu_baseline"] = cpu_baseline(A, args.cpu_seconds)
     print(json.dumps(result), flush=True)
 

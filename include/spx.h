@@ -48,6 +48,12 @@ enum {
   SPX_EUNSUPPORTED = 4, /* semiring / value-type combination not provided */
   SPX_EDEVICE = 5       /* a HIP runtime call failed */
 };
+/* Fault injection for tests of the error paths: with the environment
+ * variable SPX_FAULT set to "alloc:N", the N-th device allocation the
+ * library makes (plan scratch and one-shot outputs, counted from the moment
+ * the variable took its current value) fails as SPX_ENOMEM; "alloc:N+"
+ * fails that allocation and every later one.  An entry point that fails
+ * releases what it had allocated and leaves its outputs untouched. */
 
 /* ---- descriptors ----------------------------------------------------- */
 enum { SPX_CSC = 0, SPX_DCSC = 1 };                 /* storage format (Section 3.2) */

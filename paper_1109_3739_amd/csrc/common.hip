@@ -1,6 +1,7 @@
 // Error reporting, scratch allocation and small fill kernels of libspx.
 #include "common.h"
 
+#include <cstdlib>
 #include <mutex>
 
 namespace spx {
@@ -8,6 +9,32 @@ namespace spx {
 static thread_local std::string g_last_error;
 
 void set_error(const std::string& msg) { g_last_error = msg; }
+
+// Allocation fault injection for tests of the error paths.  SPX_FAULT set
+// to "alloc:N" makes the N-th device allocation request of the library
+// fail (1-based, counted from the moment the variable took its current
+// value); "alloc:N+" makes that request and every later one fail.  Unset or
+// any other value: no faults.  Both the plans' scratch and the one-shot
+// entry points' outputs count.
+static bool fault_injected() {
+  static std::mutex mu;
+  static std::string spec;
+  static long long count = 0;
+  const char* env = getenv("SPX_FAULT");
+  const std::string cur = env ? env : "";
+  std::lock_guard<std::mutex> lock(mu);
+  if (cur != spec) {
+    spec = cur;
+    count = 0;
+  }
+  if (spec.compare(0, 6, "alloc:") != 0) return false;
+  char* end = nullptr;
+  const long long n = strtoll(spec.c_str() + 6, &end, 10);
+  if (end == spec.c_str() + 6 || n < 1) return false;
+  const bool and_later = *end == '+';
+  ++count;
+  return and_later ? count >= n : count == n;
+}
 
 Scratch::Scratch(const spx_ctx* ctx) : stream_(stream_of(ctx)) {
   if (ctx)
@@ -20,6 +47,7 @@ Scratch::~Scratch() { release_all(); }
 
 int Scratch::raw_alloc(size_t bytes, void** out) {
   void* p = nullptr;
+  if (fault_injected()) return fail(SPX_ENOMEM, "allocation failed (injected by SPX_FAULT)");
   if (ctx_.alloc) {
     p = ctx_.alloc(bytes, ctx_.user);
     if (!p) return fail(SPX_ENOMEM, "allocation callback failed for " + std::to_string(bytes) + " bytes");
@@ -80,6 +108,7 @@ int OutAlloc::get(size_t bytes, void** out) {
   *out = nullptr;
   if (bytes == 0) bytes = 16;
   void* p = nullptr;
+  if (fault_injected()) return fail(SPX_ENOMEM, "allocation of an output buffer failed (injected by SPX_FAULT)");
   if (ctx_ && ctx_->alloc) {
     p = ctx_->alloc(bytes, ctx_->user);
   } else if (hipMalloc(&p, bytes) != hipSuccess) {

@@ -303,9 +303,13 @@ class Server:
                     r.status, r.done = "rejected", self.now()
                     continue
                 r.start = self.now()
-                self._run_one(r)
-                self.stream.synchronize()
-                r.done, r.status = self.now(), "ok"
+                try:
+                    self._run_one(r)
+                    self.stream.synchronize()
+                    r.status = "ok"
+                except Exception as e:  # reported on the request; the loop goes on
+                    r.status, r.error, r.result = "failed", str(e)[:200], None
+                r.done = self.now()
                 self.max_used = max(self.max_used, r.est_bytes)
                 self.max_inflight = max(self.max_inflight, 1)
                 if not self.keep_results:
