@@ -314,8 +314,9 @@ def galerkin(spx, W, torch, count=512, seed=4):
     """Batched Galerkin products P^T (A P) for `count` 7-point Laplacians
     (n^3 grids, n log-uniform in [16, 96]) with 2x2x2 aggregation: one batch
     plan per product level (persistent launches over all instances), against
-    2*count separate plan+exec calls on the same GPU.  Parity: every
-    P^T A P must equal 4 x the coarse Laplacian exactly."""
+    2*count separate plan+exec calls on the same GPU, and the numeric phases
+    of both levels captured once in HIP graphs and replayed.  Parity: every
+    one of the P^T A P must equal 4 x the coarse Laplacian exactly."""
     import numpy as np
     from paper_1109_3739_amd import autotune
     sizes = W.galerkin_sizes(count, seed)
@@ -352,17 +353,53 @@ def galerkin(spx, W, torch, count=512, seed=4):
                 res.append(spx.spgemm(pt, ap))
             return res
 
+        refs = {}
+        for n in sorted(set(int(x) for x in sizes)):
+            r = W.laplacian7(n // 2, dt)
+            refs[n] = spx.from_host(r.with_values(4 * r.num))
+
+        def closed_form_ok(Gs):
+            # every coarse operator equals 4 L_(n/2) exactly (small integers)
+            return all(C.nnz == refs[int(n)].nnz and torch.equal(C.cp, refs[int(n)].cp)
+                       and torch.equal(C.ir, refs[int(n)].ir) and torch.equal(C.num, refs[int(n)].num)
+                       for n, C in zip(sizes, Gs))
+
         Gs = batched()
         torch.cuda.synchronize()
-        ok = True
-        for n, C in zip(sizes[:64], Gs[:64]):
-            ref = W.laplacian7(int(n) // 2, dt)
-            got = C.to_host_csc()
-            ok &= bool(np.array_equal(got.cp, ref.cp) and np.array_equal(got.ir, ref.ir)
-                       and np.array_equal(got.num, 4 * ref.num))
+        ok = closed_form_ok(Gs)
         del Gs
         t_b = time_steps(batched, 3, torch.cuda.synchronize)
         t_p = time_steps(plain, 1, torch.cuda.synchronize)
+
+        # the pattern is fixed, only values change from call to call (an AMG
+        # setup re-run on new coefficients): both levels' numeric phases are
+        # captured once into HIP graphs on one stream and replayed; each
+        # replay refreshes the values of A and of A P from their arrays
+        gstream = torch.cuda.Stream()
+        with torch.cuda.stream(gstream):
+            # level 2 is planned on level 1's output, so level 1 runs once
+            # before it is captured; both capture into the pools of that run
+            q1 = spx.BatchPlan(As, Ps, tuning=tun, stream=gstream)
+            gAPs = q1.execute()
+            q2 = spx.BatchPlan(PTs, gAPs, tuning=tun2, stream=gstream)
+            q2.execute()
+            gAPs = q1.capture()
+            gGs = q2.capture()
+
+            def replay():
+                q1.replay()
+                q2.replay()
+
+            replay()
+            gstream.synchronize()
+            ok_g = closed_form_ok(gGs)
+            t_g = time_steps(replay, 10, gstream.synchronize)
+            replay()
+            gstream.synchronize()
+            ok_g = ok_g and closed_form_ok(gGs)
+            q1.close()
+            q2.close()
+        del gAPs, gGs
 
         # fused P^T A P: with the aggregation S = P^T, P^T A P = S A S^T, one
         # contraction of the block-diagonal matrix of all instances with the
@@ -396,7 +433,7 @@ def galerkin(spx, W, torch, count=512, seed=4):
         torch.cuda.synchronize()
         cp_h, ir_h, num_h = G.cp.cpu().numpy(), G.ir.cpu().numpy(), G.num.cpu().numpy()
         ok_f = True
-        for i, n in enumerate(sizes[:64]):
+        for i, n in enumerate(sizes):
             ref = W.laplacian7(int(n) // 2, dt)
             c0, c1 = int(co[i]), int(co[i + 1])
             sub_cp = cp_h[c0:c1 + 1] - cp_h[c0]
@@ -409,9 +446,11 @@ def galerkin(spx, W, torch, count=512, seed=4):
         del Abd, bd_cp, bd_ir, bd_num, agg
         out[name] = {"batched_ms": round(1e3 * t_b, 3), "plain_ms": round(1e3 * t_p, 3),
                      "speedup": round(t_p / t_b, 2), "mults": mults,
-                     "batched_gflops": round(2 * mults / t_b / 1e9, 2), "closed_form_ok_first64": ok,
+                     "batched_gflops": round(2 * mults / t_b / 1e9, 2), "closed_form_ok_all": ok,
+                     "graph_replay_ms": round(1e3 * t_g, 3), "graph_replay_gflops": round(2 * mults / t_g / 1e9, 2),
+                     "graph_replay_closed_form_ok_all": ok_g,
                      "fused_contraction_ms": round(1e3 * t_f, 3), "fused_mults": fmults,
-                     "fused_closed_form_ok_first64": ok_f,
+                     "fused_closed_form_ok_all": ok_f,
                      "tuning": {"AP": tinfo["tuning"], "PtAP": tinfo2["tuning"]},
                      "tuning_cached": bool(tinfo["cached"] and tinfo2["cached"])}
         log(f"galerkin {name}: batched {1e3 * t_b:.1f} ms, fused contraction {1e3 * t_f:.1f} ms, "

@@ -141,6 +141,26 @@ def test_batched_galerkin_512_every_instance(spx, dtype):
         p1.close()
         p2.close()
         del APs, Gs
+    # both levels captured into HIP graphs on one stream and replayed, as the
+    # benchmark times them; every replay is checked (eager work in between)
+    import torch
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        p1 = spx.BatchPlan(As, Ps, stream=stream)
+        APs = p1.execute()
+        p2 = spx.BatchPlan(PTs, APs, stream=stream)
+        p2.execute()
+        p1.capture()
+        Gs = p2.capture()
+        for rep in range(3):
+            torch.zeros(1024, device="cuda").sum().item()  # eager work between replays
+            p1.replay()
+            p2.replay()
+            stream.synchronize()
+            bad = closed_form_all(spx, sizes, Gs, dtype)
+            assert not bad, f"replay {rep}: instances {bad[:10]} differ from 4 L_(n/2)"
+        p1.close()
+        p2.close()
 
 
 def test_batch_graph_replay(spx):
