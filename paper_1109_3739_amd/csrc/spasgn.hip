@@ -20,6 +20,7 @@
 // entries by (row, position in B), so a row's values are added to A's value
 // in B's storage order.
 #include <algorithm>
+#include <type_traits>
 
 #include "common.h"
 #include "operand.h"
@@ -33,7 +34,6 @@ constexpr int kAsgnMaxInsert = 4096;  // inserted rows per column handled in LDS
 // Columns with at most this many inserted (landing) entries take one wave and
 // a small LDS area; the others go to a list served by 256-thread workgroups.
 constexpr int kAsgnSmall = 64;
-constexpr int64_t kCopyTile = 4096;   // A entries per copy workgroup
 
 // ---------------------------------------------------------------- helpers
 // Pointers of a DCSC operand expanded to CSC (cp[j] = start of column j);
@@ -167,11 +167,15 @@ struct SpasgnPlan : spx_plan {
   int32_t* big = nullptr;    // modified columns (indices into mod) above kAsgnSmall inserts
   unsigned long long* nbig_d = nullptr;
   int64_t nbig = 0;
+  int32_t* mid = nullptr;    // the others whose A or B column exceeds one wave
+  unsigned long long* nmid_d = nullptr;
+  int64_t nmid = 0;
   int64_t* icnt = nullptr;   // [nmod] inserted entries per modified column
   int64_t* hoff = nullptr;   // [nbig+1] key segment of each big column (0 length unless huge)
   uint64_t* hkeys = nullptr; // sorted (row, position in B's column) keys of the huge columns
   int64_t nhuge_keys = 0;
-  int64_t* tstart = nullptr;  // first column of every copy tile of A
+  int64_t* tmod = nullptr;    // [ntiles+1] modified columns before each copy tile (k_copy_tiles)
+  int64_t ntiles = 0;
   unsigned* err = nullptr;
   unsigned long long* nmod_d = nullptr;
 };
@@ -221,107 +225,230 @@ int list_modified(const Operand& A, const int32_t* lastJ, int64_t* cnt, int32_t*
 }
 
 // Per modified column: kept A entries, dropped ones, inserted B entries.
+// One wave per column; the counts are ballot popcounts (no LDS, no barrier).
 __global__ void __launch_bounds__(256) k_asgn_mod_count(Operand A, Operand B, const int32_t* I, const int32_t* lastI,
                                                         const int32_t* lastJ, const int32_t* mod, int64_t nmod,
                                                         int64_t* cnt, int64_t* dcnt, int64_t* icnt, int32_t* big,
-                                                        unsigned long long* nbig) {
-  __shared__ int64_t red[256 / kWave + 1];
-  for (int64_t u = blockIdx.x; u < nmod; u += gridDim.x) {
+                                                        unsigned long long* nbig, int32_t* mid,
+                                                        unsigned long long* nmid) {
+  const int lane = lane_id();
+  const int64_t wave = __builtin_amdgcn_readfirstlane((int)((blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kWave));
+  const int64_t nwaves = (int64_t)gridDim.x * blockDim.x / kWave;
+  for (int64_t u = wave; u < nmod; u += nwaves) {
     const int32_t j = mod[u];
     const int64_t a0 = slot_begin(A, j), a1 = slot_begin(A, j + 1);
     const int32_t q = lastJ[j];
     const int64_t b0 = slot_begin(B, q), b1 = slot_begin(B, q + 1);
     int64_t kept = 0, ins = 0;
-    for (int64_t e = a0 + threadIdx.x; e < a1; e += blockDim.x) kept += lastI[A.ir[e]] < 0;
-    for (int64_t e = b0 + threadIdx.x; e < b1; e += blockDim.x) {
-      const int32_t p = B.ir[e];
-      ins += lastI[I[p]] == p;
+    for (int64_t ec = a0; ec < a1; ec += kWave) {
+      const int64_t e = ec + lane;
+      kept += __popcll(__ballot(e < a1 && lastI[A.ir[e]] < 0));
     }
-    int64_t tk, ti;
-    block_excl_scan(kept, red, &tk);
-    block_excl_scan(ins, red, &ti);
-    if (threadIdx.x == 0) {
-      cnt[j] = tk + ti;
-      dcnt[u] = (a1 - a0) - tk;
-      icnt[u] = ti;
-      if (ti > kAsgnSmall) big[atomicAdd(nbig, 1ull)] = (int32_t)u;
+    for (int64_t ec = b0; ec < b1; ec += kWave) {
+      const int64_t e = ec + lane;
+      bool take = false;
+      if (e < b1) {
+        const int32_t p = B.ir[e];
+        take = lastI[I[p]] == p;
+      }
+      ins += __popcll(__ballot(take));
+    }
+    if (lane == 0) {
+      cnt[j] = kept + ins;
+      dcnt[u] = (a1 - a0) - kept;
+      icnt[u] = ins;
+      if (ins > kAsgnSmall)
+        big[atomicAdd(nbig, 1ull)] = (int32_t)u;
+      else if (a1 - a0 > kWave || b1 - b0 > kWave)
+        mid[atomicAdd(nmid, 1ull)] = (int32_t)u;
     }
   }
 }
 
-// Copies the unmodified columns: each workgroup takes a tile of A's
-// entries, whose first column the plan has found (k_tile_starts).  One pass
-// over the tile's columns then writes,
-// in LDS, each column's output shift off[c] - cp[c] (a sentinel for the
-// modified columns) and the column of every entry of the tile, so the
-// entries are copied with no further pointer loads.  Tiles spanning more
-// than kCopyMapCols columns (long runs of empty columns) search each
-// entry's column instead.
-constexpr int kCopyMapCols = 2048;
-constexpr int64_t kCopySkip = INT64_MIN;
-
-// tstart[t] = the column holding entry t * kCopyTile (t < number of tiles);
-// tstart[nt] = n - 1.  One pass over the column pointers.
-__global__ void k_tile_starts(Operand A, int64_t nt, int64_t* tstart) {
-  for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < A.n; c += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t s0 = slot_begin(A, c), s1 = slot_begin(A, c + 1);
-    for (int64_t t = (s0 + kCopyTile - 1) / kCopyTile; t * kCopyTile < s1; ++t) tstart[t] = c;
+// Ascending bitonic sort of one 64-bit key per lane over the whole wave
+// (every lane active), by lane exchanges.
+__device__ __forceinline__ uint64_t wave_sort_u64(uint64_t key) {
+  const int lane = lane_id();
+#pragma unroll
+  for (int k = 2; k <= kWave; k <<= 1) {
+#pragma unroll
+    for (int jj = k >> 1; jj > 0; jj >>= 1) {
+      const uint64_t other = xor_lane(key, jj);
+      const bool up = (lane & k) == 0, lower = (lane & jj) == 0;
+      const uint64_t mn = other < key ? other : key, mx = other < key ? key : other;
+      key = lower == up ? mn : mx;
+    }
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) tstart[nt] = A.n - 1;
+  return key;
 }
 
-int tile_starts(const Operand& A, Scratch& scr, hipStream_t st, int64_t** tstart) {
-  const int64_t nt = ceil_div(A.nnz, kCopyTile);
-  SPX_TRY(scr.get_n(nt + 1, tstart));
-  if (A.n > 0) {
-    k_tile_starts<<<grid_for(A.n, 256, 65536), 256, 0, st>>>(A, nt, *tstart);
-    SPX_HIP(hipGetLastError());
+// Modified columns whose A column and B column both fit the 64 lanes of a
+// wave, done in registers: lane l holds A(:,j)'s l-th entry (kept if its row
+// is not in I) and B(:,q)'s l-th entry (inserted at row I(p) if p is that
+// row's last occurrence); the inserted keys (row, lane) are sorted across
+// the wave.  A kept entry goes to its kept rank plus the inserted rows below
+// it, an inserted one to its rank plus the kept rows below it (counted by
+// reading the other list lane by lane).  The LDS kernels skip these columns.
+__global__ void __launch_bounds__(256) k_asgn_mod_wave(Operand A, Operand B, const int32_t* I, const int32_t* lastI,
+                                                       const int32_t* lastJ, const int32_t* mod, int64_t nmod,
+                                                       const int64_t* off, int vb, int32_t* cir, void* cnum) {
+  const int lane = lane_id();
+  const int64_t wave = __builtin_amdgcn_readfirstlane((int)((blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kWave));
+  const int64_t nwaves = (int64_t)gridDim.x * blockDim.x / kWave;
+  for (int64_t u = wave; u < nmod; u += nwaves) {
+    const int32_t j = mod[u];
+    const int64_t a0 = slot_begin(A, j), a1 = slot_begin(A, j + 1);
+    const int32_t q = lastJ[j];
+    const int64_t b0 = slot_begin(B, q), b1 = slot_begin(B, q + 1);
+    if (a1 - a0 > kWave || b1 - b0 > kWave) continue;  // uniform: an LDS kernel's column
+    const int alen = (int)(a1 - a0), blen = (int)(b1 - b0);
+    const int64_t cbase = off[j];
+    int32_t arow = 0x7fffffff;
+    bool keep = false;
+    if (lane < alen) {
+      arow = A.ir[a0 + lane];
+      keep = lastI[arow] < 0;
+    }
+    uint64_t key = ~0ull;
+    if (lane < blen) {
+      const int32_t p = B.ir[b0 + lane];
+      const int32_t row = I[p];
+      if (lastI[row] == p) key = ((uint64_t)(uint32_t)row << 32) | (uint32_t)lane;
+    }
+    const uint64_t keptmask = __ballot(keep);
+    const int nins = __popcll(__ballot(key != ~0ull));
+    key = wave_sort_u64(key);
+    const int32_t irow = (int32_t)(key >> 32);  // lane k < nins: the k-th inserted row
+    int below = 0;   // inserted rows below this lane's A row
+    for (int t = 0; t < nins; ++t) below += __builtin_amdgcn_readlane(irow, t) < arow ? 1 : 0;
+    int kbelow = 0;  // kept A rows below this lane's inserted row
+    for (int t = 0; t < alen; ++t)
+      kbelow += ((keptmask >> t) & 1ull) && __builtin_amdgcn_readlane(arow, t) < irow ? 1 : 0;
+    if (keep) {
+      const int64_t o = cbase + __popcll(keptmask & lanemask_lt()) + below;
+      cir[o] = arow;
+      copy_value(A.num, a0 + lane, cnum, o, vb);
+    }
+    if (lane < nins) {
+      const int64_t o = cbase + lane + kbelow;
+      cir[o] = irow;
+      copy_value(B.num, b0 + (int64_t)(key & 0xffffffffu), cnum, o, vb);
+    }
   }
+}
+
+// Copy of the unmodified columns, balanced over A's entries and the
+// modified columns together.  In A's storage order, modified column u is
+// placed right after its last entry, at merged position end(u) + u with
+// end(u) = cp[mod[u] + 1]; each workgroup takes kCopyItems consecutive items
+// of that merged order.  tmod[t] = the number of modified columns placed
+// before item t * kCopyItems, so tile t holds A's entries
+// [t*T - tmod[t], (t+1)*T - tmod[t+1]) and modified columns tmod[t] ..
+// tmod[t+1] (T = kCopyItems): at most T + 1 of them, staged in LDS with
+// their entry ranges and the output shift of the run of unmodified columns
+// before each.  An entry's run is then the number of staged columns ending
+// at or before it (a binary search in LDS), and it is skipped when it lies
+// inside the next one.
+constexpr int kCopyItems = 2048;
+constexpr int kCopyThreads = 256;
+
+// tmod[t] for t = 0..nt: modified column u owns the merged positions
+// (end(u-1) + u - 1, end(u) + u], and the tile starts among them.
+__global__ void k_copy_tiles(Operand A, const int32_t* mod, int64_t nmod, int64_t nt, int64_t* tmod) {
+  for (int64_t u = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; u <= nmod; u += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t lo = u == 0 ? 0 : slot_begin(A, (int64_t)mod[u - 1] + 1) + u;
+    const int64_t hi = u == nmod ? INT64_MAX : slot_begin(A, (int64_t)mod[u] + 1) + u;
+    for (int64_t t = (lo + kCopyItems - 1) / kCopyItems; t <= nt && t * kCopyItems <= hi; ++t) tmod[t] = u;
+  }
+}
+
+int copy_tiles(const Operand& A, const int32_t* mod, int64_t nmod, Scratch& scr, hipStream_t st, int64_t** tmod,
+               int64_t* ntiles) {
+  const int64_t nt = ceil_div(A.nnz + nmod, (int64_t)kCopyItems);
+  SPX_TRY(scr.get_n(nt + 1, tmod));
+  k_copy_tiles<<<grid_for(nmod + 1, 256, 65536), 256, 0, st>>>(A, mod, nmod, nt, *tmod);
+  SPX_HIP(hipGetLastError());
+  *ntiles = nt;
   return SPX_OK;
 }
 
-__global__ void __launch_bounds__(256) k_asgn_copy(Operand A, const int64_t* tstart, const int32_t* lastJ,
-                                                   const int64_t* off, int vb, int32_t* cir, void* cnum) {
-  __shared__ int64_t s_shift[kCopyMapCols];
-  __shared__ int16_t s_col[kCopyTile];
-  const int64_t nt = (A.nnz + kCopyTile - 1) / kCopyTile;
-  for (int64_t tile = blockIdx.x; tile < nt; tile += gridDim.x) {
-    const int64_t e0 = tile * kCopyTile;
-    const int64_t e1 = e0 + kCopyTile < A.nnz ? e0 + kCopyTile : A.nnz;
-    // the tile's columns lie in [j0, j1] (j1: the next tile's first column)
-    const int64_t j0 = tstart[tile], j1 = tstart[tile + 1];
-    const bool mapped = j1 - j0 < kCopyMapCols;
-    if (mapped) {
-      for (int64_t c = j0 + threadIdx.x; c <= j1; c += blockDim.x) {
-        const int64_t s0 = slot_begin(A, c), s1 = slot_begin(A, c + 1);
-        s_shift[c - j0] = lastJ[c] >= 0 ? kCopySkip : off[c] - s0;
-        for (int64_t e = s0 > e0 ? s0 : e0; e < s1 && e < e1; ++e) s_col[e - e0] = (int16_t)(c - j0);
+template <int VB>
+__global__ void __launch_bounds__(kCopyThreads) k_asgn_copy(Operand A, const int32_t* mod, int64_t nmod,
+                                                            const int64_t* tmod, int64_t nt, const int64_t* off,
+                                                            int32_t* cir, void* cnum) {
+  using V = typename std::conditional<VB == 8, uint64_t, uint32_t>::type;
+  constexpr int kPer = kCopyItems / kCopyThreads;
+  __shared__ int32_t s_beg[kCopyItems + 1];  // staged column's entries, relative to the tile's first
+  __shared__ int32_t s_end[kCopyItems + 1];  // entry and clamped to [0, kCopyItems]
+  __shared__ int64_t s_shift[kCopyItems + 1];
+  const V* anum = static_cast<const V*>(A.num);
+  V* out = static_cast<V*>(cnum);
+  for (int64_t t = blockIdx.x; t < nt; t += gridDim.x) {
+    const int64_t us = tmod[t], ue = tmod[t + 1];
+    const int64_t es = t * kCopyItems - us;
+    const int64_t ee = std::min<int64_t>((t + 1) * kCopyItems - ue, A.nnz);
+    const int64_t nst = std::min<int64_t>(ue, nmod - 1) - us + 1;  // staged columns (may be 0)
+    for (int64_t i = threadIdx.x; i <= ue - us; i += kCopyThreads) {
+      const int64_t r = us + i;
+      const int64_t c0 = r == 0 ? 0 : (int64_t)mod[r - 1] + 1;  // the run before column r starts here
+      s_shift[i] = off[c0] - slot_begin(A, c0);
+      if (i < nst) {
+        const int64_t c = mod[r];
+        s_beg[i] = (int32_t)std::min<int64_t>(std::max<int64_t>(slot_begin(A, c) - es, 0), kCopyItems);
+        s_end[i] = (int32_t)std::min<int64_t>(std::max<int64_t>(slot_begin(A, c + 1) - es, 0), kCopyItems);
       }
-      __syncthreads();
-      for (int64_t e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
-        const int64_t sh = s_shift[s_col[e - e0]];
-        if (sh == kCopySkip) continue;
-        cir[e + sh] = A.ir[e];
-        copy_value(A.num, e, cnum, e + sh, vb);
-      }
-    } else {
-      for (int64_t e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
-        int64_t lo = j0, hi = j1;
+    }
+    __syncthreads();
+    int32_t row[kPer];
+    V val[kPer];
+    int64_t dst[kPer];
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      const int32_t x = threadIdx.x + k * kCopyThreads;
+      dst[k] = -1;
+      if (es + x < ee) {
+        int32_t lo = 0, hi = (int32_t)nst;
         while (lo < hi) {
-          const int64_t mid = (lo + hi) >> 1;
-          if (slot_begin(A, mid + 1) <= e)
+          const int32_t mid = (lo + hi) >> 1;
+          if (s_end[mid] <= x)
             lo = mid + 1;
           else
             hi = mid;
         }
-        if (lastJ[lo] >= 0) continue;
-        const int64_t o = off[lo] + (e - slot_begin(A, lo));
-        cir[o] = A.ir[e];
-        copy_value(A.num, e, cnum, o, vb);
+        if (!(lo < nst && s_beg[lo] <= x)) dst[k] = es + x + s_shift[lo];
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      if (dst[k] >= 0) {
+        const int64_t e = es + threadIdx.x + k * kCopyThreads;
+        row[k] = A.ir[e];
+        if (VB) val[k] = anum[e];
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      if (dst[k] >= 0) {
+        cir[dst[k]] = row[k];
+        if (VB) out[dst[k]] = val[k];
       }
     }
     __syncthreads();
   }
+}
+
+int launch_copy(const Operand& A, const int32_t* mod, int64_t nmod, const int64_t* tmod, int64_t nt,
+                const int64_t* off, int vb, int32_t* cir, void* cnum, hipStream_t st) {
+  if (A.nnz == 0) return SPX_OK;
+  const unsigned grid = (unsigned)std::min<int64_t>(nt, (int64_t)device_cu_count() * 16);
+  if (vb == 8)
+    k_asgn_copy<8><<<grid, kCopyThreads, 0, st>>>(A, mod, nmod, tmod, nt, off, cir, cnum);
+  else if (vb == 4)
+    k_asgn_copy<4><<<grid, kCopyThreads, 0, st>>>(A, mod, nmod, tmod, nt, off, cir, cnum);
+  else
+    k_asgn_copy<0><<<grid, kCopyThreads, 0, st>>>(A, mod, nmod, tmod, nt, off, cir, cnum);
+  SPX_HIP(hipGetLastError());
+  return SPX_OK;
 }
 
 // Merge of one modified column j (rows strictly increasing, as in A):
@@ -422,10 +549,11 @@ __device__ __forceinline__ int64_t asgn_insert_keys(const Operand& B, const int3
   return nins;
 }
 
-// Modified columns with at most CAP inserted rows: the keys are sorted in
-// LDS.  The one-wave variant (CAP = kAsgnSmall) runs over all modified
-// columns and skips larger ones, which the 256-thread variant takes from
-// `list`; it in turn skips the huge columns (k_asgn_huge_fill).
+// Modified columns with at most CAP inserted rows, taken from `list`: the
+// keys are sorted in LDS.  The one-wave variant (CAP = kAsgnSmall) serves
+// the columns whose A or B column exceeds a wave (k_asgn_mod_wave does the
+// rest); the 256-thread variant serves the big list and skips its huge
+// columns (k_asgn_huge_fill).
 template <int CAP>
 __global__ void __launch_bounds__(256) k_asgn_mod_fill(Operand A, Operand B, const int32_t* I, const int32_t* lastI,
                                                        const int32_t* lastJ, const int32_t* mod, const int32_t* list,
@@ -523,7 +651,10 @@ struct ExtAddPlan : spx_plan {
   int64_t* cnt = nullptr;    // [n]
   int64_t* off = nullptr;    // [n+1] = C.cp
   int32_t* mod = nullptr;    // [n] modified columns
-  int32_t* big = nullptr;    // modified columns (indices into mod) above kAsgnSmall landing entries
+  int32_t* rest = nullptr;   // modified columns (indices into mod) beyond k_ea_wave's reach
+  unsigned long long* nrest_d = nullptr;
+  int64_t nrest = 0;
+  int32_t* big = nullptr;    // those above kAsgnSmall landing entries
   unsigned long long* nbig_d = nullptr;
   int64_t nbig = 0;
   int64_t* hcnt = nullptr;   // [nmod] per big-list entry: landing entries of a huge column, else 0
@@ -532,7 +663,8 @@ struct ExtAddPlan : spx_plan {
   int32_t* hhead = nullptr;  // per huge column, hoff[w] + w .. : distinct-row heads
   int32_t* hnin = nullptr;   // and new-row counts
   int64_t nhuge_keys = 0;
-  int64_t* tstart = nullptr;  // first column of every copy tile of A
+  int64_t* tmod = nullptr;    // [ntiles+1] modified columns before each copy tile (k_copy_tiles)
+  int64_t ntiles = 0;
   unsigned* err = nullptr;
   unsigned long long* nmod_d = nullptr;
 };
@@ -709,12 +841,102 @@ __device__ __forceinline__ int64_t ea_landing_keys(const Operand& B, const int32
   return nins;
 }
 
+// Modified columns of extend-add whose A column and landing entries both
+// fit the 64 lanes of a wave, done in registers: lane l holds A(:,j)'s l-th
+// entry and the l-th landing key (I(p) << 32 | e), the keys sorted across
+// the wave.  The first lane of each distinct landing row finds the row among
+// A's (lane reads): its output position is A's rows below it plus the new
+// rows below it, and it sums the row's landing values in key order onto A's
+// value, or onto the first landing value for a new row.  A's entries that
+// receive nothing move down by the new rows below them.  The count pass
+// writes nnz(C(:,j)) and lists the other columns in `rest` for the LDS
+// kernels; the fill pass skips them.
+template <bool kFill, bool kVals, typename T, class Acc>
+__global__ void __launch_bounds__(256) k_ea_wave(Operand A, Operand B, const int32_t* I, const int32_t* mod,
+                                                 int64_t nmod, const int64_t* qoff, const int32_t* qlist,
+                                                 int64_t* cnt, const int64_t* off, int32_t* rest,
+                                                 unsigned long long* nrest, int32_t* cir, T* cnum) {
+  const T* anum = static_cast<const T*>(A.num);
+  const T* bnum = static_cast<const T*>(B.num);
+  const int lane = lane_id();
+  const int64_t wave = __builtin_amdgcn_readfirstlane((int)((blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kWave));
+  const int64_t nwaves = (int64_t)gridDim.x * blockDim.x / kWave;
+  for (int64_t u = wave; u < nmod; u += nwaves) {
+    const int32_t j = mod[u];
+    const int64_t a0 = slot_begin(A, j), a1 = slot_begin(A, j + 1);
+    const int64_t q0 = qoff[j], q1 = qoff[j + 1];
+    int64_t nins = 0;
+    uint64_t key = ~0ull;
+    for (int64_t t = q0; t < q1 && nins <= kWave; ++t) {  // uniform
+      const int32_t q = qlist[t];
+      const int64_t b0 = slot_begin(B, q), len = slot_begin(B, q + 1) - b0;
+      if (nins + len <= kWave && lane >= nins && lane < nins + len) {
+        const int64_t e = b0 + (lane - nins);
+        key = ((uint64_t)(uint32_t)I[B.ir[e]] << 32) | (uint32_t)e;
+      }
+      nins += len;
+    }
+    if (a1 - a0 > kWave || nins > kWave) {  // uniform: an LDS kernel's column
+      if (!kFill && lane == 0) rest[atomicAdd(nrest, 1ull)] = (int32_t)u;
+      continue;
+    }
+    const int alen = (int)(a1 - a0), nk = (int)nins;
+    const int32_t arow = lane < alen ? A.ir[a0 + lane] : 0x7fffffff;
+    key = wave_sort_u64(key);
+    const int32_t krow = (int32_t)(key >> 32);  // lane < nk: the lane-th landing row
+    const int32_t prev = __shfl(krow, lane == 0 ? 0 : lane - 1);
+    const bool head = lane < nk && (lane == 0 || prev != krow);
+    int at = 0;  // A rows below krow
+    bool found = false;
+    for (int t = 0; t < alen; ++t) {
+      const int32_t r = __builtin_amdgcn_readlane(arow, t);
+      at += r < krow ? 1 : 0;
+      found = found || r == krow;
+    }
+    const uint64_t freshmask = __ballot(head && !found);
+    if (!kFill) {
+      if (lane == 0) cnt[j] = alen + __popcll(freshmask);
+      continue;
+    }
+    const int64_t cbase = off[j];
+    // A's entries that receive no landing value
+    bool landed = false;
+    int fbelow = 0;  // new rows below arow
+    for (int t = 0; t < nk; ++t) {
+      const int32_t r = __builtin_amdgcn_readlane(krow, t);
+      landed = landed || r == arow;
+      fbelow += ((freshmask >> t) & 1ull) && r < arow ? 1 : 0;
+    }
+    if (lane < alen && !landed) {
+      const int64_t o = cbase + lane + fbelow;
+      cir[o] = arow;
+      if (kVals) cnum[o] = anum[a0 + lane];
+    }
+    // one entry per distinct landing row
+    const uint64_t headmask = __ballot(head);
+    const uint64_t after = lane == 63 ? 0ull : headmask >> (lane + 1);
+    const int glen = head ? (after ? __ffsll((unsigned long long)after) : nk - lane) : 0;
+    if (head) cir[cbase + at + __popcll(freshmask & lanemask_lt())] = krow;
+    if (kVals) {
+      const T bv = lane < nk ? bnum[(uint32_t)key] : T(0);
+      T acc = found ? anum[a0 + at] : bv;
+      int gmax = glen;
+      for (int s = 1; s < kWave; s <<= 1) gmax = max(gmax, __shfl_xor(gmax, s));
+      for (int d = 0; d < gmax; ++d) {
+        const T v = __shfl(bv, (lane + d) & (kWave - 1));
+        if (d < glen && (found || d > 0)) acc = Acc::add(acc, v);
+      }
+      if (head) cnum[cbase + at + __popcll(freshmask & lanemask_lt())] = acc;
+    }
+  }
+}
+
 // One workgroup per modified column j (grid-stride over the list) whose
 // landing entries fit CAP: they are sorted in LDS, then ea_column_body.  The
-// one-wave variant (CAP = kAsgnSmall, `list` NULL) runs over every modified
-// column; in the count pass it hands larger columns to the `big` list, which
-// the 256-thread variant (CAP = kAsgnMaxInsert) then serves (its length read
-// from *nlist_d); in its count pass that variant records, per list entry,
+// one-wave variant (CAP = kAsgnSmall) serves the rest list of k_ea_wave; in
+// the count pass it hands larger columns to the `big` list, which the
+// 256-thread variant (CAP = kAsgnMaxInsert) then serves (list lengths read
+// from *nlist_d in the count pass); in its count pass that variant records, per list entry,
 // the landing entries of a column above CAP in hcnt (0 for the others), and
 // such ("huge") columns are done by k_ea_huge.
 template <bool kFill, bool kVals, int CAP, typename T, class Acc>
@@ -780,9 +1002,10 @@ __global__ void __launch_bounds__(256) k_ea_huge(Operand A, Operand B, const int
   }
 }
 
-// One-wave variant over all modified columns, then the 256-thread variant
-// over the big list (its length is on the device in the count pass; the fill
-// pass knows it from the plan).  `huge`: the huge columns' kernel instead.
+// The register kernel over all modified columns, the one-wave LDS variant
+// over the rest list, then the 256-thread variant over the big list (list
+// lengths are on the device in the count pass; the fill pass knows them from
+// the plan).  `huge`: the huge columns' kernel instead.
 template <bool kFill, bool kVals, typename T, class Acc>
 int launch_ea(const ExtAddPlan* P, int32_t* cir, void* cnum, hipStream_t st, bool huge) {
   const int cus = device_cu_count();
@@ -796,11 +1019,17 @@ int launch_ea(const ExtAddPlan* P, int32_t* cir, void* cnum, hipStream_t st, boo
     }
     return SPX_OK;
   }
-  k_ea_column<kFill, kVals, kAsgnSmall, T, Acc><<<(unsigned)std::min<int64_t>(P->nmod, (int64_t)cus * 32), 64, 0,
-                                                  st>>>(P->A, P->B, P->I, P->mod, nullptr, nullptr, P->nmod, P->qoff,
-                                                        P->qlist, P->cnt, P->off, P->big, P->nbig_d, P->hcnt, cir,
-                                                        out);
+  k_ea_wave<kFill, kVals, T, Acc><<<(unsigned)std::min<int64_t>(ceil_div(P->nmod, (int64_t)4), (int64_t)cus * 16),
+                                     256, 0, st>>>(P->A, P->B, P->I, P->mod, P->nmod, P->qoff, P->qlist, P->cnt,
+                                                   P->off, P->rest, P->nrest_d, cir, out);
   SPX_HIP(hipGetLastError());
+  if (!kFill || P->nrest > 0) {
+    const int64_t grid = kFill ? std::min<int64_t>(P->nrest, (int64_t)cus * 32) : (int64_t)cus * 32;
+    k_ea_column<kFill, kVals, kAsgnSmall, T, Acc><<<(unsigned)grid, 64, 0, st>>>(
+        P->A, P->B, P->I, P->mod, P->rest, kFill ? nullptr : P->nrest_d, P->nrest, P->qoff, P->qlist, P->cnt,
+        P->off, P->big, P->nbig_d, P->hcnt, cir, out);
+    SPX_HIP(hipGetLastError());
+  }
   if (!kFill || P->nbig > 0) {
     const int64_t grid = kFill ? std::min<int64_t>(P->nbig, (int64_t)cus * 4) : (int64_t)cus * 4;
     k_ea_column<kFill, kVals, kAsgnMaxInsert, T, Acc><<<(unsigned)grid, 256, 0, st>>>(
@@ -883,7 +1112,6 @@ extern "C" int spx_spasgn_plan(const spx_ctx* ctx, const spx_mat* A, const int32
   SPX_TRY(scr.get_n(n + 1, &P->off));
   SPX_TRY(scr.get_n(std::max<int64_t>(n, 1), &P->mod));
   SPX_TRY(list_modified(P->A, P->lastJ, P->cnt, P->mod, P->nmod_d, scr, st));
-  SPX_TRY(tile_starts(P->A, scr, st, &P->tstart));
   unsigned long long nmod_h = 0;
   unsigned err_h = 0;
   SPX_HIP(hipMemcpyAsync(&nmod_h, P->nmod_d, 8, hipMemcpyDeviceToHost, st));
@@ -892,32 +1120,37 @@ extern "C" int spx_spasgn_plan(const spx_ctx* ctx, const spx_mat* A, const int32
   if (err_h & 1u) return fail(SPX_EINVAL, "I has an index outside [0, m)");
   if (err_h & 2u) return fail(SPX_EINVAL, "J has an index outside [0, n)");
   P->nmod = (int64_t)nmod_h;
+  SPX_TRY(copy_tiles(P->A, P->mod, P->nmod, scr, st, &P->tmod, &P->ntiles));
   SPX_TRY(scr.get_n(std::max<int64_t>(P->nmod, 1), &P->dcnt));
   SPX_TRY(scr.get_n(P->nmod + 1, &P->doff));
   SPX_TRY(scr.get_n(std::max<int64_t>(P->nmod, 1), &P->big));
   SPX_TRY(scr.get_n(std::max<int64_t>(P->nmod, 1), &P->icnt));
   SPX_TRY(scr.get_n(P->nmod + 1, &P->hoff));
-  SPX_TRY(scr.get_n(1, &P->nbig_d));
-  SPX_TRY(fill_i64((int64_t*)P->nbig_d, 1, 0, st));
+  SPX_TRY(scr.get_n(std::max<int64_t>(P->nmod, 1), &P->mid));
+  SPX_TRY(scr.get_n(2, &P->nbig_d));
+  P->nmid_d = P->nbig_d + 1;
+  SPX_TRY(fill_i64((int64_t*)P->nbig_d, 2, 0, st));
   if (P->nmod > 0) {
-    k_asgn_mod_count<<<(unsigned)std::min<int64_t>(P->nmod, (int64_t)cus * 32), 64, 0, st>>>(
-        P->A, P->B, I, P->lastI, P->lastJ, P->mod, P->nmod, P->cnt, P->dcnt, P->icnt, P->big, P->nbig_d);
+    k_asgn_mod_count<<<(unsigned)std::min<int64_t>(ceil_div(P->nmod, (int64_t)4), (int64_t)cus * 16), 256, 0, st>>>(
+        P->A, P->B, I, P->lastI, P->lastJ, P->mod, P->nmod, P->cnt, P->dcnt, P->icnt, P->big, P->nbig_d, P->mid,
+        P->nmid_d);
     SPX_HIP(hipGetLastError());
   }
   SPX_TRY(exclusive_scan(LoadI64{P->cnt}, n, P->off, scr, st));
   SPX_TRY(exclusive_scan(LoadI64{P->dcnt}, P->nmod, P->doff, scr, st));
   // key segments of the huge columns (big-list order; entries past nbig are empty)
   SPX_TRY(exclusive_scan(HugeCap{P->icnt, P->big, P->nbig_d}, P->nmod, P->hoff, scr, st));
-  int64_t tail[4] = {0, 0, 0, 0};
+  int64_t tail[5] = {0, 0, 0, 0, 0};
   SPX_HIP(hipMemcpyAsync(&tail[0], P->off + n, 8, hipMemcpyDeviceToHost, st));
   SPX_HIP(hipMemcpyAsync(&tail[1], P->doff + P->nmod, 8, hipMemcpyDeviceToHost, st));
-  SPX_HIP(hipMemcpyAsync(&tail[2], P->nbig_d, 8, hipMemcpyDeviceToHost, st));
-  SPX_HIP(hipMemcpyAsync(&tail[3], P->hoff + P->nmod, 8, hipMemcpyDeviceToHost, st));
+  SPX_HIP(hipMemcpyAsync(&tail[2], P->nbig_d, 16, hipMemcpyDeviceToHost, st));
+  SPX_HIP(hipMemcpyAsync(&tail[4], P->hoff + P->nmod, 8, hipMemcpyDeviceToHost, st));
   SPX_HIP(hipStreamSynchronize(st));
   P->nnz = tail[0];
   P->ndrop = tail[1];
   P->nbig = tail[2];
-  P->nhuge_keys = tail[3];
+  P->nmid = tail[3];
+  P->nhuge_keys = tail[4];
   SPX_TRY(scr.get_n(std::max<int64_t>(P->ndrop, 1), &P->drows));
   if (P->nhuge_keys > 0) {
     SPX_TRY(scr.get_n(P->nhuge_keys, &P->hkeys));
@@ -944,15 +1177,15 @@ extern "C" int spx_spasgn_exec(spx_plan* plan, spx_mat* C) {
   hipStream_t st = stream_of(&P->ctx);
   const int vb = value_size(P->A.val_t);
   const int cus = device_cu_count();
-  if (P->A.nnz > 0) {
-    const int64_t tiles = ceil_div(P->A.nnz, kCopyTile);
-    k_asgn_copy<<<(unsigned)std::min<int64_t>(tiles, (int64_t)cus * 8), 256, 0, st>>>(P->A, P->tstart, P->lastJ,
-                                                                                       P->off, vb, C->ir, C->num);
+  SPX_TRY(launch_copy(P->A, P->mod, P->nmod, P->tmod, P->ntiles, P->off, vb, C->ir, C->num, st));
+  if (P->nmod > 0) {
+    k_asgn_mod_wave<<<(unsigned)std::min<int64_t>(ceil_div(P->nmod, (int64_t)4), (int64_t)cus * 16), 256, 0, st>>>(
+        P->A, P->B, P->I, P->lastI, P->lastJ, P->mod, P->nmod, P->off, vb, C->ir, C->num);
     SPX_HIP(hipGetLastError());
   }
-  if (P->nmod > 0) {
-    k_asgn_mod_fill<kAsgnSmall><<<(unsigned)std::min<int64_t>(P->nmod, (int64_t)cus * 32), 64, 0, st>>>(
-        P->A, P->B, P->I, P->lastI, P->lastJ, P->mod, nullptr, P->nmod, P->icnt, P->off, P->doff, P->drows, vb,
+  if (P->nmid > 0) {
+    k_asgn_mod_fill<kAsgnSmall><<<(unsigned)std::min<int64_t>(P->nmid, (int64_t)cus * 32), 64, 0, st>>>(
+        P->A, P->B, P->I, P->lastI, P->lastJ, P->mod, P->mid, P->nmid, P->icnt, P->off, P->doff, P->drows, vb,
         C->ir, C->num);
     SPX_HIP(hipGetLastError());
   }
@@ -1028,7 +1261,6 @@ extern "C" int spx_extend_add_plan(const spx_ctx* ctx, const spx_mat* A, const i
   SPX_TRY(scr.get_n(n + 1, &P->off));
   SPX_TRY(scr.get_n(std::max<int64_t>(n, 1), &P->mod));
   SPX_TRY(list_modified(P->A, P->lastJ, P->cnt, P->mod, P->nmod_d, scr, st));
-  SPX_TRY(tile_starts(P->A, scr, st, &P->tstart));
   unsigned long long nmod_h = 0;
   unsigned err_h = 0;
   SPX_HIP(hipMemcpyAsync(&nmod_h, P->nmod_d, 8, hipMemcpyDeviceToHost, st));
@@ -1037,6 +1269,7 @@ extern "C" int spx_extend_add_plan(const spx_ctx* ctx, const spx_mat* A, const i
   if (err_h & 1u) return fail(SPX_EINVAL, "I has an index outside [0, m)");
   if (err_h & 2u) return fail(SPX_EINVAL, "J has an index outside [0, n)");
   P->nmod = (int64_t)nmod_h;
+  SPX_TRY(copy_tiles(P->A, P->mod, P->nmod, scr, st, &P->tmod, &P->ntiles));
   SPX_TRY(scr.get_n(n + 1, &P->qoff));
   SPX_TRY(scr.get_n(std::max<int64_t>(lenJ, 1), &P->qlist));
   SPX_TRY(exclusive_scan(LoadI32{P->qcnt}, n, P->qoff, scr, st));
@@ -1047,18 +1280,21 @@ extern "C" int spx_extend_add_plan(const spx_ctx* ctx, const spx_mat* A, const i
   SPX_TRY(scr.get_n(std::max<int64_t>(P->nmod, 1), &P->big));
   SPX_TRY(scr.get_n(std::max<int64_t>(P->nmod, 1), &P->hcnt));
   SPX_TRY(scr.get_n(P->nmod + 1, &P->hoff));
-  SPX_TRY(scr.get_n(1, &P->nbig_d));
-  SPX_TRY(fill_i64((int64_t*)P->nbig_d, 1, 0, st));
+  SPX_TRY(scr.get_n(std::max<int64_t>(P->nmod, 1), &P->rest));
+  SPX_TRY(scr.get_n(2, &P->nbig_d));
+  P->nrest_d = P->nbig_d + 1;
+  SPX_TRY(fill_i64((int64_t*)P->nbig_d, 2, 0, st));
   if (P->nmod > 0) SPX_TRY(dispatch_ea<false>(P, nullptr, nullptr, st, false));
   // key segments of the huge columns (big-list order; entries past nbig are empty)
   SPX_TRY(exclusive_scan(HugeCap{P->hcnt, nullptr, P->nbig_d}, P->nmod, P->hoff, scr, st));
   {
-    int64_t h[2] = {0, 0};
-    SPX_HIP(hipMemcpyAsync(&h[0], P->nbig_d, 8, hipMemcpyDeviceToHost, st));
-    SPX_HIP(hipMemcpyAsync(&h[1], P->hoff + P->nmod, 8, hipMemcpyDeviceToHost, st));
+    int64_t h[3] = {0, 0, 0};
+    SPX_HIP(hipMemcpyAsync(&h[0], P->nbig_d, 16, hipMemcpyDeviceToHost, st));
+    SPX_HIP(hipMemcpyAsync(&h[2], P->hoff + P->nmod, 8, hipMemcpyDeviceToHost, st));
     SPX_HIP(hipStreamSynchronize(st));
     P->nbig = h[0];
-    P->nhuge_keys = h[1];
+    P->nrest = h[1];
+    P->nhuge_keys = h[2];
   }
   if (P->nhuge_keys > 0) {
     if (P->nhuge_keys >= (1ll << 31)) return fail(SPX_EUNSUPPORTED, "landing entries of the large columns exceed 2^31");
@@ -1094,13 +1330,7 @@ extern "C" int spx_extend_add_exec(spx_plan* plan, spx_mat* C) {
   C->nzc = 0;
   hipStream_t st = stream_of(&P->ctx);
   const int vb = value_size(P->A.val_t);
-  const int cus = device_cu_count();
-  if (P->A.nnz > 0) {
-    const int64_t tiles = ceil_div(P->A.nnz, kCopyTile);
-    k_asgn_copy<<<(unsigned)std::min<int64_t>(tiles, (int64_t)cus * 8), 256, 0, st>>>(P->A, P->tstart, P->lastJ,
-                                                                                       P->off, vb, C->ir, C->num);
-    SPX_HIP(hipGetLastError());
-  }
+  SPX_TRY(launch_copy(P->A, P->mod, P->nmod, P->tmod, P->ntiles, P->off, vb, C->ir, C->num, st));
   if (P->nmod > 0) {
     SPX_TRY(dispatch_ea<true>(P, C->ir, C->num, st, false));
     SPX_TRY(dispatch_ea<true>(P, C->ir, C->num, st, true));

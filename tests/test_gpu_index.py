@@ -342,3 +342,30 @@ def test_extend_add_errors(spx):
 def test_config3_extend_add_full(spx, config3):
     A, I, J, Bp = config3
     extend_add_check(spx, A, I, J, Bp)
+
+
+@pytest.mark.parametrize("kind,semiring", [("f32", "plus_times"), ("f64", "min_plus"), ("i64", "plus_times"),
+                                           ("none", "or_and")])
+def test_register_path_limits(spx, kind, semiring):
+    # A columns of 63, 64 and 65 entries and 63, 64 or 65 incoming B entries,
+    # one column fed by two B columns (32 + 32) and one by two (10 + 55), with
+    # repeated target rows: the register kernels take exactly the columns
+    # whose A column and incoming entries fit a wave, the others go to the
+    # LDS kernels, and both agree with the oracle bit for bit
+    rng = np.random.default_rng(71)
+    m = 400
+    alens = [63, 64, 65, 64, 0, 64, 30, 5]
+    arows = [np.sort(rng.choice(m, k, replace=False)) for k in alens]
+    A = W.from_triples(np.concatenate(arows), np.repeat(np.arange(len(alens)), alens),
+                       np.arange(sum(alens), dtype=np.int64), m, len(alens))
+    A = with_values(A, kind, rng)
+    I = rng.integers(0, m, size=200).astype(np.int32)  # repeated rows
+    J = np.array([0, 1, 2, 3, 4, 5, 6, 5, 6], dtype=np.int32)
+    blens = [64, 64, 63, 65, 64, 32, 10, 32, 55]
+    brows = [np.sort(rng.choice(200, k, replace=False)) for k in blens]
+    B = W.from_triples(np.concatenate(brows), np.repeat(np.arange(len(blens)), blens),
+                       np.arange(sum(blens), dtype=np.int64), 200, len(blens))
+    B = with_values(B, kind, rng)
+    extend_add_check(spx, A, I, J, B, semiring)
+    if kind != "none":
+        spasgn_check(spx, A, I, J, B)
