@@ -163,19 +163,19 @@ struct SpasgnPlan : spx_plan {
   int32_t* mod = nullptr;    // [n] modified columns
   int64_t* dcnt = nullptr;   // [nmod] dropped entries per modified column
   int64_t* doff = nullptr;   // [nmod+1]
-  int32_t* drows = nullptr;  // [ndrop] rows of the dropped entries
-  int32_t* big = nullptr;    // modified columns (indices into mod) above kAsgnSmall inserts
+  int32_t* drows = nullptr;  // [ndrop] rows of the dropped entries, ascending per column
+  int64_t* icnt = nullptr;   // [nmod] inserted entries per modified column
+  int64_t* kbase = nullptr;  // [nmod] start of the column's B column (its keys sit at ikeys[kbase ..])
+  uint64_t* ikeys = nullptr; // [nnz(B)] sorted (row, position in B's column) keys of the inserted entries
+  int32_t* big = nullptr;    // modified columns (indices into mod) whose B column exceeds a wave
   unsigned long long* nbig_d = nullptr;
   int64_t nbig = 0;
-  int32_t* mid = nullptr;    // the others whose A or B column exceeds one wave
-  unsigned long long* nmid_d = nullptr;
-  int64_t nmid = 0;
-  int64_t* icnt = nullptr;   // [nmod] inserted entries per modified column
   int64_t* hoff = nullptr;   // [nbig+1] key segment of each big column (0 length unless huge)
-  uint64_t* hkeys = nullptr; // sorted (row, position in B's column) keys of the huge columns
+  uint64_t* hkeys = nullptr; // huge columns' padded key segments, sorted in place
   int64_t nhuge_keys = 0;
-  int64_t* tmod = nullptr;    // [ntiles+1] modified columns before each copy tile (k_copy_tiles)
+  int64_t* tmod = nullptr;    // [ntiles+1] modified columns before each tile (k_copy_tiles)
   int64_t ntiles = 0;
+  int64_t* lastseg = nullptr; // [ntiles] dropped entries of each tile's last column
   unsigned* err = nullptr;
   unsigned long long* nmod_d = nullptr;
 };
@@ -224,47 +224,6 @@ int list_modified(const Operand& A, const int32_t* lastJ, int64_t* cnt, int32_t*
   return SPX_OK;
 }
 
-// Per modified column: kept A entries, dropped ones, inserted B entries.
-// One wave per column; the counts are ballot popcounts (no LDS, no barrier).
-__global__ void __launch_bounds__(256) k_asgn_mod_count(Operand A, Operand B, const int32_t* I, const int32_t* lastI,
-                                                        const int32_t* lastJ, const int32_t* mod, int64_t nmod,
-                                                        int64_t* cnt, int64_t* dcnt, int64_t* icnt, int32_t* big,
-                                                        unsigned long long* nbig, int32_t* mid,
-                                                        unsigned long long* nmid) {
-  const int lane = lane_id();
-  const int64_t wave = __builtin_amdgcn_readfirstlane((int)((blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kWave));
-  const int64_t nwaves = (int64_t)gridDim.x * blockDim.x / kWave;
-  for (int64_t u = wave; u < nmod; u += nwaves) {
-    const int32_t j = mod[u];
-    const int64_t a0 = slot_begin(A, j), a1 = slot_begin(A, j + 1);
-    const int32_t q = lastJ[j];
-    const int64_t b0 = slot_begin(B, q), b1 = slot_begin(B, q + 1);
-    int64_t kept = 0, ins = 0;
-    for (int64_t ec = a0; ec < a1; ec += kWave) {
-      const int64_t e = ec + lane;
-      kept += __popcll(__ballot(e < a1 && lastI[A.ir[e]] < 0));
-    }
-    for (int64_t ec = b0; ec < b1; ec += kWave) {
-      const int64_t e = ec + lane;
-      bool take = false;
-      if (e < b1) {
-        const int32_t p = B.ir[e];
-        take = lastI[I[p]] == p;
-      }
-      ins += __popcll(__ballot(take));
-    }
-    if (lane == 0) {
-      cnt[j] = kept + ins;
-      dcnt[u] = (a1 - a0) - kept;
-      icnt[u] = ins;
-      if (ins > kAsgnSmall)
-        big[atomicAdd(nbig, 1ull)] = (int32_t)u;
-      else if (a1 - a0 > kWave || b1 - b0 > kWave)
-        mid[atomicAdd(nmid, 1ull)] = (int32_t)u;
-    }
-  }
-}
-
 // Ascending bitonic sort of one 64-bit key per lane over the whole wave
 // (every lane active), by lane exchanges.
 __device__ __forceinline__ uint64_t wave_sort_u64(uint64_t key) {
@@ -282,245 +241,40 @@ __device__ __forceinline__ uint64_t wave_sort_u64(uint64_t key) {
   return key;
 }
 
-// Modified columns whose A column and B column both fit the 64 lanes of a
-// wave, done in registers: lane l holds A(:,j)'s l-th entry (kept if its row
-// is not in I) and B(:,q)'s l-th entry (inserted at row I(p) if p is that
-// row's last occurrence); the inserted keys (row, lane) are sorted across
-// the wave.  A kept entry goes to its kept rank plus the inserted rows below
-// it, an inserted one to its rank plus the kept rows below it (counted by
-// reading the other list lane by lane).  The LDS kernels skip these columns.
-__global__ void __launch_bounds__(256) k_asgn_mod_wave(Operand A, Operand B, const int32_t* I, const int32_t* lastI,
-                                                       const int32_t* lastJ, const int32_t* mod, int64_t nmod,
-                                                       const int64_t* off, int vb, int32_t* cir, void* cnum) {
-  const int lane = lane_id();
-  const int64_t wave = __builtin_amdgcn_readfirstlane((int)((blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kWave));
-  const int64_t nwaves = (int64_t)gridDim.x * blockDim.x / kWave;
-  for (int64_t u = wave; u < nmod; u += nwaves) {
-    const int32_t j = mod[u];
-    const int64_t a0 = slot_begin(A, j), a1 = slot_begin(A, j + 1);
-    const int32_t q = lastJ[j];
-    const int64_t b0 = slot_begin(B, q), b1 = slot_begin(B, q + 1);
-    if (a1 - a0 > kWave || b1 - b0 > kWave) continue;  // uniform: an LDS kernel's column
-    const int alen = (int)(a1 - a0), blen = (int)(b1 - b0);
-    const int64_t cbase = off[j];
-    int32_t arow = 0x7fffffff;
-    bool keep = false;
-    if (lane < alen) {
-      arow = A.ir[a0 + lane];
-      keep = lastI[arow] < 0;
-    }
-    uint64_t key = ~0ull;
-    if (lane < blen) {
-      const int32_t p = B.ir[b0 + lane];
-      const int32_t row = I[p];
-      if (lastI[row] == p) key = ((uint64_t)(uint32_t)row << 32) | (uint32_t)lane;
-    }
-    const uint64_t keptmask = __ballot(keep);
-    const int nins = __popcll(__ballot(key != ~0ull));
-    key = wave_sort_u64(key);
-    const int32_t irow = (int32_t)(key >> 32);  // lane k < nins: the k-th inserted row
-    int below = 0;   // inserted rows below this lane's A row
-    for (int t = 0; t < nins; ++t) below += __builtin_amdgcn_readlane(irow, t) < arow ? 1 : 0;
-    int kbelow = 0;  // kept A rows below this lane's inserted row
-    for (int t = 0; t < alen; ++t)
-      kbelow += ((keptmask >> t) & 1ull) && __builtin_amdgcn_readlane(arow, t) < irow ? 1 : 0;
-    if (keep) {
-      const int64_t o = cbase + __popcll(keptmask & lanemask_lt()) + below;
-      cir[o] = arow;
-      copy_value(A.num, a0 + lane, cnum, o, vb);
-    }
-    if (lane < nins) {
-      const int64_t o = cbase + lane + kbelow;
-      cir[o] = irow;
-      copy_value(B.num, b0 + (int64_t)(key & 0xffffffffu), cnum, o, vb);
-    }
-  }
-}
-
-// Copy of the unmodified columns, balanced over A's entries and the
-// modified columns together.  In A's storage order, modified column u is
-// placed right after its last entry, at merged position end(u) + u with
-// end(u) = cp[mod[u] + 1]; each workgroup takes kCopyItems consecutive items
-// of that merged order.  tmod[t] = the number of modified columns placed
-// before item t * kCopyItems, so tile t holds A's entries
-// [t*T - tmod[t], (t+1)*T - tmod[t+1]) and modified columns tmod[t] ..
-// tmod[t+1] (T = kCopyItems): at most T + 1 of them, staged in LDS with
-// their entry ranges and the output shift of the run of unmodified columns
-// before each.  An entry's run is then the number of staged columns ending
-// at or before it (a binary search in LDS), and it is skipped when it lies
-// inside the next one.
-constexpr int kCopyItems = 2048;
-constexpr int kCopyThreads = 256;
-
-// tmod[t] for t = 0..nt: modified column u owns the merged positions
-// (end(u-1) + u - 1, end(u) + u], and the tile starts among them.
-__global__ void k_copy_tiles(Operand A, const int32_t* mod, int64_t nmod, int64_t nt, int64_t* tmod) {
-  for (int64_t u = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; u <= nmod; u += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t lo = u == 0 ? 0 : slot_begin(A, (int64_t)mod[u - 1] + 1) + u;
-    const int64_t hi = u == nmod ? INT64_MAX : slot_begin(A, (int64_t)mod[u] + 1) + u;
-    for (int64_t t = (lo + kCopyItems - 1) / kCopyItems; t <= nt && t * kCopyItems <= hi; ++t) tmod[t] = u;
-  }
-}
-
-int copy_tiles(const Operand& A, const int32_t* mod, int64_t nmod, Scratch& scr, hipStream_t st, int64_t** tmod,
-               int64_t* ntiles) {
-  const int64_t nt = ceil_div(A.nnz + nmod, (int64_t)kCopyItems);
-  SPX_TRY(scr.get_n(nt + 1, tmod));
-  k_copy_tiles<<<grid_for(nmod + 1, 256, 65536), 256, 0, st>>>(A, mod, nmod, nt, *tmod);
-  SPX_HIP(hipGetLastError());
-  *ntiles = nt;
-  return SPX_OK;
-}
-
-template <int VB>
-__global__ void __launch_bounds__(kCopyThreads) k_asgn_copy(Operand A, const int32_t* mod, int64_t nmod,
-                                                            const int64_t* tmod, int64_t nt, const int64_t* off,
-                                                            int32_t* cir, void* cnum) {
-  using V = typename std::conditional<VB == 8, uint64_t, uint32_t>::type;
-  constexpr int kPer = kCopyItems / kCopyThreads;
-  __shared__ int32_t s_beg[kCopyItems + 1];  // staged column's entries, relative to the tile's first
-  __shared__ int32_t s_end[kCopyItems + 1];  // entry and clamped to [0, kCopyItems]
-  __shared__ int64_t s_shift[kCopyItems + 1];
-  const V* anum = static_cast<const V*>(A.num);
-  V* out = static_cast<V*>(cnum);
-  for (int64_t t = blockIdx.x; t < nt; t += gridDim.x) {
-    const int64_t us = tmod[t], ue = tmod[t + 1];
-    const int64_t es = t * kCopyItems - us;
-    const int64_t ee = std::min<int64_t>((t + 1) * kCopyItems - ue, A.nnz);
-    const int64_t nst = std::min<int64_t>(ue, nmod - 1) - us + 1;  // staged columns (may be 0)
-    for (int64_t i = threadIdx.x; i <= ue - us; i += kCopyThreads) {
-      const int64_t r = us + i;
-      const int64_t c0 = r == 0 ? 0 : (int64_t)mod[r - 1] + 1;  // the run before column r starts here
-      s_shift[i] = off[c0] - slot_begin(A, c0);
-      if (i < nst) {
-        const int64_t c = mod[r];
-        s_beg[i] = (int32_t)std::min<int64_t>(std::max<int64_t>(slot_begin(A, c) - es, 0), kCopyItems);
-        s_end[i] = (int32_t)std::min<int64_t>(std::max<int64_t>(slot_begin(A, c + 1) - es, 0), kCopyItems);
-      }
-    }
-    __syncthreads();
-    int32_t row[kPer];
-    V val[kPer];
-    int64_t dst[kPer];
-#pragma unroll
-    for (int k = 0; k < kPer; ++k) {
-      const int32_t x = threadIdx.x + k * kCopyThreads;
-      dst[k] = -1;
-      if (es + x < ee) {
-        int32_t lo = 0, hi = (int32_t)nst;
-        while (lo < hi) {
-          const int32_t mid = (lo + hi) >> 1;
-          if (s_end[mid] <= x)
-            lo = mid + 1;
-          else
-            hi = mid;
+// Ascending bitonic sort of s[0, n) in LDS (n <= kAsgnMaxInsert), padded with ~0.
+__device__ __forceinline__ void lds_sort_keys(uint64_t* s, int n) {
+  int p2 = 1;
+  while (p2 < n) p2 <<= 1;
+  for (int t = n + threadIdx.x; t < p2; t += blockDim.x) s[t] = ~0ull;
+  __syncthreads();
+  for (int k = 2; k <= p2; k <<= 1) {
+    for (int jj = k >> 1; jj > 0; jj >>= 1) {
+      for (int t = threadIdx.x; t < (p2 >> 1); t += blockDim.x) {
+        const int lo = 2 * t - (t & (jj - 1));
+        const int hi = lo + jj;
+        const bool asc = (lo & k) == 0;
+        const uint64_t x = s[lo], y = s[hi];
+        if ((x > y) == asc) {
+          s[lo] = y;
+          s[hi] = x;
         }
-        if (!(lo < nst && s_beg[lo] <= x)) dst[k] = es + x + s_shift[lo];
       }
+      __syncthreads();
     }
-#pragma unroll
-    for (int k = 0; k < kPer; ++k) {
-      if (dst[k] >= 0) {
-        const int64_t e = es + threadIdx.x + k * kCopyThreads;
-        row[k] = A.ir[e];
-        if (VB) val[k] = anum[e];
-      }
-    }
-#pragma unroll
-    for (int k = 0; k < kPer; ++k) {
-      if (dst[k] >= 0) {
-        cir[dst[k]] = row[k];
-        if (VB) out[dst[k]] = val[k];
-      }
-    }
-    __syncthreads();
   }
 }
 
-int launch_copy(const Operand& A, const int32_t* mod, int64_t nmod, const int64_t* tmod, int64_t nt,
-                const int64_t* off, int vb, int32_t* cir, void* cnum, hipStream_t st) {
-  if (A.nnz == 0) return SPX_OK;
-  const unsigned grid = (unsigned)std::min<int64_t>(nt, (int64_t)device_cu_count() * 16);
-  if (vb == 8)
-    k_asgn_copy<8><<<grid, kCopyThreads, 0, st>>>(A, mod, nmod, tmod, nt, off, cir, cnum);
-  else if (vb == 4)
-    k_asgn_copy<4><<<grid, kCopyThreads, 0, st>>>(A, mod, nmod, tmod, nt, off, cir, cnum);
-  else
-    k_asgn_copy<0><<<grid, kCopyThreads, 0, st>>>(A, mod, nmod, tmod, nt, off, cir, cnum);
-  SPX_HIP(hipGetLastError());
-  return SPX_OK;
-}
-
-// Merge of one modified column j (rows strictly increasing, as in A):
-// the kept A entries (rows not in I) and the inserted entries, given as
-// keys (row << 32 | position in B(:,q)) sorted by row in `keys` (LDS or
-// global).  A kept entry's output position is its kept rank plus the
-// inserted rows below it; an inserted entry's is its rank plus the kept
-// rows below it (A's rows below minus the dropped ones, which are listed).
-// Called by the whole workgroup.
-template <class KeyPtr>
-__device__ __forceinline__ void asgn_merge_column(const Operand& A, const Operand& B, const int32_t* lastI, int32_t j,
-                                                  int64_t b0, int64_t cbase, int64_t dbase, KeyPtr keys, int64_t nins,
-                                                  int64_t* red, int32_t* drows, int vb, int32_t* cir, void* cnum) {
-  const int64_t a0 = slot_begin(A, j), a1 = slot_begin(A, j + 1);
-  int64_t kept_run = 0, drop_run = 0;
-  for (int64_t ec = a0; ec < a1; ec += blockDim.x) {
-    const int64_t e = ec + threadIdx.x;
-    int64_t keep = 0, drop = 0;
-    int32_t row = 0;
-    if (e < a1) {
-      row = A.ir[e];
-      keep = lastI[row] < 0;
-      drop = !keep;
-    }
-    int64_t tk, td;
-    const int64_t xk = block_excl_scan(keep, red, &tk);
-    const int64_t xd = block_excl_scan(drop, red, &td);
-    if (keep) {
-      int64_t lo = 0, hi = nins;  // inserted rows < row
-      while (lo < hi) {
-        const int64_t mid = (lo + hi) >> 1;
-        if ((int32_t)(keys[mid] >> 32) < row)
-          lo = mid + 1;
-        else
-          hi = mid;
-      }
-      const int64_t o = cbase + kept_run + xk + lo;
-      cir[o] = row;
-      copy_value(A.num, e, cnum, o, vb);
-    }
-    if (drop) drows[dbase + drop_run + xd] = row;
-    kept_run += tk;
-    drop_run += td;
+// Number of rows < row in the sorted column col[0, len).
+__device__ __forceinline__ int64_t rows_below(const int32_t* col, int64_t len, int32_t row) {
+  int64_t lo = 0, hi = len;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (col[mid] < row)
+      lo = mid + 1;
+    else
+      hi = mid;
   }
-  __threadfence_block();
-  __syncthreads();
-  const int32_t* acol = A.ir + a0;
-  const int32_t alen = (int32_t)(a1 - a0);
-  for (int64_t s = threadIdx.x; s < nins; s += blockDim.x) {
-    const uint64_t key = keys[s];
-    const int32_t row = (int32_t)(key >> 32);
-    int32_t lo = 0, hi = alen;  // A rows < row
-    while (lo < hi) {
-      const int32_t mid = (lo + hi) >> 1;
-      if (acol[mid] < row)
-        lo = mid + 1;
-      else
-        hi = mid;
-    }
-    int64_t dlo = 0, dhi = drop_run;  // dropped rows < row
-    while (dlo < dhi) {
-      const int64_t mid = (dlo + dhi) >> 1;
-      if (drows[dbase + mid] < row)
-        dlo = mid + 1;
-      else
-        dhi = mid;
-    }
-    const int64_t o = cbase + s + (lo - dlo);
-    cir[o] = row;
-    copy_value(B.num, b0 + (int64_t)(key & 0xffffffffu), cnum, o, vb);
-  }
-  __syncthreads();
+  return lo;
 }
 
 // Keys (row << 32 | position in B(:,q)) of a modified column's inserted
@@ -549,56 +303,272 @@ __device__ __forceinline__ int64_t asgn_insert_keys(const Operand& B, const int3
   return nins;
 }
 
-// Modified columns with at most CAP inserted rows, taken from `list`: the
-// keys are sorted in LDS.  The one-wave variant (CAP = kAsgnSmall) serves
-// the columns whose A or B column exceeds a wave (k_asgn_mod_wave does the
-// rest); the 256-thread variant serves the big list and skips its huge
-// columns (k_asgn_huge_fill).
-template <int CAP>
-__global__ void __launch_bounds__(256) k_asgn_mod_fill(Operand A, Operand B, const int32_t* I, const int32_t* lastI,
-                                                       const int32_t* lastJ, const int32_t* mod, const int32_t* list,
-                                                       int64_t nlist, const int64_t* icnt, const int64_t* off,
-                                                       const int64_t* doff, int32_t* drows, int vb, int32_t* cir,
-                                                       void* cnum) {
-  __shared__ uint64_t s_key[CAP];
-  __shared__ int64_t red[256 / kWave + 1];
-  for (int64_t w = blockIdx.x; w < nlist; w += gridDim.x) {
-    const int64_t u = list ? list[w] : w;
-    if (icnt[u] > CAP) continue;  // uniform: a column of the other variant
+// --------------------------------------------------- merged-order tiles of A
+// A's entries and the modified columns are processed together in one
+// balanced order.  In A's storage order, modified column u is placed right
+// after its last entry, at merged position end(u) + u with
+// end(u) = cp[mod[u] + 1]; each workgroup takes kTileItems consecutive items
+// of that merged order.  tmod[t] = the number of modified columns placed
+// before item t * kTileItems, so tile t holds A's entries
+// [t*T - tmod[t], (t+1)*T - tmod[t+1]) and meets modified columns tmod[t] ..
+// tmod[t+1] (T = kTileItems): at most T + 1 of them, staged in LDS with
+// their entry ranges relative to the tile.  An entry's staged index is the
+// number of staged columns ending at or before it (a binary search in LDS):
+// the entry lies inside that column when the column begins at or before
+// it, else in the run of unmodified columns before it.
+constexpr int kTileItems = 1024;
+constexpr int kTileThreads = 256;
+constexpr int kTilePer = kTileItems / kTileThreads;
+
+// tmod[t] for t = 0..nt: modified column u owns the merged positions
+// (end(u-1) + u - 1, end(u) + u], and the tile starts among them.
+__global__ void k_copy_tiles(Operand A, const int32_t* mod, int64_t nmod, int64_t nt, int64_t* tmod) {
+  for (int64_t u = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; u <= nmod; u += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t lo = u == 0 ? 0 : slot_begin(A, (int64_t)mod[u - 1] + 1) + u;
+    const int64_t hi = u == nmod ? INT64_MAX : slot_begin(A, (int64_t)mod[u] + 1) + u;
+    for (int64_t t = (lo + kTileItems - 1) / kTileItems; t <= nt && t * kTileItems <= hi; ++t) tmod[t] = u;
+  }
+}
+
+int copy_tiles(const Operand& A, const int32_t* mod, int64_t nmod, Scratch& scr, hipStream_t st, int64_t** tmod,
+               int64_t* ntiles) {
+  const int64_t nt = ceil_div(A.nnz + nmod, (int64_t)kTileItems);
+  SPX_TRY(scr.get_n(nt + 1, tmod));
+  k_copy_tiles<<<grid_for(nmod + 1, 256, 65536), 256, 0, st>>>(A, mod, nmod, nt, *tmod);
+  SPX_HIP(hipGetLastError());
+  *ntiles = nt;
+  return SPX_OK;
+}
+
+struct TileSpan {
+  int64_t us, ue;  // modified columns tmod[t] .. tmod[t+1]
+  int64_t es, ee;  // A's entries [es, ee)
+  int32_t nst;     // staged columns us .. us + nst - 1 (those below nmod)
+};
+
+__device__ __forceinline__ TileSpan tile_span(const Operand& A, int64_t nmod, const int64_t* tmod, int64_t t) {
+  TileSpan s;
+  s.us = tmod[t];
+  s.ue = tmod[t + 1];
+  s.es = t * kTileItems - s.us;
+  s.ee = std::min<int64_t>((t + 1) * kTileItems - s.ue, A.nnz);
+  s.nst = (int32_t)(std::min<int64_t>(s.ue, nmod - 1) - s.us + 1);
+  return s;
+}
+
+// Entry position relative to the tile, clamped to [0, kTileItems] (which
+// keeps every comparison with an in-tile position).
+__device__ __forceinline__ int32_t tile_rel(int64_t pos, int64_t es) {
+  return (int32_t)std::min<int64_t>(std::max<int64_t>(pos - es, 0), kTileItems);
+}
+
+// Staged columns ending at or before in-tile position x.
+__device__ __forceinline__ int32_t staged_rank(const int32_t* s_end, int32_t nst, int32_t x) {
+  int32_t lo = 0, hi = nst;
+  while (lo < hi) {
+    const int32_t mid = (lo + hi) >> 1;
+    if (s_end[mid] <= x)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+// Extend-add's copy of the unmodified columns: an entry in the run before
+// staged column i moves by that run's output shift off[c0] - cp[c0].
+template <int VB>
+__global__ void __launch_bounds__(kTileThreads) k_asgn_copy(Operand A, const int32_t* mod, int64_t nmod,
+                                                            const int64_t* tmod, int64_t nt, const int64_t* off,
+                                                            int32_t* cir, void* cnum) {
+  using V = typename std::conditional<VB == 8, uint64_t, uint32_t>::type;
+  __shared__ int32_t s_beg[kTileItems + 1];
+  __shared__ int32_t s_end[kTileItems + 1];
+  __shared__ int64_t s_shift[kTileItems + 1];
+  const V* anum = static_cast<const V*>(A.num);
+  V* out = static_cast<V*>(cnum);
+  for (int64_t t = blockIdx.x; t < nt; t += gridDim.x) {
+    const TileSpan sp = tile_span(A, nmod, tmod, t);
+    for (int64_t i = threadIdx.x; i <= sp.ue - sp.us; i += kTileThreads) {
+      const int64_t r = sp.us + i;
+      const int64_t c0 = r == 0 ? 0 : (int64_t)mod[r - 1] + 1;  // the run before column r starts here
+      s_shift[i] = off[c0] - slot_begin(A, c0);
+      if (i < sp.nst) {
+        const int64_t c = mod[r];
+        s_beg[i] = tile_rel(slot_begin(A, c), sp.es);
+        s_end[i] = tile_rel(slot_begin(A, c + 1), sp.es);
+      }
+    }
+    __syncthreads();
+    int32_t row[kTilePer];
+    V val[kTilePer];
+    int64_t dst[kTilePer];
+#pragma unroll
+    for (int k = 0; k < kTilePer; ++k) {
+      const int32_t x = threadIdx.x + k * kTileThreads;
+      dst[k] = -1;
+      if (sp.es + x < sp.ee) {
+        const int32_t lo = staged_rank(s_end, sp.nst, x);
+        if (!(lo < sp.nst && s_beg[lo] <= x)) dst[k] = sp.es + x + s_shift[lo];
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < kTilePer; ++k) {
+      if (dst[k] >= 0) {
+        const int64_t e = sp.es + threadIdx.x + k * kTileThreads;
+        row[k] = A.ir[e];
+        if (VB) val[k] = anum[e];
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < kTilePer; ++k) {
+      if (dst[k] >= 0) {
+        cir[dst[k]] = row[k];
+        if (VB) out[dst[k]] = val[k];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+int launch_copy(const Operand& A, const int32_t* mod, int64_t nmod, const int64_t* tmod, int64_t nt,
+                const int64_t* off, int vb, int32_t* cir, void* cnum, hipStream_t st) {
+  if (A.nnz == 0) return SPX_OK;
+  const unsigned grid = (unsigned)std::min<int64_t>(nt, (int64_t)device_cu_count() * 32);
+  if (vb == 8)
+    k_asgn_copy<8><<<grid, kTileThreads, 0, st>>>(A, mod, nmod, tmod, nt, off, cir, cnum);
+  else if (vb == 4)
+    k_asgn_copy<4><<<grid, kTileThreads, 0, st>>>(A, mod, nmod, tmod, nt, off, cir, cnum);
+  else
+    k_asgn_copy<0><<<grid, kTileThreads, 0, st>>>(A, mod, nmod, tmod, nt, off, cir, cnum);
+  SPX_HIP(hipGetLastError());
+  return SPX_OK;
+}
+
+// ------------------------------------------------ SpAsgn's modified columns
+// An entry of A in modified column j is dropped when its row is in I, else
+// kept.  Its kept rank in the column is its position there minus the
+// dropped entries before it: the merged-order tile counts those among its
+// own entries with a scan and, for a column begun in earlier tiles, adds
+// their dropped counts of it (recorded per tile by the plan's count pass).
+// A kept entry lands at off[j] + kept rank + the inserted rows below it (a
+// binary search in the column's sorted inserted keys); a dropped one records
+// its row at its rank in the column's list of dropped rows (ascending, as
+// A's rows are).  The inserted entry of sorted rank s and row r lands at
+// off[j] + s + (A's rows below r) - (dropped rows below r).
+
+// Count pass over the tiles: dropped entries per modified column (dcnt,
+// accumulated atomically, zero on entry) and, per tile, those of the last
+// column it meets (lastseg; 0 when that column starts after the tile).
+__global__ void __launch_bounds__(kTileThreads) k_asgn_drop_count(Operand A, const int32_t* lastI,
+                                                                  const int32_t* mod, int64_t nmod,
+                                                                  const int64_t* tmod, int64_t nt,
+                                                                  unsigned long long* dcnt, int64_t* lastseg) {
+  __shared__ int32_t s_beg[kTileItems + 1];
+  __shared__ int32_t s_end[kTileItems + 1];
+  __shared__ int32_t s_cnt[kTileItems + 1];
+  for (int64_t t = blockIdx.x; t < nt; t += gridDim.x) {
+    const TileSpan sp = tile_span(A, nmod, tmod, t);
+    for (int32_t i = threadIdx.x; i < sp.nst; i += kTileThreads) {
+      const int64_t c = mod[sp.us + i];
+      s_beg[i] = tile_rel(slot_begin(A, c), sp.es);
+      s_end[i] = tile_rel(slot_begin(A, c + 1), sp.es);
+      s_cnt[i] = 0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kTilePer; ++k) {
+      const int32_t x = threadIdx.x + k * kTileThreads;
+      if (sp.es + x < sp.ee) {
+        const int32_t lo = staged_rank(s_end, sp.nst, x);
+        if (lo < sp.nst && s_beg[lo] <= x && lastI[A.ir[sp.es + x]] >= 0) atomicAdd(&s_cnt[lo], 1);
+      }
+    }
+    __syncthreads();
+    for (int32_t i = threadIdx.x; i < sp.nst; i += kTileThreads)
+      if (s_cnt[i]) atomicAdd(&dcnt[sp.us + i], (unsigned long long)s_cnt[i]);
+    if (threadIdx.x == 0) lastseg[t] = sp.ue < nmod ? s_cnt[sp.ue - sp.us] : 0;
+    __syncthreads();
+  }
+}
+
+// Per modified column (one wave each): the inserted entries (B entries whose
+// row index is the last occurrence in I), their count icnt, the column's
+// output length cnt[j] = nnz(A(:,j)) - dropped + inserted, and B's column
+// start kbase.  A B column of at most 64 entries has its keys
+// (row << 32 | position in the B column) sorted in registers and stored at
+// ikeys[kbase ..]; longer ones go to the big list, sorted by
+// k_asgn_big_keys or, past kAsgnMaxInsert, k_asgn_huge_keys.
+__global__ void __launch_bounds__(256) k_asgn_keys(Operand A, Operand B, const int32_t* I, const int32_t* lastI,
+                                                   const int32_t* lastJ, const int32_t* mod, int64_t nmod,
+                                                   const unsigned long long* dcnt, int64_t* icnt, int64_t* kbase,
+                                                   uint64_t* ikeys, int64_t* cnt, int32_t* big,
+                                                   unsigned long long* nbig) {
+  const int lane = lane_id();
+  const int64_t wave = __builtin_amdgcn_readfirstlane((int)((blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kWave));
+  const int64_t nwaves = (int64_t)gridDim.x * blockDim.x / kWave;
+  for (int64_t u = wave; u < nmod; u += nwaves) {
     const int32_t j = mod[u];
     const int32_t q = lastJ[j];
     const int64_t b0 = slot_begin(B, q), b1 = slot_begin(B, q + 1);
-    const int64_t nins = asgn_insert_keys(B, I, lastI, b0, b1, s_key, CAP, red);
-    int p2 = 1;
-    while (p2 < nins) p2 <<= 1;
-    for (int s = (int)nins + threadIdx.x; s < p2; s += blockDim.x) s_key[s] = ~0ull;
-    __syncthreads();
-    for (int k = 2; k <= p2; k <<= 1) {
-      for (int jj = k >> 1; jj > 0; jj >>= 1) {
-        for (int t = threadIdx.x; t < (p2 >> 1); t += blockDim.x) {
-          const int lo = 2 * t - (t & (jj - 1));
-          const int hi = lo + jj;
-          const bool asc = (lo & k) == 0;
-          const uint64_t x = s_key[lo], y = s_key[hi];
-          if ((x > y) == asc) {
-            s_key[lo] = y;
-            s_key[hi] = x;
-          }
+    int64_t ins = 0;
+    if (b1 - b0 <= kWave) {
+      uint64_t key = ~0ull;
+      if (lane < b1 - b0) {
+        const int32_t p = B.ir[b0 + lane];
+        const int32_t row = I[p];
+        if (lastI[row] == p) key = ((uint64_t)(uint32_t)row << 32) | (uint32_t)lane;
+      }
+      ins = __popcll(__ballot(key != ~0ull));
+      key = wave_sort_u64(key);
+      if (lane < ins) ikeys[b0 + lane] = key;
+    } else {
+      for (int64_t ec = b0; ec < b1; ec += kWave) {
+        const int64_t e = ec + lane;
+        bool take = false;
+        if (e < b1) {
+          const int32_t p = B.ir[e];
+          take = lastI[I[p]] == p;
         }
-        __syncthreads();
+        ins += __popcll(__ballot(take));
       }
     }
-    asgn_merge_column(A, B, lastI, j, b0, off[j], doff[u], s_key, nins, red, drows, vb, cir, cnum);
+    if (lane == 0) {
+      icnt[u] = ins;
+      kbase[u] = b0;
+      cnt[j] = slot_begin(A, j + 1) - slot_begin(A, j) - (int64_t)dcnt[u] + ins;
+      if (b1 - b0 > kWave) big[atomicAdd(nbig, 1ull)] = (int32_t)u;
+    }
+  }
+}
+
+// Big-list columns with at most kAsgnMaxInsert inserted entries: keys
+// compacted and sorted in LDS, then stored at ikeys[kbase ..].
+__global__ void __launch_bounds__(256) k_asgn_big_keys(Operand B, const int32_t* I, const int32_t* lastI,
+                                                       const int32_t* lastJ, const int32_t* mod, const int32_t* big,
+                                                       int64_t nbig, const int64_t* icnt, uint64_t* ikeys) {
+  __shared__ uint64_t s_key[kAsgnMaxInsert];
+  __shared__ int64_t red[256 / kWave + 1];
+  for (int64_t w = blockIdx.x; w < nbig; w += gridDim.x) {
+    const int64_t u = big[w];
+    if (icnt[u] > kAsgnMaxInsert) continue;  // uniform: a huge column
+    const int32_t q = lastJ[mod[u]];
+    const int64_t b0 = slot_begin(B, q);
+    const int64_t nins = asgn_insert_keys(B, I, lastI, b0, slot_begin(B, q + 1), s_key, kAsgnMaxInsert, red);
+    lds_sort_keys(s_key, (int)nins);
+    for (int64_t s = threadIdx.x; s < nins; s += blockDim.x) ikeys[b0 + s] = s_key[s];
+    __syncthreads();
   }
 }
 
 // Huge columns (more than kAsgnMaxInsert inserted rows), at plan time: each
 // workgroup writes one column's keys into its segment of hkeys, pads the
-// segment to its power-of-two length and sorts it in global memory.
+// segment to its power-of-two length, sorts it in global memory and stores
+// the sorted keys at ikeys[kbase ..].
 __global__ void __launch_bounds__(256) k_asgn_huge_keys(Operand B, const int32_t* I, const int32_t* lastI,
                                                         const int32_t* lastJ, const int32_t* mod, const int32_t* big,
                                                         int64_t nbig, const int64_t* icnt, const int64_t* hoff,
-                                                        uint64_t* hkeys) {
+                                                        uint64_t* hkeys, uint64_t* ikeys) {
   __shared__ uint64_t s_tile[kAsgnMaxInsert];
   __shared__ int64_t red[256 / kWave + 1];
   for (int64_t w = blockIdx.x; w < nbig; w += gridDim.x) {
@@ -606,30 +576,179 @@ __global__ void __launch_bounds__(256) k_asgn_huge_keys(Operand B, const int32_t
     if (p2 == 0) continue;  // uniform: not a huge column
     const int64_t u = big[w];
     const int32_t q = lastJ[mod[u]];
+    const int64_t b0 = slot_begin(B, q);
     uint64_t* seg = hkeys + hoff[w];
-    const int64_t nins = asgn_insert_keys(B, I, lastI, slot_begin(B, q), slot_begin(B, q + 1), seg, p2, red);
+    const int64_t nins = asgn_insert_keys(B, I, lastI, b0, slot_begin(B, q + 1), seg, p2, red);
     for (int64_t s = nins + threadIdx.x; s < p2; s += blockDim.x) seg[s] = ~0ull;
     __threadfence_block();
     __syncthreads();
     wg_sort_global(seg, p2, s_tile);
+    for (int64_t s = threadIdx.x; s < nins; s += blockDim.x) ikeys[b0 + s] = seg[s];
+    __syncthreads();
   }
 }
 
-// Huge columns at exec time: the merge from the sorted global keys.
-__global__ void __launch_bounds__(256) k_asgn_huge_fill(Operand A, Operand B, const int32_t* lastI,
-                                                        const int32_t* lastJ, const int32_t* mod, const int32_t* big,
-                                                        int64_t nbig, const int64_t* icnt, const int64_t* hoff,
-                                                        const uint64_t* hkeys, const int64_t* off, const int64_t* doff,
-                                                        int32_t* drows, int vb, int32_t* cir, void* cnum) {
-  __shared__ int64_t red[256 / kWave + 1];
-  for (int64_t w = blockIdx.x; w < nbig; w += gridDim.x) {
-    if (hoff[w + 1] == hoff[w]) continue;  // uniform: not a huge column
-    const int64_t u = big[w];
-    const int32_t j = mod[u];
-    const int32_t q = lastJ[j];
-    asgn_merge_column(A, B, lastI, j, slot_begin(B, q), off[j], doff[u], hkeys + hoff[w], icnt[u], red, drows, vb,
-                      cir, cnum);
+// Fill pass over the tiles: unmodified runs are copied with their output
+// shift; entries of modified columns are kept or dropped as described above.
+template <int VB>
+__global__ void __launch_bounds__(kTileThreads) k_asgn_fill(Operand A, const int32_t* lastI, const int32_t* mod,
+                                                            int64_t nmod, const int64_t* tmod, int64_t nt,
+                                                            const int64_t* lastseg, const int64_t* off,
+                                                            const int64_t* icnt, const int64_t* kbase,
+                                                            const uint64_t* ikeys, const int64_t* doff,
+                                                            int32_t* drows, int32_t* cir, void* cnum) {
+  using V = typename std::conditional<VB == 8, uint64_t, uint32_t>::type;
+  constexpr int kWaves = kTileThreads / kWave;
+  __shared__ int32_t s_beg[kTileItems + 1];
+  __shared__ int32_t s_end[kTileItems + 1];
+  __shared__ int32_t s_dbase[kTileItems + 1];   // dropped entries of the tile before the column's first
+  __shared__ int64_t s_shift[kTileItems + 1];   // output shift of the run before staged column i
+  __shared__ int64_t s_mshift[kTileItems + 1];  // off[c] - cp[c] of staged column i
+  __shared__ int32_t s_wt[kTilePer][kWaves];    // dropped entries per wave and round
+  __shared__ int64_t s_red[kWaves];
+  __shared__ int64_t s_a0;
+  const V* anum = static_cast<const V*>(A.num);
+  V* out = static_cast<V*>(cnum);
+  const int lane = lane_id(), wid = threadIdx.x / kWave;
+  for (int64_t t = blockIdx.x; t < nt; t += gridDim.x) {
+    const TileSpan sp = tile_span(A, nmod, tmod, t);
+    for (int64_t i = threadIdx.x; i <= sp.ue - sp.us; i += kTileThreads) {
+      const int64_t r = sp.us + i;
+      const int64_t c0 = r == 0 ? 0 : (int64_t)mod[r - 1] + 1;
+      s_shift[i] = off[c0] - slot_begin(A, c0);
+      if (i < sp.nst) {
+        const int64_t c = mod[r];
+        const int64_t cb = slot_begin(A, c);
+        s_beg[i] = tile_rel(cb, sp.es);
+        s_end[i] = tile_rel(slot_begin(A, c + 1), sp.es);
+        s_mshift[i] = off[c] - cb;
+        if (i == 0) s_a0 = cb;
+      }
+    }
+    __syncthreads();
+    // dropped entries of the first staged column in the tiles before this one
+    int64_t dprev = 0;
+    if (sp.nst > 0 && s_a0 < sp.es) {  // uniform
+      int64_t part = 0;
+      for (int64_t tt = (s_a0 + sp.us) / kTileItems + threadIdx.x; tt < t; tt += kTileThreads) part += lastseg[tt];
+      part = wave_sum(part);
+      if (lane == 0) s_red[wid] = part;
+      __syncthreads();
+      for (int w = 0; w < kWaves; ++w) dprev += s_red[w];
+    }
+    int32_t lo[kTilePer], row[kTilePer], ex[kTilePer];
+    bool inmod[kTilePer], drop[kTilePer];
+    V val[kTilePer];
+#pragma unroll
+    for (int k = 0; k < kTilePer; ++k) {
+      const int32_t x = threadIdx.x + k * kTileThreads;
+      const bool valid = sp.es + x < sp.ee;
+      lo[k] = valid ? staged_rank(s_end, sp.nst, x) : 0;
+      inmod[k] = valid && lo[k] < sp.nst && s_beg[lo[k]] <= x;
+      row[k] = valid ? A.ir[sp.es + x] : -1;
+      if (VB && valid) val[k] = anum[sp.es + x];
+    }
+#pragma unroll
+    for (int k = 0; k < kTilePer; ++k) {
+      drop[k] = inmod[k] && lastI[row[k]] >= 0;
+      const uint64_t m = __ballot(drop[k]);
+      ex[k] = __popcll(m & lanemask_lt());
+      if (lane == 0) s_wt[k][wid] = __popcll(m);
+    }
+    __syncthreads();
+    int32_t base = 0;
+#pragma unroll
+    for (int k = 0; k < kTilePer; ++k) {
+      int32_t before = 0, tot = 0;
+      for (int w = 0; w < kWaves; ++w) {
+        before += w < wid ? s_wt[k][w] : 0;
+        tot += s_wt[k][w];
+      }
+      ex[k] += base + before;  // dropped entries of the tile before this one
+      base += tot;
+      const int32_t x = threadIdx.x + k * kTileThreads;
+      if (inmod[k] && x == s_beg[lo[k]]) s_dbase[lo[k]] = ex[k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kTilePer; ++k) {
+      if (row[k] < 0) continue;
+      const int64_t e = sp.es + threadIdx.x + k * kTileThreads;
+      int64_t dst;
+      if (!inmod[k]) {
+        dst = e + s_shift[lo[k]];
+      } else {
+        const int64_t db = ex[k] - s_dbase[lo[k]] + (lo[k] == 0 ? dprev : 0);
+        const int64_t u = sp.us + lo[k];
+        if (drop[k]) {
+          drows[doff[u] + db] = row[k];
+          continue;
+        }
+        // inserted rows below this row
+        const uint64_t* keys = ikeys + kbase[u];
+        int64_t a = 0, b = icnt[u];
+        while (a < b) {
+          const int64_t mid = (a + b) >> 1;
+          if ((int32_t)(keys[mid] >> 32) < row[k])
+            a = mid + 1;
+          else
+            b = mid;
+        }
+        dst = e + s_mshift[lo[k]] - db + a;
+      }
+      cir[dst] = row[k];
+      if (VB) out[dst] = val[k];
+    }
+    __syncthreads();
   }
+}
+
+// Inserted entries: one wave per modified column of at most 64 (lane s
+// takes the key of rank s), or one workgroup per big-list column above 64.
+template <bool kBlock>
+__global__ void __launch_bounds__(256) k_asgn_insert(Operand A, Operand B, const int32_t* mod, const int32_t* list,
+                                                     int64_t nlist, const int64_t* icnt, const int64_t* kbase,
+                                                     const uint64_t* ikeys, const int64_t* off, const int64_t* doff,
+                                                     const int32_t* drows, int vb, int32_t* cir, void* cnum) {
+  const int64_t unit = kBlock ? blockIdx.x
+                              : __builtin_amdgcn_readfirstlane(
+                                    (int)((blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kWave));
+  const int64_t nunits = kBlock ? gridDim.x : (int64_t)gridDim.x * blockDim.x / kWave;
+  const int32_t sub = kBlock ? threadIdx.x : lane_id();
+  const int32_t step = kBlock ? blockDim.x : kWave;
+  for (int64_t w = unit; w < nlist; w += nunits) {
+    const int64_t u = kBlock ? list[w] : w;
+    const int64_t n = icnt[u];
+    if (kBlock ? n <= kAsgnSmall : n > kAsgnSmall) continue;  // uniform: the other variant's column
+    const int32_t j = mod[u];
+    const int64_t a0 = slot_begin(A, j), alen = slot_begin(A, j + 1) - a0;
+    const int64_t d0 = doff[u], dlen = doff[u + 1] - d0;
+    const int64_t kb = kbase[u], cbase = off[j];
+    for (int64_t s = sub; s < n; s += step) {
+      const uint64_t key = ikeys[kb + s];
+      const int32_t r = (int32_t)(key >> 32);
+      const int64_t o = cbase + s + rows_below(A.ir + a0, alen, r) - rows_below(drows + d0, dlen, r);
+      cir[o] = r;
+      copy_value(B.num, kb + (int64_t)(key & 0xffffffffu), cnum, o, vb);
+    }
+  }
+}
+
+int launch_asgn_fill(const SpasgnPlan* P, int vb, int32_t* cir, void* cnum, hipStream_t st) {
+  if (P->ntiles == 0) return SPX_OK;
+  const unsigned grid = (unsigned)std::min<int64_t>(P->ntiles, (int64_t)device_cu_count() * 32);
+#define SPX_ASGN_FILL(VB)                                                                                          \
+  k_asgn_fill<VB><<<grid, kTileThreads, 0, st>>>(P->A, P->lastI, P->mod, P->nmod, P->tmod, P->ntiles, P->lastseg, \
+                                                 P->off, P->icnt, P->kbase, P->ikeys, P->doff, P->drows, cir, cnum)
+  if (vb == 8)
+    SPX_ASGN_FILL(8);
+  else if (vb == 4)
+    SPX_ASGN_FILL(4);
+  else
+    SPX_ASGN_FILL(0);
+#undef SPX_ASGN_FILL
+  SPX_HIP(hipGetLastError());
+  return SPX_OK;
 }
 
 __global__ void k_asgn_write_cp(const int64_t* off, int64_t n, void* cp, int32_t ptr_t) {
@@ -696,42 +815,6 @@ struct LoadI32 {
   const int32_t* p;
   __device__ int64_t operator()(int64_t i) const { return p[i]; }
 };
-
-// Ascending bitonic sort of s[0, n) in LDS (n <= kAsgnMaxInsert), padded with ~0.
-__device__ __forceinline__ void lds_sort_keys(uint64_t* s, int n) {
-  int p2 = 1;
-  while (p2 < n) p2 <<= 1;
-  for (int t = n + threadIdx.x; t < p2; t += blockDim.x) s[t] = ~0ull;
-  __syncthreads();
-  for (int k = 2; k <= p2; k <<= 1) {
-    for (int jj = k >> 1; jj > 0; jj >>= 1) {
-      for (int t = threadIdx.x; t < (p2 >> 1); t += blockDim.x) {
-        const int lo = 2 * t - (t & (jj - 1));
-        const int hi = lo + jj;
-        const bool asc = (lo & k) == 0;
-        const uint64_t x = s[lo], y = s[hi];
-        if ((x > y) == asc) {
-          s[lo] = y;
-          s[hi] = x;
-        }
-      }
-      __syncthreads();
-    }
-  }
-}
-
-// Number of rows < row in the sorted column col[0, len).
-__device__ __forceinline__ int64_t rows_below(const int32_t* col, int64_t len, int32_t row) {
-  int64_t lo = 0, hi = len;
-  while (lo < hi) {
-    const int64_t mid = (lo + hi) >> 1;
-    if (col[mid] < row)
-      lo = mid + 1;
-    else
-      hi = mid;
-  }
-  return lo;
-}
 
 // One modified column j of extend-add from its landing entries, given as
 // keys (I(p) << 32 | e), e the entry's position in B, sorted ascending in
@@ -1122,40 +1205,52 @@ extern "C" int spx_spasgn_plan(const spx_ctx* ctx, const spx_mat* A, const int32
   P->nmod = (int64_t)nmod_h;
   SPX_TRY(copy_tiles(P->A, P->mod, P->nmod, scr, st, &P->tmod, &P->ntiles));
   SPX_TRY(scr.get_n(std::max<int64_t>(P->nmod, 1), &P->dcnt));
+  SPX_TRY(scr.get_n(std::max<int64_t>(P->ntiles, 1), &P->lastseg));
+  SPX_TRY(fill_i64(P->dcnt, P->nmod, 0, st));
+  if (P->nmod > 0 && P->ntiles > 0) {
+    k_asgn_drop_count<<<(unsigned)std::min<int64_t>(P->ntiles, (int64_t)cus * 32), kTileThreads, 0, st>>>(
+        P->A, P->lastI, P->mod, P->nmod, P->tmod, P->ntiles, reinterpret_cast<unsigned long long*>(P->dcnt),
+        P->lastseg);
+    SPX_HIP(hipGetLastError());
+  }
   SPX_TRY(scr.get_n(P->nmod + 1, &P->doff));
-  SPX_TRY(scr.get_n(std::max<int64_t>(P->nmod, 1), &P->big));
   SPX_TRY(scr.get_n(std::max<int64_t>(P->nmod, 1), &P->icnt));
+  SPX_TRY(scr.get_n(std::max<int64_t>(P->nmod, 1), &P->kbase));
+  SPX_TRY(scr.get_n(std::max<int64_t>(P->B.nnz, 1), &P->ikeys));
+  SPX_TRY(scr.get_n(std::max<int64_t>(P->nmod, 1), &P->big));
   SPX_TRY(scr.get_n(P->nmod + 1, &P->hoff));
-  SPX_TRY(scr.get_n(std::max<int64_t>(P->nmod, 1), &P->mid));
-  SPX_TRY(scr.get_n(2, &P->nbig_d));
-  P->nmid_d = P->nbig_d + 1;
-  SPX_TRY(fill_i64((int64_t*)P->nbig_d, 2, 0, st));
+  SPX_TRY(scr.get_n(1, &P->nbig_d));
+  SPX_TRY(fill_i64((int64_t*)P->nbig_d, 1, 0, st));
   if (P->nmod > 0) {
-    k_asgn_mod_count<<<(unsigned)std::min<int64_t>(ceil_div(P->nmod, (int64_t)4), (int64_t)cus * 16), 256, 0, st>>>(
-        P->A, P->B, I, P->lastI, P->lastJ, P->mod, P->nmod, P->cnt, P->dcnt, P->icnt, P->big, P->nbig_d, P->mid,
-        P->nmid_d);
+    k_asgn_keys<<<(unsigned)std::min<int64_t>(ceil_div(P->nmod, (int64_t)4), (int64_t)cus * 16), 256, 0, st>>>(
+        P->A, P->B, I, P->lastI, P->lastJ, P->mod, P->nmod, reinterpret_cast<const unsigned long long*>(P->dcnt),
+        P->icnt, P->kbase, P->ikeys, P->cnt, P->big, P->nbig_d);
     SPX_HIP(hipGetLastError());
   }
   SPX_TRY(exclusive_scan(LoadI64{P->cnt}, n, P->off, scr, st));
   SPX_TRY(exclusive_scan(LoadI64{P->dcnt}, P->nmod, P->doff, scr, st));
   // key segments of the huge columns (big-list order; entries past nbig are empty)
   SPX_TRY(exclusive_scan(HugeCap{P->icnt, P->big, P->nbig_d}, P->nmod, P->hoff, scr, st));
-  int64_t tail[5] = {0, 0, 0, 0, 0};
+  int64_t tail[4] = {0, 0, 0, 0};
   SPX_HIP(hipMemcpyAsync(&tail[0], P->off + n, 8, hipMemcpyDeviceToHost, st));
   SPX_HIP(hipMemcpyAsync(&tail[1], P->doff + P->nmod, 8, hipMemcpyDeviceToHost, st));
-  SPX_HIP(hipMemcpyAsync(&tail[2], P->nbig_d, 16, hipMemcpyDeviceToHost, st));
-  SPX_HIP(hipMemcpyAsync(&tail[4], P->hoff + P->nmod, 8, hipMemcpyDeviceToHost, st));
+  SPX_HIP(hipMemcpyAsync(&tail[2], P->nbig_d, 8, hipMemcpyDeviceToHost, st));
+  SPX_HIP(hipMemcpyAsync(&tail[3], P->hoff + P->nmod, 8, hipMemcpyDeviceToHost, st));
   SPX_HIP(hipStreamSynchronize(st));
   P->nnz = tail[0];
   P->ndrop = tail[1];
   P->nbig = tail[2];
-  P->nmid = tail[3];
-  P->nhuge_keys = tail[4];
+  P->nhuge_keys = tail[3];
   SPX_TRY(scr.get_n(std::max<int64_t>(P->ndrop, 1), &P->drows));
+  if (P->nbig > 0) {
+    k_asgn_big_keys<<<(unsigned)std::min<int64_t>(P->nbig, (int64_t)cus * 4), 256, 0, st>>>(
+        P->B, I, P->lastI, P->lastJ, P->mod, P->big, P->nbig, P->icnt, P->ikeys);
+    SPX_HIP(hipGetLastError());
+  }
   if (P->nhuge_keys > 0) {
     SPX_TRY(scr.get_n(P->nhuge_keys, &P->hkeys));
     k_asgn_huge_keys<<<(unsigned)std::min<int64_t>(P->nbig, (int64_t)cus * 2), 256, 0, st>>>(
-        P->B, I, P->lastI, P->lastJ, P->mod, P->big, P->nbig, P->icnt, P->hoff, P->hkeys);
+        P->B, I, P->lastI, P->lastJ, P->mod, P->big, P->nbig, P->icnt, P->hoff, P->hkeys, P->ikeys);
     SPX_HIP(hipGetLastError());
   }
   if (nnz_c) *nnz_c = P->nnz;
@@ -1177,28 +1272,17 @@ extern "C" int spx_spasgn_exec(spx_plan* plan, spx_mat* C) {
   hipStream_t st = stream_of(&P->ctx);
   const int vb = value_size(P->A.val_t);
   const int cus = device_cu_count();
-  SPX_TRY(launch_copy(P->A, P->mod, P->nmod, P->tmod, P->ntiles, P->off, vb, C->ir, C->num, st));
+  SPX_TRY(launch_asgn_fill(P, vb, C->ir, C->num, st));
   if (P->nmod > 0) {
-    k_asgn_mod_wave<<<(unsigned)std::min<int64_t>(ceil_div(P->nmod, (int64_t)4), (int64_t)cus * 16), 256, 0, st>>>(
-        P->A, P->B, P->I, P->lastI, P->lastJ, P->mod, P->nmod, P->off, vb, C->ir, C->num);
-    SPX_HIP(hipGetLastError());
-  }
-  if (P->nmid > 0) {
-    k_asgn_mod_fill<kAsgnSmall><<<(unsigned)std::min<int64_t>(P->nmid, (int64_t)cus * 32), 64, 0, st>>>(
-        P->A, P->B, P->I, P->lastI, P->lastJ, P->mod, P->mid, P->nmid, P->icnt, P->off, P->doff, P->drows, vb,
-        C->ir, C->num);
+    k_asgn_insert<false><<<(unsigned)std::min<int64_t>(ceil_div(P->nmod, (int64_t)4), (int64_t)cus * 16), 256, 0,
+                           st>>>(P->A, P->B, P->mod, nullptr, P->nmod, P->icnt, P->kbase, P->ikeys, P->off, P->doff,
+                                 P->drows, vb, C->ir, C->num);
     SPX_HIP(hipGetLastError());
   }
   if (P->nbig > 0) {
-    k_asgn_mod_fill<kAsgnMaxInsert><<<(unsigned)std::min<int64_t>(P->nbig, (int64_t)cus * 2), 256, 0, st>>>(
-        P->A, P->B, P->I, P->lastI, P->lastJ, P->mod, P->big, P->nbig, P->icnt, P->off, P->doff, P->drows, vb,
-        C->ir, C->num);
-    SPX_HIP(hipGetLastError());
-  }
-  if (P->nhuge_keys > 0) {
-    k_asgn_huge_fill<<<(unsigned)std::min<int64_t>(P->nbig, (int64_t)cus * 2), 256, 0, st>>>(
-        P->A, P->B, P->lastI, P->lastJ, P->mod, P->big, P->nbig, P->icnt, P->hoff, P->hkeys, P->off, P->doff,
-        P->drows, vb, C->ir, C->num);
+    k_asgn_insert<true><<<(unsigned)std::min<int64_t>(P->nbig, (int64_t)cus * 4), 256, 0, st>>>(
+        P->A, P->B, P->mod, P->big, P->nbig, P->icnt, P->kbase, P->ikeys, P->off, P->doff, P->drows, vb, C->ir,
+        C->num);
     SPX_HIP(hipGetLastError());
   }
   k_asgn_write_cp<<<grid_for(P->A.n + 1, 256, 65536), 256, 0, st>>>(P->off, P->A.n, C->cp, C->ptr_t);
