@@ -363,7 +363,8 @@ __device__ __forceinline__ int32_t tile_rel(int64_t pos, int64_t es) {
 }
 
 // Staged columns ending at or before in-tile position x.
-__device__ __forceinline__ int32_t staged_rank(const int32_t* s_end, int32_t nst, int32_t x) {
+template <typename P>
+__device__ __forceinline__ int32_t staged_rank(const P* s_end, int32_t nst, int32_t x) {
   int32_t lo = 0, hi = nst;
   while (lo < hi) {
     const int32_t mid = (lo + hi) >> 1;
@@ -492,52 +493,103 @@ __global__ void __launch_bounds__(kTileThreads) k_asgn_drop_count(Operand A, con
   }
 }
 
-// Per modified column (one wave each): the inserted entries (B entries whose
-// row index is the last occurrence in I), their count icnt, the column's
-// output length cnt[j] = nnz(A(:,j)) - dropped + inserted, and B's column
-// start kbase.  A B column of at most 64 entries has its keys
-// (row << 32 | position in the B column) sorted in registers and stored at
-// ikeys[kbase ..]; longer ones go to the big list, sorted by
-// k_asgn_big_keys or, past kAsgnMaxInsert, k_asgn_huge_keys.
+// Ascending bitonic sort of one 64-bit key per lane within each 16-lane
+// group of the wave (every lane active).
+__device__ __forceinline__ uint64_t group16_sort_u64(uint64_t key) {
+  const int gl = lane_id() & 15;
+#pragma unroll
+  for (int k = 2; k <= 16; k <<= 1) {
+#pragma unroll
+    for (int jj = k >> 1; jj > 0; jj >>= 1) {
+      const uint64_t other = xor_lane(key, jj);
+      const bool up = (gl & k) == 0, lower = (gl & jj) == 0;
+      const uint64_t mn = other < key ? other : key, mx = other < key ? key : other;
+      key = lower == up ? mn : mx;
+    }
+  }
+  return key;
+}
+
+// Per modified column: the inserted entries (B entries whose row index is
+// the last occurrence in I), their count icnt, the column's output length
+// cnt[j] = nnz(A(:,j)) - dropped + inserted, and B's column start kbase.
+// A wave takes four columns at a time, one per 16-lane group: a B column of
+// at most 16 entries has its keys (row << 32 | position in the B column)
+// sorted within the group and stored at ikeys[kbase ..].  The others are
+// then taken by the whole wave, one by one: up to 64 entries sorted across
+// the wave, longer ones counted and put on the big list (sorted by
+// k_asgn_big_keys or, past kAsgnMaxInsert, k_asgn_huge_keys).
 __global__ void __launch_bounds__(256) k_asgn_keys(Operand A, Operand B, const int32_t* I, const int32_t* lastI,
                                                    const int32_t* lastJ, const int32_t* mod, int64_t nmod,
                                                    const unsigned long long* dcnt, int64_t* icnt, int64_t* kbase,
                                                    uint64_t* ikeys, int64_t* cnt, int32_t* big,
                                                    unsigned long long* nbig) {
-  const int lane = lane_id();
+  const int lane = lane_id(), g = lane >> 4, gl = lane & 15;
   const int64_t wave = __builtin_amdgcn_readfirstlane((int)((blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kWave));
   const int64_t nwaves = (int64_t)gridDim.x * blockDim.x / kWave;
-  for (int64_t u = wave; u < nmod; u += nwaves) {
-    const int32_t j = mod[u];
-    const int32_t q = lastJ[j];
-    const int64_t b0 = slot_begin(B, q), b1 = slot_begin(B, q + 1);
-    int64_t ins = 0;
-    if (b1 - b0 <= kWave) {
-      uint64_t key = ~0ull;
-      if (lane < b1 - b0) {
-        const int32_t p = B.ir[b0 + lane];
-        const int32_t row = I[p];
-        if (lastI[row] == p) key = ((uint64_t)(uint32_t)row << 32) | (uint32_t)lane;
-      }
-      ins = __popcll(__ballot(key != ~0ull));
-      key = wave_sort_u64(key);
-      if (lane < ins) ikeys[b0 + lane] = key;
-    } else {
-      for (int64_t ec = b0; ec < b1; ec += kWave) {
-        const int64_t e = ec + lane;
-        bool take = false;
-        if (e < b1) {
-          const int32_t p = B.ir[e];
-          take = lastI[I[p]] == p;
-        }
-        ins += __popcll(__ballot(take));
+  for (int64_t base = wave * 4; base < nmod; base += nwaves * 4) {
+    const int64_t u = base + g;
+    const bool has = u < nmod;
+    int32_t j = 0;
+    int64_t b0 = 0, b1 = 0;
+    if (has) {
+      j = mod[u];
+      const int32_t q = lastJ[j];
+      b0 = slot_begin(B, q);
+      b1 = slot_begin(B, q + 1);
+    }
+    const bool small = has && b1 - b0 <= 16;
+    uint64_t key = ~0ull;
+    if (small && gl < b1 - b0) {
+      const int32_t p = B.ir[b0 + gl];
+      const int32_t row = I[p];
+      if (lastI[row] == p) key = ((uint64_t)(uint32_t)row << 32) | (uint32_t)gl;
+    }
+    const int ins_g = __popcll((__ballot(key != ~0ull) >> (g * 16)) & 0xffffull);
+    key = group16_sort_u64(key);
+    if (small) {
+      if (gl < ins_g) ikeys[b0 + gl] = key;
+      if (gl == 0) {
+        icnt[u] = ins_g;
+        kbase[u] = b0;
+        cnt[j] = slot_begin(A, j + 1) - slot_begin(A, j) - (int64_t)dcnt[u] + ins_g;
       }
     }
-    if (lane == 0) {
-      icnt[u] = ins;
-      kbase[u] = b0;
-      cnt[j] = slot_begin(A, j + 1) - slot_begin(A, j) - (int64_t)dcnt[u] + ins;
-      if (b1 - b0 > kWave) big[atomicAdd(nbig, 1ull)] = (int32_t)u;
+    uint64_t rest = __ballot(has && !small && gl == 0);
+    while (rest) {  // uniform
+      const int64_t v = base + (__ffsll((unsigned long long)rest) - 1) / 16;
+      rest &= rest - 1;
+      const int32_t jv = mod[v];
+      const int32_t q = lastJ[jv];
+      const int64_t c0 = slot_begin(B, q), c1 = slot_begin(B, q + 1);
+      int64_t ins = 0;
+      if (c1 - c0 <= kWave) {
+        uint64_t kv = ~0ull;
+        if (lane < c1 - c0) {
+          const int32_t p = B.ir[c0 + lane];
+          const int32_t row = I[p];
+          if (lastI[row] == p) kv = ((uint64_t)(uint32_t)row << 32) | (uint32_t)lane;
+        }
+        ins = __popcll(__ballot(kv != ~0ull));
+        kv = wave_sort_u64(kv);
+        if (lane < ins) ikeys[c0 + lane] = kv;
+      } else {
+        for (int64_t ec = c0; ec < c1; ec += kWave) {
+          const int64_t e = ec + lane;
+          bool take = false;
+          if (e < c1) {
+            const int32_t p = B.ir[e];
+            take = lastI[I[p]] == p;
+          }
+          ins += __popcll(__ballot(take));
+        }
+      }
+      if (lane == 0) {
+        icnt[v] = ins;
+        kbase[v] = c0;
+        cnt[jv] = slot_begin(A, jv + 1) - slot_begin(A, jv) - (int64_t)dcnt[v] + ins;
+        if (c1 - c0 > kWave) big[atomicAdd(nbig, 1ull)] = (int32_t)v;
+      }
     }
   }
 }
@@ -599,9 +651,9 @@ __global__ void __launch_bounds__(kTileThreads) k_asgn_fill(Operand A, const int
                                                             int32_t* drows, int32_t* cir, void* cnum) {
   using V = typename std::conditional<VB == 8, uint64_t, uint32_t>::type;
   constexpr int kWaves = kTileThreads / kWave;
-  __shared__ int32_t s_beg[kTileItems + 1];
-  __shared__ int32_t s_end[kTileItems + 1];
-  __shared__ int32_t s_dbase[kTileItems + 1];   // dropped entries of the tile before the column's first
+  __shared__ int16_t s_beg[kTileItems + 1];
+  __shared__ int16_t s_end[kTileItems + 1];
+  __shared__ int16_t s_dbase[kTileItems + 1];   // dropped entries of the tile before the column's first
   __shared__ int64_t s_shift[kTileItems + 1];   // output shift of the run before staged column i
   __shared__ int64_t s_mshift[kTileItems + 1];  // off[c] - cp[c] of staged column i
   __shared__ int32_t s_wt[kTilePer][kWaves];    // dropped entries per wave and round
@@ -619,8 +671,8 @@ __global__ void __launch_bounds__(kTileThreads) k_asgn_fill(Operand A, const int
       if (i < sp.nst) {
         const int64_t c = mod[r];
         const int64_t cb = slot_begin(A, c);
-        s_beg[i] = tile_rel(cb, sp.es);
-        s_end[i] = tile_rel(slot_begin(A, c + 1), sp.es);
+        s_beg[i] = (int16_t)tile_rel(cb, sp.es);
+        s_end[i] = (int16_t)tile_rel(slot_begin(A, c + 1), sp.es);
         s_mshift[i] = off[c] - cb;
         if (i == 0) s_a0 = cb;
       }
@@ -639,6 +691,8 @@ __global__ void __launch_bounds__(kTileThreads) k_asgn_fill(Operand A, const int
     int32_t lo[kTilePer], row[kTilePer], ex[kTilePer];
     bool inmod[kTilePer], drop[kTilePer];
     V val[kTilePer];
+    int64_t nkey[kTilePer];
+    const uint64_t* keys[kTilePer];
 #pragma unroll
     for (int k = 0; k < kTilePer; ++k) {
       const int32_t x = threadIdx.x + k * kTileThreads;
@@ -647,6 +701,12 @@ __global__ void __launch_bounds__(kTileThreads) k_asgn_fill(Operand A, const int
       inmod[k] = valid && lo[k] < sp.nst && s_beg[lo[k]] <= x;
       row[k] = valid ? A.ir[sp.es + x] : -1;
       if (VB && valid) val[k] = anum[sp.es + x];
+      nkey[k] = 0;
+      keys[k] = ikeys;
+      if (inmod[k]) {  // the column's inserted keys, for kept entries
+        nkey[k] = icnt[sp.us + lo[k]];
+        keys[k] = ikeys + kbase[sp.us + lo[k]];
+      }
     }
 #pragma unroll
     for (int k = 0; k < kTilePer; ++k) {
@@ -667,7 +727,7 @@ __global__ void __launch_bounds__(kTileThreads) k_asgn_fill(Operand A, const int
       ex[k] += base + before;  // dropped entries of the tile before this one
       base += tot;
       const int32_t x = threadIdx.x + k * kTileThreads;
-      if (inmod[k] && x == s_beg[lo[k]]) s_dbase[lo[k]] = ex[k];
+      if (inmod[k] && x == s_beg[lo[k]]) s_dbase[lo[k]] = (int16_t)ex[k];
     }
     __syncthreads();
 #pragma unroll
@@ -685,11 +745,10 @@ __global__ void __launch_bounds__(kTileThreads) k_asgn_fill(Operand A, const int
           continue;
         }
         // inserted rows below this row
-        const uint64_t* keys = ikeys + kbase[u];
-        int64_t a = 0, b = icnt[u];
+        int64_t a = 0, b = nkey[k];
         while (a < b) {
           const int64_t mid = (a + b) >> 1;
-          if ((int32_t)(keys[mid] >> 32) < row[k])
+          if ((int32_t)(keys[k][mid] >> 32) < row[k])
             a = mid + 1;
           else
             b = mid;
@@ -703,34 +762,57 @@ __global__ void __launch_bounds__(kTileThreads) k_asgn_fill(Operand A, const int
   }
 }
 
-// Inserted entries: one wave per modified column of at most 64 (lane s
-// takes the key of rank s), or one workgroup per big-list column above 64.
-template <bool kBlock>
-__global__ void __launch_bounds__(256) k_asgn_insert(Operand A, Operand B, const int32_t* mod, const int32_t* list,
-                                                     int64_t nlist, const int64_t* icnt, const int64_t* kbase,
+// One inserted entry: key of sorted rank s in modified column u.
+__device__ __forceinline__ void asgn_insert_one(const Operand& A, const Operand& B, const int32_t* mod, int64_t u,
+                                                int64_t s, const int64_t* kbase, const uint64_t* ikeys,
+                                                const int64_t* off, const int64_t* doff, const int32_t* drows, int vb,
+                                                int32_t* cir, void* cnum) {
+  const int32_t j = mod[u];
+  const int64_t a0 = slot_begin(A, j), alen = slot_begin(A, j + 1) - a0;
+  const int64_t d0 = doff[u], dlen = doff[u + 1] - d0;
+  const int64_t kb = kbase[u];
+  const uint64_t key = ikeys[kb + s];
+  const int32_t r = (int32_t)(key >> 32);
+  const int64_t o = off[j] + s + rows_below(A.ir + a0, alen, r) - rows_below(drows + d0, dlen, r);
+  cir[o] = r;
+  copy_value(B.num, kb + (int64_t)(key & 0xffffffffu), cnum, o, vb);
+}
+
+// Inserted entries of the columns with at most 64: a wave takes four
+// columns at a time, one per 16-lane group (lane s of the group takes the
+// key of rank s); a column above 16 then takes the whole wave.
+__global__ void __launch_bounds__(256) k_asgn_insert(Operand A, Operand B, const int32_t* mod, int64_t nmod,
+                                                     const int64_t* icnt, const int64_t* kbase,
                                                      const uint64_t* ikeys, const int64_t* off, const int64_t* doff,
                                                      const int32_t* drows, int vb, int32_t* cir, void* cnum) {
-  const int64_t unit = kBlock ? blockIdx.x
-                              : __builtin_amdgcn_readfirstlane(
-                                    (int)((blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kWave));
-  const int64_t nunits = kBlock ? gridDim.x : (int64_t)gridDim.x * blockDim.x / kWave;
-  const int32_t sub = kBlock ? threadIdx.x : lane_id();
-  const int32_t step = kBlock ? blockDim.x : kWave;
-  for (int64_t w = unit; w < nlist; w += nunits) {
-    const int64_t u = kBlock ? list[w] : w;
-    const int64_t n = icnt[u];
-    if (kBlock ? n <= kAsgnSmall : n > kAsgnSmall) continue;  // uniform: the other variant's column
-    const int32_t j = mod[u];
-    const int64_t a0 = slot_begin(A, j), alen = slot_begin(A, j + 1) - a0;
-    const int64_t d0 = doff[u], dlen = doff[u + 1] - d0;
-    const int64_t kb = kbase[u], cbase = off[j];
-    for (int64_t s = sub; s < n; s += step) {
-      const uint64_t key = ikeys[kb + s];
-      const int32_t r = (int32_t)(key >> 32);
-      const int64_t o = cbase + s + rows_below(A.ir + a0, alen, r) - rows_below(drows + d0, dlen, r);
-      cir[o] = r;
-      copy_value(B.num, kb + (int64_t)(key & 0xffffffffu), cnum, o, vb);
+  const int lane = lane_id(), g = lane >> 4, gl = lane & 15;
+  const int64_t wave = __builtin_amdgcn_readfirstlane((int)((blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kWave));
+  const int64_t nwaves = (int64_t)gridDim.x * blockDim.x / kWave;
+  for (int64_t base = wave * 4; base < nmod; base += nwaves * 4) {
+    const int64_t u = base + g;
+    const int64_t n = u < nmod ? icnt[u] : 0;
+    if (n <= 16 && gl < n) asgn_insert_one(A, B, mod, u, gl, kbase, ikeys, off, doff, drows, vb, cir, cnum);
+    uint64_t rest = __ballot(n > 16 && n <= kAsgnSmall && gl == 0);
+    while (rest) {  // uniform
+      const int64_t v = base + (__ffsll((unsigned long long)rest) - 1) / 16;
+      rest &= rest - 1;
+      if (lane < icnt[v]) asgn_insert_one(A, B, mod, v, lane, kbase, ikeys, off, doff, drows, vb, cir, cnum);
     }
+  }
+}
+
+// Inserted entries of the big-list columns above 64: one workgroup each.
+__global__ void __launch_bounds__(256) k_asgn_insert_big(Operand A, Operand B, const int32_t* mod, const int32_t* big,
+                                                         int64_t nbig, const int64_t* icnt, const int64_t* kbase,
+                                                         const uint64_t* ikeys, const int64_t* off,
+                                                         const int64_t* doff, const int32_t* drows, int vb,
+                                                         int32_t* cir, void* cnum) {
+  for (int64_t w = blockIdx.x; w < nbig; w += gridDim.x) {
+    const int64_t u = big[w];
+    const int64_t n = icnt[u];
+    if (n <= kAsgnSmall) continue;  // uniform: k_asgn_insert's column
+    for (int64_t s = threadIdx.x; s < n; s += blockDim.x)
+      asgn_insert_one(A, B, mod, u, s, kbase, ikeys, off, doff, drows, vb, cir, cnum);
   }
 }
 
@@ -1222,7 +1304,7 @@ extern "C" int spx_spasgn_plan(const spx_ctx* ctx, const spx_mat* A, const int32
   SPX_TRY(scr.get_n(1, &P->nbig_d));
   SPX_TRY(fill_i64((int64_t*)P->nbig_d, 1, 0, st));
   if (P->nmod > 0) {
-    k_asgn_keys<<<(unsigned)std::min<int64_t>(ceil_div(P->nmod, (int64_t)4), (int64_t)cus * 16), 256, 0, st>>>(
+    k_asgn_keys<<<(unsigned)std::min<int64_t>(ceil_div(P->nmod, (int64_t)16), (int64_t)cus * 16), 256, 0, st>>>(
         P->A, P->B, I, P->lastI, P->lastJ, P->mod, P->nmod, reinterpret_cast<const unsigned long long*>(P->dcnt),
         P->icnt, P->kbase, P->ikeys, P->cnt, P->big, P->nbig_d);
     SPX_HIP(hipGetLastError());
@@ -1274,13 +1356,12 @@ extern "C" int spx_spasgn_exec(spx_plan* plan, spx_mat* C) {
   const int cus = device_cu_count();
   SPX_TRY(launch_asgn_fill(P, vb, C->ir, C->num, st));
   if (P->nmod > 0) {
-    k_asgn_insert<false><<<(unsigned)std::min<int64_t>(ceil_div(P->nmod, (int64_t)4), (int64_t)cus * 16), 256, 0,
-                           st>>>(P->A, P->B, P->mod, nullptr, P->nmod, P->icnt, P->kbase, P->ikeys, P->off, P->doff,
-                                 P->drows, vb, C->ir, C->num);
+    k_asgn_insert<<<(unsigned)std::min<int64_t>(ceil_div(P->nmod, (int64_t)16), (int64_t)cus * 16), 256, 0, st>>>(
+        P->A, P->B, P->mod, P->nmod, P->icnt, P->kbase, P->ikeys, P->off, P->doff, P->drows, vb, C->ir, C->num);
     SPX_HIP(hipGetLastError());
   }
   if (P->nbig > 0) {
-    k_asgn_insert<true><<<(unsigned)std::min<int64_t>(P->nbig, (int64_t)cus * 4), 256, 0, st>>>(
+    k_asgn_insert_big<<<(unsigned)std::min<int64_t>(P->nbig, (int64_t)cus * 4), 256, 0, st>>>(
         P->A, P->B, P->mod, P->big, P->nbig, P->icnt, P->kbase, P->ikeys, P->off, P->doff, P->drows, vb, C->ir,
         C->num);
     SPX_HIP(hipGetLastError());
