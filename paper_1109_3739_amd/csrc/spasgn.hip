@@ -176,6 +176,10 @@ struct SpasgnPlan : spx_plan {
   int64_t* tmod = nullptr;    // [ntiles+1] modified columns before each tile (k_copy_tiles)
   int64_t ntiles = 0;
   int64_t* lastseg = nullptr; // [ntiles] dropped entries of each tile's last column
+  int64_t* colb = nullptr;    // [nmod] A's entry range of each modified column
+  int64_t* cole = nullptr;
+  int64_t* runshift = nullptr;  // [nmod+1] output shift of the unmodified run before modified column u
+  int64_t* mshift = nullptr;    // [nmod] off[j] - cp[j] of modified column u
   unsigned* err = nullptr;
   unsigned long long* nmod_d = nullptr;
 };
@@ -321,20 +325,31 @@ constexpr int kTileThreads = 256;
 constexpr int kTilePer = kTileItems / kTileThreads;
 
 // tmod[t] for t = 0..nt: modified column u owns the merged positions
-// (end(u-1) + u - 1, end(u) + u], and the tile starts among them.
-__global__ void k_copy_tiles(Operand A, const int32_t* mod, int64_t nmod, int64_t nt, int64_t* tmod) {
+// (end(u-1) + u - 1, end(u) + u], and the tile starts among them.  Also
+// records each modified column's entry range [colb[u], cole[u]).
+__global__ void k_copy_tiles(Operand A, const int32_t* mod, int64_t nmod, int64_t nt, int64_t* tmod, int64_t* colb,
+                             int64_t* cole) {
   for (int64_t u = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; u <= nmod; u += (int64_t)gridDim.x * blockDim.x) {
     const int64_t lo = u == 0 ? 0 : slot_begin(A, (int64_t)mod[u - 1] + 1) + u;
-    const int64_t hi = u == nmod ? INT64_MAX : slot_begin(A, (int64_t)mod[u] + 1) + u;
+    int64_t hi = INT64_MAX;
+    if (u < nmod) {
+      const int64_t c = mod[u];
+      const int64_t e = slot_begin(A, c + 1);
+      colb[u] = slot_begin(A, c);
+      cole[u] = e;
+      hi = e + u;
+    }
     for (int64_t t = (lo + kTileItems - 1) / kTileItems; t <= nt && t * kTileItems <= hi; ++t) tmod[t] = u;
   }
 }
 
 int copy_tiles(const Operand& A, const int32_t* mod, int64_t nmod, Scratch& scr, hipStream_t st, int64_t** tmod,
-               int64_t* ntiles) {
+               int64_t* ntiles, int64_t** colb, int64_t** cole) {
   const int64_t nt = ceil_div(A.nnz + nmod, (int64_t)kTileItems);
   SPX_TRY(scr.get_n(nt + 1, tmod));
-  k_copy_tiles<<<grid_for(nmod + 1, 256, 65536), 256, 0, st>>>(A, mod, nmod, nt, *tmod);
+  SPX_TRY(scr.get_n(std::max<int64_t>(nmod, 1), colb));
+  SPX_TRY(scr.get_n(std::max<int64_t>(nmod, 1), cole));
+  k_copy_tiles<<<grid_for(nmod + 1, 256, 65536), 256, 0, st>>>(A, mod, nmod, nt, *tmod, *colb, *cole);
   SPX_HIP(hipGetLastError());
   *ntiles = nt;
   return SPX_OK;
@@ -462,8 +477,8 @@ int launch_copy(const Operand& A, const int32_t* mod, int64_t nmod, const int64_
 // accumulated atomically, zero on entry) and, per tile, those of the last
 // column it meets (lastseg; 0 when that column starts after the tile).
 __global__ void __launch_bounds__(kTileThreads) k_asgn_drop_count(Operand A, const int32_t* lastI,
-                                                                  const int32_t* mod, int64_t nmod,
-                                                                  const int64_t* tmod, int64_t nt,
+                                                                  const int64_t* colb, const int64_t* cole,
+                                                                  int64_t nmod, const int64_t* tmod, int64_t nt,
                                                                   unsigned long long* dcnt, int64_t* lastseg) {
   __shared__ int32_t s_beg[kTileItems + 1];
   __shared__ int32_t s_end[kTileItems + 1];
@@ -471,9 +486,8 @@ __global__ void __launch_bounds__(kTileThreads) k_asgn_drop_count(Operand A, con
   for (int64_t t = blockIdx.x; t < nt; t += gridDim.x) {
     const TileSpan sp = tile_span(A, nmod, tmod, t);
     for (int32_t i = threadIdx.x; i < sp.nst; i += kTileThreads) {
-      const int64_t c = mod[sp.us + i];
-      s_beg[i] = tile_rel(slot_begin(A, c), sp.es);
-      s_end[i] = tile_rel(slot_begin(A, c + 1), sp.es);
+      s_beg[i] = tile_rel(colb[sp.us + i], sp.es);
+      s_end[i] = tile_rel(cole[sp.us + i], sp.es);
       s_cnt[i] = 0;
     }
     __syncthreads();
@@ -640,12 +654,25 @@ __global__ void __launch_bounds__(256) k_asgn_huge_keys(Operand B, const int32_t
   }
 }
 
+// Output shifts for the fill tiles: runshift[u] = off[c0] - cp[c0] for the
+// run of unmodified columns c0 = mod[u-1] + 1 .. mod[u] - 1, and
+// mshift[u] = off[mod[u]] - cp[mod[u]].
+__global__ void k_asgn_shifts(Operand A, const int32_t* mod, int64_t nmod, const int64_t* off, const int64_t* colb,
+                              int64_t* runshift, int64_t* mshift) {
+  for (int64_t u = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; u <= nmod; u += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t c0 = u == 0 ? 0 : (int64_t)mod[u - 1] + 1;
+    runshift[u] = off[c0] - slot_begin(A, c0);
+    if (u < nmod) mshift[u] = off[mod[u]] - colb[u];
+  }
+}
+
 // Fill pass over the tiles: unmodified runs are copied with their output
 // shift; entries of modified columns are kept or dropped as described above.
 template <int VB>
-__global__ void __launch_bounds__(kTileThreads) k_asgn_fill(Operand A, const int32_t* lastI, const int32_t* mod,
-                                                            int64_t nmod, const int64_t* tmod, int64_t nt,
-                                                            const int64_t* lastseg, const int64_t* off,
+__global__ void __launch_bounds__(kTileThreads) k_asgn_fill(Operand A, const int32_t* lastI, const int64_t* colb,
+                                                            const int64_t* cole, const int64_t* runshift,
+                                                            const int64_t* mshift, int64_t nmod, const int64_t* tmod,
+                                                            int64_t nt, const int64_t* lastseg,
                                                             const int64_t* icnt, const int64_t* kbase,
                                                             const uint64_t* ikeys, const int64_t* doff,
                                                             int32_t* drows, int32_t* cir, void* cnum) {
@@ -666,14 +693,12 @@ __global__ void __launch_bounds__(kTileThreads) k_asgn_fill(Operand A, const int
     const TileSpan sp = tile_span(A, nmod, tmod, t);
     for (int64_t i = threadIdx.x; i <= sp.ue - sp.us; i += kTileThreads) {
       const int64_t r = sp.us + i;
-      const int64_t c0 = r == 0 ? 0 : (int64_t)mod[r - 1] + 1;
-      s_shift[i] = off[c0] - slot_begin(A, c0);
+      s_shift[i] = runshift[r];
       if (i < sp.nst) {
-        const int64_t c = mod[r];
-        const int64_t cb = slot_begin(A, c);
+        const int64_t cb = colb[r];
         s_beg[i] = (int16_t)tile_rel(cb, sp.es);
-        s_end[i] = (int16_t)tile_rel(slot_begin(A, c + 1), sp.es);
-        s_mshift[i] = off[c] - cb;
+        s_end[i] = (int16_t)tile_rel(cole[r], sp.es);
+        s_mshift[i] = mshift[r];
         if (i == 0) s_a0 = cb;
       }
     }
@@ -693,6 +718,7 @@ __global__ void __launch_bounds__(kTileThreads) k_asgn_fill(Operand A, const int
     V val[kTilePer];
     int64_t nkey[kTilePer];
     const uint64_t* keys[kTilePer];
+    int32_t ins[kTilePer];  // inserted rows below a kept entry's row (short key lists)
 #pragma unroll
     for (int k = 0; k < kTilePer; ++k) {
       const int32_t x = threadIdx.x + k * kTileThreads;
@@ -711,6 +737,12 @@ __global__ void __launch_bounds__(kTileThreads) k_asgn_fill(Operand A, const int
 #pragma unroll
     for (int k = 0; k < kTilePer; ++k) {
       drop[k] = inmod[k] && lastI[row[k]] >= 0;
+      ins[k] = 0;
+      if (inmod[k] && nkey[k] <= 8) {  // independent loads, issued with lastI's
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+          if (q < nkey[k]) ins[k] += (int32_t)(keys[k][q] >> 32) < row[k] ? 1 : 0;
+      }
       const uint64_t m = __ballot(drop[k]);
       ex[k] = __popcll(m & lanemask_lt());
       if (lane == 0) s_wt[k][wid] = __popcll(m);
@@ -745,7 +777,8 @@ __global__ void __launch_bounds__(kTileThreads) k_asgn_fill(Operand A, const int
           continue;
         }
         // inserted rows below this row
-        int64_t a = 0, b = nkey[k];
+        int64_t a = 0, b = nkey[k] <= 8 ? 0 : nkey[k];
+        if (b == 0) a = ins[k];
         while (a < b) {
           const int64_t mid = (a + b) >> 1;
           if ((int32_t)(keys[k][mid] >> 32) < row[k])
@@ -820,8 +853,9 @@ int launch_asgn_fill(const SpasgnPlan* P, int vb, int32_t* cir, void* cnum, hipS
   if (P->ntiles == 0) return SPX_OK;
   const unsigned grid = (unsigned)std::min<int64_t>(P->ntiles, (int64_t)device_cu_count() * 32);
 #define SPX_ASGN_FILL(VB)                                                                                          \
-  k_asgn_fill<VB><<<grid, kTileThreads, 0, st>>>(P->A, P->lastI, P->mod, P->nmod, P->tmod, P->ntiles, P->lastseg, \
-                                                 P->off, P->icnt, P->kbase, P->ikeys, P->doff, P->drows, cir, cnum)
+  k_asgn_fill<VB><<<grid, kTileThreads, 0, st>>>(P->A, P->lastI, P->colb, P->cole, P->runshift, P->mshift,       \
+                                                 P->nmod, P->tmod, P->ntiles, P->lastseg, P->icnt, P->kbase,      \
+                                                 P->ikeys, P->doff, P->drows, cir, cnum)
   if (vb == 8)
     SPX_ASGN_FILL(8);
   else if (vb == 4)
@@ -866,6 +900,8 @@ struct ExtAddPlan : spx_plan {
   int64_t nhuge_keys = 0;
   int64_t* tmod = nullptr;    // [ntiles+1] modified columns before each copy tile (k_copy_tiles)
   int64_t ntiles = 0;
+  int64_t* colb = nullptr;    // [nmod] A's entry range of each modified column
+  int64_t* cole = nullptr;
   unsigned* err = nullptr;
   unsigned long long* nmod_d = nullptr;
 };
@@ -1285,14 +1321,14 @@ extern "C" int spx_spasgn_plan(const spx_ctx* ctx, const spx_mat* A, const int32
   if (err_h & 1u) return fail(SPX_EINVAL, "I has an index outside [0, m)");
   if (err_h & 2u) return fail(SPX_EINVAL, "J has an index outside [0, n)");
   P->nmod = (int64_t)nmod_h;
-  SPX_TRY(copy_tiles(P->A, P->mod, P->nmod, scr, st, &P->tmod, &P->ntiles));
+  SPX_TRY(copy_tiles(P->A, P->mod, P->nmod, scr, st, &P->tmod, &P->ntiles, &P->colb, &P->cole));
   SPX_TRY(scr.get_n(std::max<int64_t>(P->nmod, 1), &P->dcnt));
   SPX_TRY(scr.get_n(std::max<int64_t>(P->ntiles, 1), &P->lastseg));
   SPX_TRY(fill_i64(P->dcnt, P->nmod, 0, st));
   if (P->nmod > 0 && P->ntiles > 0) {
     k_asgn_drop_count<<<(unsigned)std::min<int64_t>(P->ntiles, (int64_t)cus * 32), kTileThreads, 0, st>>>(
-        P->A, P->lastI, P->mod, P->nmod, P->tmod, P->ntiles, reinterpret_cast<unsigned long long*>(P->dcnt),
-        P->lastseg);
+        P->A, P->lastI, P->colb, P->cole, P->nmod, P->tmod, P->ntiles,
+        reinterpret_cast<unsigned long long*>(P->dcnt), P->lastseg);
     SPX_HIP(hipGetLastError());
   }
   SPX_TRY(scr.get_n(P->nmod + 1, &P->doff));
@@ -1313,6 +1349,11 @@ extern "C" int spx_spasgn_plan(const spx_ctx* ctx, const spx_mat* A, const int32
   SPX_TRY(exclusive_scan(LoadI64{P->dcnt}, P->nmod, P->doff, scr, st));
   // key segments of the huge columns (big-list order; entries past nbig are empty)
   SPX_TRY(exclusive_scan(HugeCap{P->icnt, P->big, P->nbig_d}, P->nmod, P->hoff, scr, st));
+  SPX_TRY(scr.get_n(P->nmod + 1, &P->runshift));
+  SPX_TRY(scr.get_n(std::max<int64_t>(P->nmod, 1), &P->mshift));
+  k_asgn_shifts<<<grid_for(P->nmod + 1, 256, 65536), 256, 0, st>>>(P->A, P->mod, P->nmod, P->off, P->colb,
+                                                                   P->runshift, P->mshift);
+  SPX_HIP(hipGetLastError());
   int64_t tail[4] = {0, 0, 0, 0};
   SPX_HIP(hipMemcpyAsync(&tail[0], P->off + n, 8, hipMemcpyDeviceToHost, st));
   SPX_HIP(hipMemcpyAsync(&tail[1], P->doff + P->nmod, 8, hipMemcpyDeviceToHost, st));
@@ -1434,7 +1475,7 @@ extern "C" int spx_extend_add_plan(const spx_ctx* ctx, const spx_mat* A, const i
   if (err_h & 1u) return fail(SPX_EINVAL, "I has an index outside [0, m)");
   if (err_h & 2u) return fail(SPX_EINVAL, "J has an index outside [0, n)");
   P->nmod = (int64_t)nmod_h;
-  SPX_TRY(copy_tiles(P->A, P->mod, P->nmod, scr, st, &P->tmod, &P->ntiles));
+  SPX_TRY(copy_tiles(P->A, P->mod, P->nmod, scr, st, &P->tmod, &P->ntiles, &P->colb, &P->cole));
   SPX_TRY(scr.get_n(n + 1, &P->qoff));
   SPX_TRY(scr.get_n(std::max<int64_t>(lenJ, 1), &P->qlist));
   SPX_TRY(exclusive_scan(LoadI32{P->qcnt}, n, P->qoff, scr, st));
