@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <initializer_list>
 #include <string>
 #include <vector>
 
@@ -75,6 +76,17 @@ class Scratch {
     *out = static_cast<T*>(p);
     return rc;
   }
+  // One allocation carved into several arrays (each 256-byte aligned), so
+  // that a plan's arrays of one phase cost a single allocator call.
+  struct Part {
+    void** out;
+    size_t bytes;
+  };
+  template <typename T>
+  static Part part(T** out, int64_t count) {
+    return {reinterpret_cast<void**>(out), (size_t)(count > 0 ? count : 0) * sizeof(T) + 16};
+  }
+  int get_many(std::initializer_list<Part> parts);
   void release_all();
   hipStream_t stream() const { return stream_; }
 
@@ -97,6 +109,15 @@ int device_cu_count();
 // library can be captured into a HIP graph).
 int fill_i64(int64_t* p, int64_t n, int64_t v, hipStream_t stream);
 int fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t stream);
+
+// Reads up to 8 device scalars of 4 or 8 bytes (4-byte ones zero-extended)
+// with one kernel that writes them to this thread's pinned host words, and
+// waits for the stream: one launch instead of a copy per scalar.
+struct DevWord {
+  const void* p;
+  int bytes;
+};
+int read_device_words(hipStream_t stream, std::initializer_list<DevWord> words, int64_t* out);
 
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 inline int64_t next_pow2(int64_t x) {

@@ -346,9 +346,7 @@ __global__ void k_copy_tiles(Operand A, const int32_t* mod, int64_t nmod, int64_
 int copy_tiles(const Operand& A, const int32_t* mod, int64_t nmod, Scratch& scr, hipStream_t st, int64_t** tmod,
                int64_t* ntiles, int64_t** colb, int64_t** cole) {
   const int64_t nt = ceil_div(A.nnz + nmod, (int64_t)kTileItems);
-  SPX_TRY(scr.get_n(nt + 1, tmod));
-  SPX_TRY(scr.get_n(std::max<int64_t>(nmod, 1), colb));
-  SPX_TRY(scr.get_n(std::max<int64_t>(nmod, 1), cole));
+  SPX_TRY(scr.get_many({Scratch::part(tmod, nt + 1), Scratch::part(colb, nmod), Scratch::part(cole, nmod)}));
   k_copy_tiles<<<grid_for(nmod + 1, 256, 65536), 256, 0, st>>>(A, mod, nmod, nt, *tmod, *colb, *cole);
   SPX_HIP(hipGetLastError());
   *ntiles = nt;
@@ -1293,12 +1291,11 @@ extern "C" int spx_spasgn_plan(const spx_ctx* ctx, const spx_mat* A, const int32
   P->lenJ = lenJ;
   const int64_t m = A->m, n = A->n;
   const int cus = device_cu_count();
-  SPX_TRY(scr.get_n(4, &P->err));
+  SPX_TRY(scr.get_many({Scratch::part(&P->err, 4), Scratch::part(&P->nmod_d, 1), Scratch::part(&P->lastI, m),
+                        Scratch::part(&P->lastJ, n), Scratch::part(&P->cnt, n), Scratch::part(&P->off, n + 1),
+                        Scratch::part(&P->mod, n)}));
   SPX_TRY(fill_u32(P->err, 1, 0, st));
-  SPX_TRY(scr.get_n(1, &P->nmod_d));
   SPX_TRY(fill_i64((int64_t*)P->nmod_d, 1, 0, st));
-  SPX_TRY(scr.get_n(std::max<int64_t>(m, 1), &P->lastI));
-  SPX_TRY(scr.get_n(std::max<int64_t>(n, 1), &P->lastJ));
   SPX_TRY(fill_u32((uint32_t*)P->lastI, m, 0xffffffffu, st));
   SPX_TRY(fill_u32((uint32_t*)P->lastJ, n, 0xffffffffu, st));
   if (lenI > 0) {
@@ -1309,21 +1306,19 @@ extern "C" int spx_spasgn_plan(const spx_ctx* ctx, const spx_mat* A, const int32
     k_last_occ<<<grid_for(lenJ, 256, 4096), 256, 0, st>>>(J, lenJ, n, P->lastJ, P->err, 2u);
     SPX_HIP(hipGetLastError());
   }
-  SPX_TRY(scr.get_n(std::max<int64_t>(n, 1), &P->cnt));
-  SPX_TRY(scr.get_n(n + 1, &P->off));
-  SPX_TRY(scr.get_n(std::max<int64_t>(n, 1), &P->mod));
   SPX_TRY(list_modified(P->A, P->lastJ, P->cnt, P->mod, P->nmod_d, scr, st));
-  unsigned long long nmod_h = 0;
-  unsigned err_h = 0;
-  SPX_HIP(hipMemcpyAsync(&nmod_h, P->nmod_d, 8, hipMemcpyDeviceToHost, st));
-  SPX_HIP(hipMemcpyAsync(&err_h, P->err, 4, hipMemcpyDeviceToHost, st));
-  SPX_HIP(hipStreamSynchronize(st));
-  if (err_h & 1u) return fail(SPX_EINVAL, "I has an index outside [0, m)");
-  if (err_h & 2u) return fail(SPX_EINVAL, "J has an index outside [0, n)");
-  P->nmod = (int64_t)nmod_h;
+  int64_t h1[2] = {0, 0};
+  SPX_TRY(read_device_words(st, {{P->nmod_d, 8}, {P->err, 4}}, h1));
+  if (h1[1] & 1) return fail(SPX_EINVAL, "I has an index outside [0, m)");
+  if (h1[1] & 2) return fail(SPX_EINVAL, "J has an index outside [0, n)");
+  P->nmod = h1[0];
   SPX_TRY(copy_tiles(P->A, P->mod, P->nmod, scr, st, &P->tmod, &P->ntiles, &P->colb, &P->cole));
-  SPX_TRY(scr.get_n(std::max<int64_t>(P->nmod, 1), &P->dcnt));
-  SPX_TRY(scr.get_n(std::max<int64_t>(P->ntiles, 1), &P->lastseg));
+  const int64_t nm = P->nmod;
+  SPX_TRY(scr.get_many({Scratch::part(&P->dcnt, nm), Scratch::part(&P->lastseg, P->ntiles),
+                        Scratch::part(&P->doff, nm + 1), Scratch::part(&P->icnt, nm), Scratch::part(&P->kbase, nm),
+                        Scratch::part(&P->ikeys, P->B.nnz), Scratch::part(&P->big, nm),
+                        Scratch::part(&P->hoff, nm + 1), Scratch::part(&P->nbig_d, 1),
+                        Scratch::part(&P->runshift, nm + 1), Scratch::part(&P->mshift, nm)}));
   SPX_TRY(fill_i64(P->dcnt, P->nmod, 0, st));
   if (P->nmod > 0 && P->ntiles > 0) {
     k_asgn_drop_count<<<(unsigned)std::min<int64_t>(P->ntiles, (int64_t)cus * 32), kTileThreads, 0, st>>>(
@@ -1331,13 +1326,6 @@ extern "C" int spx_spasgn_plan(const spx_ctx* ctx, const spx_mat* A, const int32
         reinterpret_cast<unsigned long long*>(P->dcnt), P->lastseg);
     SPX_HIP(hipGetLastError());
   }
-  SPX_TRY(scr.get_n(P->nmod + 1, &P->doff));
-  SPX_TRY(scr.get_n(std::max<int64_t>(P->nmod, 1), &P->icnt));
-  SPX_TRY(scr.get_n(std::max<int64_t>(P->nmod, 1), &P->kbase));
-  SPX_TRY(scr.get_n(std::max<int64_t>(P->B.nnz, 1), &P->ikeys));
-  SPX_TRY(scr.get_n(std::max<int64_t>(P->nmod, 1), &P->big));
-  SPX_TRY(scr.get_n(P->nmod + 1, &P->hoff));
-  SPX_TRY(scr.get_n(1, &P->nbig_d));
   SPX_TRY(fill_i64((int64_t*)P->nbig_d, 1, 0, st));
   if (P->nmod > 0) {
     k_asgn_keys<<<(unsigned)std::min<int64_t>(ceil_div(P->nmod, (int64_t)16), (int64_t)cus * 16), 256, 0, st>>>(
@@ -1349,17 +1337,12 @@ extern "C" int spx_spasgn_plan(const spx_ctx* ctx, const spx_mat* A, const int32
   SPX_TRY(exclusive_scan(LoadI64{P->dcnt}, P->nmod, P->doff, scr, st));
   // key segments of the huge columns (big-list order; entries past nbig are empty)
   SPX_TRY(exclusive_scan(HugeCap{P->icnt, P->big, P->nbig_d}, P->nmod, P->hoff, scr, st));
-  SPX_TRY(scr.get_n(P->nmod + 1, &P->runshift));
-  SPX_TRY(scr.get_n(std::max<int64_t>(P->nmod, 1), &P->mshift));
   k_asgn_shifts<<<grid_for(P->nmod + 1, 256, 65536), 256, 0, st>>>(P->A, P->mod, P->nmod, P->off, P->colb,
                                                                    P->runshift, P->mshift);
   SPX_HIP(hipGetLastError());
   int64_t tail[4] = {0, 0, 0, 0};
-  SPX_HIP(hipMemcpyAsync(&tail[0], P->off + n, 8, hipMemcpyDeviceToHost, st));
-  SPX_HIP(hipMemcpyAsync(&tail[1], P->doff + P->nmod, 8, hipMemcpyDeviceToHost, st));
-  SPX_HIP(hipMemcpyAsync(&tail[2], P->nbig_d, 8, hipMemcpyDeviceToHost, st));
-  SPX_HIP(hipMemcpyAsync(&tail[3], P->hoff + P->nmod, 8, hipMemcpyDeviceToHost, st));
-  SPX_HIP(hipStreamSynchronize(st));
+  SPX_TRY(read_device_words(st, {{P->off + n, 8}, {P->doff + P->nmod, 8}, {P->nbig_d, 8}, {P->hoff + P->nmod, 8}},
+                            tail));
   P->nnz = tail[0];
   P->ndrop = tail[1];
   P->nbig = tail[2];
@@ -1445,12 +1428,12 @@ extern "C" int spx_extend_add_plan(const spx_ctx* ctx, const spx_mat* A, const i
   P->lenJ = lenJ;
   P->sr = semiring;
   const int64_t m = A->m, n = A->n;
-  SPX_TRY(scr.get_n(4, &P->err));
+  SPX_TRY(scr.get_many({Scratch::part(&P->err, 4), Scratch::part(&P->nmod_d, 1), Scratch::part(&P->lastJ, n),
+                        Scratch::part(&P->qcnt, n), Scratch::part(&P->cnt, n), Scratch::part(&P->off, n + 1),
+                        Scratch::part(&P->mod, n), Scratch::part(&P->qoff, n + 1),
+                        Scratch::part(&P->qlist, lenJ)}));
   SPX_TRY(fill_u32(P->err, 1, 0, st));
-  SPX_TRY(scr.get_n(1, &P->nmod_d));
   SPX_TRY(fill_i64((int64_t*)P->nmod_d, 1, 0, st));
-  SPX_TRY(scr.get_n(std::max<int64_t>(n, 1), &P->lastJ));
-  SPX_TRY(scr.get_n(std::max<int64_t>(n, 1), &P->qcnt));
   SPX_TRY(fill_u32((uint32_t*)P->lastJ, n, 0xffffffffu, st));
   SPX_TRY(fill_u32((uint32_t*)P->qcnt, n, 0u, st));
   if (lenI > 0) {
@@ -1463,31 +1446,21 @@ extern "C" int spx_extend_add_plan(const spx_ctx* ctx, const spx_mat* A, const i
     k_count_q<<<grid_for(lenJ, 256, 4096), 256, 0, st>>>(J, lenJ, n, P->qcnt);
     SPX_HIP(hipGetLastError());
   }
-  SPX_TRY(scr.get_n(std::max<int64_t>(n, 1), &P->cnt));
-  SPX_TRY(scr.get_n(n + 1, &P->off));
-  SPX_TRY(scr.get_n(std::max<int64_t>(n, 1), &P->mod));
   SPX_TRY(list_modified(P->A, P->lastJ, P->cnt, P->mod, P->nmod_d, scr, st));
-  unsigned long long nmod_h = 0;
-  unsigned err_h = 0;
-  SPX_HIP(hipMemcpyAsync(&nmod_h, P->nmod_d, 8, hipMemcpyDeviceToHost, st));
-  SPX_HIP(hipMemcpyAsync(&err_h, P->err, 4, hipMemcpyDeviceToHost, st));
-  SPX_HIP(hipStreamSynchronize(st));
-  if (err_h & 1u) return fail(SPX_EINVAL, "I has an index outside [0, m)");
-  if (err_h & 2u) return fail(SPX_EINVAL, "J has an index outside [0, n)");
-  P->nmod = (int64_t)nmod_h;
+  int64_t h1[2] = {0, 0};
+  SPX_TRY(read_device_words(st, {{P->nmod_d, 8}, {P->err, 4}}, h1));
+  if (h1[1] & 1) return fail(SPX_EINVAL, "I has an index outside [0, m)");
+  if (h1[1] & 2) return fail(SPX_EINVAL, "J has an index outside [0, n)");
+  P->nmod = h1[0];
   SPX_TRY(copy_tiles(P->A, P->mod, P->nmod, scr, st, &P->tmod, &P->ntiles, &P->colb, &P->cole));
-  SPX_TRY(scr.get_n(n + 1, &P->qoff));
-  SPX_TRY(scr.get_n(std::max<int64_t>(lenJ, 1), &P->qlist));
   SPX_TRY(exclusive_scan(LoadI32{P->qcnt}, n, P->qoff, scr, st));
   if (lenJ > 0) {
     k_scatter_q<<<grid_for(lenJ, 256, 4096), 256, 0, st>>>(J, lenJ, P->qoff, P->qcnt, P->qlist);
     SPX_HIP(hipGetLastError());
   }
-  SPX_TRY(scr.get_n(std::max<int64_t>(P->nmod, 1), &P->big));
-  SPX_TRY(scr.get_n(std::max<int64_t>(P->nmod, 1), &P->hcnt));
-  SPX_TRY(scr.get_n(P->nmod + 1, &P->hoff));
-  SPX_TRY(scr.get_n(std::max<int64_t>(P->nmod, 1), &P->rest));
-  SPX_TRY(scr.get_n(2, &P->nbig_d));
+  SPX_TRY(scr.get_many({Scratch::part(&P->rest, P->nmod), Scratch::part(&P->big, P->nmod),
+                        Scratch::part(&P->hcnt, P->nmod), Scratch::part(&P->hoff, P->nmod + 1),
+                        Scratch::part(&P->nbig_d, 2)}));
   P->nrest_d = P->nbig_d + 1;
   SPX_TRY(fill_i64((int64_t*)P->nbig_d, 2, 0, st));
   if (P->nmod > 0) SPX_TRY(dispatch_ea<false>(P, nullptr, nullptr, st, false));
@@ -1495,18 +1468,15 @@ extern "C" int spx_extend_add_plan(const spx_ctx* ctx, const spx_mat* A, const i
   SPX_TRY(exclusive_scan(HugeCap{P->hcnt, nullptr, P->nbig_d}, P->nmod, P->hoff, scr, st));
   {
     int64_t h[3] = {0, 0, 0};
-    SPX_HIP(hipMemcpyAsync(&h[0], P->nbig_d, 16, hipMemcpyDeviceToHost, st));
-    SPX_HIP(hipMemcpyAsync(&h[2], P->hoff + P->nmod, 8, hipMemcpyDeviceToHost, st));
-    SPX_HIP(hipStreamSynchronize(st));
+    SPX_TRY(read_device_words(st, {{P->nbig_d, 8}, {P->nbig_d + 1, 8}, {P->hoff + P->nmod, 8}}, h));
     P->nbig = h[0];
     P->nrest = h[1];
     P->nhuge_keys = h[2];
   }
   if (P->nhuge_keys > 0) {
     if (P->nhuge_keys >= (1ll << 31)) return fail(SPX_EUNSUPPORTED, "landing entries of the large columns exceed 2^31");
-    SPX_TRY(scr.get_n(P->nhuge_keys, &P->hkeys));
-    SPX_TRY(scr.get_n(P->nhuge_keys + P->nbig, &P->hhead));
-    SPX_TRY(scr.get_n(P->nhuge_keys + P->nbig, &P->hnin));
+    SPX_TRY(scr.get_many({Scratch::part(&P->hkeys, P->nhuge_keys), Scratch::part(&P->hhead, P->nhuge_keys + P->nbig),
+                          Scratch::part(&P->hnin, P->nhuge_keys + P->nbig)}));
     const int cus = device_cu_count();
     k_ea_huge_keys<<<(unsigned)std::min<int64_t>(P->nbig, (int64_t)cus * 2), 256, 0, st>>>(
         P->B, I, P->mod, P->big, P->nbig, P->qoff, P->qlist, P->hoff, P->hkeys);
@@ -1515,8 +1485,7 @@ extern "C" int spx_extend_add_plan(const spx_ctx* ctx, const spx_mat* A, const i
   }
   SPX_TRY(exclusive_scan(LoadI64{P->cnt}, n, P->off, scr, st));
   int64_t total = 0;
-  SPX_HIP(hipMemcpyAsync(&total, P->off + n, 8, hipMemcpyDeviceToHost, st));
-  SPX_HIP(hipStreamSynchronize(st));
+  SPX_TRY(read_device_words(st, {{P->off + n, 8}}, &total));
   P->nnz = total;
   if (nnz_c) *nnz_c = P->nnz;
   *plan = guard.release();

@@ -351,7 +351,13 @@ extern "C" int spx_spref_plan(const spx_ctx* ctx, const spx_mat* A, const int32_
   P->lenJ = lenJ;
   const int64_t m = A->m;
   const int cus = device_cu_count();
-  SPX_TRY(scr.get_n(4, &P->err));
+  unsigned* rcnt = nullptr;
+  unsigned long long *clscount = nullptr, *fill = nullptr;
+  SPX_TRY(scr.get_many({Scratch::part(&P->err, 4), Scratch::part(&rcnt, m + 1), Scratch::part(&P->rptr, m + 1),
+                        Scratch::part(&P->rpos, lenI), Scratch::part(&P->qa0, lenJ), Scratch::part(&P->qlen, lenJ),
+                        Scratch::part(&P->cnt, lenJ), Scratch::part(&P->off, lenJ + 1), Scratch::part(&P->list, lenJ),
+                        Scratch::part(&P->clsoff, kNumCls + 1), Scratch::part(&clscount, kNumCls),
+                        Scratch::part(&fill, kNumCls)}));
   SPX_TRY(fill_u32(P->err, 1, 0, st));
   if (lenI > 0) {
     k_check_index<<<grid_for(lenI, 256, 4096), 256, 0, st>>>(I, lenI, m, P->err, 1u);
@@ -362,11 +368,7 @@ extern "C" int spx_spref_plan(const spx_ctx* ctx, const spx_mat* A, const int32_
     SPX_HIP(hipGetLastError());
   }
   // transpose of R: rows of I grouped by index, positions ascending
-  unsigned* rcnt = nullptr;
-  SPX_TRY(scr.get_n(m + 1, &rcnt));
   SPX_TRY(fill_u32(rcnt, m + 1, 0, st));
-  SPX_TRY(scr.get_n(m + 1, &P->rptr));
-  SPX_TRY(scr.get_n(std::max<int64_t>(lenI, 1), &P->rpos));
   if (lenI > 0) {
     k_row_hist<<<grid_for(lenI, 256, 4096), 256, 0, st>>>(I, lenI, m, rcnt);
     SPX_HIP(hipGetLastError());
@@ -382,15 +384,6 @@ extern "C" int spx_spref_plan(const spx_ctx* ctx, const spx_mat* A, const int32_
   // A*Q: the columns J(q) of A
   int64_t *aux = nullptr, chunk = 1;
   SPX_TRY(build_aux(P->A, scr, st, &aux, &chunk));
-  SPX_TRY(scr.get_n(std::max<int64_t>(lenJ, 1), &P->qa0));
-  SPX_TRY(scr.get_n(std::max<int64_t>(lenJ, 1), &P->qlen));
-  SPX_TRY(scr.get_n(std::max<int64_t>(lenJ, 1), &P->cnt));
-  SPX_TRY(scr.get_n(lenJ + 1, &P->off));
-  SPX_TRY(scr.get_n(std::max<int64_t>(lenJ, 1), &P->list));
-  SPX_TRY(scr.get_n(kNumCls + 1, &P->clsoff));
-  unsigned long long *clscount = nullptr, *fill = nullptr;
-  SPX_TRY(scr.get_n(kNumCls, &clscount));
-  SPX_TRY(scr.get_n(kNumCls, &fill));
   SPX_TRY(fill_i64((int64_t*)clscount, kNumCls, 0, st));
   if (lenJ > 0) {
     k_col_info<<<grid_for(lenJ, 256, 4096), 256, 0, st>>>(P->A, aux, chunk, J, lenJ, P->qa0, P->qlen);
@@ -406,14 +399,15 @@ extern "C" int spx_spref_plan(const spx_ctx* ctx, const spx_mat* A, const int32_
     SPX_HIP(hipGetLastError());
   }
   SPX_TRY(exclusive_scan(LoadI64{P->cnt}, lenJ, P->off, scr, st));
-  unsigned err_h = 0;
-  int64_t nnz = 0;
-  SPX_HIP(hipMemcpyAsync(P->clsoff_h, P->clsoff, sizeof(P->clsoff_h), hipMemcpyDeviceToHost, st));
-  SPX_HIP(hipMemcpyAsync(&nnz, P->off + lenJ, 8, hipMemcpyDeviceToHost, st));
-  SPX_HIP(hipMemcpyAsync(&err_h, P->err, 4, hipMemcpyDeviceToHost, st));
-  SPX_HIP(hipStreamSynchronize(st));
-  if (err_h & 1u) return fail(SPX_EINVAL, "I has an index outside [0, m)");
-  if (err_h & 2u) return fail(SPX_EINVAL, "J has an index outside [0, n)");
+  static_assert(kNumCls + 1 == 5, "the read below takes the class offsets as five words");
+  int64_t h[7] = {};
+  const int64_t* co = P->clsoff;
+  SPX_TRY(read_device_words(st, {{co, 8}, {co + 1, 8}, {co + 2, 8}, {co + 3, 8}, {co + 4, 8}, {P->off + lenJ, 8},
+                                 {P->err, 4}}, h));
+  if (h[6] & 1) return fail(SPX_EINVAL, "I has an index outside [0, m)");
+  if (h[6] & 2) return fail(SPX_EINVAL, "J has an index outside [0, n)");
+  for (int c = 0; c <= kNumCls; ++c) P->clsoff_h[c] = h[c];
+  const int64_t nnz = h[5];
   P->nnz = nnz;
   if (nnz_b) *nnz_b = nnz;
   *plan = guard.release();
