@@ -194,10 +194,27 @@ __global__ void k_last_occ(const int32_t* v, int64_t len, int64_t bound, int32_t
   }
 }
 
-// Unmodified columns keep their length (modified ones are counted later).
-__global__ void k_asgn_cols(Operand A, const int32_t* lastJ, int64_t* cnt) {
-  for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < A.n; j += (int64_t)gridDim.x * blockDim.x)
-    cnt[j] = lastJ[j] >= 0 ? 0 : slot_begin(A, j + 1) - slot_begin(A, j);
+// Unmodified columns keep their length (modified ones are counted later);
+// *modent (when given) accumulates the entries of the modified columns.
+__global__ void k_asgn_cols(Operand A, const int32_t* lastJ, int64_t* cnt, unsigned long long* modent) {
+  int64_t mine = 0;
+  for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < A.n; j += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t len = slot_begin(A, j + 1) - slot_begin(A, j);
+    const bool m = lastJ[j] >= 0;
+    cnt[j] = m ? 0 : len;
+    mine += m ? len : 0;
+  }
+  if (modent) {  // one atomic per workgroup
+    __shared__ int64_t red[256 / kWave];
+    mine = wave_sum(mine);
+    if (lane_id() == 0) red[threadIdx.x / kWave] = mine;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int64_t t = 0;
+      for (int w = 0; w < (int)(blockDim.x / kWave); ++w) t += red[w];
+      if (t) atomicAdd(modent, (unsigned long long)t);
+    }
+  }
 }
 
 // 1 for a column that receives B's entries.
@@ -214,13 +231,11 @@ __global__ void k_list_modified(const int32_t* lastJ, int64_t n, const int64_t* 
 
 // Lists the modified columns and leaves their number in *nmod.
 int list_modified(const Operand& A, const int32_t* lastJ, int64_t* cnt, int32_t* mod, unsigned long long* nmod,
-                  Scratch& scr, hipStream_t st) {
+                  int64_t* pos, unsigned long long* modent, Scratch& scr, hipStream_t st) {
   const int64_t n = A.n;
   if (n == 0) return fill_i64(reinterpret_cast<int64_t*>(nmod), 1, 0, st);
-  k_asgn_cols<<<grid_for(n, 256, 65536), 256, 0, st>>>(A, lastJ, cnt);
+  k_asgn_cols<<<grid_for(n, 256, (int64_t)device_cu_count() * 4), 256, 0, st>>>(A, lastJ, cnt, modent);
   SPX_HIP(hipGetLastError());
-  int64_t* pos = nullptr;
-  SPX_TRY(scr.get_n(n + 1, &pos));
   SPX_TRY(exclusive_scan(LoadModified{lastJ}, n, pos, scr, st));
   k_list_modified<<<grid_for(n, 256, 65536), 256, 0, st>>>(lastJ, n, pos, mod);
   SPX_HIP(hipGetLastError());
@@ -343,13 +358,14 @@ __global__ void k_copy_tiles(Operand A, const int32_t* mod, int64_t nmod, int64_
   }
 }
 
-int copy_tiles(const Operand& A, const int32_t* mod, int64_t nmod, Scratch& scr, hipStream_t st, int64_t** tmod,
-               int64_t* ntiles, int64_t** colb, int64_t** cole) {
-  const int64_t nt = ceil_div(A.nnz + nmod, (int64_t)kTileItems);
-  SPX_TRY(scr.get_many({Scratch::part(tmod, nt + 1), Scratch::part(colb, nmod), Scratch::part(cole, nmod)}));
-  k_copy_tiles<<<grid_for(nmod + 1, 256, 65536), 256, 0, st>>>(A, mod, nmod, nt, *tmod, *colb, *cole);
+// Number of merged-order tiles of A with nmod modified columns.
+inline int64_t tile_count(const Operand& A, int64_t nmod) { return ceil_div(A.nnz + nmod, (int64_t)kTileItems); }
+
+// tmod[0..nt], colb and cole[0..nmod) are the caller's.
+int copy_tiles(const Operand& A, const int32_t* mod, int64_t nmod, int64_t nt, int64_t* tmod, int64_t* colb,
+               int64_t* cole, hipStream_t st) {
+  k_copy_tiles<<<grid_for(nmod + 1, 256, 65536), 256, 0, st>>>(A, mod, nmod, nt, tmod, colb, cole);
   SPX_HIP(hipGetLastError());
-  *ntiles = nt;
   return SPX_OK;
 }
 
@@ -368,6 +384,7 @@ __device__ __forceinline__ TileSpan tile_span(const Operand& A, int64_t nmod, co
   s.nst = (int32_t)(std::min<int64_t>(s.ue, nmod - 1) - s.us + 1);
   return s;
 }
+
 
 // Entry position relative to the tile, clamped to [0, kTileItems] (which
 // keeps every comparison with an in-tile position).
@@ -716,7 +733,6 @@ __global__ void __launch_bounds__(kTileThreads) k_asgn_fill(Operand A, const int
     V val[kTilePer];
     int64_t nkey[kTilePer];
     const uint64_t* keys[kTilePer];
-    int32_t ins[kTilePer];  // inserted rows below a kept entry's row (short key lists)
 #pragma unroll
     for (int k = 0; k < kTilePer; ++k) {
       const int32_t x = threadIdx.x + k * kTileThreads;
@@ -735,12 +751,6 @@ __global__ void __launch_bounds__(kTileThreads) k_asgn_fill(Operand A, const int
 #pragma unroll
     for (int k = 0; k < kTilePer; ++k) {
       drop[k] = inmod[k] && lastI[row[k]] >= 0;
-      ins[k] = 0;
-      if (inmod[k] && nkey[k] <= 8) {  // independent loads, issued with lastI's
-#pragma unroll
-        for (int q = 0; q < 8; ++q)
-          if (q < nkey[k]) ins[k] += (int32_t)(keys[k][q] >> 32) < row[k] ? 1 : 0;
-      }
       const uint64_t m = __ballot(drop[k]);
       ex[k] = __popcll(m & lanemask_lt());
       if (lane == 0) s_wt[k][wid] = __popcll(m);
@@ -775,8 +785,7 @@ __global__ void __launch_bounds__(kTileThreads) k_asgn_fill(Operand A, const int
           continue;
         }
         // inserted rows below this row
-        int64_t a = 0, b = nkey[k] <= 8 ? 0 : nkey[k];
-        if (b == 0) a = ins[k];
+        int64_t a = 0, b = nkey[k];
         while (a < b) {
           const int64_t mid = (a + b) >> 1;
           if ((int32_t)(keys[k][mid] >> 32) < row[k])
@@ -1291,11 +1300,12 @@ extern "C" int spx_spasgn_plan(const spx_ctx* ctx, const spx_mat* A, const int32
   P->lenJ = lenJ;
   const int64_t m = A->m, n = A->n;
   const int cus = device_cu_count();
-  SPX_TRY(scr.get_many({Scratch::part(&P->err, 4), Scratch::part(&P->nmod_d, 1), Scratch::part(&P->lastI, m),
+  int64_t* pos = nullptr;
+  SPX_TRY(scr.get_many({Scratch::part(&P->err, 4), Scratch::part(&P->nmod_d, 2), Scratch::part(&P->lastI, m),
                         Scratch::part(&P->lastJ, n), Scratch::part(&P->cnt, n), Scratch::part(&P->off, n + 1),
-                        Scratch::part(&P->mod, n)}));
+                        Scratch::part(&P->mod, n), Scratch::part(&pos, n + 1)}));
   SPX_TRY(fill_u32(P->err, 1, 0, st));
-  SPX_TRY(fill_i64((int64_t*)P->nmod_d, 1, 0, st));
+  SPX_TRY(fill_i64((int64_t*)P->nmod_d, 2, 0, st));  // modified columns, their entries
   SPX_TRY(fill_u32((uint32_t*)P->lastI, m, 0xffffffffu, st));
   SPX_TRY(fill_u32((uint32_t*)P->lastJ, n, 0xffffffffu, st));
   if (lenI > 0) {
@@ -1306,19 +1316,23 @@ extern "C" int spx_spasgn_plan(const spx_ctx* ctx, const spx_mat* A, const int32
     k_last_occ<<<grid_for(lenJ, 256, 4096), 256, 0, st>>>(J, lenJ, n, P->lastJ, P->err, 2u);
     SPX_HIP(hipGetLastError());
   }
-  SPX_TRY(list_modified(P->A, P->lastJ, P->cnt, P->mod, P->nmod_d, scr, st));
-  int64_t h1[2] = {0, 0};
-  SPX_TRY(read_device_words(st, {{P->nmod_d, 8}, {P->err, 4}}, h1));
+  SPX_TRY(list_modified(P->A, P->lastJ, P->cnt, P->mod, P->nmod_d, pos, P->nmod_d + 1, scr, st));
+  int64_t h1[3] = {0, 0, 0};
+  SPX_TRY(read_device_words(st, {{P->nmod_d, 8}, {P->err, 4}, {P->nmod_d + 1, 8}}, h1));
   if (h1[1] & 1) return fail(SPX_EINVAL, "I has an index outside [0, m)");
   if (h1[1] & 2) return fail(SPX_EINVAL, "J has an index outside [0, n)");
   P->nmod = h1[0];
-  SPX_TRY(copy_tiles(P->A, P->mod, P->nmod, scr, st, &P->tmod, &P->ntiles, &P->colb, &P->cole));
   const int64_t nm = P->nmod;
-  SPX_TRY(scr.get_many({Scratch::part(&P->dcnt, nm), Scratch::part(&P->lastseg, P->ntiles),
+  P->ntiles = tile_count(P->A, nm);
+  // dropped entries are at most the modified columns' entries
+  SPX_TRY(scr.get_many({Scratch::part(&P->tmod, P->ntiles + 1), Scratch::part(&P->colb, nm),
+                        Scratch::part(&P->cole, nm), Scratch::part(&P->drows, h1[2]),
+                        Scratch::part(&P->dcnt, nm), Scratch::part(&P->lastseg, P->ntiles),
                         Scratch::part(&P->doff, nm + 1), Scratch::part(&P->icnt, nm), Scratch::part(&P->kbase, nm),
                         Scratch::part(&P->ikeys, P->B.nnz), Scratch::part(&P->big, nm),
                         Scratch::part(&P->hoff, nm + 1), Scratch::part(&P->nbig_d, 1),
                         Scratch::part(&P->runshift, nm + 1), Scratch::part(&P->mshift, nm)}));
+  SPX_TRY(copy_tiles(P->A, P->mod, nm, P->ntiles, P->tmod, P->colb, P->cole, st));
   SPX_TRY(fill_i64(P->dcnt, P->nmod, 0, st));
   if (P->nmod > 0 && P->ntiles > 0) {
     k_asgn_drop_count<<<(unsigned)std::min<int64_t>(P->ntiles, (int64_t)cus * 32), kTileThreads, 0, st>>>(
@@ -1347,7 +1361,6 @@ extern "C" int spx_spasgn_plan(const spx_ctx* ctx, const spx_mat* A, const int32
   P->ndrop = tail[1];
   P->nbig = tail[2];
   P->nhuge_keys = tail[3];
-  SPX_TRY(scr.get_n(std::max<int64_t>(P->ndrop, 1), &P->drows));
   if (P->nbig > 0) {
     k_asgn_big_keys<<<(unsigned)std::min<int64_t>(P->nbig, (int64_t)cus * 4), 256, 0, st>>>(
         P->B, I, P->lastI, P->lastJ, P->mod, P->big, P->nbig, P->icnt, P->ikeys);
@@ -1428,10 +1441,11 @@ extern "C" int spx_extend_add_plan(const spx_ctx* ctx, const spx_mat* A, const i
   P->lenJ = lenJ;
   P->sr = semiring;
   const int64_t m = A->m, n = A->n;
+  int64_t* pos = nullptr;
   SPX_TRY(scr.get_many({Scratch::part(&P->err, 4), Scratch::part(&P->nmod_d, 1), Scratch::part(&P->lastJ, n),
                         Scratch::part(&P->qcnt, n), Scratch::part(&P->cnt, n), Scratch::part(&P->off, n + 1),
                         Scratch::part(&P->mod, n), Scratch::part(&P->qoff, n + 1),
-                        Scratch::part(&P->qlist, lenJ)}));
+                        Scratch::part(&P->qlist, lenJ), Scratch::part(&pos, n + 1)}));
   SPX_TRY(fill_u32(P->err, 1, 0, st));
   SPX_TRY(fill_i64((int64_t*)P->nmod_d, 1, 0, st));
   SPX_TRY(fill_u32((uint32_t*)P->lastJ, n, 0xffffffffu, st));
@@ -1446,13 +1460,16 @@ extern "C" int spx_extend_add_plan(const spx_ctx* ctx, const spx_mat* A, const i
     k_count_q<<<grid_for(lenJ, 256, 4096), 256, 0, st>>>(J, lenJ, n, P->qcnt);
     SPX_HIP(hipGetLastError());
   }
-  SPX_TRY(list_modified(P->A, P->lastJ, P->cnt, P->mod, P->nmod_d, scr, st));
+  SPX_TRY(list_modified(P->A, P->lastJ, P->cnt, P->mod, P->nmod_d, pos, nullptr, scr, st));
   int64_t h1[2] = {0, 0};
   SPX_TRY(read_device_words(st, {{P->nmod_d, 8}, {P->err, 4}}, h1));
   if (h1[1] & 1) return fail(SPX_EINVAL, "I has an index outside [0, m)");
   if (h1[1] & 2) return fail(SPX_EINVAL, "J has an index outside [0, n)");
   P->nmod = h1[0];
-  SPX_TRY(copy_tiles(P->A, P->mod, P->nmod, scr, st, &P->tmod, &P->ntiles, &P->colb, &P->cole));
+  P->ntiles = tile_count(P->A, P->nmod);
+  SPX_TRY(scr.get_many({Scratch::part(&P->tmod, P->ntiles + 1), Scratch::part(&P->colb, P->nmod),
+                        Scratch::part(&P->cole, P->nmod)}));
+  SPX_TRY(copy_tiles(P->A, P->mod, P->nmod, P->ntiles, P->tmod, P->colb, P->cole, st));
   SPX_TRY(exclusive_scan(LoadI32{P->qcnt}, n, P->qoff, scr, st));
   if (lenJ > 0) {
     k_scatter_q<<<grid_for(lenJ, 256, 4096), 256, 0, st>>>(J, lenJ, P->qoff, P->qcnt, P->qlist);
