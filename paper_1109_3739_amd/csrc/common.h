@@ -110,14 +110,22 @@ int device_cu_count();
 int fill_i64(int64_t* p, int64_t n, int64_t v, hipStream_t stream);
 int fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t stream);
 
-// Reads up to 8 device scalars of 4 or 8 bytes (4-byte ones zero-extended)
-// with one kernel that writes them to this thread's pinned host words, and
-// waits for the stream: one launch instead of a copy per scalar.
+// Reads device scalars of 4 or 8 bytes (4-byte ones zero-extended), or
+// runs of `count` of them, at most kMaxReadRanges runs and kMaxReadWords
+// words in all, with one kernel that writes them to this thread's pinned
+// host words, and waits for the stream: one launch instead of a copy per
+// scalar.  out[] receives the words in the order given.
+constexpr int kMaxReadRanges = 12;
+constexpr int kMaxReadWords = 64;
 struct DevWord {
   const void* p;
   int bytes;
+  int count = 1;
 };
-int read_device_words(hipStream_t stream, std::initializer_list<DevWord> words, int64_t* out);
+int read_device_words(hipStream_t stream, const DevWord* words, int nwords, int64_t* out);
+inline int read_device_words(hipStream_t stream, std::initializer_list<DevWord> words, int64_t* out) {
+  return read_device_words(stream, words.begin(), (int)words.size(), out);
+}
 
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 inline int64_t next_pow2(int64_t x) {

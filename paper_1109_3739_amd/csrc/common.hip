@@ -143,45 +143,58 @@ int Scratch::get_many(std::initializer_list<Part> parts) {
 }
 
 struct WordList {
-  const void* p[8];
-  int32_t bytes[8];
+  const void* p[kMaxReadRanges];
+  int32_t bytes[kMaxReadRanges];
+  int32_t count[kMaxReadRanges];
   int32_t n;
 };
 
 __global__ void k_read_words(WordList w, int64_t* dst) {
   const int i = threadIdx.x;
-  if (i < w.n)
-    dst[i] = w.bytes[i] == 4 ? (int64_t) * static_cast<const uint32_t*>(w.p[i])
-                             : *static_cast<const int64_t*>(w.p[i]);
+  int base = 0;
+  for (int r = 0; r < w.n; ++r) {
+    if (i < base + w.count[r]) {
+      const int k = i - base;
+      dst[i] = w.bytes[r] == 4 ? (int64_t) static_cast<const uint32_t*>(w.p[r])[k]
+                               : static_cast<const int64_t*>(w.p[r])[k];
+      return;
+    }
+    base += w.count[r];
+  }
 }
 
-int read_device_words(hipStream_t stream, std::initializer_list<DevWord> words, int64_t* out) {
+int read_device_words(hipStream_t stream, const DevWord* words, int nwords, int64_t* out) {
   constexpr int kMaxDev = 64;
   // per thread and device, allocated on first use and kept for the process
   static thread_local int64_t* host[kMaxDev] = {};
   static thread_local int64_t* mapped[kMaxDev] = {};  // the same words' device address
-  if (words.size() > 8) return fail(SPX_EINVAL, "read_device_words takes at most 8 words");
+  if (nwords > kMaxReadRanges) return fail(SPX_EINVAL, "read_device_words: too many runs");
+  WordList w{};
+  int total = 0;
+  for (int r = 0; r < nwords; ++r) {
+    const DevWord& d = words[r];
+    w.p[w.n] = d.p;
+    w.bytes[w.n] = d.bytes;
+    w.count[w.n] = d.count;
+    total += d.count;
+    ++w.n;
+  }
+  if (total > kMaxReadWords) return fail(SPX_EINVAL, "read_device_words: too many words");
   int dev = 0;
   SPX_HIP(hipGetDevice(&dev));
   if (dev < 0 || dev >= kMaxDev) return fail(SPX_EDEVICE, "device id out of the supported range");
   if (!host[dev]) {
     void* h = nullptr;
-    SPX_HIP(hipHostMalloc(&h, 8 * sizeof(int64_t), hipHostMallocCoherent | hipHostMallocMapped));
+    SPX_HIP(hipHostMalloc(&h, kMaxReadWords * sizeof(int64_t), hipHostMallocCoherent | hipHostMallocMapped));
     void* d = nullptr;
     SPX_HIP(hipHostGetDevicePointer(&d, h, 0));
     host[dev] = static_cast<int64_t*>(h);
     mapped[dev] = static_cast<int64_t*>(d);
   }
-  WordList w{};
-  for (const DevWord& d : words) {
-    w.p[w.n] = d.p;
-    w.bytes[w.n] = d.bytes;
-    ++w.n;
-  }
-  k_read_words<<<1, 64, 0, stream>>>(w, mapped[dev]);
+  k_read_words<<<1, kMaxReadWords, 0, stream>>>(w, mapped[dev]);
   SPX_HIP(hipGetLastError());
   SPX_HIP(hipStreamSynchronize(stream));
-  for (int i = 0; i < w.n; ++i) out[i] = host[dev][i];
+  for (int i = 0; i < total; ++i) out[i] = host[dev][i];
   return SPX_OK;
 }
 

@@ -1777,9 +1777,22 @@ int build_aux(const Operand& X, Scratch& scr, hipStream_t st, int64_t** aux, int
   return SPX_OK;
 }
 
-int summary_sync(GemmPlan* P, hipStream_t st, Summary* host) {
-  SPX_HIP(hipMemcpyAsync(host, P->sum, sizeof(Summary), hipMemcpyDeviceToHost, st));
-  SPX_HIP(hipStreamSynchronize(st));
+// Waits for the stream and reads the plan's summary together with the
+// given extra device words (one read-back launch).
+int summary_sync(GemmPlan* P, hipStream_t st, Summary* host, std::initializer_list<DevWord> extra = {},
+                 int64_t* extra_out = nullptr) {
+  static_assert(sizeof(Summary) == 6 * sizeof(int64_t), "the summary is read as six words");
+  DevWord w[kMaxReadRanges];
+  int n = 0, nx = 0;
+  for (const DevWord& d : extra) {
+    w[n++] = d;
+    nx += d.count;
+  }
+  w[n++] = DevWord{P->sum, 8, 6};
+  int64_t out[kMaxReadWords];
+  SPX_TRY(read_device_words(st, w, n, out));
+  for (int i = 0; i < nx; ++i) extra_out[i] = out[i];
+  std::memcpy(host, out + nx, sizeof(Summary));
   return SPX_OK;
 }
 
@@ -1946,19 +1959,14 @@ extern "C" int spx_spgemm_plan(const spx_ctx* ctx, const spx_mat* A, const spx_m
   P->nslice_req = std::max(1, std::min(tune.xcd_slices, 64));
   P->mark(kEvPlan0, st);
 
-  SPX_TRY(scr.get_n(1, &P->sum));
-  SPX_TRY(fill_i64((int64_t*)P->sum, sizeof(Summary) / 8, 0, st));
-  SPX_TRY(scr.get_n(std::max<int64_t>(B->nnz, 1), &P->bq_a0));
-  SPX_TRY(scr.get_n(std::max<int64_t>(B->nnz, 1), &P->bq_alen));
-  SPX_TRY(scr.get_n(std::max<int64_t>(nslots, 1), &P->mults_d));
-  SPX_TRY(scr.get_n(std::max<int64_t>(nslots, 1), &P->cnt));
-  SPX_TRY(scr.get_n(nslots + 1, &P->off));
-  SPX_TRY(scr.get_n(nslots + 1, &P->zoff));
-  SPX_TRY(scr.get_n(std::max<int64_t>(nslots, 1), &P->list));
-  SPX_TRY(scr.get_n(kNumBins + 1, &P->binoff));
   unsigned long long *bincount = nullptr, *binfill = nullptr;
-  SPX_TRY(scr.get_n(kNumBins, &bincount));
-  SPX_TRY(scr.get_n(kNumBins, &binfill));
+  SPX_TRY(scr.get_many({Scratch::part(&P->sum, 1), Scratch::part(&P->bq_a0, B->nnz),
+                        Scratch::part(&P->bq_alen, B->nnz), Scratch::part(&P->bq_split, B->nnz),
+                        Scratch::part(&P->mults_d, nslots), Scratch::part(&P->cnt, nslots),
+                        Scratch::part(&P->off, nslots + 1), Scratch::part(&P->zoff, nslots + 1),
+                        Scratch::part(&P->list, nslots), Scratch::part(&P->binoff, kNumBins + 1),
+                        Scratch::part(&bincount, kNumBins), Scratch::part(&binfill, kNumBins)}));
+  SPX_TRY(fill_i64((int64_t*)P->sum, sizeof(Summary) / 8, 0, st));
   SPX_TRY(fill_i64((int64_t*)bincount, kNumBins, 0, st));
   SPX_TRY(fill_i64(P->cnt, std::max<int64_t>(nslots, 1), 0, st));
   unsigned* err = &P->sum->err;
@@ -1983,7 +1991,6 @@ extern "C" int spx_spgemm_plan(const spx_ctx* ctx, const spx_mat* A, const spx_m
         P->A, sid_off + nslots_a, split_cap, slot_of_split, P->splits, sstride, rb);
     SPX_HIP(hipGetLastError());
   }
-  SPX_TRY(scr.get_n(std::max<int64_t>(B->nnz, 1), &P->bq_split));
   if (B->nnz > 0) {
     k_rowinfo<<<grid_for(B->nnz, 256, (int64_t)cus * 32), 256, 0, st>>>(P->A, P->B, P->aux, chunk, sid_off, P->bq_a0,
                                                                          P->bq_alen, P->bq_split, err);
@@ -2016,8 +2023,8 @@ extern "C" int spx_spgemm_plan(const spx_ctx* ctx, const spx_mat* A, const spx_m
   }
   // sync 1: bin sizes and the total number of multiplications
   Summary hs{};
-  SPX_HIP(hipMemcpyAsync(P->binoff_h, P->binoff, sizeof(P->binoff_h), hipMemcpyDeviceToHost, st));
-  SPX_TRY(summary_sync(P, st, &hs));
+  static_assert(sizeof(P->binoff_h) == (kNumBins + 1) * sizeof(int64_t), "bin offsets are read as words");
+  SPX_TRY(summary_sync(P, st, &hs, {{P->binoff, 8, kNumBins + 1}}, P->binoff_h));
   if (hs.err & 1u) return fail(SPX_EINVAL, "B has a row index outside A's columns");
   P->mults = (int64_t)hs.mults;
   const int64_t* bo = P->binoff_h;
@@ -2111,13 +2118,11 @@ extern "C" int spx_spgemm_plan(const spx_ctx* ctx, const spx_mat* A, const spx_m
   }
   // sync 2: sizes
   int64_t tail[4] = {0, 0, 0, 0};
-  SPX_HIP(hipMemcpyAsync(&tail[0], P->off + nslots, 8, hipMemcpyDeviceToHost, st));
-  SPX_HIP(hipMemcpyAsync(&tail[1], P->zoff + nslots, 8, hipMemcpyDeviceToHost, st));
-  if (npos > 0) {
-    SPX_HIP(hipMemcpyAsync(&tail[2], poff + npos, 8, hipMemcpyDeviceToHost, st));
-    SPX_HIP(hipMemcpyAsync(&tail[3], poff + multi_end, 8, hipMemcpyDeviceToHost, st));
-  }
-  SPX_TRY(summary_sync(P, st, &hs));
+  if (npos > 0)
+    SPX_TRY(summary_sync(P, st, &hs, {{P->off + nslots, 8}, {P->zoff + nslots, 8}, {poff + npos, 8},
+                                      {poff + multi_end, 8}}, tail));
+  else
+    SPX_TRY(summary_sync(P, st, &hs, {{P->off + nslots, 8}, {P->zoff + nslots, 8}}, tail));
   if (hs.err & 4u) return fail(SPX_EUNSUPPORTED, "a row block is too dense for the LDS budget");
   // Columns with many B entries per product (a tall-skinny right operand):
   // every part walks all of its column's B entries, so range set-ups
@@ -2138,9 +2143,7 @@ extern "C" int spx_spgemm_plan(const spx_ctx* ctx, const spx_mat* A, const spx_m
           nullptr, nullptr, P->mults_d, &P->sum->setup, err);
       SPX_HIP(hipGetLastError());
       SPX_TRY(exclusive_scan(LoadI64{np}, npos, poff, scr, st));
-      SPX_HIP(hipMemcpyAsync(&tail[2], poff + npos, 8, hipMemcpyDeviceToHost, st));
-      SPX_HIP(hipMemcpyAsync(&tail[3], poff + multi_end, 8, hipMemcpyDeviceToHost, st));
-      SPX_TRY(summary_sync(P, st, &hs));
+      SPX_TRY(summary_sync(P, st, &hs, {{poff + npos, 8}, {poff + multi_end, 8}}, tail + 2));
       if (hs.err & 4u) return fail(SPX_EUNSUPPORTED, "a row block is too dense for the LDS budget");
     }
   }
@@ -2301,11 +2304,9 @@ extern "C" int spx_plan_get_info(const spx_plan* plan, spx_plan_info* info) {
   if (plan->kind != kPlanGemm) return SPX_OK;
   auto* P = const_cast<GemmPlan*>(static_cast<const GemmPlan*>(plan));
   if (P->nnz_multi < 0) {
-    unsigned long long v = 0;
-    hipStream_t st = stream_of(&P->ctx);
-    SPX_HIP(hipMemcpyAsync(&v, &P->sum->nnz_multi, 8, hipMemcpyDeviceToHost, st));
-    SPX_HIP(hipStreamSynchronize(st));
-    P->nnz_multi = (int64_t)v;
+    int64_t v = 0;
+    SPX_TRY(read_device_words(stream_of(&P->ctx), {{&P->sum->nnz_multi, 8}}, &v));
+    P->nnz_multi = v;
   }
   const int64_t* bo = P->binoff_h;
   info->mults = P->mults;
