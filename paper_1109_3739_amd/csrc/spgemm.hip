@@ -657,11 +657,13 @@ __device__ __forceinline__ K group_sort(K key, int gl) {  // ascending bitonic s
 // One tiny column (at most G products) in a group of G lanes: the group
 // gathers every product into LDS, sorts the (row, product index) keys, and
 // either counts the distinct rows (COUNT) or sums each run of equal rows in
-// product order -- the order of Algorithm 1 -- and writes the column.
+// product order -- the order of Algorithm 1 -- and writes the column.  The
+// column's B range [b0, b1) and output offset come from the caller.
 template <int G, int SR, typename T, bool COUNT>
 __device__ __forceinline__ void tiny_column(const Operand& A, const Operand& B, const int64_t* bq_a0,
-                                            const int32_t* bq_alen, int32_t t, int64_t* cnt, const int64_t* off,
-                                            int32_t* cir, T* cnum, int32_t* s_row, int32_t* s_aux, T* s_val) {
+                                            const int32_t* bq_alen, int32_t t, int64_t b0, int64_t b1,
+                                            int64_t obase, int64_t* cnt, int32_t* cir, T* cnum, int32_t* s_row,
+                                            int32_t* s_aux, T* s_val) {
   using S = Semiring<SR, T>;
   constexpr bool kVal = SR != SPX_OR_AND;
   const int lane = lane_id();
@@ -670,10 +672,6 @@ __device__ __forceinline__ void tiny_column(const Operand& A, const Operand& B, 
   s_row += gb;
   s_aux += gb;
   s_val += gb;
-  const int64_t b0 = slot_begin(B, t), b1 = slot_begin(B, t + 1);
-  // the output offset is loaded with the column's pointers, so its latency
-  // overlaps theirs instead of adding a level at the end
-  const int64_t obase = COUNT ? 0 : off[t];
   const T* an = (const T*)A.num;
   const T* bn = (const T*)B.num;
   int total = 0;
@@ -770,9 +768,13 @@ __device__ __forceinline__ void tiny_column(const Operand& A, const Operand& B, 
   wave_sync();
 }
 
-// Tiny columns (at most 64 products), one wave per pair of consecutive
-// columns of the bin: two columns of at most 32 products each share the
-// wave (one per half), otherwise they are done one after the other.
+// Tiny columns (at most 64 products), by pairs of consecutive columns of
+// the bin: two columns of at most 32 products each share a wave (one per
+// half), otherwise they are done one after the other.  A wave takes 64
+// pairs at a time: lane k loads pair k's column ids, products, B ranges and
+// output offsets into the wave's LDS table (two load levels for the 64
+// pairs), and the pair loop reads them from there, so a column waits only
+// on its B entries' A ranges and then A's rows and values.
 template <int SR, typename T, bool COUNT>
 __global__ void __launch_bounds__(256) k_tiny(Operand A, Operand B, const int64_t* bq_a0, const int32_t* bq_alen,
                                               const int64_t* mults, const int32_t* list, const int64_t* binoff,
@@ -780,32 +782,54 @@ __global__ void __launch_bounds__(256) k_tiny(Operand A, Operand B, const int64_
   __shared__ int32_t s_row[4][kWave];
   __shared__ int32_t s_aux[4][kWave];
   __shared__ T s_val[4][kWave];
+  struct PairRow {
+    int32_t t[2];
+    int32_t m[2];  // products (a tiny column's fit 32 bits)
+    int64_t b0[2], b1[2], o[2];
+  };
+  __shared__ PairRow s_pair[4][kWave];
   const int w = threadIdx.x / kWave, lane = lane_id();
   const int64_t beg = binoff[kBinTiny], end = binoff[kBinTiny + 1];
-  const int64_t stride = (int64_t)gridDim.x * 8;
-  int64_t pos = beg + ((int64_t)blockIdx.x * 4 + w) * 2;
-  // the column ids of the wave's next pair are loaded one pair ahead
-  int32_t t0 = 0, t1 = 0;
-  if (pos < end) {
-    t0 = list[pos];
-    t1 = pos + 1 < end ? list[pos + 1] : 0;
-  }
-  for (; pos < end; pos += stride) {
-    const bool has1 = pos + 1 < end;
-    const int64_t m0 = mults[t0], m1 = has1 ? mults[t1] : 0;
-    const int64_t np = pos + stride;
-    const int32_t n0 = np < end ? list[np] : 0;
-    const int32_t n1 = np + 1 < end ? list[np + 1] : 0;
-    if (has1 && m0 <= 32 && m1 <= 32) {
-      tiny_column<32, SR, T, COUNT>(A, B, bq_a0, bq_alen, lane < 32 ? t0 : t1, cnt, off, cir, cnum, s_row[w], s_aux[w],
-                                    s_val[w]);
-    } else {
-      tiny_column<64, SR, T, COUNT>(A, B, bq_a0, bq_alen, t0, cnt, off, cir, cnum, s_row[w], s_aux[w], s_val[w]);
-      if (has1)
-        tiny_column<64, SR, T, COUNT>(A, B, bq_a0, bq_alen, t1, cnt, off, cir, cnum, s_row[w], s_aux[w], s_val[w]);
+  const int64_t npairs = (end - beg + 1) / 2;
+  const int64_t wave = (int64_t)blockIdx.x * 4 + w, nwaves = (int64_t)gridDim.x * 4;
+  for (int64_t c0 = wave * kWave; c0 < npairs; c0 += nwaves * kWave) {
+    {  // lane k: pair c0 + k
+      const int64_t pos = beg + 2 * (c0 + lane);
+      PairRow r{};
+      r.m[1] = -1;  // no second column
+      if (c0 + lane < npairs) {
+        for (int h = 0; h < 2; ++h) {
+          if (pos + h >= end) break;
+          const int32_t t = list[pos + h];
+          r.t[h] = t;
+          r.m[h] = (int32_t)mults[t];
+          r.b0[h] = slot_begin(B, t);
+          r.b1[h] = slot_begin(B, t + 1);
+          r.o[h] = COUNT ? 0 : off[t];
+        }
+      }
+      s_pair[w][lane] = r;
     }
-    t0 = n0;
-    t1 = n1;
+    wave_sync();
+    const int np = (int)std::min<int64_t>(kWave, npairs - c0);
+    for (int k = 0; k < np; ++k) {
+      const PairRow& r = s_pair[w][k];
+      const int32_t m1 = __builtin_amdgcn_readfirstlane(r.m[1]);
+      const bool has1 = m1 >= 0;
+      const int32_t m0 = __builtin_amdgcn_readfirstlane(r.m[0]);
+      if (has1 && m0 <= 32 && m1 <= 32) {
+        const int h = lane < 32 ? 0 : 1;
+        tiny_column<32, SR, T, COUNT>(A, B, bq_a0, bq_alen, r.t[h], r.b0[h], r.b1[h], r.o[h], cnt, cir, cnum,
+                                      s_row[w], s_aux[w], s_val[w]);
+      } else {
+        tiny_column<64, SR, T, COUNT>(A, B, bq_a0, bq_alen, r.t[0], r.b0[0], r.b1[0], r.o[0], cnt, cir, cnum,
+                                      s_row[w], s_aux[w], s_val[w]);
+        if (has1)
+          tiny_column<64, SR, T, COUNT>(A, B, bq_a0, bq_alen, r.t[1], r.b0[1], r.b1[1], r.o[1], cnt, cir, cnum,
+                                        s_row[w], s_aux[w], s_val[w]);
+      }
+    }
+    wave_sync();  // the table is rewritten for the next 64 pairs
   }
 }
 
@@ -1851,7 +1875,7 @@ static int launch_numeric(GemmPlan* P, spx_mat* C, hipStream_t st) {
   P->mark(kEvParts, st);
   const int64_t ntiny = P->binoff_h[kBinTiny + 1] - P->binoff_h[kBinTiny];
   if (ntiny > 0) {
-    hipLaunchKernelGGL((k_tiny<SR, T, false>), dim3(grid_for(ntiny, 8, (int64_t)cus * 16)), dim3(256), 0, st, P->A,
+    hipLaunchKernelGGL((k_tiny<SR, T, false>), dim3(grid_for(ntiny, 512, (int64_t)cus * 16)), dim3(256), 0, st, P->A,
                        P->B, P->bq_a0, P->bq_alen, P->mults_d, P->list, P->binoff, P->cnt, P->off, cir, cnum);
     SPX_HIP(hipGetLastError());
   }
@@ -2041,7 +2065,7 @@ extern "C" int spx_spgemm_plan(const spx_ctx* ctx, const spx_mat* A, const spx_m
   // exact counts
   const int64_t ntiny = bo[kBinTiny + 1] - bo[kBinTiny];
   if (ntiny > 0) {
-    k_tiny<SPX_OR_AND, float, true><<<grid_for(ntiny, 8, (int64_t)cus * 16), 256, 0, st>>>(
+    k_tiny<SPX_OR_AND, float, true><<<grid_for(ntiny, 512, (int64_t)cus * 16), 256, 0, st>>>(
         P->A, P->B, P->bq_a0, P->bq_alen, P->mults_d, P->list, P->binoff, P->cnt, nullptr, nullptr, nullptr);
     SPX_HIP(hipGetLastError());
   }
