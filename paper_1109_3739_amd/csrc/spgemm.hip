@@ -770,11 +770,12 @@ __device__ __forceinline__ void tiny_column(const Operand& A, const Operand& B, 
 
 // Tiny columns (at most 64 products), by pairs of consecutive columns of
 // the bin: two columns of at most 32 products each share a wave (one per
-// half), otherwise they are done one after the other.  A wave takes 64
-// pairs at a time: lane k loads pair k's column ids, products, B ranges and
-// output offsets into the wave's LDS table (two load levels for the 64
-// pairs), and the pair loop reads them from there, so a column waits only
-// on its B entries' A ranges and then A's rows and values.
+// half), otherwise they are done one after the other.  A wave takes up to
+// 64 pairs at a time (fewer when the bin is too small to give every wave
+// 64): lane k loads pair k's column ids, products, B ranges and output
+// offsets into the wave's LDS table (two load levels for all of them), and
+// the pair loop reads them from there, so a column waits only on its B
+// entries' A ranges and then A's rows and values.
 template <int SR, typename T, bool COUNT>
 __global__ void __launch_bounds__(256) k_tiny(Operand A, Operand B, const int64_t* bq_a0, const int32_t* bq_alen,
                                               const int64_t* mults, const int32_t* list, const int64_t* binoff,
@@ -792,12 +793,13 @@ __global__ void __launch_bounds__(256) k_tiny(Operand A, Operand B, const int64_
   const int64_t beg = binoff[kBinTiny], end = binoff[kBinTiny + 1];
   const int64_t npairs = (end - beg + 1) / 2;
   const int64_t wave = (int64_t)blockIdx.x * 4 + w, nwaves = (int64_t)gridDim.x * 4;
-  for (int64_t c0 = wave * kWave; c0 < npairs; c0 += nwaves * kWave) {
+  const int64_t per = std::min<int64_t>(kWave, std::max<int64_t>(1, (npairs + nwaves - 1) / nwaves));
+  for (int64_t c0 = wave * per; c0 < npairs; c0 += nwaves * per) {
     {  // lane k: pair c0 + k
       const int64_t pos = beg + 2 * (c0 + lane);
       PairRow r{};
       r.m[1] = -1;  // no second column
-      if (c0 + lane < npairs) {
+      if (lane < per && c0 + lane < npairs) {
         for (int h = 0; h < 2; ++h) {
           if (pos + h >= end) break;
           const int32_t t = list[pos + h];
@@ -811,7 +813,7 @@ __global__ void __launch_bounds__(256) k_tiny(Operand A, Operand B, const int64_
       s_pair[w][lane] = r;
     }
     wave_sync();
-    const int np = (int)std::min<int64_t>(kWave, npairs - c0);
+    const int np = (int)std::min<int64_t>(per, npairs - c0);
     for (int k = 0; k < np; ++k) {
       const PairRow& r = s_pair[w][k];
       const int32_t m1 = __builtin_amdgcn_readfirstlane(r.m[1]);
@@ -1875,7 +1877,7 @@ static int launch_numeric(GemmPlan* P, spx_mat* C, hipStream_t st) {
   P->mark(kEvParts, st);
   const int64_t ntiny = P->binoff_h[kBinTiny + 1] - P->binoff_h[kBinTiny];
   if (ntiny > 0) {
-    hipLaunchKernelGGL((k_tiny<SR, T, false>), dim3(grid_for(ntiny, 512, (int64_t)cus * 16)), dim3(256), 0, st, P->A,
+    hipLaunchKernelGGL((k_tiny<SR, T, false>), dim3(grid_for(ntiny, 8, (int64_t)cus * 16)), dim3(256), 0, st, P->A,
                        P->B, P->bq_a0, P->bq_alen, P->mults_d, P->list, P->binoff, P->cnt, P->off, cir, cnum);
     SPX_HIP(hipGetLastError());
   }
@@ -2065,7 +2067,7 @@ extern "C" int spx_spgemm_plan(const spx_ctx* ctx, const spx_mat* A, const spx_m
   // exact counts
   const int64_t ntiny = bo[kBinTiny + 1] - bo[kBinTiny];
   if (ntiny > 0) {
-    k_tiny<SPX_OR_AND, float, true><<<grid_for(ntiny, 512, (int64_t)cus * 16), 256, 0, st>>>(
+    k_tiny<SPX_OR_AND, float, true><<<grid_for(ntiny, 8, (int64_t)cus * 16), 256, 0, st>>>(
         P->A, P->B, P->bq_a0, P->bq_alen, P->mults_d, P->list, P->binoff, P->cnt, nullptr, nullptr, nullptr);
     SPX_HIP(hipGetLastError());
   }
