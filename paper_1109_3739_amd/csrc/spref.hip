@@ -95,9 +95,16 @@ __global__ void k_ref_count(const Operand A, const int64_t* qa0, const int32_t* 
     const int64_t a0 = qa0[q];
     const int32_t al = qlen[q];
     int64_t s = 0;
-    for (int32_t e = lane; e < al; e += kWave) {
-      const int32_t i = A.ir[a0 + e];
-      s += rptr[i + 1] - rptr[i];
+    for (int32_t e0 = 0; e0 < al; e0 += 4 * kWave) {  // four rows in flight per lane
+      int32_t i[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int32_t e = e0 + k * kWave + lane;
+        i[k] = e < al ? A.ir[a0 + e] : -1;
+      }
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        if (i[k] >= 0) s += rptr[i[k] + 1] - rptr[i[k]];
     }
     s = wave_sum(s);
     const int c = s == 0 ? kClsEmpty : s <= kRefSmall ? kClsSmall : s <= kRefMedium ? kClsMedium : kClsLarge;
@@ -132,15 +139,42 @@ __global__ void k_cls_offsets(unsigned long long* clscount, int64_t* clsoff, uns
   }
 }
 
-__global__ void k_cls_fill(const int64_t* cnt, int64_t lenJ, const int64_t* clsoff, unsigned long long* fill,
-                           int32_t* list) {
-  for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < lenJ; q += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t s = cnt[q];
-    const int c = s == 0 ? kClsEmpty : s <= kRefSmall ? kClsSmall : s <= kRefMedium ? kClsMedium : kClsLarge;
-    for (int k = 0; k < kNumCls; ++k) {  // one atomic per wave and class
-      const unsigned long long slot = wave_claim(&fill[k], c == k);
-      if (c == k) list[clsoff[k] + (int64_t)slot] = (int32_t)q;
+// Columns grouped by class (any order inside a class).  A thread takes
+// kClsPer consecutive columns; the class counts of a thread are packed in
+// 16-bit fields, so one workgroup scan ranks every column in its class and
+// one atomic per class and workgroup claims the workgroup's slots.
+constexpr int kClsPer = 8;
+__global__ void __launch_bounds__(256) k_cls_fill(const int64_t* cnt, int64_t lenJ, const int64_t* clsoff,
+                                                  unsigned long long* fill, int32_t* list) {
+  __shared__ uint64_t red[256 / kWave + 1];
+  __shared__ unsigned long long s_base[kNumCls];
+  auto cls = [](int64_t s) {
+    return s == 0 ? kClsEmpty : s <= kRefSmall ? kClsSmall : s <= kRefMedium ? kClsMedium : kClsLarge;
+  };
+  for (int64_t q0 = (int64_t)blockIdx.x * 256 * kClsPer; q0 < lenJ; q0 += (int64_t)gridDim.x * 256 * kClsPer) {
+    const int64_t qt = q0 + (int64_t)threadIdx.x * kClsPer;
+    int c[kClsPer];
+    uint64_t mine = 0;
+#pragma unroll
+    for (int k = 0; k < kClsPer; ++k) {
+      c[k] = qt + k < lenJ ? cls(cnt[qt + k]) : -1;
+      if (c[k] >= 0) mine += 1ull << (16 * c[k]);
     }
+    uint64_t tot;
+    uint64_t ex = block_excl_scan(mine, red, &tot);
+    if (threadIdx.x < kNumCls) {
+      const unsigned long long n = (tot >> (16 * threadIdx.x)) & 0xffffull;
+      s_base[threadIdx.x] = n ? atomicAdd(&fill[threadIdx.x], n) : 0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kClsPer; ++k) {
+      if (c[k] < 0) continue;
+      const int64_t slot = (int64_t)s_base[c[k]] + (int64_t)((ex >> (16 * c[k])) & 0xffffull);
+      list[clsoff[c[k]] + slot] = (int32_t)(qt + k);
+      ex += 1ull << (16 * c[k]);
+    }
+    __syncthreads();
   }
 }
 
@@ -395,7 +429,7 @@ extern "C" int spx_spref_plan(const spx_ctx* ctx, const spx_mat* A, const int32_
   k_cls_offsets<<<1, 64, 0, st>>>(clscount, P->clsoff, fill);
   SPX_HIP(hipGetLastError());
   if (lenJ > 0) {
-    k_cls_fill<<<grid_for(lenJ, 256, 4096), 256, 0, st>>>(P->cnt, lenJ, P->clsoff, fill, P->list);
+    k_cls_fill<<<grid_for(lenJ, 256 * kClsPer, 4096), 256, 0, st>>>(P->cnt, lenJ, P->clsoff, fill, P->list);
     SPX_HIP(hipGetLastError());
   }
   SPX_TRY(exclusive_scan(LoadI64{P->cnt}, lenJ, P->off, scr, st));
