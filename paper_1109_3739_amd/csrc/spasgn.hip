@@ -34,6 +34,10 @@ constexpr int kAsgnMaxInsert = 4096;  // inserted rows per column handled in LDS
 // Columns with at most this many inserted (landing) entries take one wave and
 // a small LDS area; the others go to a list served by 256-thread workgroups.
 constexpr int kAsgnSmall = 64;
+// Extend-add: modified columns with more A entries than this have their A
+// entries placed by the tiles (spread over the whole device) rather than by
+// the one workgroup that handles the column.
+constexpr int64_t kEaLongA = 1024;
 
 // ---------------------------------------------------------------- helpers
 // Pointers of a DCSC operand expanded to CSC (cp[j] = start of column j);
@@ -134,6 +138,24 @@ __device__ void wg_sort_global(uint64_t* keys, int64_t p2, uint64_t* tile) {
     }
   }
 }
+
+// Extend-add's key segments: a huge column's as HugeCap; a long A column's
+// (flag set) max(keys, 1); 0 for the others and past *len.
+struct EaSeg {
+  const int64_t* n;
+  const int32_t* flag;
+  const unsigned long long* len;
+  __device__ int64_t operator()(int64_t w) const {
+    if (w >= (int64_t)*len) return 0;
+    const int64_t c = n[w];
+    if (c > kAsgnMaxInsert) {
+      int64_t p = kAsgnMaxInsert;
+      while (p < c) p <<= 1;
+      return p;
+    }
+    return flag[w] ? (c > 0 ? c : 1) : 0;
+  }
+};
 
 // Smallest power of two >= max(n, kAsgnMaxInsert) for a huge column, 0 for others.
 struct HugeCap {
@@ -404,76 +426,6 @@ __device__ __forceinline__ int32_t staged_rank(const P* s_end, int32_t nst, int3
       hi = mid;
   }
   return lo;
-}
-
-// Extend-add's copy of the unmodified columns: an entry in the run before
-// staged column i moves by that run's output shift off[c0] - cp[c0].
-template <int VB>
-__global__ void __launch_bounds__(kTileThreads) k_asgn_copy(Operand A, const int32_t* mod, int64_t nmod,
-                                                            const int64_t* tmod, int64_t nt, const int64_t* off,
-                                                            int32_t* cir, void* cnum) {
-  using V = typename std::conditional<VB == 8, uint64_t, uint32_t>::type;
-  __shared__ int32_t s_beg[kTileItems + 1];
-  __shared__ int32_t s_end[kTileItems + 1];
-  __shared__ int64_t s_shift[kTileItems + 1];
-  const V* anum = static_cast<const V*>(A.num);
-  V* out = static_cast<V*>(cnum);
-  for (int64_t t = blockIdx.x; t < nt; t += gridDim.x) {
-    const TileSpan sp = tile_span(A, nmod, tmod, t);
-    for (int64_t i = threadIdx.x; i <= sp.ue - sp.us; i += kTileThreads) {
-      const int64_t r = sp.us + i;
-      const int64_t c0 = r == 0 ? 0 : (int64_t)mod[r - 1] + 1;  // the run before column r starts here
-      s_shift[i] = off[c0] - slot_begin(A, c0);
-      if (i < sp.nst) {
-        const int64_t c = mod[r];
-        s_beg[i] = tile_rel(slot_begin(A, c), sp.es);
-        s_end[i] = tile_rel(slot_begin(A, c + 1), sp.es);
-      }
-    }
-    __syncthreads();
-    int32_t row[kTilePer];
-    V val[kTilePer];
-    int64_t dst[kTilePer];
-#pragma unroll
-    for (int k = 0; k < kTilePer; ++k) {
-      const int32_t x = threadIdx.x + k * kTileThreads;
-      dst[k] = -1;
-      if (sp.es + x < sp.ee) {
-        const int32_t lo = staged_rank(s_end, sp.nst, x);
-        if (!(lo < sp.nst && s_beg[lo] <= x)) dst[k] = sp.es + x + s_shift[lo];
-      }
-    }
-#pragma unroll
-    for (int k = 0; k < kTilePer; ++k) {
-      if (dst[k] >= 0) {
-        const int64_t e = sp.es + threadIdx.x + k * kTileThreads;
-        row[k] = A.ir[e];
-        if (VB) val[k] = anum[e];
-      }
-    }
-#pragma unroll
-    for (int k = 0; k < kTilePer; ++k) {
-      if (dst[k] >= 0) {
-        cir[dst[k]] = row[k];
-        if (VB) out[dst[k]] = val[k];
-      }
-    }
-    __syncthreads();
-  }
-}
-
-int launch_copy(const Operand& A, const int32_t* mod, int64_t nmod, const int64_t* tmod, int64_t nt,
-                const int64_t* off, int vb, int32_t* cir, void* cnum, hipStream_t st) {
-  if (A.nnz == 0) return SPX_OK;
-  const unsigned grid = (unsigned)std::min<int64_t>(nt, (int64_t)device_cu_count() * 32);
-  if (vb == 8)
-    k_asgn_copy<8><<<grid, kTileThreads, 0, st>>>(A, mod, nmod, tmod, nt, off, cir, cnum);
-  else if (vb == 4)
-    k_asgn_copy<4><<<grid, kTileThreads, 0, st>>>(A, mod, nmod, tmod, nt, off, cir, cnum);
-  else
-    k_asgn_copy<0><<<grid, kTileThreads, 0, st>>>(A, mod, nmod, tmod, nt, off, cir, cnum);
-  SPX_HIP(hipGetLastError());
-  return SPX_OK;
 }
 
 // ------------------------------------------------ SpAsgn's modified columns
@@ -902,8 +854,11 @@ struct ExtAddPlan : spx_plan {
   int64_t* hcnt = nullptr;   // [nmod] per big-list entry: landing entries of a huge column, else 0
   int64_t* hoff = nullptr;   // [nmod+1] key segment of each big-list entry (0 length unless huge)
   uint64_t* hkeys = nullptr; // sorted (row, position in B) keys of the huge columns
-  int32_t* hhead = nullptr;  // per huge column, hoff[w] + w .. : distinct-row heads
+  int32_t* hhead = nullptr;  // per segment column, hoff[w] + w .. : distinct-row heads
   int32_t* hnin = nullptr;   // and new-row counts
+  int32_t* hlong = nullptr;  // [nmod] per big-list entry: 1 for a long A column (its A entries go to the tiles)
+  int64_t* hnu = nullptr;    // [nmod] per segment column: distinct landing rows
+  int32_t* lw = nullptr;     // [nmod] per modified column: its big-list entry if long, else -1
   int64_t nhuge_keys = 0;
   int64_t* tmod = nullptr;    // [ntiles+1] modified columns before each copy tile (k_copy_tiles)
   int64_t ntiles = 0;
@@ -951,9 +906,10 @@ struct LoadI32 {
 //      landing values.  Sums run in key order (B's storage order).
 // Called by the whole workgroup.
 template <bool kFill, bool kVals, typename T, class Acc, class KeyPtr, class IdxPtr>
-__device__ __forceinline__ void ea_column_body(const Operand& A, int32_t j, KeyPtr keys, int64_t nins, IdxPtr head,
-                                               IdxPtr nin, int64_t* red, int64_t* cnt, const int64_t* off,
-                                               const T* bnum, int32_t* cir, T* cnum) {
+__device__ __forceinline__ int64_t ea_column_body(const Operand& A, int32_t j, KeyPtr keys, int64_t nins,
+                                                  IdxPtr head, IdxPtr nin, int64_t* red, int64_t* cnt,
+                                                  const int64_t* off, const T* bnum, int32_t* cir, T* cnum,
+                                                  bool skip_a = false) {
   const T* anum = static_cast<const T*>(A.num);
   const int64_t a0 = slot_begin(A, j), a1 = slot_begin(A, j + 1);
   const int32_t* acol = A.ir + a0;
@@ -992,11 +948,11 @@ __device__ __forceinline__ void ea_column_body(const Operand& A, int32_t j, KeyP
   __syncthreads();
   if (!kFill) {
     if (threadIdx.x == 0) cnt[j] = alen + nnew;
-    return;
+    return nu;
   }
   const int64_t cbase = off[j];
-  // A's entries
-  for (int64_t t = threadIdx.x; t < alen; t += blockDim.x) {
+  // A's entries (a long column's go through the tiles instead)
+  for (int64_t t = skip_a ? alen : threadIdx.x; t < alen; t += blockDim.x) {
     const int32_t row = acol[t];
     int64_t lo = 0, hi = nu;  // distinct landing rows < row
     while (lo < hi) {
@@ -1028,6 +984,7 @@ __device__ __forceinline__ void ea_column_body(const Operand& A, int32_t j, KeyP
     }
   }
   __syncthreads();
+  return nu;
 }
 
 // Keys (I(p) << 32 | e) of the entries of every B(:,q) with J(q) = j that
@@ -1140,19 +1097,22 @@ __global__ void __launch_bounds__(256) k_ea_wave(Operand A, Operand B, const int
 }
 
 // One workgroup per modified column j (grid-stride over the list) whose
-// landing entries fit CAP: they are sorted in LDS, then ea_column_body.  The
+// landing entries fit CAP and whose A column has at most kEaLongA entries:
+// the keys are sorted in LDS, then ea_column_body.  The
 // one-wave variant (CAP = kAsgnSmall) serves the rest list of k_ea_wave; in
 // the count pass it hands larger columns to the `big` list, which the
 // 256-thread variant (CAP = kAsgnMaxInsert) then serves (list lengths read
 // from *nlist_d in the count pass); in its count pass that variant records, per list entry,
-// the landing entries of a column above CAP in hcnt (0 for the others), and
-// such ("huge") columns are done by k_ea_huge.
+// the landing entries of a column above CAP or with a long A column in hcnt
+// (0 for the others), and such ("segment") columns are done by k_ea_huge,
+// with a long column's A entries left to the tiles (k_ea_tiles).
 template <bool kFill, bool kVals, int CAP, typename T, class Acc>
 __global__ void __launch_bounds__(256) k_ea_column(Operand A, Operand B, const int32_t* I, const int32_t* mod,
                                                    const int32_t* list, const unsigned long long* nlist_d,
                                                    int64_t nlist_h, const int64_t* qoff, const int32_t* qlist,
                                                    int64_t* cnt, const int64_t* off, int32_t* big,
-                                                   unsigned long long* nbig, int64_t* hcnt, int32_t* cir, T* cnum) {
+                                                   unsigned long long* nbig, int64_t* hcnt, int32_t* hlong,
+                                                   int32_t* lw, int32_t* cir, T* cnum) {
   __shared__ uint64_t s_key[CAP];
   __shared__ int32_t s_head[CAP + 1];  // sorted position of each distinct row's first key
   __shared__ int32_t s_nin[CAP + 1];   // distinct rows before k that A(:,j) lacks
@@ -1162,9 +1122,14 @@ __global__ void __launch_bounds__(256) k_ea_column(Operand A, Operand B, const i
   for (int64_t w = blockIdx.x; w < nl; w += gridDim.x) {
     const int64_t u = list ? list[w] : w;
     const int32_t j = mod[u];
+    const bool long_a = slot_begin(A, j + 1) - slot_begin(A, j) > kEaLongA;
     const int64_t nins = ea_landing_keys(B, I, j, qoff, qlist, s_key, CAP);
-    if (!kFill && CAP == kAsgnMaxInsert && threadIdx.x == 0) hcnt[w] = nins > CAP ? nins : 0;
-    if (nins > CAP) {  // uniform across the workgroup
+    if (!kFill && CAP == kAsgnMaxInsert && threadIdx.x == 0) {
+      hcnt[w] = nins > CAP || long_a ? nins : 0;
+      hlong[w] = long_a ? 1 : 0;
+      if (long_a) lw[u] = (int32_t)w;
+    }
+    if (nins > CAP || long_a) {  // uniform: a segment column (k_ea_huge), listed by the one-wave variant
       if (!kFill && CAP < kAsgnMaxInsert && threadIdx.x == 0) big[atomicAdd(nbig, 1ull)] = (int32_t)u;
       __syncthreads();
       continue;
@@ -1174,17 +1139,27 @@ __global__ void __launch_bounds__(256) k_ea_column(Operand A, Operand B, const i
   }
 }
 
-// Huge columns (more than kAsgnMaxInsert landing entries), at plan time:
-// each workgroup writes one column's keys into its segment of hkeys, pads
-// the segment to its power-of-two length and sorts it in global memory.
+// Segment columns, at plan time: each workgroup writes one column's keys
+// into its segment of hkeys.  A huge column's (more than kAsgnMaxInsert
+// landing entries) is padded to its power-of-two length and sorted in
+// global memory; a long A column's fewer keys are sorted in LDS (segment of
+// max(keys, 1) entries).
 __global__ void __launch_bounds__(256) k_ea_huge_keys(Operand B, const int32_t* I, const int32_t* mod,
                                                       const int32_t* big, int64_t nbig, const int64_t* qoff,
                                                       const int32_t* qlist, const int64_t* hoff, uint64_t* hkeys) {
   __shared__ uint64_t s_tile[kAsgnMaxInsert];
   for (int64_t w = blockIdx.x; w < nbig; w += gridDim.x) {
     const int64_t p2 = hoff[w + 1] - hoff[w];
-    if (p2 == 0) continue;  // uniform: not a huge column
+    if (p2 == 0) continue;  // uniform: not a segment column
     uint64_t* seg = hkeys + hoff[w];
+    if (p2 < kAsgnMaxInsert) {  // a long A column's few keys: sorted in LDS
+      const int64_t nins = ea_landing_keys(B, I, mod[big[w]], qoff, qlist, s_tile, kAsgnMaxInsert);
+      __syncthreads();
+      lds_sort_keys(s_tile, (int)nins);
+      for (int64_t s = threadIdx.x; s < p2; s += blockDim.x) seg[s] = s_tile[s];
+      __syncthreads();
+      continue;
+    }
     const int64_t nins = ea_landing_keys(B, I, mod[big[w]], qoff, qlist, seg, p2);
     for (int64_t s = nins + threadIdx.x; s < p2; s += blockDim.x) seg[s] = ~0ull;
     __threadfence_block();
@@ -1193,20 +1168,103 @@ __global__ void __launch_bounds__(256) k_ea_huge_keys(Operand B, const int32_t* 
   }
 }
 
-// Huge columns, count (plan) or fill (exec) pass: ea_column_body over the
-// sorted global keys; head and nin take hoff[w] + w .. + p2 + 1 of hidx.
+// Segment columns, count (plan) or fill (exec) pass: ea_column_body over
+// the sorted global keys; head and nin take hoff[w] + w .. + p2 + 1 of
+// hhead and hnin, and the count pass records the distinct rows in hnu.  The
+// fill pass leaves a long A column's entries to the tiles.
 template <bool kFill, bool kVals, typename T, class Acc>
 __global__ void __launch_bounds__(256) k_ea_huge(Operand A, Operand B, const int32_t* mod, const int32_t* big,
                                                  int64_t nbig, const int64_t* hcnt, const int64_t* hoff,
-                                                 const uint64_t* hkeys, int32_t* hhead, int32_t* hnin, int64_t* cnt,
+                                                 const uint64_t* hkeys, int32_t* hhead, int32_t* hnin,
+                                                 const int32_t* hlong, int64_t* hnu, int64_t* cnt,
                                                  const int64_t* off, int32_t* cir, T* cnum) {
   __shared__ int64_t red[256 / kWave + 1];
   const T* bnum = static_cast<const T*>(B.num);
   for (int64_t w = blockIdx.x; w < nbig; w += gridDim.x) {
-    if (hoff[w + 1] == hoff[w]) continue;  // uniform: not a huge column
+    if (hoff[w + 1] == hoff[w]) continue;  // uniform: not a segment column
     const int64_t seg = hoff[w] + w;
-    ea_column_body<kFill, kVals, T, Acc>(A, mod[big[w]], hkeys + hoff[w], hcnt[w], hhead + seg, hnin + seg, red, cnt,
-                                         off, bnum, cir, cnum);
+    const int64_t nu = ea_column_body<kFill, kVals, T, Acc>(A, mod[big[w]], hkeys + hoff[w], hcnt[w], hhead + seg,
+                                                            hnin + seg, red, cnt, off, bnum, cir, cnum,
+                                                            kFill && hlong[w]);
+    if (!kFill && threadIdx.x == 0) hnu[w] = nu;
+  }
+}
+
+// Extend-add's tiles (the merged order above): an entry in the run before
+// staged column i moves by that run's output shift; an entry of a long
+// modified column (big-list entry lw[u] >= 0) keeps its place among A's
+// rows and moves by the new rows below it, found in the column's sorted
+// distinct landing rows (segment w: keys, heads, new-row counts), and adds
+// the landing values of its own row in key order.  The other modified
+// columns' entries are left to the column kernels.
+template <bool kVals, typename T, class Acc>
+__global__ void __launch_bounds__(kTileThreads) k_ea_tiles(Operand A, Operand B, const int32_t* mod, int64_t nmod,
+                                                           const int64_t* tmod, int64_t nt, const int64_t* off,
+                                                           const int32_t* lw, const int64_t* hoff,
+                                                           const uint64_t* hkeys, const int32_t* hhead,
+                                                           const int32_t* hnin, const int64_t* hnu, int32_t* cir,
+                                                           T* cnum) {
+  __shared__ int16_t s_beg[kTileItems + 1];
+  __shared__ int16_t s_end[kTileItems + 1];
+  __shared__ int32_t s_lw[kTileItems + 1];
+  __shared__ int64_t s_shift[kTileItems + 1];  // output shift of the run before staged column i
+  __shared__ int64_t s_mo[kTileItems + 1];     // off[c] - cp[c] of a long staged column
+  const T* anum = static_cast<const T*>(A.num);
+  const T* bnum = static_cast<const T*>(B.num);
+  for (int64_t t = blockIdx.x; t < nt; t += gridDim.x) {
+    const TileSpan sp = tile_span(A, nmod, tmod, t);
+    for (int64_t i = threadIdx.x; i <= sp.ue - sp.us; i += kTileThreads) {
+      const int64_t r = sp.us + i;
+      const int64_t c0 = r == 0 ? 0 : (int64_t)mod[r - 1] + 1;
+      s_shift[i] = off[c0] - slot_begin(A, c0);
+      if (i < sp.nst) {
+        const int64_t c = mod[r];
+        const int64_t cb = slot_begin(A, c);
+        s_beg[i] = (int16_t)tile_rel(cb, sp.es);
+        s_end[i] = (int16_t)tile_rel(slot_begin(A, c + 1), sp.es);
+        s_lw[i] = lw[r];
+        s_mo[i] = off[c] - cb;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kTilePer; ++k) {
+      const int32_t x = threadIdx.x + k * kTileThreads;
+      const int64_t e = sp.es + x;
+      if (e >= sp.ee) continue;
+      const int32_t lo = staged_rank(s_end, sp.nst, x);
+      const bool inmod = lo < sp.nst && s_beg[lo] <= x;
+      if (!inmod) {
+        const int64_t dst = e + s_shift[lo];
+        cir[dst] = A.ir[e];
+        if (kVals) cnum[dst] = anum[e];
+        continue;
+      }
+      const int32_t w = s_lw[lo];
+      if (w < 0) continue;  // a column kernel's entry
+      const int32_t row = A.ir[e];
+      const uint64_t* keys = hkeys + hoff[w];
+      const int64_t seg = hoff[w] + w;
+      const int32_t* head = hhead + seg;
+      const int64_t nu = hnu[w];
+      int64_t a = 0, b = nu;  // distinct landing rows below this row
+      while (a < b) {
+        const int64_t mid = (a + b) >> 1;
+        if ((int32_t)(keys[head[mid]] >> 32) < row)
+          a = mid + 1;
+        else
+          b = mid;
+      }
+      const int64_t dst = e + s_mo[lo] + hnin[seg + a];
+      cir[dst] = row;
+      if (kVals) {
+        T acc = anum[e];
+        if (a < nu && (int32_t)(keys[head[a]] >> 32) == row)
+          for (int64_t h = head[a]; h < head[a + 1]; ++h) acc = Acc::add(acc, bnum[(uint32_t)keys[h]]);
+        cnum[dst] = acc;
+      }
+    }
+    __syncthreads();
   }
 }
 
@@ -1221,12 +1279,19 @@ int launch_ea(const ExtAddPlan* P, int32_t* cir, void* cnum, hipStream_t st, boo
   if (huge) {
     if (P->nhuge_keys > 0) {
       k_ea_huge<kFill, kVals, T, Acc><<<(unsigned)std::min<int64_t>(P->nbig, (int64_t)cus * 2), 256, 0, st>>>(
-          P->A, P->B, P->mod, P->big, P->nbig, P->hcnt, P->hoff, P->hkeys, P->hhead, P->hnin, P->cnt, P->off, cir,
-          out);
+          P->A, P->B, P->mod, P->big, P->nbig, P->hcnt, P->hoff, P->hkeys, P->hhead, P->hnin, P->hlong, P->hnu,
+          P->cnt, P->off, cir, out);
       SPX_HIP(hipGetLastError());
     }
     return SPX_OK;
   }
+  if (kFill && P->ntiles > 0) {  // unmodified runs and the long columns' A entries
+    k_ea_tiles<kVals, T, Acc><<<(unsigned)std::min<int64_t>(P->ntiles, (int64_t)cus * 32), kTileThreads, 0, st>>>(
+        P->A, P->B, P->mod, P->nmod, P->tmod, P->ntiles, P->off, P->lw, P->hoff, P->hkeys, P->hhead, P->hnin, P->hnu,
+        cir, out);
+    SPX_HIP(hipGetLastError());
+  }
+  if (P->nmod == 0) return SPX_OK;
   k_ea_wave<kFill, kVals, T, Acc><<<(unsigned)std::min<int64_t>(ceil_div(P->nmod, (int64_t)4), (int64_t)cus * 16),
                                      256, 0, st>>>(P->A, P->B, P->I, P->mod, P->nmod, P->qoff, P->qlist, P->cnt,
                                                    P->off, P->rest, P->nrest_d, cir, out);
@@ -1235,14 +1300,14 @@ int launch_ea(const ExtAddPlan* P, int32_t* cir, void* cnum, hipStream_t st, boo
     const int64_t grid = kFill ? std::min<int64_t>(P->nrest, (int64_t)cus * 32) : (int64_t)cus * 32;
     k_ea_column<kFill, kVals, kAsgnSmall, T, Acc><<<(unsigned)grid, 64, 0, st>>>(
         P->A, P->B, P->I, P->mod, P->rest, kFill ? nullptr : P->nrest_d, P->nrest, P->qoff, P->qlist, P->cnt,
-        P->off, P->big, P->nbig_d, P->hcnt, cir, out);
+        P->off, P->big, P->nbig_d, P->hcnt, P->hlong, P->lw, cir, out);
     SPX_HIP(hipGetLastError());
   }
   if (!kFill || P->nbig > 0) {
     const int64_t grid = kFill ? std::min<int64_t>(P->nbig, (int64_t)cus * 4) : (int64_t)cus * 4;
     k_ea_column<kFill, kVals, kAsgnMaxInsert, T, Acc><<<(unsigned)grid, 256, 0, st>>>(
         P->A, P->B, P->I, P->mod, P->big, kFill ? nullptr : P->nbig_d, P->nbig, P->qoff, P->qlist, P->cnt, P->off,
-        P->big, P->nbig_d, P->hcnt, cir, out);
+        P->big, P->nbig_d, P->hcnt, P->hlong, P->lw, cir, out);
     SPX_HIP(hipGetLastError());
   }
   return SPX_OK;
@@ -1477,12 +1542,14 @@ extern "C" int spx_extend_add_plan(const spx_ctx* ctx, const spx_mat* A, const i
   }
   SPX_TRY(scr.get_many({Scratch::part(&P->rest, P->nmod), Scratch::part(&P->big, P->nmod),
                         Scratch::part(&P->hcnt, P->nmod), Scratch::part(&P->hoff, P->nmod + 1),
-                        Scratch::part(&P->nbig_d, 2)}));
+                        Scratch::part(&P->nbig_d, 2), Scratch::part(&P->hlong, P->nmod),
+                        Scratch::part(&P->lw, P->nmod)}));
+  SPX_TRY(fill_u32(reinterpret_cast<uint32_t*>(P->lw), P->nmod, 0xffffffffu, st));
   P->nrest_d = P->nbig_d + 1;
   SPX_TRY(fill_i64((int64_t*)P->nbig_d, 2, 0, st));
   if (P->nmod > 0) SPX_TRY(dispatch_ea<false>(P, nullptr, nullptr, st, false));
   // key segments of the huge columns (big-list order; entries past nbig are empty)
-  SPX_TRY(exclusive_scan(HugeCap{P->hcnt, nullptr, P->nbig_d}, P->nmod, P->hoff, scr, st));
+  SPX_TRY(exclusive_scan(EaSeg{P->hcnt, P->hlong, P->nbig_d}, P->nmod, P->hoff, scr, st));
   {
     int64_t h[3] = {0, 0, 0};
     SPX_TRY(read_device_words(st, {{P->nbig_d, 8}, {P->nbig_d + 1, 8}, {P->hoff + P->nmod, 8}}, h));
@@ -1493,7 +1560,7 @@ extern "C" int spx_extend_add_plan(const spx_ctx* ctx, const spx_mat* A, const i
   if (P->nhuge_keys > 0) {
     if (P->nhuge_keys >= (1ll << 31)) return fail(SPX_EUNSUPPORTED, "landing entries of the large columns exceed 2^31");
     SPX_TRY(scr.get_many({Scratch::part(&P->hkeys, P->nhuge_keys), Scratch::part(&P->hhead, P->nhuge_keys + P->nbig),
-                          Scratch::part(&P->hnin, P->nhuge_keys + P->nbig)}));
+                          Scratch::part(&P->hnin, P->nhuge_keys + P->nbig), Scratch::part(&P->hnu, P->nbig)}));
     const int cus = device_cu_count();
     k_ea_huge_keys<<<(unsigned)std::min<int64_t>(P->nbig, (int64_t)cus * 2), 256, 0, st>>>(
         P->B, I, P->mod, P->big, P->nbig, P->qoff, P->qlist, P->hoff, P->hkeys);
@@ -1521,12 +1588,8 @@ extern "C" int spx_extend_add_exec(spx_plan* plan, spx_mat* C) {
   C->nnz = P->nnz;
   C->nzc = 0;
   hipStream_t st = stream_of(&P->ctx);
-  const int vb = value_size(P->A.val_t);
-  SPX_TRY(launch_copy(P->A, P->mod, P->nmod, P->tmod, P->ntiles, P->off, vb, C->ir, C->num, st));
-  if (P->nmod > 0) {
-    SPX_TRY(dispatch_ea<true>(P, C->ir, C->num, st, false));
-    SPX_TRY(dispatch_ea<true>(P, C->ir, C->num, st, true));
-  }
+  SPX_TRY(dispatch_ea<true>(P, C->ir, C->num, st, false));  // tiles, then the column kernels
+  if (P->nmod > 0) SPX_TRY(dispatch_ea<true>(P, C->ir, C->num, st, true));
   k_asgn_write_cp<<<grid_for(P->A.n + 1, 256, 65536), 256, 0, st>>>(P->off, P->A.n, C->cp, C->ptr_t);
   SPX_HIP(hipGetLastError());
   return SPX_OK;
