@@ -272,16 +272,29 @@ class Server:
 
     # ---- request loops ---------------------------------------------------
     def run(self, requests: List[Request], keep_results: bool = False) -> List[Request]:
+        """Serve `requests` (arrival times relative to the start).  The
+        interpreter's cyclic garbage collector is paused meanwhile, as serving
+        loops do: a full collection stops every thread for milliseconds and
+        would land in the latency tail (reference counting still frees the
+        requests' buffers as they complete)."""
+        import gc
         import torch
         self.keep_results = keep_results
         for r in requests:
             r.est_bytes = estimate_bytes(self.store, r)
         torch.cuda.synchronize()
-        self._t0 = time.perf_counter()
-        if self.mode == "plain":
-            self._run_plain(requests)
-        else:
-            self._run_batched(requests)
+        was_enabled = gc.isenabled()
+        gc.collect()
+        gc.disable()
+        try:
+            self._t0 = time.perf_counter()
+            if self.mode == "plain":
+                self._run_plain(requests)
+            else:
+                self._run_batched(requests)
+        finally:
+            if was_enabled:
+                gc.enable()
         return requests
 
     def _run_plain(self, requests: List[Request]):
@@ -374,11 +387,22 @@ class Server:
                 ts = self.now()
                 for r in batch:
                     r.start = ts
-                lane = free[0]
-                lane.busy = True
-                self.rounds += 1
+                # the admitted requests go to every idle lane: the heaviest
+                # first, each to the lane with the least work so far (by the
+                # requests' HBM estimates), keeping arrival order in a lane
+                k = min(len(free), len(batch))
+                parts: List[List[Request]] = [[] for _ in range(k)]
+                load = [0] * k
+                for r in sorted(batch, key=lambda r: -r.est_bytes):
+                    i = load.index(min(load))
+                    parts[i].append(r)
+                    load[i] += r.est_bytes
+                for lane, part in zip(free, parts):
+                    part.sort(key=lambda r: r.arrival)
+                    lane.busy = True
+                    self.rounds += 1
+                    lane.inbox.put(part)
                 self.max_busy_lanes = max(self.max_busy_lanes, sum(ln.busy for ln in lanes))
-                lane.inbox.put(batch)
         finally:
             for ln in lanes:
                 ln.inbox.put(None)
