@@ -19,7 +19,6 @@
 #include "operand.h"
 #include "plan.h"
 #include "scan.h"
-#include "sort.h"
 
 namespace spx {
 
@@ -62,14 +61,86 @@ struct LoadU32 {
   __device__ int64_t operator()(int64_t i) const { return (int64_t)p[i]; }
 };
 
-__global__ void k_pair_keys(const int32_t* I, int64_t lenI, uint64_t* keys) {
-  for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < lenI; p += (int64_t)gridDim.x * blockDim.x)
-    keys[p] = ((uint64_t)(uint32_t)I[p] << 32) | (uint32_t)p;
+// Transpose of R: the positions p of each row index i = I(p), ascending,
+// at rpos[rptr[i] ..].  A counting scatter fills each row's slots in any
+// order (its count in rcnt runs down to zero), then every row sorts its
+// own slots: rows of at most kRowShort positions by one thread in place,
+// longer ones by a workgroup (LDS bitonic sort up to kRowLds positions,
+// else one ordered pass over I that keeps the positions of that row).
+constexpr int64_t kRowShort = 16;
+constexpr int kRowLds = 4096;
+
+__global__ void k_scatter_rows(const int32_t* I, int64_t lenI, int64_t m, const int64_t* rptr, unsigned* rcnt,
+                               int32_t* rpos) {
+  for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < lenI; p += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t i = I[p];
+    if (i >= 0 && i < m) rpos[rptr[i] + atomicSub(&rcnt[i], 1u) - 1] = (int32_t)p;
+  }
 }
 
-__global__ void k_low32(const uint64_t* keys, int64_t n, int32_t* out) {
-  for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < n; s += (int64_t)gridDim.x * blockDim.x)
-    out[s] = (int32_t)(keys[s] & 0xffffffffu);
+__global__ void k_sort_rows(const int64_t* rptr, int64_t m, int32_t* rpos, int32_t* longs,
+                            unsigned long long* nlong) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r0 = rptr[i], r1 = rptr[i + 1];
+    if (r1 - r0 > kRowShort) {
+      longs[atomicAdd(nlong, 1ull)] = (int32_t)i;
+      continue;
+    }
+    for (int64_t a = r0 + 1; a < r1; ++a) {  // insertion sort
+      const int32_t x = rpos[a];
+      int64_t b = a - 1;
+      while (b >= r0 && rpos[b] > x) {
+        rpos[b + 1] = rpos[b];
+        --b;
+      }
+      rpos[b + 1] = x;
+    }
+  }
+}
+
+__global__ void __launch_bounds__(256) k_sort_long_rows(const int32_t* I, int64_t lenI, const int64_t* rptr,
+                                                        const int32_t* longs, const unsigned long long* nlong,
+                                                        int32_t* rpos) {
+  __shared__ uint32_t s[kRowLds];
+  __shared__ int64_t red[256 / kWave + 1];
+  const int64_t n = (int64_t)*nlong;
+  for (int64_t w = blockIdx.x; w < n; w += gridDim.x) {
+    const int32_t i = longs[w];
+    const int64_t r0 = rptr[i], len = rptr[i + 1] - r0;
+    if (len <= kRowLds) {  // uniform
+      int p2 = 1;
+      while (p2 < len) p2 <<= 1;
+      for (int t = threadIdx.x; t < p2; t += blockDim.x) s[t] = t < len ? (uint32_t)rpos[r0 + t] : 0xffffffffu;
+      __syncthreads();
+      for (int k = 2; k <= p2; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+          for (int t = threadIdx.x; t < (p2 >> 1); t += blockDim.x) {
+            const int lo = 2 * t - (t & (j - 1));
+            const int hi = lo + j;
+            const bool asc = (lo & k) == 0;
+            const uint32_t x = s[lo], y = s[hi];
+            if ((x > y) == asc) {
+              s[lo] = y;
+              s[hi] = x;
+            }
+          }
+          __syncthreads();
+        }
+      }
+      for (int t = threadIdx.x; t < len; t += blockDim.x) rpos[r0 + t] = (int32_t)s[t];
+      __syncthreads();
+    } else {
+      int64_t run = 0;
+      for (int64_t pc = 0; pc < lenI; pc += blockDim.x) {
+        const int64_t p = pc + threadIdx.x;
+        const int64_t f = p < lenI && I[p] == i;
+        int64_t tot;
+        const int64_t ex = block_excl_scan(f, red, &tot);
+        if (f) rpos[r0 + run + ex] = (int32_t)p;
+        run += tot;
+      }
+    }
+  }
 }
 
 __global__ void k_col_info(Operand A, const int64_t* aux, int64_t chunk, const int32_t* J, int64_t lenJ, int64_t* qa0,
@@ -264,21 +335,29 @@ __global__ void __launch_bounds__(256) k_ref_medium(Operand A, const int64_t* qa
     const int32_t al = qlen[q];
     const int c = (int)cnt[q];
     int64_t total = 0;
-    for (int32_t ec = 0; ec < al; ec += blockDim.x) {
-      const int32_t e = ec + threadIdx.x;
-      int32_t i = 0;
-      int64_t rc = 0;
-      if (e < al) {
-        i = A.ir[a0 + e];
-        rc = rptr[i + 1] - rptr[i];
+    // four consecutive gathered entries per thread and round, their loads in flight together
+    for (int32_t ec = 0; ec < al; ec += 4 * (int32_t)blockDim.x) {
+      const int32_t e0 = ec + 4 * (int32_t)threadIdx.x;
+      int32_t i[4];
+      int64_t rb[4], rc[4];
+      int64_t mine = 0;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) i[k] = e0 + k < al ? A.ir[a0 + e0 + k] : -1;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        rb[k] = i[k] >= 0 ? rptr[i[k]] : 0;
+        rc[k] = i[k] >= 0 ? rptr[i[k] + 1] - rb[k] : 0;
+        mine += rc[k];
       }
       int64_t ctot;
-      const int64_t excl = block_excl_scan(rc, red, &ctot);
-      for (int64_t r = 0; r < rc; ++r) {
-        const int64_t slot = total + excl + r;
-        if (slot < kRefMedium) {
-          s_key[slot] = ((uint64_t)(uint32_t)rpos[rptr[i] + r] << 32) | (uint32_t)slot;
-          s_e[slot] = a0 + e;
+      int64_t slot = total + block_excl_scan(mine, red, &ctot);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        for (int64_t r = 0; r < rc[k]; ++r, ++slot) {
+          if (slot < kRefMedium) {
+            s_key[slot] = ((uint64_t)(uint32_t)rpos[rb[k] + r] << 32) | (uint32_t)slot;
+            s_e[slot] = a0 + e0 + k;
+          }
         }
       }
       total += ctot;
@@ -386,13 +465,16 @@ extern "C" int spx_spref_plan(const spx_ctx* ctx, const spx_mat* A, const int32_
   const int64_t m = A->m;
   const int cus = device_cu_count();
   unsigned* rcnt = nullptr;
-  unsigned long long *clscount = nullptr, *fill = nullptr;
-  SPX_TRY(scr.get_many({Scratch::part(&P->err, 4), Scratch::part(&rcnt, m + 1), Scratch::part(&P->rptr, m + 1),
+  unsigned long long *clscount = nullptr, *fill = nullptr, *nlong = nullptr;
+  int32_t* longs = nullptr;  // rows with more than kRowShort positions (at most lenI / 17)
+  SPX_TRY(scr.get_many({Scratch::part(&nlong, 1), Scratch::part(&longs, lenI / (kRowShort + 1) + 1),
+                        Scratch::part(&P->err, 4), Scratch::part(&rcnt, m + 1), Scratch::part(&P->rptr, m + 1),
                         Scratch::part(&P->rpos, lenI), Scratch::part(&P->qa0, lenJ), Scratch::part(&P->qlen, lenJ),
                         Scratch::part(&P->cnt, lenJ), Scratch::part(&P->off, lenJ + 1), Scratch::part(&P->list, lenJ),
                         Scratch::part(&P->clsoff, kNumCls + 1), Scratch::part(&clscount, kNumCls),
                         Scratch::part(&fill, kNumCls)}));
   SPX_TRY(fill_u32(P->err, 1, 0, st));
+  SPX_TRY(fill_i64(reinterpret_cast<int64_t*>(nlong), 1, 0, st));
   if (lenI > 0) {
     k_check_index<<<grid_for(lenI, 256, 4096), 256, 0, st>>>(I, lenI, m, P->err, 1u);
     SPX_HIP(hipGetLastError());
@@ -406,15 +488,16 @@ extern "C" int spx_spref_plan(const spx_ctx* ctx, const spx_mat* A, const int32_
   if (lenI > 0) {
     k_row_hist<<<grid_for(lenI, 256, 4096), 256, 0, st>>>(I, lenI, m, rcnt);
     SPX_HIP(hipGetLastError());
-    uint64_t* keys = nullptr;
-    SPX_TRY(scr.get_n(sort_capacity(lenI), &keys));
-    k_pair_keys<<<grid_for(lenI, 256, 4096), 256, 0, st>>>(I, lenI, keys);
-    SPX_HIP(hipGetLastError());
-    SPX_TRY(sort_u64(keys, lenI, st));
-    k_low32<<<grid_for(lenI, 256, 4096), 256, 0, st>>>(keys, lenI, P->rpos);
-    SPX_HIP(hipGetLastError());
   }
   SPX_TRY(exclusive_scan(LoadU32{rcnt}, m, P->rptr, scr, st));
+  if (lenI > 0) {
+    k_scatter_rows<<<grid_for(lenI, 256, 4096), 256, 0, st>>>(I, lenI, m, P->rptr, rcnt, P->rpos);
+    SPX_HIP(hipGetLastError());
+    k_sort_rows<<<grid_for(m, 256, 4096), 256, 0, st>>>(P->rptr, m, P->rpos, longs, nlong);
+    SPX_HIP(hipGetLastError());
+    k_sort_long_rows<<<(unsigned)(cus * 2), 256, 0, st>>>(I, lenI, P->rptr, longs, nlong, P->rpos);
+    SPX_HIP(hipGetLastError());
+  }
   // A*Q: the columns J(q) of A
   int64_t *aux = nullptr, chunk = 1;
   SPX_TRY(build_aux(P->A, scr, st, &aux, &chunk));

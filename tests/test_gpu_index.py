@@ -42,6 +42,11 @@ def test_spref_long_columns_and_heavy_repeats(spx):
     spref_check(spx, A, I, J)
     I2 = np.concatenate([np.full(200, 5, np.int32), rng.integers(0, m, 100).astype(np.int32)])
     spref_check(spx, A, I2, J)
+    # a row index repeated 5000 times, interleaved with others: the transpose of R
+    # sorts that row's positions by an ordered pass over I (above the LDS sort's 4096)
+    I3 = rng.integers(0, m, 9000).astype(np.int32)
+    I3[rng.choice(9000, 5000, replace=False)] = 7
+    spref_check(spx, A, I3, J)
 
 
 def test_spref_permutation_roundtrip(spx):
