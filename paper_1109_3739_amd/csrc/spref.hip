@@ -41,6 +41,7 @@ struct SprefPlan : spx_plan {
   int32_t* list = nullptr;   // [lenJ] columns grouped by class
   int64_t* clsoff = nullptr; // [kNumCls+1]
   int64_t clsoff_h[kNumCls + 1] = {};
+  int64_t nwide = 0;         // columns gathering more than kRefWide entries of A
   unsigned* err = nullptr;
 };
 
@@ -156,8 +157,19 @@ __global__ void k_col_info(Operand A, const int64_t* aux, int64_t chunk, const i
 
 // nnz(B(:,q)) = sum over the entries (i, v) of A(:,J(q)) of |{p : I(p) = i}|;
 // one wave per column.  Also classifies the column.
+// Columns gathering more entries of A than this are counted (and, with at
+// most kRefMedium outputs, extracted) by 1024-thread workgroups, so that a
+// hub column of A is not left to one wave or one small workgroup.
+constexpr int32_t kRefWide = 4096;
+
+// Output class of a column with s outputs gathering al entries of A (a wide
+// column with few outputs still goes to the workgroup path).
+__device__ __forceinline__ int ref_class(int64_t s, int32_t al) {
+  return s == 0 ? kClsEmpty : (s <= kRefSmall && al <= kRefWide) ? kClsSmall : s <= kRefMedium ? kClsMedium : kClsLarge;
+}
+
 __global__ void k_ref_count(const Operand A, const int64_t* qa0, const int32_t* qlen, const int64_t* rptr, int64_t lenJ,
-                            int64_t* cnt, unsigned long long* clscount) {
+                            int64_t* cnt, unsigned long long* clscount, int32_t* wide, unsigned long long* nwide) {
   const int lane = lane_id();
   const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kWave;
   const int64_t nw = (int64_t)gridDim.x * blockDim.x / kWave;
@@ -165,6 +177,10 @@ __global__ void k_ref_count(const Operand A, const int64_t* qa0, const int32_t* 
   for (int64_t q = wave; q < lenJ; q += nw) {
     const int64_t a0 = qa0[q];
     const int32_t al = qlen[q];
+    if (al > kRefWide) {  // uniform: k_ref_count_wide's column
+      if (lane == 0) wide[atomicAdd(nwide, 1ull)] = (int32_t)q;
+      continue;
+    }
     int64_t s = 0;
     for (int32_t e0 = 0; e0 < al; e0 += 4 * kWave) {  // four rows in flight per lane
       int32_t i[4];
@@ -178,7 +194,7 @@ __global__ void k_ref_count(const Operand A, const int64_t* qa0, const int32_t* 
         if (i[k] >= 0) s += rptr[i[k] + 1] - rptr[i[k]];
     }
     s = wave_sum(s);
-    const int c = s == 0 ? kClsEmpty : s <= kRefSmall ? kClsSmall : s <= kRefMedium ? kClsMedium : kClsLarge;
+    const int c = ref_class(s, al);
     n0 += c == kClsEmpty;
     n1 += c == kClsSmall;
     n2 += c == kClsMedium;
@@ -198,6 +214,39 @@ __global__ void k_ref_count(const Operand A, const int64_t* qa0, const int32_t* 
   if (threadIdx.x < kNumCls && s_cls[threadIdx.x]) atomicAdd(&clscount[threadIdx.x], s_cls[threadIdx.x]);
 }
 
+// The wide columns' counts: one 1024-thread workgroup per column, four rows
+// in flight per thread.
+__global__ void __launch_bounds__(1024) k_ref_count_wide(const Operand A, const int64_t* qa0, const int32_t* qlen,
+                                                         const int64_t* rptr, const int32_t* wide,
+                                                         const unsigned long long* nwide, int64_t* cnt,
+                                                         unsigned long long* clscount) {
+  __shared__ int64_t red[1024 / kWave + 1];
+  const int64_t n = (int64_t)*nwide;
+  for (int64_t w = blockIdx.x; w < n; w += gridDim.x) {
+    const int32_t q = wide[w];
+    const int64_t a0 = qa0[q];
+    const int32_t al = qlen[q];
+    int64_t s = 0;
+    for (int32_t e0 = 0; e0 < al; e0 += 4 * (int32_t)blockDim.x) {
+      int32_t i[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int32_t e = e0 + k * (int32_t)blockDim.x + (int32_t)threadIdx.x;
+        i[k] = e < al ? A.ir[a0 + e] : -1;
+      }
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        if (i[k] >= 0) s += rptr[i[k] + 1] - rptr[i[k]];
+    }
+    int64_t tot;
+    block_excl_scan(s, red, &tot);
+    if (threadIdx.x == 0) {
+      cnt[q] = tot;
+      atomicAdd(&clscount[ref_class(tot, al)], 1ull);
+    }
+  }
+}
+
 __global__ void k_cls_offsets(unsigned long long* clscount, int64_t* clsoff, unsigned long long* fill) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     int64_t run = 0;
@@ -215,20 +264,17 @@ __global__ void k_cls_offsets(unsigned long long* clscount, int64_t* clsoff, uns
 // 16-bit fields, so one workgroup scan ranks every column in its class and
 // one atomic per class and workgroup claims the workgroup's slots.
 constexpr int kClsPer = 8;
-__global__ void __launch_bounds__(256) k_cls_fill(const int64_t* cnt, int64_t lenJ, const int64_t* clsoff,
-                                                  unsigned long long* fill, int32_t* list) {
+__global__ void __launch_bounds__(256) k_cls_fill(const int64_t* cnt, const int32_t* qlen, int64_t lenJ,
+                                                  const int64_t* clsoff, unsigned long long* fill, int32_t* list) {
   __shared__ uint64_t red[256 / kWave + 1];
   __shared__ unsigned long long s_base[kNumCls];
-  auto cls = [](int64_t s) {
-    return s == 0 ? kClsEmpty : s <= kRefSmall ? kClsSmall : s <= kRefMedium ? kClsMedium : kClsLarge;
-  };
   for (int64_t q0 = (int64_t)blockIdx.x * 256 * kClsPer; q0 < lenJ; q0 += (int64_t)gridDim.x * 256 * kClsPer) {
     const int64_t qt = q0 + (int64_t)threadIdx.x * kClsPer;
     int c[kClsPer];
     uint64_t mine = 0;
 #pragma unroll
     for (int k = 0; k < kClsPer; ++k) {
-      c[k] = qt + k < lenJ ? cls(cnt[qt + k]) : -1;
+      c[k] = qt + k < lenJ ? ref_class(cnt[qt + k], qlen[qt + k]) : -1;
       if (c[k] >= 0) mine += 1ull << (16 * c[k]);
     }
     uint64_t tot;
@@ -321,18 +367,20 @@ __global__ void __launch_bounds__(256) k_ref_small(Operand A, const int64_t* qa0
 }
 
 // Columns with at most 4096 entries: one workgroup, LDS bitonic sort.
-__global__ void __launch_bounds__(256) k_ref_medium(Operand A, const int64_t* qa0, const int32_t* qlen,
-                                                    const int64_t* rptr, const int32_t* rpos, const int32_t* list,
-                                                    const int64_t* clsoff, const int64_t* cnt, const int64_t* off,
-                                                    int vb, int32_t* bir, void* bnum) {
+template <int BLOCK>
+__global__ void __launch_bounds__(BLOCK) k_ref_medium(Operand A, const int64_t* qa0, const int32_t* qlen,
+                                                      const int64_t* rptr, const int32_t* rpos, const int32_t* list,
+                                                      const int64_t* clsoff, const int64_t* cnt, const int64_t* off,
+                                                      int vb, int32_t* bir, void* bnum) {
   __shared__ uint64_t s_key[kRefMedium];
   __shared__ int64_t s_e[kRefMedium];
-  __shared__ int64_t red[256 / kWave + 1];
+  __shared__ int64_t red[BLOCK / kWave + 1];
   const int64_t beg = clsoff[kClsMedium], end = clsoff[kClsMedium + 1];
   for (int64_t pos = beg + blockIdx.x; pos < end; pos += gridDim.x) {
     const int32_t q = list[pos];
     const int64_t a0 = qa0[q];
     const int32_t al = qlen[q];
+    if ((al > kRefWide) != (BLOCK > 256)) continue;  // uniform: the other variant's column
     const int c = (int)cnt[q];
     int64_t total = 0;
     // four consecutive gathered entries per thread and round, their loads in flight together
@@ -467,14 +515,17 @@ extern "C" int spx_spref_plan(const spx_ctx* ctx, const spx_mat* A, const int32_
   unsigned* rcnt = nullptr;
   unsigned long long *clscount = nullptr, *fill = nullptr, *nlong = nullptr;
   int32_t* longs = nullptr;  // rows with more than kRowShort positions (at most lenI / 17)
-  SPX_TRY(scr.get_many({Scratch::part(&nlong, 1), Scratch::part(&longs, lenI / (kRowShort + 1) + 1),
+  int32_t* wide = nullptr;   // columns gathering more than kRefWide entries of A
+  SPX_TRY(scr.get_many({Scratch::part(&nlong, 2), Scratch::part(&longs, lenI / (kRowShort + 1) + 1),
+                        Scratch::part(&wide, lenJ),
                         Scratch::part(&P->err, 4), Scratch::part(&rcnt, m + 1), Scratch::part(&P->rptr, m + 1),
                         Scratch::part(&P->rpos, lenI), Scratch::part(&P->qa0, lenJ), Scratch::part(&P->qlen, lenJ),
                         Scratch::part(&P->cnt, lenJ), Scratch::part(&P->off, lenJ + 1), Scratch::part(&P->list, lenJ),
                         Scratch::part(&P->clsoff, kNumCls + 1), Scratch::part(&clscount, kNumCls),
                         Scratch::part(&fill, kNumCls)}));
   SPX_TRY(fill_u32(P->err, 1, 0, st));
-  SPX_TRY(fill_i64(reinterpret_cast<int64_t*>(nlong), 1, 0, st));
+  SPX_TRY(fill_i64(reinterpret_cast<int64_t*>(nlong), 2, 0, st));  // long rows, wide columns
+  unsigned long long* nwide = nlong + 1;
   if (lenI > 0) {
     k_check_index<<<grid_for(lenI, 256, 4096), 256, 0, st>>>(I, lenI, m, P->err, 1u);
     SPX_HIP(hipGetLastError());
@@ -506,25 +557,27 @@ extern "C" int spx_spref_plan(const spx_ctx* ctx, const spx_mat* A, const int32_
     k_col_info<<<grid_for(lenJ, 256, 4096), 256, 0, st>>>(P->A, aux, chunk, J, lenJ, P->qa0, P->qlen);
     SPX_HIP(hipGetLastError());
     k_ref_count<<<grid_for(lenJ * kWave, 256, (int64_t)cus * 8), 256, 0, st>>>(P->A, P->qa0, P->qlen, P->rptr, lenJ,
-                                                                                P->cnt, clscount);
+                                                                                P->cnt, clscount, wide, nwide);
+    SPX_HIP(hipGetLastError());
+    k_ref_count_wide<<<(unsigned)(cus * 2), 1024, 0, st>>>(P->A, P->qa0, P->qlen, P->rptr, wide, nwide, P->cnt,
+                                                           clscount);
     SPX_HIP(hipGetLastError());
   }
   k_cls_offsets<<<1, 64, 0, st>>>(clscount, P->clsoff, fill);
   SPX_HIP(hipGetLastError());
   if (lenJ > 0) {
-    k_cls_fill<<<grid_for(lenJ, 256 * kClsPer, 4096), 256, 0, st>>>(P->cnt, lenJ, P->clsoff, fill, P->list);
+    k_cls_fill<<<grid_for(lenJ, 256 * kClsPer, 4096), 256, 0, st>>>(P->cnt, P->qlen, lenJ, P->clsoff, fill,
+                                                                     P->list);
     SPX_HIP(hipGetLastError());
   }
   SPX_TRY(exclusive_scan(LoadI64{P->cnt}, lenJ, P->off, scr, st));
-  static_assert(kNumCls + 1 == 5, "the read below takes the class offsets as five words");
-  int64_t h[7] = {};
-  const int64_t* co = P->clsoff;
-  SPX_TRY(read_device_words(st, {{co, 8}, {co + 1, 8}, {co + 2, 8}, {co + 3, 8}, {co + 4, 8}, {P->off + lenJ, 8},
-                                 {P->err, 4}}, h));
-  if (h[6] & 1) return fail(SPX_EINVAL, "I has an index outside [0, m)");
-  if (h[6] & 2) return fail(SPX_EINVAL, "J has an index outside [0, n)");
+  int64_t h[kNumCls + 4] = {};
+  SPX_TRY(read_device_words(st, {{P->clsoff, 8, kNumCls + 1}, {P->off + lenJ, 8}, {P->err, 4}, {nwide, 8}}, h));
+  if (h[kNumCls + 2] & 1) return fail(SPX_EINVAL, "I has an index outside [0, m)");
+  if (h[kNumCls + 2] & 2) return fail(SPX_EINVAL, "J has an index outside [0, n)");
   for (int c = 0; c <= kNumCls; ++c) P->clsoff_h[c] = h[c];
-  const int64_t nnz = h[5];
+  P->nwide = h[kNumCls + 3];
+  const int64_t nnz = h[kNumCls + 1];
   P->nnz = nnz;
   if (nnz_b) *nnz_b = nnz;
   *plan = guard.release();
@@ -552,9 +605,14 @@ extern "C" int spx_spref_exec(spx_plan* plan, spx_mat* B) {
     SPX_HIP(hipGetLastError());
   }
   if (co[kClsMedium + 1] > co[kClsMedium]) {
-    k_ref_medium<<<grid_for(co[kClsMedium + 1] - co[kClsMedium], 1, (int64_t)cus * 2), 256, 0, st>>>(
+    k_ref_medium<256><<<grid_for(co[kClsMedium + 1] - co[kClsMedium], 1, (int64_t)cus * 2), 256, 0, st>>>(
         P->A, P->qa0, P->qlen, P->rptr, P->rpos, P->list, P->clsoff, P->cnt, P->off, vb, B->ir, B->num);
     SPX_HIP(hipGetLastError());
+    if (P->nwide > 0) {  // medium columns that gather more than kRefWide entries
+      k_ref_medium<1024><<<(unsigned)std::min<int64_t>(P->nwide, (int64_t)cus * 2), 1024, 0, st>>>(
+          P->A, P->qa0, P->qlen, P->rptr, P->rpos, P->list, P->clsoff, P->cnt, P->off, vb, B->ir, B->num);
+      SPX_HIP(hipGetLastError());
+    }
   }
   if (co[kClsLarge + 1] > co[kClsLarge]) {
     k_ref_large<<<grid_for(co[kClsLarge + 1] - co[kClsLarge], 1, (int64_t)cus * 2), 1024, 0, st>>>(

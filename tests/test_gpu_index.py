@@ -47,6 +47,8 @@ def test_spref_long_columns_and_heavy_repeats(spx):
     I3 = rng.integers(0, m, 9000).astype(np.int32)
     I3[rng.choice(9000, 5000, replace=False)] = 7
     spref_check(spx, A, I3, J)
+    # few outputs from columns that gather thousands of entries (the wide-column path)
+    spref_check(spx, A, rng.integers(0, m, 30).astype(np.int32), J)
 
 
 def test_spref_permutation_roundtrip(spx):
