@@ -1006,92 +1006,145 @@ __device__ __forceinline__ int64_t ea_landing_keys(const Operand& B, const int32
   return nins;
 }
 
-// Modified columns of extend-add whose A column and landing entries both
-// fit the 64 lanes of a wave, done in registers: lane l holds A(:,j)'s l-th
-// entry and the l-th landing key (I(p) << 32 | e), the keys sorted across
-// the wave.  The first lane of each distinct landing row finds the row among
-// A's (lane reads): its output position is A's rows below it plus the new
-// rows below it, and it sums the row's landing values in key order onto A's
-// value, or onto the first landing value for a new row.  A's entries that
-// receive nothing move down by the new rows below them.  The count pass
-// writes nnz(C(:,j)) and lists the other columns in `rest` for the LDS
-// kernels; the fill pass skips them.
+// One modified column of extend-add per group of G lanes (G = 16 or 64, the
+// group aligned in the wave), done in registers: lane l of the group holds
+// A(:,j)'s l-th entry and the l-th landing key (I(p) << 32 | e), the keys
+// sorted within the group.  The first lane of each distinct landing row
+// finds the row among A's (lane reads): its output position is A's rows
+// below it plus the new rows below it, and it sums the row's landing values
+// in key order onto A's value, or onto the first landing value for a new
+// row.  A's entries that receive nothing move down by the new rows below
+// them.  `keep` (per group) says whether the group's results are written:
+// every lane runs the exchanges.  Count pass: nnz(C(:,j)); fill pass: the
+// entries.
+template <int G, bool kFill, bool kVals, typename T, class Acc>
+__device__ __forceinline__ void ea_group_column(const Operand& A, const Operand& B, bool keep, int32_t j,
+                                                int64_t a0, int alen, int nk, uint64_t key, int64_t* cnt,
+                                                const int64_t* off, int32_t* cir, T* cnum) {
+  const T* anum = static_cast<const T*>(A.num);
+  const T* bnum = static_cast<const T*>(B.num);
+  const int lane = lane_id();
+  const int gl = lane & (G - 1), gb = lane & ~(G - 1);
+  const uint64_t gbits = G == 64 ? ~0ull : ((1ull << G) - 1);
+  const int32_t arow = gl < alen ? A.ir[a0 + gl] : 0x7fffffff;
+  key = G == 64 ? wave_sort_u64(key) : group16_sort_u64(key);
+  const int32_t krow = (int32_t)(key >> 32);  // lane gl < nk: the gl-th landing row
+  const int32_t prev = __shfl(krow, gl == 0 ? lane : lane - 1);
+  const bool head = gl < nk && (gl == 0 || prev != krow);
+  int at = 0;  // A rows below krow
+  bool found = false;
+  for (int t = 0; t < (G == kWave ? alen : G); ++t) {  // the whole wave: a uniform bound and lane reads
+    const int32_t r = G == kWave ? __builtin_amdgcn_readlane(arow, t) : __shfl(arow, gb + t);
+    if (t < alen) {
+      at += r < krow ? 1 : 0;
+      found = found || r == krow;
+    }
+  }
+  const uint64_t fm = (__ballot(head && !found) >> gb) & gbits;  // the group's new rows, bit gl
+  if (!kFill) {
+    if (keep && gl == 0) cnt[j] = alen + __popcll(fm);
+    return;
+  }
+  const int64_t cbase = keep ? off[j] : 0;
+  // A's entries that receive no landing value
+  bool landed = false;
+  int fbelow = 0;  // new rows below arow
+  for (int t = 0; t < (G == kWave ? nk : G); ++t) {
+    const int32_t r = G == kWave ? __builtin_amdgcn_readlane(krow, t) : __shfl(krow, gb + t);
+    if (t < nk) {
+      landed = landed || r == arow;
+      fbelow += ((fm >> t) & 1ull) && r < arow ? 1 : 0;
+    }
+  }
+  if (keep && gl < alen && !landed) {
+    const int64_t o = cbase + gl + fbelow;
+    cir[o] = arow;
+    if (kVals) cnum[o] = anum[a0 + gl];
+  }
+  // one entry per distinct landing row
+  const uint64_t hm = (__ballot(head) >> gb) & gbits;
+  const uint64_t after = gl == G - 1 ? 0ull : hm >> (gl + 1);
+  const int glen = head ? (after ? __ffsll((unsigned long long)after) : nk - gl) : 0;
+  const uint64_t below = gl == 0 ? 0ull : (fm & ((1ull << gl) - 1));
+  if (keep && head) cir[cbase + at + __popcll(below)] = krow;
+  if (kVals) {
+    const T bv = gl < nk ? bnum[(uint32_t)key] : T(0);
+    T acc = found && keep ? anum[a0 + at] : bv;
+    int gmax = glen;
+    for (int s = 1; s < kWave; s <<= 1) gmax = max(gmax, __shfl_xor(gmax, s));
+    for (int d = 0; d < gmax; ++d) {
+      const T v = __shfl(bv, gb + ((gl + d) & (G - 1)));
+      if (d < glen && (found || d > 0)) acc = Acc::add(acc, v);
+    }
+    if (keep && head) cnum[cbase + at + __popcll(below)] = acc;
+  }
+}
+
+// Landing keys of column j for a group of G lanes: lane gl takes the gl-th
+// landing entry (B columns q with J(q) = j, in list order); returns the
+// number of landing entries (counting stops once above G).
+template <int G>
+__device__ __forceinline__ int64_t ea_group_keys(const Operand& B, const int32_t* I, const int32_t* qlist, int64_t q0,
+                                                 int64_t q1, uint64_t* key) {
+  const int gl = lane_id() & (G - 1);
+  int64_t nins = 0;
+  *key = ~0ull;
+  for (int64_t t = q0; t < q1 && nins <= G; ++t) {
+    const int32_t q = qlist[t];
+    const int64_t b0 = slot_begin(B, q), len = slot_begin(B, q + 1) - b0;
+    if (nins + len <= G && gl >= nins && gl < nins + len) {
+      const int64_t e = b0 + (gl - nins);
+      *key = ((uint64_t)(uint32_t)I[B.ir[e]] << 32) | (uint32_t)e;
+    }
+    nins += len;
+  }
+  return nins;
+}
+
+// Modified columns whose A column and landing entries fit in registers: a
+// wave takes four columns at a time, one per 16-lane group; a column that
+// does not fit 16 then takes the whole wave (64), and one that does not fit
+// 64 goes, in the count pass, to the `rest` list for the LDS kernels (the
+// fill pass skips it).
 template <bool kFill, bool kVals, typename T, class Acc>
 __global__ void __launch_bounds__(256) k_ea_wave(Operand A, Operand B, const int32_t* I, const int32_t* mod,
                                                  int64_t nmod, const int64_t* qoff, const int32_t* qlist,
                                                  int64_t* cnt, const int64_t* off, int32_t* rest,
                                                  unsigned long long* nrest, int32_t* cir, T* cnum) {
-  const T* anum = static_cast<const T*>(A.num);
-  const T* bnum = static_cast<const T*>(B.num);
-  const int lane = lane_id();
+  const int lane = lane_id(), g = lane >> 4, gl = lane & 15;
   const int64_t wave = __builtin_amdgcn_readfirstlane((int)((blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kWave));
   const int64_t nwaves = (int64_t)gridDim.x * blockDim.x / kWave;
-  for (int64_t u = wave; u < nmod; u += nwaves) {
-    const int32_t j = mod[u];
-    const int64_t a0 = slot_begin(A, j), a1 = slot_begin(A, j + 1);
-    const int64_t q0 = qoff[j], q1 = qoff[j + 1];
-    int64_t nins = 0;
-    uint64_t key = ~0ull;
-    for (int64_t t = q0; t < q1 && nins <= kWave; ++t) {  // uniform
-      const int32_t q = qlist[t];
-      const int64_t b0 = slot_begin(B, q), len = slot_begin(B, q + 1) - b0;
-      if (nins + len <= kWave && lane >= nins && lane < nins + len) {
-        const int64_t e = b0 + (lane - nins);
-        key = ((uint64_t)(uint32_t)I[B.ir[e]] << 32) | (uint32_t)e;
+  for (int64_t base = wave * 4; base < nmod; base += nwaves * 4) {
+    const int64_t u = base + g;
+    const bool has = u < nmod;
+    int32_t j = 0;
+    int64_t a0 = 0, a1 = 0, q0 = 0, q1 = 0;
+    if (has) {
+      j = mod[u];
+      a0 = slot_begin(A, j);
+      a1 = slot_begin(A, j + 1);
+      q0 = qoff[j];
+      q1 = qoff[j + 1];
+    }
+    uint64_t key;
+    const int64_t nins = ea_group_keys<16>(B, I, qlist, q0, q1, &key);
+    const bool small = has && a1 - a0 <= 16 && nins <= 16;
+    ea_group_column<16, kFill, kVals, T, Acc>(A, B, small, j, a0, small ? (int)(a1 - a0) : 0,
+                                             small ? (int)nins : 0, key, cnt, off, cir, cnum);
+    uint64_t more = __ballot(has && !small && gl == 0);
+    while (more) {  // uniform: the whole wave per remaining column
+      const int64_t v = base + (__ffsll((unsigned long long)more) - 1) / 16;
+      more &= more - 1;
+      const int32_t jv = mod[v];
+      const int64_t b0 = slot_begin(A, jv), b1 = slot_begin(A, jv + 1);
+      uint64_t kv;
+      const int64_t nv = ea_group_keys<kWave>(B, I, qlist, qoff[jv], qoff[jv + 1], &kv);
+      if (b1 - b0 > kWave || nv > kWave) {  // uniform: an LDS kernel's column
+        if (!kFill && lane == 0) rest[atomicAdd(nrest, 1ull)] = (int32_t)v;
+        continue;
       }
-      nins += len;
-    }
-    if (a1 - a0 > kWave || nins > kWave) {  // uniform: an LDS kernel's column
-      if (!kFill && lane == 0) rest[atomicAdd(nrest, 1ull)] = (int32_t)u;
-      continue;
-    }
-    const int alen = (int)(a1 - a0), nk = (int)nins;
-    const int32_t arow = lane < alen ? A.ir[a0 + lane] : 0x7fffffff;
-    key = wave_sort_u64(key);
-    const int32_t krow = (int32_t)(key >> 32);  // lane < nk: the lane-th landing row
-    const int32_t prev = __shfl(krow, lane == 0 ? 0 : lane - 1);
-    const bool head = lane < nk && (lane == 0 || prev != krow);
-    int at = 0;  // A rows below krow
-    bool found = false;
-    for (int t = 0; t < alen; ++t) {
-      const int32_t r = __builtin_amdgcn_readlane(arow, t);
-      at += r < krow ? 1 : 0;
-      found = found || r == krow;
-    }
-    const uint64_t freshmask = __ballot(head && !found);
-    if (!kFill) {
-      if (lane == 0) cnt[j] = alen + __popcll(freshmask);
-      continue;
-    }
-    const int64_t cbase = off[j];
-    // A's entries that receive no landing value
-    bool landed = false;
-    int fbelow = 0;  // new rows below arow
-    for (int t = 0; t < nk; ++t) {
-      const int32_t r = __builtin_amdgcn_readlane(krow, t);
-      landed = landed || r == arow;
-      fbelow += ((freshmask >> t) & 1ull) && r < arow ? 1 : 0;
-    }
-    if (lane < alen && !landed) {
-      const int64_t o = cbase + lane + fbelow;
-      cir[o] = arow;
-      if (kVals) cnum[o] = anum[a0 + lane];
-    }
-    // one entry per distinct landing row
-    const uint64_t headmask = __ballot(head);
-    const uint64_t after = lane == 63 ? 0ull : headmask >> (lane + 1);
-    const int glen = head ? (after ? __ffsll((unsigned long long)after) : nk - lane) : 0;
-    if (head) cir[cbase + at + __popcll(freshmask & lanemask_lt())] = krow;
-    if (kVals) {
-      const T bv = lane < nk ? bnum[(uint32_t)key] : T(0);
-      T acc = found ? anum[a0 + at] : bv;
-      int gmax = glen;
-      for (int s = 1; s < kWave; s <<= 1) gmax = max(gmax, __shfl_xor(gmax, s));
-      for (int d = 0; d < gmax; ++d) {
-        const T v = __shfl(bv, (lane + d) & (kWave - 1));
-        if (d < glen && (found || d > 0)) acc = Acc::add(acc, v);
-      }
-      if (head) cnum[cbase + at + __popcll(freshmask & lanemask_lt())] = acc;
+      ea_group_column<kWave, kFill, kVals, T, Acc>(A, B, true, jv, b0, (int)(b1 - b0), (int)nv, kv, cnt, off, cir,
+                                                  cnum);
     }
   }
 }
@@ -1292,7 +1345,7 @@ int launch_ea(const ExtAddPlan* P, int32_t* cir, void* cnum, hipStream_t st, boo
     SPX_HIP(hipGetLastError());
   }
   if (P->nmod == 0) return SPX_OK;
-  k_ea_wave<kFill, kVals, T, Acc><<<(unsigned)std::min<int64_t>(ceil_div(P->nmod, (int64_t)4), (int64_t)cus * 16),
+  k_ea_wave<kFill, kVals, T, Acc><<<(unsigned)std::min<int64_t>(ceil_div(P->nmod, (int64_t)16), (int64_t)cus * 16),
                                      256, 0, st>>>(P->A, P->B, P->I, P->mod, P->nmod, P->qoff, P->qlist, P->cnt,
                                                    P->off, P->rest, P->nrest_d, cir, out);
   SPX_HIP(hipGetLastError());
