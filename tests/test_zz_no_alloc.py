@@ -2,6 +2,7 @@
 through the C ABI: its output equals spx_csc_to_dcsc's on two calls in a row,
 the second with a smaller input, and it never calls the allocator."""
 import ctypes
+import gc
 
 import numpy as np
 import pytest
@@ -32,11 +33,19 @@ def _noalloc(spx, lib, A, nzc, counter):
                     torch.full((nzc,), -7, dtype=torch.int32, device="cuda"), spx.DCSC)
     nzc_dev = torch.full((1,), -1, dtype=torch.int64, device="cuda")
     a, d = A.desc(), out.desc()
-    before = torch.cuda.memory_allocated()
-    rc = lib.spx_csc_to_dcsc_noalloc(ctypes.byref(ctx), ctypes.byref(a), ctypes.byref(d),
-                                     ctypes.c_void_p(nzc_dev.data_ptr()))
+    # the cyclic collector stays off across the call, so that no tensor freed by a
+    # collection of earlier tests' garbage moves the allocator's count meanwhile
+    gc.collect()
+    gc.disable()
+    try:
+        before = torch.cuda.memory_allocated()
+        rc = lib.spx_csc_to_dcsc_noalloc(ctypes.byref(ctx), ctypes.byref(a), ctypes.byref(d),
+                                         ctypes.c_void_p(nzc_dev.data_ptr()))
+        after = torch.cuda.memory_allocated()
+    finally:
+        gc.enable()
     assert rc == spx.SPX_OK, lib.spx_last_error().decode()
-    assert torch.cuda.memory_allocated() == before
+    assert after == before
     torch.cuda.synchronize()
     return out, int(nzc_dev.item()), d
 
