@@ -981,7 +981,10 @@ __global__ void k_count_bitmap(Operand B, ProdSrc S, const int64_t* mults, const
       const int w2 = (words + 1) >> 1;
       for (int i = threadIdx.x; i < w2; i += blockDim.x) {
         const int k = 2 * i;
-        g[i] = make_uint2(bm[k], k + 1 < words ? bm[k + 1] : 0u);
+        // streaming (non-temporal) stores: the bitmaps are read back only by the
+        // numeric phase, so they need not displace A's gathered entries from L2
+        const uint64_t pair = ((uint64_t)(k + 1 < words ? bm[k + 1] : 0u) << 32) | bm[k];
+        __builtin_nontemporal_store(pair, reinterpret_cast<uint64_t*>(g) + i);
       }
     }
     __syncthreads();
@@ -1442,7 +1445,10 @@ __global__ void __launch_bounds__(1024) k_numeric_parts(Operand A, Operand B, Pr
         else
           block_products<8, T, SR_::kUsesA, SR_::kUsesB, false, true, OFF32>(S, an, bn, b0, b1, P.r0, P.r1, full, s_rng, red, qx, acc);
         __syncthreads();
-        for (int i = threadIdx.x; i < c; i += blockDim.x) cnum[P.off + i] = vals[i];
+        // C is written once, coalesced: streaming stores keep the L2 for A's gathers
+        // (a part's scattered hash-mode writes stay ordinary: streamed partial lines
+        // cost more than they save)
+        for (int i = threadIdx.x; i < c; i += blockDim.x) __builtin_nontemporal_store(vals[i], &cnum[P.off + i]);
         __syncthreads();
       }
       // rows in rank order: staged in the value area, then written coalesced
@@ -1458,7 +1464,7 @@ __global__ void __launch_bounds__(1024) k_numeric_parts(Operand A, Operand B, Pr
         }
       }
       __syncthreads();
-      for (int i = threadIdx.x; i < c; i += blockDim.x) cir[P.off + i] = rows[i];
+      for (int i = threadIdx.x; i < c; i += blockDim.x) __builtin_nontemporal_store(rows[i], &cir[P.off + i]);
       __syncthreads();
     } else {
       int p2 = 64;
