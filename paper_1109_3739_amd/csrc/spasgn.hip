@@ -747,8 +747,8 @@ __global__ void __launch_bounds__(kTileThreads) k_asgn_fill(Operand A, const int
         }
         dst = e + s_mshift[lo[k]] - db + a;
       }
-      cir[dst] = row[k];
-      if (VB) out[dst] = val[k];
+      __builtin_nontemporal_store(row[k], &cir[dst]);  // C is written once: streaming stores
+      if (VB) __builtin_nontemporal_store(val[k], &out[dst]);
     }
     __syncthreads();
   }
@@ -1289,8 +1289,8 @@ __global__ void __launch_bounds__(kTileThreads) k_ea_tiles(Operand A, Operand B,
       const bool inmod = lo < sp.nst && s_beg[lo] <= x;
       if (!inmod) {
         const int64_t dst = e + s_shift[lo];
-        cir[dst] = A.ir[e];
-        if (kVals) cnum[dst] = anum[e];
+        __builtin_nontemporal_store(A.ir[e], &cir[dst]);  // C is written once: streaming stores
+        if (kVals) __builtin_nontemporal_store(anum[e], &cnum[dst]);
         continue;
       }
       const int32_t w = s_lw[lo];
