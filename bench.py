@@ -9,7 +9,11 @@ multiplication counts, binning, exact column counts, int64 scans, part
 cutting; one host read-back of the output size) and numeric phase (wave /
 LDS accumulation, ordered write-out of IR and NUM, column pointers).  The
 input is resident in HBM before timing starts; the 43 GB output buffer is
-allocated once and rewritten by every step.
+allocated once and rewritten by every step.  Python's cyclic garbage
+collector is frozen over the objects that exist once set-up is done: a full
+collection over torch's heap takes ~40 ms and would otherwise land inside
+whichever step is running (the host side of a plan); collections of objects
+made later still run.
 
 Prints one JSON line: GFLOP/s counted as 2 x multiplications per second,
 achieved compulsory GB/s, the roofline of the dominant kernel (HIP events
@@ -26,6 +30,7 @@ product, SpRef / SpAsgn / extend-add, and the restriction S A S^T.
 from __future__ import annotations
 
 import argparse
+import gc
 import json
 import os
 import statistics
@@ -530,6 +535,8 @@ def main():
     spx.load()
     torch.cuda.set_device(0)
     sync = torch.cuda.synchronize
+    gc.collect()
+    gc.freeze()
     if args.calibrate_copy:
         x = torch.empty(args.calibrate_copy // 4, dtype=torch.float32, device="cuda").fill_(1.0)
         y = torch.empty_like(x)
@@ -551,6 +558,8 @@ def main():
     A = W.rmat(20, 8, seed=20)
     dA = spx.from_host(A)
     sync()
+    gc.collect()
+    gc.freeze()
 
     # warm-up (also sizes the output once)
     p = spx.GemmPlan(dA, dA)
