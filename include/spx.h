@@ -270,7 +270,11 @@ int spx_contract_exec(spx_plan* plan, spx_mat* C);
  * spx_batch_exec: refreshes the operand values from A_i.num / B_i.num
  *   (patterns must be unchanged), runs the numeric phase and fills C[i]:
  *   C[i].cp points into cp_pool (int64, cp_total entries), C[i].ir / num into
- *   ir_pool / num_pool (nnz_total entries); the caller owns the pools.
+ *   ir_pool / num_pool (nnz_total entries); the caller owns the pools, which
+ *   must not overlap any operand.  When the distinct A_i.num (or all B_i.num)
+ *   lie back to back in batch order in one allocation -- as the C_i of an
+ *   earlier batch do -- they are read in place rather than copied, so they
+ *   must stay allocated for as long as the plan is executed.
  * spx_batch_capture / spx_batch_replay: record spx_batch_exec with the given
  *   pools into a HIP graph once, then launch it on the plan's stream (values
  *   may change between replays).                                           */

@@ -6,7 +6,8 @@
 // operands passed more than once (the same arrays) enter the concatenation
 // once, and every B_i that uses them points at that block.  The
 // concatenated operands are built once by the plan (patterns) and refreshed
-// by every exec (values); the symbolic phase, the binning and the persistent
+// by every exec (values, unless the callers' value arrays already lie back to
+// back in batch order: then they are read in place); the symbolic phase, the binning and the persistent
 // numeric launches of the ordinary SpGEMM then run over the work items of
 // all products together.  C_i are views into caller-owned pools.
 #include <algorithm>
@@ -54,6 +55,7 @@ struct BatchPlan : spx_plan {
   int64_t* ccp = nullptr;  // column pointers of [C_1 ... C_n]
   spx_plan* gemm = nullptr;
   int64_t nnz_total = 0, cp_total = 0, mmax = 0;
+  bool anum_in_place = false, bnum_in_place = false;  // anum / bnum alias the callers' arrays
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
 };
@@ -135,13 +137,31 @@ __global__ void k_gather_i64(const int64_t* src, const int64_t* idx, int n, int6
   if (i < n) out[i] = src[idx[i]];
 }
 
+// Start of the concatenation when every nonempty value array of the batch
+// already lies at its concatenated offset from one address (nz holds the
+// entry offsets, count + 1 of them), else null.  The outputs of an earlier
+// batch are views into one pool in batch order, so a batch that takes them
+// as its right operands reads their values in place instead of copying them.
+static void* in_place_base(const std::vector<const void*>& ptrs, const std::vector<int64_t>& nz, int vb) {
+  uintptr_t base = 0;
+  bool any = false;
+  for (size_t i = 0; i < ptrs.size(); ++i) {
+    if (nz[i + 1] == nz[i]) continue;  // an empty operand is never read
+    const uintptr_t b = reinterpret_cast<uintptr_t>(ptrs[i]) - (uintptr_t)(nz[i] * vb);
+    if (!ptrs[i] || (any && b != base)) return nullptr;
+    base = b;
+    any = true;
+  }
+  return any ? reinterpret_cast<void*>(base) : nullptr;
+}
+
 static int run_exec(BatchPlan* P, int64_t* cp_pool, int32_t* ir_pool, void* num_pool, hipStream_t st) {
   const int64_t anz = P->anz_h[P->count_a], bnz = P->bnz_h[P->count];
-  if (P->vb_a && anz > 0) {
+  if (P->vb_a && anz > 0 && !P->anum_in_place) {
     launch_cat(P, kCatANum, P->anz, P->acol, P->vb_a, P->anum, max_len(P->anz_h), st);
     SPX_HIP(hipGetLastError());
   }
-  if (P->vb_b && bnz > 0) {
+  if (P->vb_b && bnz > 0 && !P->bnum_in_place) {
     launch_cat(P, kCatBNum, P->bnz, P->bcol, P->vb_b, P->bnum, max_len(P->bnz_h), st);
     SPX_HIP(hipGetLastError());
   }
@@ -256,8 +276,22 @@ extern "C" int spx_batch_plan(const spx_ctx* ctx, int32_t count, const spx_mat* 
   SPX_TRY(scr.get_n(nb + 1, &P->bcp));
   SPX_TRY(scr.get_n(std::max<int64_t>(bnz, 1), &P->bir));
   SPX_TRY(scr.get_n(nb + 1, &P->ccp));
-  if (P->vb_a) SPX_TRY(scr.get(std::max<int64_t>(anz, 1) * P->vb_a, &P->anum));
-  if (P->vb_b) SPX_TRY(scr.get(std::max<int64_t>(bnz, 1) * P->vb_b, &P->bnum));
+  // values: read in place when the callers' arrays already form the
+  // concatenation, else copied by every exec into the plan's own arrays
+  if (P->vb_a && anz > 0) {
+    std::vector<const void*> ap(na);
+    for (int u = 0; u < na; ++u) ap[u] = hd[u].anum;
+    P->anum = in_place_base(ap, P->anz_h, P->vb_a);
+    P->anum_in_place = P->anum != nullptr;
+  }
+  if (P->vb_b && bnz > 0) {
+    std::vector<const void*> bp(count);
+    for (int i = 0; i < count; ++i) bp[i] = hd[i].bnum;
+    P->bnum = in_place_base(bp, P->bnz_h, P->vb_b);
+    P->bnum_in_place = P->bnum != nullptr;
+  }
+  if (P->vb_a && !P->anum_in_place) SPX_TRY(scr.get(std::max<int64_t>(anz, 1) * P->vb_a, &P->anum));
+  if (P->vb_b && !P->bnum_in_place) SPX_TRY(scr.get(std::max<int64_t>(bnz, 1) * P->vb_b, &P->bnum));
   // patterns of the concatenated operands (values are copied by every exec)
   launch_cat(P, kCatACp, P->anz, P->acol, 0, P->acp, max_len(P->acol_h), st);
   launch_cat(P, kCatBCp, P->bnz, P->bcol, 0, P->bcp, max_len(P->bcol_h), st);

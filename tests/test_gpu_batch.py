@@ -189,6 +189,68 @@ def test_batch_graph_replay(spx):
         plan.close()
 
 
+def test_batch_values_in_place(spx):
+    """Operand values that already lie back to back in batch order in one
+    allocation (as the outputs of an earlier batch do) are read in place.
+    Results match the copied path bit for bit and the oracle; an exec and a
+    graph replay after the shared values change see the new values; an empty
+    operand in the middle and a repeated right operand (not back to back, so
+    copied) are handled."""
+    import dataclasses
+    import torch
+    shapes = [(300, 200, 3), (128, 64, 5), (700, 1, 2), (256, 256, 4), (90, 300, 6)]
+    As = [W.erdos_renyi(m, k, d, seed=300 + i) for i, (m, k, d) in enumerate(shapes)]
+    # B_2 has no entries: its values are never read
+    Bs = [W.erdos_renyi(k, n, d, seed=400 + i) for i, (k, n, d) in enumerate([(200, 150, 3), (64, 90, 3), (1, 40, 0),
+                                                                              (256, 256, 3), (300, 70, 3)])]
+    assert Bs[2].nnz == 0
+    dA = [spx.from_host(a) for a in As]
+    dB = [spx.from_host(b) for b in Bs]
+
+    def packed(ms):
+        vals = torch.cat([m.num for m in ms])
+        out, off = [], 0
+        for m in ms:
+            out.append(dataclasses.replace(m, num=vals[off:off + m.nnz]))
+            off += m.nnz
+        return vals, out
+
+    avals, pA = packed(dA)
+    bvals, pB = packed(dB)
+    copied = [host(c) for c in spx.batch_spgemm(dA, dB)]
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        plan = spx.BatchPlan(pA, pB, stream=stream)
+        got = [host(c) for c in plan.execute()]
+        stream.synchronize()
+        for i, (g, c) in enumerate(zip(got, copied)):
+            assert np.array_equal(g.cp, c.cp) and np.array_equal(g.ir, c.ir) and np.array_equal(g.num, c.num), i
+            assert_same_csc(g, oracle.spgemm_csc(As[i], Bs[i]), what=f"in place, product {i}")
+        # new values in the shared arrays: a second exec reads them
+        avals.mul_(2.0)
+        bvals.mul_(0.5)
+        stream.synchronize()
+        again = [host(c) for c in plan.execute()]
+        stream.synchronize()
+        for i, (g, c) in enumerate(zip(again, copied)):
+            assert np.array_equal(g.ir, c.ir) and np.array_equal(g.num, c.num), f"rescaled, product {i}"
+        # captured once, replayed after the values change again
+        views = plan.capture()
+        bvals.mul_(4.0)
+        torch.cuda.synchronize()
+        plan.replay()
+        stream.synchronize()
+        for i, (v, c) in enumerate(zip(views, copied)):
+            assert np.array_equal(host(v).num, c.num * 4), f"replay, product {i}"
+        plan.close()
+    # a repeated right operand breaks the back-to-back layout: values are copied
+    rep = [pB[0], pB[1], pB[0]]
+    Cs = spx.batch_spgemm([pA[0], pA[1], pA[0]], rep)
+    for i, (a, b) in enumerate([(0, 0), (1, 1), (0, 0)]):
+        ref = oracle.spgemm_csc(As[a].with_values(2.0 * As[a].num), Bs[b].with_values(2.0 * Bs[b].num))
+        assert_same_csc(host(Cs[i]), ref, what=f"repeated operand, product {i}")
+
+
 def test_batch_errors(spx):
     A = spx.from_host(W.erdos_renyi(10, 8, 2, seed=1))
     with pytest.raises(spx.SpxError):
