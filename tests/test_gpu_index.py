@@ -153,7 +153,7 @@ def test_formats(spx):
 
 
 @pytest.fixture(scope="module")
-def config3():
+def rmat22_index():
     A = W.rmat(22, 16, seed=22, values="edge_id")
     I = W.index_vector(1 << 18, A.m, seed=221)
     J = W.index_vector(1 << 18, A.n, seed=222)
@@ -161,13 +161,13 @@ def config3():
     return A, I, J, Bp
 
 
-def test_config3_spref_full(spx, config3):
-    A, I, J, _ = config3
+def test_rmat22_spref_full(spx, rmat22_index):
+    A, I, J, _ = rmat22_index
     spref_check(spx, A, I, J)
 
 
-def test_config3_spasgn_full(spx, config3):
-    A, I, J, Bp = config3
+def test_rmat22_spasgn_full(spx, rmat22_index):
+    A, I, J, Bp = rmat22_index
     spasgn_check(spx, A, I, J, Bp)
 
 
@@ -317,13 +317,13 @@ def test_spasgn_extend_add_dcsc_operands(spx, a_dcsc, b_dcsc):
 
 
 @pytest.mark.timeout(900)
-def test_section52_assignment_rmat21_into_rmat22(spx, config3):
+def test_section52_assignment_rmat21_into_rmat22(spx, rmat22_index):
     """Section 5.2's assignment at one-GPU scale: A(I, J) = B with A the
     scale-22 R-MAT of the SpRef/SpAsgn workload, B an R-MAT of scale 21
     (edge factor 16, int64 ids 2^40 + position, hub columns far above 4096
     entries), I and J of length 2^21 with 10% repeated indices; bit-exact
     against the oracle, and extend-add of the same block."""
-    A, _, _, _ = config3
+    A, _, _, _ = rmat22_index
     L = 1 << 21
     I = W.index_vector(L, A.m, seed=521)
     J = W.index_vector(L, A.n, seed=522)
@@ -346,8 +346,8 @@ def test_extend_add_errors(spx):
     assert e.value.code == spx.SPX_EUNSUPPORTED
 
 
-def test_config3_extend_add_full(spx, config3):
-    A, I, J, Bp = config3
+def test_rmat22_extend_add_full(spx, rmat22_index):
+    A, I, J, Bp = rmat22_index
     extend_add_check(spx, A, I, J, Bp)
 
 
