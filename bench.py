@@ -466,7 +466,7 @@ def galerkin(spx, W, torch, count=512, seed=4):
 
 
 def serving(spx, torch, pool_size=256, n_req=5000, discard=500,
-            fracs=(0.5, 0.6, 0.7, 0.8, 0.9, 1.0, 1.1, 1.2, 1.25, 1.3, 1.35, 1.4, 1.5, 2.0, 3.0)):
+            fracs=(0.5, 0.6, 0.7, 0.8, 0.9, 1.0, 1.1, 1.15, 1.2, 1.22, 1.25, 1.28, 1.3, 1.35, 1.4, 1.5, 2.0, 3.0)):
     """Served request stream: plain per-request launches vs continuous
     batching, at offered loads relative to plain's saturation rate.  A pool
     of `pool_size` resident matrices (scales 10-18, about 28 per scale);
