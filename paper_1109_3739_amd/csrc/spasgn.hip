@@ -245,23 +245,50 @@ struct LoadModified {
   __device__ int64_t operator()(int64_t j) const { return lastJ[j] >= 0; }
 };
 
-// The modified columns in ascending order, at their scan positions.
-__global__ void k_list_modified(const int32_t* lastJ, int64_t n, const int64_t* pos, int32_t* mod) {
-  for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x)
-    if (lastJ[j] >= 0) mod[pos[j]] = (int32_t)j;
+// The modified columns in ascending order, compacted in place of a scan:
+// block b of kScanTile columns starts at carry[b] (the scanned block counts
+// of the modified flags; null for a single block), ranks its own flags with
+// a block scan and writes its columns.  The last thread of the last block
+// leaves the total in *nmod.  Items are taken kScanItems consecutive per
+// thread, as by k_scan_apply.
+__global__ void __launch_bounds__(kScanThreads) k_list_modified(const int32_t* lastJ, int64_t n, const int64_t* carry,
+                                                                int32_t* mod, unsigned long long* nmod) {
+  __shared__ int64_t red[kScanThreads / kWave + 1];
+  const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+  bool f[kScanItems];
+  int64_t s = 0;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    f[k] = base + k < n && lastJ[base + k] >= 0;
+    s += f[k];
+  }
+  int64_t total;
+  int64_t run = block_excl_scan(s, red, &total) + (carry ? carry[blockIdx.x] : 0);
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k)
+    if (f[k]) mod[run++] = (int32_t)(base + k);
+  if (blockIdx.x == gridDim.x - 1 && threadIdx.x == blockDim.x - 1) *nmod = (unsigned long long)run;
 }
 
 // Lists the modified columns and leaves their number in *nmod.
 int list_modified(const Operand& A, const int32_t* lastJ, int64_t* cnt, int32_t* mod, unsigned long long* nmod,
-                  int64_t* pos, unsigned long long* modent, Scratch& scr, hipStream_t st) {
+                  unsigned long long* modent, Scratch& scr, hipStream_t st) {
   const int64_t n = A.n;
   if (n == 0) return fill_i64(reinterpret_cast<int64_t*>(nmod), 1, 0, st);
   k_asgn_cols<<<grid_for(n, 256, (int64_t)device_cu_count() * 4), 256, 0, st>>>(A, lastJ, cnt, modent);
   SPX_HIP(hipGetLastError());
-  SPX_TRY(exclusive_scan(LoadModified{lastJ}, n, pos, scr, st));
-  k_list_modified<<<grid_for(n, 256, 65536), 256, 0, st>>>(lastJ, n, pos, mod);
+  const int64_t nblocks = ceil_div(n, kScanTile);
+  int64_t* carry = nullptr;
+  if (nblocks > 1) {
+    int64_t* sums = nullptr;
+    SPX_TRY(scr.get_n(nblocks, &sums));
+    SPX_TRY(scr.get_n(nblocks + 1, &carry));
+    k_scan_reduce<LoadModified><<<(unsigned)nblocks, kScanThreads, 0, st>>>(LoadModified{lastJ}, n, sums);
+    SPX_HIP(hipGetLastError());
+    SPX_TRY(exclusive_scan(LoadI64{sums}, nblocks, carry, scr, st));
+  }
+  k_list_modified<<<(unsigned)nblocks, kScanThreads, 0, st>>>(lastJ, n, carry, mod, nmod);
   SPX_HIP(hipGetLastError());
-  SPX_HIP(hipMemcpyAsync(nmod, pos + n, 8, hipMemcpyDeviceToDevice, st));
   return SPX_OK;
 }
 
@@ -1418,10 +1445,9 @@ extern "C" int spx_spasgn_plan(const spx_ctx* ctx, const spx_mat* A, const int32
   P->lenJ = lenJ;
   const int64_t m = A->m, n = A->n;
   const int cus = device_cu_count();
-  int64_t* pos = nullptr;
   SPX_TRY(scr.get_many({Scratch::part(&P->err, 4), Scratch::part(&P->nmod_d, 2), Scratch::part(&P->lastI, m),
                         Scratch::part(&P->lastJ, n), Scratch::part(&P->cnt, n), Scratch::part(&P->off, n + 1),
-                        Scratch::part(&P->mod, n), Scratch::part(&pos, n + 1)}));
+                        Scratch::part(&P->mod, n)}));
   SPX_TRY(fill_u32(P->err, 1, 0, st));
   SPX_TRY(fill_i64((int64_t*)P->nmod_d, 2, 0, st));  // modified columns, their entries
   SPX_TRY(fill_u32((uint32_t*)P->lastI, m, 0xffffffffu, st));
@@ -1434,7 +1460,7 @@ extern "C" int spx_spasgn_plan(const spx_ctx* ctx, const spx_mat* A, const int32
     k_last_occ<<<grid_for(lenJ, 256, 4096), 256, 0, st>>>(J, lenJ, n, P->lastJ, P->err, 2u);
     SPX_HIP(hipGetLastError());
   }
-  SPX_TRY(list_modified(P->A, P->lastJ, P->cnt, P->mod, P->nmod_d, pos, P->nmod_d + 1, scr, st));
+  SPX_TRY(list_modified(P->A, P->lastJ, P->cnt, P->mod, P->nmod_d, P->nmod_d + 1, scr, st));
   int64_t h1[3] = {0, 0, 0};
   SPX_TRY(read_device_words(st, {{P->nmod_d, 8}, {P->err, 4}, {P->nmod_d + 1, 8}}, h1));
   if (h1[1] & 1) return fail(SPX_EINVAL, "I has an index outside [0, m)");
@@ -1559,11 +1585,10 @@ extern "C" int spx_extend_add_plan(const spx_ctx* ctx, const spx_mat* A, const i
   P->lenJ = lenJ;
   P->sr = semiring;
   const int64_t m = A->m, n = A->n;
-  int64_t* pos = nullptr;
   SPX_TRY(scr.get_many({Scratch::part(&P->err, 4), Scratch::part(&P->nmod_d, 1), Scratch::part(&P->lastJ, n),
                         Scratch::part(&P->qcnt, n), Scratch::part(&P->cnt, n), Scratch::part(&P->off, n + 1),
                         Scratch::part(&P->mod, n), Scratch::part(&P->qoff, n + 1),
-                        Scratch::part(&P->qlist, lenJ), Scratch::part(&pos, n + 1)}));
+                        Scratch::part(&P->qlist, lenJ)}));
   SPX_TRY(fill_u32(P->err, 1, 0, st));
   SPX_TRY(fill_i64((int64_t*)P->nmod_d, 1, 0, st));
   SPX_TRY(fill_u32((uint32_t*)P->lastJ, n, 0xffffffffu, st));
@@ -1578,7 +1603,7 @@ extern "C" int spx_extend_add_plan(const spx_ctx* ctx, const spx_mat* A, const i
     k_count_q<<<grid_for(lenJ, 256, 4096), 256, 0, st>>>(J, lenJ, n, P->qcnt);
     SPX_HIP(hipGetLastError());
   }
-  SPX_TRY(list_modified(P->A, P->lastJ, P->cnt, P->mod, P->nmod_d, pos, nullptr, scr, st));
+  SPX_TRY(list_modified(P->A, P->lastJ, P->cnt, P->mod, P->nmod_d, nullptr, scr, st));
   int64_t h1[2] = {0, 0};
   SPX_TRY(read_device_words(st, {{P->nmod_d, 8}, {P->err, 4}}, h1));
   if (h1[1] & 1) return fail(SPX_EINVAL, "I has an index outside [0, m)");
