@@ -42,6 +42,7 @@ struct SprefPlan : spx_plan {
   int64_t* clsoff = nullptr; // [kNumCls+1]
   int64_t clsoff_h[kNumCls + 1] = {};
   int64_t nwide = 0;         // columns gathering more than kRefWide entries of A
+  int32_t* wide = nullptr;   // [lenJ] those columns (the first nwide entries)
   unsigned* err = nullptr;
 };
 
@@ -366,22 +367,30 @@ __global__ void __launch_bounds__(256) k_ref_small(Operand A, const int64_t* qa0
   }
 }
 
-// Columns with at most 4096 entries: one workgroup, LDS bitonic sort.
+// Columns with at most 4096 entries: one workgroup, LDS bitonic sort.  The
+// 256-thread variant walks the medium class list and leaves out its wide
+// columns; the 1024-thread variant walks the list of wide columns (nwide
+// entries) and takes those of the medium class, so its workgroups share the
+// wide columns evenly.
 template <int BLOCK>
 __global__ void __launch_bounds__(BLOCK) k_ref_medium(Operand A, const int64_t* qa0, const int32_t* qlen,
                                                       const int64_t* rptr, const int32_t* rpos, const int32_t* list,
-                                                      const int64_t* clsoff, const int64_t* cnt, const int64_t* off,
-                                                      int vb, int32_t* bir, void* bnum) {
+                                                      const int32_t* wide, int64_t nwide, const int64_t* clsoff,
+                                                      const int64_t* cnt, const int64_t* off, int vb, int32_t* bir,
+                                                      void* bnum) {
+  constexpr bool kWide = BLOCK > 256;
   __shared__ uint64_t s_key[kRefMedium];
   __shared__ int64_t s_e[kRefMedium];
   __shared__ int64_t red[BLOCK / kWave + 1];
-  const int64_t beg = clsoff[kClsMedium], end = clsoff[kClsMedium + 1];
+  const int64_t beg = kWide ? 0 : clsoff[kClsMedium], end = kWide ? nwide : clsoff[kClsMedium + 1];
   for (int64_t pos = beg + blockIdx.x; pos < end; pos += gridDim.x) {
-    const int32_t q = list[pos];
+    const int32_t q = kWide ? wide[pos] : list[pos];
     const int64_t a0 = qa0[q];
     const int32_t al = qlen[q];
-    if ((al > kRefWide) != (BLOCK > 256)) continue;  // uniform: the other variant's column
-    const int c = (int)cnt[q];
+    const int64_t c64 = cnt[q];
+    // uniform: a column of the other variant (or, in the wide list, of another class)
+    if (kWide ? (c64 == 0 || c64 > kRefMedium) : al > kRefWide) continue;
+    const int c = (int)c64;
     int64_t total = 0;
     // four consecutive gathered entries per thread and round, their loads in flight together
     for (int32_t ec = 0; ec < al; ec += 4 * (int32_t)blockDim.x) {
@@ -515,9 +524,8 @@ extern "C" int spx_spref_plan(const spx_ctx* ctx, const spx_mat* A, const int32_
   unsigned* rcnt = nullptr;
   unsigned long long *clscount = nullptr, *fill = nullptr, *nlong = nullptr;
   int32_t* longs = nullptr;  // rows with more than kRowShort positions (at most lenI / 17)
-  int32_t* wide = nullptr;   // columns gathering more than kRefWide entries of A
   SPX_TRY(scr.get_many({Scratch::part(&nlong, 2), Scratch::part(&longs, lenI / (kRowShort + 1) + 1),
-                        Scratch::part(&wide, lenJ),
+                        Scratch::part(&P->wide, lenJ),
                         Scratch::part(&P->err, 4), Scratch::part(&rcnt, m + 1), Scratch::part(&P->rptr, m + 1),
                         Scratch::part(&P->rpos, lenI), Scratch::part(&P->qa0, lenJ), Scratch::part(&P->qlen, lenJ),
                         Scratch::part(&P->cnt, lenJ), Scratch::part(&P->off, lenJ + 1), Scratch::part(&P->list, lenJ),
@@ -557,9 +565,9 @@ extern "C" int spx_spref_plan(const spx_ctx* ctx, const spx_mat* A, const int32_
     k_col_info<<<grid_for(lenJ, 256, 4096), 256, 0, st>>>(P->A, aux, chunk, J, lenJ, P->qa0, P->qlen);
     SPX_HIP(hipGetLastError());
     k_ref_count<<<grid_for(lenJ * kWave, 256, (int64_t)cus * 8), 256, 0, st>>>(P->A, P->qa0, P->qlen, P->rptr, lenJ,
-                                                                                P->cnt, clscount, wide, nwide);
+                                                                                P->cnt, clscount, P->wide, nwide);
     SPX_HIP(hipGetLastError());
-    k_ref_count_wide<<<(unsigned)(cus * 2), 1024, 0, st>>>(P->A, P->qa0, P->qlen, P->rptr, wide, nwide, P->cnt,
+    k_ref_count_wide<<<(unsigned)(cus * 2), 1024, 0, st>>>(P->A, P->qa0, P->qlen, P->rptr, P->wide, nwide, P->cnt,
                                                            clscount);
     SPX_HIP(hipGetLastError());
   }
@@ -606,11 +614,13 @@ extern "C" int spx_spref_exec(spx_plan* plan, spx_mat* B) {
   }
   if (co[kClsMedium + 1] > co[kClsMedium]) {
     k_ref_medium<256><<<grid_for(co[kClsMedium + 1] - co[kClsMedium], 1, (int64_t)cus * 2), 256, 0, st>>>(
-        P->A, P->qa0, P->qlen, P->rptr, P->rpos, P->list, P->clsoff, P->cnt, P->off, vb, B->ir, B->num);
+        P->A, P->qa0, P->qlen, P->rptr, P->rpos, P->list, P->wide, P->nwide, P->clsoff, P->cnt, P->off, vb, B->ir,
+        B->num);
     SPX_HIP(hipGetLastError());
     if (P->nwide > 0) {  // medium columns that gather more than kRefWide entries
       k_ref_medium<1024><<<(unsigned)std::min<int64_t>(P->nwide, (int64_t)cus * 2), 1024, 0, st>>>(
-          P->A, P->qa0, P->qlen, P->rptr, P->rpos, P->list, P->clsoff, P->cnt, P->off, vb, B->ir, B->num);
+          P->A, P->qa0, P->qlen, P->rptr, P->rpos, P->list, P->wide, P->nwide, P->clsoff, P->cnt, P->off, vb, B->ir,
+          B->num);
       SPX_HIP(hipGetLastError());
     }
   }
