@@ -127,6 +127,19 @@ inline int read_device_words(hipStream_t stream, std::initializer_list<DevWord> 
   return read_device_words(stream, words.begin(), (int)words.size(), out);
 }
 
+// A second stream of the calling host thread on the current device (default
+// priority), for a launch that may run beside the work of the caller's
+// stream: side_fork makes it wait for what `st` holds so far, side_join
+// makes `st` wait for what was enqueued on it since.  Created on first use
+// and destroyed when the thread ends.
+struct SideStream {
+  hipStream_t s = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
+  ~SideStream();
+};
+int side_fork(hipStream_t st, SideStream** out);
+int side_join(SideStream* ss, hipStream_t st);
+
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 inline int64_t next_pow2(int64_t x) {
   int64_t p = 1;

@@ -198,6 +198,36 @@ int read_device_words(hipStream_t stream, const DevWord* words, int nwords, int6
   return SPX_OK;
 }
 
+SideStream::~SideStream() {
+  if (join) (void)hipEventDestroy(join);
+  if (fork) (void)hipEventDestroy(fork);
+  if (s) (void)hipStreamDestroy(s);
+}
+
+int side_fork(hipStream_t st, SideStream** out) {
+  constexpr int kMaxDev = 64;
+  static thread_local SideStream per_dev[kMaxDev];
+  int dev = 0;
+  SPX_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDev) return fail(SPX_EDEVICE, "device id out of the supported range");
+  SideStream& ss = per_dev[dev];
+  if (!ss.s) {
+    if (!ss.fork) SPX_HIP(hipEventCreateWithFlags(&ss.fork, hipEventDisableTiming));
+    if (!ss.join) SPX_HIP(hipEventCreateWithFlags(&ss.join, hipEventDisableTiming));
+    SPX_HIP(hipStreamCreateWithFlags(&ss.s, hipStreamNonBlocking));
+  }
+  SPX_HIP(hipEventRecord(ss.fork, st));
+  SPX_HIP(hipStreamWaitEvent(ss.s, ss.fork, 0));
+  *out = &ss;
+  return SPX_OK;
+}
+
+int side_join(SideStream* ss, hipStream_t st) {
+  SPX_HIP(hipEventRecord(ss->join, ss->s));
+  SPX_HIP(hipStreamWaitEvent(st, ss->join, 0));
+  return SPX_OK;
+}
+
 template <typename T>
 __global__ void k_fill(T* p, int64_t n, T v) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)

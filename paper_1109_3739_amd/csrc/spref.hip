@@ -145,23 +145,27 @@ __global__ void __launch_bounds__(256) k_sort_long_rows(const int32_t* I, int64_
   }
 }
 
+// Columns gathering more entries of A than this are counted (and, with at
+// most kRefMedium outputs, extracted) by 1024-thread workgroups, so that a
+// hub column of A is not left to one wave or one small workgroup.
+constexpr int32_t kRefWide = 4096;
+
+// Where each gathered column A(:,J(q)) starts and how long it is; columns
+// longer than kRefWide are also appended to the wide list.
 __global__ void k_col_info(Operand A, const int64_t* aux, int64_t chunk, const int32_t* J, int64_t lenJ, int64_t* qa0,
-                           int32_t* qlen) {
+                           int32_t* qlen, int32_t* wide, unsigned long long* nwide) {
   for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < lenJ; q += (int64_t)gridDim.x * blockDim.x) {
     int64_t a0 = 0, a1 = 0;
     const int32_t k = J[q];
     if (k >= 0 && k < A.n) column_range(A, aux, chunk, k, a0, a1);
     qa0[q] = a0;
     qlen[q] = (int32_t)(a1 - a0);
+    if (a1 - a0 > kRefWide) wide[atomicAdd(nwide, 1ull)] = (int32_t)q;
   }
 }
 
 // nnz(B(:,q)) = sum over the entries (i, v) of A(:,J(q)) of |{p : I(p) = i}|;
 // one wave per column.  Also classifies the column.
-// Columns gathering more entries of A than this are counted (and, with at
-// most kRefMedium outputs, extracted) by 1024-thread workgroups, so that a
-// hub column of A is not left to one wave or one small workgroup.
-constexpr int32_t kRefWide = 4096;
 
 // Output class of a column with s outputs gathering al entries of A (a wide
 // column with few outputs still goes to the workgroup path).
@@ -170,7 +174,7 @@ __device__ __forceinline__ int ref_class(int64_t s, int32_t al) {
 }
 
 __global__ void k_ref_count(const Operand A, const int64_t* qa0, const int32_t* qlen, const int64_t* rptr, int64_t lenJ,
-                            int64_t* cnt, unsigned long long* clscount, int32_t* wide, unsigned long long* nwide) {
+                            int64_t* cnt, unsigned long long* clscount) {
   const int lane = lane_id();
   const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kWave;
   const int64_t nw = (int64_t)gridDim.x * blockDim.x / kWave;
@@ -178,10 +182,7 @@ __global__ void k_ref_count(const Operand A, const int64_t* qa0, const int32_t* 
   for (int64_t q = wave; q < lenJ; q += nw) {
     const int64_t a0 = qa0[q];
     const int32_t al = qlen[q];
-    if (al > kRefWide) {  // uniform: k_ref_count_wide's column
-      if (lane == 0) wide[atomicAdd(nwide, 1ull)] = (int32_t)q;
-      continue;
-    }
+    if (al > kRefWide) continue;  // uniform: k_ref_count_wide's column
     int64_t s = 0;
     for (int32_t e0 = 0; e0 < al; e0 += 4 * kWave) {  // four rows in flight per lane
       int32_t i[4];
@@ -562,14 +563,19 @@ extern "C" int spx_spref_plan(const spx_ctx* ctx, const spx_mat* A, const int32_
   SPX_TRY(build_aux(P->A, scr, st, &aux, &chunk));
   SPX_TRY(fill_i64((int64_t*)clscount, kNumCls, 0, st));
   if (lenJ > 0) {
-    k_col_info<<<grid_for(lenJ, 256, 4096), 256, 0, st>>>(P->A, aux, chunk, J, lenJ, P->qa0, P->qlen);
+    k_col_info<<<grid_for(lenJ, 256, 4096), 256, 0, st>>>(P->A, aux, chunk, J, lenJ, P->qa0, P->qlen, P->wide,
+                                                          nwide);
+    SPX_HIP(hipGetLastError());
+    // the few workgroups of the wide columns' count run beside the wave count
+    SideStream* ss = nullptr;
+    SPX_TRY(side_fork(st, &ss));
+    k_ref_count_wide<<<(unsigned)(cus * 2), 1024, 0, ss->s>>>(P->A, P->qa0, P->qlen, P->rptr, P->wide, nwide, P->cnt,
+                                                              clscount);
     SPX_HIP(hipGetLastError());
     k_ref_count<<<grid_for(lenJ * kWave, 256, (int64_t)cus * 8), 256, 0, st>>>(P->A, P->qa0, P->qlen, P->rptr, lenJ,
-                                                                                P->cnt, clscount, P->wide, nwide);
+                                                                                P->cnt, clscount);
     SPX_HIP(hipGetLastError());
-    k_ref_count_wide<<<(unsigned)(cus * 2), 1024, 0, st>>>(P->A, P->qa0, P->qlen, P->rptr, P->wide, nwide, P->cnt,
-                                                           clscount);
-    SPX_HIP(hipGetLastError());
+    SPX_TRY(side_join(ss, st));
   }
   k_cls_offsets<<<1, 64, 0, st>>>(clscount, P->clsoff, fill);
   SPX_HIP(hipGetLastError());
@@ -607,6 +613,15 @@ extern "C" int spx_spref_exec(spx_plan* plan, spx_mat* B) {
   const int vb = value_size(P->A.val_t);
   const int cus = device_cu_count();
   const int64_t* co = P->clsoff_h;
+  // the wide medium columns' few workgroups run beside the other classes
+  SideStream* ss = nullptr;
+  if (co[kClsMedium + 1] > co[kClsMedium] && P->nwide > 0) {
+    SPX_TRY(side_fork(st, &ss));
+    k_ref_medium<1024><<<(unsigned)std::min<int64_t>(P->nwide, (int64_t)cus * 2), 1024, 0, ss->s>>>(
+        P->A, P->qa0, P->qlen, P->rptr, P->rpos, P->list, P->wide, P->nwide, P->clsoff, P->cnt, P->off, vb, B->ir,
+        B->num);
+    SPX_HIP(hipGetLastError());
+  }
   if (co[kClsSmall + 1] > co[kClsSmall]) {
     k_ref_small<<<grid_for(co[kClsSmall + 1] - co[kClsSmall], 4, (int64_t)cus * 16), 256, 0, st>>>(
         P->A, P->qa0, P->qlen, P->rptr, P->rpos, P->list, P->clsoff, P->off, vb, B->ir, B->num);
@@ -617,18 +632,13 @@ extern "C" int spx_spref_exec(spx_plan* plan, spx_mat* B) {
         P->A, P->qa0, P->qlen, P->rptr, P->rpos, P->list, P->wide, P->nwide, P->clsoff, P->cnt, P->off, vb, B->ir,
         B->num);
     SPX_HIP(hipGetLastError());
-    if (P->nwide > 0) {  // medium columns that gather more than kRefWide entries
-      k_ref_medium<1024><<<(unsigned)std::min<int64_t>(P->nwide, (int64_t)cus * 2), 1024, 0, st>>>(
-          P->A, P->qa0, P->qlen, P->rptr, P->rpos, P->list, P->wide, P->nwide, P->clsoff, P->cnt, P->off, vb, B->ir,
-          B->num);
-      SPX_HIP(hipGetLastError());
-    }
   }
   if (co[kClsLarge + 1] > co[kClsLarge]) {
     k_ref_large<<<grid_for(co[kClsLarge + 1] - co[kClsLarge], 1, (int64_t)cus * 2), 1024, 0, st>>>(
         P->A, P->qa0, P->qlen, P->I, P->lenI, P->list, P->clsoff, P->off, vb, B->ir, B->num);
     SPX_HIP(hipGetLastError());
   }
+  if (ss) SPX_TRY(side_join(ss, st));
   k_write_cp<<<grid_for(P->lenJ + 1, 256, 65536), 256, 0, st>>>(P->off, P->lenJ, B->cp, B->ptr_t);
   SPX_HIP(hipGetLastError());
   return SPX_OK;
