@@ -655,15 +655,16 @@ __device__ __forceinline__ K group_sort(K key, int gl) {  // ascending bitonic s
 }
 
 // One tiny column (at most G products) in a group of G lanes: the group
-// gathers every product into LDS, sorts the (row, product index) keys, and
-// either counts the distinct rows (COUNT) or sums each run of equal rows in
-// product order -- the order of Algorithm 1 -- and writes the column.  The
-// column's B range [b0, b1) and output offset come from the caller.
+// gathers every product into LDS; the count (COUNT) inserts the rows into a
+// small LDS table and counts the distinct ones; the numeric pass sorts the
+// (row, product index) keys, sums each run of equal rows in product order
+// -- the order of Algorithm 1 -- and writes the column.  The column's B
+// range [b0, b1) and output offset come from the caller.
 template <int G, int SR, typename T, bool COUNT>
 __device__ __forceinline__ void tiny_column(const Operand& A, const Operand& B, const int64_t* bq_a0,
                                             const int32_t* bq_alen, int32_t t, int64_t b0, int64_t b1,
                                             int64_t obase, int64_t* cnt, int32_t* cir, T* cnum, int32_t* s_row,
-                                            int32_t* s_aux, T* s_val) {
+                                            int32_t* s_aux, T* s_val, uint32_t* s_tab) {
   using S = Semiring<SR, T>;
   constexpr bool kVal = SR != SPX_OR_AND;
   const int lane = lane_id();
@@ -713,6 +714,34 @@ __device__ __forceinline__ void tiny_column(const Operand& A, const Operand& B, 
     wave_sync();
   }
   if (total > G) total = G;  // cannot happen: the caller checked the column's products
+  if constexpr (COUNT) {
+    // distinct rows: each lane inserts its product's row into the group's
+    // table of 2G slots (linear probing; a row is below 2^31, so the empty
+    // mark never matches); the lanes that claimed a slot hold the distinct rows
+    uint32_t* tab = s_tab + 2 * gb;
+    tab[gl] = 0xffffffffu;
+    tab[gl + G] = 0xffffffffu;
+    wave_sync();
+    bool fresh = false;
+    if (gl < total) {
+      const uint32_t r = (uint32_t)s_row[gl];
+      uint32_t h = (r * 0x9E3779B1u) >> (32 - (G == 64 ? 7 : 6));
+      for (;;) {
+        const uint32_t old = atomicCAS(&tab[h], 0xffffffffu, r);
+        if (old == 0xffffffffu) {
+          fresh = true;
+          break;
+        }
+        if (old == r) break;
+        h = (h + 1) & (2 * G - 1);
+      }
+    }
+    const uint64_t gmask = G == 64 ? ~0ull : (0xffffffffull << gb);
+    const uint64_t fm = __ballot(fresh) & gmask;
+    if (gl == 0) cnt[t] = __popcll(fm);
+    wave_sync();
+    return;
+  }
   // sort (row, product index): 32-bit keys when the rows leave 6 bits for
   // the index (the count needs the rows only)
   int32_t row;
@@ -789,6 +818,7 @@ __global__ void __launch_bounds__(256) k_tiny(Operand A, Operand B, const int64_
     int64_t b0[2], b1[2], o[2];
   };
   __shared__ PairRow s_pair[4][kWave];
+  __shared__ uint32_t s_tab[4][2 * kWave];  // the count's distinct-row tables
   const int w = threadIdx.x / kWave, lane = lane_id();
   const int64_t beg = binoff[kBinTiny], end = binoff[kBinTiny + 1];
   const int64_t npairs = (end - beg + 1) / 2;
@@ -822,13 +852,13 @@ __global__ void __launch_bounds__(256) k_tiny(Operand A, Operand B, const int64_
       if (has1 && m0 <= 32 && m1 <= 32) {
         const int h = lane < 32 ? 0 : 1;
         tiny_column<32, SR, T, COUNT>(A, B, bq_a0, bq_alen, r.t[h], r.b0[h], r.b1[h], r.o[h], cnt, cir, cnum,
-                                      s_row[w], s_aux[w], s_val[w]);
+                                      s_row[w], s_aux[w], s_val[w], s_tab[w]);
       } else {
         tiny_column<64, SR, T, COUNT>(A, B, bq_a0, bq_alen, r.t[0], r.b0[0], r.b1[0], r.o[0], cnt, cir, cnum,
-                                      s_row[w], s_aux[w], s_val[w]);
+                                      s_row[w], s_aux[w], s_val[w], s_tab[w]);
         if (has1)
           tiny_column<64, SR, T, COUNT>(A, B, bq_a0, bq_alen, r.t[1], r.b0[1], r.b1[1], r.o[1], cnt, cir, cnum,
-                                        s_row[w], s_aux[w], s_val[w]);
+                                        s_row[w], s_aux[w], s_val[w], s_tab[w]);
       }
     }
     wave_sync();  // the table is rewritten for the next 64 pairs
