@@ -301,10 +301,10 @@ int spx_batch_spgemm(const spx_ctx* ctx, int32_t count, const spx_mat* A, const 
  * spx_spref_plan returns nnz(B); spx_spref_exec fills B (CSC, lenI x lenJ,
  * caller-allocated: cp [lenJ+1], ir [nnz], num [nnz]).  SPX_EINVAL if an
  * index is out of range (checked on the device during the plan).
- * Both calls may put the columns that gather more than 4096 entries of A on
- * a second stream of the calling host thread (created on first use); that
- * work is joined back into ctx->stream by an event before the call returns,
- * so everything enqueued on ctx->stream afterwards sees it.              */
+ * spx_spref_exec may put the columns that gather more than 4096 entries of
+ * A on a second stream of the calling host thread (created on first use);
+ * that work is joined back into ctx->stream by an event before the call
+ * returns, so everything enqueued on ctx->stream afterwards sees it.      */
 int spx_spref_plan(const spx_ctx* ctx, const spx_mat* A, const int32_t* I, int64_t lenI, const int32_t* J,
                    int64_t lenJ, spx_plan** plan, int64_t* nnz_b);
 int spx_spref_exec(spx_plan* plan, spx_mat* B);

@@ -566,16 +566,12 @@ extern "C" int spx_spref_plan(const spx_ctx* ctx, const spx_mat* A, const int32_
     k_col_info<<<grid_for(lenJ, 256, 4096), 256, 0, st>>>(P->A, aux, chunk, J, lenJ, P->qa0, P->qlen, P->wide,
                                                           nwide);
     SPX_HIP(hipGetLastError());
-    // the few workgroups of the wide columns' count run beside the wave count
-    SideStream* ss = nullptr;
-    SPX_TRY(side_fork(st, &ss));
-    k_ref_count_wide<<<(unsigned)(cus * 2), 1024, 0, ss->s>>>(P->A, P->qa0, P->qlen, P->rptr, P->wide, nwide, P->cnt,
-                                                              clscount);
+    k_ref_count_wide<<<(unsigned)(cus * 2), 1024, 0, st>>>(P->A, P->qa0, P->qlen, P->rptr, P->wide, nwide, P->cnt,
+                                                           clscount);
     SPX_HIP(hipGetLastError());
     k_ref_count<<<grid_for(lenJ * kWave, 256, (int64_t)cus * 8), 256, 0, st>>>(P->A, P->qa0, P->qlen, P->rptr, lenJ,
                                                                                 P->cnt, clscount);
     SPX_HIP(hipGetLastError());
-    SPX_TRY(side_join(ss, st));
   }
   k_cls_offsets<<<1, 64, 0, st>>>(clscount, P->clsoff, fill);
   SPX_HIP(hipGetLastError());
