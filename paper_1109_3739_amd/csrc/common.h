@@ -140,6 +140,22 @@ struct SideStream {
 int side_fork(hipStream_t st, SideStream** out);
 int side_join(SideStream* ss, hipStream_t st);
 
+// Joins a forked side stream back into `st` when it goes out of scope, so
+// that an early error return still leaves no side work unordered with the
+// caller's stream; join() does it at a chosen point and reports errors.
+struct SideJoin {
+  SideStream* ss = nullptr;
+  hipStream_t st = nullptr;
+  int join() {
+    SideStream* s = ss;
+    ss = nullptr;
+    return s ? side_join(s, st) : SPX_OK;
+  }
+  ~SideJoin() {
+    if (ss) (void)side_join(ss, st);
+  }
+};
+
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 inline int64_t next_pow2(int64_t x) {
   int64_t p = 1;

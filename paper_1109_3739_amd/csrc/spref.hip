@@ -610,10 +610,10 @@ extern "C" int spx_spref_exec(spx_plan* plan, spx_mat* B) {
   const int cus = device_cu_count();
   const int64_t* co = P->clsoff_h;
   // the wide medium columns' few workgroups run beside the other classes
-  SideStream* ss = nullptr;
+  SideJoin side{nullptr, st};
   if (co[kClsMedium + 1] > co[kClsMedium] && P->nwide > 0) {
-    SPX_TRY(side_fork(st, &ss));
-    k_ref_medium<1024><<<(unsigned)std::min<int64_t>(P->nwide, (int64_t)cus * 2), 1024, 0, ss->s>>>(
+    SPX_TRY(side_fork(st, &side.ss));
+    k_ref_medium<1024><<<(unsigned)std::min<int64_t>(P->nwide, (int64_t)cus * 2), 1024, 0, side.ss->s>>>(
         P->A, P->qa0, P->qlen, P->rptr, P->rpos, P->list, P->wide, P->nwide, P->clsoff, P->cnt, P->off, vb, B->ir,
         B->num);
     SPX_HIP(hipGetLastError());
@@ -634,7 +634,7 @@ extern "C" int spx_spref_exec(spx_plan* plan, spx_mat* B) {
         P->A, P->qa0, P->qlen, P->I, P->lenI, P->list, P->clsoff, P->off, vb, B->ir, B->num);
     SPX_HIP(hipGetLastError());
   }
-  if (ss) SPX_TRY(side_join(ss, st));
+  SPX_TRY(side.join());
   k_write_cp<<<grid_for(P->lenJ + 1, 256, 65536), 256, 0, st>>>(P->off, P->lenJ, B->cp, B->ptr_t);
   SPX_HIP(hipGetLastError());
   return SPX_OK;
