@@ -51,6 +51,49 @@ def test_spref_long_columns_and_heavy_repeats(spx):
     spref_check(spx, A, rng.integers(0, m, 30).astype(np.int32), J)
 
 
+def test_spref_wide_columns_from_threads(spx):
+    """Wide columns (more than 4096 gathered entries, few outputs) are
+    extracted on a second stream of the calling thread: three threads, each
+    with its own stream, extract at once and repeatedly; every result equals
+    the oracle's."""
+    import threading
+    import torch
+    m = 20000
+    rng = np.random.default_rng(9)
+    rows = [np.arange(m), np.arange(0, m, 3)] + [np.sort(rng.choice(m, 5, replace=False)) for _ in range(50)]
+    cols = np.concatenate([np.full(r.size, c, np.int64) for c, r in enumerate(rows)])
+    rows = np.concatenate(rows)
+    A = W.from_triples(rows, cols, np.arange(rows.size, dtype=np.int64), m, 52)
+    dA = spx.from_host(A)
+    J = np.concatenate([[0, 1], np.arange(2, 52), [1, 0]]).astype(np.int32)
+    cases = [rng.integers(0, m, size=n).astype(np.int32) for n in (30, 200, 1500)]
+    refs = [oracle.spref(A, I, J) for I in cases]
+    got = [[] for _ in cases]
+    errors = []
+
+    def work(k):
+        try:
+            st = torch.cuda.Stream()
+            with torch.cuda.stream(st):
+                for _ in range(4):
+                    B = spx.spref(dA, cases[k], J)
+                    st.synchronize()
+                    got[k].append(B.to_host_csc())
+        except Exception as e:  # reported below
+            errors.append(repr(e))
+
+    threads = [threading.Thread(target=work, args=(k,)) for k in range(len(cases))]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join()
+    assert not errors, errors
+    for k, ref in enumerate(refs):
+        assert len(got[k]) == 4
+        for B in got[k]:
+            assert_same_csc(B, ref, exact_values=True, what=f"thread {k}")
+
+
 def test_spref_permutation_roundtrip(spx):
     A = W.rmat(14, 8, seed=3, values="f64")
     p = W.random_permutation(A.n, seed=4)
