@@ -109,6 +109,13 @@ int device_cu_count();
 // library can be captured into a HIP graph).
 int fill_i64(int64_t* p, int64_t n, int64_t v, hipStream_t stream);
 int fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t stream);
+// Zeroes up to kMaxZeroRuns runs of 8-byte words with one launch.
+constexpr int kMaxZeroRuns = 8;
+struct ZeroRun {
+  void* p;
+  int64_t words;
+};
+int zero_words(hipStream_t stream, std::initializer_list<ZeroRun> runs);
 
 // Reads device scalars of 4 or 8 bytes (4-byte ones zero-extended), or
 // runs of `count` of them, at most kMaxReadRanges runs and kMaxReadWords

@@ -241,6 +241,38 @@ int fill_i64(int64_t* p, int64_t n, int64_t v, hipStream_t stream) {
   return SPX_OK;
 }
 
+struct ZeroList {
+  int64_t* p[kMaxZeroRuns];
+  int64_t end[kMaxZeroRuns];  // inclusive prefix of the runs' lengths
+  int n;
+};
+
+__global__ void k_zero_words(ZeroList z) {
+  const int64_t total = z.end[z.n - 1];
+  int r = 0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+    while (i >= z.end[r]) ++r;  // i only grows, so r does too
+    z.p[r][i - (r ? z.end[r - 1] : 0)] = 0;
+  }
+}
+
+int zero_words(hipStream_t stream, std::initializer_list<ZeroRun> runs) {
+  if (runs.size() > (size_t)kMaxZeroRuns) return fail(SPX_EINVAL, "zero_words: too many runs");
+  ZeroList z{};
+  int64_t total = 0;
+  for (const ZeroRun& r : runs) {
+    if (r.words <= 0) continue;
+    total += r.words;
+    z.p[z.n] = static_cast<int64_t*>(r.p);
+    z.end[z.n] = total;
+    ++z.n;
+  }
+  if (total == 0) return SPX_OK;
+  k_zero_words<<<grid_for(total, 256, 4096), 256, 0, stream>>>(z);
+  SPX_HIP(hipGetLastError());
+  return SPX_OK;
+}
+
 int fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t stream) {
   if (n <= 0) return SPX_OK;
   k_fill<uint32_t><<<grid_for(n, 256, 4096), 256, 0, stream>>>(p, n, v);

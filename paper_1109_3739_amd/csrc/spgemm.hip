@@ -213,25 +213,27 @@ __global__ void k_bin_count(const int64_t* mults, int64_t nslots, BinCfg cfg, un
     if (hist[i]) atomicAdd(&counts[i], (unsigned long long)hist[i]);
 }
 
-__global__ void k_bin_offsets(unsigned long long* counts, int64_t* binoff, unsigned long long* fill) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    int64_t run = 0;
-    for (int i = 0; i < kNumBins; ++i) {
-      binoff[i] = run;
-      fill[i] = 0;
-      run += (int64_t)counts[i];
-    }
-    binoff[kNumBins] = run;
-  }
-}
-
 // Each thread ranks kFillPer slots per round in LDS, so a workgroup reserves
-// its ranges of the bins once per blockDim * kFillPer slots.
+// its ranges of the bins once per blockDim * kFillPer slots.  Every
+// workgroup derives the bin offsets from the counts itself; the first one
+// also stores them (binoff, kNumBins + 1 entries).  fill must be zero.
 constexpr int kFillPer = 8;
-__global__ void k_bin_fill(const int64_t* mults, int64_t nslots, BinCfg cfg, const int64_t* binoff,
-                           unsigned long long* fill, int32_t* list) {
+__global__ void k_bin_fill(const int64_t* mults, int64_t nslots, BinCfg cfg, const unsigned long long* counts,
+                           int64_t* binoff, unsigned long long* fill, int32_t* list) {
   __shared__ unsigned hist[kNumBins];
   __shared__ int64_t base[kNumBins];
+  __shared__ int64_t off[kNumBins + 1];
+  if (threadIdx.x == 0) {
+    int64_t run = 0;
+    for (int i = 0; i < kNumBins; ++i) {
+      off[i] = run;
+      run += (int64_t)counts[i];
+    }
+    off[kNumBins] = run;
+  }
+  __syncthreads();
+  if (blockIdx.x == 0)
+    for (int i = threadIdx.x; i <= kNumBins; i += blockDim.x) binoff[i] = off[i];
   const int64_t span = (int64_t)blockDim.x * kFillPer;
   for (int64_t t0 = (int64_t)blockIdx.x * span; t0 < nslots; t0 += (int64_t)gridDim.x * span) {
     for (int i = threadIdx.x; i < kNumBins; i += blockDim.x) hist[i] = 0;
@@ -246,7 +248,7 @@ __global__ void k_bin_fill(const int64_t* mults, int64_t nslots, BinCfg cfg, con
     }
     __syncthreads();
     for (int i = threadIdx.x; i < kNumBins; i += blockDim.x)
-      if (hist[i]) base[i] = binoff[i] + (int64_t)atomicAdd(&fill[i], (unsigned long long)hist[i]);
+      if (hist[i]) base[i] = off[i] + (int64_t)atomicAdd(&fill[i], (unsigned long long)hist[i]);
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < kFillPer; ++k)
@@ -2021,16 +2023,18 @@ extern "C" int spx_spgemm_plan(const spx_ctx* ctx, const spx_mat* A, const spx_m
   P->nslice_req = std::max(1, std::min(tune.xcd_slices, 64));
   P->mark(kEvPlan0, st);
 
-  unsigned long long *bincount = nullptr, *binfill = nullptr;
+  unsigned long long *bincount = nullptr, *binfill = nullptr, *nlong = nullptr;
+  int32_t* longs = nullptr;  // slots with more than kLongSlot B entries
   SPX_TRY(scr.get_many({Scratch::part(&P->sum, 1), Scratch::part(&P->bq_a0, B->nnz),
                         Scratch::part(&P->bq_alen, B->nnz), Scratch::part(&P->bq_split, B->nnz),
                         Scratch::part(&P->mults_d, nslots), Scratch::part(&P->cnt, nslots),
                         Scratch::part(&P->off, nslots + 1), Scratch::part(&P->zoff, nslots + 1),
                         Scratch::part(&P->list, nslots), Scratch::part(&P->binoff, kNumBins + 1),
-                        Scratch::part(&bincount, kNumBins), Scratch::part(&binfill, kNumBins)}));
-  SPX_TRY(fill_i64((int64_t*)P->sum, sizeof(Summary) / 8, 0, st));
-  SPX_TRY(fill_i64((int64_t*)bincount, kNumBins, 0, st));
-  SPX_TRY(fill_i64(P->cnt, std::max<int64_t>(nslots, 1), 0, st));
+                        Scratch::part(&bincount, kNumBins), Scratch::part(&binfill, kNumBins),
+                        Scratch::part(&longs, std::max<int64_t>(nslots, 1)), Scratch::part(&nlong, 1)}));
+  // bin offsets stay zero when there are no slots (k_bin_fill writes them otherwise)
+  SPX_TRY(zero_words(st, {{P->sum, (int64_t)(sizeof(Summary) / 8)}, {bincount, kNumBins}, {binfill, kNumBins},
+                          {P->cnt, std::max<int64_t>(nslots, 1)}, {nlong, 1}, {P->binoff, kNumBins + 1}}));
   unsigned* err = &P->sum->err;
 
   // AUX index for a DCSC A
@@ -2062,11 +2066,6 @@ extern "C" int spx_spgemm_plan(const spx_ctx* ctx, const spx_mat* A, const spx_m
                    (A->nnz < (1ll << 29) && !tune.force_off64) ? 1 : 0};
   BinCfg bc{tune.tiny_max, tune.hash_count_max};
   if (nslots > 0) {
-    int32_t* longs = nullptr;
-    unsigned long long* nlong = nullptr;
-    SPX_TRY(scr.get_n(std::max<int64_t>(nslots, 1), &longs));
-    SPX_TRY(scr.get_n(1, &nlong));
-    SPX_TRY(fill_i64(reinterpret_cast<int64_t*>(nlong), 1, 0, st));
     k_slot_mults<<<grid_for(nslots * 8, 256, (int64_t)cus * 16), 256, 0, st>>>(P->B, P->bq_alen, nslots, P->mults_d,
                                                                               &P->sum->mults, longs, nlong);
     SPX_HIP(hipGetLastError());
@@ -2075,12 +2074,9 @@ extern "C" int spx_spgemm_plan(const spx_ctx* ctx, const spx_mat* A, const spx_m
     k_bin_count<<<grid_for(nslots, 256, (int64_t)cus * 8), 256, 0, st>>>(P->mults_d, nslots, bc, bincount);
     SPX_HIP(hipGetLastError());
   }
-  k_bin_offsets<<<1, 64, 0, st>>>(bincount, P->binoff, binfill);
-  SPX_HIP(hipGetLastError());
   if (nslots > 0) {
-    k_bin_fill<<<grid_for(ceil_div(nslots, kFillPer), 256, (int64_t)cus * 8), 256, 0, st>>>(P->mults_d, nslots, bc,
-                                                                                           P->binoff, binfill,
-                                                                        P->list);
+    k_bin_fill<<<grid_for(ceil_div(nslots, kFillPer), 256, (int64_t)cus * 8), 256, 0, st>>>(
+        P->mults_d, nslots, bc, bincount, P->binoff, binfill, P->list);
     SPX_HIP(hipGetLastError());
   }
   // sync 1: bin sizes and the total number of multiplications
