@@ -46,9 +46,15 @@ struct SprefPlan : spx_plan {
   unsigned* err = nullptr;
 };
 
-__global__ void k_check_index(const int32_t* v, int64_t len, int64_t bound, unsigned* err, unsigned bit) {
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < len; i += (int64_t)gridDim.x * blockDim.x)
-    if (v[i] < 0 || v[i] >= bound) atomicOr(err, bit);
+// Range checks of I (against m, error bit 1) and J (against n, bit 2) in one pass.
+__global__ void k_check_index(const int32_t* I, int64_t lenI, int64_t m, const int32_t* J, int64_t lenJ, int64_t n,
+                              unsigned* err) {
+  for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < lenI + lenJ;
+       x += (int64_t)gridDim.x * blockDim.x) {
+    const bool in_i = x < lenI;
+    const int32_t v = in_i ? I[x] : J[x - lenI];
+    if (v < 0 || v >= (in_i ? m : n)) atomicOr(err, in_i ? 1u : 2u);
+  }
 }
 
 __global__ void k_row_hist(const int32_t* I, int64_t lenI, int64_t m, unsigned* rcnt) {
@@ -249,27 +255,29 @@ __global__ void __launch_bounds__(1024) k_ref_count_wide(const Operand A, const 
   }
 }
 
-__global__ void k_cls_offsets(unsigned long long* clscount, int64_t* clsoff, unsigned long long* fill) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    int64_t run = 0;
-    for (int c = 0; c < kNumCls; ++c) {
-      clsoff[c] = run;
-      fill[c] = 0;
-      run += (int64_t)clscount[c];
-    }
-    clsoff[kNumCls] = run;
-  }
-}
-
 // Columns grouped by class (any order inside a class).  A thread takes
 // kClsPer consecutive columns; the class counts of a thread are packed in
 // 16-bit fields, so one workgroup scan ranks every column in its class and
-// one atomic per class and workgroup claims the workgroup's slots.
+// one atomic per class and workgroup claims the workgroup's slots.  Every
+// workgroup derives the class offsets from the counts itself; the first one
+// also stores them (clsoff, kNumCls + 1 entries).  fill must be zero.
 constexpr int kClsPer = 8;
 __global__ void __launch_bounds__(256) k_cls_fill(const int64_t* cnt, const int32_t* qlen, int64_t lenJ,
-                                                  const int64_t* clsoff, unsigned long long* fill, int32_t* list) {
+                                                  const unsigned long long* clscount, int64_t* clsoff,
+                                                  unsigned long long* fill, int32_t* list) {
   __shared__ uint64_t red[256 / kWave + 1];
   __shared__ unsigned long long s_base[kNumCls];
+  __shared__ int64_t s_off[kNumCls + 1];
+  if (threadIdx.x == 0) {
+    int64_t run = 0;
+    for (int c = 0; c < kNumCls; ++c) {
+      s_off[c] = run;
+      run += (int64_t)clscount[c];
+    }
+    s_off[kNumCls] = run;
+  }
+  __syncthreads();
+  if (blockIdx.x == 0 && threadIdx.x <= kNumCls) clsoff[threadIdx.x] = s_off[threadIdx.x];
   for (int64_t q0 = (int64_t)blockIdx.x * 256 * kClsPer; q0 < lenJ; q0 += (int64_t)gridDim.x * 256 * kClsPer) {
     const int64_t qt = q0 + (int64_t)threadIdx.x * kClsPer;
     int c[kClsPer];
@@ -290,7 +298,7 @@ __global__ void __launch_bounds__(256) k_cls_fill(const int64_t* cnt, const int3
     for (int k = 0; k < kClsPer; ++k) {
       if (c[k] < 0) continue;
       const int64_t slot = (int64_t)s_base[c[k]] + (int64_t)((ex >> (16 * c[k])) & 0xffffull);
-      list[clsoff[c[k]] + slot] = (int32_t)(qt + k);
+      list[s_off[c[k]] + slot] = (int32_t)(qt + k);
       ex += 1ull << (16 * c[k]);
     }
     __syncthreads();
@@ -532,15 +540,12 @@ extern "C" int spx_spref_plan(const spx_ctx* ctx, const spx_mat* A, const int32_
                         Scratch::part(&P->cnt, lenJ), Scratch::part(&P->off, lenJ + 1), Scratch::part(&P->list, lenJ),
                         Scratch::part(&P->clsoff, kNumCls + 1), Scratch::part(&clscount, kNumCls),
                         Scratch::part(&fill, kNumCls)}));
-  SPX_TRY(fill_u32(P->err, 1, 0, st));
-  SPX_TRY(fill_i64(reinterpret_cast<int64_t*>(nlong), 2, 0, st));  // long rows, wide columns
+  // error bits, long rows and wide columns, class counts and fills; the class
+  // offsets stay zero when J is empty (k_cls_fill writes them otherwise)
+  SPX_TRY(zero_words(st, {{P->err, 2}, {nlong, 2}, {clscount, kNumCls}, {fill, kNumCls}, {P->clsoff, kNumCls + 1}}));
   unsigned long long* nwide = nlong + 1;
-  if (lenI > 0) {
-    k_check_index<<<grid_for(lenI, 256, 4096), 256, 0, st>>>(I, lenI, m, P->err, 1u);
-    SPX_HIP(hipGetLastError());
-  }
-  if (lenJ > 0) {
-    k_check_index<<<grid_for(lenJ, 256, 4096), 256, 0, st>>>(J, lenJ, A->n, P->err, 2u);
+  if (lenI + lenJ > 0) {
+    k_check_index<<<grid_for(lenI + lenJ, 256, 4096), 256, 0, st>>>(I, lenI, m, J, lenJ, A->n, P->err);
     SPX_HIP(hipGetLastError());
   }
   // transpose of R: rows of I grouped by index, positions ascending
@@ -561,7 +566,6 @@ extern "C" int spx_spref_plan(const spx_ctx* ctx, const spx_mat* A, const int32_
   // A*Q: the columns J(q) of A
   int64_t *aux = nullptr, chunk = 1;
   SPX_TRY(build_aux(P->A, scr, st, &aux, &chunk));
-  SPX_TRY(fill_i64((int64_t*)clscount, kNumCls, 0, st));
   if (lenJ > 0) {
     k_col_info<<<grid_for(lenJ, 256, 4096), 256, 0, st>>>(P->A, aux, chunk, J, lenJ, P->qa0, P->qlen, P->wide,
                                                           nwide);
@@ -573,11 +577,9 @@ extern "C" int spx_spref_plan(const spx_ctx* ctx, const spx_mat* A, const int32_
                                                                                 P->cnt, clscount);
     SPX_HIP(hipGetLastError());
   }
-  k_cls_offsets<<<1, 64, 0, st>>>(clscount, P->clsoff, fill);
-  SPX_HIP(hipGetLastError());
   if (lenJ > 0) {
-    k_cls_fill<<<grid_for(lenJ, 256 * kClsPer, 4096), 256, 0, st>>>(P->cnt, P->qlen, lenJ, P->clsoff, fill,
-                                                                     P->list);
+    k_cls_fill<<<grid_for(lenJ, 256 * kClsPer, 4096), 256, 0, st>>>(P->cnt, P->qlen, lenJ, clscount, P->clsoff,
+                                                                     fill, P->list);
     SPX_HIP(hipGetLastError());
   }
   SPX_TRY(exclusive_scan(LoadI64{P->cnt}, lenJ, P->off, scr, st));
